@@ -1,0 +1,234 @@
+"""CPU oracle for view-independent adjoint light tracing -- TEST INFRASTRUCTURE.
+
+Only tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  The product path (``paper_2310_02043_amd``) never
+imports, links or runs it.  The heavy lifting is plain C in ``lt_oracle.c``
+(FP32 path arithmetic under the written contract, FP64 reductions, int64
+fixed-point texels); this module only marshals numpy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lt_oracle.c")
+_LIB = os.path.join(_HERE, "liblt_oracle.so")
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+          "-fvisibility=hidden", "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP contraction off, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Scene(C.Structure):
+    _fields_ = [("verts", C.c_void_p), ("tris", C.c_void_p), ("tri_patch", C.c_void_p),
+                ("n_tris", C.c_int64), ("pf", C.c_void_p), ("pres", C.c_void_p), ("pbase", C.c_void_p),
+                ("n_patches", C.c_int32), ("n_texels", C.c_int64), ("bvh", C.c_void_p)]
+
+
+class _Lights(C.Structure):
+    _fields_ = [("type", C.c_void_p), ("lobe_n", C.c_void_p), ("size", C.c_void_p),
+                ("layout_offsets", C.c_void_p), ("n_lights", C.c_int32), ("n_layouts", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        L.or_philox.argtypes = [P, P, P]
+        L.or_sincos2pi.argtypes = [C.c_float, P, P]
+        L.or_log2.argtypes = [C.c_float]
+        L.or_log2.restype = C.c_float
+        L.or_exp2.argtypes = [C.c_float]
+        L.or_exp2.restype = C.c_float
+        L.or_sincos_f64.argtypes = [C.c_double, P, P]
+        L.or_bvh_build.argtypes = [P, P, C.c_int64, C.c_double]
+        L.or_bvh_build.restype = P
+        L.or_bvh_free.argtypes = [P]
+        L.or_intersect_batch.argtypes = [P, P, C.c_int64, P, P, P]
+        L.or_forward.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int64, C.c_int, P]
+        L.or_forward.restype = C.c_int64
+        L.or_adjoint.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int64, C.c_int, P, P]
+        L.or_adjoint.restype = C.c_int64
+        L.or_record.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int64,
+                                C.c_int64, P, P, P, P]
+        L.or_fixed_to_float.argtypes = [P, C.c_int64, P]
+        L.or_objective.argtypes = [P, P, P, P, C.c_int64, C.c_int64, P]
+        L.or_objective.restype = C.c_double
+        L.or_light_frames.argtypes = [P, P, C.c_int64, P]
+        L.or_first_hit_dlog.argtypes = [P, P, C.c_int, P, P, P, C.c_float, C.c_float, P]
+        L.or_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+class OracleScene:
+    """Holds the scene arrays (and optionally the oracle's own BVH)."""
+
+    def __init__(self, scene, use_bvh: bool = False):
+        self.scene = scene
+        self.verts = np.ascontiguousarray(scene.verts, np.float32)
+        self.tris = np.ascontiguousarray(scene.tris, np.int32)
+        self.tri_patch = np.ascontiguousarray(scene.tri_patch, np.int32)
+        self.pf = scene.patch_floats()
+        self.pres = scene.patch_res()
+        self.pbase = scene.patch_base()
+        self.n_texels = int(scene.n_texels)
+        self._bvh = None
+        if use_bvh:
+            lo, hi = self.verts.min(0).astype(np.float64), self.verts.max(0).astype(np.float64)
+            pad = 1e-5 * (float(np.abs(np.concatenate([lo, hi])).max()) + float((hi - lo).max()) + 1.0)
+            self._bvh = lib().or_bvh_build(self.verts.ctypes.data, self.tris.ctypes.data,
+                                           int(self.tris.shape[0]), pad)
+        self.c = _Scene(self.verts.ctypes.data, self.tris.ctypes.data, self.tri_patch.ctypes.data,
+                        int(self.tris.shape[0]), self.pf.ctypes.data, self.pres.ctypes.data,
+                        self.pbase.ctypes.data, int(self.pf.shape[0]), self.n_texels, self._bvh)
+
+    def __del__(self):
+        if self._bvh is not None and _lib is not None:
+            _lib.or_bvh_free(self._bvh)
+            self._bvh = None
+
+
+class OracleLights:
+    def __init__(self, lights):
+        st = lights.static
+        self.type = np.ascontiguousarray(st["type"], np.int32)
+        self.lobe = np.ascontiguousarray(st["lobe_n"], np.float32)
+        self.size = np.ascontiguousarray(np.stack([st["size_w"], st["size_h"]], 1), np.float32)
+        self.offs = np.ascontiguousarray(lights.layout_offsets, np.int32)
+        self.n_lights = int(st.shape[0])
+        self.n_layouts = int(self.offs.shape[0] - 1)
+        self.c = _Lights(self.type.ctypes.data, self.lobe.ctypes.data, self.size.ctypes.data,
+                         self.offs.ctypes.data, self.n_lights, self.n_layouts)
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().or_philox(c.ctypes.data, k.ctypes.data, out.ctypes.data)
+    return out
+
+
+def sincos2pi(u):
+    s, c = C.c_float(), C.c_float()
+    lib().or_sincos2pi(float(u), C.byref(s), C.byref(c))
+    return s.value, c.value
+
+
+def log2(x):
+    return lib().or_log2(float(x))
+
+
+def exp2(x):
+    return lib().or_exp2(float(x))
+
+
+def sincos_f64(x):
+    s, c = C.c_double(), C.c_double()
+    lib().or_sincos_f64(float(x), C.byref(s), C.byref(c))
+    return s.value, c.value
+
+
+def intersect(osc: OracleScene, rays: np.ndarray, skip=None):
+    rays = np.ascontiguousarray(rays, np.float32).reshape(-1, 6)
+    n = rays.shape[0]
+    t = np.zeros(n, np.float32)
+    prim = np.zeros(n, np.int64)
+    sk = None if skip is None else np.ascontiguousarray(skip, np.int32)
+    lib().or_intersect_batch(C.byref(osc.c), rays.ctypes.data, n, _p(sk), t.ctypes.data, prim.ctypes.data)
+    return t, prim
+
+
+def forward(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,
+            limit_per_light: int = 0, n_threads: int = 0):
+    """Alg. 1: returns (S [n_layouts,K] int64, misses)."""
+    prm = np.ascontiguousarray(params, np.float32)
+    S = np.zeros((ol.n_layouts, osc.n_texels), np.int64)
+    m = lib().or_forward(C.byref(osc.c), C.byref(ol.c), prm.ctypes.data, int(seed) & 0xFFFFFFFFFFFFFFFF,
+                         int(paths_per_layout), int(max_hits), int(limit_per_light), int(n_threads),
+                         S.ctypes.data)
+    return S, int(m)
+
+
+def adjoint(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,
+            dOdE, limit_per_light: int = 0, n_threads: int = 0):
+    """Alg. 2: returns (grad [L,6] float64, misses)."""
+    prm = np.ascontiguousarray(params, np.float32)
+    g = np.ascontiguousarray(dOdE, np.float32).reshape(ol.n_layouts, osc.n_texels)
+    out = np.zeros((ol.n_lights, 6), np.float64)
+    m = lib().or_adjoint(C.byref(osc.c), C.byref(ol.c), prm.ctypes.data, int(seed) & 0xFFFFFFFFFFFFFFFF,
+                         int(paths_per_layout), int(max_hits), int(limit_per_light), int(n_threads),
+                         g.ctypes.data, out.ctypes.data)
+    return out, int(m)
+
+
+def record(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,
+           layout: int, light: int, first: int, count: int, dOdE=None):
+    prm = np.ascontiguousarray(params, np.float32)
+    prim = np.zeros((count, max_hits), np.int32)
+    tex = np.zeros((count, max_hits), np.int32)
+    g = None if dOdE is None else np.ascontiguousarray(dOdE, np.float32)
+    contrib = None if dOdE is None else np.zeros((count, 6), np.float32)
+    lib().or_record(C.byref(osc.c), C.byref(ol.c), prm.ctypes.data, int(seed) & 0xFFFFFFFFFFFFFFFF,
+                    int(paths_per_layout), int(max_hits), int(layout), int(light), int(first), int(count),
+                    prim.ctypes.data, tex.ctypes.data, _p(g), _p(contrib))
+    return prim, tex, contrib
+
+
+def fixed_to_float(S):
+    S = np.ascontiguousarray(S, np.int64)
+    E = np.zeros(S.shape, np.float32)
+    lib().or_fixed_to_float(S.ctypes.data, S.size, E.ctypes.data)
+    return E
+
+
+def objective(E, Et, A, alpha=None):
+    E = np.ascontiguousarray(E, np.float32)
+    Et = np.ascontiguousarray(Et, np.float32)
+    A = np.ascontiguousarray(A, np.float32)
+    al = None if alpha is None else np.ascontiguousarray(alpha, np.float32)
+    g = np.zeros(E.shape, np.float32)
+    O = lib().or_objective(E.ctypes.data, Et.ctypes.data, _p(al), A.ctypes.data, A.size, E.size, g.ctypes.data)
+    return O, g
+
+
+def light_frames(ol: OracleLights, params, paths_per_layout: int):
+    prm = np.ascontiguousarray(params, np.float32)
+    out = np.zeros((ol.n_lights, 29), np.float32)
+    lib().or_light_frames(C.byref(ol.c), prm.ctypes.data, int(paths_per_layout), out.ctypes.data)
+    return out
+
+
+def first_hit_dlog(ol: OracleLights, params, light: int, x1, y, n1, au=0.0, av=0.0):
+    prm = np.ascontiguousarray(params, np.float32)
+    a = [np.ascontiguousarray(v, np.float32) for v in (x1, y, n1)]
+    out = np.zeros(6, np.float32)
+    lib().or_first_hit_dlog(C.byref(ol.c), prm.ctypes.data, int(light), a[0].ctypes.data, a[1].ctypes.data,
+                            a[2].ctypes.data, float(au), float(av), out.ctypes.data)
+    return out
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())

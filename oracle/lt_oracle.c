@@ -1,0 +1,813 @@
+/*
+ * Light-tracing oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow CPU implementation of view-independent adjoint light tracing
+ * (Lipp et al., "View-Independent Adjoint Light Tracing for Lighting Design
+ * Optimization").  Only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark may load it; the product library never does.  It shares no
+ * code with the GPU path: the two sides implement the same written arithmetic
+ * contract (FP32 path arithmetic in a fixed operation order, no contraction,
+ * IEEE division and square root, own transcendental polynomials, Philox4x32-10)
+ * independently.
+ *
+ * What it computes, with the passage each step follows:
+ *   - Primal light tracing, Alg. 1 (Sec. 4.2): per light N_l rays, each
+ *     carrying flux Phi_r = P / N_l; at every hit the incident flux is splatted
+ *     into the hit texel as irradiance (Eq. directionalCoeffs with n = 0,
+ *     H_0^0 = 1 and the box basis of the mass-lumped projection, supplement
+ *     Eq. spatialRep / appdxSpatialCoeffs); the path continues with a
+ *     cosine-weighted bounce and Phi_{i+1} = Phi_i * rho (Eq. indirectFlux for
+ *     a Lambertian BRDF f = rho/pi sampled with pdf cos/pi).
+ *   - Objective, Eq. objective with alpha_l = 1: O = 1/2 sum_k A_k alpha_k
+ *     (E_k - E*_k)^2, and its derivative g_k = dO/dE_k.
+ *   - Adjoint light tracing, Alg. 2 (Sec. 4.3): the same paths replayed from
+ *     the counter-based generator; the adjoint state dO/dPhi_r accumulates
+ *     g_k * dE_k/dPhi_i * dPhi_i/dPhi_r at every hit (Eq. adjointFlux); at the
+ *     first hit dPhi_r/dp is formed with x_1 held fixed (Sec. 4.3 "constant
+ *     sample", Sec. 4.4.2 Eq. posDeriv, rotation and area-light terms of the
+ *     supplement, generalised to a cos^n lobe); at path end
+ *     dO/dp += dO/dPhi_r * dPhi_r/dp (Eq. objGradAdjoint, first term; the BRDF
+ *     terms vanish for Lambertian surfaces, Eq. dLdp discussion).
+ *
+ * Floating point: path arithmetic is FP32 because the kernels compute in FP32
+ * and FP32 decides integers here (which triangle is hit, which texel, the
+ * fixed-point code of a splat); texel sums are exact int64 fixed point
+ * (Q31.32); reductions over paths and texels are FP64.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define EXPORT __attribute__((visibility("default")))
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10, from Salmon, Moraes, Dror, Shaw, "Parallel random numbers:  */
+/* as easy as 1, 2, 3" (SC'11): 10 rounds of two 32x32->64 multiplies with    */
+/* a Weyl-sequence key schedule.                                              */
+/* ------------------------------------------------------------------------- */
+EXPORT void or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        uint32_t y1 = (uint32_t)p1;
+        uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        uint32_t y3 = (uint32_t)p0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* 24 high bits of a 32-bit word as a float in [0, 1 - 2^-24]. */
+static float unit_float(uint32_t x) { return (float)(x >> 8) * 0x1p-24f; }
+
+static void draw4(uint64_t seed, uint32_t i, uint32_t stream, uint32_t block, float u[4])
+{
+    uint32_t ctr[4] = {i, stream, block, 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t r[4];
+    or_philox(ctr, key, r);
+    for (int c = 0; c < 4; ++c) u[c] = unit_float(r[c]);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Own transcendentals (FP32 contract).                                       */
+/* ------------------------------------------------------------------------- */
+
+/* sin and cos of 2*pi*u for u in [0,1): quadrant from round(4u), remainder
+ * x = (4u - q) * pi/2 in [-pi/4, pi/4], Taylor polynomials in Horner form. */
+EXPORT void or_sincos2pi(float u, float* s_out, float* c_out)
+{
+    const float HALF_PI = (float)1.57079632679489661923;
+    float q4 = u * 4.0f;
+    float qf = rintf(q4);
+    float r = q4 - qf;
+    float x = r * HALF_PI;
+    float x2 = x * x;
+    float ps = (float)(1.0 / 362880.0);
+    ps = ps * x2 + (float)(-1.0 / 5040.0);
+    ps = ps * x2 + (float)(1.0 / 120.0);
+    ps = ps * x2 + (float)(-1.0 / 6.0);
+    ps = ps * x2;
+    float s = x + x * ps;
+    float pc = (float)(1.0 / 3628800.0);
+    pc = pc * x2 + (float)(-1.0 / 40320.0);
+    pc = pc * x2 + (float)(1.0 / 720.0);
+    pc = pc * x2 + (float)(-1.0 / 24.0);
+    pc = pc * x2 + (float)(1.0 / 2.0);
+    float c = 1.0f - pc * x2;
+    int q = ((int)qf) & 3;
+    float so, co;
+    if (q == 0) { so = s; co = c; }
+    else if (q == 1) { so = c; co = -s; }
+    else if (q == 2) { so = -s; co = -c; }
+    else { so = -c; co = s; }
+    *s_out = so;
+    *c_out = co;
+}
+
+/* log2 of a positive normal float: x = m 2^e with m in [sqrt(1/2), sqrt(2)),
+ * ln m = 2 atanh(s), s = (m-1)/(m+1), odd series to s^11. */
+EXPORT float or_log2(float x)
+{
+    const float SQRT_HALF = (float)0.70710678118654752440;
+    const float INV_LN2 = (float)1.44269504088896340736;
+    int e;
+    float m = frexpf(x, &e);
+    if (m < SQRT_HALF) {
+        m = m * 2.0f;
+        e = e - 1;
+    }
+    float f = m - 1.0f;
+    float s = f / (m + 1.0f);
+    float s2 = s * s;
+    float p = (float)(1.0 / 11.0);
+    p = p * s2 + (float)(1.0 / 9.0);
+    p = p * s2 + (float)(1.0 / 7.0);
+    p = p * s2 + (float)(1.0 / 5.0);
+    p = p * s2 + (float)(1.0 / 3.0);
+    p = p * s2;
+    float h = s + s * p;
+    float ln_m = h + h;
+    return (float)e + ln_m * INV_LN2;
+}
+
+/* 2^y: k = round(y), f = y - k in [-1/2, 1/2], e^(f ln2) by Taylor to degree 7. */
+EXPORT float or_exp2(float y)
+{
+    const float LN2 = (float)0.69314718055994530942;
+    float k = rintf(y);
+    float f = y - k;
+    float z = f * LN2;
+    float p = (float)(1.0 / 5040.0);
+    p = p * z + (float)(1.0 / 720.0);
+    p = p * z + (float)(1.0 / 120.0);
+    p = p * z + (float)(1.0 / 24.0);
+    p = p * z + (float)(1.0 / 6.0);
+    p = p * z + 0.5f;
+    p = p * z + 1.0f;
+    p = p * z + 1.0f;
+    return ldexpf(p, (int)k);
+}
+
+/* sin and cos of an arbitrary angle in FP64 (used for the light frame only):
+ * k = round(x 2/pi), r = (x - k P1) - k P2 with pi/2 = P1 + P2 (P1 has 33
+ * significant bits), Taylor polynomials to r^17 / r^18. */
+EXPORT void or_sincos_f64(double x, double* s_out, double* c_out)
+{
+    const double TWO_OVER_PI = 6.36619772367581382433e-01;
+    const double P1 = 1.57079632673412561417e+00;
+    const double P2 = 6.07710050650619224932e-11;
+    double k = rint(x * TWO_OVER_PI);
+    double r = (x - k * P1) - k * P2;
+    double r2 = r * r;
+    double ps = -1.0 / 355687428096000.0;       /* -1/17! */
+    ps = ps * r2 + 1.0 / 1307674368000.0;       /* 1/15! */
+    ps = ps * r2 - 1.0 / 6227020800.0;          /* -1/13! */
+    ps = ps * r2 + 1.0 / 39916800.0;            /* 1/11! */
+    ps = ps * r2 - 1.0 / 362880.0;              /* -1/9! */
+    ps = ps * r2 + 1.0 / 5040.0;                /* 1/7! */
+    ps = ps * r2 - 1.0 / 120.0;                 /* -1/5! */
+    ps = ps * r2 + 1.0 / 6.0;                   /* 1/3! */
+    double s = r - r * (r2 * ps);
+    double pc = 1.0 / 6402373705728000.0;       /* 1/18! */
+    pc = pc * r2 - 1.0 / 20922789888000.0;      /* -1/16! */
+    pc = pc * r2 + 1.0 / 87178291200.0;         /* 1/14! */
+    pc = pc * r2 - 1.0 / 479001600.0;           /* -1/12! */
+    pc = pc * r2 + 1.0 / 3628800.0;             /* 1/10! */
+    pc = pc * r2 - 1.0 / 40320.0;               /* -1/8! */
+    pc = pc * r2 + 1.0 / 720.0;                 /* 1/6! */
+    pc = pc * r2 - 1.0 / 24.0;                  /* -1/4! */
+    pc = pc * r2 + 0.5;                         /* 1/2! */
+    double c = 1.0 - r2 * pc;
+    int q = (int)(((long long)k) & 3);
+    if (q == 0) { *s_out = s; *c_out = c; }
+    else if (q == 1) { *s_out = c; *c_out = -s; }
+    else if (q == 2) { *s_out = -s; *c_out = -c; }
+    else { *s_out = -c; *c_out = s; }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Scene                                                                      */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    const float* verts;       /* [V,3] */
+    const int32_t* tris;      /* [T,3] */
+    const int32_t* tri_patch; /* [T] */
+    int64_t n_tris;
+    const float* pf;          /* [P,17] origin, e_u, e_v, normal, inv_len2_u, inv_len2_v,
+                                 texel_area, inv_texel_area, albedo */
+    const int32_t* pres;      /* [P,2] res_u, res_v */
+    const int64_t* pbase;     /* [P] first texel */
+    int32_t n_patches;
+    int64_t n_texels;
+    const void* bvh;          /* or_bvh* or NULL for brute force */
+} or_scene;
+
+typedef struct {
+    const int32_t* type;      /* [L] 0 point, 1 spot, 2 rectangle */
+    const float* lobe_n;      /* [L] */
+    const float* size;        /* [L,2] */
+    const int32_t* layout_offsets; /* [n_layouts+1] */
+    int32_t n_lights;
+    int32_t n_layouts;
+} or_lights;
+
+static float dot3(const float* a, const float* b) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
+
+/* Moeller-Trumbore ray/triangle test, barycentric bounds widened by 2^-20.
+ * Returns 1 and t on a hit with t > 0. */
+static int ray_triangle(const float* o, const float* d, const float* v0, const float* v1, const float* v2,
+                        float* t_out)
+{
+    const float EPS = 0x1p-20f;
+    float e1[3] = {v1[0] - v0[0], v1[1] - v0[1], v1[2] - v0[2]};
+    float e2[3] = {v2[0] - v0[0], v2[1] - v0[1], v2[2] - v0[2]};
+    float p[3] = {d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0]};
+    float det = dot3(e1, p);
+    if (det == 0.0f) return 0;
+    float inv = 1.0f / det;
+    float s[3] = {o[0] - v0[0], o[1] - v0[1], o[2] - v0[2]};
+    float u = dot3(s, p) * inv;
+    if (u < -EPS || u > 1.0f + EPS) return 0;
+    float q[3] = {s[1] * e1[2] - s[2] * e1[1], s[2] * e1[0] - s[0] * e1[2], s[0] * e1[1] - s[1] * e1[0]};
+    float v = dot3(d, q) * inv;
+    if (v < -EPS || u + v > 1.0f + EPS) return 0;
+    float t = dot3(e2, q) * inv;
+    if (!(t > 0.0f)) return 0;
+    *t_out = t;
+    return 1;
+}
+
+/* closest hit = lexicographic minimum of (t, primitive id) */
+static void consider(const or_scene* S, int64_t prim, const float* o, const float* d, int32_t skip_patch,
+                     float* tb, int64_t* pb)
+{
+    if (S->tri_patch[prim] == skip_patch) return;
+    const int32_t* tr = S->tris + 3 * prim;
+    float t;
+    if (!ray_triangle(o, d, S->verts + 3 * tr[0], S->verts + 3 * tr[1], S->verts + 3 * tr[2], &t)) return;
+    if (t < *tb || (t == *tb && prim < *pb)) {
+        *tb = t;
+        *pb = prim;
+    }
+}
+
+/* ---- a plain median-split BVH (oracle-own; checked against brute force) --- */
+typedef struct {
+    double lo[3], hi[3];
+    int64_t left, right;   /* children, or -1 for a leaf */
+    int64_t first, count;  /* leaf primitive range in `order` */
+} obnode;
+
+typedef struct {
+    obnode* nodes;
+    int64_t n_nodes;
+    int64_t* order;
+    double pad;
+} or_bvh;
+
+static void tri_bounds(const float* verts, const int32_t* tr, double lo[3], double hi[3])
+{
+    for (int c = 0; c < 3; ++c) {
+        double a = verts[3 * tr[0] + c], b = verts[3 * tr[1] + c], e = verts[3 * tr[2] + c];
+        lo[c] = fmin(a, fmin(b, e));
+        hi[c] = fmax(a, fmax(b, e));
+    }
+}
+
+typedef struct { const double* key; } sort_ctx_t;
+static const double* g_sort_key;
+static int cmp_idx(const void* a, const void* b)
+{
+    double ka = g_sort_key[*(const int64_t*)a], kb = g_sort_key[*(const int64_t*)b];
+    if (ka < kb) return -1;
+    if (ka > kb) return 1;
+    int64_t ia = *(const int64_t*)a, ib = *(const int64_t*)b;
+    return (ia > ib) - (ia < ib);
+}
+
+static int64_t build_rec(or_bvh* B, const float* verts, const int32_t* tris, const double* cen,
+                         double* key, int64_t first, int64_t count)
+{
+    int64_t id = B->n_nodes++;
+    obnode* n = &B->nodes[id];
+    for (int c = 0; c < 3; ++c) { n->lo[c] = INFINITY; n->hi[c] = -INFINITY; }
+    double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = first; i < first + count; ++i) {
+        double lo[3], hi[3];
+        int64_t p = B->order[i];
+        tri_bounds(verts, tris + 3 * p, lo, hi);
+        for (int c = 0; c < 3; ++c) {
+            n->lo[c] = fmin(n->lo[c], lo[c]);
+            n->hi[c] = fmax(n->hi[c], hi[c]);
+            clo[c] = fmin(clo[c], cen[3 * p + c]);
+            chi[c] = fmax(chi[c], cen[3 * p + c]);
+        }
+    }
+    for (int c = 0; c < 3; ++c) { n->lo[c] -= B->pad; n->hi[c] += B->pad; }
+    if (count <= 4) {
+        n->left = n->right = -1;
+        n->first = first;
+        n->count = count;
+        return id;
+    }
+    int ax = 0;
+    for (int c = 1; c < 3; ++c)
+        if (chi[c] - clo[c] > chi[ax] - clo[ax]) ax = c;
+    for (int64_t i = first; i < first + count; ++i) key[B->order[i]] = cen[3 * B->order[i] + ax];
+    g_sort_key = key;
+    qsort(B->order + first, (size_t)count, sizeof(int64_t), cmp_idx);
+    int64_t half = count / 2;
+    int64_t l = build_rec(B, verts, tris, cen, key, first, half);
+    int64_t r = build_rec(B, verts, tris, cen, key, first + half, count - half);
+    n = &B->nodes[id];
+    n->left = l;
+    n->right = r;
+    n->first = n->count = 0;
+    return id;
+}
+
+/* Build the oracle's BVH.  Node boxes are padded by `pad` (metres) so the
+ * FP64 slab test below can never reject a box that holds an accepted hit. */
+EXPORT void* or_bvh_build(const float* verts, const int32_t* tris, int64_t n_tris, double pad)
+{
+    or_bvh* B = (or_bvh*)calloc(1, sizeof(or_bvh));
+    B->nodes = (obnode*)calloc((size_t)(2 * n_tris + 1), sizeof(obnode));
+    B->order = (int64_t*)malloc((size_t)n_tris * sizeof(int64_t));
+    B->pad = pad;
+    double* cen = (double*)malloc((size_t)n_tris * 3 * sizeof(double));
+    double* key = (double*)malloc((size_t)n_tris * sizeof(double));
+    for (int64_t p = 0; p < n_tris; ++p) {
+        B->order[p] = p;
+        for (int c = 0; c < 3; ++c)
+            cen[3 * p + c] = ((double)verts[3 * tris[3 * p] + c] + verts[3 * tris[3 * p + 1] + c] +
+                              verts[3 * tris[3 * p + 2] + c]) / 3.0;
+    }
+    if (n_tris > 0) build_rec(B, verts, tris, cen, key, 0, n_tris);
+    free(cen);
+    free(key);
+    return B;
+}
+
+EXPORT void or_bvh_free(void* p)
+{
+    or_bvh* B = (or_bvh*)p;
+    if (!B) return;
+    free(B->nodes);
+    free(B->order);
+    free(B);
+}
+
+static int box_hit(const obnode* n, const double* o, const double* inv, double tmax)
+{
+    double t0 = 0.0, t1 = tmax;
+    for (int c = 0; c < 3; ++c) {
+        double a = (n->lo[c] - o[c]) * inv[c], b = (n->hi[c] - o[c]) * inv[c];
+        if (a > b) { double tmp = a; a = b; b = tmp; }
+        if (a > t0) t0 = a;
+        if (b < t1) t1 = b;
+    }
+    return t0 <= t1;
+}
+
+/* Closest hit of ray (o, d) skipping every triangle of patch skip_patch.
+ * Returns the primitive or -1 for a miss. */
+static int64_t intersect(const or_scene* S, const float* o, const float* d, int32_t skip_patch, float* t_out)
+{
+    float tb = INFINITY;
+    int64_t pb = -1;
+    if (!S->bvh) {
+        for (int64_t p = 0; p < S->n_tris; ++p) consider(S, p, o, d, skip_patch, &tb, &pb);
+    } else {
+        const or_bvh* B = (const or_bvh*)S->bvh;
+        double od[3], inv[3];
+        for (int c = 0; c < 3; ++c) {
+            od[c] = o[c];
+            double dc = d[c];
+            inv[c] = 1.0 / (dc != 0.0 ? dc : (signbit(dc) ? -1e-300 : 1e-300));
+        }
+        int64_t stack[256];
+        int sp = 0;
+        if (B->n_nodes > 0) stack[sp++] = 0;
+        while (sp > 0) {
+            const obnode* n = &B->nodes[stack[--sp]];
+            double tmax = isinf(tb) ? INFINITY : (double)tb;
+            if (!box_hit(n, od, inv, tmax)) continue;
+            if (n->left < 0) {
+                for (int64_t i = n->first; i < n->first + n->count; ++i)
+                    consider(S, B->order[i], o, d, skip_patch, &tb, &pb);
+            } else {
+                stack[sp++] = n->left;
+                stack[sp++] = n->right;
+            }
+        }
+    }
+    *t_out = tb;
+    return pb;
+}
+
+/* batch entry for the brute-force / BVH equivalence pin */
+EXPORT void or_intersect_batch(const or_scene* S, const float* rays, int64_t n, const int32_t* skip,
+                               float* t_out, int64_t* prim_out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        prim_out[i] = intersect(S, rays + 6 * i, rays + 6 * i + 3, skip ? skip[i] : -1, &t_out[i]);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Luminaires: frame R = R_y(beta) R_x(alpha), axis d = R(0,0,-1),            */
+/* tangent t = R(1,0,0), bitangent b = R(0,1,0), and their angle derivatives. */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int type;
+    float n, w, h;
+    float c[3], d[3], t[3], b[3];
+    float dd_da[3], dd_db[3], dt_db[3], db_da[3], db_db[3];
+    float P, phi_r;
+    int64_t n_paths;
+} olight;
+
+static void light_setup(const or_lights* Ls, const float* params, int gl, int64_t n_paths, olight* L)
+{
+    const float* p = params + 6 * gl;
+    L->type = Ls->type[gl];
+    L->n = Ls->lobe_n[gl];
+    L->w = Ls->size[2 * gl];
+    L->h = Ls->size[2 * gl + 1];
+    for (int c = 0; c < 3; ++c) L->c[c] = p[c];
+    double sa_d, ca_d, sb_d, cb_d;
+    or_sincos_f64((double)p[3], &sa_d, &ca_d);
+    or_sincos_f64((double)p[4], &sb_d, &cb_d);
+    float sa = (float)sa_d, ca = (float)ca_d, sb = (float)sb_d, cb = (float)cb_d;
+    L->d[0] = -(sb * ca); L->d[1] = sa; L->d[2] = -(cb * ca);
+    L->t[0] = cb; L->t[1] = 0.0f; L->t[2] = -sb;
+    L->b[0] = sb * sa; L->b[1] = ca; L->b[2] = cb * sa;
+    L->dd_da[0] = sb * sa; L->dd_da[1] = ca; L->dd_da[2] = cb * sa;
+    L->dd_db[0] = -(cb * ca); L->dd_db[1] = 0.0f; L->dd_db[2] = sb * ca;
+    L->dt_db[0] = -sb; L->dt_db[1] = 0.0f; L->dt_db[2] = -cb;
+    L->db_da[0] = sb * ca; L->db_da[1] = -sa; L->db_da[2] = cb * ca;
+    L->db_db[0] = cb * sa; L->db_db[1] = 0.0f; L->db_db[2] = -(sb * sa);
+    L->P = p[5];
+    L->n_paths = n_paths;
+    L->phi_r = p[5] / (float)n_paths;
+}
+
+static int64_t paths_of_light(int64_t n_layout, int n_in_layout, int l)
+{
+    return n_layout / n_in_layout + ((int64_t)l < n_layout % n_in_layout ? 1 : 0);
+}
+
+/* ---- one path ------------------------------------------------------------ */
+typedef struct {
+    int64_t* S;            /* forward: texel accumulators of this layout (or NULL) */
+    const float* g;        /* adjoint: dO/dE of this layout (or NULL) */
+    double* acc;           /* adjoint: per-light gradient accumulator [6] */
+    float* contrib;        /* record: per-path contribution [6] (or NULL) */
+    int32_t* rec_prim;     /* record: [B] (or NULL) */
+    int32_t* rec_texel;    /* record: [B] */
+    int64_t misses;
+} path_io;
+
+/* dlog of the first-hit irradiance kernel w.r.t. (c, alpha, beta, P), x_1 fixed:
+ * log E = log P + n log(d.w) + log(-n1.w) - 2 log r + const, w = (x1 - y)/r. */
+static void first_hit_dlog(const olight* L, const float* x1, const float* y, const float* n1, float au,
+                           float av, float dl[6])
+{
+    for (int c = 0; c < 5; ++c) dl[c] = 0.0f;
+    dl[5] = 1.0f / L->P;
+    float v[3] = {x1[0] - y[0], x1[1] - y[1], x1[2] - y[2]};
+    float r2 = dot3(v, v);
+    if (r2 <= 1e-12f) return;
+    float r = sqrtf(r2);
+    float inv_r = 1.0f / r;
+    float w[3] = {v[0] * inv_r, v[1] * inv_r, v[2] * inv_r};
+    float c1 = -dot3(n1, w);
+    if (c1 <= 1e-6f) return;
+    float k1 = 1.0f / (r * c1);
+    float k3 = 2.0f * inv_r;
+    float G[3];
+    if (L->type == 0) {
+        for (int c = 0; c < 3; ++c) G[c] = (n1[c] + c1 * w[c]) * k1 + w[c] * k3;
+        for (int c = 0; c < 3; ++c) dl[c] = G[c];
+        return;
+    }
+    float ce = dot3(L->d, w);
+    if (ce <= 1e-6f) return;
+    float ka = L->n / (r * ce);
+    for (int c = 0; c < 3; ++c) {
+        float t1 = -((L->d[c] - ce * w[c]) * ka);
+        float t2 = (n1[c] + c1 * w[c]) * k1;
+        float t3 = w[c] * k3;
+        G[c] = (t1 + t2) + t3;
+    }
+    float kd = L->n / ce;
+    float ra = dot3(L->dd_da, w) * kd;
+    float rb = dot3(L->dd_db, w) * kd;
+    if (L->type == 2) {
+        float dya[3], dyb[3];
+        for (int c = 0; c < 3; ++c) {
+            dya[c] = av * L->db_da[c];
+            dyb[c] = au * L->dt_db[c] + av * L->db_db[c];
+        }
+        ra = dot3(G, dya) + ra;
+        rb = dot3(G, dyb) + rb;
+    }
+    dl[0] = G[0]; dl[1] = G[1]; dl[2] = G[2];
+    dl[3] = ra; dl[4] = rb;
+}
+
+static void trace_path(const or_scene* S, const olight* L, int layout, int l_local, uint32_t i, uint64_t seed,
+                       int B, path_io* io)
+{
+    const uint32_t stream = ((uint32_t)layout << 16) | (uint32_t)l_local;
+    float u[4];
+    draw4(seed, i, stream, 0u, u);
+    /* emission: origin y, direction w0 (Alg. 1 "generate exitant ray") */
+    float y[3] = {L->c[0], L->c[1], L->c[2]};
+    float dir[3];
+    float au = 0.0f, av = 0.0f;
+    if (L->type == 0) {
+        float z = 1.0f - 2.0f * u[2];
+        float rr = sqrtf(fmaxf(0.0f, 1.0f - z * z));
+        float sp, cp;
+        or_sincos2pi(u[3], &sp, &cp);
+        dir[0] = rr * cp; dir[1] = rr * sp; dir[2] = z;
+    } else {
+        float ct = 0.0f;
+        if (u[2] > 0.0f) ct = or_exp2(or_log2(u[2]) / (L->n + 1.0f));
+        float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+        float sp, cp;
+        or_sincos2pi(u[3], &sp, &cp);
+        float a = st * cp, bb = st * sp;
+        for (int c = 0; c < 3; ++c) dir[c] = (a * L->t[c] + bb * L->b[c]) + ct * L->d[c];
+        if (L->type == 2) {
+            au = (u[0] - 0.5f) * L->w;
+            av = (u[1] - 0.5f) * L->h;
+            for (int c = 0; c < 3; ++c) y[c] = (L->c[c] + au * L->t[c]) + av * L->b[c];
+        }
+    }
+    float o[3] = {y[0], y[1], y[2]};
+    int32_t skip = -1;
+    float T = 1.0f;
+    float s_r = 0.0f;
+    float dphi[6] = {0, 0, 0, 0, 0, 0};
+    int hits = 0;
+    for (int h = 1; h <= B; ++h) {
+        float t;
+        int64_t prim = intersect(S, o, dir, skip, &t);
+        if (prim < 0) {
+            io->misses++;
+            break;
+        }
+        hits = h;
+        float x[3];
+        for (int c = 0; c < 3; ++c) x[c] = o[c] + t * dir[c];
+        int32_t q = S->tri_patch[prim];
+        const float* pf = S->pf + 17 * (int64_t)q;
+        float du[3] = {x[0] - pf[0], x[1] - pf[1], x[2] - pf[2]};
+        float su = dot3(du, pf + 3) * pf[12];
+        float sv = dot3(du, pf + 6) * pf[13];
+        int32_t ru = S->pres[2 * q], rv = S->pres[2 * q + 1];
+        int32_t iu = (int32_t)floorf(su * (float)ru);
+        int32_t iv = (int32_t)floorf(sv * (float)rv);
+        if (iu < 0) iu = 0;
+        if (iu > ru - 1) iu = ru - 1;
+        if (iv < 0) iv = 0;
+        if (iv > rv - 1) iv = rv - 1;
+        int64_t k = S->pbase[q] + (int64_t)iv * ru + iu;
+        float inv_a = pf[15];
+        const float* nq = pf + 9;
+        float nd = dot3(nq, dir);
+        float no[3];
+        if (nd < 0.0f) { no[0] = nq[0]; no[1] = nq[1]; no[2] = nq[2]; }
+        else { no[0] = -nq[0]; no[1] = -nq[1]; no[2] = -nq[2]; }
+        if (io->S) {
+            float val = (L->phi_r * T) * inv_a;
+            long long code = llrintf(val * 4294967296.0f);
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+            io->S[k] += code;
+        }
+        if (io->g) {
+            s_r = s_r + (io->g[k] * inv_a) * T;
+            if (h == 1) {
+                float dl[6];
+                first_hit_dlog(L, x, y, no, au, av, dl);
+                for (int c = 0; c < 6; ++c) dphi[c] = L->phi_r * dl[c];
+            }
+        }
+        if (io->rec_prim) {
+            io->rec_prim[h - 1] = (int32_t)prim;
+            io->rec_texel[h - 1] = (int32_t)k;
+        }
+        if (h == B) break;
+        /* cosine-weighted bounce about the oriented normal (Malley's method in
+         * the Duff et al. 2017 orthonormal basis); Phi_{i+1} = Phi_i rho. */
+        float ub[4];
+        draw4(seed, i, stream, 1u + (uint32_t)h, ub);
+        float sign = copysignf(1.0f, no[2]);
+        float a = -1.0f / (sign + no[2]);
+        float bxy = (no[0] * no[1]) * a;
+        float b1[3] = {1.0f + ((sign * no[0]) * no[0]) * a, sign * bxy, -(sign * no[0])};
+        float b2[3] = {bxy, sign + (no[1] * no[1]) * a, -no[1]};
+        float rr = sqrtf(ub[0]);
+        float sp, cp;
+        or_sincos2pi(ub[1], &sp, &cp);
+        float lx = rr * cp, ly = rr * sp;
+        float lz = sqrtf(fmaxf(0.0f, 1.0f - ub[0]));
+        for (int c = 0; c < 3; ++c) dir[c] = (lx * b1[c] + ly * b2[c]) + lz * no[c];
+        for (int c = 0; c < 3; ++c) o[c] = x[c];
+        skip = q;
+        T = T * pf[16];
+    }
+    if (io->g && hits >= 1) {
+        for (int c = 0; c < 6; ++c) {
+            float cr = s_r * dphi[c];
+            if (io->acc) io->acc[c] += (double)cr;
+            if (io->contrib) io->contrib[c] = cr;
+        }
+    } else if (io->contrib) {
+        for (int c = 0; c < 6; ++c) io->contrib[c] = 0.0f;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Entry points                                                               */
+/* ------------------------------------------------------------------------- */
+
+/* Primal light tracing (Alg. 1).  S_out: [n_layouts, K] int64, overwritten.
+ * limit_per_light > 0 traces only the first paths of each light (still with
+ * Phi_r = P / N_l of the full path count). */
+EXPORT int64_t or_forward(const or_scene* S, const or_lights* Ls, const float* params, uint64_t seed,
+                          int64_t paths_per_layout, int max_hits, int64_t limit_per_light, int n_threads,
+                          int64_t* S_out)
+{
+    memset(S_out, 0, (size_t)(S->n_texels * Ls->n_layouts) * sizeof(int64_t));
+    int64_t misses = 0;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+    for (int j = 0; j < Ls->n_layouts; ++j) {
+        int l0 = Ls->layout_offsets[j], l1 = Ls->layout_offsets[j + 1];
+        for (int gl = l0; gl < l1; ++gl) {
+            olight L;
+            int64_t nl = paths_of_light(paths_per_layout, l1 - l0, gl - l0);
+            light_setup(Ls, params, gl, nl, &L);
+            int64_t lim = (limit_per_light > 0 && limit_per_light < nl) ? limit_per_light : nl;
+            int64_t m = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : m)
+#endif
+            for (int64_t i = 0; i < lim; ++i) {
+                path_io io;
+                memset(&io, 0, sizeof(io));
+                io.S = S_out + (int64_t)j * S->n_texels;
+                trace_path(S, &L, j, gl - l0, (uint32_t)i, seed, max_hits, &io);
+                m += io.misses;
+            }
+            misses += m;
+        }
+    }
+    return misses;
+}
+
+/* Adjoint light tracing (Alg. 2).  dOdE: [n_layouts, K]; grad_out: [L,6] FP64. */
+EXPORT int64_t or_adjoint(const or_scene* S, const or_lights* Ls, const float* params, uint64_t seed,
+                          int64_t paths_per_layout, int max_hits, int64_t limit_per_light, int n_threads,
+                          const float* dOdE, double* grad_out)
+{
+    int64_t misses = 0;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+    for (int j = 0; j < Ls->n_layouts; ++j) {
+        int l0 = Ls->layout_offsets[j], l1 = Ls->layout_offsets[j + 1];
+        for (int gl = l0; gl < l1; ++gl) {
+            olight L;
+            int64_t nl = paths_of_light(paths_per_layout, l1 - l0, gl - l0);
+            light_setup(Ls, params, gl, nl, &L);
+            int64_t lim = (limit_per_light > 0 && limit_per_light < nl) ? limit_per_light : nl;
+            double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+            int64_t m = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : a0, a1, a2, a3, a4, a5, m)
+#endif
+            for (int64_t i = 0; i < lim; ++i) {
+                double acc[6] = {0, 0, 0, 0, 0, 0};
+                path_io io;
+                memset(&io, 0, sizeof(io));
+                io.g = dOdE + (int64_t)j * S->n_texels;
+                io.acc = acc;
+                trace_path(S, &L, j, gl - l0, (uint32_t)i, seed, max_hits, &io);
+                a0 += acc[0]; a1 += acc[1]; a2 += acc[2]; a3 += acc[3]; a4 += acc[4]; a5 += acc[5];
+                m += io.misses;
+            }
+            double* g = grad_out + 6 * (int64_t)gl;
+            g[0] = a0; g[1] = a1; g[2] = a2; g[3] = a3; g[4] = a4; g[5] = a5;
+            misses += m;
+        }
+    }
+    return misses;
+}
+
+/* Hit sequences (primitive and texel per hit, -1 = none) of paths
+ * [first, first+count) of one light; with dOdE also the per-path
+ * contribution dO/dPhi_r * dPhi_r/dp [count,6]. */
+EXPORT void or_record(const or_scene* S, const or_lights* Ls, const float* params, uint64_t seed,
+                      int64_t paths_per_layout, int max_hits, int layout, int l_local, int64_t first,
+                      int64_t count, int32_t* prim_out, int32_t* texel_out, const float* dOdE, float* contrib)
+{
+    int l0 = Ls->layout_offsets[layout], l1 = Ls->layout_offsets[layout + 1];
+    int gl = l0 + l_local;
+    olight L;
+    light_setup(Ls, params, gl, paths_of_light(paths_per_layout, l1 - l0, l_local), &L);
+    for (int64_t r = 0; r < count; ++r) {
+        path_io io;
+        memset(&io, 0, sizeof(io));
+        for (int h = 0; h < max_hits; ++h) {
+            prim_out[r * max_hits + h] = -1;
+            texel_out[r * max_hits + h] = -1;
+        }
+        io.rec_prim = prim_out + r * max_hits;
+        io.rec_texel = texel_out + r * max_hits;
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        if (dOdE) {
+            io.g = dOdE + (int64_t)layout * S->n_texels;
+            io.acc = acc;
+            io.contrib = contrib + 6 * r;
+        }
+        trace_path(S, &L, layout, l_local, (uint32_t)(first + r), seed, max_hits, &io);
+    }
+}
+
+/* E_k = S_k 2^-32 (Q31.32 fixed point to float through FP64). */
+EXPORT void or_fixed_to_float(const int64_t* S, int64_t n, float* E)
+{
+    for (int64_t k = 0; k < n; ++k) E[k] = (float)((double)S[k] * 0x1p-32);
+}
+
+/* Eq. objective with alpha_l = 1: O = 1/2 sum_k A_k alpha_k (E_k - E*_k)^2
+ * (FP64 sum); g_k = (A_k alpha_k)(E_k - E*_k) in FP32.  A is per texel and
+ * repeats for every layout (n = n_layouts * K). */
+EXPORT double or_objective(const float* E, const float* Et, const float* alpha, const float* A, int64_t K,
+                           int64_t n, float* g)
+{
+    double O = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        float a = A[i % K];
+        float al = alpha ? alpha[i] : 1.0f;
+        if (g) g[i] = (a * al) * (E[i] - Et[i]);
+        double e = (double)E[i] - (double)Et[i];
+        O += (double)a * (double)al * e * e;
+    }
+    return 0.5 * O;
+}
+
+/* light frame as the oracle computes it: [L, 3+3+3+3+15+2] for the pins */
+EXPORT void or_light_frames(const or_lights* Ls, const float* params, int64_t paths_per_layout, float* out)
+{
+    for (int j = 0; j < Ls->n_layouts; ++j) {
+        int l0 = Ls->layout_offsets[j], l1 = Ls->layout_offsets[j + 1];
+        for (int gl = l0; gl < l1; ++gl) {
+            olight L;
+            light_setup(Ls, params, gl, paths_of_light(paths_per_layout, l1 - l0, gl - l0), &L);
+            float* o = out + 29 * (int64_t)gl;
+            memcpy(o, L.c, 12); memcpy(o + 3, L.d, 12); memcpy(o + 6, L.t, 12); memcpy(o + 9, L.b, 12);
+            memcpy(o + 12, L.dd_da, 12); memcpy(o + 15, L.dd_db, 12); memcpy(o + 18, L.dt_db, 12);
+            memcpy(o + 21, L.db_da, 12); memcpy(o + 24, L.db_db, 12);
+            o[27] = L.phi_r;
+            o[28] = (float)L.n_paths;
+        }
+    }
+}
+
+/* the first-hit derivative alone, for the closed-form pins */
+EXPORT void or_first_hit_dlog(const or_lights* Ls, const float* params, int gl, const float* x1,
+                              const float* y, const float* n1, float au, float av, float* dl)
+{
+    olight L;
+    light_setup(Ls, params, gl, 1, &L);
+    first_hit_dlog(&L, x1, y, n1, au, av, dl);
+}
+
+EXPORT int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

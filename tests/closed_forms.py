@@ -1,0 +1,121 @@
+"""Independent closed forms and quadratures used to pin the oracle.
+
+Nothing here calls the oracle or the GPU path.  Everything is float64 numpy
+written from radiometry: solid angles of rectangles, Gauss-Legendre
+integration of an emitter's irradiance over texels, and the log-irradiance
+of a luminaire at a fixed receiver point (for derivative checks).
+"""
+import numpy as np
+
+
+def rot_y(b):
+    c, s = np.cos(b), np.sin(b)
+    return np.array([[c, 0, s], [0, 1, 0], [-s, 0, c]])
+
+
+def rot_x(a):
+    c, s = np.cos(a), np.sin(a)
+    return np.array([[1, 0, 0], [0, c, -s], [0, s, c]])
+
+
+def frame(alpha, beta):
+    """Light frame R = R_y(beta) R_x(alpha): axis d = R(0,0,-1), t = R e_x, b = R e_y."""
+    R = rot_y(beta) @ rot_x(alpha)
+    return R @ np.array([0, 0, -1.0]), R[:, 0], R[:, 1]
+
+
+def corner_solid_angle(a, b, h):
+    """Solid angle of the rectangle [0,a] x [0,b] (signed) seen from height h."""
+    return np.arctan(a * b / (h * np.sqrt(a * a + b * b + h * h)))
+
+
+def rect_solid_angle(x0, x1, y0, y1, h):
+    f = corner_solid_angle
+    return f(x1, y1, h) - f(x0, y1, h) - f(x1, y0, h) + f(x0, y0, h)
+
+
+def corner_form_factor(a, b, h):
+    """Differential-area (facing the plane) to corner rectangle [0,a]x[0,b] on a
+    parallel plane at distance h (signed in a, b)."""
+    X, Y = a / h, b / h
+    sx, sy = np.sqrt(1 + X * X), np.sqrt(1 + Y * Y)
+    return (X / sx * np.arctan(Y / sx) + Y / sy * np.arctan(X / sy)) / (2 * np.pi)
+
+
+def rect_form_factor(x0, x1, y0, y1, h):
+    f = corner_form_factor
+    return f(x1, y1, h) - f(x0, y1, h) - f(x1, y0, h) + f(x0, y0, h)
+
+
+def gauss_legendre(n):
+    x, w = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (x + 1.0), 0.5 * w   # on [0,1]
+
+
+def plane_texels(half, res):
+    """Texel rectangles of plane_scene: x-index i runs along +x, j along +y."""
+    edges = np.linspace(-half, half, res + 1)
+    i = np.arange(res)
+    x0, x1 = edges[i], edges[i + 1]
+    X0, Y0 = np.meshgrid(x0, x0, indexing="xy")
+    X1, Y1 = np.meshgrid(x1, x1, indexing="xy")
+    # texel k = j*res + i  -> rows j (y), columns i (x)
+    return X0.ravel(), X1.ravel(), Y0.ravel(), Y1.ravel()
+
+
+def lobe_density(kind, n, d, w):
+    """Direction pdf of a luminaire (per steradian) for unit directions w."""
+    if kind == 0:
+        return np.full(w.shape[:-1], 1.0 / (4 * np.pi))
+    c = w @ d
+    return np.where(c > 0, (n + 1) / (2 * np.pi) * np.clip(c, 0, None) ** n, 0.0)
+
+
+def plane_hit_probability(kind, n, p, size, half, res, q_tex=6, q_light=4):
+    """Probability that one emitted path first hits each texel of the z=0
+    plane_scene (texel order k = j*res + i)."""
+    c = np.asarray(p[:3], np.float64)
+    d, t, b = frame(p[3], p[4])
+    x0, x1, y0, y1 = plane_texels(half, res)
+    gx, gw = gauss_legendre(q_tex)
+    pts_u, pts_w = np.meshgrid(gx, gx, indexing="ij"), np.outer(gw, gw)
+    fu, fv = pts_u[0].ravel(), pts_u[1].ravel()
+    wq = pts_w.ravel()
+    X = x0[:, None] + (x1 - x0)[:, None] * fu[None, :]
+    Y = y0[:, None] + (y1 - y0)[:, None] * fv[None, :]
+    area = ((x1 - x0) * (y1 - y0))[:, None]
+    if kind == 2:
+        lx, lw = gauss_legendre(q_light)
+        su, sv = np.meshgrid(lx, lx, indexing="ij")
+        sw = np.outer(lw, lw).ravel()
+        au = (su.ravel() - 0.5) * size[0]
+        av = (sv.ravel() - 0.5) * size[1]
+        origins = c[None, :] + au[:, None] * t[None, :] + av[:, None] * b[None, :]
+    else:
+        origins = c[None, :]
+        sw = np.ones(1)
+    prob = np.zeros(X.shape[0])
+    for o, ow in zip(origins, sw):
+        v = np.stack([X - o[0], Y - o[1], -np.full_like(X, o[2])], -1)
+        r = np.linalg.norm(v, axis=-1)
+        w = v / r[..., None]
+        dens = lobe_density(kind, n, d, w)
+        cos_i = o[2] / r          # receiver normal +z, emitter above
+        prob += ow * np.sum(dens * cos_i / r ** 2 * wq[None, :] * area, axis=1)
+    return prob
+
+
+def log_irradiance(kind, n, p, x1, n1, au=0.0, av=0.0):
+    """log of the first-hit irradiance kernel at receiver x1 with unit normal
+    n1 (facing the light), up to p-independent constants: a luminaire of power
+    P with direction pdf ~ cos^n about its axis, origin c + a_u t + a_v b."""
+    c = np.asarray(p[:3], np.float64)
+    d, t, b = frame(p[3], p[4])
+    y = c + au * t + av * b
+    v = np.asarray(x1, np.float64) - y
+    r = np.linalg.norm(v)
+    w = v / r
+    val = np.log(p[5]) + np.log(-np.dot(n1, w)) - 2 * np.log(r)
+    if kind != 0:
+        val += n * np.log(np.dot(d, w))
+    return val
