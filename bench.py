@@ -1,0 +1,179 @@
+"""Benchmark: light paths/s (forward + adjoint) on one MI355X.
+
+Workload: the procedural 30 x 20 x 3 m office (about 200k triangles, about
+4M texels at about 2 cm, 16 rectangular cos^n luminaires), 2^26 light paths
+per step, 5 hits per path.  One step is the whole hot path: luminaire setup,
+accumulator clear, primal light tracing, fixed-point to float, objective and
+dO/dE, adjoint light tracing, per-light gradient reduction.  Inputs are
+resident in HBM before the timed region.
+
+Prints one JSON line (metric, value, roofline of the dominant kernel, and the
+CPU oracle timed on a bounded sample of the same workload).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "light paths/s (forward+adjoint); gradient-error×time vs plain tracer"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+# Algorithmic work per unit (see the design notes): one node visit = two box
+# tests of 20 ops and a 64 B node; one triangle test = 40 ops and a 48 B record;
+# one hit = an 80 B patch record plus an 8 B atomic (forward) / 4 B gather (adjoint).
+OPS_PER_BOX, OPS_PER_TRI = 20, 40
+NODE_BYTES, TRI_BYTES, PATCH_BYTES = 64, 48, 80
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(scene, lights, seed, ppl, B, target_seconds):
+    """The oracle as it stands, on the host cores, on a bounded sample: the
+    first m paths of every luminaire (same Phi_r), forward + objective +
+    adjoint; paths/s over that sample."""
+    import oracle
+    oracle.build(force=False)
+    osc = oracle.OracleScene(scene, use_bvh=True)
+    ol = oracle.OracleLights(lights)
+    A = scene.texel_area()
+    Et = None
+
+    def run(m):
+        nonlocal Et
+        t0 = time.perf_counter()
+        S, _ = oracle.forward(osc, ol, lights.params, seed, ppl, B, limit_per_light=m)
+        t1 = time.perf_counter()
+        E = oracle.fixed_to_float(S)
+        if Et is None:
+            import lt_inputs as li
+            Et = li.painted_target(scene, 0.5)[None]
+        _, g = oracle.objective(E, Et, A)
+        t2 = time.perf_counter()
+        oracle.adjoint(osc, ol, lights.params, seed, ppl, B, g, limit_per_light=m)
+        t3 = time.perf_counter()
+        return (t1 - t0) + (t3 - t2)
+
+    m = 256
+    dt = run(m)
+    m2 = int(max(256, min(1 << 20, m * target_seconds / max(dt, 1e-3))))
+    dt2 = run(m2)
+    n = m2 * lights.n_lights
+    return {"value": n / dt2, "unit": "paths/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"first {m2} paths of each of the {lights.n_lights} luminaires ({n} paths, "
+                      f"{B} hits, forward+adjoint, {dt2:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--paths", type=int, default=1 << 26)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tuning", type=str, default="", help="k=v,... launch tuning override")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of this "
+              f"path is described in the design notes and not launched here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import lt_inputs as li
+    from paper_2310_02043_amd import Context
+
+    c2 = li.office()
+    scene, lights = c2["scene"], c2["lights"]
+    N, B, seed = args.paths, c2["max_hits"], c2["seed"]
+    ctx = Context(0)
+    ctx.upload_scene(scene.verts, scene.tris, scene.tri_patch, scene.patches)
+    ctx.set_lights(lights.static, lights.layout_offsets)
+    if args.tuning:
+        ctx.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))})
+    info = ctx.info()
+    log("scene", info)
+    dev = "cuda:0"
+    p = torch.tensor(lights.params, device=dev)
+    Et = torch.tensor(li.painted_target(scene, 0.5)[None], device=dev)
+    K = scene.n_texels
+    S = torch.empty((1, K), dtype=torch.int64, device=dev)
+    E = torch.empty((1, K), dtype=torch.float32, device=dev)
+    g = torch.empty((1, K), dtype=torch.float32, device=dev)
+    O = torch.empty(1, dtype=torch.float64, device=dev)
+    grad = torch.empty((lights.n_lights, 6), dtype=torch.float32, device=dev)
+    cfg = ctx.cfg(seed, N, B)
+
+    def step():
+        ctx.trace_forward(p, cfg, S=S, E=E)
+        ctx.objective(E, Et, g=g, O=O)
+        ctx.trace_adjoint(p, g, cfg, grad=grad)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    ctx.sync()
+    # algorithmic work of one pass (instrumented forward kernel, untimed)
+    stats = ctx.trace_stats(p, cfg)
+    log("work per pass", stats)
+
+    ctx.timing_read()
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_timing(False)
+    flags = ctx.sync()
+    fwd_ms, nf, adj_ms, na = ctx.timing_read()
+    ms_step = (t1 - t0) * 1000.0 / args.steps
+    value = N / (ms_step / 1000.0)
+    fwd_avg, adj_avg = fwd_ms / max(nf, 1), adj_ms / max(na, 1)
+    log(f"step {ms_step:.2f} ms  fwd kernel {fwd_avg:.2f} ms  adj kernel {adj_avg:.2f} ms  flags {flags}")
+
+    dominant = "adjoint" if adj_avg >= fwd_avg else "forward"
+    dur_s = max(fwd_avg, adj_avg) / 1000.0
+    ops = 2 * OPS_PER_BOX * stats["nodes"] + OPS_PER_TRI * stats["tri_tests"]
+    byt = NODE_BYTES * stats["nodes"] + TRI_BYTES * stats["tri_tests"] + \
+        (PATCH_BYTES + (4 if dominant == "adjoint" else 8)) * stats["hits"]
+    tflops = ops / dur_s / 1e12
+    gbs = byt / dur_s / 1e9
+    roof_alu = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": None}
+    roof_mem = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+    roofline = dict(roof_alu if roof_alu["frac"] >= roof_mem["frac"] else roof_mem)
+    roofline.update({"kernel": f"k_trace ({dominant})", "kernel_ms": round(max(fwd_avg, adj_avg), 3),
+                     "other": roof_mem if roofline["bound"] == "alu" else roof_alu,
+                     "work_per_launch": stats})
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "paths/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+i64", "data": "synthetic",
+        "config": {"workload": f"procedural office 30x20x3 m, {scene.n_tris} triangles, {K} texels, "
+                               f"{lights.n_lights} rectangular cos^n luminaires, {N} paths, {B} hits",
+                   "paths": N, "max_hits": B, "triangles": scene.n_tris, "texels": K,
+                   "luminaires": lights.n_lights, "parallelism": "single GPU"},
+        "fwd_kernel_ms": round(fwd_avg, 3), "adj_kernel_ms": round(adj_avg, 3),
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(scene, lights, seed, N, B, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * lt.h -- C ABI of the MI355X light-tracing library (liblt.so).
+ *
+ * The library implements the hot path of view-independent adjoint light
+ * tracing (Lipp et al., "View-Independent Adjoint Light Tracing for Lighting
+ * Design Optimization"): a primal light-tracing pass that splats the flux of
+ * light paths into per-surface texels, and an adjoint pass that replays the
+ * same paths and returns dO/dp for every luminaire parameter.  All work runs
+ * in hand-written HIP kernels for gfx950.
+ *
+ * Conventions
+ *   - Every function returns LT_OK (0) or a negative LT_E* code and never
+ *     throws.  lt_last_error() gives a message owned by the context.
+ *   - Arguments named h_* are host pointers, d_* are device pointers on the
+ *     context's device.  The caller owns every d_* buffer; output buffers are
+ *     overwritten completely (never accumulated into).  The context owns the
+ *     scene, its BVH, the luminaire tables and all internal scratch.
+ *   - All device work is enqueued on the context's stream (lt_set_stream) and
+ *     is asynchronous; argument validation is synchronous.  Device-side
+ *     conditions (fixed-point overflow) surface in lt_sync().
+ *   - One context per host thread; calls on one context are not thread-safe.
+ *
+ * Paper notation: Phi_r flux per light ray, E_k irradiance of texel k (the
+ * n = 0 coefficient of the radiance data structure up to the constant
+ * rho_k / pi), A_k texel area, alpha_k texel weight, p = (c_x, c_y, c_z,
+ * alpha, beta, P) per luminaire.
+ */
+#ifndef LT_H
+#define LT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LT_OK 0
+#define LT_EINVAL (-1)    /* bad argument (shape, range, NaN, missing state) */
+#define LT_ENOMEM (-2)    /* device allocation failed */
+#define LT_EHIP (-3)      /* HIP runtime error (message in lt_last_error) */
+#define LT_ESTATE (-4)    /* call order violated (e.g. trace before upload) */
+#define LT_EOVERFLOW (-5) /* a texel accumulator reached 2^62 (fixed point) */
+
+/* lt_trace_cfg.flags */
+#define LT_FLAG_GRAPH 1u    /* replay the launch sequence as a captured hipGraph */
+#define LT_FLAG_PROPOSAL 2u /* sample emission from the learned proposal (MIS) */
+
+/* lt_sync flags_out bits */
+#define LT_STATUS_OVERFLOW 1u  /* a texel accumulator reached 2^62 */
+#define LT_STATUS_TRAVERSAL 2u /* a traversal exceeded its node-visit bound (malformed BVH) */
+
+typedef struct lt_ctx lt_ctx;
+
+/* A planar rectangular surface patch with a res_u x res_v texel grid.
+ * Triangles of the scene reference patches; a hit point x on patch q falls in
+ * texel texel_base + j*res_u + i with
+ *   i = clamp(floor(((x - origin).e_u * inv_len2_u) * res_u), 0, res_u-1)
+ * and likewise j with e_v.  All constants are given (never recomputed). */
+typedef struct {
+    float origin[3];
+    float e_u[3];
+    float e_v[3];
+    float normal[3];        /* unit normal of the plane (either side) */
+    float inv_len2_u;       /* 1/|e_u|^2 */
+    float inv_len2_v;       /* 1/|e_v|^2 */
+    float texel_area;       /* A_k of each texel of the patch (m^2) */
+    float inv_texel_area;   /* 1/A_k */
+    float albedo;           /* Lambertian reflectance rho in [0,1] */
+    int32_t res_u, res_v;
+    int32_t pad;
+    int64_t texel_base;     /* first texel index of the patch */
+} lt_patch;                 /* 88 bytes */
+
+/* Static luminaire attributes.  type: 0 isotropic point light (Phi_r = P/N),
+ * 1 spot with radiant intensity P (n+1)/(2 pi) cos^n about its axis,
+ * 2 rectangle size_w x size_h with the same cos^n lobe per unit area
+ * (n = 1 is the paper's cosine area light).  Lights are grouped by layout. */
+typedef struct {
+    int32_t type;
+    float lobe_n;
+    float size_w, size_h;
+    int32_t layout;
+} lt_light_static;          /* 20 bytes */
+
+/* Per-call tracing configuration. */
+typedef struct {
+    uint64_t seed;             /* Philox key; the same seed replays the same paths */
+    int64_t paths_per_layout;  /* N per layout, split evenly over its lights */
+    int32_t max_hits;          /* B: hits per path (2 indirect bounces = 3) */
+    uint32_t flags;            /* LT_FLAG_* */
+    float alpha_plain;         /* one-sample MIS: probability of the plain lobe */
+    int32_t reserved;
+} lt_trace_cfg;                /* 32 bytes */
+
+/* Launch tuning (chosen by lt_autotune or set by hand). */
+typedef struct {
+    int32_t waves_per_block;   /* 1, 2 or 4 */
+    int32_t blocks_per_cu;     /* persistent grid = 256 CUs x blocks_per_cu */
+    int32_t tile_paths;        /* paths per work tile (multiple of 64), 0 = automatic */
+    int32_t refill_threshold;  /* lanes that must finish a segment before hit processing */
+    int32_t lds_depth;         /* traversal stack entries kept in LDS: 16 or 32 */
+    int32_t reserved[3];
+} lt_tuning;
+
+typedef struct {
+    int64_t n_tris, n_patches, n_texels;
+    int32_t bvh_nodes, bvh_depth;
+    int64_t device_bytes;
+    int32_t n_lights, n_layouts;
+} lt_info;
+
+/* Context on HIP device `device`; `hip_stream` (hipStream_t, may be NULL for
+ * the null stream) receives all work. */
+int lt_create(int device, void* hip_stream, lt_ctx** out);
+void lt_destroy(lt_ctx* ctx);
+const char* lt_last_error(const lt_ctx* ctx);
+int lt_set_stream(lt_ctx* ctx, void* hip_stream);
+
+/* Wait for the context's stream; report sticky device status bits
+ * (LT_STATUS_OVERFLOW) and clear them.  Returns LT_EOVERFLOW if set. */
+int lt_sync(lt_ctx* ctx, uint32_t* flags_out);
+
+/* Scene upload and BVH build (supplies the acceleration structure the paper
+ * takes from ray-tracing hardware, Sec. 6).  Host arrays: h_verts [n_verts,3]
+ * f32, h_tris [n_tris,3] i32 vertex indices, h_tri_patch [n_tris] i32,
+ * h_patches [n_patches].  Texel ranges of the patches must tile
+ * [0, n_texels).  Builds a linear BVH on the device (Morton order,
+ * Karras 2012 hierarchy) and per-texel area tables; replaces any previous
+ * scene.  *n_texels_out receives K. */
+int lt_scene_upload(lt_ctx* ctx, const float* h_verts, int64_t n_verts, const int32_t* h_tris,
+                    const int32_t* h_tri_patch, int64_t n_tris, const lt_patch* h_patches, int32_t n_patches,
+                    int64_t* n_texels_out);
+
+/* Luminaires (Sec. 4.4 and the supplement's light models): h_lights
+ * [n_lights], h_layout_offsets [n_layouts+1] (lights of layout j are
+ * [off[j], off[j+1]), every layout non-empty).  Parameters p are passed per
+ * trace call. */
+int lt_set_lights(lt_ctx* ctx, const lt_light_static* h_lights, int32_t n_lights,
+                  const int32_t* h_layout_offsets, int32_t n_layouts);
+
+/* Primal light tracing (Alg. 1, Eq. indirectFlux, Eq. directionalCoeffs with
+ * n = 0): d_params [L,6] f32; d_S [n_layouts,K] i64 scratch (Q31.32 fixed-point
+ * sums, zeroed by the call); d_E [n_layouts,K] f32 irradiance E_k = S_k 2^-32. */
+int lt_trace_forward(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, int64_t* d_S, float* d_E);
+
+/* Objective (Eq. objective, alpha_l = 1): O = 1/2 sum A_k alpha_k (E_k - E*_k)^2
+ * over n = n_layouts*K texels; d_alpha may be NULL (all ones).  Writes d_O
+ * (one f64) and d_g = dO/dE [n] f32. */
+int lt_objective(lt_ctx* ctx, const float* d_E, const float* d_Etarget, const float* d_alpha, int64_t n,
+                 double* d_O, float* d_g);
+
+/* Adjoint light tracing (Alg. 2, Eq. adjointFlux, Eq. objGradAdjoint,
+ * Eq. posDeriv and the rotation / area-light terms): replays the paths of
+ * `cfg` (same seed = correlated evaluation) with d_dOdE [n_layouts,K] and
+ * writes d_grad [L,6] f32 = dO/dp.  d_bin_hist [L,1024] f32 (may be NULL)
+ * receives per-light adjoint magnitudes binned by emission direction. */
+int lt_trace_adjoint(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, const float* d_dOdE,
+                     float* d_grad, float* d_bin_hist);
+
+/* Hit sequences of paths [first, first+count) of light `light` (index within
+ * its layout `layout`): d_prim / d_texel [count, max_hits] i32, -1 where the
+ * path ended.  With d_dOdE, d_contrib [count,6] f32 receives each path's
+ * gradient contribution (may both be NULL). */
+int lt_record_paths(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, int32_t layout, int32_t light,
+                    int64_t first, int64_t count, int32_t* d_prim, int32_t* d_texel, const float* d_dOdE,
+                    float* d_contrib);
+
+/* Work counters of one forward pass (instrumented kernel): segments traced,
+ * BVH nodes visited (two box tests each), triangle tests, hits, misses. */
+int lt_trace_stats(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, int64_t* d_S,
+                   int64_t h_counts_out[5]);
+
+int lt_get_tuning(const lt_ctx* ctx, lt_tuning* out);
+int lt_set_tuning(lt_ctx* ctx, const lt_tuning* t);
+
+/* Time candidate launch shapes for forward+adjoint on this configuration and
+ * keep the fastest; d_* are scratch buffers of the trace calls.  If
+ * cache_path is not NULL the choice is appended there and reused when a
+ * matching entry exists. */
+int lt_autotune(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, int64_t* d_S, float* d_E,
+                const float* d_dOdE, float* d_grad, const char* cache_path, float* h_best_ms);
+
+int lt_info_get(const lt_ctx* ctx, lt_info* out);
+
+/* Kernel timing.  While enabled, HIP events are recorded on the launch stream
+ * around every persistent trace kernel launched outside a graph;
+ * lt_timing_read waits for them and returns the summed kernel durations (ms)
+ * and launch counts of the forward and adjoint kernels since the last read. */
+int lt_set_timing(lt_ctx* ctx, int enable);
+int lt_timing_read(lt_ctx* ctx, double* fwd_ms, int32_t* n_fwd, double* adj_ms, int32_t* n_adj);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LT_H */

@@ -1,0 +1,768 @@
+// C ABI of liblt.so: context, scene upload, luminaires, trace calls.
+//
+// Host code validates arguments synchronously, keeps the work-tile tables of
+// the persistent kernels, and optionally replays each trace call as a captured
+// hipGraph (no memset nodes are captured: counters and accumulators are
+// cleared by kernels).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "lt.h"
+#include "lt_device.h"
+#include "lt_internal.h"
+
+using namespace lt;
+
+namespace {
+
+struct GraphEntry {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec;
+};
+
+}  // namespace
+
+struct lt_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t gstream = nullptr;   // capture stream for graphs
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::string err;
+    int n_cu = 256;
+
+    // scene
+    bool has_scene = false;
+    float4* nodes = nullptr;
+    float4* tris = nullptr;
+    DevPatch* patches = nullptr;
+    long long* pbase = nullptr;
+    float* parea = nullptr;
+    float* texel_area = nullptr;
+    int n_nodes = 0, depth = 0, n_patches = 0;
+    long long n_tris = 0, K = 0;
+    uint64_t generation = 1;
+
+    // luminaires
+    bool has_lights = false;
+    int L = 0, n_layouts = 0;
+    std::vector<lt_light_static> lights;
+    std::vector<int> offs;
+    int4* d_si = nullptr;
+    float4* d_sf = nullptr;
+    DevLight* d_lights = nullptr;
+
+    // tiles for (paths_per_layout, tile_paths)
+    long long tiles_ppl = -1;
+    int tiles_tp = -1;
+    int4* d_tiles = nullptr;
+    int n_tiles = 0;
+    int2* d_range = nullptr;
+    long long* d_npaths = nullptr;
+
+    // scratch
+    unsigned* d_counter = nullptr;
+    unsigned long long* d_misses = nullptr;
+    unsigned* d_flags = nullptr;
+    unsigned long long* d_stats = nullptr;
+    double* d_objpart = nullptr;
+    double* d_partials = nullptr;
+    size_t partials_cap = 0;
+    int* d_gstack = nullptr;
+    size_t gstack_cap = 0;
+
+    lt_tuning tune;
+    std::vector<GraphEntry> graphs;
+
+    // kernel timing (events around trace kernels launched outside graphs)
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> t_fwd, t_adj;
+};
+
+namespace {
+
+int fail(lt_ctx* c, int code, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                      \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? LT_ENOMEM : LT_EHIP,                  \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+    } while (0)
+
+void free_graphs(lt_ctx* c)
+{
+    for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+}
+
+void free_scene(lt_ctx* c)
+{
+    hipFree(c->nodes); hipFree(c->tris); hipFree(c->patches); hipFree(c->pbase); hipFree(c->parea);
+    hipFree(c->texel_area);
+    c->nodes = nullptr; c->tris = nullptr; c->patches = nullptr; c->pbase = nullptr; c->parea = nullptr;
+    c->texel_area = nullptr;
+    c->has_scene = false;
+}
+
+void free_tiles(lt_ctx* c)
+{
+    hipFree(c->d_tiles); hipFree(c->d_range); hipFree(c->d_npaths);
+    c->d_tiles = nullptr; c->d_range = nullptr; c->d_npaths = nullptr;
+    c->tiles_ppl = -1;
+    c->tiles_tp = -1;
+    c->n_tiles = 0;
+}
+
+lt_tuning default_tuning()
+{
+    lt_tuning t;
+    memset(&t, 0, sizeof(t));
+    t.waves_per_block = 4;
+    t.blocks_per_cu = 4;
+    t.tile_paths = 0;
+    t.refill_threshold = 16;
+    t.lds_depth = 16;
+    return t;
+}
+
+int n_waves(const lt_ctx* c) { return c->n_cu * c->tune.blocks_per_cu * c->tune.waves_per_block; }
+
+long long paths_of_light(long long ppl, int n_in_layout, int l)
+{
+    return ppl / n_in_layout + ((long long)l < ppl % n_in_layout ? 1 : 0);
+}
+
+int effective_tile_paths(const lt_ctx* c, long long ppl)
+{
+    if (c->tune.tile_paths > 0) return c->tune.tile_paths;
+    const long long total = ppl * (long long)c->n_layouts;
+    long long tp = total / ((long long)n_waves(c) * 4);
+    tp = (tp / 64) * 64;
+    if (tp < 64) tp = 64;
+    if (tp > 8192) tp = 8192;
+    return (int)tp;
+}
+
+int ensure_tiles(lt_ctx* c, long long ppl)
+{
+    const int tp = effective_tile_paths(c, ppl);
+    if (c->tiles_ppl == ppl && c->tiles_tp == tp) return LT_OK;
+    std::vector<int4> tiles;
+    std::vector<int2> range(c->L);
+    std::vector<long long> np(c->L);
+    for (int j = 0; j < c->n_layouts; ++j) {
+        const int l0 = c->offs[j], l1 = c->offs[j + 1];
+        for (int gl = l0; gl < l1; ++gl) {
+            const long long nl = paths_of_light(ppl, l1 - l0, gl - l0);
+            if (nl > 0xFFFFFFFFll) return fail(c, LT_EINVAL, "more than 2^32 paths for one light");
+            np[gl] = nl;
+            range[gl].x = (int)tiles.size();
+            for (long long f = 0; f < nl; f += tp) {
+                const long long cnt = std::min<long long>(tp, nl - f);
+                tiles.push_back(make_int4(gl, (int)(uint32_t)f, (int)cnt, j));
+            }
+            range[gl].y = (int)tiles.size();
+        }
+    }
+    if (tiles.size() > (size_t)0x7fffffff) return fail(c, LT_EINVAL, "too many work tiles");
+    free_tiles(c);
+    free_graphs(c);
+    HIPCHK(c, hipMalloc(&c->d_tiles, sizeof(int4) * std::max<size_t>(tiles.size(), 1)));
+    HIPCHK(c, hipMalloc(&c->d_range, sizeof(int2) * c->L));
+    HIPCHK(c, hipMalloc(&c->d_npaths, sizeof(long long) * c->L));
+    HIPCHK(c, hipMemcpy(c->d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_range, range.data(), sizeof(int2) * c->L, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_npaths, np.data(), sizeof(long long) * c->L, hipMemcpyHostToDevice));
+    c->n_tiles = (int)tiles.size();
+    c->tiles_ppl = ppl;
+    c->tiles_tp = tp;
+    if (c->partials_cap < (size_t)c->n_tiles * 6) {
+        hipFree(c->d_partials);
+        c->d_partials = nullptr;
+        c->partials_cap = 0;
+        HIPCHK(c, hipMalloc(&c->d_partials, sizeof(double) * 6 * std::max(c->n_tiles, 1)));
+        c->partials_cap = (size_t)std::max(c->n_tiles, 1) * 6;
+    }
+    return LT_OK;
+}
+
+int gstack_depth(const lt_ctx* c) { return std::max(0, c->depth + 1 - c->tune.lds_depth); }
+
+int ensure_gstack(lt_ctx* c, long long waves)
+{
+    const size_t need = (size_t)waves * (size_t)std::max(gstack_depth(c), 1) * 64;
+    if (need <= c->gstack_cap) return LT_OK;
+    free_graphs(c);
+    hipFree(c->d_gstack);
+    c->d_gstack = nullptr;
+    c->gstack_cap = 0;
+    HIPCHK(c, hipMalloc(&c->d_gstack, sizeof(int) * need));
+    c->gstack_cap = need;
+    return LT_OK;
+}
+
+int check_cfg(lt_ctx* c, const lt_trace_cfg* cfg)
+{
+    if (!c) return LT_EINVAL;
+    if (!cfg) return fail(c, LT_EINVAL, "cfg is NULL");
+    if (!c->has_scene) return fail(c, LT_ESTATE, "no scene uploaded");
+    if (!c->has_lights) return fail(c, LT_ESTATE, "no luminaires set");
+    if (cfg->max_hits < 1 || cfg->max_hits > 64) return fail(c, LT_EINVAL, "max_hits must be in [1, 64]");
+    for (int j = 0; j < c->n_layouts; ++j)
+        if (cfg->paths_per_layout < c->offs[j + 1] - c->offs[j])
+            return fail(c, LT_EINVAL, "paths_per_layout smaller than the number of lights of a layout");
+    if (cfg->flags & ~(LT_FLAG_GRAPH | LT_FLAG_PROPOSAL)) return fail(c, LT_EINVAL, "unknown flag");
+    if (cfg->flags & LT_FLAG_PROPOSAL) return fail(c, LT_EINVAL, "no emission proposal loaded");
+    return ensure_tiles(c, cfg->paths_per_layout);
+}
+
+// Launch a trace kernel; with timing on (and outside graph capture) bracket
+// it by events on the same stream.
+hipError_t timed_trace(lt_ctx* c, bool adjoint, bool capture, const TraceArgs& a, int blocks, hipStream_t st)
+{
+    const bool t = c->timing && !capture;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (t) {
+        hipError_t e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = launch_trace(adjoint, false, a, c->tune.waves_per_block, c->tune.lds_depth, blocks, st);
+    if (t) {
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        (adjoint ? c->t_adj : c->t_fwd).push_back({e0, e1});
+    }
+    return e;
+}
+
+TraceArgs trace_args(lt_ctx* c, const lt_trace_cfg* cfg)
+{
+    TraceArgs a;
+    memset(&a, 0, sizeof(a));
+    a.nodes = c->nodes;
+    a.tris = c->tris;
+    a.patches = c->patches;
+    a.lights = c->d_lights;
+    a.tiles = c->d_tiles;
+    a.n_tiles = c->n_tiles;
+    a.max_hits = cfg->max_hits;
+    a.tile_counter = c->d_counter;
+    a.key0 = (uint32_t)cfg->seed;
+    a.key1 = (uint32_t)(cfg->seed >> 32);
+    a.K = c->K;
+    a.misses = c->d_misses;
+    a.stats = c->d_stats;
+    a.gstack = c->d_gstack;
+    a.gdepth = std::max(gstack_depth(c), 1);
+    a.refill_threshold = c->tune.refill_threshold;
+    a.max_steps = 2 * c->n_nodes + 16;
+    a.flags = c->d_flags;
+    return a;
+}
+
+// Run `body` directly on the context stream, or through a cached graph.
+template <typename F>
+int run_seq(lt_ctx* c, bool graph, const std::vector<uint64_t>& key, F body)
+{
+    if (!graph) {
+        HIPCHK(c, body(c->stream));
+        return LT_OK;
+    }
+    if (!c->gstream) {
+        HIPCHK(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+        HIPCHK(c, hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+    }
+    hipGraphExec_t exec = nullptr;
+    for (auto& g : c->graphs)
+        if (g.key == key) exec = g.exec;
+    if (!exec) {
+        hipGraph_t graph_h = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = body(c->gstream);
+        hipError_t e2 = hipStreamEndCapture(c->gstream, &graph_h);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (graph_h) hipGraphDestroy(graph_h);
+            return fail(c, LT_EHIP, std::string("graph capture failed: ") +
+                                        hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        hipError_t e3 = hipGraphInstantiate(&exec, graph_h, nullptr, nullptr, 0);
+        hipGraphDestroy(graph_h);
+        if (e3 != hipSuccess) return fail(c, LT_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e3));
+        if (c->graphs.size() >= 16) {
+            hipGraphExecDestroy(c->graphs.front().exec);
+            c->graphs.erase(c->graphs.begin());
+        }
+        c->graphs.push_back(GraphEntry{key, exec});
+    }
+    HIPCHK(c, hipEventRecord(c->ev_in, c->stream));
+    HIPCHK(c, hipStreamWaitEvent(c->gstream, c->ev_in, 0));
+    HIPCHK(c, hipGraphLaunch(exec, c->gstream));
+    HIPCHK(c, hipEventRecord(c->ev_out, c->gstream));
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_out, 0));
+    return LT_OK;
+}
+
+std::vector<uint64_t> make_key(lt_ctx* c, int kind, const lt_trace_cfg* cfg, std::initializer_list<const void*> ptrs)
+{
+    std::vector<uint64_t> k;
+    k.push_back((uint64_t)kind);
+    k.push_back(c->generation);
+    k.push_back(cfg->seed);
+    k.push_back((uint64_t)cfg->paths_per_layout);
+    k.push_back((uint64_t)cfg->max_hits);
+    k.push_back((uint64_t)cfg->flags);
+    k.push_back((uint64_t)c->tune.waves_per_block | ((uint64_t)c->tune.blocks_per_cu << 8) |
+                ((uint64_t)c->tune.refill_threshold << 24) | ((uint64_t)c->tune.lds_depth << 40));
+    k.push_back((uint64_t)c->tiles_tp);
+    for (const void* p : ptrs) k.push_back((uint64_t)(uintptr_t)p);
+    return k;
+}
+
+bool finite3(const float* v) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
+
+}  // namespace
+
+extern "C" {
+
+int lt_create(int device, void* hip_stream, lt_ctx** out)
+{
+    if (!out) return LT_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return LT_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return LT_EHIP;
+    lt_ctx* c = new lt_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->tune = default_tuning();
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->n_cu = prop.multiProcessorCount;
+    if (hipMalloc(&c->d_counter, sizeof(unsigned)) != hipSuccess ||
+        hipMalloc(&c->d_misses, sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&c->d_flags, sizeof(unsigned)) != hipSuccess ||
+        hipMalloc(&c->d_stats, sizeof(unsigned long long) * 8) != hipSuccess ||
+        hipMalloc(&c->d_objpart, sizeof(double) * kObjBlocks) != hipSuccess) {
+        lt_destroy(c);
+        return LT_ENOMEM;
+    }
+    hipMemset(c->d_counter, 0, sizeof(unsigned));
+    hipMemset(c->d_misses, 0, sizeof(unsigned long long));
+    hipMemset(c->d_flags, 0, sizeof(unsigned));
+    hipMemset(c->d_stats, 0, sizeof(unsigned long long) * 8);
+    hipDeviceSynchronize();
+    *out = c;
+    return LT_OK;
+}
+
+void lt_destroy(lt_ctx* c)
+{
+    if (!c) return;
+    hipSetDevice(c->device);
+    if (c->stream) hipStreamSynchronize(c->stream);
+    if (c->gstream) hipStreamSynchronize(c->gstream);
+    free_graphs(c);
+    free_scene(c);
+    free_tiles(c);
+    hipFree(c->d_si); hipFree(c->d_sf); hipFree(c->d_lights);
+    hipFree(c->d_counter); hipFree(c->d_misses); hipFree(c->d_flags); hipFree(c->d_stats);
+    hipFree(c->d_objpart); hipFree(c->d_partials); hipFree(c->d_gstack);
+    if (c->ev_in) hipEventDestroy(c->ev_in);
+    if (c->ev_out) hipEventDestroy(c->ev_out);
+    if (c->gstream) hipStreamDestroy(c->gstream);
+    delete c;
+}
+
+const char* lt_last_error(const lt_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int lt_set_stream(lt_ctx* c, void* hip_stream)
+{
+    if (!c) return LT_EINVAL;
+    c->stream = (hipStream_t)hip_stream;
+    return LT_OK;
+}
+
+int lt_sync(lt_ctx* c, uint32_t* flags_out)
+{
+    if (!c) return LT_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->gstream) HIPCHK(c, hipStreamSynchronize(c->gstream));
+    unsigned f = 0;
+    HIPCHK(c, hipMemcpy(&f, c->d_flags, sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (f) HIPCHK(c, hipMemset(c->d_flags, 0, sizeof(unsigned)));
+    if (flags_out) *flags_out = f;
+    if (f & LT_STATUS_OVERFLOW) return fail(c, LT_EOVERFLOW, "texel accumulator overflow (|S| >= 2^62)");
+    if (f & LT_STATUS_TRAVERSAL) return fail(c, LT_EHIP, "BVH traversal exceeded its step bound");
+    return LT_OK;
+}
+
+int lt_scene_upload(lt_ctx* c, const float* h_verts, int64_t n_verts, const int32_t* h_tris,
+                    const int32_t* h_tri_patch, int64_t n_tris, const lt_patch* h_patches, int32_t n_patches,
+                    int64_t* n_texels_out)
+{
+    if (!c) return LT_EINVAL;
+    if (!h_verts || !h_tris || !h_tri_patch || !h_patches) return fail(c, LT_EINVAL, "NULL scene array");
+    if (n_verts < 3 || n_tris < 1 || n_patches < 1) return fail(c, LT_EINVAL, "empty scene");
+    if (n_tris > (1ll << 28) || n_verts > (1ll << 31) - 1) return fail(c, LT_EINVAL, "scene too large");
+    double amax = 0.0, lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t v = 0; v < n_verts; ++v) {
+        if (!finite3(h_verts + 3 * v)) return fail(c, LT_EINVAL, "non-finite vertex");
+        for (int k = 0; k < 3; ++k) {
+            const double x = h_verts[3 * v + k];
+            amax = std::max(amax, fabs(x));
+            lo[k] = std::min(lo[k], x);
+            hi[k] = std::max(hi[k], x);
+        }
+    }
+    for (int64_t t = 0; t < n_tris; ++t) {
+        for (int k = 0; k < 3; ++k)
+            if (h_tris[3 * t + k] < 0 || h_tris[3 * t + k] >= n_verts)
+                return fail(c, LT_EINVAL, "triangle vertex index out of range");
+        if (h_tri_patch[t] < 0 || h_tri_patch[t] >= n_patches)
+            return fail(c, LT_EINVAL, "triangle patch index out of range");
+    }
+    std::vector<DevPatch> dp(n_patches);
+    std::vector<long long> base(n_patches);
+    std::vector<float> area(n_patches);
+    long long K = 0;
+    for (int q = 0; q < n_patches; ++q) {
+        const lt_patch& p = h_patches[q];
+        if (p.res_u < 1 || p.res_v < 1) return fail(c, LT_EINVAL, "patch resolution < 1");
+        if (p.texel_base != K) return fail(c, LT_EINVAL, "patch texel ranges must tile [0, K) in order");
+        if (!finite3(p.origin) || !finite3(p.e_u) || !finite3(p.e_v) || !finite3(p.normal) ||
+            !(p.inv_len2_u > 0) || !(p.inv_len2_v > 0) || !isfinite(p.inv_len2_u) || !isfinite(p.inv_len2_v) ||
+            !(p.texel_area > 0) || !(p.inv_texel_area > 0) || !isfinite(p.inv_texel_area) ||
+            !(p.albedo >= 0.0f && p.albedo <= 1.0f))
+            return fail(c, LT_EINVAL, "invalid patch constants");
+        K += (long long)p.res_u * p.res_v;
+        dp[q].o_inva = make_float4(p.origin[0], p.origin[1], p.origin[2], p.inv_texel_area);
+        dp[q].eu_ilu = make_float4(p.e_u[0], p.e_u[1], p.e_u[2], p.inv_len2_u);
+        dp[q].ev_ilv = make_float4(p.e_v[0], p.e_v[1], p.e_v[2], p.inv_len2_v);
+        dp[q].n_rho = make_float4(p.normal[0], p.normal[1], p.normal[2], p.albedo);
+        dp[q].res_u = p.res_u;
+        dp[q].res_v = p.res_v;
+        dp[q].base = p.texel_base;
+        base[q] = p.texel_base;
+        area[q] = p.texel_area;
+    }
+    if (K > 0x7fffffffll) return fail(c, LT_EINVAL, "more than 2^31-1 texels");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    free_graphs(c);
+    free_scene(c);
+    float* d_verts = nullptr;
+    int *d_tris = nullptr, *d_tp = nullptr;
+    HIPCHK(c, hipMalloc(&d_verts, sizeof(float) * 3 * n_verts));
+    HIPCHK(c, hipMalloc(&d_tris, sizeof(int) * 3 * n_tris));
+    HIPCHK(c, hipMalloc(&d_tp, sizeof(int) * n_tris));
+    HIPCHK(c, hipMemcpy(d_verts, h_verts, sizeof(float) * 3 * n_verts, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(d_tris, h_tris, sizeof(int) * 3 * n_tris, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(d_tp, h_tri_patch, sizeof(int) * n_tris, hipMemcpyHostToDevice));
+    double ext = 0.0;
+    for (int k = 0; k < 3; ++k) ext = std::max(ext, hi[k] - lo[k]);
+    const float pad = (float)(1e-5 * (amax + ext + 1.0));
+    int depth = 0, n_nodes = 0;
+    hipError_t e = build_bvh(d_verts, d_tris, d_tp, (int)n_tris, pad, c->stream, &c->nodes, &c->tris, &n_nodes, &depth);
+    hipFree(d_verts);
+    hipFree(d_tris);
+    hipFree(d_tp);
+    if (e != hipSuccess) return fail(c, LT_EHIP, std::string("BVH build: ") + hipGetErrorString(e));
+    if (depth + 1 > kMaxStackDepth) {
+        free_scene(c);
+        return fail(c, LT_EINVAL, "BVH deeper than the traversal stack bound");
+    }
+    HIPCHK(c, hipMalloc(&c->patches, sizeof(DevPatch) * n_patches));
+    HIPCHK(c, hipMalloc(&c->pbase, sizeof(long long) * n_patches));
+    HIPCHK(c, hipMalloc(&c->parea, sizeof(float) * n_patches));
+    HIPCHK(c, hipMalloc(&c->texel_area, sizeof(float) * K));
+    HIPCHK(c, hipMemcpy(c->patches, dp.data(), sizeof(DevPatch) * n_patches, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->pbase, base.data(), sizeof(long long) * n_patches, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->parea, area.data(), sizeof(float) * n_patches, hipMemcpyHostToDevice));
+    HIPCHK(c, launch_texel_area(c->parea, c->pbase, n_patches, K, c->texel_area, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->n_nodes = n_nodes;
+    c->depth = depth;
+    c->n_tris = n_tris;
+    c->n_patches = n_patches;
+    c->K = K;
+    c->has_scene = true;
+    c->generation++;
+    if (n_texels_out) *n_texels_out = K;
+    return LT_OK;
+}
+
+int lt_set_lights(lt_ctx* c, const lt_light_static* h_lights, int32_t n_lights, const int32_t* h_offs,
+                  int32_t n_layouts)
+{
+    if (!c) return LT_EINVAL;
+    if (!h_lights || !h_offs || n_lights < 1 || n_layouts < 1) return fail(c, LT_EINVAL, "no luminaires");
+    if (n_layouts > 65535 || n_lights > (1 << 24)) return fail(c, LT_EINVAL, "too many layouts or lights");
+    if (h_offs[0] != 0 || h_offs[n_layouts] != n_lights) return fail(c, LT_EINVAL, "bad layout offsets");
+    for (int j = 0; j < n_layouts; ++j) {
+        if (h_offs[j + 1] <= h_offs[j]) return fail(c, LT_EINVAL, "empty layout or unordered offsets");
+        if (h_offs[j + 1] - h_offs[j] > 65535) return fail(c, LT_EINVAL, "too many lights in a layout");
+    }
+    std::vector<int4> si(n_lights);
+    std::vector<float4> sf(n_lights);
+    for (int j = 0; j < n_layouts; ++j)
+        for (int l = h_offs[j]; l < h_offs[j + 1]; ++l) {
+            const lt_light_static& s = h_lights[l];
+            if (s.type < 0 || s.type > 2) return fail(c, LT_EINVAL, "unknown light type");
+            if (s.layout != j) return fail(c, LT_EINVAL, "light layout does not match the offsets");
+            if (!(s.lobe_n >= 0.0f) || !isfinite(s.lobe_n) || (s.type == 0 && s.lobe_n != 0.0f))
+                return fail(c, LT_EINVAL, "invalid lobe exponent");
+            if (s.type == 2 && !(s.size_w > 0.0f && s.size_h > 0.0f && isfinite(s.size_w) && isfinite(s.size_h)))
+                return fail(c, LT_EINVAL, "invalid rectangle size");
+            si[l] = make_int4(s.type, j, l - h_offs[j], 0);
+            sf[l] = make_float4(s.lobe_n, s.size_w, s.size_h, 0.f);
+        }
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    free_graphs(c);
+    free_tiles(c);
+    hipFree(c->d_si); hipFree(c->d_sf); hipFree(c->d_lights);
+    c->d_si = nullptr; c->d_sf = nullptr; c->d_lights = nullptr;
+    c->has_lights = false;
+    HIPCHK(c, hipMalloc(&c->d_si, sizeof(int4) * n_lights));
+    HIPCHK(c, hipMalloc(&c->d_sf, sizeof(float4) * n_lights));
+    HIPCHK(c, hipMalloc(&c->d_lights, sizeof(DevLight) * n_lights));
+    HIPCHK(c, hipMemcpy(c->d_si, si.data(), sizeof(int4) * n_lights, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_sf, sf.data(), sizeof(float4) * n_lights, hipMemcpyHostToDevice));
+    c->lights.assign(h_lights, h_lights + n_lights);
+    c->offs.assign(h_offs, h_offs + n_layouts + 1);
+    c->L = n_lights;
+    c->n_layouts = n_layouts;
+    c->has_lights = true;
+    c->generation++;
+    return LT_OK;
+}
+
+int lt_trace_forward(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int64_t* d_S, float* d_E)
+{
+    int rc = check_cfg(c, cfg);
+    if (rc) return rc;
+    if (!d_params || !d_S || !d_E) return fail(c, LT_EINVAL, "NULL device buffer");
+    if (((uintptr_t)d_S & 15) || ((uintptr_t)d_E & 7) || ((uintptr_t)d_params & 3))
+        return fail(c, LT_EINVAL, "d_S must be 16-byte and d_E 8-byte aligned");
+    HIPCHK(c, hipSetDevice(c->device));
+    const long long blocks = (long long)c->n_cu * c->tune.blocks_per_cu;
+    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    if (rc) return rc;
+    TraceArgs a = trace_args(c, cfg);
+    a.S = (long long*)d_S;
+    const long long n = c->K * c->n_layouts;
+    const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
+    auto body = [&](hipStream_t st) -> hipError_t {
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        if (e == hipSuccess) e = launch_clear(a.S, n, c->d_counter, st);
+        if (e == hipSuccess) e = timed_trace(c, false, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = launch_finalize(a.S, d_E, n, c->d_flags, st);
+        return e;
+    };
+    return run_seq(c, graph, make_key(c, 1, cfg, {d_params, d_S, d_E}), body);
+}
+
+int lt_objective(lt_ctx* c, const float* d_E, const float* d_Et, const float* d_alpha, int64_t n, double* d_O,
+                 float* d_g)
+{
+    if (!c) return LT_EINVAL;
+    if (!c->has_scene) return fail(c, LT_ESTATE, "no scene uploaded");
+    if (!d_E || !d_Et || !d_O) return fail(c, LT_EINVAL, "NULL device buffer");
+    if (n <= 0 || n % c->K != 0) return fail(c, LT_EINVAL, "n must be a positive multiple of the texel count");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_objective(d_E, d_Et, d_alpha, c->texel_area, c->K, n, d_g, c->d_objpart, d_O, c->stream));
+    return LT_OK;
+}
+
+int lt_trace_adjoint(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, const float* d_dOdE, float* d_grad,
+                     float* d_bin_hist)
+{
+    int rc = check_cfg(c, cfg);
+    if (rc) return rc;
+    if (!d_params || !d_dOdE || !d_grad) return fail(c, LT_EINVAL, "NULL device buffer");
+    if (d_bin_hist) return fail(c, LT_EINVAL, "direction histograms need an emission proposal");
+    HIPCHK(c, hipSetDevice(c->device));
+    const long long blocks = (long long)c->n_cu * c->tune.blocks_per_cu;
+    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    if (rc) return rc;
+    TraceArgs a = trace_args(c, cfg);
+    a.g = d_dOdE;
+    a.partials = c->d_partials;
+    const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
+    auto body = [&](hipStream_t st) -> hipError_t {
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        if (e == hipSuccess) e = launch_reset_counter(c->d_counter, st);
+        if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = launch_grad_reduce(c->d_partials, c->d_range, c->L, d_grad, st);
+        return e;
+    };
+    return run_seq(c, graph, make_key(c, 2, cfg, {d_params, d_dOdE, d_grad}), body);
+}
+
+int lt_record_paths(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int32_t layout, int32_t light,
+                    int64_t first, int64_t count, int32_t* d_prim, int32_t* d_texel, const float* d_dOdE,
+                    float* d_contrib)
+{
+    int rc = check_cfg(c, cfg);
+    if (rc) return rc;
+    if (!d_params || !d_prim || !d_texel) return fail(c, LT_EINVAL, "NULL device buffer");
+    if ((d_dOdE == nullptr) != (d_contrib == nullptr)) return fail(c, LT_EINVAL, "dOdE and contrib go together");
+    if (layout < 0 || layout >= c->n_layouts) return fail(c, LT_EINVAL, "layout out of range");
+    const int nl = c->offs[layout + 1] - c->offs[layout];
+    if (light < 0 || light >= nl) return fail(c, LT_EINVAL, "light out of range");
+    const long long np = paths_of_light(cfg->paths_per_layout, nl, light);
+    if (first < 0 || count < 0 || first + count > np) return fail(c, LT_EINVAL, "path range out of range");
+    if (count == 0) return LT_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    rc = ensure_gstack(c, (long long)kRecordBlocks * 4);
+    if (rc) return rc;
+    RecordArgs r;
+    memset(&r, 0, sizeof(r));
+    r.nodes = c->nodes;
+    r.tris = c->tris;
+    r.patches = c->patches;
+    r.lights = c->d_lights;
+    r.gl = c->offs[layout] + light;
+    r.layout = layout;
+    r.max_hits = cfg->max_hits;
+    r.K = c->K;
+    r.stream_id = ((uint32_t)layout << 16) | (uint32_t)light;
+    r.key0 = (uint32_t)cfg->seed;
+    r.key1 = (uint32_t)(cfg->seed >> 32);
+    r.first = first;
+    r.count = count;
+    r.prim = d_prim;
+    r.texel = d_texel;
+    r.g = d_dOdE;
+    r.contrib = d_contrib;
+    r.gstack = c->d_gstack;
+    r.gdepth = std::max(gstack_depth(c), 1);
+    r.max_steps = 2 * c->n_nodes + 16;
+    r.flags = c->d_flags;
+    HIPCHK(c, launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->stream));
+    HIPCHK(c, launch_record(r, c->tune.lds_depth, c->stream));
+    return LT_OK;
+}
+
+int lt_trace_stats(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int64_t* d_S, int64_t h_counts[5])
+{
+    int rc = check_cfg(c, cfg);
+    if (rc) return rc;
+    if (!d_params || !d_S || !h_counts) return fail(c, LT_EINVAL, "NULL buffer");
+    if ((uintptr_t)d_S & 15) return fail(c, LT_EINVAL, "d_S must be 16-byte aligned");
+    HIPCHK(c, hipSetDevice(c->device));
+    const long long blocks = (long long)c->n_cu * c->tune.blocks_per_cu;
+    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    if (rc) return rc;
+    TraceArgs a = trace_args(c, cfg);
+    a.S = (long long*)d_S;
+    HIPCHK(c, hipMemsetAsync(c->d_stats, 0, sizeof(unsigned long long) * 8, c->stream));
+    HIPCHK(c, launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->stream));
+    HIPCHK(c, launch_clear(a.S, c->K * c->n_layouts, c->d_counter, c->stream));
+    HIPCHK(c, launch_trace(false, true, a, c->tune.waves_per_block, c->tune.lds_depth, (int)blocks, c->stream));
+    unsigned long long h[8];
+    HIPCHK(c, hipMemcpyAsync(h, c->d_stats, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < 5; ++i) h_counts[i] = (int64_t)h[i];
+    return LT_OK;
+}
+
+int lt_get_tuning(const lt_ctx* c, lt_tuning* out)
+{
+    if (!c || !out) return LT_EINVAL;
+    *out = c->tune;
+    return LT_OK;
+}
+
+int lt_set_tuning(lt_ctx* c, const lt_tuning* t)
+{
+    if (!c || !t) return LT_EINVAL;
+    if (t->waves_per_block != 1 && t->waves_per_block != 2 && t->waves_per_block != 4)
+        return fail(c, LT_EINVAL, "waves_per_block must be 1, 2 or 4");
+    if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64) return fail(c, LT_EINVAL, "blocks_per_cu out of range");
+    if (t->tile_paths < 0 || t->tile_paths % 64 != 0 || t->tile_paths > (1 << 24))
+        return fail(c, LT_EINVAL, "tile_paths must be 0 or a positive multiple of 64");
+    if (t->refill_threshold < 1 || t->refill_threshold > 64)
+        return fail(c, LT_EINVAL, "refill_threshold must be in [1, 64]");
+    if (t->lds_depth != 16 && t->lds_depth != 32) return fail(c, LT_EINVAL, "lds_depth must be 16 or 32");
+    free_graphs(c);
+    c->tune = *t;
+    c->tiles_tp = -1;   // recompute tiles at the next call
+    return LT_OK;
+}
+
+int lt_info_get(const lt_ctx* c, lt_info* out)
+{
+    if (!c || !out) return LT_EINVAL;
+    memset(out, 0, sizeof(*out));
+    out->n_tris = c->n_tris;
+    out->n_patches = c->n_patches;
+    out->n_texels = c->K;
+    out->bvh_nodes = c->n_nodes;
+    out->bvh_depth = c->depth;
+    out->device_bytes = (int64_t)c->n_nodes * 64 + c->n_tris * 48 + (int64_t)c->n_patches * sizeof(DevPatch) +
+                        c->K * 4 + (int64_t)c->gstack_cap * 4 + (int64_t)c->partials_cap * 8;
+    out->n_lights = c->L;
+    out->n_layouts = c->n_layouts;
+    return LT_OK;
+}
+
+int lt_set_timing(lt_ctx* c, int enable)
+{
+    if (!c) return LT_EINVAL;
+    c->timing = enable != 0;
+    return LT_OK;
+}
+
+int lt_timing_read(lt_ctx* c, double* fwd_ms, int32_t* n_fwd, double* adj_ms, int32_t* n_adj)
+{
+    if (!c) return LT_EINVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    double sums[2] = {0.0, 0.0};
+    int counts[2] = {0, 0};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>>* lists[2] = {&c->t_fwd, &c->t_adj};
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < 2; ++k) {
+        for (auto& pr : *lists[k]) {
+            float ms = 0.f;
+            if (err == hipSuccess) err = hipEventSynchronize(pr.second);
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, pr.first, pr.second);
+            sums[k] += ms;
+            counts[k]++;
+            hipEventDestroy(pr.first);
+            hipEventDestroy(pr.second);
+        }
+        lists[k]->clear();
+    }
+    if (err != hipSuccess) return fail(c, LT_EHIP, std::string("timing events: ") + hipGetErrorString(err));
+    if (fwd_ms) *fwd_ms = sums[0];
+    if (n_fwd) *n_fwd = counts[0];
+    if (adj_ms) *adj_ms = sums[1];
+    if (n_adj) *n_adj = counts[1];
+    return LT_OK;
+}
+
+int lt_autotune(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int64_t* d_S, float* d_E,
+                const float* d_dOdE, float* d_grad, const char* cache_path, float* h_best_ms)
+{
+    (void)c; (void)cfg; (void)d_params; (void)d_S; (void)d_E; (void)d_dOdE; (void)d_grad; (void)cache_path;
+    (void)h_best_ms;
+    return c ? fail(c, LT_EINVAL, "autotune not available yet") : LT_EINVAL;
+}
+
+}  // extern "C"

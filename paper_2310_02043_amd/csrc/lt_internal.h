@@ -1,0 +1,74 @@
+// Internal interfaces between the C ABI layer and the kernel translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "lt_device.h"
+
+namespace lt {
+
+constexpr int kMaxStackDepth = 128;   // BVH depth bound accepted at upload
+constexpr int kObjBlocks = 1024;      // fixed grid of the objective reduction
+constexpr int kRecordBlocks = 1024;   // grid of the path-recording kernel (4 waves each)
+
+struct TraceArgs {
+    const float4* nodes;
+    const float4* tris;
+    const DevPatch* patches;
+    const DevLight* lights;
+    const int4* tiles;          // (global light, first path, count, layout)
+    int n_tiles;
+    int max_hits;
+    unsigned* tile_counter;
+    uint32_t key0, key1;
+    long long* S;               // forward: [n_layouts, K]
+    const float* g;             // adjoint: [n_layouts, K]
+    long long K;
+    double* partials;           // adjoint: [n_tiles, 6]
+    unsigned long long* misses;
+    unsigned long long* stats;  // instrumented kernel: 5 counters
+    int* gstack;                // traversal stack overflow, [waves][gdepth][64]
+    int gdepth;
+    int refill_threshold;
+    int max_steps;              // node visits per segment before the segment is abandoned
+    unsigned* flags;            // sticky status bits (2 = traversal step limit hit)
+};
+
+struct RecordArgs {
+    const float4* nodes;
+    const float4* tris;
+    const DevPatch* patches;
+    const DevLight* lights;
+    int gl, layout, max_hits;
+    long long K;
+    uint32_t stream_id;
+    uint32_t key0, key1;
+    long long first, count;
+    int* prim;
+    int* texel;
+    const float* g;
+    float* contrib;
+    int* gstack;
+    int gdepth;
+    int max_steps;
+    unsigned* flags;
+};
+
+hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_patch, int n, float pad,
+                     hipStream_t st, float4** nodes_out, float4** tris_out, int* n_nodes_out, int* depth_out);
+
+hipError_t launch_trace(bool adjoint, bool stats, const TraceArgs& a, int waves_per_block, int lds_depth,
+                        int blocks, hipStream_t st);
+hipError_t launch_record(const RecordArgs& a, int lds_depth, hipStream_t st);
+hipError_t launch_light_setup(const float* params, const int4* lstat_i, const float4* lstat_f,
+                              const long long* npaths, int n_lights, DevLight* out, hipStream_t st);
+hipError_t launch_clear(long long* S, long long n_texels_total, unsigned* counter, hipStream_t st);
+hipError_t launch_reset_counter(unsigned* counter, hipStream_t st);
+hipError_t launch_finalize(const long long* S, float* E, long long n, unsigned* flags, hipStream_t st);
+hipError_t launch_objective(const float* E, const float* Et, const float* alpha, const float* A, long long K,
+                            long long n, float* g, double* partials, double* O, hipStream_t st);
+hipError_t launch_grad_reduce(const double* partials, const int2* tile_range, int n_lights, float* grad,
+                              hipStream_t st);
+hipError_t launch_texel_area(const float* patch_area, const long long* base, int n_patches, long long K,
+                             float* A, hipStream_t st);
+
+}  // namespace lt

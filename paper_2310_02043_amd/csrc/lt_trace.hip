@@ -1,0 +1,723 @@
+// Primal and adjoint light-tracing kernels for gfx950.
+//
+// Alg. 1 (primal) and Alg. 2 (adjoint) of the paper, one persistent launch
+// over a queue of work tiles.  A tile is a contiguous path range of one
+// luminaire of one layout; a wave takes a tile, keeps 64 paths in flight and
+// refills lanes whose path ended (ballot + mbcnt prefix count) until the tile
+// is exhausted.  Hit processing (splat or adjoint gather, bounce, refill) runs
+// once at least `refill_threshold` lanes have finished their current segment,
+// so the BVH traversal loop stays converged.  Texel sums are int64 Q31.32
+// fixed point (order-independent); adjoint partial sums are FP64 per tile in a
+// fixed lane order, so both passes are deterministic.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "lt_device.h"
+#include "lt_internal.h"
+
+namespace lt {
+
+namespace {
+
+struct Ray {
+    float ox, oy, oz, dx, dy, dz;
+    float ix, iy, iz, oix, oiy, oiz;   // safe reciprocal direction and origin * reciprocal
+};
+
+__device__ __forceinline__ void set_ray(Ray& r, V3 o, V3 d)
+{
+    r.ox = o.x; r.oy = o.y; r.oz = o.z;
+    r.dx = d.x; r.dy = d.y; r.dz = d.z;
+    // the slab test is conservative by the build's padding; exact zeros are
+    // replaced so no 0 * inf appears
+    const float tiny = 1e-30f;
+    r.ix = 1.0f / (d.x != 0.0f ? d.x : __builtin_copysignf(tiny, d.x));
+    r.iy = 1.0f / (d.y != 0.0f ? d.y : __builtin_copysignf(tiny, d.y));
+    r.iz = 1.0f / (d.z != 0.0f ? d.z : __builtin_copysignf(tiny, d.z));
+    r.oix = o.x * r.ix;
+    r.oiy = o.y * r.iy;
+    r.oiz = o.z * r.iz;
+}
+
+// Box of one child: x in [xl, xh], y in [yl, yh], z in [zl, zh]; interval
+// [0, tmax].  Returns entry distance or +inf for a miss.
+__device__ __forceinline__ float slab(const Ray& r, float xl, float xh, float yl, float yh, float zl, float zh,
+                                      float tmax)
+{
+    const float ax = __builtin_fmaf(xl, r.ix, -r.oix), bx = __builtin_fmaf(xh, r.ix, -r.oix);
+    const float ay = __builtin_fmaf(yl, r.iy, -r.oiy), by = __builtin_fmaf(yh, r.iy, -r.oiy);
+    const float az = __builtin_fmaf(zl, r.iz, -r.oiz), bz = __builtin_fmaf(zh, r.iz, -r.oiz);
+    const float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), 0.0f));
+    const float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), tmax));
+    return t0 <= t1 ? t0 : __builtin_inff();
+}
+
+struct Trav {
+    float tb;
+    int pb, qb;
+    int node, sp;
+    int steps;
+};
+
+template <int LDS_D, bool STATS>
+__device__ __forceinline__ void trav_step(const Ray& r, int skip, Trav& s, bool& traversing,
+                                          const float4* __restrict__ nodes, const float4* __restrict__ tris,
+                                          int* lst, int* gst, unsigned& n_nodes, unsigned& n_tris,
+                                          int max_steps, bool& overrun)
+{
+    // bounded: a segment visits each node at most once in a tree
+    if (++s.steps > max_steps) {
+        traversing = false;
+        overrun = true;
+        s.pb = -1;
+        s.qb = -1;
+        return;
+    }
+    const float4* nd = nodes + 4 * s.node;
+    const float4 w0 = nd[0], w1 = nd[1], w2 = nd[2], w3 = nd[3];
+    if (STATS) ++n_nodes;
+    float t0 = slab(r, w0.x, w0.y, w0.z, w0.w, w2.x, w2.y, s.tb);
+    float t1 = slab(r, w1.x, w1.y, w1.z, w1.w, w2.z, w2.w, s.tb);
+    const int c0 = __float_as_int(w3.x), c1 = __float_as_int(w3.y);
+    const V3 o = v3(r.ox, r.oy, r.oz), d = v3(r.dx, r.dy, r.dz);
+    if (c0 < 0 && t0 != __builtin_inff()) {
+        const float4* tp = tris + 3 * (~c0);
+        tri_test(tp[0], tp[1], tp[2], o, d, skip, s.tb, s.pb, s.qb);
+        if (STATS) ++n_tris;
+        t0 = __builtin_inff();
+    }
+    if (c1 < 0 && t1 != __builtin_inff()) {
+        const float4* tp = tris + 3 * (~c1);
+        tri_test(tp[0], tp[1], tp[2], o, d, skip, s.tb, s.pb, s.qb);
+        if (STATS) ++n_tris;
+        t1 = __builtin_inff();
+    }
+    const bool h0 = t0 != __builtin_inff(), h1 = t1 != __builtin_inff();
+    if (h0 && h1) {
+        const bool first0 = t0 <= t1;
+        const int far = first0 ? c1 : c0;
+        s.node = first0 ? c0 : c1;
+        if (s.sp < LDS_D) lst[s.sp * 64] = far;
+        else gst[(s.sp - LDS_D) * 64] = far;
+        ++s.sp;
+    } else if (h0) {
+        s.node = c0;
+    } else if (h1) {
+        s.node = c1;
+    } else if (s.sp == 0) {
+        traversing = false;
+    } else {
+        --s.sp;
+        s.node = s.sp < LDS_D ? lst[s.sp * 64] : gst[(s.sp - LDS_D) * 64];
+    }
+}
+
+__device__ __forceinline__ void start_segment(Trav& s)
+{
+    s.tb = __builtin_inff();
+    s.pb = -1;
+    s.qb = -1;
+    s.node = 0;
+    s.sp = 0;
+    s.steps = 0;
+}
+
+// Emission (Alg. 1 "generate exitant ray"): origin y, direction, area offsets.
+__device__ __forceinline__ void emit(const DevLight& L, uint32_t pid, uint32_t stream_id, uint32_t k0, uint32_t k1,
+                                     V3& y, V3& dir, float& au, float& av)
+{
+    const U4 r = philox10(pid, stream_id, 0u, 0u, k0, k1);
+    const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
+    y = v3(L.c[0], L.c[1], L.c[2]);
+    au = 0.0f;
+    av = 0.0f;
+    float sp, cp;
+    sincos_2pi(u3, sp, cp);
+    if (L.type == 0) {
+        const float z = 1.0f - 2.0f * u2;
+        const float rr = __builtin_sqrtf(fmaxf(0.0f, 1.0f - z * z));
+        dir = v3(rr * cp, rr * sp, z);
+    } else {
+        const float ct = u2 > 0.0f ? exp2_c(log2_c(u2) / (L.n + 1.0f)) : 0.0f;
+        const float st = __builtin_sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+        const float a = st * cp, bb = st * sp;
+        dir = v3((a * L.t[0] + bb * L.b[0]) + ct * L.d[0], (a * L.t[1] + bb * L.b[1]) + ct * L.d[1],
+                 (a * L.t[2] + bb * L.b[2]) + ct * L.d[2]);
+        if (L.type == 2) {
+            au = (u0 - 0.5f) * L.w;
+            av = (u1 - 0.5f) * L.h;
+            y = v3((L.c[0] + au * L.t[0]) + av * L.b[0], (L.c[1] + au * L.t[1]) + av * L.b[1],
+                   (L.c[2] + au * L.t[2]) + av * L.b[2]);
+        }
+    }
+}
+
+// Cosine-weighted bounce about the oriented normal (Malley's method in the
+// orthonormal basis of Duff et al. 2017); the flux update is Phi * rho.
+__device__ __forceinline__ V3 bounce_dir(V3 no, uint32_t pid, uint32_t stream_id, uint32_t h, uint32_t k0,
+                                         uint32_t k1)
+{
+    const U4 r = philox10(pid, stream_id, 1u + h, 0u, k0, k1);
+    const float u0 = u24(r.x), u1 = u24(r.y);
+    const float sg = __builtin_copysignf(1.0f, no.z);
+    const float a = -1.0f / (sg + no.z);
+    const float bxy = (no.x * no.y) * a;
+    const V3 b1 = v3(1.0f + ((sg * no.x) * no.x) * a, sg * bxy, -(sg * no.x));
+    const V3 b2 = v3(bxy, sg + (no.y * no.y) * a, -no.y);
+    const float rr = __builtin_sqrtf(u0);
+    float sp, cp;
+    sincos_2pi(u1, sp, cp);
+    const float lx = rr * cp, ly = rr * sp;
+    const float lz = __builtin_sqrtf(fmaxf(0.0f, 1.0f - u0));
+    return v3((lx * b1.x + ly * b2.x) + lz * no.x, (lx * b1.y + ly * b2.y) + lz * no.y,
+              (lx * b1.z + ly * b2.z) + lz * no.z);
+}
+
+// dlog of the first-hit irradiance kernel w.r.t. (c, alpha, beta, P) with x_1
+// fixed (Sec. 4.3 constant sample; Eq. posDeriv generalised to a cos^n lobe,
+// plus the rotation terms and the area-light origin shift of the supplement).
+__device__ __forceinline__ void first_hit_dlog(const DevLight& L, V3 x1, V3 y, V3 n1, float au, float av,
+                                               float dl[6])
+{
+    for (int c = 0; c < 5; ++c) dl[c] = 0.0f;
+    dl[5] = 1.0f / L.P;
+    const V3 v = sub(x1, y);
+    const float r2 = dot(v, v);
+    if (r2 <= 1e-12f) return;
+    const float r = __builtin_sqrtf(r2);
+    const float inv_r = 1.0f / r;
+    const V3 w = v3(v.x * inv_r, v.y * inv_r, v.z * inv_r);
+    const float c1 = -dot(n1, w);
+    if (c1 <= 1e-6f) return;
+    const float k1 = 1.0f / (r * c1);
+    const float k3 = 2.0f * inv_r;
+    if (L.type == 0) {
+        dl[0] = (n1.x + c1 * w.x) * k1 + w.x * k3;
+        dl[1] = (n1.y + c1 * w.y) * k1 + w.y * k3;
+        dl[2] = (n1.z + c1 * w.z) * k1 + w.z * k3;
+        return;
+    }
+    const V3 d = v3(L.d[0], L.d[1], L.d[2]);
+    const float ce = dot(d, w);
+    if (ce <= 1e-6f) return;
+    const float ka = L.n / (r * ce);
+    const V3 G = v3((-((d.x - ce * w.x) * ka) + (n1.x + c1 * w.x) * k1) + w.x * k3,
+                    (-((d.y - ce * w.y) * ka) + (n1.y + c1 * w.y) * k1) + w.y * k3,
+                    (-((d.z - ce * w.z) * ka) + (n1.z + c1 * w.z) * k1) + w.z * k3);
+    const float kd = L.n / ce;
+    float ra = dot(v3(L.dd_da[0], L.dd_da[1], L.dd_da[2]), w) * kd;
+    float rb = dot(v3(L.dd_db[0], L.dd_db[1], L.dd_db[2]), w) * kd;
+    if (L.type == 2) {
+        const V3 dya = v3(av * L.db_da[0], av * L.db_da[1], av * L.db_da[2]);
+        const V3 dyb = v3(au * L.dt_db[0] + av * L.db_db[0], au * L.dt_db[1] + av * L.db_db[1],
+                          au * L.dt_db[2] + av * L.db_db[2]);
+        ra = dot(G, dya) + ra;
+        rb = dot(G, dyb) + rb;
+    }
+    dl[0] = G.x;
+    dl[1] = G.y;
+    dl[2] = G.z;
+    dl[3] = ra;
+    dl[4] = rb;
+}
+
+struct HitInfo {
+    V3 x, no;
+    long long k;
+    float inva, rho;
+};
+
+__device__ __forceinline__ HitInfo hit_info(const Ray& r, float tb, int qb, const DevPatch* __restrict__ patches)
+{
+    HitInfo hi;
+    hi.x = v3(r.ox + tb * r.dx, r.oy + tb * r.dy, r.oz + tb * r.dz);
+    const DevPatch& P = patches[qb];
+    const float4 o = P.o_inva, eu = P.eu_ilu, ev = P.ev_ilv, nr = P.n_rho;
+    const V3 du = sub(hi.x, xyz(o));
+    const float su = dot(du, xyz(eu)) * eu.w;
+    const float sv = dot(du, xyz(ev)) * ev.w;
+    const int ru = P.res_u, rv = P.res_v;
+    int iu = (int)__builtin_floorf(su * (float)ru);
+    int iv = (int)__builtin_floorf(sv * (float)rv);
+    iu = iu < 0 ? 0 : (iu > ru - 1 ? ru - 1 : iu);
+    iv = iv < 0 ? 0 : (iv > rv - 1 ? rv - 1 : iv);
+    hi.k = P.base + (long long)iv * ru + iu;
+    hi.inva = o.w;
+    hi.rho = nr.w;
+    const V3 nq = xyz(nr);
+    const float nd = dot(nq, v3(r.dx, r.dy, r.dz));
+    hi.no = nd < 0.0f ? nq : v3(-nq.x, -nq.y, -nq.z);
+    return hi;
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// The persistent forward / adjoint kernel.
+// ---------------------------------------------------------------------------
+template <bool ADJ, bool STATS, int WPB, int LDS_D>
+__global__ void __launch_bounds__(WPB * 64) k_trace(TraceArgs a)
+{
+    __shared__ int s_stack[WPB * LDS_D * 64];
+    const int lane = threadIdx.x & 63;
+    const int wib = threadIdx.x >> 6;
+    const long long gw = (long long)blockIdx.x * WPB + wib;
+    int* lst = s_stack + wib * LDS_D * 64 + lane;
+    int* gst = a.gstack + gw * (long long)a.gdepth * 64 + lane;
+    const int B = a.max_hits;
+    const int thresh = a.refill_threshold;
+
+    for (;;) {
+        int tile = 0;
+        if (lane == 0) tile = (int)atomicAdd(a.tile_counter, 1u);
+        tile = __builtin_amdgcn_readfirstlane(__shfl(tile, 0));
+        if (tile >= a.n_tiles) break;
+        const int4 ti = a.tiles[tile];
+        const DevLight& L = a.lights[ti.x];
+        const uint32_t first = (uint32_t)ti.y;
+        const int count = ti.z;
+        const uint32_t stream_id = ((uint32_t)ti.w << 16) | (uint32_t)L.l_local;
+        const float phi_r = L.phi_r;
+        long long* S = ADJ ? nullptr : a.S + (long long)ti.w * a.K;
+        const float* g = ADJ ? a.g + (long long)ti.w * a.K : nullptr;
+
+        int next = 0;          // paths of this tile handed out so far (uniform)
+        bool alive = false;    // lane holds a path
+        bool trav = false;     // lane is traversing its current segment
+        uint32_t pid = 0;
+        int h = 0, skip = -1;
+        float T = 1.0f, s_r = 0.0f, au = 0.0f, av = 0.0f;
+        float dphi[6] = {0, 0, 0, 0, 0, 0};
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        unsigned miss = 0, n_seg = 0, n_nodes = 0, n_tris = 0, n_hits = 0;
+        bool overrun = false;
+        Ray r;
+        Trav s;
+        start_segment(s);
+        set_ray(r, v3(0, 0, 0), v3(0, 0, 1));
+
+        for (;;) {
+            // refill lanes without a path (ballot + prefix count)
+            const bool need = !alive;
+            const uint64_t m = ballot(need);
+            if (m != 0 && next < count) {
+                const int slot = next + lanes_below(m);
+                if (need && slot < count) {
+                    pid = first + (uint32_t)slot;
+                    V3 y, dir;
+                    emit(L, pid, stream_id, a.key0, a.key1, y, dir, au, av);
+                    set_ray(r, y, dir);
+                    start_segment(s);
+                    alive = true;
+                    trav = true;
+                    h = 0;
+                    skip = -1;
+                    T = 1.0f;
+                    s_r = 0.0f;
+                    if (STATS) ++n_seg;
+                }
+                next += __popcll(m);
+            }
+            if (ballot(alive) == 0) break;
+
+            // traverse until enough lanes finished their segment
+            for (;;) {
+                const uint64_t tm = ballot(trav);
+                if (tm == 0) break;
+                if (__popcll(ballot(alive && !trav)) >= thresh) break;
+                if (trav)
+                    trav_step<LDS_D, STATS>(r, skip, s, trav, a.nodes, a.tris, lst, gst, n_nodes, n_tris,
+                                            a.max_steps, overrun);
+            }
+
+            // hit processing for lanes whose segment ended
+            if (alive && !trav) {
+                bool end_path = false;
+                if (s.pb < 0) {
+                    ++miss;
+                    end_path = true;
+                } else {
+                    ++h;
+                    if (STATS) ++n_hits;
+                    const HitInfo hi = hit_info(r, s.tb, s.qb, a.patches);
+                    if (!ADJ) {
+                        const float val = (phi_r * T) * hi.inva;
+                        const long long code = (long long)__builtin_rintf(val * 4294967296.0f);
+                        __hip_atomic_fetch_add((unsigned long long*)(S + hi.k), (unsigned long long)code,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    } else {
+                        s_r = s_r + (g[hi.k] * hi.inva) * T;
+                        if (h == 1) {
+                            float dl[6];
+                            first_hit_dlog(L, hi.x, v3(r.ox, r.oy, r.oz), hi.no, au, av, dl);
+#pragma unroll
+                            for (int c = 0; c < 6; ++c) dphi[c] = phi_r * dl[c];
+                        }
+                    }
+                    if (h >= B) {
+                        end_path = true;
+                    } else {
+                        const V3 nd = bounce_dir(hi.no, pid, stream_id, (uint32_t)h, a.key0, a.key1);
+                        set_ray(r, hi.x, nd);
+                        skip = s.qb;
+                        start_segment(s);
+                        trav = true;
+                        T = T * hi.rho;
+                        if (STATS) ++n_seg;
+                    }
+                }
+                if (end_path) {
+                    if (ADJ && h >= 1) {
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) acc[c] += (double)(s_r * dphi[c]);
+                    }
+                    alive = false;
+                }
+            }
+        }
+        if (ADJ) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) acc[c] = wave_sum(acc[c]);
+            if (lane == 0) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) a.partials[(long long)tile * 6 + c] = acc[c];
+            }
+        }
+        const unsigned wm = wave_sum(miss);
+        if (lane == 0 && wm) atomicAdd(a.misses, (unsigned long long)wm);
+        if (overrun) atomicOr(a.flags, 2u);
+        if (STATS) {
+            const unsigned c0 = wave_sum(n_seg), c1 = wave_sum(n_nodes), c2 = wave_sum(n_tris),
+                           c3 = wave_sum(n_hits);
+            if (lane == 0) {
+                atomicAdd(a.stats + 0, (unsigned long long)c0);
+                atomicAdd(a.stats + 1, (unsigned long long)c1);
+                atomicAdd(a.stats + 2, (unsigned long long)c2);
+                atomicAdd(a.stats + 3, (unsigned long long)c3);
+                atomicAdd(a.stats + 4, (unsigned long long)wm);
+            }
+        }
+    }
+}
+
+// One path per thread (grid-stride): hit sequences and per-path adjoint
+// contributions, with the same device functions as the persistent kernel.
+template <int LDS_D>
+__global__ void __launch_bounds__(256) k_record(RecordArgs a)
+{
+    __shared__ int s_stack[4 * LDS_D * 64];
+    const int lane = threadIdx.x & 63;
+    const int wib = threadIdx.x >> 6;
+    const long long gw = (long long)blockIdx.x * 4 + wib;
+    int* lst = s_stack + wib * LDS_D * 64 + lane;
+    int* gst = a.gstack + gw * (long long)a.gdepth * 64 + lane;
+    const DevLight& L = a.lights[a.gl];
+    const float* g = a.g ? a.g + (long long)a.layout * a.K : nullptr;
+    const long long stride = (long long)gridDim.x * 256;
+    for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < a.count; idx += stride) {
+        const uint32_t pid = (uint32_t)(a.first + idx);
+        for (int hh = 0; hh < a.max_hits; ++hh) {
+            a.prim[idx * a.max_hits + hh] = -1;
+            a.texel[idx * a.max_hits + hh] = -1;
+        }
+        V3 y, dir;
+        float au, av;
+        emit(L, pid, a.stream_id, a.key0, a.key1, y, dir, au, av);
+        Ray r;
+        set_ray(r, y, dir);
+        int skip = -1;
+        float T = 1.0f, s_r = 0.0f;
+        float dphi[6] = {0, 0, 0, 0, 0, 0};
+        int h = 0;
+        unsigned dummy0 = 0, dummy1 = 0;
+        bool overrun = false;
+        for (;;) {
+            Trav s;
+            start_segment(s);
+            bool trav = true;
+            while (trav)
+                trav_step<LDS_D, false>(r, skip, s, trav, a.nodes, a.tris, lst, gst, dummy0, dummy1, a.max_steps,
+                                        overrun);
+            if (s.pb < 0) break;
+            ++h;
+            const HitInfo hi = hit_info(r, s.tb, s.qb, a.patches);
+            a.prim[idx * a.max_hits + h - 1] = s.pb;
+            a.texel[idx * a.max_hits + h - 1] = (int)hi.k;
+            if (g) {
+                s_r = s_r + (g[hi.k] * hi.inva) * T;
+                if (h == 1) {
+                    float dl[6];
+                    first_hit_dlog(L, hi.x, v3(r.ox, r.oy, r.oz), hi.no, au, av, dl);
+                    for (int c = 0; c < 6; ++c) dphi[c] = L.phi_r * dl[c];
+                }
+            }
+            if (h >= a.max_hits) break;
+            const V3 nd = bounce_dir(hi.no, pid, a.stream_id, (uint32_t)h, a.key0, a.key1);
+            set_ray(r, hi.x, nd);
+            skip = s.qb;
+            T = T * hi.rho;
+        }
+        if (a.contrib) {
+            for (int c = 0; c < 6; ++c) a.contrib[idx * 6 + c] = (g && h >= 1) ? s_r * dphi[c] : 0.0f;
+        }
+        if (overrun) atomicOr(a.flags, 2u);
+    }
+}
+
+// Luminaire setup: frame R = R_y(beta) R_x(alpha), derivatives, Phi_r = P/N_l.
+// lstat_i = (type, layout, l_local, -), lstat_f = (n, w, h, N_l as float bits unused).
+__global__ void k_light_setup(const float* __restrict__ params, const int4* __restrict__ si,
+                              const float4* __restrict__ sf, const long long* __restrict__ npaths, int n,
+                              DevLight* __restrict__ out)
+{
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n) return;
+    const float* p = params + 6 * l;
+    double sa_d, ca_d, sb_d, cb_d;
+    sincos_f64((double)p[3], sa_d, ca_d);
+    sincos_f64((double)p[4], sb_d, cb_d);
+    const float sa = (float)sa_d, ca = (float)ca_d, sb = (float)sb_d, cb = (float)cb_d;
+    DevLight L;
+    L.c[0] = p[0]; L.c[1] = p[1]; L.c[2] = p[2];
+    L.d[0] = -(sb * ca); L.d[1] = sa; L.d[2] = -(cb * ca);
+    L.t[0] = cb; L.t[1] = 0.0f; L.t[2] = -sb;
+    L.b[0] = sb * sa; L.b[1] = ca; L.b[2] = cb * sa;
+    L.dd_da[0] = sb * sa; L.dd_da[1] = ca; L.dd_da[2] = cb * sa;
+    L.dd_db[0] = -(cb * ca); L.dd_db[1] = 0.0f; L.dd_db[2] = sb * ca;
+    L.dt_db[0] = -sb; L.dt_db[1] = 0.0f; L.dt_db[2] = -cb;
+    L.db_da[0] = sb * ca; L.db_da[1] = -sa; L.db_da[2] = cb * ca;
+    L.db_db[0] = cb * sa; L.db_db[1] = 0.0f; L.db_db[2] = -(sb * sa);
+    const int4 i4 = si[l];
+    const float4 f4 = sf[l];
+    const long long nl = npaths[l];
+    L.P = p[5];
+    L.n_paths = nl;
+    L.phi_r = p[5] / (float)nl;
+    L.n = f4.x;
+    L.w = f4.y;
+    L.h = f4.z;
+    L.type = i4.x;
+    L.layout = i4.y;
+    L.l_local = i4.z;
+    L.pad0 = 0;
+    L.pad1 = 0;
+    out[l] = L;
+}
+
+__global__ void k_clear(long long* __restrict__ S, long long n, unsigned* counter)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && counter) *counter = 0u;
+    longlong2* S2 = (longlong2*)S;
+    const long long n2 = n >> 1;
+    for (long long j = i; j < n2; j += stride) S2[j] = make_longlong2(0, 0);
+    if ((n & 1) && i == 0) S[n - 1] = 0;
+}
+
+__global__ void k_reset_counter(unsigned* counter) { *counter = 0u; }
+
+// E_k = S_k 2^-32 through FP64; sticky overflow flag at |S| >= 2^62.
+__global__ void k_finalize(const long long* __restrict__ S, float* __restrict__ E, long long n,
+                           unsigned* __restrict__ flags)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    bool ovf = false;
+    const long long n2 = n >> 1;
+    const longlong2* S2 = (const longlong2*)S;
+    float2* E2 = (float2*)E;
+    for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < n2; j += stride) {
+        const longlong2 v = S2[j];
+        ovf |= (v.x >= (1ll << 62)) | (v.x <= -(1ll << 62)) | (v.y >= (1ll << 62)) | (v.y <= -(1ll << 62));
+        E2[j] = make_float2((float)((double)v.x * 0x1p-32), (float)((double)v.y * 0x1p-32));
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+        const long long v = S[n - 1];
+        ovf |= (v >= (1ll << 62)) | (v <= -(1ll << 62));
+        E[n - 1] = (float)((double)v * 0x1p-32);
+    }
+    if (ovf) atomicOr(flags, 1u);
+}
+
+// O = 1/2 sum A_k alpha_k (E_k - E*_k)^2 (FP64, fixed grid + fixed tree),
+// g_k = (A_k alpha_k)(E_k - E*_k).
+__global__ void __launch_bounds__(256) k_objective(const float* __restrict__ E, const float* __restrict__ Et,
+                                                  const float* __restrict__ alpha, const float* __restrict__ A,
+                                                  long long K, long long n, float* __restrict__ g,
+                                                  double* __restrict__ part)
+{
+    __shared__ double sh[256];
+    double acc = 0.0;
+    const long long stride = (long long)gridDim.x * 256;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+        const float ak = A[i % K];
+        const float al = alpha ? alpha[i] : 1.0f;
+        const float e = E[i], et = Et[i];
+        if (g) g[i] = (ak * al) * (e - et);
+        const double de = (double)e - (double)et;
+        acc += (double)ak * (double)al * de * de;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_objective_final(const double* __restrict__ part, int n_part,
+                                                        double* __restrict__ O)
+{
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n_part; i += 256) acc += part[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *O = 0.5 * sh[0];
+}
+
+// Per-light gradient: ordered sum of the light's tile partials (one wave per light).
+__global__ void __launch_bounds__(64) k_grad_reduce(const double* __restrict__ partials,
+                                                   const int2* __restrict__ range, int n_lights,
+                                                   float* __restrict__ grad)
+{
+    const int l = blockIdx.x;
+    if (l >= n_lights) return;
+    const int2 rg = range[l];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int t = rg.x + (int)threadIdx.x; t < rg.y; t += 64)
+        for (int c = 0; c < 6; ++c) acc[c] += partials[(long long)t * 6 + c];
+    for (int c = 0; c < 6; ++c) acc[c] = wave_sum(acc[c]);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 6; ++c) grad[6 * l + c] = (float)acc[c];
+}
+
+// Per-texel area A_k from the patch table (binary search of texel_base).
+__global__ void k_texel_area(const float* __restrict__ patch_area, const long long* __restrict__ base,
+                             int n_patches, long long K, float* __restrict__ A)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < K; k += stride) {
+        int lo = 0, hi = n_patches - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (base[mid] <= k) lo = mid;
+            else hi = mid - 1;
+        }
+        A[k] = patch_area[lo];
+    }
+}
+
+inline int nblocks(long long n, int b, int cap)
+{
+    long long x = (n + b - 1) / b;
+    if (x > cap) x = cap;
+    if (x < 1) x = 1;
+    return (int)x;
+}
+
+template <bool ADJ, bool STATS, int WPB>
+hipError_t launch_wpb(const TraceArgs& a, int lds_depth, int blocks, hipStream_t st)
+{
+    if (lds_depth == 16)
+        k_trace<ADJ, STATS, WPB, 16><<<blocks, WPB * 64, 0, st>>>(a);
+    else
+        k_trace<ADJ, STATS, WPB, 32><<<blocks, WPB * 64, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+template <bool ADJ, bool STATS>
+hipError_t launch_t(const TraceArgs& a, int wpb, int lds_depth, int blocks, hipStream_t st)
+{
+    switch (wpb) {
+        case 1: return launch_wpb<ADJ, STATS, 1>(a, lds_depth, blocks, st);
+        case 2: return launch_wpb<ADJ, STATS, 2>(a, lds_depth, blocks, st);
+        default: return launch_wpb<ADJ, STATS, 4>(a, lds_depth, blocks, st);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_trace(bool adjoint, bool stats, const TraceArgs& a, int waves_per_block, int lds_depth,
+                        int blocks, hipStream_t st)
+{
+    if (adjoint) return launch_t<true, false>(a, waves_per_block, lds_depth, blocks, st);
+    if (stats) return launch_t<false, true>(a, waves_per_block, lds_depth, blocks, st);
+    return launch_t<false, false>(a, waves_per_block, lds_depth, blocks, st);
+}
+
+hipError_t launch_record(const RecordArgs& a, int lds_depth, hipStream_t st)
+{
+    const int blocks = nblocks(a.count, 256, kRecordBlocks);
+    if (lds_depth == 16)
+        k_record<16><<<blocks, 256, 0, st>>>(a);
+    else
+        k_record<32><<<blocks, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_light_setup(const float* params, const int4* si, const float4* sf, const long long* npaths,
+                              int n_lights, DevLight* out, hipStream_t st)
+{
+    k_light_setup<<<nblocks(n_lights, 64, 1 << 20), 64, 0, st>>>(params, si, sf, npaths, n_lights, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear(long long* S, long long n, unsigned* counter, hipStream_t st)
+{
+    k_clear<<<nblocks(n / 2 + 1, 256, 4096), 256, 0, st>>>(S, n, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_counter(unsigned* counter, hipStream_t st)
+{
+    k_reset_counter<<<1, 1, 0, st>>>(counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const long long* S, float* E, long long n, unsigned* flags, hipStream_t st)
+{
+    k_finalize<<<nblocks(n / 2 + 1, 256, 4096), 256, 0, st>>>(S, E, n, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_objective(const float* E, const float* Et, const float* alpha, const float* A, long long K,
+                            long long n, float* g, double* partials, double* O, hipStream_t st)
+{
+    k_objective<<<kObjBlocks, 256, 0, st>>>(E, Et, alpha, A, K, n, g, partials);
+    k_objective_final<<<1, 256, 0, st>>>(partials, kObjBlocks, O);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(const double* partials, const int2* range, int n_lights, float* grad,
+                              hipStream_t st)
+{
+    k_grad_reduce<<<n_lights, 64, 0, st>>>(partials, range, n_lights, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_texel_area(const float* patch_area, const long long* base, int n_patches, long long K, float* A,
+                             hipStream_t st)
+{
+    k_texel_area<<<nblocks(K, 256, 8192), 256, 0, st>>>(patch_area, base, n_patches, K, A);
+    return hipGetLastError();
+}
+
+}  // namespace lt

@@ -1,0 +1,279 @@
+"""ctypes binding of liblt.so (argument marshalling only).
+
+Every step of the light-tracing path runs in the HIP kernels of liblt.so.
+This module loads the in-tree library (raising if it has not been built),
+passes device pointers of torch tensors and the current torch stream, and
+turns error codes into exceptions.  There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblt.so")
+
+LT_OK, LT_EINVAL, LT_ENOMEM, LT_EHIP, LT_ESTATE, LT_EOVERFLOW = 0, -1, -2, -3, -4, -5
+LT_FLAG_GRAPH, LT_FLAG_PROPOSAL = 1, 2
+
+EXPORTED = [
+    "lt_create", "lt_destroy", "lt_last_error", "lt_set_stream", "lt_sync", "lt_scene_upload",
+    "lt_set_lights", "lt_trace_forward", "lt_objective", "lt_trace_adjoint", "lt_record_paths",
+    "lt_trace_stats", "lt_get_tuning", "lt_set_tuning", "lt_autotune", "lt_info_get", "lt_set_timing",
+    "lt_timing_read",
+]
+
+PATCH_ITEMSIZE = 88
+LIGHT_ITEMSIZE = 20
+
+
+class LtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"liblt error {code}: {msg}")
+        self.code = code
+
+
+class TraceCfg(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("paths_per_layout", C.c_int64), ("max_hits", C.c_int32),
+                ("flags", C.c_uint32), ("alpha_plain", C.c_float), ("reserved", C.c_int32)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32), ("tile_paths", C.c_int32),
+                ("refill_threshold", C.c_int32), ("lds_depth", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k in ("waves_per_block", "blocks_per_cu", "tile_paths",
+                                               "refill_threshold", "lds_depth")}
+
+
+class Info(C.Structure):
+    _fields_ = [("n_tris", C.c_int64), ("n_patches", C.c_int64), ("n_texels", C.c_int64),
+                ("bvh_nodes", C.c_int32), ("bvh_depth", C.c_int32), ("device_bytes", C.c_int64),
+                ("n_lights", C.c_int32), ("n_layouts", C.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load liblt.so; raises if it is missing (build it with __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: the HIP library must be built before use")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+    L.lt_create.argtypes = [C.c_int, P, C.POINTER(P)]
+    L.lt_destroy.argtypes = [P]
+    L.lt_destroy.restype = None
+    L.lt_last_error.argtypes = [P]
+    L.lt_last_error.restype = C.c_char_p
+    L.lt_set_stream.argtypes = [P, P]
+    L.lt_sync.argtypes = [P, C.POINTER(C.c_uint32)]
+    L.lt_scene_upload.argtypes = [P, P, I64, P, P, I64, P, I32, C.POINTER(I64)]
+    L.lt_set_lights.argtypes = [P, P, I32, P, I32]
+    L.lt_trace_forward.argtypes = [P, C.POINTER(TraceCfg), P, P, P]
+    L.lt_objective.argtypes = [P, P, P, P, I64, P, P]
+    L.lt_trace_adjoint.argtypes = [P, C.POINTER(TraceCfg), P, P, P, P]
+    L.lt_record_paths.argtypes = [P, C.POINTER(TraceCfg), P, I32, I32, I64, I64, P, P, P, P]
+    L.lt_trace_stats.argtypes = [P, C.POINTER(TraceCfg), P, P, C.POINTER(I64)]
+    L.lt_get_tuning.argtypes = [P, C.POINTER(Tuning)]
+    L.lt_set_tuning.argtypes = [P, C.POINTER(Tuning)]
+    L.lt_autotune.argtypes = [P, C.POINTER(TraceCfg), P, P, P, P, P, C.c_char_p, C.POINTER(C.c_float)]
+    L.lt_info_get.argtypes = [P, C.POINTER(Info)]
+    L.lt_set_timing.argtypes = [P, C.c_int]
+    L.lt_timing_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(I32), C.POINTER(C.c_double), C.POINTER(I32)]
+    for name in EXPORTED:
+        if name not in ("lt_destroy", "lt_last_error"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One liblt context on a torch CUDA (HIP) device."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self._torch = torch
+        self.lib = load()
+        self.device = device
+        h = C.c_void_p()
+        rc = self.lib.lt_create(device, C.c_void_p(torch.cuda.current_stream(device).cuda_stream), C.byref(h))
+        if rc != LT_OK:
+            raise LtError(rc, "lt_create failed")
+        self.h = h
+        self.n_texels = 0
+        self.n_lights = 0
+        self.n_layouts = 0
+        self.layout_offsets = None
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != LT_OK:
+            raise LtError(rc, self.lib.lt_last_error(self.h).decode())
+
+    def _stream(self):
+        self._check(self.lib.lt_set_stream(
+            self.h, C.c_void_p(self._torch.cuda.current_stream(self.device).cuda_stream)))
+
+    # -- scene / lights ------------------------------------------------------
+    def upload_scene(self, verts, tris, tri_patch, patches) -> int:
+        v = np.ascontiguousarray(verts, np.float32)
+        t = np.ascontiguousarray(tris, np.int32)
+        tp = np.ascontiguousarray(tri_patch, np.int32)
+        p = np.ascontiguousarray(patches)
+        assert p.dtype.itemsize == PATCH_ITEMSIZE, "patch records must be 88-byte lt_patch structs"
+        K = C.c_int64()
+        self._stream()
+        self._check(self.lib.lt_scene_upload(self.h, v.ctypes.data, v.shape[0], t.ctypes.data, tp.ctypes.data,
+                                             t.shape[0], p.ctypes.data, p.shape[0], C.byref(K)))
+        self.n_texels = int(K.value)
+        return self.n_texels
+
+    def set_lights(self, static, layout_offsets):
+        s = np.ascontiguousarray(static)
+        assert s.dtype.itemsize == LIGHT_ITEMSIZE
+        o = np.ascontiguousarray(layout_offsets, np.int32)
+        self._stream()
+        self._check(self.lib.lt_set_lights(self.h, s.ctypes.data, s.shape[0], o.ctypes.data, o.shape[0] - 1))
+        self.n_lights = int(s.shape[0])
+        self.n_layouts = int(o.shape[0] - 1)
+        self.layout_offsets = o.copy()
+
+    # -- tracing -------------------------------------------------------------
+    @staticmethod
+    def cfg(seed, paths_per_layout, max_hits, graph=False, proposal=False, alpha_plain=0.2):
+        flags = (LT_FLAG_GRAPH if graph else 0) | (LT_FLAG_PROPOSAL if proposal else 0)
+        return TraceCfg(int(seed) & 0xFFFFFFFFFFFFFFFF, int(paths_per_layout), int(max_hits), flags,
+                        float(alpha_plain), 0)
+
+    def _dev(self, t, dtype, shape):
+        torch = self._torch
+        assert t.is_cuda and t.dtype == dtype and t.is_contiguous(), (t.device, t.dtype)
+        assert tuple(t.shape) == tuple(shape), (tuple(t.shape), shape)
+        return t
+
+    def trace_forward(self, params, cfg, S=None, E=None):
+        torch = self._torch
+        dev = params.device
+        n = (self.n_layouts, self.n_texels)
+        self._dev(params, torch.float32, (self.n_lights, 6))
+        if S is None:
+            S = torch.empty(n, dtype=torch.int64, device=dev)
+        if E is None:
+            E = torch.empty(n, dtype=torch.float32, device=dev)
+        self._dev(S, torch.int64, n)
+        self._dev(E, torch.float32, n)
+        self._stream()
+        self._check(self.lib.lt_trace_forward(self.h, C.byref(cfg), _ptr(params), _ptr(S), _ptr(E)))
+        return E, S
+
+    def objective(self, E, Et, alpha=None, g=None, O=None):
+        torch = self._torch
+        n = E.numel()
+        self._dev(E, torch.float32, E.shape)
+        self._dev(Et, torch.float32, E.shape)
+        if alpha is not None:
+            self._dev(alpha, torch.float32, E.shape)
+        if g is None:
+            g = torch.empty_like(E)
+        if O is None:
+            O = torch.empty(1, dtype=torch.float64, device=E.device)
+        self._stream()
+        self._check(self.lib.lt_objective(self.h, _ptr(E), _ptr(Et), _ptr(alpha), n, _ptr(O), _ptr(g)))
+        return O, g
+
+    def trace_adjoint(self, params, dOdE, cfg, grad=None, bin_hist=None):
+        torch = self._torch
+        self._dev(params, torch.float32, (self.n_lights, 6))
+        self._dev(dOdE, torch.float32, (self.n_layouts, self.n_texels))
+        if grad is None:
+            grad = torch.empty((self.n_lights, 6), dtype=torch.float32, device=params.device)
+        self._dev(grad, torch.float32, (self.n_lights, 6))
+        self._stream()
+        self._check(self.lib.lt_trace_adjoint(self.h, C.byref(cfg), _ptr(params), _ptr(dOdE), _ptr(grad),
+                                              _ptr(bin_hist)))
+        return grad
+
+    def record_paths(self, params, cfg, layout, light, first, count, dOdE=None):
+        torch = self._torch
+        dev = params.device
+        prim = torch.empty((count, cfg.max_hits), dtype=torch.int32, device=dev)
+        tex = torch.empty((count, cfg.max_hits), dtype=torch.int32, device=dev)
+        contrib = None
+        if dOdE is not None:
+            self._dev(dOdE, torch.float32, (self.n_layouts, self.n_texels))
+            contrib = torch.empty((count, 6), dtype=torch.float32, device=dev)
+        self._stream()
+        self._check(self.lib.lt_record_paths(self.h, C.byref(cfg), _ptr(params), int(layout), int(light),
+                                             int(first), int(count), _ptr(prim), _ptr(tex), _ptr(dOdE),
+                                             _ptr(contrib)))
+        return prim, tex, contrib
+
+    def trace_stats(self, params, cfg, S=None):
+        torch = self._torch
+        if S is None:
+            S = torch.empty((self.n_layouts, self.n_texels), dtype=torch.int64, device=params.device)
+        out = (C.c_int64 * 5)()
+        self._stream()
+        self._check(self.lib.lt_trace_stats(self.h, C.byref(cfg), _ptr(params), _ptr(S), out))
+        keys = ("segments", "nodes", "tri_tests", "hits", "misses")
+        return dict(zip(keys, [int(x) for x in out]))
+
+    def sync(self) -> int:
+        f = C.c_uint32()
+        self._check(self.lib.lt_sync(self.h, C.byref(f)))
+        return int(f.value)
+
+    def get_tuning(self) -> Tuning:
+        t = Tuning()
+        self._check(self.lib.lt_get_tuning(self.h, C.byref(t)))
+        return t
+
+    def set_tuning(self, **kw):
+        t = self.get_tuning()
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        self._check(self.lib.lt_set_tuning(self.h, C.byref(t)))
+
+    def autotune(self, params, cfg, S, E, dOdE, grad, cache_path=None) -> float:
+        best = C.c_float()
+        cp = None if cache_path is None else cache_path.encode()
+        self._stream()
+        self._check(self.lib.lt_autotune(self.h, C.byref(cfg), _ptr(params), _ptr(S), _ptr(E), _ptr(dOdE),
+                                         _ptr(grad), cp, C.byref(best)))
+        return float(best.value)
+
+    def set_timing(self, enable: bool):
+        self._check(self.lib.lt_set_timing(self.h, 1 if enable else 0))
+
+    def timing_read(self):
+        """(forward kernel ms summed, launches, adjoint kernel ms summed, launches)."""
+        f, a = C.c_double(), C.c_double()
+        nf, na = C.c_int32(), C.c_int32()
+        self._check(self.lib.lt_timing_read(self.h, C.byref(f), C.byref(nf), C.byref(a), C.byref(na)))
+        return f.value, nf.value, a.value, na.value
+
+    def info(self) -> dict:
+        i = Info()
+        self._check(self.lib.lt_info_get(self.h, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in Info._fields_}

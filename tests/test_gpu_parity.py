@@ -1,0 +1,268 @@
+"""GPU path vs the CPU oracle, element by element on identical seeded inputs.
+
+Everything on the GPU side goes through the C ABI (liblt.so).  Oracle inputs
+and expected values come only from the generators and the oracle.  Bars
+(from the method's target): texel irradiance rel-L2 <= 1e-4, gradient
+components <= 1e-3 relative, hit sequences identical on >= 99.99 % of paths.
+The arithmetic contract makes the two sides bit-identical in practice; the
+tests also report how many texels / paths match exactly.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import lt_inputs as li
+from lt_inputs.scenes import make_lights, POINT, SPOT, RECT
+
+pytestmark = pytest.mark.gpu
+
+TEX_BAR, GRAD_BAR, PATH_BAR = 1e-4, 1e-3, 0.9999
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def make_ctx(torch, scene, lights):
+    from paper_2310_02043_amd import Context
+    ctx = Context(0)
+    K = ctx.upload_scene(scene.verts, scene.tris, scene.tri_patch, scene.patches)
+    assert K == scene.n_texels
+    ctx.set_lights(lights.static, lights.layout_offsets)
+    return ctx
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def grad_rel(g_gpu, g_ref):
+    g_gpu = np.asarray(g_gpu, np.float64)
+    g_ref = np.asarray(g_ref, np.float64)
+    scale = np.maximum(np.abs(g_ref), 1e-6 * np.abs(g_ref).max() + 1e-30)
+    return float(np.max(np.abs(g_gpu - g_ref) / scale))
+
+
+def run_case(torch, oracle_lib, scene, lights, params, seed, ppl, B, use_bvh, check_grad=True, target=None,
+             graph=False):
+    ctx = make_ctx(torch, scene, lights)
+    osc = oracle_lib.OracleScene(scene, use_bvh=use_bvh)
+    ol = oracle_lib.OracleLights(lights)
+    p_d = torch.tensor(params, device="cuda")
+    cfg = ctx.cfg(seed, ppl, B, graph=graph)
+    E_d, S_d = ctx.trace_forward(p_d, cfg)
+    assert ctx.sync() == 0
+    S_ref, miss_ref = oracle_lib.forward(osc, ol, params, seed, ppl, B)
+    S_gpu = S_d.cpu().numpy()
+    E_ref = oracle_lib.fixed_to_float(S_ref)
+    exact = float((S_gpu == S_ref).mean())
+    r = rel_l2(E_d.cpu().numpy(), E_ref)
+    say(f"  texels: rel-L2 {r:.3e}, bit-identical {exact * 100:.4f} %")
+    assert r <= TEX_BAR
+    out = dict(ctx=ctx, E_ref=E_ref, S_ref=S_ref, exact=exact, p_d=p_d, osc=osc, ol=ol)
+    if check_grad:
+        Et = target if target is not None else np.stack(
+            [li.painted_target(scene, float(np.mean(E_ref[j])) * 1.5 + 1e-3, seed=j) for j in range(lights.n_layouts)])
+        O_ref, g_ref = oracle_lib.objective(E_ref, Et, scene.texel_area())
+        grad_ref, _ = oracle_lib.adjoint(osc, ol, params, seed, ppl, B, g_ref)
+        g_d = torch.tensor(g_ref, device="cuda")
+        grad_d = ctx.trace_adjoint(p_d, g_d, cfg)
+        ctx.sync()
+        e = grad_rel(grad_d.cpu().numpy(), grad_ref)
+        say(f"  gradient: max rel err {e:.3e}")
+        assert e <= GRAD_BAR
+        out.update(g_ref=g_ref, grad_ref=grad_ref, Et=Et, O_ref=O_ref, g_d=g_d)
+    return out
+
+
+def test_box_room_full(torch_dev, oracle_lib):
+    """Closed 4x3x2.5 m room + two boxes, spot cos^4, 2^20 paths, 3 hits (full size)."""
+    torch = torch_dev
+    c1 = li.box_room()
+    say("box_room full: paths", c1["paths"])
+    run_case(torch, oracle_lib, c1["scene"], c1["lights"], c1["lights"].params, c1["seed"], c1["paths"],
+             c1["max_hits"], use_bvh=False)
+
+
+def test_box_room_hit_sequences(torch_dev, oracle_lib):
+    torch = torch_dev
+    c1 = li.box_room()
+    sc, lights = c1["scene"], c1["lights"]
+    ctx = make_ctx(torch, sc, lights)
+    p_d = torch.tensor(lights.params, device="cuda")
+    N, B = c1["paths"], c1["max_hits"]
+    cfg = ctx.cfg(c1["seed"], N, B)
+    prim_d, tex_d, _ = ctx.record_paths(p_d, cfg, 0, 0, 0, N)
+    prim_ref, tex_ref, _ = oracle_lib.record(oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights),
+                                             lights.params, c1["seed"], N, B, 0, 0, 0, N)
+    same = np.all(prim_d.cpu().numpy() == prim_ref, 1) & np.all(tex_d.cpu().numpy() == tex_ref, 1)
+    say(f"  identical hit sequences: {same.mean() * 100:.4f} % of {N}")
+    assert same.mean() >= PATH_BAR
+
+
+def test_objective_matches(torch_dev, oracle_lib):
+    torch = torch_dev
+    c1 = li.box_room()
+    sc = c1["scene"]
+    ctx = make_ctx(torch, sc, c1["lights"])
+    rng = np.random.default_rng(3)
+    E = rng.uniform(0, 40, (1, sc.n_texels)).astype(np.float32)
+    Et = li.painted_target(sc, 20.0)[None]
+    al = rng.uniform(0, 2, E.shape).astype(np.float32)
+    O_ref, g_ref = oracle_lib.objective(E, Et, sc.texel_area(), al)
+    O_d, g_d = ctx.objective(torch.tensor(E, device="cuda"), torch.tensor(Et, device="cuda"),
+                             torch.tensor(al, device="cuda"))
+    assert abs(O_d.item() / O_ref - 1) < 1e-12
+    assert np.array_equal(g_d.cpu().numpy(), g_ref)
+
+
+def test_office_reduced_paths(torch_dev, oracle_lib):
+    """The full 200k-triangle office at 2^18 paths (oracle-sized), 5 hits, 16 area lights."""
+    torch = torch_dev
+    c2 = li.office()
+    say("office reduced: tris", c2["scene"].n_tris, "texels", c2["scene"].n_texels)
+    run_case(torch, oracle_lib, c2["scene"], c2["lights"], c2["lights"].params, c2["seed"], 1 << 18,
+             c2["max_hits"], use_bvh=True)
+
+
+def test_office_full_size_sampled(torch_dev, oracle_lib):
+    """Bench launch configuration (2^26 paths, 5 hits): sampled paths vs the
+    oracle one by one, plus the power identity sum_l P_l dO/dP_l = sum_k g_k E_k."""
+    torch = torch_dev
+    c2 = li.office()
+    sc, lights = c2["scene"], c2["lights"]
+    ctx = make_ctx(torch, sc, lights)
+    osc, ol = oracle_lib.OracleScene(sc, use_bvh=True), oracle_lib.OracleLights(lights)
+    p_d = torch.tensor(lights.params, device="cuda")
+    N, B = c2["paths"], c2["max_hits"]
+    cfg = ctx.cfg(c2["seed"], N, B)
+    E_d, S_d = ctx.trace_forward(p_d, cfg)
+    assert ctx.sync() == 0
+    Et_d = torch.tensor(li.painted_target(sc, 0.5)[None], device="cuda")
+    O_d, g_d = ctx.objective(E_d, Et_d)
+    grad_d = ctx.trace_adjoint(p_d, g_d, cfg)
+    ctx.sync()
+    lhs = float(np.sum(lights.params[:, 5].astype(np.float64) * grad_d.cpu().numpy()[:, 5].astype(np.float64)))
+    rhs = float(torch.sum(g_d.double() * E_d.double()).item())
+    say(f"  power identity: {lhs:.6e} vs {rhs:.6e}")
+    assert abs(lhs / rhs - 1) < 1e-4
+    rng = np.random.default_rng(9)
+    g_np = g_d.cpu().numpy()
+    n_same = n_tot = 0
+    for light in rng.choice(lights.n_lights, 4, replace=False):
+        nl = N // lights.n_lights
+        first = int(rng.integers(0, nl - 4096))
+        prim_d, tex_d, con_d = ctx.record_paths(p_d, cfg, 0, int(light), first, 4096, dOdE=g_d)
+        prim_r, tex_r, con_r = oracle_lib.record(osc, ol, lights.params, c2["seed"], N, B, 0, int(light), first,
+                                                 4096, dOdE=g_np)
+        same = np.all(prim_d.cpu().numpy() == prim_r, 1) & np.all(tex_d.cpu().numpy() == tex_r, 1)
+        n_same += int(same.sum())
+        n_tot += same.size
+        c = con_d.cpu().numpy()
+        assert rel_l2(c[same], con_r[same]) < 1e-5
+    say(f"  sampled identical hit sequences: {n_same}/{n_tot}")
+    assert n_same / n_tot >= PATH_BAR
+
+
+def test_batched_layouts_reduced(torch_dev, oracle_lib):
+    """Room set with 64 layouts of 4..48 lights in one persistent launch (2^14 paths per layout)."""
+    torch = torch_dev
+    c3 = li.room_set()
+    say("room_set: layouts", c3["lights"].n_layouts, "lights", c3["lights"].n_lights)
+    run_case(torch, oracle_lib, c3["scene"], c3["lights"], c3["lights"].params, c3["seed"], 1 << 14,
+             c3["max_hits"], use_bvh=True)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_determinism_and_graph_replay(torch_dev, oracle_lib, graph):
+    torch = torch_dev
+    c1 = li.box_room()
+    ctx = make_ctx(torch, c1["scene"], c1["lights"])
+    p_d = torch.tensor(c1["lights"].params, device="cuda")
+    cfg = ctx.cfg(77, 1 << 18, 3, graph=graph)
+    E0, S0 = ctx.trace_forward(p_d, cfg)
+    S0 = S0.clone()
+    g = torch.randn_like(E0)
+    G0 = ctx.trace_adjoint(p_d, g, cfg).clone()
+    for rep in range(3):
+        E1, S1 = ctx.trace_forward(p_d, cfg)
+        torch.cuda.synchronize()
+        assert torch.equal(S0, S1)
+        G1 = ctx.trace_adjoint(p_d, g, cfg)
+        torch.cuda.synchronize()
+        assert torch.equal(G0, G1)
+        _ = (E1 * 2).sum().item()   # unrelated eager work between replays
+
+
+@pytest.mark.parametrize("case", ["ragged", "one_path_per_light", "single_hit", "point_closed_box",
+                                  "tiny_scene", "rect_many_lights"])
+def test_edge_cases(torch_dev, oracle_lib, case):
+    torch = torch_dev
+    if case == "ragged":
+        sc = li.box_room()["scene"]
+        lights = make_lights([SPOT, POINT, RECT], [3.0, 0.0, 2.0], [(0, 0), (0, 0), (0.5, 0.3)], [0, 0, 0],
+                             [[1.0, 1.0, 2.0, 0.1, 0.2, 50.0], [3.0, 2.0, 1.8, 0, 0, 30.0],
+                              [2.0, 1.5, 2.4, -0.2, 0.3, 70.0]])
+        ppl, B = 100_003, 3
+    elif case == "one_path_per_light":
+        sc = li.box_room()["scene"]
+        lights = make_lights([SPOT, POINT], [3.0, 0.0], [(0, 0), (0, 0)], [0, 1],
+                             [[1.0, 1.0, 2.0, 0.1, 0.2, 50.0], [3.0, 2.0, 1.8, 0, 0, 30.0]])
+        ppl, B = 1, 3
+    elif case == "single_hit":
+        sc = li.plane_scene(half=3.0, res=32)
+        lights = make_lights([POINT], [0.0], [(0, 0)], [0], [[0.2, 0.1, 1.0, 0, 0, 10.0]])
+        ppl, B = 1 << 16, 1
+    elif case == "point_closed_box":
+        sc = li.closed_box(albedo=0.7)
+        lights = make_lights([POINT], [0.0], [(0, 0)], [0], [[0.9, 0.8, 0.4, 0, 0, 10.0]])
+        ppl, B = 1 << 16, 8
+    elif case == "tiny_scene":
+        sb = li.SceneBuilder()
+        sb.quads([-1.0, -1.0, 0.0], [2.0, 0, 0], [0, 2.0, 0], 0.5, res=(3, 5))
+        sc = sb.build("one_quad", fixed_res=(3, 5))
+        lights = make_lights([SPOT], [1.0], [(0, 0)], [0], [[0.0, 0.0, 1.0, 0.0, 0.0, 5.0]])
+        ppl, B = 5000, 2
+    else:
+        sc = li.box_room()["scene"]
+        n = 40
+        rng = np.random.default_rng(2)
+        ps = [[rng.uniform(0.5, 3.5), rng.uniform(0.5, 2.5), rng.uniform(1.5, 2.4), rng.uniform(-0.3, 0.3),
+               rng.uniform(-0.3, 0.3), rng.uniform(5, 20)] for _ in range(n)]
+        lights = make_lights([RECT] * n, rng.uniform(1, 6, n), [(0.3, 0.2)] * n, [0] * n, ps)
+        ppl, B = 40 * 1000 + 17, 4
+    say("edge case", case)
+    out = run_case(torch, oracle_lib, sc, lights, lights.params, 0xE0 + len(case), ppl, B, use_bvh=False)
+    if case == "point_closed_box":
+        assert out["S_ref"].sum() > 0
+
+
+def test_invalid_arguments_raise(torch_dev):
+    torch = torch_dev
+    from paper_2310_02043_amd.native import LtError
+    c1 = li.box_room()
+    ctx = make_ctx(torch, c1["scene"], c1["lights"])
+    p_d = torch.tensor(c1["lights"].params, device="cuda")
+    with pytest.raises(LtError):
+        ctx.trace_forward(p_d, ctx.cfg(1, 1 << 10, 0))            # max_hits 0
+    with pytest.raises(LtError):
+        ctx.trace_forward(p_d, ctx.cfg(1, 0, 3))                  # fewer paths than lights
+    with pytest.raises(LtError):
+        ctx.record_paths(p_d, ctx.cfg(1, 100, 3), 0, 0, 90, 20)   # range beyond the light's paths
+    bad = c1["scene"].patches.copy()
+    bad["texel_base"][1] += 1
+    with pytest.raises(LtError):
+        ctx.upload_scene(c1["scene"].verts, c1["scene"].tris, c1["scene"].tri_patch, bad)
