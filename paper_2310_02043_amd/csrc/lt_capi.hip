@@ -67,7 +67,6 @@ struct lt_ctx {
     long long* d_npaths = nullptr;
 
     // scratch
-    unsigned* d_counter = nullptr;
     unsigned long long* d_misses = nullptr;
     unsigned* d_flags = nullptr;
     unsigned long long* d_stats = nullptr;
@@ -130,14 +129,19 @@ lt_tuning default_tuning()
     lt_tuning t;
     memset(&t, 0, sizeof(t));
     t.waves_per_block = 4;
-    t.blocks_per_cu = 4;
+    t.xcd_remap = 1;
     t.tile_paths = 0;
     t.refill_threshold = 16;
-    t.lds_depth = 16;
+    t.lds_depth = 32;
     return t;
 }
 
-int n_waves(const lt_ctx* c) { return c->n_cu * c->tune.blocks_per_cu * c->tune.waves_per_block; }
+// waves of the trace launch: one per work tile, rounded up to whole blocks
+long long trace_blocks(const lt_ctx* c)
+{
+    const int w = c->tune.waves_per_block;
+    return std::max<long long>(1, (c->n_tiles + w - 1) / w);
+}
 
 long long paths_of_light(long long ppl, int n_in_layout, int l)
 {
@@ -147,8 +151,9 @@ long long paths_of_light(long long ppl, int n_in_layout, int l)
 int effective_tile_paths(const lt_ctx* c, long long ppl)
 {
     if (c->tune.tile_paths > 0) return c->tune.tile_paths;
+    // about 64 tiles per CU: enough waves to fill the chip and balance the tail
     const long long total = ppl * (long long)c->n_layouts;
-    long long tp = total / ((long long)n_waves(c) * 4);
+    long long tp = total / ((long long)c->n_cu * 64);
     tp = (tp / 64) * 64;
     if (tp < 64) tp = 64;
     if (tp > 8192) tp = 8192;
@@ -259,7 +264,7 @@ TraceArgs trace_args(lt_ctx* c, const lt_trace_cfg* cfg)
     a.tiles = c->d_tiles;
     a.n_tiles = c->n_tiles;
     a.max_hits = cfg->max_hits;
-    a.tile_counter = c->d_counter;
+    a.xcd_remap = c->tune.xcd_remap;
     a.key0 = (uint32_t)cfg->seed;
     a.key1 = (uint32_t)(cfg->seed >> 32);
     a.K = c->K;
@@ -325,7 +330,7 @@ std::vector<uint64_t> make_key(lt_ctx* c, int kind, const lt_trace_cfg* cfg, std
     k.push_back((uint64_t)cfg->paths_per_layout);
     k.push_back((uint64_t)cfg->max_hits);
     k.push_back((uint64_t)cfg->flags);
-    k.push_back((uint64_t)c->tune.waves_per_block | ((uint64_t)c->tune.blocks_per_cu << 8) |
+    k.push_back((uint64_t)c->tune.waves_per_block | ((uint64_t)c->tune.xcd_remap << 8) |
                 ((uint64_t)c->tune.refill_threshold << 24) | ((uint64_t)c->tune.lds_depth << 40));
     k.push_back((uint64_t)c->tiles_tp);
     for (const void* p : ptrs) k.push_back((uint64_t)(uintptr_t)p);
@@ -352,15 +357,13 @@ int lt_create(int device, void* hip_stream, lt_ctx** out)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->n_cu = prop.multiProcessorCount;
-    if (hipMalloc(&c->d_counter, sizeof(unsigned)) != hipSuccess ||
-        hipMalloc(&c->d_misses, sizeof(unsigned long long)) != hipSuccess ||
+    if (hipMalloc(&c->d_misses, sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&c->d_flags, sizeof(unsigned)) != hipSuccess ||
         hipMalloc(&c->d_stats, sizeof(unsigned long long) * 8) != hipSuccess ||
         hipMalloc(&c->d_objpart, sizeof(double) * kObjBlocks) != hipSuccess) {
         lt_destroy(c);
         return LT_ENOMEM;
     }
-    hipMemset(c->d_counter, 0, sizeof(unsigned));
     hipMemset(c->d_misses, 0, sizeof(unsigned long long));
     hipMemset(c->d_flags, 0, sizeof(unsigned));
     hipMemset(c->d_stats, 0, sizeof(unsigned long long) * 8);
@@ -379,7 +382,7 @@ void lt_destroy(lt_ctx* c)
     free_scene(c);
     free_tiles(c);
     hipFree(c->d_si); hipFree(c->d_sf); hipFree(c->d_lights);
-    hipFree(c->d_counter); hipFree(c->d_misses); hipFree(c->d_flags); hipFree(c->d_stats);
+    hipFree(c->d_misses); hipFree(c->d_flags); hipFree(c->d_stats);
     hipFree(c->d_objpart); hipFree(c->d_partials); hipFree(c->d_gstack);
     if (c->ev_in) hipEventDestroy(c->ev_in);
     if (c->ev_out) hipEventDestroy(c->ev_out);
@@ -560,7 +563,7 @@ int lt_trace_forward(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     if (((uintptr_t)d_S & 15) || ((uintptr_t)d_E & 7) || ((uintptr_t)d_params & 3))
         return fail(c, LT_EINVAL, "d_S must be 16-byte and d_E 8-byte aligned");
     HIPCHK(c, hipSetDevice(c->device));
-    const long long blocks = (long long)c->n_cu * c->tune.blocks_per_cu;
+    const long long blocks = trace_blocks(c);
     rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
     if (rc) return rc;
     TraceArgs a = trace_args(c, cfg);
@@ -569,7 +572,7 @@ int lt_trace_forward(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
     auto body = [&](hipStream_t st) -> hipError_t {
         hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
-        if (e == hipSuccess) e = launch_clear(a.S, n, c->d_counter, st);
+        if (e == hipSuccess) e = launch_clear(a.S, n, st);
         if (e == hipSuccess) e = timed_trace(c, false, graph, a, (int)blocks, st);
         if (e == hipSuccess) e = launch_finalize(a.S, d_E, n, c->d_flags, st);
         return e;
@@ -597,7 +600,7 @@ int lt_trace_adjoint(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     if (!d_params || !d_dOdE || !d_grad) return fail(c, LT_EINVAL, "NULL device buffer");
     if (d_bin_hist) return fail(c, LT_EINVAL, "direction histograms need an emission proposal");
     HIPCHK(c, hipSetDevice(c->device));
-    const long long blocks = (long long)c->n_cu * c->tune.blocks_per_cu;
+    const long long blocks = trace_blocks(c);
     rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
     if (rc) return rc;
     TraceArgs a = trace_args(c, cfg);
@@ -606,7 +609,6 @@ int lt_trace_adjoint(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
     auto body = [&](hipStream_t st) -> hipError_t {
         hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
-        if (e == hipSuccess) e = launch_reset_counter(c->d_counter, st);
         if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
         if (e == hipSuccess) e = launch_grad_reduce(c->d_partials, c->d_range, c->L, d_grad, st);
         return e;
@@ -666,14 +668,14 @@ int lt_trace_stats(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, in
     if (!d_params || !d_S || !h_counts) return fail(c, LT_EINVAL, "NULL buffer");
     if ((uintptr_t)d_S & 15) return fail(c, LT_EINVAL, "d_S must be 16-byte aligned");
     HIPCHK(c, hipSetDevice(c->device));
-    const long long blocks = (long long)c->n_cu * c->tune.blocks_per_cu;
+    const long long blocks = trace_blocks(c);
     rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
     if (rc) return rc;
     TraceArgs a = trace_args(c, cfg);
     a.S = (long long*)d_S;
     HIPCHK(c, hipMemsetAsync(c->d_stats, 0, sizeof(unsigned long long) * 8, c->stream));
     HIPCHK(c, launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->stream));
-    HIPCHK(c, launch_clear(a.S, c->K * c->n_layouts, c->d_counter, c->stream));
+    HIPCHK(c, launch_clear(a.S, c->K * c->n_layouts, c->stream));
     HIPCHK(c, launch_trace(false, true, a, c->tune.waves_per_block, c->tune.lds_depth, (int)blocks, c->stream));
     unsigned long long h[8];
     HIPCHK(c, hipMemcpyAsync(h, c->d_stats, sizeof(h), hipMemcpyDeviceToHost, c->stream));
@@ -694,7 +696,7 @@ int lt_set_tuning(lt_ctx* c, const lt_tuning* t)
     if (!c || !t) return LT_EINVAL;
     if (t->waves_per_block != 1 && t->waves_per_block != 2 && t->waves_per_block != 4)
         return fail(c, LT_EINVAL, "waves_per_block must be 1, 2 or 4");
-    if (t->blocks_per_cu < 1 || t->blocks_per_cu > 64) return fail(c, LT_EINVAL, "blocks_per_cu out of range");
+    if (t->xcd_remap != 0 && t->xcd_remap != 1) return fail(c, LT_EINVAL, "xcd_remap must be 0 or 1");
     if (t->tile_paths < 0 || t->tile_paths % 64 != 0 || t->tile_paths > (1 << 24))
         return fail(c, LT_EINVAL, "tile_paths must be 0 or a positive multiple of 64");
     if (t->refill_threshold < 1 || t->refill_threshold > 64)

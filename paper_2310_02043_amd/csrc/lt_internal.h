@@ -18,7 +18,7 @@ struct TraceArgs {
     const int4* tiles;          // (global light, first path, count, layout)
     int n_tiles;
     int max_hits;
-    unsigned* tile_counter;
+    int xcd_remap;              // map blocks of one XCD to a contiguous tile range
     uint32_t key0, key1;
     long long* S;               // forward: [n_layouts, K]
     const float* g;             // adjoint: [n_layouts, K]
@@ -61,8 +61,7 @@ hipError_t launch_trace(bool adjoint, bool stats, const TraceArgs& a, int waves_
 hipError_t launch_record(const RecordArgs& a, int lds_depth, hipStream_t st);
 hipError_t launch_light_setup(const float* params, const int4* lstat_i, const float4* lstat_f,
                               const long long* npaths, int n_lights, DevLight* out, hipStream_t st);
-hipError_t launch_clear(long long* S, long long n_texels_total, unsigned* counter, hipStream_t st);
-hipError_t launch_reset_counter(unsigned* counter, hipStream_t st);
+hipError_t launch_clear(long long* S, long long n_texels_total, hipStream_t st);
 hipError_t launch_finalize(const long long* S, float* E, long long n, unsigned* flags, hipStream_t st);
 hipError_t launch_objective(const float* E, const float* Et, const float* alpha, const float* A, long long K,
                             long long n, float* g, double* partials, double* O, hipStream_t st);

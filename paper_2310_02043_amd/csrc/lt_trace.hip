@@ -1,10 +1,10 @@
 // Primal and adjoint light-tracing kernels for gfx950.
 //
-// Alg. 1 (primal) and Alg. 2 (adjoint) of the paper, one persistent launch
-// over a queue of work tiles.  A tile is a contiguous path range of one
-// luminaire of one layout; a wave takes a tile, keeps 64 paths in flight and
-// refills lanes whose path ended (ballot + mbcnt prefix count) until the tile
-// is exhausted.  Hit processing (splat or adjoint gather, bounce, refill) runs
+// Alg. 1 (primal) and Alg. 2 (adjoint) of the paper, one launch over a grid
+// of work tiles covering every layout.  A tile is a contiguous path range of
+// one luminaire of one layout; its wave keeps 64 paths in flight and refills
+// lanes whose path ended (ballot + mbcnt prefix count) until the tile is
+// exhausted.  Hit processing (splat or adjoint gather, bounce, refill) runs
 // once at least `refill_threshold` lanes have finished their current segment,
 // so the BVH traversal loop stays converged.  Texel sums are int64 Q31.32
 // fixed point (order-independent); adjoint partial sums are FP64 per tile in a
@@ -265,25 +265,36 @@ __device__ __forceinline__ T wave_sum(T v)
 }
 
 // ---------------------------------------------------------------------------
-// The persistent forward / adjoint kernel.
+// The forward / adjoint kernel: one wave per work tile, all tiles of all
+// layouts in one launch.  The hardware dispatcher drains the tile grid; no
+// loop carries lane-divergent code across its back edge, so every wave-wide
+// operation (ballot, shuffle) runs on a converged wave.
 // ---------------------------------------------------------------------------
+
+// Block b of nb runs on XCD b % 8; give each XCD a contiguous range of tiles
+// (a bijection of [0, nb)) so rays of one luminaire share an L2.
+__device__ __forceinline__ long long xcd_block(long long b, long long nb, int remap)
+{
+    if (!remap) return b;
+    const long long x = b & 7, i = b >> 3, q = nb >> 3, r = nb & 7;
+    return x * q + (x < r ? x : r) + i;
+}
+
 template <bool ADJ, bool STATS, int WPB, int LDS_D>
 __global__ void __launch_bounds__(WPB * 64) k_trace(TraceArgs a)
 {
     __shared__ int s_stack[WPB * LDS_D * 64];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
-    const long long gw = (long long)blockIdx.x * WPB + wib;
+    const long long blk = xcd_block(blockIdx.x, gridDim.x, a.xcd_remap);
+    const long long gw = blk * WPB + wib;
+    if (gw >= a.n_tiles) return;
     int* lst = s_stack + wib * LDS_D * 64 + lane;
     int* gst = a.gstack + gw * (long long)a.gdepth * 64 + lane;
     const int B = a.max_hits;
     const int thresh = a.refill_threshold;
-
-    for (;;) {
-        int tile = 0;
-        if (lane == 0) tile = (int)atomicAdd(a.tile_counter, 1u);
-        tile = __builtin_amdgcn_readfirstlane(__shfl(tile, 0));
-        if (tile >= a.n_tiles) break;
+    const int tile = (int)gw;
+    {
         const int4 ti = a.tiles[tile];
         const DevLight& L = a.lights[ti.x];
         const uint32_t first = (uint32_t)ti.y;
@@ -413,7 +424,7 @@ __global__ void __launch_bounds__(WPB * 64) k_trace(TraceArgs a)
 }
 
 // One path per thread (grid-stride): hit sequences and per-path adjoint
-// contributions, with the same device functions as the persistent kernel.
+// contributions, with the same device functions as the tracing kernel.
 template <int LDS_D>
 __global__ void __launch_bounds__(256) k_record(RecordArgs a)
 {
@@ -516,18 +527,15 @@ __global__ void k_light_setup(const float* __restrict__ params, const int4* __re
     out[l] = L;
 }
 
-__global__ void k_clear(long long* __restrict__ S, long long n, unsigned* counter)
+__global__ void k_clear(long long* __restrict__ S, long long n)
 {
     const long long stride = (long long)gridDim.x * blockDim.x;
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0 && counter) *counter = 0u;
     longlong2* S2 = (longlong2*)S;
     const long long n2 = n >> 1;
     for (long long j = i; j < n2; j += stride) S2[j] = make_longlong2(0, 0);
     if ((n & 1) && i == 0) S[n - 1] = 0;
 }
-
-__global__ void k_reset_counter(unsigned* counter) { *counter = 0u; }
 
 // E_k = S_k 2^-32 through FP64; sticky overflow flag at |S| >= 2^62.
 __global__ void k_finalize(const long long* __restrict__ S, float* __restrict__ E, long long n,
@@ -680,15 +688,9 @@ hipError_t launch_light_setup(const float* params, const int4* si, const float4*
     return hipGetLastError();
 }
 
-hipError_t launch_clear(long long* S, long long n, unsigned* counter, hipStream_t st)
+hipError_t launch_clear(long long* S, long long n, hipStream_t st)
 {
-    k_clear<<<nblocks(n / 2 + 1, 256, 4096), 256, 0, st>>>(S, n, counter);
-    return hipGetLastError();
-}
-
-hipError_t launch_reset_counter(unsigned* counter, hipStream_t st)
-{
-    k_reset_counter<<<1, 1, 0, st>>>(counter);
+    k_clear<<<nblocks(n / 2 + 1, 256, 4096), 256, 0, st>>>(S, n);
     return hipGetLastError();
 }
 

@@ -41,11 +41,11 @@ class TraceCfg(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("waves_per_block", C.c_int32), ("blocks_per_cu", C.c_int32), ("tile_paths", C.c_int32),
+    _fields_ = [("waves_per_block", C.c_int32), ("xcd_remap", C.c_int32), ("tile_paths", C.c_int32),
                 ("refill_threshold", C.c_int32), ("lds_depth", C.c_int32), ("reserved", C.c_int32 * 3)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k in ("waves_per_block", "blocks_per_cu", "tile_paths",
+        return {k: getattr(self, k) for k in ("waves_per_block", "xcd_remap", "tile_paths",
                                                "refill_threshold", "lds_depth")}
 
 
