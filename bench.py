@@ -35,6 +35,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_trace_office_2e26.traffic.json")
+
+
+def measured_traffic(kind):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    passes (scaled by the copy-kernel calibration), or None if the kernel
+    sources changed since the counters were taken."""
+    import hashlib
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for s in d["sources"]:
+        h.update(open(os.path.join(ROOT, s), "rb").read())
+    if h.hexdigest() != d["kernel_sources_sha256"]:
+        return None
+    k = d[kind]
+    return int((k["fetch_kib"] * d["fetch_scale"] + k["write_kib"] * d["write_scale"]) * 1024)
+
+
 def cpu_baseline(scene, lights, seed, ppl, B, target_seconds):
     """The oracle as it stands, on the host cores, on a bounded sample: the
     first m paths of every luminaire (same Phi_r), forward + objective +
@@ -80,7 +101,19 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", type=str, default="", help="k=v,... launch tuning override")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only copy this many bytes device-to-device 3 times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {n * 4} bytes 3 times")
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding of this "
               f"path is described in the design notes and not launched here.", file=sys.stderr)
@@ -152,6 +185,10 @@ def main():
                 "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": None}
     roof_mem = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
+    traffic = measured_traffic(dominant)
+    roof_mem["traffic"] = traffic
+    roof_mem["note"] = ("achieved counts the node, triangle and patch bytes the traversal fetches (L2 / "
+                        "Infinity Cache level); traffic is the HBM bytes rocprofv3 measured per launch")
     roofline = dict(roof_alu if roof_alu["frac"] >= roof_mem["frac"] else roof_mem)
     roofline.update({"kernel": f"k_trace ({dominant})", "kernel_ms": round(max(fwd_avg, adj_avg), 3),
                      "other": roof_mem if roofline["bound"] == "alu" else roof_alu,

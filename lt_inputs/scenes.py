@@ -454,7 +454,8 @@ def office(seed: int = 2, target_tris: int = 200_000, target_texels: int = 4_000
     clusters with partitions, wall cabinets and clutter boxes up to
     target_tris; texel density sqrt(total area / target_texels); 16
     rectangular 0.6 x 0.6 m cos^n luminaires (n ~ U[1,8], P ~ U[30,60] W)
-    on a jittered 4 x 4 grid just below the ceiling, facing down."""
+    on a jittered 4 x 4 grid 0.15 m below the ceiling (pendant fittings: a
+    tilted 0.6 m emitter stays below the ceiling plane), facing down."""
     rng = np.random.default_rng(seed)
     W, D, H = 30.0, 20.0, 3.0
     sb = SceneBuilder()
@@ -471,11 +472,11 @@ def office(seed: int = 2, target_tris: int = 200_000, target_texels: int = 4_000
         i, j = k % gx, k // gx
         x = (i + 0.5) * W / gx + rng.uniform(-1.0, 1.0)
         y = (j + 0.5) * D / gy + rng.uniform(-0.7, 0.7)
-        params.append([x, y, H - 0.01, 0.0, 0.0, rng.uniform(30, 60)])
+        params.append([x, y, H - 0.15, 0.0, 0.0, rng.uniform(30, 60)])
         lobe.append(rng.uniform(1.0, 8.0))
     params = np.asarray(params, np.float32)
     lights = make_lights([RECT] * n_lights, lobe, [(0.6, 0.6)] * n_lights, [0] * n_lights, params)
-    init = perturb_params(params, seed + 7, lo=[0.5, 0.5, H - 0.01], hi=[W - 0.5, D - 0.5, H - 0.01])
+    init = perturb_params(params, seed + 7, lo=[0.5, 0.5, H - 0.15], hi=[W - 0.5, D - 0.5, H - 0.15])
     lights.params[:] = init
     return dict(scene=scene, lights=lights, params_target=params, paths=paths,
                 max_hits=max_hits, seed=0x5EED0 + seed, seed_target=0x7A46E7 + seed)
@@ -560,12 +561,12 @@ def building_floor(seed: int = 5, target_tris: int = 2_000_000, target_texels: i
     for k in range(n_lights):
         i, j = k % gx, k // gx
         params.append([(i + 0.5) * W / gx + rng.uniform(-1, 1), (j + 0.5) * D / gy + rng.uniform(-1, 1),
-                       H - 0.01, 0.0, 0.0, rng.uniform(30, 60)])
+                       H - 0.15, 0.0, 0.0, rng.uniform(30, 60)])
         lobe.append(rng.uniform(1.0, 8.0))
     params = np.asarray(params, np.float32)
     lights = make_lights([RECT] * n_lights, lobe, [(0.6, 0.6)] * n_lights, [0] * n_lights, params)
-    lights.params[:] = perturb_params(params, seed + 7, lo=[0.5, 0.5, H - 0.01],
-                                      hi=[W - 0.5, D - 0.5, H - 0.01])
+    lights.params[:] = perturb_params(params, seed + 7, lo=[0.5, 0.5, H - 0.15],
+                                      hi=[W - 0.5, D - 0.5, H - 0.15])
     return dict(scene=scene, lights=lights, params_target=params, paths=paths,
                 max_hits=max_hits, seed=0xF100 + seed, seed_target=0xF200 + seed)
 
