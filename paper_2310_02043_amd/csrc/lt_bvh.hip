@@ -1,12 +1,16 @@
-// Linear BVH build on the device.
+// BVH build on the device.
 //
 // The paper traces rays with the ray-tracing units of its GPU (Sec. 6); the
 // MI355X has none, so the scene's acceleration structure is built here:
 // 63-bit Morton codes of triangle centroids, a bitonic sort of (code, index),
-// the binary radix tree of Karras (HPG 2012) with index tie-breaking, and
-// bottom-up bounds.  Output nodes hold both child boxes inline (64 B, one
-// fetch = two box tests); leaves are single triangles stored in Morton order
-// as (v0, id), (v1 - v0, patch), (v2 - v0, 0).
+// then parallel locally-ordered clustering (PLOC, Meister and Bittner 2018):
+// every cluster finds its nearest neighbour (smallest merged surface area)
+// within a window of the Morton order, mutual nearest neighbours merge, the
+// cluster list is compacted by a prefix sum, until one cluster is left.
+// Internal nodes are numbered from the root (0) in reverse creation order.
+// Output nodes hold both child boxes inline (64 B, one fetch = two box
+// tests); leaves are single triangles stored in Morton order as (v0, id),
+// (v1 - v0, patch), (v2 - v0, 0).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <float.h>
@@ -122,57 +126,6 @@ __global__ void k_bitonic(uint64_t* __restrict__ keys, int* __restrict__ vals, i
     }
 }
 
-// common prefix length of sorted keys i and j (index tie-break), -1 outside
-__device__ __forceinline__ int delta(const uint64_t* keys, int n, int i, int j)
-{
-    if (j < 0 || j >= n) return -1;
-    const uint64_t a = keys[i], b = keys[j];
-    if (a != b) return __clzll((long long)(a ^ b));
-    return 64 + __clz((int)((uint32_t)i ^ (uint32_t)j));
-}
-
-// Karras 2012: internal node i covers a key range; children are internal
-// nodes or leaves (encoded as ~leaf).
-__global__ void k_hierarchy(const uint64_t* __restrict__ keys, int n, int2* __restrict__ child,
-                            int* __restrict__ parent_int, int* __restrict__ parent_leaf)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n - 1) return;
-    const int d = (delta(keys, n, i, i + 1) - delta(keys, n, i, i - 1)) >= 0 ? 1 : -1;
-    const int dmin = delta(keys, n, i, i - d);
-    int lmax = 2;
-    while (delta(keys, n, i, i + lmax * d) > dmin) lmax <<= 1;
-    int l = 0;
-    for (int t = lmax >> 1; t >= 1; t >>= 1)
-        if (delta(keys, n, i, i + (l + t) * d) > dmin) l += t;
-    const int j = i + l * d;
-    const int dnode = delta(keys, n, i, j);
-    int s = 0;
-    int t = l;
-    do {
-        t = (t + 1) >> 1;
-        if (delta(keys, n, i, i + (s + t) * d) > dnode) s += t;
-    } while (t > 1);
-    const int gamma = i + s * d + (d < 0 ? d : 0);
-    const int lo = i < j ? i : j, hi = i < j ? j : i;
-    int left, right;
-    if (lo == gamma) {
-        left = ~gamma;
-        parent_leaf[gamma] = i;
-    } else {
-        left = gamma;
-        parent_int[gamma] = i;
-    }
-    if (hi == gamma + 1) {
-        right = ~(gamma + 1);
-        parent_leaf[gamma + 1] = i;
-    } else {
-        right = gamma + 1;
-        parent_int[gamma + 1] = i;
-    }
-    child[i] = make_int2(left, right);
-}
-
 __device__ __forceinline__ void child_box(int c, const float4* tlo, const float4* thi, const int* vals,
                                           const float4* nlo, const float4* nhi, float4& lo, float4& hi)
 {
@@ -186,27 +139,159 @@ __device__ __forceinline__ void child_box(int c, const float4* tlo, const float4
     }
 }
 
-// bottom-up bounds: the second thread to reach a node computes its box
-__global__ void k_bounds_up(int n, const int2* __restrict__ child, const int* __restrict__ parent_int,
-                            const int* __restrict__ parent_leaf, const int* __restrict__ vals,
-                            const float4* __restrict__ tlo, const float4* __restrict__ thi, float4* nlo, float4* nhi,
-                            int* flags)
+// ---- PLOC -------------------------------------------------------------------
+__device__ __forceinline__ float half_area(float4 lo, float4 hi)
 {
-    const int leaf = blockIdx.x * blockDim.x + threadIdx.x;
-    if (leaf >= n) return;
-    int node = parent_leaf[leaf];
-    while (node >= 0) {
-        const int prev = __hip_atomic_fetch_add(&flags[node], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == 0) return;
-        const int2 c = child[node];
-        float4 al, ah, bl, bh;
-        child_box(c.x, tlo, thi, vals, nlo, nhi, al, ah);
-        child_box(c.y, tlo, thi, vals, nlo, nhi, bl, bh);
-        nlo[node] = make_float4(fminf(al.x, bl.x), fminf(al.y, bl.y), fminf(al.z, bl.z), 0.f);
-        nhi[node] = make_float4(fmaxf(ah.x, bh.x), fmaxf(ah.y, bh.y), fmaxf(ah.z, bh.z), 0.f);
-        __atomic_thread_fence(__ATOMIC_RELEASE);
-        node = node == 0 ? -1 : parent_int[node];
+    const float dx = hi.x - lo.x, dy = hi.y - lo.y, dz = hi.z - lo.z;
+    return dx * dy + dy * dz + dz * dx;
+}
+
+__global__ void k_ploc_init(int n, const int* __restrict__ vals, const float4* __restrict__ tlo,
+                            const float4* __restrict__ thi, int* __restrict__ cid, float4* __restrict__ clo,
+                            float4* __restrict__ chi)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int t = vals[s];
+    cid[s] = ~s;
+    clo[s] = tlo[t];
+    chi[s] = thi[t];
+}
+
+// nearest neighbour within [i-R, i+R] by merged half surface area (ties: lower index)
+__global__ void k_ploc_nn(int nc, int R, const float4* __restrict__ clo, const float4* __restrict__ chi,
+                          int* __restrict__ nn)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nc) return;
+    const float4 a = clo[i], b = chi[i];
+    const int j0 = i - R < 0 ? 0 : i - R;
+    const int j1 = i + R > nc - 1 ? nc - 1 : i + R;
+    float best = __builtin_inff();
+    int bj = -1;
+    for (int j = j0; j <= j1; ++j) {
+        if (j == i) continue;
+        const float4 c = clo[j], d = chi[j];
+        const float ha = half_area(make_float4(fminf(a.x, c.x), fminf(a.y, c.y), fminf(a.z, c.z), 0.f),
+                                   make_float4(fmaxf(b.x, d.x), fmaxf(b.y, d.y), fmaxf(b.z, d.z), 0.f));
+        if (ha < best) {
+            best = ha;
+            bj = j;
+        }
     }
+    nn[i] = bj;
+}
+
+// flag = keep << 32 | merge  (mutual pair: the lower index keeps and merges)
+__global__ void k_ploc_flags(int nc, const int* __restrict__ nn, unsigned long long* __restrict__ flags)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nc) return;
+    const int j = nn[i];
+    const bool mutual = j >= 0 && nn[j] == i;
+    const unsigned long long keep = (mutual && i > j) ? 0ull : 1ull;
+    const unsigned long long merge = (mutual && i < j) ? 1ull : 0ull;
+    flags[i] = (keep << 32) | merge;
+}
+
+__global__ void k_ploc_write(int nc, int n_int, int node_base, const int* __restrict__ nn,
+                             const unsigned long long* __restrict__ flags, const unsigned long long* __restrict__ scan,
+                             const int* __restrict__ cid, const float4* __restrict__ clo,
+                             const float4* __restrict__ chi, int* __restrict__ oid, float4* __restrict__ olo,
+                             float4* __restrict__ ohi, int2* __restrict__ child, float4* __restrict__ nlo,
+                             float4* __restrict__ nhi, int* __restrict__ parent_int, int* __restrict__ parent_leaf)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nc) return;
+    const unsigned long long f = flags[i];
+    if (!(f >> 32)) return;
+    const int p = (int)(scan[i] >> 32);
+    if (f & 1ull) {
+        const int j = nn[i];
+        const int node = n_int - 1 - (node_base + (int)(scan[i] & 0xffffffffull));
+        const int ca = cid[i], cb = cid[j];
+        child[node] = make_int2(ca, cb);
+        if (ca >= 0) parent_int[ca] = node;
+        else parent_leaf[~ca] = node;
+        if (cb >= 0) parent_int[cb] = node;
+        else parent_leaf[~cb] = node;
+        const float4 a = clo[i], b = chi[i], c = clo[j], d = chi[j];
+        const float4 ul = make_float4(fminf(a.x, c.x), fminf(a.y, c.y), fminf(a.z, c.z), 0.f);
+        const float4 uh = make_float4(fmaxf(b.x, d.x), fmaxf(b.y, d.y), fmaxf(b.z, d.z), 0.f);
+        nlo[node] = ul;
+        nhi[node] = uh;
+        oid[p] = node;
+        olo[p] = ul;
+        ohi[p] = uh;
+    } else {
+        oid[p] = cid[i];
+        olo[p] = clo[i];
+        ohi[p] = chi[i];
+    }
+}
+
+// ---- exclusive prefix sum of u64 (block-local, block sums, add) --------------
+constexpr int kScanItems = 1024;   // 256 threads x 4
+
+__global__ void __launch_bounds__(256) k_scan_local(const unsigned long long* __restrict__ in,
+                                                   unsigned long long* __restrict__ out,
+                                                   unsigned long long* __restrict__ sums, int n)
+{
+    __shared__ unsigned long long sh[256];
+    const int base = blockIdx.x * kScanItems + threadIdx.x * 4;
+    unsigned long long v[4], t = 0;
+    for (int k = 0; k < 4; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0ull;
+        t += v[k];
+    }
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const unsigned long long x = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0ull;
+        __syncthreads();
+        sh[threadIdx.x] += x;
+        __syncthreads();
+    }
+    unsigned long long run = sh[threadIdx.x] - t;   // exclusive prefix of this thread
+    for (int k = 0; k < 4; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 255) sums[blockIdx.x] = sh[255];
+}
+
+// single block: exclusive scan of the block sums in place; *total = sum
+__global__ void __launch_bounds__(256) k_scan_sums(unsigned long long* __restrict__ sums, int nb,
+                                                  unsigned long long* __restrict__ total)
+{
+    __shared__ unsigned long long sh[256];
+    unsigned long long carry = 0;
+    for (int c0 = 0; c0 < nb; c0 += 256) {
+        const int i = c0 + threadIdx.x;
+        const unsigned long long v = i < nb ? sums[i] : 0ull;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const unsigned long long x = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0ull;
+            __syncthreads();
+            sh[threadIdx.x] += x;
+            __syncthreads();
+        }
+        if (i < nb) sums[i] = carry + sh[threadIdx.x] - v;
+        const unsigned long long chunk = sh[255];
+        __syncthreads();
+        carry += chunk;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void __launch_bounds__(256) k_scan_add(unsigned long long* __restrict__ out,
+                                                 const unsigned long long* __restrict__ sums, int n)
+{
+    const int base = blockIdx.x * kScanItems + threadIdx.x * 4;
+    const unsigned long long s = sums[blockIdx.x];
+    for (int k = 0; k < 4; ++k)
+        if (base + k < n) out[base + k] += s;
 }
 
 __global__ void k_write_nodes(int n_int, const int2* __restrict__ child, const int* __restrict__ vals,
@@ -260,6 +345,34 @@ inline int blocks_for(long long n, int b) { return (int)((n + b - 1) / b); }
 
 }  // namespace
 
+namespace {
+
+// device buffer freed on scope exit unless released
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    hipError_t alloc(size_t n) { return hipMalloc(&p, sizeof(T) * (n > 0 ? n : 1)); }
+    T* release()
+    {
+        T* q = p;
+        p = nullptr;
+        return q;
+    }
+    ~DevBuf() { hipFree(p); }
+};
+
+hipError_t scan_u64(const unsigned long long* in, unsigned long long* out, unsigned long long* sums,
+                    unsigned long long* total, int n, hipStream_t st)
+{
+    const int nb = blocks_for(n, kScanItems);
+    k_scan_local<<<nb, 256, 0, st>>>(in, out, sums, n);
+    k_scan_sums<<<1, 256, 0, st>>>(sums, nb, total);
+    k_scan_add<<<nb, 256, 0, st>>>(out, sums, n);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 // Builds nodes [max(n-1,1) * 4 float4] and leaf triangles [n * 3 float4].
 // Device inputs: d_verts [V*3], d_tris [n*3], d_tri_patch [n].
 hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_patch, int n, float pad,
@@ -272,69 +385,83 @@ hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_p
     while (n_pow2 < n) n_pow2 <<= 1;
     const int n_int = n - 1 > 0 ? n - 1 : 1;
     const int n_part = 256;
-    float4 *tlo = nullptr, *thi = nullptr, *cen = nullptr, *part = nullptr, *nlo = nullptr, *nhi = nullptr;
-    uint64_t* keys = nullptr;
-    int *vals = nullptr, *pint = nullptr, *pleaf = nullptr, *flags = nullptr, *dmax = nullptr;
-    int2* child = nullptr;
-    float4 *nodes = nullptr, *otris = nullptr;
-    const int2 single_leaf = make_int2(~0, ~0);
-    hipError_t e = hipSuccess;
-#define LT_TRY(x)                          \
-    do {                                   \
-        e = (x);                           \
-        if (e != hipSuccess) goto cleanup; \
+    const int radius = kPlocRadius;
+    DevBuf<float4> tlo, thi, cen, part, nlo, nhi, clo[2], chi[2], nodes, otris;
+    DevBuf<uint64_t> keys;
+    DevBuf<unsigned long long> flags, scan, sums, total;
+    DevBuf<int> vals, pint, pleaf, dmax, nn, cid[2];
+    DevBuf<int2> child;
+    hipError_t e;
+#define LT_TRY(x)                      \
+    do {                               \
+        e = (x);                       \
+        if (e != hipSuccess) return e; \
     } while (0)
-    LT_TRY(hipMalloc(&tlo, sizeof(float4) * n));
-    LT_TRY(hipMalloc(&thi, sizeof(float4) * n));
-    LT_TRY(hipMalloc(&cen, sizeof(float4) * n));
-    LT_TRY(hipMalloc(&part, sizeof(float4) * 2 * n_part));
-    LT_TRY(hipMalloc(&keys, sizeof(uint64_t) * n_pow2));
-    LT_TRY(hipMalloc(&vals, sizeof(int) * n_pow2));
-    LT_TRY(hipMalloc(&child, sizeof(int2) * n_int));
-    LT_TRY(hipMalloc(&pint, sizeof(int) * n_int));
-    LT_TRY(hipMalloc(&pleaf, sizeof(int) * n));
-    LT_TRY(hipMalloc(&flags, sizeof(int) * n_int));
-    LT_TRY(hipMalloc(&nlo, sizeof(float4) * n_int));
-    LT_TRY(hipMalloc(&nhi, sizeof(float4) * n_int));
-    LT_TRY(hipMalloc(&dmax, sizeof(int)));
-    LT_TRY(hipMalloc(&nodes, sizeof(float4) * 4 * n_int));
-    LT_TRY(hipMalloc(&otris, sizeof(float4) * 3 * n));
+    LT_TRY(tlo.alloc(n)); LT_TRY(thi.alloc(n)); LT_TRY(cen.alloc(n)); LT_TRY(part.alloc(2 * n_part));
+    LT_TRY(keys.alloc(n_pow2)); LT_TRY(vals.alloc(n_pow2));
+    LT_TRY(child.alloc(n_int)); LT_TRY(pint.alloc(n_int)); LT_TRY(pleaf.alloc(n));
+    LT_TRY(nlo.alloc(n_int)); LT_TRY(nhi.alloc(n_int)); LT_TRY(dmax.alloc(1));
+    LT_TRY(nodes.alloc(4 * (size_t)n_int)); LT_TRY(otris.alloc(3 * (size_t)n));
 
-    k_tri_setup<<<blocks_for(n, 256), 256, 0, st>>>(d_verts, d_tris, n, pad, tlo, thi, cen);
-    k_bounds_partial<<<n_part, 256, 0, st>>>(cen, n, part);
-    k_morton<<<blocks_for(n_pow2, 256), 256, 0, st>>>(cen, n, n_pow2, part, n_part, keys, vals);
+    k_tri_setup<<<blocks_for(n, 256), 256, 0, st>>>(d_verts, d_tris, n, pad, tlo.p, thi.p, cen.p);
+    k_bounds_partial<<<n_part, 256, 0, st>>>(cen.p, n, part.p);
+    k_morton<<<blocks_for(n_pow2, 256), 256, 0, st>>>(cen.p, n, n_pow2, part.p, n_part, keys.p, vals.p);
     for (int k = 2; k <= n_pow2; k <<= 1)
         for (int j = k >> 1; j > 0; j >>= 1)
-            k_bitonic<<<blocks_for(n_pow2, 256), 256, 0, st>>>(keys, vals, n_pow2, j, k);
+            k_bitonic<<<blocks_for(n_pow2, 256), 256, 0, st>>>(keys.p, vals.p, n_pow2, j, k);
     LT_TRY(hipGetLastError());
     if (n == 1) {
         // a single triangle: one node whose two children are that leaf
-        LT_TRY(hipMemcpyAsync(child, &single_leaf, sizeof(int2), hipMemcpyHostToDevice, st));
-        LT_TRY(hipMemsetAsync(pleaf, 0, sizeof(int), st));
+        const int2 single_leaf = make_int2(~0, ~0);
+        LT_TRY(hipMemcpyAsync(child.p, &single_leaf, sizeof(int2), hipMemcpyHostToDevice, st));
+        LT_TRY(hipStreamSynchronize(st));
     } else {
-        k_hierarchy<<<blocks_for(n - 1, 256), 256, 0, st>>>(keys, n, child, pint, pleaf);
-        LT_TRY(hipMemsetAsync(flags, 0, sizeof(int) * n_int, st));
-        k_bounds_up<<<blocks_for(n, 256), 256, 0, st>>>(n, child, pint, pleaf, vals, tlo, thi, nlo, nhi, flags);
+        for (int b = 0; b < 2; ++b) {
+            LT_TRY(clo[b].alloc(n)); LT_TRY(chi[b].alloc(n)); LT_TRY(cid[b].alloc(n));
+        }
+        LT_TRY(nn.alloc(n)); LT_TRY(flags.alloc(n)); LT_TRY(scan.alloc(n));
+        LT_TRY(sums.alloc(blocks_for(n, kScanItems))); LT_TRY(total.alloc(1));
+        k_ploc_init<<<blocks_for(n, 256), 256, 0, st>>>(n, vals.p, tlo.p, thi.p, cid[0].p, clo[0].p, chi[0].p);
+        int nc = n, node_base = 0, cur = 0, iter = 0;
+        while (nc > 1) {
+            if (++iter > 4 * n + 64) return hipErrorUnknown;   // every round merges at least one pair
+            const int nx = cur ^ 1;
+            k_ploc_nn<<<blocks_for(nc, 256), 256, 0, st>>>(nc, radius, clo[cur].p, chi[cur].p, nn.p);
+            k_ploc_flags<<<blocks_for(nc, 256), 256, 0, st>>>(nc, nn.p, flags.p);
+            LT_TRY(scan_u64(flags.p, scan.p, sums.p, total.p, nc, st));
+            k_ploc_write<<<blocks_for(nc, 256), 256, 0, st>>>(nc, n_int, node_base, nn.p, flags.p, scan.p,
+                                                              cid[cur].p, clo[cur].p, chi[cur].p, cid[nx].p,
+                                                              clo[nx].p, chi[nx].p, child.p, nlo.p, nhi.p,
+                                                              pint.p, pleaf.p);
+            unsigned long long tot = 0;
+            LT_TRY(hipMemcpyAsync(&tot, total.p, sizeof(tot), hipMemcpyDeviceToHost, st));
+            LT_TRY(hipStreamSynchronize(st));
+            const int kept = (int)(tot >> 32), merged = (int)(tot & 0xffffffffull);
+            if (merged < 1 || kept != nc - merged) return hipErrorUnknown;
+            node_base += merged;
+            nc = kept;
+            cur = nx;
+        }
+        if (node_base != n - 1) return hipErrorUnknown;
     }
-    k_write_nodes<<<blocks_for(n_int, 256), 256, 0, st>>>(n_int, child, vals, tlo, thi, nlo, nhi, nodes);
-    k_write_tris<<<blocks_for(n, 256), 256, 0, st>>>(n, vals, d_verts, d_tris, d_tri_patch, otris);
-    LT_TRY(hipMemsetAsync(dmax, 0, sizeof(int), st));
-    if (n > 1) k_depth<<<blocks_for(n, 256), 256, 0, st>>>(n, pint, pleaf, dmax);
+    k_write_nodes<<<blocks_for(n_int, 256), 256, 0, st>>>(n_int, child.p, vals.p, tlo.p, thi.p, nlo.p, nhi.p,
+                                                          nodes.p);
+    k_write_tris<<<blocks_for(n, 256), 256, 0, st>>>(n, vals.p, d_verts, d_tris, d_tri_patch, otris.p);
+    int depth = 1;
+    if (n > 1) {
+        LT_TRY(hipMemsetAsync(dmax.p, 0, sizeof(int), st));
+        k_depth<<<blocks_for(n, 256), 256, 0, st>>>(n, pint.p, pleaf.p, dmax.p);
+        LT_TRY(hipGetLastError());
+        LT_TRY(hipMemcpyAsync(&depth, dmax.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    }
     LT_TRY(hipGetLastError());
-    LT_TRY(hipMemcpyAsync(depth_out, dmax, sizeof(int), hipMemcpyDeviceToHost, st));
     LT_TRY(hipStreamSynchronize(st));
-    if (n == 1) *depth_out = 1;
-    *nodes_out = nodes;
-    *tris_out = otris;
-    *n_nodes_out = n_int;
-    nodes = nullptr;
-    otris = nullptr;
-cleanup:
-    hipFree(tlo); hipFree(thi); hipFree(cen); hipFree(part); hipFree(keys); hipFree(vals);
-    hipFree(child); hipFree(pint); hipFree(pleaf); hipFree(flags); hipFree(nlo); hipFree(nhi);
-    hipFree(dmax); hipFree(nodes); hipFree(otris);
 #undef LT_TRY
-    return e;
+    *depth_out = depth;
+    *nodes_out = nodes.release();
+    *tris_out = otris.release();
+    *n_nodes_out = n_int;
+    return hipSuccess;
 }
 
 }  // namespace lt

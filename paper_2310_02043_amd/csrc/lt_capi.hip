@@ -129,10 +129,10 @@ lt_tuning default_tuning()
     lt_tuning t;
     memset(&t, 0, sizeof(t));
     t.waves_per_block = 4;
-    t.xcd_remap = 1;
+    t.xcd_remap = 0;
     t.tile_paths = 0;
-    t.refill_threshold = 16;
-    t.lds_depth = 32;
+    t.refill_threshold = 24;
+    t.lds_depth = 16;
     return t;
 }
 
@@ -759,12 +759,143 @@ int lt_timing_read(lt_ctx* c, double* fwd_ms, int32_t* n_fwd, double* adj_ms, in
     return LT_OK;
 }
 
-int lt_autotune(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int64_t* d_S, float* d_E,
+namespace {
+
+std::string tune_key(const lt_ctx* c, const lt_trace_cfg* cfg)
+{
+    char buf[256];
+    hipDeviceProp_t prop;
+    const char* arch = "unknown";
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
+    snprintf(buf, sizeof(buf), "arch=%s tris=%lld texels=%lld lights=%d layouts=%d ppl=%lld hits=%d", arch,
+             (long long)c->n_tris, (long long)c->K, c->L, c->n_layouts, (long long)cfg->paths_per_layout,
+             cfg->max_hits);
+    for (char* q = buf; *q; ++q)
+        if (*q == '|' || *q == '\n') *q = '_';
+    return buf;
+}
+
+bool tune_lookup(const char* path, const std::string& key, lt_tuning* t, float* ms)
+{
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (fgets(line, sizeof(line), f)) {
+        char* bar = strchr(line, '|');
+        if (!bar) continue;
+        *bar = 0;
+        if (key != line) continue;
+        lt_tuning x;
+        memset(&x, 0, sizeof(x));
+        float m = 0.f;
+        if (sscanf(bar + 1, "%d %d %d %d %d %f", &x.waves_per_block, &x.xcd_remap, &x.tile_paths,
+                   &x.refill_threshold, &x.lds_depth, &m) == 6) {
+            *t = x;
+            *ms = m;
+            found = true;   // the last matching line wins
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+}  // namespace
+
+// Coordinate descent over the launch shape, timing forward + adjoint with
+// HIP events on the context stream (one warm-up, best of two).
+int lt_autotune(lt_ctx* c, const lt_trace_cfg* cfg_in, const float* d_params, int64_t* d_S, float* d_E,
                 const float* d_dOdE, float* d_grad, const char* cache_path, float* h_best_ms)
 {
-    (void)c; (void)cfg; (void)d_params; (void)d_S; (void)d_E; (void)d_dOdE; (void)d_grad; (void)cache_path;
-    (void)h_best_ms;
-    return c ? fail(c, LT_EINVAL, "autotune not available yet") : LT_EINVAL;
+    int rc = check_cfg(c, cfg_in);
+    if (rc) return rc;
+    if (!d_params || !d_S || !d_E || !d_dOdE || !d_grad) return fail(c, LT_EINVAL, "NULL device buffer");
+    lt_trace_cfg cfg = *cfg_in;
+    cfg.flags &= ~LT_FLAG_GRAPH;
+    const std::string key = tune_key(c, &cfg);
+    lt_tuning best_t;
+    float best_ms = 0.f;
+    if (cache_path && tune_lookup(cache_path, key, &best_t, &best_ms)) {
+        rc = lt_set_tuning(c, &best_t);
+        if (rc) return rc;
+        if (h_best_ms) *h_best_ms = best_ms;
+        return LT_OK;
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    const bool timing_was = c->timing;
+    c->timing = false;
+    auto measure = [&](const lt_tuning& t, float* out) -> int {
+        int r = lt_set_tuning(c, &t);
+        if (r) return r;
+        float bestm = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIPCHK(c, hipEventRecord(e0, c->stream));
+            r = lt_trace_forward(c, &cfg, d_params, d_S, d_E);
+            if (!r) r = lt_trace_adjoint(c, &cfg, d_params, d_dOdE, d_grad, nullptr);
+            if (r) return r;
+            HIPCHK(c, hipEventRecord(e1, c->stream));
+            HIPCHK(c, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) bestm = std::min(bestm, ms);
+        }
+        *out = bestm;
+        return LT_OK;
+    };
+    const int auto_tp = effective_tile_paths(c, cfg.paths_per_layout);
+    lt_tuning cur = c->tune;
+    float cur_ms = 0.f;
+    rc = measure(cur, &cur_ms);
+    const int opts_wpb[] = {1, 2, 4};
+    const int opts_lds[] = {16, 32};
+    const int opts_thr[] = {4, 8, 16, 24, 32, 48};
+    const int opts_xcd[] = {0, 1};
+    for (int pass = 0; pass < 2 && !rc; ++pass) {
+        for (int dim = 0; dim < 5 && !rc; ++dim) {
+            std::vector<lt_tuning> cands;
+            lt_tuning t = cur;
+            if (dim == 0) for (int v : opts_wpb) { t.waves_per_block = v; cands.push_back(t); }
+            if (dim == 1) for (int v : opts_lds) { t.lds_depth = v; cands.push_back(t); }
+            if (dim == 2) for (int v : opts_thr) { t.refill_threshold = v; cands.push_back(t); }
+            if (dim == 3) for (int v : opts_xcd) { t.xcd_remap = v; cands.push_back(t); }
+            if (dim == 4)
+                for (int f : {-2, -1, 0, 1, 2}) {
+                    long long tp = f >= 0 ? (long long)auto_tp << f : (long long)auto_tp >> (-f);
+                    tp = std::max<long long>(64, std::min<long long>(1 << 16, (tp / 64) * 64));
+                    t.tile_paths = (int)tp;
+                    cands.push_back(t);
+                }
+            for (const lt_tuning& cand : cands) {
+                if (!memcmp(&cand, &cur, sizeof(cand))) continue;
+                float ms = 0.f;
+                rc = measure(cand, &ms);
+                if (rc) break;
+                if (ms < cur_ms) {
+                    cur = cand;
+                    cur_ms = ms;
+                }
+            }
+        }
+    }
+    c->timing = timing_was;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    rc = lt_set_tuning(c, &cur);
+    if (rc) return rc;
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "%s|%d %d %d %d %d %.3f\n", key.c_str(), cur.waves_per_block, cur.xcd_remap, cur.tile_paths,
+                    cur.refill_threshold, cur.lds_depth, cur_ms);
+            fclose(f);
+        }
+    }
+    if (h_best_ms) *h_best_ms = cur_ms;
+    return LT_OK;
 }
 
 }  // extern "C"

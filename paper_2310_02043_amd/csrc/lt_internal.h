@@ -9,6 +9,7 @@ namespace lt {
 constexpr int kMaxStackDepth = 128;   // BVH depth bound accepted at upload
 constexpr int kObjBlocks = 1024;      // fixed grid of the objective reduction
 constexpr int kRecordBlocks = 1024;   // grid of the path-recording kernel (4 waves each)
+constexpr int kPlocRadius = 16;       // nearest-neighbour window of the BVH build
 
 struct TraceArgs {
     const float4* nodes;
