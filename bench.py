@@ -24,11 +24,12 @@ sys.path.insert(0, ROOT)
 METRIC = "light paths/s (forward+adjoint); gradient-error×time vs plain tracer"
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
-# Algorithmic work per unit (see the design notes): one node visit = two box
-# tests of 20 ops and a 64 B node; one triangle test = 40 ops and a 48 B record;
-# one hit = an 80 B patch record plus an 8 B atomic (forward) / 4 B gather (adjoint).
-OPS_PER_BOX, OPS_PER_TRI = 20, 40
-NODE_BYTES, TRI_BYTES, PATCH_BYTES = 64, 48, 80
+# Algorithmic work per unit (see the design notes): one node visit = four box
+# tests of 20 ops and a 128 B node (4-wide tree); one triangle test = 40 ops and
+# a 48 B record; one hit = an 80 B patch record plus an 8 B atomic (forward) or
+# a 4 B gather (adjoint).
+BOXES_PER_NODE, OPS_PER_BOX, OPS_PER_TRI = 4, 20, 40
+NODE_BYTES, TRI_BYTES, PATCH_BYTES = 128, 48, 80
 
 
 def log(*a):
@@ -176,7 +177,7 @@ def main():
 
     dominant = "adjoint" if adj_avg >= fwd_avg else "forward"
     dur_s = max(fwd_avg, adj_avg) / 1000.0
-    ops = 2 * OPS_PER_BOX * stats["nodes"] + OPS_PER_TRI * stats["tri_tests"]
+    ops = BOXES_PER_NODE * OPS_PER_BOX * stats["nodes"] + OPS_PER_TRI * stats["tri_tests"]
     byt = NODE_BYTES * stats["nodes"] + TRI_BYTES * stats["tri_tests"] + \
         (PATCH_BYTES + (4 if dominant == "adjoint" else 8)) * stats["hits"]
     tflops = ops / dur_s / 1e12

@@ -104,7 +104,7 @@ typedef struct {
 
 typedef struct {
     int64_t n_tris, n_patches, n_texels;
-    int32_t bvh_nodes, bvh_depth;
+    int32_t bvh_nodes, bvh_depth;   /* 4-wide nodes, levels */
     int64_t device_bytes;
     int32_t n_lights, n_layouts;
 } lt_info;
@@ -124,9 +124,10 @@ int lt_sync(lt_ctx* ctx, uint32_t* flags_out);
  * takes from ray-tracing hardware, Sec. 6).  Host arrays: h_verts [n_verts,3]
  * f32, h_tris [n_tris,3] i32 vertex indices, h_tri_patch [n_tris] i32,
  * h_patches [n_patches].  Texel ranges of the patches must tile
- * [0, n_texels).  Builds a linear BVH on the device (Morton order,
- * Karras 2012 hierarchy) and per-texel area tables; replaces any previous
- * scene.  *n_texels_out receives K. */
+ * [0, n_texels) in order; at most 2^28 triangles.  Builds the BVH on the
+ * device (Morton order, PLOC clustering, collapse to a 4-wide tree) and the
+ * per-texel area table; replaces any previous scene.  *n_texels_out
+ * receives K. */
 int lt_scene_upload(lt_ctx* ctx, const float* h_verts, int64_t n_verts, const int32_t* h_tris,
                     const int32_t* h_tri_patch, int64_t n_tris, const lt_patch* h_patches, int32_t n_patches,
                     int64_t* n_texels_out);
@@ -166,9 +167,11 @@ int lt_record_paths(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params,
                     float* d_contrib);
 
 /* Work counters of one forward pass (instrumented kernel): segments traced,
- * BVH nodes visited (two box tests each), triangle tests, hits, misses. */
+ * BVH nodes visited (four box tests each), triangle tests, hits, misses,
+ * traversal-loop wave iterations, active lanes summed over those iterations,
+ * hit-processing phases. */
 int lt_trace_stats(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, int64_t* d_S,
-                   int64_t h_counts_out[5]);
+                   int64_t h_counts_out[8]);
 
 int lt_get_tuning(const lt_ctx* ctx, lt_tuning* out);
 int lt_set_tuning(lt_ctx* ctx, const lt_tuning* t);

@@ -230,6 +230,102 @@ __global__ void k_ploc_write(int nc, int n_int, int node_base, const int* __rest
     }
 }
 
+// ---- collapse of the binary tree into a 4-wide tree ------------------------
+// Node of the wide tree, 128 B: lo.x, hi.x, lo.y, hi.y, lo.z, hi.z of the four
+// children (float4 each, one lane per child), then the child references
+// (>= 0 wide node, < 0 leaf ~triangle, kEmptyChild unused) and padding.
+__device__ __forceinline__ void ref_box(int c, const float4* nlo, const float4* nhi, const int* vals,
+                                        const float4* tlo, const float4* thi, float4& lo, float4& hi)
+{
+    if (c >= 0) {
+        lo = nlo[c];
+        hi = nhi[c];
+    } else {
+        const int t = vals[~c];
+        lo = tlo[t];
+        hi = thi[t];
+    }
+}
+
+// Open the binary children of each level node: replace the internal child of
+// largest surface area by its two children while fewer than max_w children.
+__global__ void k_collapse_open(int n_level, const int* __restrict__ level, int max_w, const int2* __restrict__ child,
+                                const float4* __restrict__ nlo, const float4* __restrict__ nhi,
+                                int* __restrict__ kids, unsigned long long* __restrict__ cnt)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_level) return;
+    const int2 c0 = child[level[i]];
+    int k[4] = {c0.x, c0.y, kEmptyChild, kEmptyChild};
+    int m = 2;
+    while (m < max_w) {
+        int best = -1;
+        float ba = -1.0f;
+        for (int q = 0; q < m; ++q)
+            if (k[q] >= 0) {
+                const float a = half_area(nlo[k[q]], nhi[k[q]]);
+                if (a > ba) {
+                    ba = a;
+                    best = q;
+                }
+            }
+        if (best < 0) break;
+        const int2 cc = child[k[best]];
+        k[best] = cc.x;
+        k[m++] = cc.y;
+    }
+    unsigned long long n_int = 0;
+    for (int q = 0; q < 4; ++q) {
+        kids[4 * i + q] = k[q];
+        n_int += (k[q] >= 0) ? 1ull : 0ull;
+    }
+    cnt[i] = n_int;
+}
+
+// Write the wide nodes of a level; internal children become the next level.
+__global__ void k_collapse_write(int n_level, int out_base, int next_base, const int* __restrict__ kids,
+                                 const unsigned long long* __restrict__ off, const float4* __restrict__ nlo,
+                                 const float4* __restrict__ nhi, const int* __restrict__ vals,
+                                 const float4* __restrict__ tlo, const float4* __restrict__ thi,
+                                 float4* __restrict__ wide, int* __restrict__ next_level)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_level) return;
+    float lx[4], hx[4], ly[4], hy[4], lz[4], hz[4];
+    int ref[4];
+    int rank = 0;
+    const int base = (int)off[i];
+    for (int q = 0; q < 4; ++q) {
+        const int c = kids[4 * i + q];
+        if (c == kEmptyChild) {
+            lx[q] = hx[q] = ly[q] = hy[q] = lz[q] = hz[q] = 0.0f;
+            ref[q] = kEmptyChild;
+            continue;
+        }
+        float4 lo, hi;
+        ref_box(c, nlo, nhi, vals, tlo, thi, lo, hi);
+        lx[q] = lo.x; hx[q] = hi.x; ly[q] = lo.y; hy[q] = hi.y; lz[q] = lo.z; hz[q] = hi.z;
+        if (c >= 0) {
+            const int w = next_base + base + rank;
+            next_level[base + rank] = c;
+            ref[q] = w;
+            ++rank;
+        } else {
+            ref[q] = c;
+        }
+    }
+    float4* nd = wide + 8 * (size_t)(out_base + i);
+    nd[0] = make_float4(lx[0], lx[1], lx[2], lx[3]);
+    nd[1] = make_float4(hx[0], hx[1], hx[2], hx[3]);
+    nd[2] = make_float4(ly[0], ly[1], ly[2], ly[3]);
+    nd[3] = make_float4(hy[0], hy[1], hy[2], hy[3]);
+    nd[4] = make_float4(lz[0], lz[1], lz[2], lz[3]);
+    nd[5] = make_float4(hz[0], hz[1], hz[2], hz[3]);
+    nd[6] = make_float4(__int_as_float(ref[0]), __int_as_float(ref[1]), __int_as_float(ref[2]),
+                        __int_as_float(ref[3]));
+    nd[7] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 // ---- exclusive prefix sum of u64 (block-local, block sums, add) --------------
 constexpr int kScanItems = 1024;   // 256 threads x 4
 
@@ -294,23 +390,6 @@ __global__ void __launch_bounds__(256) k_scan_add(unsigned long long* __restrict
         if (base + k < n) out[base + k] += s;
 }
 
-__global__ void k_write_nodes(int n_int, const int2* __restrict__ child, const int* __restrict__ vals,
-                              const float4* __restrict__ tlo, const float4* __restrict__ thi,
-                              const float4* __restrict__ nlo, const float4* __restrict__ nhi,
-                              float4* __restrict__ nodes)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_int) return;
-    const int2 c = child[i];
-    float4 al, ah, bl, bh;
-    child_box(c.x, tlo, thi, vals, nlo, nhi, al, ah);
-    child_box(c.y, tlo, thi, vals, nlo, nhi, bl, bh);
-    nodes[4 * i + 0] = make_float4(al.x, ah.x, al.y, ah.y);
-    nodes[4 * i + 1] = make_float4(bl.x, bh.x, bl.y, bh.y);
-    nodes[4 * i + 2] = make_float4(al.z, ah.z, bl.z, bh.z);
-    nodes[4 * i + 3] = make_float4(__int_as_float(c.x), __int_as_float(c.y), 0.f, 0.f);
-}
-
 __global__ void k_write_tris(int n, const int* __restrict__ vals, const float* __restrict__ verts,
                              const int* __restrict__ tris, const int* __restrict__ tri_patch,
                              float4* __restrict__ out)
@@ -324,21 +403,6 @@ __global__ void k_write_tris(int n, const int* __restrict__ vals, const float* _
     out[3 * s + 1] = make_float4(verts[3 * b] - v0x, verts[3 * b + 1] - v0y, verts[3 * b + 2] - v0z,
                                  __int_as_float(tri_patch[t]));
     out[3 * s + 2] = make_float4(verts[3 * c] - v0x, verts[3 * c + 1] - v0y, verts[3 * c + 2] - v0z, 0.f);
-}
-
-// depth of every leaf (internal nodes on its root path) -> max
-__global__ void k_depth(int n, const int* __restrict__ parent_int, const int* __restrict__ parent_leaf,
-                        int* __restrict__ out)
-{
-    const int leaf = blockIdx.x * blockDim.x + threadIdx.x;
-    if (leaf >= n) return;
-    int d = 0;
-    int node = parent_leaf[leaf];
-    while (node >= 0 && d < (1 << 20)) {
-        ++d;
-        node = node == 0 ? -1 : parent_int[node];
-    }
-    atomicMax(out, d);
 }
 
 inline int blocks_for(long long n, int b) { return (int)((n + b - 1) / b); }
@@ -373,7 +437,8 @@ hipError_t scan_u64(const unsigned long long* in, unsigned long long* out, unsig
 
 }  // namespace
 
-// Builds nodes [max(n-1,1) * 4 float4] and leaf triangles [n * 3 float4].
+// Builds the 4-wide nodes [n_nodes * 8 float4] and leaf triangles [n * 3 float4];
+// *depth_out = number of wide levels.
 // Device inputs: d_verts [V*3], d_tris [n*3], d_tri_patch [n].
 hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_patch, int n, float pad,
                      hipStream_t st, float4** nodes_out, float4** tris_out, int* n_nodes_out, int* depth_out)
@@ -386,10 +451,12 @@ hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_p
     const int n_int = n - 1 > 0 ? n - 1 : 1;
     const int n_part = 256;
     const int radius = kPlocRadius;
+    const int max_width = kBvhWidth;
+    int n_wide = 0, wide_levels = 0;
     DevBuf<float4> tlo, thi, cen, part, nlo, nhi, clo[2], chi[2], nodes, otris;
     DevBuf<uint64_t> keys;
     DevBuf<unsigned long long> flags, scan, sums, total;
-    DevBuf<int> vals, pint, pleaf, dmax, nn, cid[2];
+    DevBuf<int> vals, pint, pleaf, nn, cid[2];
     DevBuf<int2> child;
     hipError_t e;
 #define LT_TRY(x)                      \
@@ -400,8 +467,8 @@ hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_p
     LT_TRY(tlo.alloc(n)); LT_TRY(thi.alloc(n)); LT_TRY(cen.alloc(n)); LT_TRY(part.alloc(2 * n_part));
     LT_TRY(keys.alloc(n_pow2)); LT_TRY(vals.alloc(n_pow2));
     LT_TRY(child.alloc(n_int)); LT_TRY(pint.alloc(n_int)); LT_TRY(pleaf.alloc(n));
-    LT_TRY(nlo.alloc(n_int)); LT_TRY(nhi.alloc(n_int)); LT_TRY(dmax.alloc(1));
-    LT_TRY(nodes.alloc(4 * (size_t)n_int)); LT_TRY(otris.alloc(3 * (size_t)n));
+    LT_TRY(nlo.alloc(n_int)); LT_TRY(nhi.alloc(n_int));
+    LT_TRY(nodes.alloc(8 * (size_t)n_int)); LT_TRY(otris.alloc(3 * (size_t)n));
 
     k_tri_setup<<<blocks_for(n, 256), 256, 0, st>>>(d_verts, d_tris, n, pad, tlo.p, thi.p, cen.p);
     k_bounds_partial<<<n_part, 256, 0, st>>>(cen.p, n, part.p);
@@ -444,23 +511,47 @@ hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_p
         }
         if (node_base != n - 1) return hipErrorUnknown;
     }
-    k_write_nodes<<<blocks_for(n_int, 256), 256, 0, st>>>(n_int, child.p, vals.p, tlo.p, thi.p, nlo.p, nhi.p,
-                                                          nodes.p);
-    k_write_tris<<<blocks_for(n, 256), 256, 0, st>>>(n, vals.p, d_verts, d_tris, d_tri_patch, otris.p);
-    int depth = 1;
-    if (n > 1) {
-        LT_TRY(hipMemsetAsync(dmax.p, 0, sizeof(int), st));
-        k_depth<<<blocks_for(n, 256), 256, 0, st>>>(n, pint.p, pleaf.p, dmax.p);
-        LT_TRY(hipGetLastError());
-        LT_TRY(hipMemcpyAsync(&depth, dmax.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    // collapse into the wide tree, level by level from the root
+    {
+        DevBuf<int> lvl[2], kids;
+        DevBuf<unsigned long long> cnt, off;
+        LT_TRY(lvl[0].alloc(n_int)); LT_TRY(lvl[1].alloc(n_int)); LT_TRY(kids.alloc(4 * (size_t)n_int));
+        LT_TRY(cnt.alloc(n_int)); LT_TRY(off.alloc(n_int));
+        if (!sums.p) LT_TRY(sums.alloc(blocks_for(n_int, kScanItems)));
+        if (!total.p) LT_TRY(total.alloc(1));
+        const int root = 0;
+        LT_TRY(hipMemcpyAsync(lvl[0].p, &root, sizeof(int), hipMemcpyHostToDevice, st));
+        int n_level = 1, out_base = 0, cur = 0, levels = 0;
+        while (n_level > 0) {
+            if (++levels > n_int + 1) return hipErrorUnknown;
+            k_collapse_open<<<blocks_for(n_level, 256), 256, 0, st>>>(n_level, lvl[cur].p, max_width, child.p, nlo.p,
+                                                                      nhi.p, kids.p, cnt.p);
+            LT_TRY(scan_u64(cnt.p, off.p, sums.p, total.p, n_level, st));
+            unsigned long long tot = 0;
+            LT_TRY(hipMemcpyAsync(&tot, total.p, sizeof(tot), hipMemcpyDeviceToHost, st));
+            LT_TRY(hipStreamSynchronize(st));
+            const int next_base = out_base + n_level;
+            if (next_base + (long long)tot > n_int) return hipErrorUnknown;   // before any write
+            k_collapse_write<<<blocks_for(n_level, 256), 256, 0, st>>>(n_level, out_base, next_base, kids.p, off.p,
+                                                                       nlo.p, nhi.p, vals.p, tlo.p, thi.p, nodes.p,
+                                                                       lvl[cur ^ 1].p);
+            LT_TRY(hipGetLastError());
+            out_base = next_base;
+            n_level = (int)tot;
+            cur ^= 1;
+        }
+        n_wide = out_base;
+        wide_levels = levels;
     }
+    k_write_tris<<<blocks_for(n, 256), 256, 0, st>>>(n, vals.p, d_verts, d_tris, d_tri_patch, otris.p);
+    int depth = wide_levels;
     LT_TRY(hipGetLastError());
     LT_TRY(hipStreamSynchronize(st));
 #undef LT_TRY
     *depth_out = depth;
     *nodes_out = nodes.release();
     *tris_out = otris.release();
-    *n_nodes_out = n_int;
+    *n_nodes_out = n_wide;
     return hipSuccess;
 }
 

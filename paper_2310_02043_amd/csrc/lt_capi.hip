@@ -203,7 +203,9 @@ int ensure_tiles(lt_ctx* c, long long ppl)
     return LT_OK;
 }
 
-int gstack_depth(const lt_ctx* c) { return std::max(0, c->depth + 1 - c->tune.lds_depth); }
+// stack entries a segment can need: up to three pushes per level of the 4-wide tree
+int stack_need(const lt_ctx* c) { return 3 * c->depth + 1; }
+int gstack_depth(const lt_ctx* c) { return std::max(0, stack_need(c) - c->tune.lds_depth); }
 
 int ensure_gstack(lt_ctx* c, long long waves)
 {
@@ -485,7 +487,7 @@ int lt_scene_upload(lt_ctx* c, const float* h_verts, int64_t n_verts, const int3
     hipFree(d_tris);
     hipFree(d_tp);
     if (e != hipSuccess) return fail(c, LT_EHIP, std::string("BVH build: ") + hipGetErrorString(e));
-    if (depth + 1 > kMaxStackDepth) {
+    if (3 * depth + 1 > kMaxStackDepth) {
         free_scene(c);
         return fail(c, LT_EINVAL, "BVH deeper than the traversal stack bound");
     }
@@ -661,7 +663,7 @@ int lt_record_paths(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, i
     return LT_OK;
 }
 
-int lt_trace_stats(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int64_t* d_S, int64_t h_counts[5])
+int lt_trace_stats(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int64_t* d_S, int64_t h_counts[8])
 {
     int rc = check_cfg(c, cfg);
     if (rc) return rc;
@@ -680,7 +682,7 @@ int lt_trace_stats(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, in
     unsigned long long h[8];
     HIPCHK(c, hipMemcpyAsync(h, c->d_stats, sizeof(h), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int i = 0; i < 5; ++i) h_counts[i] = (int64_t)h[i];
+    for (int i = 0; i < 8; ++i) h_counts[i] = (int64_t)h[i];
     return LT_OK;
 }
 
@@ -717,7 +719,7 @@ int lt_info_get(const lt_ctx* c, lt_info* out)
     out->n_texels = c->K;
     out->bvh_nodes = c->n_nodes;
     out->bvh_depth = c->depth;
-    out->device_bytes = (int64_t)c->n_nodes * 64 + c->n_tris * 48 + (int64_t)c->n_patches * sizeof(DevPatch) +
+    out->device_bytes = (int64_t)c->n_nodes * 128 + c->n_tris * 48 + (int64_t)c->n_patches * sizeof(DevPatch) +
                         c->K * 4 + (int64_t)c->gstack_cap * 4 + (int64_t)c->partials_cap * 8;
     out->n_lights = c->L;
     out->n_layouts = c->n_layouts;

@@ -10,6 +10,8 @@ constexpr int kMaxStackDepth = 128;   // BVH depth bound accepted at upload
 constexpr int kObjBlocks = 1024;      // fixed grid of the objective reduction
 constexpr int kRecordBlocks = 1024;   // grid of the path-recording kernel (4 waves each)
 constexpr int kPlocRadius = 16;       // nearest-neighbour window of the BVH build
+constexpr int kBvhWidth = 4;          // children per node of the traversed tree
+constexpr int kEmptyChild = (int)0x80000000;  // unused child slot of a wide node
 
 struct TraceArgs {
     const float4* nodes;

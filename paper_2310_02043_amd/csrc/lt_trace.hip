@@ -27,12 +27,12 @@ __device__ __forceinline__ void set_ray(Ray& r, V3 o, V3 d)
 {
     r.ox = o.x; r.oy = o.y; r.oz = o.z;
     r.dx = d.x; r.dy = d.y; r.dz = d.z;
-    // the slab test is conservative by the build's padding; exact zeros are
-    // replaced so no 0 * inf appears
+    // the slab test is conservative by the build's padding, so the hardware
+    // reciprocal (1 ulp) serves; exact zeros are replaced so no 0 * inf appears
     const float tiny = 1e-30f;
-    r.ix = 1.0f / (d.x != 0.0f ? d.x : __builtin_copysignf(tiny, d.x));
-    r.iy = 1.0f / (d.y != 0.0f ? d.y : __builtin_copysignf(tiny, d.y));
-    r.iz = 1.0f / (d.z != 0.0f ? d.z : __builtin_copysignf(tiny, d.z));
+    r.ix = __builtin_amdgcn_rcpf(d.x != 0.0f ? d.x : __builtin_copysignf(tiny, d.x));
+    r.iy = __builtin_amdgcn_rcpf(d.y != 0.0f ? d.y : __builtin_copysignf(tiny, d.y));
+    r.iz = __builtin_amdgcn_rcpf(d.z != 0.0f ? d.z : __builtin_copysignf(tiny, d.z));
     r.oix = o.x * r.ix;
     r.oiy = o.y * r.iy;
     r.oiz = o.z * r.iz;
@@ -54,16 +54,40 @@ __device__ __forceinline__ float slab(const Ray& r, float xl, float xh, float yl
 struct Trav {
     float tb;
     int pb, qb;
-    int node, sp;
+    int node, sp;   // node < 0: nothing left to visit
     int steps;
+    int nl;         // queued leaf triangles (l0..l3) found by the last node step
+    int l0, l1, l2, l3;
 };
 
+__device__ __forceinline__ void cswap(float& ta, int& ca, float& tb, int& cb)
+{
+    const bool sw = tb < ta;
+    const float t0 = sw ? tb : ta, t1 = sw ? ta : tb;
+    const int c0 = sw ? cb : ca, c1 = sw ? ca : cb;
+    ta = t0; tb = t1; ca = c0; cb = c1;
+}
+
+// One traversal operation per lane and call: either one queued leaf triangle
+// test, or one node of the 4-wide tree (four box tests; hit leaves are
+// queued, hit internal children sorted by entry distance, the nearest visited
+// next and the others pushed far-to-near).  Queued leaves are tested before
+// the next node step, so the closest-hit bound tightens as early as before.
 template <int LDS_D, bool STATS>
 __device__ __forceinline__ void trav_step(const Ray& r, int skip, Trav& s, bool& traversing,
                                           const float4* __restrict__ nodes, const float4* __restrict__ tris,
                                           int* lst, int* gst, unsigned& n_nodes, unsigned& n_tris,
                                           int max_steps, bool& overrun)
 {
+    if (s.nl > 0) {
+        const int tix = s.nl == 1 ? s.l0 : (s.nl == 2 ? s.l1 : (s.nl == 3 ? s.l2 : s.l3));
+        const float4* tp = tris + 3 * tix;
+        tri_test(tp[0], tp[1], tp[2], v3(r.ox, r.oy, r.oz), v3(r.dx, r.dy, r.dz), skip, s.tb, s.pb, s.qb);
+        if (STATS) ++n_tris;
+        --s.nl;
+        if (s.nl == 0 && s.node < 0) traversing = false;
+        return;
+    }
     // bounded: a segment visits each node at most once in a tree
     if (++s.steps > max_steps) {
         traversing = false;
@@ -72,43 +96,51 @@ __device__ __forceinline__ void trav_step(const Ray& r, int skip, Trav& s, bool&
         s.qb = -1;
         return;
     }
-    const float4* nd = nodes + 4 * s.node;
-    const float4 w0 = nd[0], w1 = nd[1], w2 = nd[2], w3 = nd[3];
+    const float4* nd = nodes + 8 * s.node;
+    const float4 lx = nd[0], hx = nd[1], ly = nd[2], hy = nd[3], lz = nd[4], hz = nd[5];
+    const float4 cr = nd[6];
     if (STATS) ++n_nodes;
-    float t0 = slab(r, w0.x, w0.y, w0.z, w0.w, w2.x, w2.y, s.tb);
-    float t1 = slab(r, w1.x, w1.y, w1.z, w1.w, w2.z, w2.w, s.tb);
-    const int c0 = __float_as_int(w3.x), c1 = __float_as_int(w3.y);
-    const V3 o = v3(r.ox, r.oy, r.oz), d = v3(r.dx, r.dy, r.dz);
-    if (c0 < 0 && t0 != __builtin_inff()) {
-        const float4* tp = tris + 3 * (~c0);
-        tri_test(tp[0], tp[1], tp[2], o, d, skip, s.tb, s.pb, s.qb);
-        if (STATS) ++n_tris;
-        t0 = __builtin_inff();
+    float t[4] = {slab(r, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, s.tb), slab(r, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, s.tb),
+                  slab(r, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, s.tb), slab(r, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, s.tb)};
+    int c[4] = {__float_as_int(cr.x), __float_as_int(cr.y), __float_as_int(cr.z), __float_as_int(cr.w)};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (c[k] == kEmptyChild) {
+            t[k] = __builtin_inff();
+        } else if (c[k] < 0 && t[k] != __builtin_inff()) {
+            const int leaf = ~c[k];
+            s.l3 = s.nl == 3 ? leaf : s.l3;
+            s.l2 = s.nl == 2 ? leaf : s.l2;
+            s.l1 = s.nl == 1 ? leaf : s.l1;
+            s.l0 = s.nl == 0 ? leaf : s.l0;
+            ++s.nl;
+            t[k] = __builtin_inff();
+        }
     }
-    if (c1 < 0 && t1 != __builtin_inff()) {
-        const float4* tp = tris + 3 * (~c1);
-        tri_test(tp[0], tp[1], tp[2], o, d, skip, s.tb, s.pb, s.qb);
-        if (STATS) ++n_tris;
-        t1 = __builtin_inff();
-    }
-    const bool h0 = t0 != __builtin_inff(), h1 = t1 != __builtin_inff();
-    if (h0 && h1) {
-        const bool first0 = t0 <= t1;
-        const int far = first0 ? c1 : c0;
-        s.node = first0 ? c0 : c1;
-        if (s.sp < LDS_D) lst[s.sp * 64] = far;
-        else gst[(s.sp - LDS_D) * 64] = far;
-        ++s.sp;
-    } else if (h0) {
-        s.node = c0;
-    } else if (h1) {
-        s.node = c1;
-    } else if (s.sp == 0) {
-        traversing = false;
+    cswap(t[0], c[0], t[1], c[1]);
+    cswap(t[2], c[2], t[3], c[3]);
+    cswap(t[0], c[0], t[2], c[2]);
+    cswap(t[1], c[1], t[3], c[3]);
+    cswap(t[1], c[1], t[2], c[2]);
+    if (t[0] == __builtin_inff()) {
+        if (s.sp == 0) {
+            s.node = -1;
+        } else {
+            --s.sp;
+            s.node = s.sp < LDS_D ? lst[s.sp * 64] : gst[(s.sp - LDS_D) * 64];
+        }
     } else {
-        --s.sp;
-        s.node = s.sp < LDS_D ? lst[s.sp * 64] : gst[(s.sp - LDS_D) * 64];
+        s.node = c[0];
+#pragma unroll
+        for (int k = 3; k >= 1; --k) {
+            if (t[k] != __builtin_inff()) {
+                if (s.sp < LDS_D) lst[s.sp * 64] = c[k];
+                else gst[(s.sp - LDS_D) * 64] = c[k];
+                ++s.sp;
+            }
+        }
     }
+    if (s.node < 0 && s.nl == 0) traversing = false;
 }
 
 __device__ __forceinline__ void start_segment(Trav& s)
@@ -119,6 +151,8 @@ __device__ __forceinline__ void start_segment(Trav& s)
     s.node = 0;
     s.sp = 0;
     s.steps = 0;
+    s.nl = 0;
+    s.l0 = s.l1 = s.l2 = s.l3 = 0;
 }
 
 // Emission (Alg. 1 "generate exitant ray"): origin y, direction, area offsets.
@@ -313,6 +347,7 @@ __global__ void __launch_bounds__(WPB * 64) k_trace(TraceArgs a)
         float dphi[6] = {0, 0, 0, 0, 0, 0};
         double acc[6] = {0, 0, 0, 0, 0, 0};
         unsigned miss = 0, n_seg = 0, n_nodes = 0, n_tris = 0, n_hits = 0;
+        unsigned n_iter = 0, n_active = 0, n_phase = 0;   // wave-uniform counters
         bool overrun = false;
         Ray r;
         Trav s;
@@ -348,12 +383,17 @@ __global__ void __launch_bounds__(WPB * 64) k_trace(TraceArgs a)
                 const uint64_t tm = ballot(trav);
                 if (tm == 0) break;
                 if (__popcll(ballot(alive && !trav)) >= thresh) break;
+                if (STATS) {
+                    ++n_iter;
+                    n_active += (unsigned)__popcll(tm);
+                }
                 if (trav)
                     trav_step<LDS_D, STATS>(r, skip, s, trav, a.nodes, a.tris, lst, gst, n_nodes, n_tris,
                                             a.max_steps, overrun);
             }
 
             // hit processing for lanes whose segment ended
+            if (STATS) ++n_phase;
             if (alive && !trav) {
                 bool end_path = false;
                 if (s.pb < 0) {
@@ -418,6 +458,9 @@ __global__ void __launch_bounds__(WPB * 64) k_trace(TraceArgs a)
                 atomicAdd(a.stats + 2, (unsigned long long)c2);
                 atomicAdd(a.stats + 3, (unsigned long long)c3);
                 atomicAdd(a.stats + 4, (unsigned long long)wm);
+                atomicAdd(a.stats + 5, (unsigned long long)n_iter);
+                atomicAdd(a.stats + 6, (unsigned long long)n_active);
+                atomicAdd(a.stats + 7, (unsigned long long)n_phase);
             }
         }
     }

@@ -233,10 +233,10 @@ class Context:
         torch = self._torch
         if S is None:
             S = torch.empty((self.n_layouts, self.n_texels), dtype=torch.int64, device=params.device)
-        out = (C.c_int64 * 5)()
+        out = (C.c_int64 * 8)()
         self._stream()
         self._check(self.lib.lt_trace_stats(self.h, C.byref(cfg), _ptr(params), _ptr(S), out))
-        keys = ("segments", "nodes", "tri_tests", "hits", "misses")
+        keys = ("segments", "nodes", "tri_tests", "hits", "misses", "wave_iters", "active_lanes", "phases")
         return dict(zip(keys, [int(x) for x in out]))
 
     def sync(self) -> int:
