@@ -1,0 +1,78 @@
+"""Differentiable light tracing for torch.
+
+``LightTraceFn.apply(params, tracer)`` runs the primal light-tracing kernel
+(Alg. 1) and returns texel irradiance E [n_layouts, K]; its backward runs the
+adjoint light-tracing kernel (Alg. 2) with the incoming dL/dE as the adjoint
+source and returns dL/dparams [L, 6].  Whether the adjoint replays the
+forward's paths (correlated evaluation, as the paper uses for validation) or
+a fresh set (decorrelated, as it uses for optimisation) is the tracer's
+``correlated`` flag (Sec. 4.3).  Both passes run on the current torch stream.
+"""
+from __future__ import annotations
+
+import torch
+
+from .native import Context
+
+DECORRELATE = 0x9E3779B97F4A7C15
+
+
+class LightTracer:
+    """Holds a liblt context with one scene and one luminaire set, and the
+    per-call configuration of the forward / adjoint passes."""
+
+    def __init__(self, scene_arrays, lights_static, layout_offsets, paths_per_layout: int, max_hits: int,
+                 seed: int = 1, correlated: bool = True, graph: bool = False, device: int = 0):
+        verts, tris, tri_patch, patches = scene_arrays
+        self.ctx = Context(device)
+        self.n_texels = self.ctx.upload_scene(verts, tris, tri_patch, patches)
+        self.ctx.set_lights(lights_static, layout_offsets)
+        self.paths_per_layout = int(paths_per_layout)
+        self.max_hits = int(max_hits)
+        self.seed = int(seed)
+        self.correlated = bool(correlated)
+        self.graph = bool(graph)
+        self._S = None
+        self.device = torch.device("cuda", device)
+
+    def cfg(self, seed=None):
+        return self.ctx.cfg(self.seed if seed is None else seed, self.paths_per_layout, self.max_hits, graph=self.graph)
+
+    def adjoint_seed(self, seed=None):
+        s = self.seed if seed is None else seed
+        return s if self.correlated else (s ^ DECORRELATE)
+
+    def scratch(self):
+        n = (self.ctx.n_layouts, self.n_texels)
+        if self._S is None or tuple(self._S.shape) != n:
+            self._S = torch.empty(n, dtype=torch.int64, device=self.device)
+        return self._S
+
+    def __call__(self, params, seed=None):
+        return LightTraceFn.apply(params, self, seed)
+
+
+class LightTraceFn(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, params, tracer: LightTracer, seed=None):
+        p = params.detach().contiguous().float()
+        E, _ = tracer.ctx.trace_forward(p, tracer.cfg(seed), S=tracer.scratch())
+        fctx.save_for_backward(p)
+        fctx.tracer = tracer
+        fctx.seed = seed
+        return E
+
+    @staticmethod
+    def backward(fctx, grad_E):
+        (p,) = fctx.saved_tensors
+        tracer = fctx.tracer
+        g = grad_E.contiguous().float()
+        grad = tracer.ctx.trace_adjoint(p, g, tracer.cfg(tracer.adjoint_seed(fctx.seed)))
+        return grad, None, None
+
+
+def objective(E, E_target, texel_area, alpha=None):
+    """O = 1/2 sum_k A_k alpha_k (E_k - E*_k)^2 (Eq. objective, alpha_l = 1) in torch."""
+    w = texel_area if alpha is None else texel_area * alpha
+    d = E - E_target
+    return 0.5 * torch.sum(w * d * d, dtype=torch.float64)
