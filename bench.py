@@ -98,7 +98,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--paths", type=int, default=1 << 26)
+    ap.add_argument("--workload", choices=["office", "room_set", "building"], default="office")
+    ap.add_argument("--paths", type=int, default=0, help="paths per layout (default: the workload's)")
+    ap.add_argument("--graph", action="store_true", help="replay forward / adjoint as captured hipGraphs")
+    ap.add_argument("--autotune", action="store_true", help="run the launch autotuner before timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", type=str, default="", help="k=v,... launch tuning override")
@@ -124,9 +127,19 @@ def main():
     import lt_inputs as li
     from paper_2310_02043_amd import Context
 
-    c2 = li.office()
-    scene, lights = c2["scene"], c2["lights"]
-    N, B, seed = args.paths, c2["max_hits"], c2["seed"]
+    if args.workload == "office":
+        wl = li.office()
+        desc = "procedural office 30x20x3 m"
+    elif args.workload == "room_set":
+        wl = li.room_set()
+        desc = "room set (four 6x5x3 m rooms), 64 candidate layouts of 4-48 point/spot lights"
+    else:
+        wl = li.building_floor()
+        desc = "building floor 80x60x3.2 m"
+    scene, lights = wl["scene"], wl["lights"]
+    B, seed = wl["max_hits"], wl["seed"]
+    N = args.paths if args.paths else wl["paths"]   # paths per layout
+    n_layouts = lights.n_layouts
     ctx = Context(0)
     ctx.upload_scene(scene.verts, scene.tris, scene.tri_patch, scene.patches)
     ctx.set_lights(lights.static, lights.layout_offsets)
@@ -136,14 +149,19 @@ def main():
     log("scene", info)
     dev = "cuda:0"
     p = torch.tensor(lights.params, device=dev)
-    Et = torch.tensor(li.painted_target(scene, 0.5)[None], device=dev)
     K = scene.n_texels
-    S = torch.empty((1, K), dtype=torch.int64, device=dev)
-    E = torch.empty((1, K), dtype=torch.float32, device=dev)
-    g = torch.empty((1, K), dtype=torch.float32, device=dev)
+    Et = torch.tensor(np.stack([li.painted_target(scene, 0.5, seed=j) for j in range(n_layouts)]), device=dev)
+    S = torch.empty((n_layouts, K), dtype=torch.int64, device=dev)
+    E = torch.empty((n_layouts, K), dtype=torch.float32, device=dev)
+    g = torch.empty((n_layouts, K), dtype=torch.float32, device=dev)
     O = torch.empty(1, dtype=torch.float64, device=dev)
     grad = torch.empty((lights.n_lights, 6), dtype=torch.float32, device=dev)
-    cfg = ctx.cfg(seed, N, B)
+    cfg = ctx.cfg(seed, N, B, graph=args.graph)
+    if args.autotune:
+        t0 = time.time()
+        g.normal_()
+        best = ctx.autotune(p, ctx.cfg(seed, N, B), S, E, g, grad)
+        log(f"autotune: {ctx.get_tuning().as_dict()} ({best:.1f} ms fwd+adj, {time.time() - t0:.1f} s)")
 
     def step():
         ctx.trace_forward(p, cfg, S=S, E=E)
@@ -159,19 +177,31 @@ def main():
     stats = ctx.trace_stats(p, cfg)
     log("work per pass", stats)
 
+    # kernel durations: HIP events recorded on the launch stream around each
+    # trace kernel inside the timed region (direct launches); with graph
+    # replay, the same number of steps is launched directly afterwards
     ctx.timing_read()
-    ctx.set_timing(True)
+    ctx.set_timing(not args.graph)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ctx.set_timing(False)
     flags = ctx.sync()
-    fwd_ms, nf, adj_ms, na = ctx.timing_read()
     ms_step = (t1 - t0) * 1000.0 / args.steps
-    value = N / (ms_step / 1000.0)
+    total_paths = N * n_layouts
+    value = total_paths / (ms_step / 1000.0)
+    if args.graph:
+        ctx.set_timing(True)
+        kcfg = ctx.cfg(seed, N, B)
+        for i in range(args.steps):
+            ctx.trace_forward(p, kcfg, S=S, E=E)
+            ctx.objective(E, Et, g=g, O=O)
+            ctx.trace_adjoint(p, g, kcfg, grad=grad)
+        torch.cuda.synchronize()
+    ctx.set_timing(False)
+    fwd_ms, nf, adj_ms, na = ctx.timing_read()
     fwd_avg, adj_avg = fwd_ms / max(nf, 1), adj_ms / max(na, 1)
     log(f"step {ms_step:.2f} ms  fwd kernel {fwd_avg:.2f} ms  adj kernel {adj_avg:.2f} ms  flags {flags}")
 
@@ -186,7 +216,7 @@ def main():
                 "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": None}
     roof_mem = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
-    traffic = measured_traffic(dominant)
+    traffic = measured_traffic(dominant) if args.workload == "office" else None
     roof_mem["traffic"] = traffic
     roof_mem["note"] = ("achieved counts the node, triangle and patch bytes the traversal fetches (L2 / "
                         "Infinity Cache level); traffic is the HBM bytes rocprofv3 measured per launch")
@@ -199,10 +229,11 @@ def main():
         "metric": METRIC, "value": round(value, 1), "unit": "paths/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+i64", "data": "synthetic",
-        "config": {"workload": f"procedural office 30x20x3 m, {scene.n_tris} triangles, {K} texels, "
-                               f"{lights.n_lights} rectangular cos^n luminaires, {N} paths, {B} hits",
-                   "paths": N, "max_hits": B, "triangles": scene.n_tris, "texels": K,
-                   "luminaires": lights.n_lights, "parallelism": "single GPU"},
+        "config": {"workload": f"{desc}, {scene.n_tris} triangles, {K} texels, {lights.n_lights} luminaires, "
+                               f"{n_layouts} layout(s) x {N} paths, {B} hits",
+                   "paths": total_paths, "paths_per_layout": N, "layouts": n_layouts, "max_hits": B,
+                   "triangles": scene.n_tris, "texels": K, "luminaires": lights.n_lights,
+                   "graph": bool(args.graph), "tuning": ctx.get_tuning().as_dict(), "parallelism": "single GPU"},
         "fwd_kernel_ms": round(fwd_avg, 3), "adj_kernel_ms": round(adj_avg, 3),
         "roofline": roofline,
         "cpu_baseline": None,
@@ -210,6 +241,8 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(scene, lights, seed, N, B, args.cpu_seconds)
+    if args.workload != "office":
+        out["metric"] = METRIC + f" [{args.workload}]"
     print(json.dumps(out), flush=True)
 
 
