@@ -153,8 +153,9 @@ int lt_objective(lt_ctx* ctx, const float* d_E, const float* d_Etarget, const fl
 /* Adjoint light tracing (Alg. 2, Eq. adjointFlux, Eq. objGradAdjoint,
  * Eq. posDeriv and the rotation / area-light terms): replays the paths of
  * `cfg` (same seed = correlated evaluation) with d_dOdE [n_layouts,K] and
- * writes d_grad [L,6] f32 = dO/dp.  d_bin_hist [L,1024] f32 (may be NULL)
- * receives per-light adjoint magnitudes binned by emission direction. */
+ * writes d_grad [L,6] f32 = dO/dp.  d_bin_hist [L,1024] f32 (may be NULL,
+ * overwritten) receives per-light adjoint magnitudes binned by emission
+ * direction (see lt_proposal_set_scale); rows of point lights stay 0. */
 int lt_trace_adjoint(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, const float* d_dOdE,
                      float* d_grad, float* d_bin_hist);
 
@@ -172,6 +173,49 @@ int lt_record_paths(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params,
  * hit-processing phases. */
 int lt_trace_stats(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, int64_t* d_S,
                    int64_t h_counts_out[8]);
+
+/* Learned emission proposal (an extension beyond the paper, which leaves
+ * importance sampling to future work, Sec. 7).  Per light, a distribution
+ * pi_b over the 32 x 32 cells of the hemi-octahedral map of the emission
+ * hemisphere (cell (i, j) covers u in [-1 + i/16, -1 + (i+1)/16], v likewise,
+ * direction p = ((u+v)/2, (u-v)/2, 1-|.|-|.|)/|p| in the light frame (t, b, d),
+ * solid-angle density pi_b * 512 * |p|^3).  With LT_FLAG_PROPOSAL a spot or
+ * rectangle emits from the plain cos^n lobe with probability alpha_plain and
+ * from the cells otherwise, with Phi_r = (P/N) p_plain / q, q = alpha p_plain
+ * + (1 - alpha) p_learn (one-sample MIS, unbiased for alpha > 0).  Point
+ * lights always use the plain sampler.  d_pdf, d_cdf [L,1024] f32 (cdf =
+ * inclusive prefix sums of pdf) are copied into the context. */
+int lt_proposal_set_table(lt_ctx* ctx, const float* d_pdf, const float* d_cdf);
+/* Copy the context's current proposal tables out (d_pdf, d_cdf [L,1024]). */
+int lt_proposal_get_table(lt_ctx* ctx, float* d_pdf, float* d_cdf);
+
+/* Per-light scale of the adjoint histogram signal: the adjoint pass adds
+ * |c_r * inv_sigma|_2 of every path's gradient contribution c_r into
+ * d_bin_hist[light][cell of its emission direction].  d_inv_sigma [L,6] f32. */
+int lt_proposal_set_scale(lt_ctx* ctx, const float* d_inv_sigma);
+
+/* The proposal network: per light x [32] = 6 normalised parameters, a 16-d
+ * learned embedding, 10 zeros -> 64 ReLU -> 64 ReLU -> 1024 cell logits ->
+ * softmax.  Weights (LT_MLP_WEIGHTS values): W1 [64][32], b1 [64], W2 [64][64],
+ * b2 [64], W3 [1024][64], b3 [1024], row-major, output-major.
+ * lt_proposal_mlp_infer: BF16 weights d_w_bf16 and inputs (rounded to BF16)
+ * on MFMA with FP32 accumulate; writes the context's proposal tables (as
+ * lt_proposal_set_table) and, if d_logits [L,1024] is not NULL, the logits.
+ * d_x is [L,32] f32. */
+#define LT_MLP_WEIGHTS 72832
+#define LT_MLP_IN 32
+int lt_proposal_mlp_infer(lt_ctx* ctx, const uint16_t* d_w_bf16, const float* d_x, float* d_logits);
+
+/* One training step: cross-entropy between softmax(MLP(x)) and the target
+ * cell distribution d_target [L,1024] (rows sum to 1), averaged over lights;
+ * backward through the network and into the embedding columns 6..21 of d_x;
+ * Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias correction with `step` >= 1,
+ * learning rate lr) on the FP32 master weights d_w with moments d_mw, d_vw
+ * and on the embeddings with d_mx, d_vx; refreshes d_w_bf16.  d_loss (one
+ * f32) and d_grad_out [LT_MLP_WEIGHTS + L*32] may be NULL. */
+int lt_proposal_mlp_train(lt_ctx* ctx, float* d_w, float* d_mw, float* d_vw, uint16_t* d_w_bf16, float* d_x,
+                          float* d_mx, float* d_vx, const float* d_target, int32_t step, float lr, float* d_loss,
+                          float* d_grad_out);
 
 int lt_get_tuning(const lt_ctx* ctx, lt_tuning* out);
 int lt_set_tuning(lt_ctx* ctx, const lt_tuning* t);

@@ -36,6 +36,29 @@ class _Scene(C.Structure):
                 ("n_patches", C.c_int32), ("n_texels", C.c_int64), ("bvh", C.c_void_p)]
 
 
+class _Proposal(C.Structure):
+    _fields_ = [("pdf", C.c_void_p), ("cdf", C.c_void_p), ("alpha", C.c_float), ("inv_sigma", C.c_void_p),
+                ("hist", C.c_void_p)]
+
+
+class Proposal:
+    """Binned emission proposal tables (pdf, cdf [L,1024] f32), plain-lobe
+    probability alpha, and for the adjoint histogram inv_sigma [L,6]."""
+
+    def __init__(self, pdf, cdf, alpha, inv_sigma=None, with_hist=False):
+        self.pdf = np.ascontiguousarray(pdf, np.float32)
+        self.cdf = np.ascontiguousarray(cdf, np.float32)
+        L = self.pdf.shape[0]
+        self.inv_sigma = np.ascontiguousarray(np.ones((L, 6)) if inv_sigma is None else inv_sigma, np.float32)
+        self.hist = np.zeros((L, 1024), np.float64) if with_hist else None
+        self.c = _Proposal(self.pdf.ctypes.data, self.cdf.ctypes.data, float(alpha), self.inv_sigma.ctypes.data,
+                           None if self.hist is None else self.hist.ctypes.data)
+
+
+def _prop(p):
+    return None if p is None else C.byref(p.c)
+
+
 class _Lights(C.Structure):
     _fields_ = [("type", C.c_void_p), ("lobe_n", C.c_void_p), ("size", C.c_void_p),
                 ("layout_offsets", C.c_void_p), ("n_lights", C.c_int32), ("n_layouts", C.c_int32)]
@@ -62,12 +85,12 @@ def lib():
         L.or_bvh_build.restype = P
         L.or_bvh_free.argtypes = [P]
         L.or_intersect_batch.argtypes = [P, P, C.c_int64, P, P, P]
-        L.or_forward.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int64, C.c_int, P]
+        L.or_forward.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int64, C.c_int, P, P]
         L.or_forward.restype = C.c_int64
-        L.or_adjoint.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int64, C.c_int, P, P]
+        L.or_adjoint.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int64, C.c_int, P, P, P]
         L.or_adjoint.restype = C.c_int64
         L.or_record.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int64,
-                                C.c_int64, P, P, P, P]
+                                C.c_int64, P, P, P, P, P]
         L.or_fixed_to_float.argtypes = [P, C.c_int64, P]
         L.or_objective.argtypes = [P, P, P, P, C.c_int64, C.c_int64, P]
         L.or_objective.restype = C.c_double
@@ -162,30 +185,33 @@ def intersect(osc: OracleScene, rays: np.ndarray, skip=None):
 
 
 def forward(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,
-            limit_per_light: int = 0, n_threads: int = 0):
+            limit_per_light: int = 0, n_threads: int = 0, proposal: Proposal = None):
     """Alg. 1: returns (S [n_layouts,K] int64, misses)."""
     prm = np.ascontiguousarray(params, np.float32)
     S = np.zeros((ol.n_layouts, osc.n_texels), np.int64)
     m = lib().or_forward(C.byref(osc.c), C.byref(ol.c), prm.ctypes.data, int(seed) & 0xFFFFFFFFFFFFFFFF,
                          int(paths_per_layout), int(max_hits), int(limit_per_light), int(n_threads),
-                         S.ctypes.data)
+                         _prop(proposal), S.ctypes.data)
     return S, int(m)
 
 
 def adjoint(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,
-            dOdE, limit_per_light: int = 0, n_threads: int = 0):
-    """Alg. 2: returns (grad [L,6] float64, misses)."""
+            dOdE, limit_per_light: int = 0, n_threads: int = 0, proposal: Proposal = None):
+    """Alg. 2: returns (grad [L,6] float64, misses); with a proposal holding a
+    histogram, fills proposal.hist."""
     prm = np.ascontiguousarray(params, np.float32)
     g = np.ascontiguousarray(dOdE, np.float32).reshape(ol.n_layouts, osc.n_texels)
     out = np.zeros((ol.n_lights, 6), np.float64)
+    if proposal is not None and proposal.hist is not None:
+        proposal.hist[:] = 0.0
     m = lib().or_adjoint(C.byref(osc.c), C.byref(ol.c), prm.ctypes.data, int(seed) & 0xFFFFFFFFFFFFFFFF,
                          int(paths_per_layout), int(max_hits), int(limit_per_light), int(n_threads),
-                         g.ctypes.data, out.ctypes.data)
+                         _prop(proposal), g.ctypes.data, out.ctypes.data)
     return out, int(m)
 
 
 def record(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,
-           layout: int, light: int, first: int, count: int, dOdE=None):
+           layout: int, light: int, first: int, count: int, dOdE=None, proposal: Proposal = None):
     prm = np.ascontiguousarray(params, np.float32)
     prim = np.zeros((count, max_hits), np.int32)
     tex = np.zeros((count, max_hits), np.int32)
@@ -193,7 +219,7 @@ def record(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layo
     contrib = None if dOdE is None else np.zeros((count, 6), np.float32)
     lib().or_record(C.byref(osc.c), C.byref(ol.c), prm.ctypes.data, int(seed) & 0xFFFFFFFFFFFFFFFF,
                     int(paths_per_layout), int(max_hits), int(layout), int(light), int(first), int(count),
-                    prim.ctypes.data, tex.ctypes.data, _p(g), _p(contrib))
+                    _prop(proposal), prim.ctypes.data, tex.ctypes.data, _p(g), _p(contrib))
     return prim, tex, contrib
 
 

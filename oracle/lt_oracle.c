@@ -224,6 +224,18 @@ typedef struct {
     int32_t n_layouts;
 } or_lights;
 
+/* Learned emission proposal (beyond the paper, which leaves importance
+ * sampling to future work, Sec. 7): per light a distribution over 32 x 32
+ * cells of the hemi-octahedral map of the emission hemisphere, mixed with the
+ * plain lobe under one-sample MIS (defensive mixture).  pdf/cdf: [L,1024]. */
+typedef struct {
+    const float* pdf;        /* bin probabilities pi_b */
+    const float* cdf;        /* inclusive prefix sums of pdf */
+    float alpha;             /* probability of the plain lobe */
+    const float* inv_sigma;  /* [L,6] scale of the histogram signal (adjoint) */
+    double* hist;            /* [L,1024] adjoint histogram (adjoint, may be NULL) */
+} or_proposal;
+
 static float dot3(const float* a, const float* b) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
 
 /* Moeller-Trumbore ray/triangle test, barycentric bounds widened by 2^-20.
@@ -528,10 +540,13 @@ static void first_hit_dlog(const olight* L, const float* x1, const float* y, con
     dl[3] = ra; dl[4] = rb;
 }
 
-static void trace_path(const or_scene* S, const olight* L, int layout, int l_local, uint32_t i, uint64_t seed,
-                       int B, path_io* io)
+static void trace_path(const or_scene* S, const olight* L, int layout, int l_local, int gl, uint32_t i, uint64_t seed,
+                       int B, const or_proposal* prop_in, path_io* io)
 {
     const uint32_t stream = ((uint32_t)layout << 16) | (uint32_t)l_local;
+    const or_proposal* prop = (prop_in && prop_in->pdf && L->type != 0) ? prop_in : NULL;
+    float phi_r = L->phi_r;
+    int ebin = -1;
     float u[4];
     draw4(seed, i, stream, 0u, u);
     /* emission: origin y, direction w0 (Alg. 1 "generate exitant ray") */
@@ -551,6 +566,53 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
         float sp, cp;
         or_sincos2pi(u[3], &sp, &cp);
         float a = st * cp, bb = st * sp;
+        if (prop) {
+            /* one-sample MIS between the plain lobe (probability alpha) and
+             * the binned proposal; Phi_r = (P/N) p_plain / q */
+            float w[4];
+            draw4(seed, i, stream, 1u, w);
+            const float* pdf = prop->pdf + 1024 * (int64_t)gl;
+            const float* cdf = prop->cdf + 1024 * (int64_t)gl;
+            float lz, pl3;
+            if (w[0] < prop->alpha) {
+                lz = ct;
+                float s = (fabsf(a) + fabsf(bb)) + lz;
+                float xp = a / s, yp = bb / s;
+                int iu = (int)floorf(((xp + yp) + 1.0f) * 16.0f);
+                int iv = (int)floorf(((xp - yp) + 1.0f) * 16.0f);
+                if (iu < 0) iu = 0;
+                if (iu > 31) iu = 31;
+                if (iv < 0) iv = 0;
+                if (iv > 31) iv = 31;
+                ebin = iv * 32 + iu;
+                pl3 = 1.0f / ((s * s) * s);
+            } else {
+                int lo = 0, hi = 1023;
+                while (lo < hi) {
+                    int mid = (lo + hi) >> 1;
+                    if (w[1] < cdf[mid]) hi = mid;
+                    else lo = mid + 1;
+                }
+                ebin = lo;
+                float uu = -1.0f + ((float)(lo & 31) + w[2]) * 0.0625f;
+                float vv = -1.0f + ((float)(lo >> 5) + w[3]) * 0.0625f;
+                float xp = (uu + vv) * 0.5f, yp = (uu - vv) * 0.5f;
+                float zp = (1.0f - fabsf(xp)) - fabsf(yp);
+                float nrm = sqrtf((xp * xp + yp * yp) + zp * zp);
+                float inv = 1.0f / nrm;
+                a = xp * inv;
+                bb = yp * inv;
+                lz = zp * inv;
+                ct = lz;
+                pl3 = (nrm * nrm) * nrm;
+            }
+            float pw = 1.0f;
+            if (L->n != 0.0f) pw = lz > 0.0f ? or_exp2(L->n * or_log2(lz)) : 0.0f;
+            float p_plain = ((L->n + 1.0f) * (float)0.15915494309189533577) * pw;
+            float p_learn = (pdf[ebin] * 512.0f) * pl3;
+            float q = prop->alpha * p_plain + (1.0f - prop->alpha) * p_learn;
+            phi_r = q > 0.0f ? phi_r * (p_plain / q) : 0.0f;
+        }
         for (int c = 0; c < 3; ++c) dir[c] = (a * L->t[c] + bb * L->b[c]) + ct * L->d[c];
         if (L->type == 2) {
             au = (u[0] - 0.5f) * L->w;
@@ -594,7 +656,7 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
         if (nd < 0.0f) { no[0] = nq[0]; no[1] = nq[1]; no[2] = nq[2]; }
         else { no[0] = -nq[0]; no[1] = -nq[1]; no[2] = -nq[2]; }
         if (io->S) {
-            float val = (L->phi_r * T) * inv_a;
+            float val = (phi_r * T) * inv_a;
             long long code = llrintf(val * 4294967296.0f);
 #ifdef _OPENMP
 #pragma omp atomic
@@ -606,7 +668,7 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
             if (h == 1) {
                 float dl[6];
                 first_hit_dlog(L, x, y, no, au, av, dl);
-                for (int c = 0; c < 6; ++c) dphi[c] = L->phi_r * dl[c];
+                for (int c = 0; c < 6; ++c) dphi[c] = phi_r * dl[c];
             }
         }
         if (io->rec_prim) {
@@ -634,10 +696,24 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
         T = T * pf[16];
     }
     if (io->g && hits >= 1) {
+        float cr[6];
         for (int c = 0; c < 6; ++c) {
-            float cr = s_r * dphi[c];
-            if (io->acc) io->acc[c] += (double)cr;
-            if (io->contrib) io->contrib[c] = cr;
+            cr[c] = s_r * dphi[c];
+            if (io->acc) io->acc[c] += (double)cr[c];
+            if (io->contrib) io->contrib[c] = cr[c];
+        }
+        if (prop && prop->hist && ebin >= 0) {
+            const float* is = prop->inv_sigma + 6 * (int64_t)gl;
+            float m2 = 0.0f;
+            for (int c = 0; c < 6; ++c) {
+                float z = cr[c] * is[c];
+                m2 = m2 + z * z;
+            }
+            double v = (double)sqrtf(m2);
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+            prop->hist[1024 * (int64_t)gl + ebin] += v;
         }
     } else if (io->contrib) {
         for (int c = 0; c < 6; ++c) io->contrib[c] = 0.0f;
@@ -653,7 +729,7 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
  * Phi_r = P / N_l of the full path count). */
 EXPORT int64_t or_forward(const or_scene* S, const or_lights* Ls, const float* params, uint64_t seed,
                           int64_t paths_per_layout, int max_hits, int64_t limit_per_light, int n_threads,
-                          int64_t* S_out)
+                          const or_proposal* prop, int64_t* S_out)
 {
     memset(S_out, 0, (size_t)(S->n_texels * Ls->n_layouts) * sizeof(int64_t));
     int64_t misses = 0;
@@ -675,7 +751,7 @@ EXPORT int64_t or_forward(const or_scene* S, const or_lights* Ls, const float* p
                 path_io io;
                 memset(&io, 0, sizeof(io));
                 io.S = S_out + (int64_t)j * S->n_texels;
-                trace_path(S, &L, j, gl - l0, (uint32_t)i, seed, max_hits, &io);
+                trace_path(S, &L, j, gl - l0, gl, (uint32_t)i, seed, max_hits, prop, &io);
                 m += io.misses;
             }
             misses += m;
@@ -687,7 +763,7 @@ EXPORT int64_t or_forward(const or_scene* S, const or_lights* Ls, const float* p
 /* Adjoint light tracing (Alg. 2).  dOdE: [n_layouts, K]; grad_out: [L,6] FP64. */
 EXPORT int64_t or_adjoint(const or_scene* S, const or_lights* Ls, const float* params, uint64_t seed,
                           int64_t paths_per_layout, int max_hits, int64_t limit_per_light, int n_threads,
-                          const float* dOdE, double* grad_out)
+                          const or_proposal* prop, const float* dOdE, double* grad_out)
 {
     int64_t misses = 0;
 #ifdef _OPENMP
@@ -711,7 +787,7 @@ EXPORT int64_t or_adjoint(const or_scene* S, const or_lights* Ls, const float* p
                 memset(&io, 0, sizeof(io));
                 io.g = dOdE + (int64_t)j * S->n_texels;
                 io.acc = acc;
-                trace_path(S, &L, j, gl - l0, (uint32_t)i, seed, max_hits, &io);
+                trace_path(S, &L, j, gl - l0, gl, (uint32_t)i, seed, max_hits, prop, &io);
                 a0 += acc[0]; a1 += acc[1]; a2 += acc[2]; a3 += acc[3]; a4 += acc[4]; a5 += acc[5];
                 m += io.misses;
             }
@@ -728,7 +804,8 @@ EXPORT int64_t or_adjoint(const or_scene* S, const or_lights* Ls, const float* p
  * contribution dO/dPhi_r * dPhi_r/dp [count,6]. */
 EXPORT void or_record(const or_scene* S, const or_lights* Ls, const float* params, uint64_t seed,
                       int64_t paths_per_layout, int max_hits, int layout, int l_local, int64_t first,
-                      int64_t count, int32_t* prim_out, int32_t* texel_out, const float* dOdE, float* contrib)
+                      int64_t count, const or_proposal* prop, int32_t* prim_out, int32_t* texel_out,
+                      const float* dOdE, float* contrib)
 {
     int l0 = Ls->layout_offsets[layout], l1 = Ls->layout_offsets[layout + 1];
     int gl = l0 + l_local;
@@ -749,7 +826,7 @@ EXPORT void or_record(const or_scene* S, const or_lights* Ls, const float* param
             io.acc = acc;
             io.contrib = contrib + 6 * r;
         }
-        trace_path(S, &L, layout, l_local, (uint32_t)(first + r), seed, max_hits, &io);
+        trace_path(S, &L, layout, l_local, gl, (uint32_t)(first + r), seed, max_hits, prop, &io);
     }
 }
 

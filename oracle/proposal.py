@@ -1,0 +1,103 @@
+"""Proposal-network oracle (numpy) -- TEST INFRASTRUCTURE.
+
+The emission proposal is an extension beyond the paper (which leaves
+importance sampling to future work, Sec. 7): a small MLP from a light's
+normalised parameters and learned embedding to probabilities over the 32 x 32
+cells of the hemi-octahedral map of its emission hemisphere.  This module
+writes the network out plainly in float64:
+
+* inference mirrors the kernel's rounding points (weights, inputs and hidden
+  activations rounded to bfloat16, accumulation in higher precision);
+* a training step is cross-entropy to a target distribution, backpropagated
+  by hand, followed by Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+IN, HID, BINS, NPAR, NEMB = 32, 64, 1024, 6, 16
+OFF_W1 = 0
+OFF_B1 = OFF_W1 + HID * IN
+OFF_W2 = OFF_B1 + HID
+OFF_B2 = OFF_W2 + HID * HID
+OFF_W3 = OFF_B2 + HID
+OFF_B3 = OFF_W3 + BINS * HID
+N_WEIGHTS = OFF_B3 + BINS
+
+
+def unpack(w):
+    w = np.asarray(w, np.float64)
+    return (w[OFF_W1:OFF_B1].reshape(HID, IN), w[OFF_B1:OFF_W2], w[OFF_W2:OFF_B2].reshape(HID, HID),
+            w[OFF_B2:OFF_W3], w[OFF_W3:OFF_B3].reshape(BINS, HID), w[OFF_B3:N_WEIGHTS])
+
+
+def bf16_round(a):
+    """Round float32 values to bfloat16 (nearest, ties to even), returned as float32."""
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)
+
+
+def bf16_bits(a):
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    return (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) & 0xFFFF).astype(np.uint16)
+
+
+def infer(w, x):
+    """Logits and cell probabilities with bfloat16 weights / activations."""
+    wb = bf16_round(np.asarray(w, np.float32)).astype(np.float64)
+    W1, b1, W2, b2, W3, b3 = unpack(wb)
+    xb = bf16_round(np.asarray(x, np.float32)).astype(np.float64)
+    h1 = bf16_round(np.maximum(xb @ W1.T + b1, 0.0).astype(np.float32)).astype(np.float64)
+    h2 = bf16_round(np.maximum(h1 @ W2.T + b2, 0.0).astype(np.float32)).astype(np.float64)
+    z = h2 @ W3.T + b3
+    e = np.exp(z - z.max(1, keepdims=True))
+    p = e / e.sum(1, keepdims=True)
+    return z, p
+
+
+def loss_and_grad(w, x, target):
+    """Mean cross-entropy over lights and its gradient w.r.t. the weights and
+    the embedding columns of x (full precision)."""
+    W1, b1, W2, b2, W3, b3 = unpack(w)
+    x = np.asarray(x, np.float64)
+    t = np.asarray(target, np.float64)
+    L = x.shape[0]
+    a1 = x @ W1.T + b1
+    h1 = np.maximum(a1, 0.0)
+    a2 = h1 @ W2.T + b2
+    h2 = np.maximum(a2, 0.0)
+    z = h2 @ W3.T + b3
+    lse = z.max(1, keepdims=True) + np.log(np.exp(z - z.max(1, keepdims=True)).sum(1, keepdims=True))
+    loss = float(-(t * (z - lse)).sum() / L)
+    dz = (np.exp(z - lse) - t) / L
+    gW3 = dz.T @ h2
+    gb3 = dz.sum(0)
+    dh2 = (dz @ W3) * (a2 > 0)
+    gW2 = dh2.T @ h1
+    gb2 = dh2.sum(0)
+    dh1 = (dh2 @ W2) * (a1 > 0)
+    gW1 = dh1.T @ x
+    gb1 = dh1.sum(0)
+    gx = dh1 @ W1
+    g = np.concatenate([gW1.ravel(), gb1, gW2.ravel(), gb2, gW3.ravel(), gb3])
+    gx_emb = np.zeros_like(x)
+    gx_emb[:, NPAR:NPAR + NEMB] = gx[:, NPAR:NPAR + NEMB]
+    return loss, g, gx_emb
+
+
+def adam(w, m, v, g, step, lr):
+    m = 0.9 * m + 0.1 * g
+    v = 0.999 * v + 0.001 * g * g
+    c1 = 1.0 - 0.9 ** step
+    c2 = 1.0 - 0.999 ** step
+    return w - lr * (m / c1) / (np.sqrt(v / c2) + 1e-8), m, v
+
+
+def cdf_table(pdf):
+    """Inclusive prefix sums (float64, then float32) with the last entry exactly 1."""
+    c = np.cumsum(np.asarray(pdf, np.float64), axis=1)
+    c = c / c[:, -1:]
+    out = c.astype(np.float32)
+    out[:, -1] = 1.0
+    return out

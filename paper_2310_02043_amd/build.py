@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblt.so")
-SOURCES = ["lt_bvh.hip", "lt_trace.hip", "lt_capi.hip"]
+SOURCES = ["lt_bvh.hip", "lt_trace.hip", "lt_proposal.hip", "lt_capi.hip"]
 ARCH = os.environ.get("LT_OFFLOAD_ARCH", "gfx950")
 
 # Path arithmetic must not be contracted into FMAs and division / square root

@@ -79,6 +79,14 @@ struct lt_ctx {
     lt_tuning tune;
     std::vector<GraphEntry> graphs;
 
+    // emission proposal tables (per light, 32 x 32 hemi-octahedral cells)
+    bool has_proposal = false;
+    float* prop_pdf = nullptr;
+    float* prop_cdf = nullptr;
+    float* inv_sigma = nullptr;
+    float* mlp_scratch = nullptr;
+    size_t mlp_scratch_cap = 0;
+
     // kernel timing (events around trace kernels launched outside graphs)
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> t_fwd, t_adj;
@@ -231,7 +239,11 @@ int check_cfg(lt_ctx* c, const lt_trace_cfg* cfg)
         if (cfg->paths_per_layout < c->offs[j + 1] - c->offs[j])
             return fail(c, LT_EINVAL, "paths_per_layout smaller than the number of lights of a layout");
     if (cfg->flags & ~(LT_FLAG_GRAPH | LT_FLAG_PROPOSAL)) return fail(c, LT_EINVAL, "unknown flag");
-    if (cfg->flags & LT_FLAG_PROPOSAL) return fail(c, LT_EINVAL, "no emission proposal loaded");
+    if (cfg->flags & LT_FLAG_PROPOSAL) {
+        if (!c->has_proposal) return fail(c, LT_EINVAL, "no emission proposal loaded");
+        if (!(cfg->alpha_plain > 0.0f && cfg->alpha_plain <= 1.0f))
+            return fail(c, LT_EINVAL, "alpha_plain must be in (0, 1] (defensive mixture)");
+    }
     return ensure_tiles(c, cfg->paths_per_layout);
 }
 
@@ -277,6 +289,12 @@ TraceArgs trace_args(lt_ctx* c, const lt_trace_cfg* cfg)
     a.refill_threshold = c->tune.refill_threshold;
     a.max_steps = 2 * c->n_nodes + 16;
     a.flags = c->d_flags;
+    if (cfg->flags & LT_FLAG_PROPOSAL) {
+        a.prop_pdf = c->prop_pdf;
+        a.prop_cdf = c->prop_cdf;
+        a.alpha_plain = cfg->alpha_plain;
+    }
+    a.inv_sigma = c->inv_sigma;
     return a;
 }
 
@@ -332,6 +350,9 @@ std::vector<uint64_t> make_key(lt_ctx* c, int kind, const lt_trace_cfg* cfg, std
     k.push_back((uint64_t)cfg->paths_per_layout);
     k.push_back((uint64_t)cfg->max_hits);
     k.push_back((uint64_t)cfg->flags);
+    uint32_t ab;
+    memcpy(&ab, &cfg->alpha_plain, 4);
+    k.push_back((uint64_t)ab);
     k.push_back((uint64_t)c->tune.waves_per_block | ((uint64_t)c->tune.xcd_remap << 8) |
                 ((uint64_t)c->tune.refill_threshold << 24) | ((uint64_t)c->tune.lds_depth << 40));
     k.push_back((uint64_t)c->tiles_tp);
@@ -384,6 +405,7 @@ void lt_destroy(lt_ctx* c)
     free_scene(c);
     free_tiles(c);
     hipFree(c->d_si); hipFree(c->d_sf); hipFree(c->d_lights);
+    hipFree(c->prop_pdf); hipFree(c->prop_cdf); hipFree(c->inv_sigma); hipFree(c->mlp_scratch);
     hipFree(c->d_misses); hipFree(c->d_flags); hipFree(c->d_stats);
     hipFree(c->d_objpart); hipFree(c->d_partials); hipFree(c->d_gstack);
     if (c->ev_in) hipEventDestroy(c->ev_in);
@@ -541,13 +563,23 @@ int lt_set_lights(lt_ctx* c, const lt_light_static* h_lights, int32_t n_lights, 
     free_graphs(c);
     free_tiles(c);
     hipFree(c->d_si); hipFree(c->d_sf); hipFree(c->d_lights);
+    hipFree(c->prop_pdf); hipFree(c->prop_cdf); hipFree(c->inv_sigma);
     c->d_si = nullptr; c->d_sf = nullptr; c->d_lights = nullptr;
+    c->prop_pdf = nullptr; c->prop_cdf = nullptr; c->inv_sigma = nullptr;
     c->has_lights = false;
+    c->has_proposal = false;
     HIPCHK(c, hipMalloc(&c->d_si, sizeof(int4) * n_lights));
     HIPCHK(c, hipMalloc(&c->d_sf, sizeof(float4) * n_lights));
     HIPCHK(c, hipMalloc(&c->d_lights, sizeof(DevLight) * n_lights));
     HIPCHK(c, hipMemcpy(c->d_si, si.data(), sizeof(int4) * n_lights, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->d_sf, sf.data(), sizeof(float4) * n_lights, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMalloc(&c->prop_pdf, sizeof(float) * 1024 * (size_t)n_lights));
+    HIPCHK(c, hipMalloc(&c->prop_cdf, sizeof(float) * 1024 * (size_t)n_lights));
+    HIPCHK(c, hipMalloc(&c->inv_sigma, sizeof(float) * 6 * (size_t)n_lights));
+    {
+        std::vector<float> ones(6 * (size_t)n_lights, 1.0f);
+        HIPCHK(c, hipMemcpy(c->inv_sigma, ones.data(), sizeof(float) * ones.size(), hipMemcpyHostToDevice));
+    }
     c->lights.assign(h_lights, h_lights + n_lights);
     c->offs.assign(h_offs, h_offs + n_layouts + 1);
     c->L = n_lights;
@@ -600,7 +632,7 @@ int lt_trace_adjoint(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     int rc = check_cfg(c, cfg);
     if (rc) return rc;
     if (!d_params || !d_dOdE || !d_grad) return fail(c, LT_EINVAL, "NULL device buffer");
-    if (d_bin_hist) return fail(c, LT_EINVAL, "direction histograms need an emission proposal");
+    if (d_bin_hist && ((uintptr_t)d_bin_hist & 15)) return fail(c, LT_EINVAL, "d_bin_hist must be 16-byte aligned");
     HIPCHK(c, hipSetDevice(c->device));
     const long long blocks = trace_blocks(c);
     rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
@@ -608,14 +640,16 @@ int lt_trace_adjoint(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     TraceArgs a = trace_args(c, cfg);
     a.g = d_dOdE;
     a.partials = c->d_partials;
+    a.bin_hist = d_bin_hist;
     const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
     auto body = [&](hipStream_t st) -> hipError_t {
         hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        if (e == hipSuccess && d_bin_hist) e = launch_fill_f32(d_bin_hist, (long long)c->L * 1024, 0.0f, st);
         if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
         if (e == hipSuccess) e = launch_grad_reduce(c->d_partials, c->d_range, c->L, d_grad, st);
         return e;
     };
-    return run_seq(c, graph, make_key(c, 2, cfg, {d_params, d_dOdE, d_grad}), body);
+    return run_seq(c, graph, make_key(c, 2, cfg, {d_params, d_dOdE, d_grad, d_bin_hist}), body);
 }
 
 int lt_record_paths(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int32_t layout, int32_t light,
@@ -658,6 +692,11 @@ int lt_record_paths(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, i
     r.gdepth = std::max(gstack_depth(c), 1);
     r.max_steps = 2 * c->n_nodes + 16;
     r.flags = c->d_flags;
+    if (cfg->flags & LT_FLAG_PROPOSAL) {
+        r.prop_pdf = c->prop_pdf;
+        r.prop_cdf = c->prop_cdf;
+        r.alpha_plain = cfg->alpha_plain;
+    }
     HIPCHK(c, launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->stream));
     HIPCHK(c, launch_record(r, c->tune.lds_depth, c->stream));
     return LT_OK;
@@ -723,6 +762,78 @@ int lt_info_get(const lt_ctx* c, lt_info* out)
                         c->K * 4 + (int64_t)c->gstack_cap * 4 + (int64_t)c->partials_cap * 8;
     out->n_lights = c->L;
     out->n_layouts = c->n_layouts;
+    return LT_OK;
+}
+
+int lt_proposal_set_table(lt_ctx* c, const float* d_pdf, const float* d_cdf)
+{
+    if (!c) return LT_EINVAL;
+    if (!c->has_lights) return fail(c, LT_ESTATE, "no luminaires set");
+    if (!d_pdf || !d_cdf) return fail(c, LT_EINVAL, "NULL device buffer");
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t n = sizeof(float) * 1024 * (size_t)c->L;
+    HIPCHK(c, hipMemcpyAsync(c->prop_pdf, d_pdf, n, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->prop_cdf, d_cdf, n, hipMemcpyDeviceToDevice, c->stream));
+    c->has_proposal = true;
+    return LT_OK;
+}
+
+int lt_proposal_get_table(lt_ctx* c, float* d_pdf, float* d_cdf)
+{
+    if (!c) return LT_EINVAL;
+    if (!c->has_proposal) return fail(c, LT_ESTATE, "no emission proposal loaded");
+    if (!d_pdf || !d_cdf) return fail(c, LT_EINVAL, "NULL device buffer");
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t n = sizeof(float) * 1024 * (size_t)c->L;
+    HIPCHK(c, hipMemcpyAsync(d_pdf, c->prop_pdf, n, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d_cdf, c->prop_cdf, n, hipMemcpyDeviceToDevice, c->stream));
+    return LT_OK;
+}
+
+int lt_proposal_set_scale(lt_ctx* c, const float* d_inv_sigma)
+{
+    if (!c) return LT_EINVAL;
+    if (!c->has_lights) return fail(c, LT_ESTATE, "no luminaires set");
+    if (!d_inv_sigma) return fail(c, LT_EINVAL, "NULL device buffer");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpyAsync(c->inv_sigma, d_inv_sigma, sizeof(float) * 6 * (size_t)c->L, hipMemcpyDeviceToDevice,
+                             c->stream));
+    return LT_OK;
+}
+
+int lt_proposal_mlp_infer(lt_ctx* c, const uint16_t* d_w_bf16, const float* d_x, float* d_logits)
+{
+    if (!c) return LT_EINVAL;
+    if (!c->has_lights) return fail(c, LT_ESTATE, "no luminaires set");
+    if (!d_w_bf16 || !d_x) return fail(c, LT_EINVAL, "NULL device buffer");
+    if (((uintptr_t)d_w_bf16 & 7) || ((uintptr_t)d_x & 3)) return fail(c, LT_EINVAL, "misaligned buffer");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_mlp_infer(d_w_bf16, d_x, c->L, d_logits, c->prop_pdf, c->prop_cdf, c->stream));
+    c->has_proposal = true;
+    return LT_OK;
+}
+
+int lt_proposal_mlp_train(lt_ctx* c, float* d_w, float* d_mw, float* d_vw, uint16_t* d_w_bf16, float* d_x,
+                          float* d_mx, float* d_vx, const float* d_target, int32_t step, float lr, float* d_loss,
+                          float* d_grad_out)
+{
+    if (!c) return LT_EINVAL;
+    if (!c->has_lights) return fail(c, LT_ESTATE, "no luminaires set");
+    if (!d_w || !d_mw || !d_vw || !d_w_bf16 || !d_x || !d_mx || !d_vx || !d_target)
+        return fail(c, LT_EINVAL, "NULL device buffer");
+    if (step < 1) return fail(c, LT_EINVAL, "step counts from 1");
+    if (!(lr > 0.0f) || !isfinite(lr)) return fail(c, LT_EINVAL, "invalid learning rate");
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t need = mlp_train_scratch_floats(c->L);
+    if (need > c->mlp_scratch_cap) {
+        hipFree(c->mlp_scratch);
+        c->mlp_scratch = nullptr;
+        c->mlp_scratch_cap = 0;
+        HIPCHK(c, hipMalloc(&c->mlp_scratch, sizeof(float) * need));
+        c->mlp_scratch_cap = need;
+    }
+    HIPCHK(c, launch_mlp_train(d_w, d_mw, d_vw, d_w_bf16, d_x, d_mx, d_vx, d_target, c->L, step, lr, c->mlp_scratch,
+                               d_loss, d_grad_out, c->stream));
     return LT_OK;
 }
 

@@ -13,6 +13,16 @@ constexpr int kPlocRadius = 16;       // nearest-neighbour window of the BVH bui
 constexpr int kBvhWidth = 4;          // children per node of the traversed tree
 constexpr int kEmptyChild = (int)0x80000000;  // unused child slot of a wide node
 
+// emission-proposal MLP: x [32] -> 64 -> 64 -> 1024 cells
+constexpr int kMlpParams = 6, kMlpEmbed = 16, kMlpIn = 32, kMlpHidden = 64, kMlpBins = 1024;
+constexpr int kMlpOffW1 = 0;                                    // [64][32]
+constexpr int kMlpOffB1 = kMlpOffW1 + kMlpHidden * kMlpIn;      // [64]
+constexpr int kMlpOffW2 = kMlpOffB1 + kMlpHidden;               // [64][64]
+constexpr int kMlpOffB2 = kMlpOffW2 + kMlpHidden * kMlpHidden;  // [64]
+constexpr int kMlpOffW3 = kMlpOffB2 + kMlpHidden;               // [1024][64]
+constexpr int kMlpOffB3 = kMlpOffW3 + kMlpBins * kMlpHidden;    // [1024]
+constexpr int kMlpWeights = kMlpOffB3 + kMlpBins;               // 72832
+
 struct TraceArgs {
     const float4* nodes;
     const float4* tris;
@@ -34,6 +44,12 @@ struct TraceArgs {
     int refill_threshold;
     int max_steps;              // node visits per segment before the segment is abandoned
     unsigned* flags;            // sticky status bits (2 = traversal step limit hit)
+    // emission proposal (one-sample MIS with the plain lobe), may be null
+    const float* prop_pdf;      // [L,1024] bin probabilities
+    const float* prop_cdf;      // [L,1024] inclusive prefix sums
+    float alpha_plain;
+    float* bin_hist;            // adjoint: [L,1024] histogram of |c_r / sigma| (may be null)
+    const float* inv_sigma;     // [L,6]
 };
 
 struct RecordArgs {
@@ -54,6 +70,9 @@ struct RecordArgs {
     int gdepth;
     int max_steps;
     unsigned* flags;
+    const float* prop_pdf;
+    const float* prop_cdf;
+    float alpha_plain;
 };
 
 hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_patch, int n, float pad,
@@ -65,11 +84,18 @@ hipError_t launch_record(const RecordArgs& a, int lds_depth, hipStream_t st);
 hipError_t launch_light_setup(const float* params, const int4* lstat_i, const float4* lstat_f,
                               const long long* npaths, int n_lights, DevLight* out, hipStream_t st);
 hipError_t launch_clear(long long* S, long long n_texels_total, hipStream_t st);
+hipError_t launch_fill_f32(float* p, long long n, float v, hipStream_t st);
 hipError_t launch_finalize(const long long* S, float* E, long long n, unsigned* flags, hipStream_t st);
 hipError_t launch_objective(const float* E, const float* Et, const float* alpha, const float* A, long long K,
                             long long n, float* g, double* partials, double* O, hipStream_t st);
 hipError_t launch_grad_reduce(const double* partials, const int2* tile_range, int n_lights, float* grad,
                               hipStream_t st);
+size_t mlp_train_scratch_floats(int L);
+hipError_t launch_mlp_infer(const uint16_t* wb, const float* x, int L, float* logits, float* pdf, float* cdf,
+                            hipStream_t st);
+hipError_t launch_mlp_train(float* w, float* mw, float* vw, uint16_t* wb, float* x, float* mx, float* vx,
+                            const float* target, int L, int step, float lr, float* scratch, float* loss,
+                            float* grad_out, hipStream_t st);
 hipError_t launch_texel_area(const float* patch_area, const long long* base, int n_patches, long long K,
                              float* A, hipStream_t st);
 

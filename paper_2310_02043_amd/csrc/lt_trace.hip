@@ -155,33 +155,89 @@ __device__ __forceinline__ void start_segment(Trav& s)
     s.l0 = s.l1 = s.l2 = s.l3 = 0;
 }
 
-// Emission (Alg. 1 "generate exitant ray"): origin y, direction, area offsets.
+// Emission (Alg. 1 "generate exitant ray"): origin y, direction, area
+// offsets, flux phi and the emission direction's cell of the hemi-octahedral
+// map (ebin, -1 for point lights).  With a proposal, the direction comes from
+// the plain cos^n lobe with probability alpha and otherwise from the binned
+// proposal (cell by inverse CDF, uniform jitter in the cell), and
+// phi = (P/N) p_plain / (alpha p_plain + (1 - alpha) p_learn).
 __device__ __forceinline__ void emit(const DevLight& L, uint32_t pid, uint32_t stream_id, uint32_t k0, uint32_t k1,
-                                     V3& y, V3& dir, float& au, float& av)
+                                     const float* __restrict__ pdf, const float* __restrict__ cdf, float alpha,
+                                     bool want_bin, V3& y, V3& dir, float& au, float& av, float& phi, int& ebin)
 {
     const U4 r = philox10(pid, stream_id, 0u, 0u, k0, k1);
     const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
     y = v3(L.c[0], L.c[1], L.c[2]);
     au = 0.0f;
     av = 0.0f;
+    phi = L.phi_r;
+    ebin = -1;
     float sp, cp;
     sincos_2pi(u3, sp, cp);
     if (L.type == 0) {
         const float z = 1.0f - 2.0f * u2;
         const float rr = __builtin_sqrtf(fmaxf(0.0f, 1.0f - z * z));
         dir = v3(rr * cp, rr * sp, z);
-    } else {
-        const float ct = u2 > 0.0f ? exp2_c(log2_c(u2) / (L.n + 1.0f)) : 0.0f;
-        const float st = __builtin_sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
-        const float a = st * cp, bb = st * sp;
-        dir = v3((a * L.t[0] + bb * L.b[0]) + ct * L.d[0], (a * L.t[1] + bb * L.b[1]) + ct * L.d[1],
-                 (a * L.t[2] + bb * L.b[2]) + ct * L.d[2]);
-        if (L.type == 2) {
-            au = (u0 - 0.5f) * L.w;
-            av = (u1 - 0.5f) * L.h;
-            y = v3((L.c[0] + au * L.t[0]) + av * L.b[0], (L.c[1] + au * L.t[1]) + av * L.b[1],
-                   (L.c[2] + au * L.t[2]) + av * L.b[2]);
+        return;
+    }
+    float ct = u2 > 0.0f ? exp2_c(log2_c(u2) / (L.n + 1.0f)) : 0.0f;
+    const float st = __builtin_sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+    float a = st * cp, bb = st * sp;
+    if (pdf != nullptr || want_bin) {
+        bool plain = true;
+        float w1 = 0.0f, w2 = 0.0f, w3 = 0.0f;
+        if (pdf != nullptr) {
+            const U4 r1 = philox10(pid, stream_id, 1u, 0u, k0, k1);
+            plain = u24(r1.x) < alpha;
+            w1 = u24(r1.y);
+            w2 = u24(r1.z);
+            w3 = u24(r1.w);
         }
+        float pl3;
+        if (plain) {
+            const float s = (fabsf(a) + fabsf(bb)) + ct;
+            const float xp = a / s, yp = bb / s;
+            int iu = (int)__builtin_floorf(((xp + yp) + 1.0f) * 16.0f);
+            int iv = (int)__builtin_floorf(((xp - yp) + 1.0f) * 16.0f);
+            iu = iu < 0 ? 0 : (iu > 31 ? 31 : iu);
+            iv = iv < 0 ? 0 : (iv > 31 ? 31 : iv);
+            ebin = iv * 32 + iu;
+            pl3 = 1.0f / ((s * s) * s);
+        } else {
+            int lo = 0, hi = 1023;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (w1 < cdf[mid]) hi = mid;
+                else lo = mid + 1;
+            }
+            ebin = lo;
+            const float uu = -1.0f + ((float)(lo & 31) + w2) * 0.0625f;
+            const float vv = -1.0f + ((float)(lo >> 5) + w3) * 0.0625f;
+            const float xp = (uu + vv) * 0.5f, yp = (uu - vv) * 0.5f;
+            const float zp = (1.0f - fabsf(xp)) - fabsf(yp);
+            const float nrm = __builtin_sqrtf((xp * xp + yp * yp) + zp * zp);
+            const float inv = 1.0f / nrm;
+            a = xp * inv;
+            bb = yp * inv;
+            ct = zp * inv;
+            pl3 = (nrm * nrm) * nrm;
+        }
+        if (pdf != nullptr) {
+            float pw = 1.0f;
+            if (L.n != 0.0f) pw = ct > 0.0f ? exp2_c(L.n * log2_c(ct)) : 0.0f;
+            const float p_plain = ((L.n + 1.0f) * (float)0.15915494309189533577) * pw;
+            const float p_learn = (pdf[ebin] * 512.0f) * pl3;
+            const float q = alpha * p_plain + (1.0f - alpha) * p_learn;
+            phi = q > 0.0f ? phi * (p_plain / q) : 0.0f;
+        }
+    }
+    dir = v3((a * L.t[0] + bb * L.b[0]) + ct * L.d[0], (a * L.t[1] + bb * L.b[1]) + ct * L.d[1],
+             (a * L.t[2] + bb * L.b[2]) + ct * L.d[2]);
+    if (L.type == 2) {
+        au = (u0 - 0.5f) * L.w;
+        av = (u1 - 0.5f) * L.h;
+        y = v3((L.c[0] + au * L.t[0]) + av * L.b[0], (L.c[1] + au * L.t[1]) + av * L.b[1],
+               (L.c[2] + au * L.t[2]) + av * L.b[2]);
     }
 }
 
@@ -334,16 +390,19 @@ __global__ void __launch_bounds__(WPB * 64) k_trace(TraceArgs a)
         const uint32_t first = (uint32_t)ti.y;
         const int count = ti.z;
         const uint32_t stream_id = ((uint32_t)ti.w << 16) | (uint32_t)L.l_local;
-        const float phi_r = L.phi_r;
         long long* S = ADJ ? nullptr : a.S + (long long)ti.w * a.K;
         const float* g = ADJ ? a.g + (long long)ti.w * a.K : nullptr;
+        const bool prop_on = a.prop_pdf != nullptr && L.type != 0;
+        const float* pdf = prop_on ? a.prop_pdf + 1024 * (long long)ti.x : nullptr;
+        const float* cdf = prop_on ? a.prop_cdf + 1024 * (long long)ti.x : nullptr;
+        float* hist = (ADJ && a.bin_hist != nullptr && L.type != 0) ? a.bin_hist + 1024 * (long long)ti.x : nullptr;
 
         int next = 0;          // paths of this tile handed out so far (uniform)
         bool alive = false;    // lane holds a path
         bool trav = false;     // lane is traversing its current segment
         uint32_t pid = 0;
-        int h = 0, skip = -1;
-        float T = 1.0f, s_r = 0.0f, au = 0.0f, av = 0.0f;
+        int h = 0, skip = -1, ebin = -1;
+        float T = 1.0f, s_r = 0.0f, au = 0.0f, av = 0.0f, phi_r = 0.0f;
         float dphi[6] = {0, 0, 0, 0, 0, 0};
         double acc[6] = {0, 0, 0, 0, 0, 0};
         unsigned miss = 0, n_seg = 0, n_nodes = 0, n_tris = 0, n_hits = 0;
@@ -363,7 +422,8 @@ __global__ void __launch_bounds__(WPB * 64) k_trace(TraceArgs a)
                 if (need && slot < count) {
                     pid = first + (uint32_t)slot;
                     V3 y, dir;
-                    emit(L, pid, stream_id, a.key0, a.key1, y, dir, au, av);
+                    emit(L, pid, stream_id, a.key0, a.key1, pdf, cdf, a.alpha_plain, hist != nullptr, y, dir, au, av,
+                         phi_r, ebin);
                     set_ray(r, y, dir);
                     start_segment(s);
                     alive = true;
@@ -431,8 +491,17 @@ __global__ void __launch_bounds__(WPB * 64) k_trace(TraceArgs a)
                 }
                 if (end_path) {
                     if (ADJ && h >= 1) {
+                        float m2 = 0.0f;
 #pragma unroll
-                        for (int c = 0; c < 6; ++c) acc[c] += (double)(s_r * dphi[c]);
+                        for (int c = 0; c < 6; ++c) {
+                            const float cr = s_r * dphi[c];
+                            acc[c] += (double)cr;
+                            if (hist) {
+                                const float z = cr * a.inv_sigma[6 * ti.x + c];
+                                m2 = m2 + z * z;
+                            }
+                        }
+                        if (hist && ebin >= 0) atomicAdd(hist + ebin, __builtin_sqrtf(m2));
                     }
                     alive = false;
                 }
@@ -487,8 +556,12 @@ __global__ void __launch_bounds__(256) k_record(RecordArgs a)
             a.texel[idx * a.max_hits + hh] = -1;
         }
         V3 y, dir;
-        float au, av;
-        emit(L, pid, a.stream_id, a.key0, a.key1, y, dir, au, av);
+        float au, av, phi_r;
+        int ebin;
+        const bool prop_on = a.prop_pdf != nullptr && L.type != 0;
+        emit(L, pid, a.stream_id, a.key0, a.key1, prop_on ? a.prop_pdf + 1024 * (long long)a.gl : nullptr,
+             prop_on ? a.prop_cdf + 1024 * (long long)a.gl : nullptr, a.alpha_plain, false, y, dir, au, av, phi_r,
+             ebin);
         Ray r;
         set_ray(r, y, dir);
         int skip = -1;
@@ -514,7 +587,7 @@ __global__ void __launch_bounds__(256) k_record(RecordArgs a)
                 if (h == 1) {
                     float dl[6];
                     first_hit_dlog(L, hi.x, v3(r.ox, r.oy, r.oz), hi.no, au, av, dl);
-                    for (int c = 0; c < 6; ++c) dphi[c] = L.phi_r * dl[c];
+                    for (int c = 0; c < 6; ++c) dphi[c] = phi_r * dl[c];
                 }
             }
             if (h >= a.max_hits) break;
@@ -568,6 +641,12 @@ __global__ void k_light_setup(const float* __restrict__ params, const int4* __re
     L.pad0 = 0;
     L.pad1 = 0;
     out[l] = L;
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, long long n, float v)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
 __global__ void k_clear(long long* __restrict__ S, long long n)
@@ -728,6 +807,12 @@ hipError_t launch_light_setup(const float* params, const int4* si, const float4*
                               int n_lights, DevLight* out, hipStream_t st)
 {
     k_light_setup<<<nblocks(n_lights, 64, 1 << 20), 64, 0, st>>>(params, si, sf, npaths, n_lights, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* p, long long n, float v, hipStream_t st)
+{
+    k_fill_f32<<<nblocks(n, 256, 4096), 256, 0, st>>>(p, n, v);
     return hipGetLastError();
 }
 

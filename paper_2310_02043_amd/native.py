@@ -22,8 +22,11 @@ EXPORTED = [
     "lt_create", "lt_destroy", "lt_last_error", "lt_set_stream", "lt_sync", "lt_scene_upload",
     "lt_set_lights", "lt_trace_forward", "lt_objective", "lt_trace_adjoint", "lt_record_paths",
     "lt_trace_stats", "lt_get_tuning", "lt_set_tuning", "lt_autotune", "lt_info_get", "lt_set_timing",
-    "lt_timing_read",
+    "lt_timing_read", "lt_proposal_set_table", "lt_proposal_get_table", "lt_proposal_set_scale",
+    "lt_proposal_mlp_infer",
+    "lt_proposal_mlp_train",
 ]
+MLP_WEIGHTS, MLP_IN, MLP_BINS = 72832, 32, 1024
 
 PATCH_ITEMSIZE = 88
 LIGHT_ITEMSIZE = 20
@@ -86,6 +89,11 @@ def load():
     L.lt_autotune.argtypes = [P, C.POINTER(TraceCfg), P, P, P, P, P, C.c_char_p, C.POINTER(C.c_float)]
     L.lt_info_get.argtypes = [P, C.POINTER(Info)]
     L.lt_set_timing.argtypes = [P, C.c_int]
+    L.lt_proposal_set_table.argtypes = [P, P, P]
+    L.lt_proposal_set_scale.argtypes = [P, P]
+    L.lt_proposal_get_table.argtypes = [P, P, P]
+    L.lt_proposal_mlp_infer.argtypes = [P, P, P, P]
+    L.lt_proposal_mlp_train.argtypes = [P, P, P, P, P, P, P, P, P, I32, C.c_float, P, P]
     L.lt_timing_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(I32), C.POINTER(C.c_double), C.POINTER(I32)]
     for name in EXPORTED:
         if name not in ("lt_destroy", "lt_last_error"):
@@ -262,6 +270,47 @@ class Context:
         self._check(self.lib.lt_autotune(self.h, C.byref(cfg), _ptr(params), _ptr(S), _ptr(E), _ptr(dOdE),
                                          _ptr(grad), cp, C.byref(best)))
         return float(best.value)
+
+    # -- emission proposal ---------------------------------------------------
+    def proposal_set_table(self, pdf, cdf):
+        torch = self._torch
+        self._dev(pdf, torch.float32, (self.n_lights, MLP_BINS))
+        self._dev(cdf, torch.float32, (self.n_lights, MLP_BINS))
+        self._stream()
+        self._check(self.lib.lt_proposal_set_table(self.h, _ptr(pdf), _ptr(cdf)))
+
+    def proposal_get_table(self):
+        torch = self._torch
+        pdf = torch.empty((self.n_lights, MLP_BINS), dtype=torch.float32, device=f"cuda:{self.device}")
+        cdf = torch.empty_like(pdf)
+        self._stream()
+        self._check(self.lib.lt_proposal_get_table(self.h, _ptr(pdf), _ptr(cdf)))
+        return pdf, cdf
+
+    def proposal_set_scale(self, inv_sigma):
+        self._dev(inv_sigma, self._torch.float32, (self.n_lights, 6))
+        self._stream()
+        self._check(self.lib.lt_proposal_set_scale(self.h, _ptr(inv_sigma)))
+
+    def mlp_infer(self, w_bf16, x, logits=None):
+        torch = self._torch
+        self._dev(w_bf16, torch.int16, (MLP_WEIGHTS,))
+        self._dev(x, torch.float32, (self.n_lights, MLP_IN))
+        self._stream()
+        self._check(self.lib.lt_proposal_mlp_infer(self.h, _ptr(w_bf16), _ptr(x), _ptr(logits)))
+
+    def mlp_train(self, w, mw, vw, w_bf16, x, mx, vx, target, step, lr, loss=None, grad_out=None):
+        torch = self._torch
+        for t in (w, mw, vw):
+            self._dev(t, torch.float32, (MLP_WEIGHTS,))
+        self._dev(w_bf16, torch.int16, (MLP_WEIGHTS,))
+        for t in (x, mx, vx):
+            self._dev(t, torch.float32, (self.n_lights, MLP_IN))
+        self._dev(target, torch.float32, (self.n_lights, MLP_BINS))
+        self._stream()
+        self._check(self.lib.lt_proposal_mlp_train(self.h, _ptr(w), _ptr(mw), _ptr(vw), _ptr(w_bf16), _ptr(x),
+                                                   _ptr(mx), _ptr(vx), _ptr(target), int(step), float(lr),
+                                                   _ptr(loss), _ptr(grad_out)))
 
     def set_timing(self, enable: bool):
         self._check(self.lib.lt_set_timing(self.h, 1 if enable else 0))

@@ -1,0 +1,88 @@
+"""Learned emission proposal driver (an extension beyond the paper).
+
+Holds the proposal network's FP32 master weights, their BF16 copy, Adam
+moments and the per-light embeddings on the device, and drives the two
+kernels of liblt: inference (BF16 MFMA) into the sampler's cell tables, and a
+training step toward the cells' share of the adjoint gradient magnitude that
+the tracer's adjoint pass histograms (lt_trace_adjoint with d_bin_hist).
+The sampler mixes the learned cells with the plain lobe (probability
+alpha_plain) under one-sample MIS, so gradients stay unbiased; point lights
+keep the plain sampler.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from .native import MLP_BINS, MLP_IN, MLP_WEIGHTS
+
+HID, NPAR, NEMB = 64, 6, 16
+_LAYERS = [(HID, MLP_IN), (HID,), (HID, HID), (HID,), (MLP_BINS, HID), (MLP_BINS,)]
+
+
+def _bf16_bits(a: np.ndarray) -> np.ndarray:
+    """float32 -> bfloat16 bit patterns, round to nearest even."""
+    u = np.ascontiguousarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    return (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) & 0xFFFF).astype(np.uint16)
+
+
+class LearnedProposal:
+    def __init__(self, ctx, param_lo, param_hi, seed: int = 0, lr: float = 2e-3, alpha_plain: float = 0.2,
+                 sigma_decay: float = 0.9):
+        self.ctx = ctx
+        self.L = ctx.n_lights
+        self.alpha_plain = float(alpha_plain)
+        self.lr = float(lr)
+        self.step = 0
+        self.sigma_decay = sigma_decay
+        dev = torch.device("cuda", ctx.device)
+        rng = np.random.default_rng(seed)
+        parts = []
+        for shp in _LAYERS:
+            if len(shp) == 2:
+                parts.append(rng.normal(0.0, np.sqrt(2.0 / shp[1]), shp).ravel())
+            else:
+                parts.append(np.zeros(shp))
+        w = np.concatenate(parts).astype(np.float32)
+        w[-MLP_BINS - MLP_BINS * HID:-MLP_BINS] *= 0.1   # start close to uniform cells
+        assert w.size == MLP_WEIGHTS
+        self.w = torch.tensor(w, device=dev)
+        self.mw = torch.zeros_like(self.w)
+        self.vw = torch.zeros_like(self.w)
+        self.wb = torch.tensor(_bf16_bits(w).view(np.int16), device=dev)
+        x = np.zeros((self.L, MLP_IN), np.float32)
+        x[:, NPAR:NPAR + NEMB] = rng.normal(0.0, 0.5, (self.L, NEMB))
+        self.x = torch.tensor(x, device=dev)
+        self.mx = torch.zeros_like(self.x)
+        self.vx = torch.zeros_like(self.x)
+        self.lo = torch.tensor(np.asarray(param_lo, np.float32), device=dev)
+        self.hi = torch.tensor(np.asarray(param_hi, np.float32), device=dev)
+        self.sig2 = None
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.hist = torch.zeros((self.L, MLP_BINS), dtype=torch.float32, device=dev)
+
+    def refresh(self, params):
+        """Normalise the luminaire parameters into x and rebuild the sampler tables."""
+        with torch.no_grad():
+            self.x[:, :NPAR] = 2.0 * (params.detach() - self.lo) / (self.hi - self.lo) - 1.0
+        self.ctx.mlp_infer(self.wb, self.x)
+
+    def update_scale(self, grad):
+        """Running RMS of each light's gradient components (the histogram's units)."""
+        g2 = grad.detach().float() ** 2
+        self.sig2 = g2 if self.sig2 is None else self.sigma_decay * self.sig2 + (1 - self.sigma_decay) * g2
+        inv = 1.0 / torch.sqrt(self.sig2 + 1e-30)
+        inv = torch.where(torch.isfinite(inv), inv, torch.zeros_like(inv)).contiguous()
+        self.ctx.proposal_set_scale(inv)
+
+    def train(self, hist=None, steps: int = 4):
+        """Fit the cell distribution to the normalised adjoint histogram."""
+        h = (self.hist if hist is None else hist).double()
+        tot = h.sum(1, keepdim=True)
+        target = torch.where(tot > 0, h / tot.clamp_min(1e-300), torch.full_like(h, 1.0 / MLP_BINS))
+        target = target.float().contiguous()
+        for _ in range(steps):
+            self.step += 1
+            self.ctx.mlp_train(self.w, self.mw, self.vw, self.wb, self.x, self.mx, self.vx, target, self.step,
+                               self.lr, loss=self.loss)
+        return float(self.loss.item())

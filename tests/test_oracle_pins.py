@@ -454,3 +454,112 @@ def test_adjoint_vs_fd_common_random_numbers(oracle_lib):
         assert abs(D[:, c].mean()) < 4 * se[c] + 1e-3 * gm[c], (c, D[:, c].mean(), se[c])
         if gm[c] > 0.1 * gm.max():
             assert abs(D[:, c].mean()) < 0.03 * gm[c]
+
+
+# --------------------------------------------------------------------------
+# emission proposal: MIS unbiasedness, hemi-octahedral Jacobian, MLP backprop
+# --------------------------------------------------------------------------
+
+def test_hemi_octahedral_cells_cover_the_hemisphere():
+    """Sum over cells of the cell solid angle (du dv / (2 |p|^3)) = 2 pi."""
+    g = (np.arange(512) + 0.5) / 512 * 2 - 1
+    U, V = np.meshgrid(g, g)
+    xp, yp = (U + V) / 2, (U - V) / 2
+    zp = 1 - np.abs(xp) - np.abs(yp)
+    dA = (2.0 / 512) ** 2
+    omega = np.sum(dA / (2 * np.sqrt(xp ** 2 + yp ** 2 + zp ** 2) ** 3))
+    assert abs(omega / (2 * np.pi) - 1) < 1e-4
+    assert zp.min() >= 0
+
+
+def _random_table(rng, L, peaky=3.0):
+    logits = rng.normal(0, peaky, (L, 1024))
+    p = np.exp(logits - logits.max(1, keepdims=True))
+    return (p / p.sum(1, keepdims=True)).astype(np.float32)
+
+
+@pytest.mark.parametrize("kind", [SPOT, RECT])
+def test_proposal_direct_gradient_unbiased(oracle_lib, kind):
+    """With a random proposal table and alpha = 0.2 the first-hit gradient is
+    still the quadrature derivative (plane, B = 1)."""
+    from oracle.proposal import cdf_table
+    half, res, N = 3.0, 24, 1 << 18
+    n = 2.5
+    size = (0.7, 0.4) if kind == RECT else (0, 0)
+    p = np.array([0.3, -0.2, 1.4, 0.3, -0.2, 40.0])
+    sc = li.plane_scene(half=half, res=res)
+    lights = make_lights([kind], [n], [size], [0], [p])
+    A = float(sc.texel_area()[0])
+    rng = np.random.default_rng(17)
+    g = rng.uniform(-1, 1, sc.n_texels).astype(np.float32)
+    pdf = _random_table(rng, 1)
+    prop = oracle_lib.Proposal(pdf, cdf_table(pdf), 0.2)
+
+    def expected_E(pp):
+        return cf.plane_hit_probability(kind, n, pp, size, half, res, q_tex=5, q_light=5) * pp[5] / A
+
+    ref = np.zeros(6)
+    for c in range(6):
+        h = 1e-4
+        pp, pm = p.copy(), p.copy()
+        pp[c] += h
+        pm[c] -= h
+        ref[c] = np.dot(g.astype(np.float64), (expected_E(pp) - expected_E(pm)) / (2 * h))
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    _, _, contrib = oracle_lib.record(osc, ol, lights.params, 0xD7, N, 1, 0, 0, 0, N, g[None], proposal=prop)
+    c64 = contrib.astype(np.float64)
+    est, sigma = c64.sum(0), c64.std(0) * math.sqrt(N)
+    for c in range(6):
+        assert abs(est[c] - ref[c]) < 4.5 * sigma[c] + 1e-3 * abs(ref[c]), (c, est[c], ref[c], sigma[c])
+    # texel expectation: the irradiance of the whole plane is unchanged
+    S, _ = oracle_lib.forward(osc, ol, lights.params, 0xD8, N, 1, proposal=prop)
+    tot = float(oracle_lib.fixed_to_float(S)[0].astype(np.float64).sum() * A)
+    tot_ref = float(expected_E(p).sum() * A)
+    assert abs(tot / tot_ref - 1) < 0.02
+
+
+def test_proposal_histogram_signal(oracle_lib):
+    """The adjoint histogram sums |c_r * inv_sigma| by emission cell: with one
+    path its total equals that path's contribution norm."""
+    from oracle.proposal import cdf_table
+    c1 = li.box_room()
+    sc, lights = c1["scene"], c1["lights"]
+    rng = np.random.default_rng(2)
+    pdf = _random_table(rng, 1)
+    inv_sigma = rng.uniform(0.5, 2.0, (1, 6)).astype(np.float32)
+    prop = oracle_lib.Proposal(pdf, cdf_table(pdf), 0.2, inv_sigma=inv_sigma, with_hist=True)
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    g = rng.normal(size=(1, sc.n_texels)).astype(np.float32)
+    N = 1 << 12
+    grad, _ = oracle_lib.adjoint(osc, ol, lights.params, 9, N, 3, g, proposal=prop)
+    hist_total = float(prop.hist.sum())
+    _, _, contrib = oracle_lib.record(osc, ol, lights.params, 9, N, 3, 0, 0, 0, N, g, proposal=prop)
+    norms = np.sqrt(((contrib.astype(np.float64) * inv_sigma) ** 2).sum(1))
+    assert abs(hist_total / norms.sum() - 1) < 1e-5
+    assert np.allclose(contrib.astype(np.float64).sum(0), grad[0], rtol=1e-9, atol=1e-12)
+
+
+def test_mlp_backprop_matches_finite_differences():
+    from oracle import proposal as op
+    rng = np.random.default_rng(3)
+    L = 5
+    w = rng.normal(0, 0.2, op.N_WEIGHTS)
+    x = np.zeros((L, op.IN))
+    x[:, :op.NPAR + op.NEMB] = rng.normal(0, 1, (L, op.NPAR + op.NEMB))
+    t = rng.dirichlet(np.ones(op.BINS), L)
+    loss, g, gx = op.loss_and_grad(w, x, t)
+    for k in list(rng.choice(op.N_WEIGHTS, 25, replace=False)) + [op.OFF_B1 + 3, op.OFF_B3 + 7]:
+        h = 1e-6
+        wp, wm = w.copy(), w.copy()
+        wp[k] += h
+        wm[k] -= h
+        fd = (op.loss_and_grad(wp, x, t)[0] - op.loss_and_grad(wm, x, t)[0]) / (2 * h)
+        assert abs(fd - g[k]) < 1e-6 + 1e-5 * abs(g[k])
+    for (r, c) in [(0, 6), (2, 13), (4, 21)]:
+        xp, xm = x.copy(), x.copy()
+        xp[r, c] += 1e-6
+        xm[r, c] -= 1e-6
+        fd = (op.loss_and_grad(w, xp, t)[0] - op.loss_and_grad(w, xm, t)[0]) / 2e-6
+        assert abs(fd - gx[r, c]) < 1e-6 + 1e-5 * abs(gx[r, c])
+    # a softmax cross-entropy lower bound: loss >= entropy of the target
+    assert loss >= float(-(t * np.log(t)).sum() / L) - 1e-9
