@@ -93,6 +93,96 @@ def cpu_baseline(scene, lights, seed, ppl, B, target_seconds):
                       f"{B} hits, forward+adjoint, {dt2:.1f} s)"}
 
 
+def proposal_study(ctx, wl, N, seeds=32, ref_runs=48, train_iters=30, alpha=0.2, train_every=4):
+    """Gradient error x time of the adjoint pass, learned proposal vs plain.
+
+    The luminaires sit at their perturbed initial parameters, the target
+    irradiance comes from the hidden ground-truth parameters, and the adjoint
+    source g = dO/dE is fixed from a 2^28-path forward pass.  The reference
+    gradient averages ref_runs plain adjoint passes of 2^28 paths.  The
+    proposal is trained online on the adjoint pass's own direction histograms
+    (train_iters passes of 2^24 paths) and then frozen; each estimator runs
+    `seeds` independent N-path adjoint passes.  eps = |g_hat - g_ref| /
+    |g_ref|; eps^2 * t is independent of N for an unbiased estimator, so the
+    ratio learned / plain is the time ratio at equal relative error.  The
+    learned form's time per gradient is its adjoint pass plus, amortised over
+    `train_every` optimisation steps, the histogram it accumulates for
+    training and the network's training + inference."""
+    import torch
+    from paper_2310_02043_amd.proposal import LearnedProposal
+    lights, B = wl["lights"], wl["max_hits"]
+    dev = "cuda:0"
+    p0 = torch.tensor(lights.params, device=dev)
+    pt = torch.tensor(wl["params_target"], device=dev)
+    big = 1 << 28
+    Et, _ = ctx.trace_forward(pt, ctx.cfg(0x7A11, big, B))
+    Et = Et.clone()
+    E0, _ = ctx.trace_forward(p0, ctx.cfg(0x7A12, big, B))
+    _, g = ctx.objective(E0, Et)
+    g = g.clone()
+    ref = torch.zeros((lights.n_lights, 6), dtype=torch.float64, device=dev)
+    for s in range(ref_runs):
+        ref += ctx.trace_adjoint(p0, g, ctx.cfg(0x10000 + s, big, B)).double()
+    ref /= ref_runs
+    unit = ref.pow(2).mean(0).sqrt()      # per-parameter RMS: a unit-free second error norm
+
+    def errs(gh):
+        e = gh.double() - ref
+        return float(e.norm() / ref.norm()), float((e / unit).norm() / (ref / unit).norm())
+
+    lp = LearnedProposal(ctx, [0, 0, 2.5, -0.6, -0.6, 0], [30, 20, 3.0, 0.6, 0.6, 80], alpha_plain=alpha,
+                         lobe_n=lights.static["lobe_n"])
+    lp.refresh(p0)
+    losses = []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for it in range(train_iters):
+        gr = ctx.trace_adjoint(p0, g, ctx.cfg(0x20000 + it, 1 << 24, B, proposal=True, alpha_plain=alpha),
+                               bin_hist=lp.hist)
+        lp.update_scale(gr)
+        ev0.record()     # proposal upkeep: 4 training steps + inference
+        losses.append(lp.train(steps=4))
+        lp.refresh(p0)
+        ev1.record()
+    torch.cuda.synchronize()
+    upkeep_ms = ev0.elapsed_time(ev1)
+
+    def timed(prop, hist, seed0, n):
+        ctx.trace_adjoint(p0, g, ctx.cfg(1, N, B, proposal=prop, alpha_plain=alpha), bin_hist=hist)
+        torch.cuda.synchronize()
+        ctx.timing_read()
+        ctx.set_timing(True)
+        ee = [errs(ctx.trace_adjoint(p0, g, ctx.cfg(seed0 + s, N, B, proposal=prop, alpha_plain=alpha),
+                                     bin_hist=hist)) for s in range(n)]
+        torch.cuda.synchronize()
+        ctx.set_timing(False)
+        _, _, adj_ms, na = ctx.timing_read()
+        return np.asarray(ee), adj_ms / max(na, 1)
+
+    e_pl, t_pl = timed(False, None, 0x30000, seeds)
+    e_le, t_le = timed(True, None, 0x40000, seeds)
+    _, t_hist = timed(True, lp.hist, 0x50000, 4)
+    t_learn = t_le + (max(t_hist - t_le, 0.0) + upkeep_ms) / train_every
+    e2_pl, e2_le = (e_pl ** 2).mean(0), (e_le ** 2).mean(0)
+    rng = np.random.default_rng(0)
+    bs = [(e_le[rng.integers(0, seeds, seeds), 0] ** 2).mean() / (e_pl[rng.integers(0, seeds, seeds), 0] ** 2).mean()
+          for _ in range(2000)]
+    ratio = e2_le[0] * t_learn / (e2_pl[0] * t_pl)
+    return {"workload": "office, adjoint pass at the perturbed initial luminaires", "paths": N, "seeds": seeds,
+            "alpha_plain": alpha, "reference": f"mean of {ref_runs} plain passes x 2^28 paths",
+            "train_iters": train_iters, "train_paths": 1 << 24,
+            "train_loss": [round(losses[0], 4), round(losses[-1], 4)], "train_every": train_every,
+            "plain": {"adjoint_ms": round(t_pl, 3), "eps": round(float(e_pl[:, 0].mean()), 6),
+                      "eps2": float(e2_pl[0]), "eps2_unit_norm": float(e2_pl[1])},
+            "learned": {"adjoint_ms": round(t_le, 3), "adjoint_with_histogram_ms": round(t_hist, 3),
+                        "proposal_upkeep_ms": round(upkeep_ms, 3), "ms_per_gradient": round(t_learn, 3),
+                        "eps": round(float(e_le[:, 0].mean()), 6), "eps2": float(e2_le[0]),
+                        "eps2_unit_norm": float(e2_le[1])},
+            "variance_ratio": round(float(e2_le[0] / e2_pl[0]), 4),
+            "variance_ratio_90ci": [round(float(np.percentile(bs, 5)), 4), round(float(np.percentile(bs, 95)), 4)],
+            "eps2_t_ratio": round(float(ratio), 4),
+            "eps2_t_ratio_unit_norm": round(float(e2_le[1] * t_learn / (e2_pl[1] * t_pl)), 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +194,8 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="run the launch autotuner before timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-proposal-study", action="store_true",
+                    help="skip the learned-proposal gradient error x time comparison (office only)")
     ap.add_argument("--tuning", type=str, default="", help="k=v,... launch tuning override")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device 3 times (HBM counter calibration)")
@@ -241,6 +333,10 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(scene, lights, seed, N, B, args.cpu_seconds)
+    if args.workload == "office" and not args.no_proposal_study:
+        log("learned proposal vs plain: gradient error x time ...")
+        out["grad_error_time"] = proposal_study(ctx, wl, N)
+        log("proposal study", json.dumps(out["grad_error_time"]))
     if args.workload != "office":
         out["metric"] = METRIC + f" [{args.workload}]"
     print(json.dumps(out), flush=True)

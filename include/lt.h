@@ -184,14 +184,25 @@ int lt_trace_stats(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, 
  * from the cells otherwise, with Phi_r = (P/N) p_plain / q, q = alpha p_plain
  * + (1 - alpha) p_learn (one-sample MIS, unbiased for alpha > 0).  Point
  * lights always use the plain sampler.  d_pdf, d_cdf [L,1024] f32 (cdf =
- * inclusive prefix sums of pdf) are copied into the context. */
+ * inclusive prefix sums of pdf, non-decreasing, last entry 1) are copied into
+ * the context, which also derives its inverse-CDF guide entries from d_cdf.
+ * A learned sample takes the first cell b with u < cdf[b] (the last cell when
+ * none); a table that is not non-decreasing gives unspecified (in-range)
+ * cells. */
 int lt_proposal_set_table(lt_ctx* ctx, const float* d_pdf, const float* d_cdf);
 /* Copy the context's current proposal tables out (d_pdf, d_cdf [L,1024]). */
 int lt_proposal_get_table(lt_ctx* ctx, float* d_pdf, float* d_cdf);
 
 /* Per-light scale of the adjoint histogram signal: the adjoint pass adds
- * |c_r * inv_sigma|_2 of every path's gradient contribution c_r into
- * d_bin_hist[light][cell of its emission direction].  d_inv_sigma [L,6] f32. */
+ * |c_r * inv_sigma|_2^2 * q / (512 |p|^3) of every path's gradient
+ * contribution c_r into d_bin_hist[light][cell of its emission direction],
+ * with q the solid-angle density the direction was drawn from (the mixture
+ * with a proposal, the plain lobe otherwise) and p its point on the
+ * octahedron.  Per cell b this estimates A_b / N independently of the
+ * sampler, where A_b integrates the second moment of the scaled integrand
+ * over the cell against d(omega) / (512 |p|^3); a sampler drawing cell b with
+ * probability pi_b (uniform in (u, v) within it) has variance sum_b A_b / pi_b,
+ * least for pi_b proportional to sqrt(A_b).  d_inv_sigma [L,6] f32. */
 int lt_proposal_set_scale(lt_ctx* ctx, const float* d_inv_sigma);
 
 /* The proposal network: per light x [32] = 6 normalised parameters, a 16-d

@@ -233,7 +233,11 @@ typedef struct {
     const float* cdf;        /* inclusive prefix sums of pdf */
     float alpha;             /* probability of the plain lobe */
     const float* inv_sigma;  /* [L,6] scale of the histogram signal (adjoint) */
-    double* hist;            /* [L,1024] adjoint histogram (adjoint, may be NULL) */
+    double* hist;            /* [L,1024] adjoint histogram (adjoint, may be NULL): per
+                              * path, |c_r * inv_sigma|^2 * q / (512 |p|^3) into
+                              * its emission cell (q: the mixture density of
+                              * the emitted direction, |p|: the norm of its
+                              * point on the octahedron) */
 } or_proposal;
 
 static float dot3(const float* a, const float* b) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
@@ -547,6 +551,7 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
     const or_proposal* prop = (prop_in && prop_in->pdf && L->type != 0) ? prop_in : NULL;
     float phi_r = L->phi_r;
     int ebin = -1;
+    float wq = 0.0f;
     float u[4];
     draw4(seed, i, stream, 0u, u);
     /* emission: origin y, direction w0 (Alg. 1 "generate exitant ray") */
@@ -612,6 +617,8 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
             float p_learn = (pdf[ebin] * 512.0f) * pl3;
             float q = prop->alpha * p_plain + (1.0f - prop->alpha) * p_learn;
             phi_r = q > 0.0f ? phi_r * (p_plain / q) : 0.0f;
+            /* the sampling density over the (u, v) measure of the cell */
+            wq = q / (512.0f * pl3);
         }
         for (int c = 0; c < 3; ++c) dir[c] = (a * L->t[c] + bb * L->b[c]) + ct * L->d[c];
         if (L->type == 2) {
@@ -709,7 +716,7 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
                 float z = cr[c] * is[c];
                 m2 = m2 + z * z;
             }
-            double v = (double)sqrtf(m2);
+            double v = (double)(m2 * wq);
 #ifdef _OPENMP
 #pragma omp atomic
 #endif

@@ -34,9 +34,17 @@ class LightTracer:
         self.graph = bool(graph)
         self._S = None
         self.device = torch.device("cuda", device)
+        # learned emission proposal (a LearnedProposal); it is trained on the
+        # adjoint's gradient contributions and used by the adjoint pass, and by
+        # the forward pass only if proposal_forward is set
+        self.proposal = None
+        self.alpha_plain = 0.2
+        self.proposal_forward = False
 
-    def cfg(self, seed=None):
-        return self.ctx.cfg(self.seed if seed is None else seed, self.paths_per_layout, self.max_hits, graph=self.graph)
+    def cfg(self, seed=None, adjoint=False):
+        prop = self.proposal is not None and (adjoint or self.proposal_forward)
+        return self.ctx.cfg(self.seed if seed is None else seed, self.paths_per_layout, self.max_hits,
+                            graph=self.graph, proposal=prop, alpha_plain=self.alpha_plain)
 
     def adjoint_seed(self, seed=None):
         s = self.seed if seed is None else seed
@@ -67,7 +75,10 @@ class LightTraceFn(torch.autograd.Function):
         (p,) = fctx.saved_tensors
         tracer = fctx.tracer
         g = grad_E.contiguous().float()
-        grad = tracer.ctx.trace_adjoint(p, g, tracer.cfg(tracer.adjoint_seed(fctx.seed)))
+        prop = tracer.proposal
+        hist = prop.hist if prop is not None and prop.collect else None
+        grad = tracer.ctx.trace_adjoint(p, g, tracer.cfg(tracer.adjoint_seed(fctx.seed), adjoint=True),
+                                         bin_hist=hist)
         return grad, None, None
 
 

@@ -83,6 +83,7 @@ struct lt_ctx {
     bool has_proposal = false;
     float* prop_pdf = nullptr;
     float* prop_cdf = nullptr;
+    int* prop_guide = nullptr;
     float* inv_sigma = nullptr;
     float* mlp_scratch = nullptr;
     size_t mlp_scratch_cap = 0;
@@ -292,6 +293,7 @@ TraceArgs trace_args(lt_ctx* c, const lt_trace_cfg* cfg)
     if (cfg->flags & LT_FLAG_PROPOSAL) {
         a.prop_pdf = c->prop_pdf;
         a.prop_cdf = c->prop_cdf;
+        a.prop_guide = c->prop_guide;
         a.alpha_plain = cfg->alpha_plain;
     }
     a.inv_sigma = c->inv_sigma;
@@ -405,7 +407,7 @@ void lt_destroy(lt_ctx* c)
     free_scene(c);
     free_tiles(c);
     hipFree(c->d_si); hipFree(c->d_sf); hipFree(c->d_lights);
-    hipFree(c->prop_pdf); hipFree(c->prop_cdf); hipFree(c->inv_sigma); hipFree(c->mlp_scratch);
+    hipFree(c->prop_pdf); hipFree(c->prop_cdf); hipFree(c->prop_guide); hipFree(c->inv_sigma); hipFree(c->mlp_scratch);
     hipFree(c->d_misses); hipFree(c->d_flags); hipFree(c->d_stats);
     hipFree(c->d_objpart); hipFree(c->d_partials); hipFree(c->d_gstack);
     if (c->ev_in) hipEventDestroy(c->ev_in);
@@ -563,9 +565,9 @@ int lt_set_lights(lt_ctx* c, const lt_light_static* h_lights, int32_t n_lights, 
     free_graphs(c);
     free_tiles(c);
     hipFree(c->d_si); hipFree(c->d_sf); hipFree(c->d_lights);
-    hipFree(c->prop_pdf); hipFree(c->prop_cdf); hipFree(c->inv_sigma);
+    hipFree(c->prop_pdf); hipFree(c->prop_cdf); hipFree(c->prop_guide); hipFree(c->inv_sigma);
     c->d_si = nullptr; c->d_sf = nullptr; c->d_lights = nullptr;
-    c->prop_pdf = nullptr; c->prop_cdf = nullptr; c->inv_sigma = nullptr;
+    c->prop_pdf = nullptr; c->prop_cdf = nullptr; c->prop_guide = nullptr; c->inv_sigma = nullptr;
     c->has_lights = false;
     c->has_proposal = false;
     HIPCHK(c, hipMalloc(&c->d_si, sizeof(int4) * n_lights));
@@ -575,6 +577,7 @@ int lt_set_lights(lt_ctx* c, const lt_light_static* h_lights, int32_t n_lights, 
     HIPCHK(c, hipMemcpy(c->d_sf, sf.data(), sizeof(float4) * n_lights, hipMemcpyHostToDevice));
     HIPCHK(c, hipMalloc(&c->prop_pdf, sizeof(float) * 1024 * (size_t)n_lights));
     HIPCHK(c, hipMalloc(&c->prop_cdf, sizeof(float) * 1024 * (size_t)n_lights));
+    HIPCHK(c, hipMalloc(&c->prop_guide, sizeof(int) * 1025 * (size_t)n_lights));
     HIPCHK(c, hipMalloc(&c->inv_sigma, sizeof(float) * 6 * (size_t)n_lights));
     {
         std::vector<float> ones(6 * (size_t)n_lights, 1.0f);
@@ -695,6 +698,7 @@ int lt_record_paths(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, i
     if (cfg->flags & LT_FLAG_PROPOSAL) {
         r.prop_pdf = c->prop_pdf;
         r.prop_cdf = c->prop_cdf;
+        r.prop_guide = c->prop_guide;
         r.alpha_plain = cfg->alpha_plain;
     }
     HIPCHK(c, launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->stream));
@@ -774,6 +778,7 @@ int lt_proposal_set_table(lt_ctx* c, const float* d_pdf, const float* d_cdf)
     const size_t n = sizeof(float) * 1024 * (size_t)c->L;
     HIPCHK(c, hipMemcpyAsync(c->prop_pdf, d_pdf, n, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->prop_cdf, d_cdf, n, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, launch_guide_build(c->prop_cdf, c->L, c->prop_guide, c->stream));
     c->has_proposal = true;
     return LT_OK;
 }
@@ -809,6 +814,7 @@ int lt_proposal_mlp_infer(lt_ctx* c, const uint16_t* d_w_bf16, const float* d_x,
     if (((uintptr_t)d_w_bf16 & 7) || ((uintptr_t)d_x & 3)) return fail(c, LT_EINVAL, "misaligned buffer");
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, launch_mlp_infer(d_w_bf16, d_x, c->L, d_logits, c->prop_pdf, c->prop_cdf, c->stream));
+    HIPCHK(c, launch_guide_build(c->prop_cdf, c->L, c->prop_guide, c->stream));
     c->has_proposal = true;
     return LT_OK;
 }

@@ -47,6 +47,7 @@ struct TraceArgs {
     // emission proposal (one-sample MIS with the plain lobe), may be null
     const float* prop_pdf;      // [L,1024] bin probabilities
     const float* prop_cdf;      // [L,1024] inclusive prefix sums
+    const int* prop_guide;      // [L,1025] first cell whose prefix sum exceeds j/1024
     float alpha_plain;
     float* bin_hist;            // adjoint: [L,1024] histogram of |c_r / sigma| (may be null)
     const float* inv_sigma;     // [L,6]
@@ -72,6 +73,7 @@ struct RecordArgs {
     unsigned* flags;
     const float* prop_pdf;
     const float* prop_cdf;
+    const int* prop_guide;
     float alpha_plain;
 };
 
@@ -91,6 +93,7 @@ hipError_t launch_objective(const float* E, const float* Et, const float* alpha,
 hipError_t launch_grad_reduce(const double* partials, const int2* tile_range, int n_lights, float* grad,
                               hipStream_t st);
 size_t mlp_train_scratch_floats(int L);
+hipError_t launch_guide_build(const float* cdf, int L, int* guide, hipStream_t st);
 hipError_t launch_mlp_infer(const uint16_t* wb, const float* x, int L, float* logits, float* pdf, float* cdf,
                             hipStream_t st);
 hipError_t launch_mlp_train(float* w, float* mw, float* vw, uint16_t* wb, float* x, float* mx, float* vx,

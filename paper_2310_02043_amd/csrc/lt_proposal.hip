@@ -289,6 +289,38 @@ __global__ void __launch_bounds__(1024) k_mlp_train(float* __restrict__ w, float
 
 size_t mlp_train_scratch_floats(int L) { return (size_t)L * (4 * kMlpHidden + kMlpBins + kMlpEmbed); }
 
+// Guide entries for the inverse-CDF lookup: guide[l][j] is the first cell
+// whose inclusive prefix sum exceeds j/1024 (1023 when none does), and
+// guide[l][1024] = 1023.  For u in [j/1024, (j+1)/1024) the cell sought lies
+// in [guide[j], guide[j+1]], so a search over that range returns the same
+// cell as a search over all 1024.
+__global__ void k_guide_build(const float* __restrict__ cdf, int L, int* __restrict__ guide)
+{
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long long)L * 1025) return;
+    const int l = (int)(idx / 1025), j = (int)(idx % 1025);
+    int out = 1023;
+    if (j < 1024) {
+        const float* c = cdf + 1024 * (long long)l;
+        const float t = (float)j * (1.0f / 1024.0f);
+        int lo = 0, hi = 1023;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (c[mid] > t) hi = mid;
+            else lo = mid + 1;
+        }
+        out = lo;
+    }
+    guide[idx] = out;
+}
+
+hipError_t launch_guide_build(const float* cdf, int L, int* guide, hipStream_t st)
+{
+    const long long n = (long long)L * 1025;
+    k_guide_build<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(cdf, L, guide);
+    return hipGetLastError();
+}
+
 hipError_t launch_mlp_infer(const uint16_t* wb, const float* x, int L, float* logits, float* pdf, float* cdf,
                             hipStream_t st)
 {

@@ -160,10 +160,15 @@ __device__ __forceinline__ void start_segment(Trav& s)
 // map (ebin, -1 for point lights).  With a proposal, the direction comes from
 // the plain cos^n lobe with probability alpha and otherwise from the binned
 // proposal (cell by inverse CDF, uniform jitter in the cell), and
-// phi = (P/N) p_plain / (alpha p_plain + (1 - alpha) p_learn).
+// phi = (P/N) p_plain / (alpha p_plain + (1 - alpha) p_learn).  wq is the
+// sample's density over the (u, v) measure of its cell, q / (512 |p|^3) with q
+// the density it was drawn from: the adjoint histogram adds |c_r / sigma|^2 wq,
+// whose expectation per cell does not depend on the sampler and is
+// proportional to the square of the variance-optimal cell probability.
 __device__ __forceinline__ void emit(const DevLight& L, uint32_t pid, uint32_t stream_id, uint32_t k0, uint32_t k1,
-                                     const float* __restrict__ pdf, const float* __restrict__ cdf, float alpha,
-                                     bool want_bin, V3& y, V3& dir, float& au, float& av, float& phi, int& ebin)
+                                     const float* __restrict__ pdf, const float* __restrict__ cdf,
+                                     const int* __restrict__ guide, float alpha, bool want_bin, V3& y, V3& dir,
+                                     float& au, float& av, float& phi, int& ebin, float& wq)
 {
     const U4 r = philox10(pid, stream_id, 0u, 0u, k0, k1);
     const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
@@ -172,29 +177,35 @@ __device__ __forceinline__ void emit(const DevLight& L, uint32_t pid, uint32_t s
     av = 0.0f;
     phi = L.phi_r;
     ebin = -1;
-    float sp, cp;
-    sincos_2pi(u3, sp, cp);
+    wq = 0.0f;
     if (L.type == 0) {
+        float sp, cp;
+        sincos_2pi(u3, sp, cp);
         const float z = 1.0f - 2.0f * u2;
         const float rr = __builtin_sqrtf(fmaxf(0.0f, 1.0f - z * z));
         dir = v3(rr * cp, rr * sp, z);
         return;
     }
-    float ct = u2 > 0.0f ? exp2_c(log2_c(u2) / (L.n + 1.0f)) : 0.0f;
-    const float st = __builtin_sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
-    float a = st * cp, bb = st * sp;
-    if (pdf != nullptr || want_bin) {
-        bool plain = true;
-        float w1 = 0.0f, w2 = 0.0f, w3 = 0.0f;
-        if (pdf != nullptr) {
-            const U4 r1 = philox10(pid, stream_id, 1u, 0u, k0, k1);
-            plain = u24(r1.x) < alpha;
-            w1 = u24(r1.y);
-            w2 = u24(r1.z);
-            w3 = u24(r1.w);
-        }
-        float pl3;
-        if (plain) {
+    // Component choice first: a sample from the learned cells never needs
+    // the plain lobe's direction, only its density.
+    bool plain = true;
+    float w1 = 0.0f, w2 = 0.0f, w3 = 0.0f;
+    if (pdf != nullptr) {
+        const U4 r1 = philox10(pid, stream_id, 1u, 0u, k0, k1);
+        plain = u24(r1.x) < alpha;
+        w1 = u24(r1.y);
+        w2 = u24(r1.z);
+        w3 = u24(r1.w);
+    }
+    float ct, a, bb, pl3 = 0.0f;
+    if (plain) {
+        float sp, cp;
+        sincos_2pi(u3, sp, cp);
+        ct = u2 > 0.0f ? exp2_c(log2_c(u2) / (L.n + 1.0f)) : 0.0f;
+        const float st = __builtin_sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+        a = st * cp;
+        bb = st * sp;
+        if (pdf != nullptr || want_bin) {
             const float s = (fabsf(a) + fabsf(bb)) + ct;
             const float xp = a / s, yp = bb / s;
             int iu = (int)__builtin_floorf(((xp + yp) + 1.0f) * 16.0f);
@@ -203,33 +214,43 @@ __device__ __forceinline__ void emit(const DevLight& L, uint32_t pid, uint32_t s
             iv = iv < 0 ? 0 : (iv > 31 ? 31 : iv);
             ebin = iv * 32 + iu;
             pl3 = 1.0f / ((s * s) * s);
-        } else {
-            int lo = 0, hi = 1023;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (w1 < cdf[mid]) hi = mid;
-                else lo = mid + 1;
-            }
-            ebin = lo;
-            const float uu = -1.0f + ((float)(lo & 31) + w2) * 0.0625f;
-            const float vv = -1.0f + ((float)(lo >> 5) + w3) * 0.0625f;
-            const float xp = (uu + vv) * 0.5f, yp = (uu - vv) * 0.5f;
-            const float zp = (1.0f - fabsf(xp)) - fabsf(yp);
-            const float nrm = __builtin_sqrtf((xp * xp + yp * yp) + zp * zp);
-            const float inv = 1.0f / nrm;
-            a = xp * inv;
-            bb = yp * inv;
-            ct = zp * inv;
-            pl3 = (nrm * nrm) * nrm;
         }
+    } else {
+        // Inverse CDF: the first cell whose inclusive prefix sum exceeds w1.
+        // The guide entries bracket it (guide[j] = first cell whose sum
+        // exceeds j/1024), so the search covers a few cells, not 1024.
+        const int j = (int)(w1 * 1024.0f);
+        int lo = guide[j], hi = guide[j + 1];
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (w1 < cdf[mid]) hi = mid;
+            else lo = mid + 1;
+        }
+        ebin = lo;
+        const float uu = -1.0f + ((float)(lo & 31) + w2) * 0.0625f;
+        const float vv = -1.0f + ((float)(lo >> 5) + w3) * 0.0625f;
+        const float xp = (uu + vv) * 0.5f, yp = (uu - vv) * 0.5f;
+        const float zp = (1.0f - fabsf(xp)) - fabsf(yp);
+        const float nrm = __builtin_sqrtf((xp * xp + yp * yp) + zp * zp);
+        const float inv = 1.0f / nrm;
+        a = xp * inv;
+        bb = yp * inv;
+        ct = zp * inv;
+        pl3 = (nrm * nrm) * nrm;
+    }
+    if (pdf != nullptr || want_bin) {
+        float pw = 1.0f;
+        if (L.n != 0.0f) pw = ct > 0.0f ? exp2_c(L.n * log2_c(ct)) : 0.0f;
+        const float p_plain = ((L.n + 1.0f) * (float)0.15915494309189533577) * pw;
+        float q = p_plain;
         if (pdf != nullptr) {
-            float pw = 1.0f;
-            if (L.n != 0.0f) pw = ct > 0.0f ? exp2_c(L.n * log2_c(ct)) : 0.0f;
-            const float p_plain = ((L.n + 1.0f) * (float)0.15915494309189533577) * pw;
             const float p_learn = (pdf[ebin] * 512.0f) * pl3;
-            const float q = alpha * p_plain + (1.0f - alpha) * p_learn;
+            q = alpha * p_plain + (1.0f - alpha) * p_learn;
             phi = q > 0.0f ? phi * (p_plain / q) : 0.0f;
         }
+        // histogram weight: the sample's density over the cell's (u, v)
+        // measure, q / (512 |p|^3)
+        wq = q / (512.0f * pl3);
     }
     dir = v3((a * L.t[0] + bb * L.b[0]) + ct * L.d[0], (a * L.t[1] + bb * L.b[1]) + ct * L.d[1],
              (a * L.t[2] + bb * L.b[2]) + ct * L.d[2]);
@@ -395,6 +416,7 @@ __global__ void __launch_bounds__(WPB * 64) k_trace(TraceArgs a)
         const bool prop_on = a.prop_pdf != nullptr && L.type != 0;
         const float* pdf = prop_on ? a.prop_pdf + 1024 * (long long)ti.x : nullptr;
         const float* cdf = prop_on ? a.prop_cdf + 1024 * (long long)ti.x : nullptr;
+        const int* guide = prop_on ? a.prop_guide + 1025 * (long long)ti.x : nullptr;
         float* hist = (ADJ && a.bin_hist != nullptr && L.type != 0) ? a.bin_hist + 1024 * (long long)ti.x : nullptr;
 
         int next = 0;          // paths of this tile handed out so far (uniform)
@@ -402,7 +424,7 @@ __global__ void __launch_bounds__(WPB * 64) k_trace(TraceArgs a)
         bool trav = false;     // lane is traversing its current segment
         uint32_t pid = 0;
         int h = 0, skip = -1, ebin = -1;
-        float T = 1.0f, s_r = 0.0f, au = 0.0f, av = 0.0f, phi_r = 0.0f;
+        float T = 1.0f, s_r = 0.0f, au = 0.0f, av = 0.0f, phi_r = 0.0f, wq = 0.0f;
         float dphi[6] = {0, 0, 0, 0, 0, 0};
         double acc[6] = {0, 0, 0, 0, 0, 0};
         unsigned miss = 0, n_seg = 0, n_nodes = 0, n_tris = 0, n_hits = 0;
@@ -422,8 +444,8 @@ __global__ void __launch_bounds__(WPB * 64) k_trace(TraceArgs a)
                 if (need && slot < count) {
                     pid = first + (uint32_t)slot;
                     V3 y, dir;
-                    emit(L, pid, stream_id, a.key0, a.key1, pdf, cdf, a.alpha_plain, hist != nullptr, y, dir, au, av,
-                         phi_r, ebin);
+                    emit(L, pid, stream_id, a.key0, a.key1, pdf, cdf, guide, a.alpha_plain, hist != nullptr, y, dir, au, av,
+                         phi_r, ebin, wq);
                     set_ray(r, y, dir);
                     start_segment(s);
                     alive = true;
@@ -501,7 +523,7 @@ __global__ void __launch_bounds__(WPB * 64) k_trace(TraceArgs a)
                                 m2 = m2 + z * z;
                             }
                         }
-                        if (hist && ebin >= 0) atomicAdd(hist + ebin, __builtin_sqrtf(m2));
+                        if (hist && ebin >= 0) atomicAdd(hist + ebin, m2 * wq);
                     }
                     alive = false;
                 }
@@ -558,10 +580,12 @@ __global__ void __launch_bounds__(256) k_record(RecordArgs a)
         V3 y, dir;
         float au, av, phi_r;
         int ebin;
+        float wq;
         const bool prop_on = a.prop_pdf != nullptr && L.type != 0;
         emit(L, pid, a.stream_id, a.key0, a.key1, prop_on ? a.prop_pdf + 1024 * (long long)a.gl : nullptr,
-             prop_on ? a.prop_cdf + 1024 * (long long)a.gl : nullptr, a.alpha_plain, false, y, dir, au, av, phi_r,
-             ebin);
+             prop_on ? a.prop_cdf + 1024 * (long long)a.gl : nullptr,
+             prop_on ? a.prop_guide + 1025 * (long long)a.gl : nullptr, a.alpha_plain, false, y, dir, au, av, phi_r,
+             ebin, wq);
         Ray r;
         set_ray(r, y, dir);
         int skip = -1;

@@ -3,9 +3,11 @@
 Holds the proposal network's FP32 master weights, their BF16 copy, Adam
 moments and the per-light embeddings on the device, and drives the two
 kernels of liblt: inference (BF16 MFMA) into the sampler's cell tables, and a
-training step toward the cells' share of the adjoint gradient magnitude that
-the tracer's adjoint pass histograms (lt_trace_adjoint with d_bin_hist).
-The sampler mixes the learned cells with the plain lobe (probability
+training step toward a target derived from the histogram of gradient
+contributions by emission cell that the tracer's adjoint pass fills
+(lt_trace_adjoint with d_bin_hist): the square root of each cell's share of
+the histogrammed second moment (the variance-optimal cell probabilities).  The
+sampler mixes the learned cells with the plain lobe (probability
 alpha_plain) under one-sample MIS, so gradients stay unbiased; point lights
 keep the plain sampler.
 """
@@ -26,15 +28,43 @@ def _bf16_bits(a: np.ndarray) -> np.ndarray:
     return (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) & 0xFFFF).astype(np.uint16)
 
 
+def plain_cell_mass(lobe_n, sub: int = 8) -> np.ndarray:
+    """Probability of each of the 32 x 32 hemi-octahedral cells under the plain
+    cos^n lobe, (n + 1)/(2 pi) cos^n(theta) d(omega) with d(omega) =
+    du dv / (2 |p|^3), by midpoint quadrature on sub x sub points per cell.
+    Returns [L, 1024] (rows sum to 1)."""
+    n = np.asarray(lobe_n, np.float64).reshape(-1, 1)
+    k = (np.arange(32 * sub) + 0.5) / (16.0 * sub) - 1.0
+    uu, vv = np.meshgrid(k, k, indexing="xy")          # [v, u]
+    x, y = (uu + vv) / 2, (uu - vv) / 2
+    z = 1.0 - np.abs(x) - np.abs(y)
+    r = np.sqrt(x * x + y * y + z * z)
+    cz = z / r
+    dw = (1.0 / (16.0 * sub)) ** 2 / (2.0 * r ** 3)
+    dens = (n[:, :, None] + 1.0) / (2 * np.pi) * cz[None] ** n[:, :, None] * dw[None]
+    m = dens.reshape(-1, 32, sub, 32, sub).sum((2, 4)).reshape(-1, 1024)
+    return m / m.sum(1, keepdims=True)
+
+
 class LearnedProposal:
     def __init__(self, ctx, param_lo, param_hi, seed: int = 0, lr: float = 2e-3, alpha_plain: float = 0.2,
-                 sigma_decay: float = 0.9):
+                 sigma_decay: float = 0.9, hist_decay: float = 0.9, lobe_n=None, plain_floor: float = 0.3):
         self.ctx = ctx
         self.L = ctx.n_lights
         self.alpha_plain = float(alpha_plain)
         self.lr = float(lr)
         self.step = 0
         self.sigma_decay = sigma_decay
+        self.hist_decay = hist_decay
+        self.h_avg = None
+        # share of the plain lobe's cell masses in the training target: the
+        # learned cells then never fall far below the plain lobe, which bounds
+        # the MIS weight of every sample
+        self.plain_floor = float(plain_floor)
+        self.plain_mass = None
+        if lobe_n is not None and plain_floor > 0:
+            self.plain_mass = torch.tensor(plain_cell_mass(lobe_n), dtype=torch.float64,
+                                           device=torch.device("cuda", ctx.device))
         dev = torch.device("cuda", ctx.device)
         rng = np.random.default_rng(seed)
         parts = []
@@ -60,6 +90,7 @@ class LearnedProposal:
         self.sig2 = None
         self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
         self.hist = torch.zeros((self.L, MLP_BINS), dtype=torch.float32, device=dev)
+        self.collect = True     # whether the next adjoint pass fills self.hist
 
     def refresh(self, params):
         """Normalise the luminaire parameters into x and rebuild the sampler tables."""
@@ -67,19 +98,33 @@ class LearnedProposal:
             self.x[:, :NPAR] = 2.0 * (params.detach() - self.lo) / (self.hi - self.lo) - 1.0
         self.ctx.mlp_infer(self.wb, self.x)
 
-    def update_scale(self, grad):
-        """Running RMS of each light's gradient components (the histogram's units)."""
+    def update_scale(self, grad, mask=None):
+        """Running RMS of each light's gradient components (the histogram's
+        units); components outside `mask` [6] do not enter the histogram."""
         g2 = grad.detach().float() ** 2
         self.sig2 = g2 if self.sig2 is None else self.sigma_decay * self.sig2 + (1 - self.sigma_decay) * g2
         inv = 1.0 / torch.sqrt(self.sig2 + 1e-30)
-        inv = torch.where(torch.isfinite(inv), inv, torch.zeros_like(inv)).contiguous()
+        inv = torch.where(torch.isfinite(inv), inv, torch.zeros_like(inv))
+        if mask is not None:
+            inv = inv * torch.as_tensor(mask, dtype=inv.dtype, device=inv.device)
+        inv = inv.contiguous()
         self.ctx.proposal_set_scale(inv)
 
     def train(self, hist=None, steps: int = 4):
-        """Fit the cell distribution to the normalised adjoint histogram."""
+        """Fit the cell distribution to the adjoint histogram.
+
+        The histogram estimates, per cell, the second moment A_b of the scaled
+        gradient integrand; the variance-optimal cell probabilities are
+        proportional to sqrt(A_b).  Each light's histogram is normalised and
+        folded into a running average (hist_decay) before the square root."""
         h = (self.hist if hist is None else hist).double()
         tot = h.sum(1, keepdim=True)
-        target = torch.where(tot > 0, h / tot.clamp_min(1e-300), torch.full_like(h, 1.0 / MLP_BINS))
+        hn = torch.where(tot > 0, h / tot.clamp_min(1e-300), torch.full_like(h, 1.0 / MLP_BINS))
+        self.h_avg = hn if self.h_avg is None else self.hist_decay * self.h_avg + (1 - self.hist_decay) * hn
+        r = torch.sqrt(self.h_avg)
+        target = r / r.sum(1, keepdim=True)
+        if self.plain_mass is not None:
+            target = (1.0 - self.plain_floor) * target + self.plain_floor * self.plain_mass
         target = target.float().contiguous()
         for _ in range(steps):
             self.step += 1
