@@ -311,6 +311,42 @@ def perturb_params(params: np.ndarray, seed: int, sigma_xy=0.5, tilt=0.2, power=
 # workloads
 # ---------------------------------------------------------------------------
 
+class _TallGeometry:
+    """Footprints of the scene's triangles that reach within `reach` of the
+    ceiling (walls, columns; the ceiling itself excluded), for keeping
+    ceiling luminaires clear of them."""
+
+    def __init__(self, scene: Scene, H: float, reach: float = 0.5):
+        v = scene.verts[scene.tris]
+        zmax, zmin = v[:, :, 2].max(1), v[:, :, 2].min(1)
+        tall = (zmax >= H - reach) & (zmin < H - 1e-3)
+        self.lo = v[tall][:, :, :2].min(1)
+        self.hi = v[tall][:, :, :2].max(1)
+
+    def clear(self, x: float, y: float, half: float) -> bool:
+        return not np.any((self.lo[:, 0] < x + half) & (self.hi[:, 0] > x - half) &
+                          (self.lo[:, 1] < y + half) & (self.hi[:, 1] > y - half))
+
+
+def _clear_luminaires(rng, tall, params, jitter, half, lo, hi, fallback=None, tries=256):
+    """Re-draw the (x, y) jitter of every luminaire whose square of half-width
+    `half` touches tall geometry (a luminaire overlapping a column or wall
+    emits from inside it); after `tries` draws it takes the fallback
+    position."""
+    p = params.copy()
+    for k in range(p.shape[0]):
+        x0, y0 = p[k, 0], p[k, 1]
+        for _ in range(tries):
+            if tall.clear(p[k, 0], p[k, 1], half):
+                break
+            p[k, 0] = np.clip(x0 + rng.uniform(-jitter[0], jitter[0]), lo[0], hi[0])
+            p[k, 1] = np.clip(y0 + rng.uniform(-jitter[1], jitter[1]), lo[1], hi[1])
+        else:
+            if fallback is not None and not tall.clear(p[k, 0], p[k, 1], half):
+                p[k, :2] = fallback[k, :2]
+    return p
+
+
 def box_room(seed: int = 1, res: int = 32):
     """Closed 4 x 3 x 2.5 m room (12 triangles) plus two seeded boxes (24
     triangles); every quad carries res x res texels; albedo U[0.5,0.8] per
@@ -455,7 +491,8 @@ def office(seed: int = 2, target_tris: int = 200_000, target_texels: int = 4_000
     target_tris; texel density sqrt(total area / target_texels); 16
     rectangular 0.6 x 0.6 m cos^n luminaires (n ~ U[1,8], P ~ U[30,60] W)
     on a jittered 4 x 4 grid 0.15 m below the ceiling (pendant fittings: a
-    tilted 0.6 m emitter stays below the ceiling plane), facing down."""
+    tilted 0.6 m emitter stays below the ceiling plane), facing down, each
+    0.25 m or more from columns and walls."""
     rng = np.random.default_rng(seed)
     W, D, H = 30.0, 20.0, 3.0
     sb = SceneBuilder()
@@ -475,8 +512,13 @@ def office(seed: int = 2, target_tris: int = 200_000, target_texels: int = 4_000
         params.append([x, y, H - 0.15, 0.0, 0.0, rng.uniform(30, 60)])
         lobe.append(rng.uniform(1.0, 8.0))
     params = np.asarray(params, np.float32)
+    # ground truth and start both keep 0.25 m between a luminaire and any
+    # column or wall
+    tall = _TallGeometry(scene, H)
+    params = _clear_luminaires(rng, tall, params, (1.0, 1.0), 0.55, (0.5, 0.5), (W - 0.5, D - 0.5))
     lights = make_lights([RECT] * n_lights, lobe, [(0.6, 0.6)] * n_lights, [0] * n_lights, params)
     init = perturb_params(params, seed + 7, lo=[0.5, 0.5, H - 0.15], hi=[W - 0.5, D - 0.5, H - 0.15])
+    init = _clear_luminaires(rng, tall, init, (0.5, 0.5), 0.55, (0.5, 0.5), (W - 0.5, D - 0.5), params)
     lights.params[:] = init
     return dict(scene=scene, lights=lights, params_target=params, paths=paths,
                 max_hits=max_hits, seed=0x5EED0 + seed, seed_target=0x7A46E7 + seed)
@@ -564,9 +606,12 @@ def building_floor(seed: int = 5, target_tris: int = 2_000_000, target_texels: i
                        H - 0.15, 0.0, 0.0, rng.uniform(30, 60)])
         lobe.append(rng.uniform(1.0, 8.0))
     params = np.asarray(params, np.float32)
+    tall = _TallGeometry(scene, H)
+    params = _clear_luminaires(rng, tall, params, (1.0, 1.0), 0.55, (0.5, 0.5), (W - 0.5, D - 0.5))
     lights = make_lights([RECT] * n_lights, lobe, [(0.6, 0.6)] * n_lights, [0] * n_lights, params)
-    lights.params[:] = perturb_params(params, seed + 7, lo=[0.5, 0.5, H - 0.15],
-                                      hi=[W - 0.5, D - 0.5, H - 0.15])
+    init = perturb_params(params, seed + 7, lo=[0.5, 0.5, H - 0.15], hi=[W - 0.5, D - 0.5, H - 0.15])
+    lights.params[:] = _clear_luminaires(rng, tall, init, (0.5, 0.5), 0.55, (0.5, 0.5), (W - 0.5, D - 0.5),
+                                         params)
     return dict(scene=scene, lights=lights, params_target=params, paths=paths,
                 max_hits=max_hits, seed=0xF100 + seed, seed_target=0xF200 + seed)
 

@@ -144,8 +144,13 @@ def main(argv=None):
     tracer.paths_per_layout = N
     H = float(sc.verts[:, 2].max())
     W, D = float(sc.verts[:, 0].max()), float(sc.verts[:, 1].max())
-    lo = [0.5, 0.5, 0.0, -0.6, -0.6, 1.0]
-    hi = [W - 0.5, D - 0.5, H, 0.6, 0.6, 200.0]
+    # tilts within +-0.15 rad keep every corner of a 0.6 m luminaire mounted
+    # 0.15 m below the ceiling at least 6 cm under it: rays that graze the
+    # ceiling from a luminaire at distance h have first-hit derivative terms of
+    # size 1/h, so a luminaire touching the ceiling makes the gradient's
+    # variance unbounded
+    lo = [0.5, 0.5, 0.0, -0.15, -0.15, 1.0]
+    hi = [W - 0.5, D - 0.5, H, 0.15, 0.15, 200.0]
     if a.proposal:
         tracer.proposal = LearnedProposal(tracer.ctx, lo, hi, alpha_plain=a.alpha_plain,
                                           lobe_n=lights.static["lobe_n"])

@@ -48,7 +48,8 @@ def plain_cell_mass(lobe_n, sub: int = 8) -> np.ndarray:
 
 class LearnedProposal:
     def __init__(self, ctx, param_lo, param_hi, seed: int = 0, lr: float = 2e-3, alpha_plain: float = 0.2,
-                 sigma_decay: float = 0.9, hist_decay: float = 0.9, lobe_n=None, plain_floor: float = 0.3):
+                 sigma_decay: float = 0.9, hist_decay: float = 0.9, lobe_n=None, plain_floor: float = 0.3,
+                 prior: float = 0.0):
         self.ctx = ctx
         self.L = ctx.n_lights
         self.alpha_plain = float(alpha_plain)
@@ -61,8 +62,9 @@ class LearnedProposal:
         # learned cells then never fall far below the plain lobe, which bounds
         # the MIS weight of every sample
         self.plain_floor = float(plain_floor)
+        self.prior = float(prior)
         self.plain_mass = None
-        if lobe_n is not None and plain_floor > 0:
+        if lobe_n is not None and (plain_floor > 0 or prior > 0):
             self.plain_mass = torch.tensor(plain_cell_mass(lobe_n), dtype=torch.float64,
                                            device=torch.device("cuda", ctx.device))
         dev = torch.device("cuda", ctx.device)
@@ -121,7 +123,13 @@ class LearnedProposal:
         tot = h.sum(1, keepdim=True)
         hn = torch.where(tot > 0, h / tot.clamp_min(1e-300), torch.full_like(h, 1.0 / MLP_BINS))
         self.h_avg = hn if self.h_avg is None else self.hist_decay * self.h_avg + (1 - self.hist_decay) * hn
-        r = torch.sqrt(self.h_avg)
+        h_avg = self.h_avg
+        if self.prior > 0 and self.plain_mass is not None:
+            # shrink the second-moment estimate toward the plain lobe's (whose
+            # square root is the plain cell mass) before the square root
+            pm2 = self.plain_mass ** 2
+            h_avg = (1.0 - self.prior) * h_avg + self.prior * pm2 / pm2.sum(1, keepdim=True)
+        r = torch.sqrt(h_avg)
         target = r / r.sum(1, keepdim=True)
         if self.plain_mass is not None:
             target = (1.0 - self.plain_floor) * target + self.plain_floor * self.plain_mass

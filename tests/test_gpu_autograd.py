@@ -137,3 +137,35 @@ def test_autograd_finite_differences(torch_dev, furnished):
             else:
                 assert abs(m) < 4.5 * se + 0.25 * ref
     say("  worst relative mean difference:", worst)
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_adam_lighting_optimisation(torch_dev, learned):
+    """Adam on the 16 ceiling luminaires of a reduced office (perturbed
+    positions, tilts and powers) through the autograd function: the objective
+    of the final parameters, from an independent forward pass, falls well
+    below the initial one, with and without the learned proposal in the
+    adjoint pass."""
+    torch = torch_dev
+    from paper_2310_02043_amd.optimize import evaluate, optimize
+    from paper_2310_02043_amd.proposal import LearnedProposal
+    c2 = li.office(target_tris=20_000, target_texels=200_000)
+    sc, lights = c2["scene"], c2["lights"]
+    tr = tracer_for(sc, lights, 1 << 24, c2["max_hits"], 3)
+    A = torch.tensor(sc.texel_area(), device="cuda")
+    pt = torch.tensor(c2["params_target"], device="cuda")
+    with torch.no_grad():
+        target = tr(pt, c2["seed_target"]).clone()
+    # tilts within +-0.15 rad keep the 0.6 m luminaires 6 cm or more below the ceiling
+    lo, hi = [0.5, 0.5, 0.0, -0.15, -0.15, 1.0], [29.5, 19.5, 3.0, 0.15, 0.15, 200.0]
+    if learned:
+        tr.proposal = LearnedProposal(tr.ctx, lo, hi, lobe_n=lights.static["lobe_n"])
+    p0 = torch.tensor(lights.params, device="cuda")
+    O0 = evaluate(tr, p0, target, A, 1 << 24)
+    p, hist = optimize(tr, p0, target, A, 40, lr=0.05, scale=[1, 1, 1, 0.5, 0.5, 10.0], mask=[1, 1, 0, 1, 1, 1],
+                       lo=lo, hi=hi, seed=17, proposal_warmup=10, warmup_paths=1 << 20)
+    O1 = evaluate(tr, p, target, A, 1 << 24)
+    say(f"  objective {O0:.4g} -> {O1:.4g} in {len(hist)} steps (learned proposal: {learned})")
+    assert np.isfinite(O1) and O1 < 0.5 * O0
+    assert torch.all(p[:, 2] == p0[:, 2])           # mounting height is not a free parameter
+    assert torch.all(p[:, 3:5].abs() <= 0.15 + 1e-6)  # projected into the bounds
