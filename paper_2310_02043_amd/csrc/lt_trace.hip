@@ -56,8 +56,8 @@ struct Trav {
     int pb, qb;
     int node, sp;   // node < 0: nothing left to visit
     int steps;
-    int nl;         // queued leaf triangles (l0..l3) found by the last node step
-    int l0, l1, l2, l3;
+    int lmask;      // children of the last node step whose leaf triangle awaits its test
+    int lq0, lq1, lq2, lq3;   // that node's child references (leaf = ~triangle)
 };
 
 __device__ __forceinline__ void cswap(float& ta, int& ca, float& tb, int& cb)
@@ -69,23 +69,25 @@ __device__ __forceinline__ void cswap(float& ta, int& ca, float& tb, int& cb)
 }
 
 // One traversal operation per lane and call: either one queued leaf triangle
-// test, or one node of the 4-wide tree (four box tests; hit leaves are
-// queued, hit internal children sorted by entry distance, the nearest visited
-// next and the others pushed far-to-near).  Queued leaves are tested before
-// the next node step, so the closest-hit bound tightens as early as before.
+// test, or one node of the 4-wide tree (four box tests; hit leaf children are
+// queued as a bit mask over the node's child references, hit internal
+// children sorted by entry distance, the nearest visited next and the others
+// pushed far-to-near).  Queued leaves are tested before the next node step,
+// so the closest-hit bound tightens as early as before.
 template <int LDS_D, bool STATS>
 __device__ __forceinline__ void trav_step(const Ray& r, int skip, Trav& s, bool& traversing,
                                           const float4* __restrict__ nodes, const float4* __restrict__ tris,
                                           int* lst, int* gst, unsigned& n_nodes, unsigned& n_tris,
                                           int max_steps, bool& overrun)
 {
-    if (s.nl > 0) {
-        const int tix = s.nl == 1 ? s.l0 : (s.nl == 2 ? s.l1 : (s.nl == 3 ? s.l2 : s.l3));
-        const float4* tp = tris + 3 * tix;
+    if (s.lmask != 0) {
+        const int k = __builtin_ctz((unsigned)s.lmask);
+        const int ref = k == 0 ? s.lq0 : (k == 1 ? s.lq1 : (k == 2 ? s.lq2 : s.lq3));
+        const float4* tp = tris + 3 * (~ref);
         tri_test(tp[0], tp[1], tp[2], v3(r.ox, r.oy, r.oz), v3(r.dx, r.dy, r.dz), skip, s.tb, s.pb, s.qb);
         if (STATS) ++n_tris;
-        --s.nl;
-        if (s.nl == 0 && s.node < 0) traversing = false;
+        s.lmask &= s.lmask - 1;
+        if (s.lmask == 0 && s.node < 0) traversing = false;
         return;
     }
     // bounded: a segment visits each node at most once in a tree
@@ -103,20 +105,21 @@ __device__ __forceinline__ void trav_step(const Ray& r, int skip, Trav& s, bool&
     float t[4] = {slab(r, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, s.tb), slab(r, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, s.tb),
                   slab(r, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, s.tb), slab(r, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, s.tb)};
     int c[4] = {__float_as_int(cr.x), __float_as_int(cr.y), __float_as_int(cr.z), __float_as_int(cr.w)};
+    // hit leaf children are queued by mask (their references stay in lq0..3);
+    // only hit internal children keep a finite entry distance for the sort
+    int lm = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        if (c[k] == kEmptyChild) {
-            t[k] = __builtin_inff();
-        } else if (c[k] < 0 && t[k] != __builtin_inff()) {
-            const int leaf = ~c[k];
-            s.l3 = s.nl == 3 ? leaf : s.l3;
-            s.l2 = s.nl == 2 ? leaf : s.l2;
-            s.l1 = s.nl == 1 ? leaf : s.l1;
-            s.l0 = s.nl == 0 ? leaf : s.l0;
-            ++s.nl;
-            t[k] = __builtin_inff();
-        }
+        const bool hit = t[k] != __builtin_inff();
+        const bool leaf = c[k] < 0 && c[k] != kEmptyChild;
+        lm |= (hit && leaf) ? (1 << k) : 0;
+        t[k] = (hit && c[k] >= 0) ? t[k] : __builtin_inff();
     }
+    s.lq0 = c[0];
+    s.lq1 = c[1];
+    s.lq2 = c[2];
+    s.lq3 = c[3];
+    s.lmask = lm;
     cswap(t[0], c[0], t[1], c[1]);
     cswap(t[2], c[2], t[3], c[3]);
     cswap(t[0], c[0], t[2], c[2]);
@@ -140,7 +143,7 @@ __device__ __forceinline__ void trav_step(const Ray& r, int skip, Trav& s, bool&
             }
         }
     }
-    if (s.node < 0 && s.nl == 0) traversing = false;
+    if (s.node < 0 && s.lmask == 0) traversing = false;
 }
 
 __device__ __forceinline__ void start_segment(Trav& s)
@@ -151,8 +154,8 @@ __device__ __forceinline__ void start_segment(Trav& s)
     s.node = 0;
     s.sp = 0;
     s.steps = 0;
-    s.nl = 0;
-    s.l0 = s.l1 = s.l2 = s.l3 = 0;
+    s.lmask = 0;
+    s.lq0 = s.lq1 = s.lq2 = s.lq3 = 0;
 }
 
 // Emission (Alg. 1 "generate exitant ray"): origin y, direction, area
@@ -391,8 +394,10 @@ __device__ __forceinline__ long long xcd_block(long long b, long long nb, int re
     return x * q + (x < r ? x : r) + i;
 }
 
+// The forward variant fits 80 VGPRs (six waves per SIMD); the adjoint
+// carries its per-path derivative state and FP64 partial sums (four waves).
 template <bool ADJ, bool STATS, int WPB, int LDS_D>
-__global__ void __launch_bounds__(WPB * 64) k_trace(TraceArgs a)
+__global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(ADJ ? 4 : 6))) k_trace(TraceArgs a)
 {
     __shared__ int s_stack[WPB * LDS_D * 64];
     const int lane = threadIdx.x & 63;
