@@ -29,6 +29,12 @@
  *     dO/dp += dO/dPhi_r * dPhi_r/dp (Eq. objGradAdjoint, first term; the BRDF
  *     terms vanish for Lambertian surfaces, Eq. dLdp discussion).
  *
+ * Pins (tests/test_oracle_pins.py): closed forms, invariants, brute force and
+ * finite differences for every step above.  Parity unpinned: agreement of
+ * the generator with the canonical Philox4x32-10 stream (no published vectors
+ * are at hand; its uniformity, serial independence and avalanche behaviour
+ * are pinned instead).
+ *
  * Floating point: path arithmetic is FP32 because the kernels compute in FP32
  * and FP32 decides integers here (which triangle is hit, which texel, the
  * fixed-point code of a splat); texel sums are exact int64 fixed point

@@ -12,6 +12,8 @@
 // tests); leaves are single triangles stored in Morton order as (v0, id),
 // (v1 - v0, patch), (v2 - v0, 0).
 #include <hip/hip_runtime.h>
+#include <utility>
+#include <vector>
 #include <stdint.h>
 #include <float.h>
 #include "lt_device.h"
@@ -247,32 +249,110 @@ __device__ __forceinline__ void ref_box(int c, const float4* nlo, const float4* 
     }
 }
 
-// Open the binary children of each level node: replace the internal child of
-// largest surface area by its two children while fewer than max_w children.
-__global__ void k_collapse_open(int n_level, const int* __restrict__ level, int max_w, const int2* __restrict__ child,
-                                const float4* __restrict__ nlo, const float4* __restrict__ nhi,
-                                int* __restrict__ kids, unsigned long long* __restrict__ cnt)
+// Cost-optimal collapse of the binary tree into the 4-wide tree (the
+// dynamic programme of Ylitie, Karras and Laine 2017 for four children).
+// D(n, i) is the least surface-area cost of representing the subtree of n with
+// at most i child slots of its wide parent: a leaf costs A(leaf) * kCostTri
+// whatever i; D(n, 1) makes n a wide node, A(n) * kCostNode plus the best
+// split of its four slots between its two binary children; D(n, i > 1) takes
+// the better of D(n, i - 1) and the best split of i slots.  dp[n] holds
+// D(n, 1..4); dec[n] holds the split of the wide node (bits 0..7) and of
+// i = 2, 3, 4 slots (bits 8 (i - 1) .. 8 (i - 1) + 7; 0 = use i - 1 slots).
+constexpr float kCostNode = 1.0f;
+constexpr float kCostTri = 1.0f;
+
+__device__ __forceinline__ void dp_of(int c, const float4* __restrict__ dp, const int* __restrict__ vals,
+                                      const float4* __restrict__ tlo, const float4* __restrict__ thi, float d[4])
+{
+    if (c < 0) {
+        const int t = vals[~c];
+        const float a = half_area(tlo[t], thi[t]) * kCostTri;
+        d[0] = d[1] = d[2] = d[3] = a;
+    } else {
+        const float4 v = dp[c];
+        d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+    }
+}
+
+// Binary nodes [lo, hi) were all created in one merge round, after their
+// children, so rounds are evaluated in creation order.
+__global__ void k_collapse_dp(int lo, int hi, const int2* __restrict__ child, const float4* __restrict__ nlo,
+                              const float4* __restrict__ nhi, const int* __restrict__ vals,
+                              const float4* __restrict__ tlo, const float4* __restrict__ thi,
+                              float4* __restrict__ dp, int* __restrict__ dec)
+{
+    const int n = lo + blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= hi) return;
+    const int2 ch = child[n];
+    float L[4], R[4];
+    dp_of(ch.x, dp, vals, tlo, thi, L);
+    dp_of(ch.y, dp, vals, tlo, thi, R);
+    float bw = __builtin_inff();
+    int kw = 1;
+    for (int k = 1; k <= 3; ++k) {
+        const float c = L[k - 1] + R[3 - k];
+        if (c < bw) {
+            bw = c;
+            kw = k;
+        }
+    }
+    float D[4];
+    int code = kw;
+    D[0] = half_area(nlo[n], nhi[n]) * kCostNode + bw;
+    for (int i = 2; i <= 4; ++i) {
+        float sb = __builtin_inff();
+        int kb = 1;
+        for (int k = 1; k < i; ++k) {
+            const float c = L[k - 1] + R[i - k - 1];
+            if (c < sb) {
+                sb = c;
+                kb = k;
+            }
+        }
+        if (sb < D[i - 2]) {
+            D[i - 1] = sb;
+            code |= kb << (8 * (i - 1));
+        } else {
+            D[i - 1] = D[i - 2];
+        }
+    }
+    dp[n] = make_float4(D[0], D[1], D[2], D[3]);
+    dec[n] = code;
+}
+
+// Children of the wide node rooted at each level node: its four slots are
+// distributed over binary descendants by the recorded decisions.
+__global__ void k_collapse_open(int n_level, const int* __restrict__ level, const int2* __restrict__ child,
+                                const int* __restrict__ dec, int* __restrict__ kids,
+                                unsigned long long* __restrict__ cnt)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_level) return;
-    const int2 c0 = child[level[i]];
-    int k[4] = {c0.x, c0.y, kEmptyChild, kEmptyChild};
-    int m = 2;
-    while (m < max_w) {
-        int best = -1;
-        float ba = -1.0f;
-        for (int q = 0; q < m; ++q)
-            if (k[q] >= 0) {
-                const float a = half_area(nlo[k[q]], nhi[k[q]]);
-                if (a > ba) {
-                    ba = a;
-                    best = q;
-                }
-            }
-        if (best < 0) break;
-        const int2 cc = child[k[best]];
-        k[best] = cc.x;
-        k[m++] = cc.y;
+    const int root = level[i];
+    const int2 c0 = child[root];
+    const int kw = dec[root] & 0xff;
+    // (node, slots) pairs; their slots sum to at most 4, each at least 1
+    int sn[4], ss[4], top = 0;
+    sn[top] = c0.y; ss[top] = 4 - kw; ++top;
+    sn[top] = c0.x; ss[top] = kw; ++top;
+    int k[4] = {kEmptyChild, kEmptyChild, kEmptyChild, kEmptyChild};
+    int m = 0;
+    while (top > 0) {
+        --top;
+        const int c = sn[top], s = ss[top];
+        if (c < 0 || s == 1) {
+            if (m < 4) k[m++] = c;
+            continue;
+        }
+        int d = (dec[c] >> (8 * (s - 1))) & 0xff;
+        if (d >= s) d = 0;   // (never recorded: every split leaves each side a slot)
+        if (d == 0) {
+            sn[top] = c; ss[top] = s - 1; ++top;
+        } else {
+            const int2 cc = child[c];
+            sn[top] = cc.y; ss[top] = s - d; ++top;
+            sn[top] = cc.x; ss[top] = d; ++top;
+        }
     }
     unsigned long long n_int = 0;
     for (int q = 0; q < 4; ++q) {
@@ -451,8 +531,8 @@ hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_p
     const int n_int = n - 1 > 0 ? n - 1 : 1;
     const int n_part = 256;
     const int radius = kPlocRadius;
-    const int max_width = kBvhWidth;
     int n_wide = 0, wide_levels = 0;
+    std::vector<std::pair<int, int>> rounds;   // binary nodes created per merge round
     DevBuf<float4> tlo, thi, cen, part, nlo, nhi, clo[2], chi[2], nodes, otris;
     DevBuf<uint64_t> keys;
     DevBuf<unsigned long long> flags, scan, sums, total;
@@ -505,16 +585,27 @@ hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_p
             LT_TRY(hipStreamSynchronize(st));
             const int kept = (int)(tot >> 32), merged = (int)(tot & 0xffffffffull);
             if (merged < 1 || kept != nc - merged) return hipErrorUnknown;
+            rounds.push_back(std::make_pair(n_int - node_base - merged, n_int - node_base));
             node_base += merged;
             nc = kept;
             cur = nx;
         }
         if (node_base != n - 1) return hipErrorUnknown;
     }
+    if (rounds.empty()) rounds.push_back(std::make_pair(0, 1));
     // collapse into the wide tree, level by level from the root
     {
-        DevBuf<int> lvl[2], kids;
+        DevBuf<int> lvl[2], kids, dec;
+        DevBuf<float4> dp;
         DevBuf<unsigned long long> cnt, off;
+        LT_TRY(dec.alloc(n_int)); LT_TRY(dp.alloc(n_int));
+        for (const auto& r : rounds) {
+            if (r.first < 0 || r.second > n_int || r.first >= r.second) return hipErrorUnknown;
+            k_collapse_dp<<<blocks_for(r.second - r.first, 256), 256, 0, st>>>(r.first, r.second, child.p, nlo.p,
+                                                                               nhi.p, vals.p, tlo.p, thi.p, dp.p,
+                                                                               dec.p);
+        }
+        LT_TRY(hipGetLastError());
         LT_TRY(lvl[0].alloc(n_int)); LT_TRY(lvl[1].alloc(n_int)); LT_TRY(kids.alloc(4 * (size_t)n_int));
         LT_TRY(cnt.alloc(n_int)); LT_TRY(off.alloc(n_int));
         if (!sums.p) LT_TRY(sums.alloc(blocks_for(n_int, kScanItems)));
@@ -524,8 +615,8 @@ hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_p
         int n_level = 1, out_base = 0, cur = 0, levels = 0;
         while (n_level > 0) {
             if (++levels > n_int + 1) return hipErrorUnknown;
-            k_collapse_open<<<blocks_for(n_level, 256), 256, 0, st>>>(n_level, lvl[cur].p, max_width, child.p, nlo.p,
-                                                                      nhi.p, kids.p, cnt.p);
+            k_collapse_open<<<blocks_for(n_level, 256), 256, 0, st>>>(n_level, lvl[cur].p, child.p, dec.p, kids.p,
+                                                                      cnt.p);
             LT_TRY(scan_u64(cnt.p, off.p, sums.p, total.p, n_level, st));
             unsigned long long tot = 0;
             LT_TRY(hipMemcpyAsync(&tot, total.p, sizeof(tot), hipMemcpyDeviceToHost, st));
