@@ -99,7 +99,10 @@ typedef struct {
     int32_t tile_paths;        /* paths per work tile (multiple of 64), 0 = automatic */
     int32_t refill_threshold;  /* lanes that must finish a segment before hit processing */
     int32_t lds_depth;         /* traversal stack entries kept in LDS: 16 or 32 */
-    int32_t reserved[3];
+    int32_t tri_share;         /* 1..8: a traversal iteration runs the queued triangle tests once at
+                                  least tri_share/8 of the traversing lanes hold some (or all do),
+                                  node steps otherwise; 0: both kinds in every iteration */
+    int32_t reserved[2];
 } lt_tuning;
 
 typedef struct {

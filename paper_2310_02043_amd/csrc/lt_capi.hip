@@ -142,6 +142,7 @@ lt_tuning default_tuning()
     t.tile_paths = 0;
     t.refill_threshold = 24;
     t.lds_depth = 16;
+    t.tri_share = 4;
     return t;
 }
 
@@ -288,6 +289,7 @@ TraceArgs trace_args(lt_ctx* c, const lt_trace_cfg* cfg)
     a.gstack = c->d_gstack;
     a.gdepth = std::max(gstack_depth(c), 1);
     a.refill_threshold = c->tune.refill_threshold;
+    a.tri_share = c->tune.tri_share;
     a.max_steps = 2 * c->n_nodes + 16;
     a.flags = c->d_flags;
     if (cfg->flags & LT_FLAG_PROPOSAL) {
@@ -356,7 +358,8 @@ std::vector<uint64_t> make_key(lt_ctx* c, int kind, const lt_trace_cfg* cfg, std
     memcpy(&ab, &cfg->alpha_plain, 4);
     k.push_back((uint64_t)ab);
     k.push_back((uint64_t)c->tune.waves_per_block | ((uint64_t)c->tune.xcd_remap << 8) |
-                ((uint64_t)c->tune.refill_threshold << 24) | ((uint64_t)c->tune.lds_depth << 40));
+                ((uint64_t)c->tune.refill_threshold << 24) | ((uint64_t)c->tune.lds_depth << 40) |
+                ((uint64_t)c->tune.tri_share << 56));
     k.push_back((uint64_t)c->tiles_tp);
     for (const void* p : ptrs) k.push_back((uint64_t)(uintptr_t)p);
     return k;
@@ -747,6 +750,7 @@ int lt_set_tuning(lt_ctx* c, const lt_tuning* t)
     if (t->refill_threshold < 1 || t->refill_threshold > 64)
         return fail(c, LT_EINVAL, "refill_threshold must be in [1, 64]");
     if (t->lds_depth != 16 && t->lds_depth != 32) return fail(c, LT_EINVAL, "lds_depth must be 16 or 32");
+    if (t->tri_share < 0 || t->tri_share > 8) return fail(c, LT_EINVAL, "tri_share must be in [0, 8]");
     free_graphs(c);
     c->tune = *t;
     c->tiles_tp = -1;   // recompute tiles at the next call
@@ -886,7 +890,7 @@ std::string tune_key(const lt_ctx* c, const lt_trace_cfg* cfg)
     hipDeviceProp_t prop;
     const char* arch = "unknown";
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
-    snprintf(buf, sizeof(buf), "arch=%s tris=%lld texels=%lld lights=%d layouts=%d ppl=%lld hits=%d", arch,
+    snprintf(buf, sizeof(buf), "v2 arch=%s tris=%lld texels=%lld lights=%d layouts=%d ppl=%lld hits=%d", arch,
              (long long)c->n_tris, (long long)c->K, c->L, c->n_layouts, (long long)cfg->paths_per_layout,
              cfg->max_hits);
     for (char* q = buf; *q; ++q)
@@ -908,8 +912,8 @@ bool tune_lookup(const char* path, const std::string& key, lt_tuning* t, float* 
         lt_tuning x;
         memset(&x, 0, sizeof(x));
         float m = 0.f;
-        if (sscanf(bar + 1, "%d %d %d %d %d %f", &x.waves_per_block, &x.xcd_remap, &x.tile_paths,
-                   &x.refill_threshold, &x.lds_depth, &m) == 6) {
+        if (sscanf(bar + 1, "%d %d %d %d %d %d %f", &x.waves_per_block, &x.xcd_remap, &x.tile_paths,
+                   &x.refill_threshold, &x.lds_depth, &x.tri_share, &m) == 7) {
             *t = x;
             *ms = m;
             found = true;   // the last matching line wins
@@ -972,14 +976,16 @@ int lt_autotune(lt_ctx* c, const lt_trace_cfg* cfg_in, const float* d_params, in
     const int opts_lds[] = {16, 32};
     const int opts_thr[] = {4, 8, 16, 24, 32, 48};
     const int opts_xcd[] = {0, 1};
+    const int opts_tri[] = {0, 2, 3, 4, 5, 6};
     for (int pass = 0; pass < 2 && !rc; ++pass) {
-        for (int dim = 0; dim < 5 && !rc; ++dim) {
+        for (int dim = 0; dim < 6 && !rc; ++dim) {
             std::vector<lt_tuning> cands;
             lt_tuning t = cur;
             if (dim == 0) for (int v : opts_wpb) { t.waves_per_block = v; cands.push_back(t); }
             if (dim == 1) for (int v : opts_lds) { t.lds_depth = v; cands.push_back(t); }
             if (dim == 2) for (int v : opts_thr) { t.refill_threshold = v; cands.push_back(t); }
             if (dim == 3) for (int v : opts_xcd) { t.xcd_remap = v; cands.push_back(t); }
+            if (dim == 5) for (int v : opts_tri) { t.tri_share = v; cands.push_back(t); }
             if (dim == 4)
                 for (int f : {-2, -1, 0, 1, 2}) {
                     long long tp = f >= 0 ? (long long)auto_tp << f : (long long)auto_tp >> (-f);
@@ -1008,8 +1014,8 @@ int lt_autotune(lt_ctx* c, const lt_trace_cfg* cfg_in, const float* d_params, in
     if (cache_path) {
         FILE* f = fopen(cache_path, "a");
         if (f) {
-            fprintf(f, "%s|%d %d %d %d %d %.3f\n", key.c_str(), cur.waves_per_block, cur.xcd_remap, cur.tile_paths,
-                    cur.refill_threshold, cur.lds_depth, cur_ms);
+            fprintf(f, "%s|%d %d %d %d %d %d %.3f\n", key.c_str(), cur.waves_per_block, cur.xcd_remap,
+                    cur.tile_paths, cur.refill_threshold, cur.lds_depth, cur.tri_share, cur_ms);
             fclose(f);
         }
     }

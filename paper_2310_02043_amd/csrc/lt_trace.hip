@@ -74,12 +74,16 @@ __device__ __forceinline__ void cswap(float& ta, int& ca, float& tb, int& cb)
 // children sorted by entry distance, the nearest visited next and the others
 // pushed far-to-near).  Queued leaves are tested before the next node step,
 // so the closest-hit bound tightens as early as before.
+// mode 1 runs only a queued triangle test, mode 2 only a node step, mode 0
+// whichever the lane has next.
 template <int LDS_D, bool STATS>
 __device__ __forceinline__ void trav_step(const Ray& r, int skip, Trav& s, bool& traversing,
                                           const float4* __restrict__ nodes, const float4* __restrict__ tris,
                                           int* lst, int* gst, unsigned& n_nodes, unsigned& n_tris,
-                                          int max_steps, bool& overrun)
+                                          int max_steps, bool& overrun, int mode = 0)
 {
+    if (mode == 1 && s.lmask == 0) return;
+    if (mode == 2 && s.lmask != 0) return;
     if (s.lmask != 0) {
         const int k = __builtin_ctz((unsigned)s.lmask);
         const int ref = k == 0 ? s.lq0 : (k == 1 ? s.lq1 : (k == 2 ? s.lq2 : s.lq3));
@@ -474,9 +478,18 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(A
                     ++n_iter;
                     n_active += (unsigned)__popcll(tm);
                 }
+                // one kind of operation per iteration: the queued triangle
+                // tests once enough traversing lanes hold some (or all do),
+                // node steps otherwise; either choice lets some lane progress
+                int mode = 0;
+                if (a.tri_share > 0) {
+                    const int nq = __popcll(ballot(trav && s.lmask != 0));
+                    const int nt = __popcll(tm);
+                    mode = (nq > 0 && (nq == nt || nq * 8 >= nt * a.tri_share)) ? 1 : 2;
+                }
                 if (trav)
                     trav_step<LDS_D, STATS>(r, skip, s, trav, a.nodes, a.tris, lst, gst, n_nodes, n_tris,
-                                            a.max_steps, overrun);
+                                            a.max_steps, overrun, mode);
             }
 
             // hit processing for lanes whose segment ended

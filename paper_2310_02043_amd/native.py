@@ -45,11 +45,12 @@ class TraceCfg(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("waves_per_block", C.c_int32), ("xcd_remap", C.c_int32), ("tile_paths", C.c_int32),
-                ("refill_threshold", C.c_int32), ("lds_depth", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("refill_threshold", C.c_int32), ("lds_depth", C.c_int32), ("tri_share", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k in ("waves_per_block", "xcd_remap", "tile_paths",
-                                               "refill_threshold", "lds_depth")}
+                                               "refill_threshold", "lds_depth", "tri_share")}
 
 
 class Info(C.Structure):

@@ -48,6 +48,7 @@ def test_struct_layouts_match_header(lib):
     from paper_2310_02043_amd import native
     assert C.sizeof(native.TraceCfg) == 32
     assert C.sizeof(native.Tuning) == 32
+    assert native.Tuning.tri_share.offset == 20
     assert li.PATCH_DTYPE.itemsize == native.PATCH_ITEMSIZE == 88
     assert li.LIGHT_DTYPE.itemsize == native.LIGHT_ITEMSIZE == 20
     # field offsets of lt_patch as laid out in the header
