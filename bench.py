@@ -21,6 +21,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+TUNING_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2310_02043_amd", "tuning.cache")
 METRIC = "light paths/s (forward+adjoint); gradient-error×time vs plain tracer"
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
@@ -191,7 +192,10 @@ def main():
     ap.add_argument("--workload", choices=["office", "room_set", "building"], default="office")
     ap.add_argument("--paths", type=int, default=0, help="paths per layout (default: the workload's)")
     ap.add_argument("--graph", action="store_true", help="replay forward / adjoint as captured hipGraphs")
-    ap.add_argument("--autotune", action="store_true", help="run the launch autotuner before timing")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch tuning instead of the autotuner's choice")
+    ap.add_argument("--tuning-cache", type=str, default=TUNING_CACHE,
+                    help="autotuner cache file (a matching entry is reused; new results are appended)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-proposal-study", action="store_true",
@@ -249,10 +253,11 @@ def main():
     O = torch.empty(1, dtype=torch.float64, device=dev)
     grad = torch.empty((lights.n_lights, 6), dtype=torch.float32, device=dev)
     cfg = ctx.cfg(seed, N, B, graph=args.graph)
-    if args.autotune:
+    if not args.tuning and not args.no_autotune:
         t0 = time.time()
         g.normal_()
-        best = ctx.autotune(p, ctx.cfg(seed, N, B), S, E, g, grad)
+        cache = args.tuning_cache if args.tuning_cache else None
+        best = ctx.autotune(p, ctx.cfg(seed, N, B), S, E, g, grad, cache_path=cache)
         log(f"autotune: {ctx.get_tuning().as_dict()} ({best:.1f} ms fwd+adj, {time.time() - t0:.1f} s)")
 
     def step():

@@ -56,6 +56,16 @@ class LightTracer:
             self._S = torch.empty(n, dtype=torch.int64, device=self.device)
         return self._S
 
+    def autotune(self, params, cache_path=None) -> float:
+        """Pick the launch tuning for this scene and path count (lt_autotune);
+        a matching entry of `cache_path` is reused."""
+        p = params.detach().contiguous().float()
+        E = torch.empty((self.ctx.n_layouts, self.n_texels), dtype=torch.float32, device=self.device)
+        g = torch.randn_like(E)
+        grad = torch.empty_like(p)
+        return self.ctx.autotune(p, self.ctx.cfg(self.seed, self.paths_per_layout, self.max_hits), self.scratch(), E,
+                                 g, grad, cache_path=cache_path)
+
     def __call__(self, params, seed=None):
         return LightTraceFn.apply(params, self, seed)
 

@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import os
 import sys
 import time
 
@@ -127,6 +128,7 @@ def main(argv=None):
     ap.add_argument("--eval-paths", type=int, default=1 << 28)
     ap.add_argument("--target-paths", type=int, default=1 << 28)
     ap.add_argument("--json", type=str, default="")
+    ap.add_argument("--no-autotune", action="store_true")
     a = ap.parse_args(argv)
     gen, steps, lr, scale, mask = WORKLOADS[a.workload]
     steps = a.steps or steps
@@ -156,6 +158,8 @@ def main(argv=None):
                                           lobe_n=lights.static["lobe_n"])
         tracer.alpha_plain = a.alpha_plain
     p0 = torch.tensor(lights.params, device=dev)
+    if not a.no_autotune:
+        tracer.autotune(p0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.cache"))
     O0 = evaluate(tracer, p0, target, area, a.eval_paths)
     print(f"{a.workload}: {sc.n_tris} triangles, {sc.n_texels} texels, {lights.n_lights} luminaires, "
           f"{N} paths x {wl['max_hits']} hits, proposal={a.proposal}; O(p0) = {O0:.6g}", flush=True)
