@@ -40,10 +40,11 @@ def log(*a):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_trace_office_2e26.traffic.json")
 
 
-def measured_traffic(kind):
+def measured_traffic(kind, tuning=None, paths=None):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     passes (scaled by the copy-kernel calibration), or None if the kernel
-    sources changed since the counters were taken."""
+    sources, the launch tuning or the path count differ from those the
+    counters were taken with."""
     import hashlib
     try:
         d = json.load(open(TRAFFIC_FILE))
@@ -53,6 +54,10 @@ def measured_traffic(kind):
     for s in d["sources"]:
         h.update(open(os.path.join(ROOT, s), "rb").read())
     if h.hexdigest() != d["kernel_sources_sha256"]:
+        return None
+    if tuning is not None and d.get("tuning") != tuning:
+        return None
+    if paths is not None and d.get("paths_per_layout") != paths:
         return None
     k = d[kind]
     return int((k["fetch_kib"] * d["fetch_scale"] + k["write_kib"] * d["write_scale"]) * 1024)
@@ -313,7 +318,7 @@ def main():
                 "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": None}
     roof_mem = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None}
-    traffic = measured_traffic(dominant) if args.workload == "office" else None
+    traffic = (measured_traffic(dominant, ctx.get_tuning().as_dict(), N) if args.workload == "office" else None)
     roof_mem["traffic"] = traffic
     roof_mem["note"] = ("achieved counts the node, triangle and patch bytes the traversal fetches (L2 / "
                         "Infinity Cache level); traffic is the HBM bytes rocprofv3 measured per launch")
