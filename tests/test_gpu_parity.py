@@ -43,6 +43,24 @@ def make_ctx(torch, scene, lights):
     return ctx
 
 
+def bench_tuning(scene, lights, ppl, B):
+    """The launch tuning bench.py uses for this workload (the autotuner's cache
+    entry), or None."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2310_02043_amd",
+                        "tuning.cache")
+    want = (f"tris={scene.n_tris} texels={scene.n_texels} lights={lights.n_lights} layouts={lights.n_layouts} "
+            f"ppl={ppl} hits={B}")
+    best = None
+    for line in open(path):
+        key, _, vals = line.strip().partition("|")
+        if key.endswith(want):
+            v = vals.split()
+            best = dict(zip(("waves_per_block", "xcd_remap", "tile_paths", "refill_threshold", "lds_depth",
+                             "tri_share"), (int(x) for x in v[:6])))
+    return best
+
+
 def rel_l2(a, b):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)
@@ -57,8 +75,10 @@ def grad_rel(g_gpu, g_ref):
 
 
 def run_case(torch, oracle_lib, scene, lights, params, seed, ppl, B, use_bvh, check_grad=True, target=None,
-             graph=False):
+             graph=False, tuning=None):
     ctx = make_ctx(torch, scene, lights)
+    if tuning:
+        ctx.set_tuning(**tuning)
     osc = oracle_lib.OracleScene(scene, use_bvh=use_bvh)
     ol = oracle_lib.OracleLights(lights)
     p_d = torch.tensor(params, device="cuda")
@@ -129,25 +149,44 @@ def test_objective_matches(torch_dev, oracle_lib):
     assert np.array_equal(g_d.cpu().numpy(), g_ref)
 
 
-def test_office_reduced_paths(torch_dev, oracle_lib):
-    """The full 200k-triangle office at 2^18 paths (oracle-sized), 5 hits, 16 area lights."""
+@pytest.mark.parametrize("launch", ["default", "bench"])
+def test_office_reduced_paths(torch_dev, oracle_lib, launch):
+    """The full 200k-triangle office at 2^18 paths (oracle-sized), 5 hits, 16
+    area lights, with the default launch tuning and with the one bench.py
+    times (the same kernel instance and tile, refill and scheduling settings)."""
     torch = torch_dev
     c2 = li.office()
-    say("office reduced: tris", c2["scene"].n_tris, "texels", c2["scene"].n_texels)
-    run_case(torch, oracle_lib, c2["scene"], c2["lights"], c2["lights"].params, c2["seed"], 1 << 18,
-             c2["max_hits"], use_bvh=True)
+    sc, lights = c2["scene"], c2["lights"]
+    tuning = bench_tuning(sc, lights, c2["paths"], c2["max_hits"]) if launch == "bench" else None
+    say("office reduced: tris", sc.n_tris, "texels", sc.n_texels, "tuning", tuning)
+    assert launch == "default" or tuning is not None
+    run_case(torch, oracle_lib, sc, lights, lights.params, c2["seed"], 1 << 18, c2["max_hits"], use_bvh=True,
+             tuning=tuning)
 
 
 def test_office_full_size_sampled(torch_dev, oracle_lib):
     """Bench launch configuration (2^26 paths, 5 hits): sampled paths vs the
     oracle one by one, plus the power identity sum_l P_l dO/dP_l = sum_k g_k E_k."""
-    torch = torch_dev
-    c2 = li.office()
+    full_size_sampled(torch_dev, oracle_lib, li.office())
+
+
+def test_building_full_size_sampled(torch_dev, oracle_lib):
+    """Building floor in the bench launch configuration (2M triangles, 16M
+    texels, 128 luminaires, 2^28 paths, 6 hits): sampled paths vs the oracle
+    one by one, plus the power identity."""
+    full_size_sampled(torch_dev, oracle_lib, li.building_floor())
+
+
+def full_size_sampled(torch, oracle_lib, c2):
     sc, lights = c2["scene"], c2["lights"]
     ctx = make_ctx(torch, sc, lights)
+    N, B = c2["paths"], c2["max_hits"]
+    tuning = bench_tuning(sc, lights, N, B)
+    assert tuning is not None
+    ctx.set_tuning(**tuning)
+    say("  tuning", tuning)
     osc, ol = oracle_lib.OracleScene(sc, use_bvh=True), oracle_lib.OracleLights(lights)
     p_d = torch.tensor(lights.params, device="cuda")
-    N, B = c2["paths"], c2["max_hits"]
     cfg = ctx.cfg(c2["seed"], N, B)
     E_d, S_d = ctx.trace_forward(p_d, cfg)
     assert ctx.sync() == 0
@@ -175,15 +214,29 @@ def test_office_full_size_sampled(torch_dev, oracle_lib):
         assert rel_l2(c[same], con_r[same]) < 1e-5
     say(f"  sampled identical hit sequences: {n_same}/{n_tot}")
     assert n_same / n_tot >= PATH_BAR
+    # every path of one light replayed one by one (the per-path kernel checked
+    # against the oracle above) sums to the tuned adjoint kernel's gradient
+    light = int(rng.integers(0, lights.n_lights))
+    nl = N // lights.n_lights + (1 if light < N % lights.n_lights else 0)
+    _, _, con_all = ctx.record_paths(p_d, cfg, 0, light, 0, nl, dOdE=g_d)
+    tot = con_all.double().sum(0).cpu().numpy()
+    gl = grad_d.cpu().numpy()[light].astype(np.float64)
+    err = float(np.max(np.abs(tot - gl)) / np.max(np.abs(gl)))
+    say(f"  light {light}: all {nl} replayed paths vs the adjoint kernel, max rel err {err:.2e}")
+    assert err < 1e-5
 
 
-def test_batched_layouts_reduced(torch_dev, oracle_lib):
-    """Room set with 64 layouts of 4..48 lights in one persistent launch (2^14 paths per layout)."""
+@pytest.mark.parametrize("launch", ["default", "bench"])
+def test_batched_layouts_reduced(torch_dev, oracle_lib, launch):
+    """Room set with 64 layouts of 4..48 lights in one launch (2^14 paths per
+    layout), with the default launch tuning and with the one bench.py times."""
     torch = torch_dev
     c3 = li.room_set()
-    say("room_set: layouts", c3["lights"].n_layouts, "lights", c3["lights"].n_lights)
+    tuning = bench_tuning(c3["scene"], c3["lights"], c3["paths"], c3["max_hits"]) if launch == "bench" else None
+    say("room_set: layouts", c3["lights"].n_layouts, "lights", c3["lights"].n_lights, "tuning", tuning)
+    assert launch == "default" or tuning is not None
     run_case(torch, oracle_lib, c3["scene"], c3["lights"], c3["lights"].params, c3["seed"], 1 << 14,
-             c3["max_hits"], use_bvh=True)
+             c3["max_hits"], use_bvh=True, tuning=tuning)
 
 
 @pytest.mark.parametrize("graph", [False, True])
