@@ -7,8 +7,11 @@ accumulator clear, primal light tracing, fixed-point to float, objective and
 dO/dE, adjoint light tracing, per-light gradient reduction.  Inputs are
 resident in HBM before the timed region.
 
-Prints one JSON line (metric, value, roofline of the dominant kernel, and the
-CPU oracle timed on a bounded sample of the same workload).
+The launch tuning comes from the autotuner (a matching entry of
+paper_2310_02043_amd/tuning.cache is reused).  Prints one JSON line: metric,
+value, the roofline of the dominant kernel, the CPU oracle timed on a bounded
+sample of the same workload, and (office) the learned-proposal study:
+gradient error x time of the adjoint pass against the plain tracer.
 """
 import argparse
 import json

@@ -86,7 +86,8 @@ def optimize(tracer: LightTracer, params0, target, texel_area, steps: int, lr: f
             prop.update_scale(grad_p, mask=mk)
             prop.train(steps=proposal_train_steps)
         Ov = float(O.item())
-        torch.cuda.synchronize(dev)
+        if dev.type == "cuda":
+            torch.cuda.synchronize(dev)
         rec = {"iter": it, "objective": Ov, "seconds": time.perf_counter() - t0,
                "grad_rms": grad_p.pow(2).mean(0).sqrt().tolist()}
         hist.append(rec)

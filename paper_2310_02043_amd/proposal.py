@@ -46,6 +46,32 @@ def plain_cell_mass(lobe_n, sub: int = 8) -> np.ndarray:
     return m / m.sum(1, keepdims=True)
 
 
+def training_target(hist, h_avg, decay: float, plain_mass=None, floor: float = 0.0, prior: float = 0.0):
+    """Training target of the proposal network from one adjoint histogram.
+
+    hist [L,1024] estimates, per cell, the second moment A_b of the scaled
+    gradient integrand; the variance-optimal cell probabilities are
+    proportional to sqrt(A_b).  Each light's histogram is normalised (a light
+    with an empty histogram gets uniform cells) and folded into the running
+    average h_avg (weight `decay` on the old average); with `prior` > 0 the
+    average is shrunk toward the plain lobe's second moments (plain cell
+    masses squared) before the square root; the result is mixed with the
+    plain lobe's cell masses by `floor`.  Returns (target, new h_avg)."""
+    h = hist.double()
+    tot = h.sum(1, keepdim=True)
+    hn = torch.where(tot > 0, h / tot.clamp_min(1e-300), torch.full_like(h, 1.0 / h.shape[1]))
+    h_avg = hn if h_avg is None else decay * h_avg + (1 - decay) * hn
+    a = h_avg
+    if prior > 0 and plain_mass is not None:
+        pm2 = plain_mass ** 2
+        a = (1.0 - prior) * a + prior * pm2 / pm2.sum(1, keepdim=True)
+    r = torch.sqrt(a)
+    target = r / r.sum(1, keepdim=True)
+    if plain_mass is not None and floor > 0:
+        target = (1.0 - floor) * target + floor * plain_mass
+    return target, h_avg
+
+
 class LearnedProposal:
     def __init__(self, ctx, param_lo, param_hi, seed: int = 0, lr: float = 2e-3, alpha_plain: float = 0.2,
                  sigma_decay: float = 0.9, hist_decay: float = 0.9, lobe_n=None, plain_floor: float = 0.3,
@@ -113,26 +139,10 @@ class LearnedProposal:
         self.ctx.proposal_set_scale(inv)
 
     def train(self, hist=None, steps: int = 4):
-        """Fit the cell distribution to the adjoint histogram.
-
-        The histogram estimates, per cell, the second moment A_b of the scaled
-        gradient integrand; the variance-optimal cell probabilities are
-        proportional to sqrt(A_b).  Each light's histogram is normalised and
-        folded into a running average (hist_decay) before the square root."""
+        """Fit the cell distribution to the adjoint histogram (training_target)."""
         h = (self.hist if hist is None else hist).double()
-        tot = h.sum(1, keepdim=True)
-        hn = torch.where(tot > 0, h / tot.clamp_min(1e-300), torch.full_like(h, 1.0 / MLP_BINS))
-        self.h_avg = hn if self.h_avg is None else self.hist_decay * self.h_avg + (1 - self.hist_decay) * hn
-        h_avg = self.h_avg
-        if self.prior > 0 and self.plain_mass is not None:
-            # shrink the second-moment estimate toward the plain lobe's (whose
-            # square root is the plain cell mass) before the square root
-            pm2 = self.plain_mass ** 2
-            h_avg = (1.0 - self.prior) * h_avg + self.prior * pm2 / pm2.sum(1, keepdim=True)
-        r = torch.sqrt(h_avg)
-        target = r / r.sum(1, keepdim=True)
-        if self.plain_mass is not None:
-            target = (1.0 - self.plain_floor) * target + self.plain_floor * self.plain_mass
+        target, self.h_avg = training_target(h, self.h_avg, self.hist_decay, self.plain_mass, self.plain_floor,
+                                             self.prior)
         target = target.float().contiguous()
         for _ in range(steps):
             self.step += 1

@@ -1,0 +1,117 @@
+"""Host-side logic of the package on the CPU (no GPU, no liblt calls).
+
+* the Adam optimisation loop against a linear stand-in for the tracer: it
+  recovers the parameters, never moves a masked coordinate and stays inside
+  the bounds;
+* the plain lobe's hemi-octahedral cell masses against an independent
+  quadrature in spherical coordinates;
+* the proposal network's training target: normalisation, running average,
+  square root and plain-lobe floor.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+
+class LinearTracer:
+    """E = M p (per layout, K texels) with autograd, standing in for the
+    light tracer in the optimisation loop."""
+
+    def __init__(self, M):
+        self.M = M
+        self.device = torch.device("cpu")
+        self.proposal = None
+        self.seed = 0
+        self.correlated = True
+
+    def __call__(self, p, seed=None):
+        return (self.M @ p.reshape(-1)).reshape(1, -1)
+
+
+def test_optimize_recovers_linear_model():
+    from paper_2310_02043_amd.optimize import optimize
+    g = torch.Generator().manual_seed(0)
+    L, K = 3, 200
+    M = torch.randn(K, 6 * L, generator=g, dtype=torch.float32)
+    p_true = torch.tensor([[1.0, 2.0, 2.85, 0.05, -0.05, 40.0]] * L)
+    p_true[:, 0] += torch.arange(L, dtype=torch.float32)
+    target = (M @ p_true.reshape(-1)).reshape(1, -1)
+    p0 = p_true.clone()
+    p0[:, 0] += 0.4
+    p0[:, 1] -= 0.3
+    p0[:, 3:5] += 0.08
+    p0[:, 5] *= 1.2
+    area = torch.ones(K)
+    lo = [0.0, 0.0, 0.0, -0.15, -0.15, 1.0]
+    hi = [10.0, 10.0, 3.0, 0.15, 0.15, 200.0]
+    p, hist = optimize(LinearTracer(M), p0, target, area, 400, lr=0.05, scale=[1, 1, 1, 0.5, 0.5, 10.0],
+                       mask=[1, 1, 0, 1, 1, 1], lo=lo, hi=hi)
+    assert hist[-1]["objective"] < 1e-4 * hist[0]["objective"]
+    assert torch.all(p[:, 2] == p0[:, 2])
+    free = [0, 1, 3, 4, 5]
+    assert torch.allclose(p[:, free], p_true[:, free], atol=2e-2, rtol=1e-3)
+    lo_t, hi_t = torch.tensor(lo), torch.tensor(hi)
+    assert torch.all(p >= lo_t - 1e-6) and torch.all(p <= hi_t + 1e-6)
+
+
+def test_optimize_projects_into_bounds():
+    """A target outside the box: the iterate ends on the bound, not past it."""
+    from paper_2310_02043_amd.optimize import optimize
+    L, K = 1, 6
+    M = torch.eye(6)
+    target = torch.tensor([[5.0, 5.0, 2.85, 0.4, -0.4, 50.0]])
+    p0 = torch.tensor([[5.0, 5.0, 2.85, 0.0, 0.0, 50.0]])
+    p, _ = optimize(LinearTracer(M), p0, target, torch.ones(K), 200, lr=0.05, scale=[1, 1, 1, 0.5, 0.5, 10.0],
+                    lo=[0, 0, 0, -0.15, -0.15, 1], hi=[10, 10, 3, 0.15, 0.15, 200])
+    assert abs(float(p[0, 3]) - 0.15) < 1e-6 and abs(float(p[0, 4]) + 0.15) < 1e-6
+
+
+def _cell_mass_spherical(n, res=32, nt=400, nph=800):
+    """Independent check: integrate (n+1)/(2 pi) cos^n theta over the
+    hemisphere in (theta, phi) and bin each direction into its hemi-octahedral
+    cell (u = x' + y', v = x' - y' with (x', y') = (x, y) / (|x| + |y| + z))."""
+    th = (np.arange(nt) + 0.5) * (math.pi / 2) / nt
+    ph = (np.arange(nph) + 0.5) * (2 * math.pi) / nph
+    T, P = np.meshgrid(th, ph, indexing="ij")
+    x, y, z = np.sin(T) * np.cos(P), np.sin(T) * np.sin(P), np.cos(T)
+    s = np.abs(x) + np.abs(y) + z
+    u, v = (x + y) / s, (x - y) / s
+    iu = np.clip(np.floor((u + 1) * res / 2).astype(int), 0, res - 1)
+    iv = np.clip(np.floor((v + 1) * res / 2).astype(int), 0, res - 1)
+    w = (n + 1) / (2 * math.pi) * z ** n * np.sin(T) * (math.pi / 2 / nt) * (2 * math.pi / nph)
+    m = np.zeros(res * res)
+    np.add.at(m, (iv * res + iu).ravel(), w.ravel())
+    return m
+
+
+@pytest.mark.parametrize("n", [0.0, 1.0, 4.0])
+def test_plain_cell_mass(n):
+    from paper_2310_02043_amd.proposal import plain_cell_mass
+    m = plain_cell_mass([n], sub=16)[0]
+    ref = _cell_mass_spherical(n)
+    assert abs(m.sum() - 1) < 1e-12 and abs(ref.sum() - 1) < 2e-3
+    # coarse 4x4 blocks agree (the spherical grid's binning is the rougher one)
+    mb = m.reshape(8, 4, 8, 4).sum((1, 3))
+    rb = ref.reshape(8, 4, 8, 4).sum((1, 3))
+    assert np.max(np.abs(mb - rb)) < 2e-3
+
+
+def test_training_target():
+    from paper_2310_02043_amd.proposal import training_target
+    h = torch.zeros(2, 4, dtype=torch.float64)
+    h[0] = torch.tensor([4.0, 0.0, 1.0, 11.0])
+    t, avg = training_target(h, None, 0.5)
+    r = torch.sqrt(torch.tensor([4.0, 0.0, 1.0, 11.0], dtype=torch.float64) / 16)
+    assert torch.allclose(t[0], r / r.sum())
+    assert torch.allclose(t[1], torch.full((4,), 0.25, dtype=torch.float64))      # empty histogram: uniform
+    # running average, then the plain-lobe floor
+    h2 = torch.tensor([[0.0, 0.0, 0.0, 8.0], [1.0, 1.0, 1.0, 1.0]], dtype=torch.float64)
+    pm = torch.tensor([[0.1, 0.2, 0.3, 0.4]] * 2, dtype=torch.float64)
+    t2, avg2 = training_target(h2, avg, 0.75, pm, 0.3)
+    a = 0.75 * avg + 0.25 * (h2 / h2.sum(1, keepdim=True))
+    r2 = torch.sqrt(a)
+    assert torch.allclose(avg2, a)
+    assert torch.allclose(t2, 0.7 * r2 / r2.sum(1, keepdim=True) + 0.3 * pm)
+    assert torch.allclose(t2.sum(1), torch.ones(2, dtype=torch.float64))
