@@ -50,6 +50,7 @@ def optimize(tracer: LightTracer, params0, target, texel_area, steps: int, lr: f
     opt = torch.optim.Adam([q], lr=lr, betas=(0.9, 0.999))
     prop = tracer.proposal
     hist = []
+    correlated = tracer.correlated
     tracer.correlated = False
     t_warm = time.perf_counter()
     if prop is not None and proposal_warmup > 0:
@@ -95,6 +96,7 @@ def optimize(tracer: LightTracer, params0, target, texel_area, steps: int, lr: f
             callback(rec)
     if prop is not None:
         prop.collect = True
+    tracer.correlated = correlated
     return (p0 + q.detach() * sc), hist
 
 
