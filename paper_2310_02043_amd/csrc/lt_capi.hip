@@ -139,8 +139,8 @@ lt_tuning default_tuning()
     memset(&t, 0, sizeof(t));
     t.waves_per_block = 4;
     t.xcd_remap = 0;
-    t.tile_paths = 0;
-    t.refill_threshold = 24;
+    t.tile_paths = 1024;
+    t.refill_threshold = 32;
     t.lds_depth = 16;
     t.tri_share = 4;
     return t;
