@@ -177,6 +177,14 @@ def test_building_full_size_sampled(torch_dev, oracle_lib):
     full_size_sampled(torch_dev, oracle_lib, li.building_floor())
 
 
+def test_room_set_full_size_sampled(torch_dev, oracle_lib):
+    """Room set in the bench launch configuration (64 layouts of 4-48 lights,
+    2^22 paths per layout, 4 hits): sampled paths of random layouts vs the
+    oracle one by one, the power identity over all layouts, and all paths of
+    one light replayed against the adjoint kernel."""
+    full_size_sampled(torch_dev, oracle_lib, li.room_set())
+
+
 def full_size_sampled(torch, oracle_lib, c2):
     sc, lights = c2["scene"], c2["lights"]
     ctx = make_ctx(torch, sc, lights)
@@ -190,7 +198,8 @@ def full_size_sampled(torch, oracle_lib, c2):
     cfg = ctx.cfg(c2["seed"], N, B)
     E_d, S_d = ctx.trace_forward(p_d, cfg)
     assert ctx.sync() == 0
-    Et_d = torch.tensor(li.painted_target(sc, 0.5)[None], device="cuda")
+    nly = lights.n_layouts
+    Et_d = torch.tensor(np.stack([li.painted_target(sc, 0.5, seed=j) for j in range(nly)]), device="cuda")
     O_d, g_d = ctx.objective(E_d, Et_d)
     grad_d = ctx.trace_adjoint(p_d, g_d, cfg)
     ctx.sync()
@@ -198,15 +207,22 @@ def full_size_sampled(torch, oracle_lib, c2):
     rhs = float(torch.sum(g_d.double() * E_d.double()).item())
     say(f"  power identity: {lhs:.6e} vs {rhs:.6e}")
     assert abs(lhs / rhs - 1) < 1e-4
+    offs = np.asarray(lights.layout_offsets)
+
+    def paths_of(gl):
+        j = int(np.searchsorted(offs, gl, side="right") - 1)
+        L, l = int(offs[j + 1] - offs[j]), int(gl - offs[j])
+        return j, l, N // L + (1 if l < N % L else 0)
+
     rng = np.random.default_rng(9)
     g_np = g_d.cpu().numpy()
     n_same = n_tot = 0
-    for light in rng.choice(lights.n_lights, 4, replace=False):
-        nl = N // lights.n_lights
+    for gl in rng.choice(lights.n_lights, 4, replace=False):
+        j, l, nl = paths_of(int(gl))
         first = int(rng.integers(0, nl - 4096))
-        prim_d, tex_d, con_d = ctx.record_paths(p_d, cfg, 0, int(light), first, 4096, dOdE=g_d)
-        prim_r, tex_r, con_r = oracle_lib.record(osc, ol, lights.params, c2["seed"], N, B, 0, int(light), first,
-                                                 4096, dOdE=g_np)
+        prim_d, tex_d, con_d = ctx.record_paths(p_d, cfg, j, l, first, 4096, dOdE=g_d)
+        prim_r, tex_r, con_r = oracle_lib.record(osc, ol, lights.params, c2["seed"], N, B, j, l, first, 4096,
+                                                 dOdE=g_np)
         same = np.all(prim_d.cpu().numpy() == prim_r, 1) & np.all(tex_d.cpu().numpy() == tex_r, 1)
         n_same += int(same.sum())
         n_tot += same.size
@@ -216,13 +232,13 @@ def full_size_sampled(torch, oracle_lib, c2):
     assert n_same / n_tot >= PATH_BAR
     # every path of one light replayed one by one (the per-path kernel checked
     # against the oracle above) sums to the tuned adjoint kernel's gradient
-    light = int(rng.integers(0, lights.n_lights))
-    nl = N // lights.n_lights + (1 if light < N % lights.n_lights else 0)
-    _, _, con_all = ctx.record_paths(p_d, cfg, 0, light, 0, nl, dOdE=g_d)
+    gl = int(rng.integers(0, lights.n_lights))
+    j, l, nl = paths_of(gl)
+    _, _, con_all = ctx.record_paths(p_d, cfg, j, l, 0, nl, dOdE=g_d)
     tot = con_all.double().sum(0).cpu().numpy()
-    gl = grad_d.cpu().numpy()[light].astype(np.float64)
-    err = float(np.max(np.abs(tot - gl)) / np.max(np.abs(gl)))
-    say(f"  light {light}: all {nl} replayed paths vs the adjoint kernel, max rel err {err:.2e}")
+    ref = grad_d.cpu().numpy()[gl].astype(np.float64)
+    err = float(np.max(np.abs(tot - ref)) / np.max(np.abs(ref)))
+    say(f"  light {gl}: all {nl} replayed paths vs the adjoint kernel, max rel err {err:.2e}")
     assert err < 1e-5
 
 
