@@ -378,7 +378,9 @@ __global__ void k_collapse_write(int n_level, int out_base, int next_base, const
     for (int q = 0; q < 4; ++q) {
         const int c = kids[4 * i + q];
         if (c == kEmptyChild) {
-            lx[q] = hx[q] = ly[q] = hy[q] = lz[q] = hz[q] = 0.0f;
+            // an inverted box: every slab test misses it
+            lx[q] = ly[q] = lz[q] = __builtin_inff();
+            hx[q] = hy[q] = hz[q] = -__builtin_inff();
             ref[q] = kEmptyChild;
             continue;
         }

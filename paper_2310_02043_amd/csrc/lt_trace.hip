@@ -118,10 +118,11 @@ __device__ __forceinline__ void trav_step(const Ray& r, int skip, Trav& s, bool&
     int lm = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
+        // empty slots hold inverted boxes, so a hit child is never empty
         const bool hit = t[k] != __builtin_inff();
-        const bool leaf = c[k] < 0 && c[k] != kEmptyChild;
+        const bool leaf = c[k] < 0;
         lm |= (hit && leaf) ? (1 << k) : 0;
-        t[k] = (hit && c[k] >= 0) ? t[k] : __builtin_inff();
+        t[k] = leaf ? __builtin_inff() : t[k];
     }
     s.lq0 = c[0];
     s.lq1 = c[1];
