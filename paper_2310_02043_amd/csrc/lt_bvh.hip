@@ -235,7 +235,8 @@ __global__ void k_ploc_write(int nc, int n_int, int node_base, const int* __rest
 // ---- collapse of the binary tree into a 4-wide tree ------------------------
 // Node of the wide tree, 128 B: lo.x, hi.x, lo.y, hi.y, lo.z, hi.z of the four
 // children (float4 each, one lane per child), then the child references
-// (>= 0 wide node, < 0 leaf ~triangle, kEmptyChild unused) and padding.
+// (>= 0 wide node, < 0 leaf ~triangle, kEmptyChild unused, with an inverted
+// box that no slab test hits) and padding.
 __device__ __forceinline__ void ref_box(int c, const float4* nlo, const float4* nhi, const int* vals,
                                         const float4* tlo, const float4* thi, float4& lo, float4& hi)
 {
