@@ -143,12 +143,22 @@ __device__ __forceinline__ void trav_step(const Ray& r, int skip, Trav& s, bool&
         }
     } else {
         s.node = c[0];
+        if (s.sp + 3 <= LDS_D) {
 #pragma unroll
-        for (int k = 3; k >= 1; --k) {
-            if (t[k] != __builtin_inff()) {
-                if (s.sp < LDS_D) lst[s.sp * 64] = c[k];
-                else gst[(s.sp - LDS_D) * 64] = c[k];
-                ++s.sp;
+            for (int k = 3; k >= 1; --k) {
+                if (t[k] != __builtin_inff()) {
+                    lst[s.sp * 64] = c[k];
+                    ++s.sp;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 3; k >= 1; --k) {
+                if (t[k] != __builtin_inff()) {
+                    if (s.sp < LDS_D) lst[s.sp * 64] = c[k];
+                    else gst[(s.sp - LDS_D) * 64] = c[k];
+                    ++s.sp;
+                }
             }
         }
     }
