@@ -7,8 +7,9 @@
 // exhausted.  Hit processing (splat or adjoint gather, bounce, refill) runs
 // once at least `refill_threshold` lanes have finished their current segment,
 // so the BVH traversal loop stays converged.  Texel sums are int64 Q31.32
-// fixed point (order-independent); adjoint partial sums are FP64 per tile in a
-// fixed lane order, so both passes are deterministic.
+// fixed point (order-independent); adjoint contributions are summed per lane
+// in path order (FP32) and per tile over the lanes in a fixed order (FP64), so
+// both passes are deterministic.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include "lt_device.h"
@@ -413,14 +414,18 @@ __device__ __forceinline__ long long xcd_block(long long b, long long nb, int re
     return x * q + (x < r ? x : r) + i;
 }
 
-// The forward variant fits 96 VGPRs (five waves per SIMD); the adjoint
-// carries its per-path derivative state and FP64 partial sums (four waves).
+// Both variants fit 96 VGPRs (five waves per SIMD); the adjoint keeps its
+// per-path first-hit derivative factors and running sums in LDS.
 template <bool ADJ, bool STATS, int WPB, int LDS_D>
-__global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(ADJ ? 4 : 5))) k_trace(TraceArgs a)
+__global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5))) k_trace(TraceArgs a)
 {
     __shared__ int s_stack[WPB * LDS_D * 64];
+    // adjoint per-lane state read once per path (first-hit derivative
+    // factors, running contribution sums), kept in LDS instead of registers
+    __shared__ float s_adj[ADJ ? WPB * 12 * 64 : 1];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
+    float* adj = s_adj + (ADJ ? wib * 12 * 64 + lane : 0);
     const long long blk = xcd_block(blockIdx.x, gridDim.x, a.xcd_remap);
     const long long gw = blk * WPB + wib;
     if (gw >= a.n_tiles) return;
@@ -449,8 +454,10 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(A
         uint32_t pid = 0;
         int h = 0, skip = -1, ebin = -1;
         float T = 1.0f, s_r = 0.0f, au = 0.0f, av = 0.0f, phi_r = 0.0f, wq = 0.0f;
-        float dphi[6] = {0, 0, 0, 0, 0, 0};
-        double acc[6] = {0, 0, 0, 0, 0, 0};
+        if (ADJ) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) adj[c * 64] = 0.0f;
+        }
         unsigned miss = 0, n_seg = 0, n_nodes = 0, n_tris = 0, n_hits = 0;
         unsigned n_iter = 0, n_active = 0, n_phase = 0;   // wave-uniform counters
         bool overrun = false;
@@ -529,7 +536,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(A
                             float dl[6];
                             first_hit_dlog(L, hi.x, v3(r.ox, r.oy, r.oz), hi.no, au, av, dl);
 #pragma unroll
-                            for (int c = 0; c < 6; ++c) dphi[c] = phi_r * dl[c];
+                            for (int c = 0; c < 6; ++c) adj[c * 64] = phi_r * dl[c];
                         }
                     }
                     if (h >= B) {
@@ -549,8 +556,8 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(A
                         float m2 = 0.0f;
 #pragma unroll
                         for (int c = 0; c < 6; ++c) {
-                            const float cr = s_r * dphi[c];
-                            acc[c] += (double)cr;
+                            const float cr = s_r * adj[c * 64];
+                            adj[(6 + c) * 64] += cr;
                             if (hist) {
                                 const float z = cr * a.inv_sigma[6 * ti.x + c];
                                 m2 = m2 + z * z;
@@ -563,8 +570,9 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(A
             }
         }
         if (ADJ) {
+            double acc[6];
 #pragma unroll
-            for (int c = 0; c < 6; ++c) acc[c] = wave_sum(acc[c]);
+            for (int c = 0; c < 6; ++c) acc[c] = wave_sum((double)adj[(6 + c) * 64]);
             if (lane == 0) {
 #pragma unroll
                 for (int c = 0; c < 6; ++c) a.partials[(long long)tile * 6 + c] = acc[c];
