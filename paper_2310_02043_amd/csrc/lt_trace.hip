@@ -489,13 +489,15 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                 }
                 next += __popcll(m);
             }
-            if (ballot(alive) == 0) break;
+            // lanes holding a path: fixed while the traversal loop runs
+            const uint64_t am = ballot(alive);
+            if (am == 0) break;
 
             // traverse until enough lanes finished their segment
             for (;;) {
                 const uint64_t tm = ballot(trav);
                 if (tm == 0) break;
-                if (__popcll(ballot(alive && !trav)) >= thresh) break;
+                if (__popcll(am & ~tm) >= thresh) break;
                 if (STATS) {
                     ++n_iter;
                     n_active += (unsigned)__popcll(tm);
