@@ -89,6 +89,9 @@ def lib():
         L.or_forward.restype = C.c_int64
         L.or_adjoint.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int64, C.c_int, P, P, P]
         L.or_adjoint.restype = C.c_int64
+        L.or_votes.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int64, C.c_int, P, P, C.c_int,
+                               C.c_int, P, P]
+        L.or_votes.restype = C.c_int64
         L.or_record.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int64,
                                 C.c_int64, P, P, P, P, P]
         L.or_fixed_to_float.argtypes = [P, C.c_int64, P]
@@ -208,6 +211,23 @@ def adjoint(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_lay
                          int(paths_per_layout), int(max_hits), int(limit_per_light), int(n_threads),
                          _prop(proposal), g.ctypes.data, out.ctypes.data)
     return out, int(m)
+
+
+def votes(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,
+          dOdE, light: int, param: int, limit_per_light: int = 0, n_threads: int = 0, proposal: Proposal = None):
+    """Gradient-contribution map (Sec. gradVis) of global light `light` and
+    parameter `param`: returns (vote [K] float64 over the texels of the
+    light's layout, grad [6] float64 of that light, misses)."""
+    prm = np.ascontiguousarray(params, np.float32)
+    g = np.ascontiguousarray(dOdE, np.float32).reshape(ol.n_layouts, osc.n_texels)
+    vote = np.zeros(osc.n_texels, np.float64)
+    grad = np.zeros(6, np.float64)
+    if not (0 <= light < ol.n_lights and 0 <= param < 6):
+        raise ValueError("light or parameter out of range")
+    m = lib().or_votes(C.byref(osc.c), C.byref(ol.c), prm.ctypes.data, int(seed) & 0xFFFFFFFFFFFFFFFF,
+                       int(paths_per_layout), int(max_hits), int(limit_per_light), int(n_threads),
+                       _prop(proposal), g.ctypes.data, int(light), int(param), vote.ctypes.data, grad.ctypes.data)
+    return vote, grad, int(m)
 
 
 def record(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,

@@ -28,6 +28,9 @@
  *     supplement, generalised to a cos^n lobe); at path end
  *     dO/dp += dO/dPhi_r * dPhi_r/dp (Eq. objGradAdjoint, first term; the BRDF
  *     terms vanish for Lambertian surfaces, Eq. dLdp discussion).
+ *   - Gradient-contribution map (Sec. gradVis): the same adjoint pass over
+ *     one light's paths, each path adding its contribution to dO/dp_j into
+ *     the texel of its first surface hit.
  *
  * Pins (tests/test_oracle_pins.py): closed forms, invariants, brute force and
  * finite differences for every step above.  Parity unpinned: agreement of
@@ -497,6 +500,8 @@ typedef struct {
     const float* g;        /* adjoint: dO/dE of this layout (or NULL) */
     double* acc;           /* adjoint: per-light gradient accumulator [6] */
     float* contrib;        /* record: per-path contribution [6] (or NULL) */
+    double* vote;          /* votes: per-texel map of one parameter's contributions (or NULL) */
+    int vote_param;        /* votes: which of the six parameters */
     int32_t* rec_prim;     /* record: [B] (or NULL) */
     int32_t* rec_texel;    /* record: [B] */
     int64_t misses;
@@ -639,6 +644,7 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
     float s_r = 0.0f;
     float dphi[6] = {0, 0, 0, 0, 0, 0};
     int hits = 0;
+    int64_t k1 = -1;
     for (int h = 1; h <= B; ++h) {
         float t;
         int64_t prim = intersect(S, o, dir, skip, &t);
@@ -679,6 +685,7 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
         if (io->g) {
             s_r = s_r + (io->g[k] * inv_a) * T;
             if (h == 1) {
+                k1 = k;
                 float dl[6];
                 first_hit_dlog(L, x, y, no, au, av, dl);
                 for (int c = 0; c < 6; ++c) dphi[c] = phi_r * dl[c];
@@ -714,6 +721,14 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
             cr[c] = s_r * dphi[c];
             if (io->acc) io->acc[c] += (double)cr[c];
             if (io->contrib) io->contrib[c] = cr[c];
+        }
+        if (io->vote) {
+            /* the path's share of dO/dp_j goes to the texel of its first
+             * surface hit (Sec. gradVis) */
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+            io->vote[k1] += (double)cr[io->vote_param];
         }
         if (prop && prop->hist && ebin >= 0) {
             const float* is = prop->inv_sigma + 6 * (int64_t)gl;
@@ -810,6 +825,49 @@ EXPORT int64_t or_adjoint(const or_scene* S, const or_lights* Ls, const float* p
         }
     }
     return misses;
+}
+
+/* Gradient-contribution map of one light gl and one parameter j (Sec.
+ * gradVis): the adjoint pass of Alg. 2 over the paths of that light, where
+ * each path adds its contribution to dO/dp_j into the texel of its first
+ * surface hit.  vote_out: [K] FP64 over the texels of the light's layout,
+ * overwritten; grad_out: [6] FP64, the light's gradient (the map sums to
+ * grad_out[j]). */
+EXPORT int64_t or_votes(const or_scene* S, const or_lights* Ls, const float* params, uint64_t seed,
+                        int64_t paths_per_layout, int max_hits, int64_t limit_per_light, int n_threads,
+                        const or_proposal* prop, const float* dOdE, int gl, int param, double* vote_out,
+                        double* grad_out)
+{
+    int j = 0;
+    while (Ls->layout_offsets[j + 1] <= gl) ++j;
+    int l0 = Ls->layout_offsets[j], l1 = Ls->layout_offsets[j + 1];
+    memset(vote_out, 0, (size_t)S->n_texels * sizeof(double));
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+    olight L;
+    int64_t nl = paths_of_light(paths_per_layout, l1 - l0, gl - l0);
+    light_setup(Ls, params, gl, nl, &L);
+    int64_t lim = (limit_per_light > 0 && limit_per_light < nl) ? limit_per_light : nl;
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+    int64_t m = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : a0, a1, a2, a3, a4, a5, m)
+#endif
+    for (int64_t i = 0; i < lim; ++i) {
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        path_io io;
+        memset(&io, 0, sizeof(io));
+        io.g = dOdE + (int64_t)j * S->n_texels;
+        io.acc = acc;
+        io.vote = vote_out;
+        io.vote_param = param;
+        trace_path(S, &L, j, gl - l0, gl, (uint32_t)i, seed, max_hits, prop, &io);
+        a0 += acc[0]; a1 += acc[1]; a2 += acc[2]; a3 += acc[3]; a4 += acc[4]; a5 += acc[5];
+        m += io.misses;
+    }
+    grad_out[0] = a0; grad_out[1] = a1; grad_out[2] = a2; grad_out[3] = a3; grad_out[4] = a4; grad_out[5] = a5;
+    return m;
 }
 
 /* Hit sequences (primitive and texel per hit, -1 = none) of paths

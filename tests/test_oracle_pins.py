@@ -417,6 +417,114 @@ def test_direct_gradient_vs_quadrature(oracle_lib, kind):
 
 
 # --------------------------------------------------------------------------
+# gradient-contribution map (Sec. gradVis)
+# --------------------------------------------------------------------------
+
+def test_votes_power_direct_equals_forward(oracle_lib):
+    """B = 1, parameter P: every path's contribution is g_k invA_k Phi_r / P,
+    so the map equals g_k E_k / P with E_k from the primal splat."""
+    sc = li.plane_scene(half=3.0, res=24)
+    p = np.array([[0.3, -0.2, 1.4, 0.2, -0.1, 40.0]], np.float32)
+    lights = make_lights([SPOT], [2.5], [(0, 0)], [0], p)
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    N, seed = 1 << 16, 0x5150
+    g = np.random.default_rng(3).uniform(-1, 1, (1, sc.n_texels)).astype(np.float32)
+    S, _ = oracle_lib.forward(osc, ol, p, seed, N, 1)
+    E = oracle_lib.fixed_to_float(S)[0].astype(np.float64)
+    vote, grad, _ = oracle_lib.votes(osc, ol, p, seed, N, 1, g, 0, 5)
+    ref = g[0].astype(np.float64) * E / float(p[0, 5])
+    assert (E > 0).sum() > 300
+    assert np.all(np.abs(vote - ref) <= 2e-6 * np.abs(ref) + 1e-15)
+    assert abs(vote.sum() / grad[5] - 1) < 1e-9
+
+
+def test_votes_partition_the_gradient(oracle_lib):
+    """Box room, B = 3, every parameter: the map is the first-hit texel
+    histogram of the per-path contributions (recorded path by path) and sums
+    to the light's gradient."""
+    c1 = li.box_room()
+    sc, lights = c1["scene"], c1["lights"]
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    N, B, seed = 1 << 13, 3, 0x77
+    g = np.random.default_rng(5).normal(size=(1, sc.n_texels)).astype(np.float32)
+    grad_all, _ = oracle_lib.adjoint(osc, ol, lights.params, seed, N, B, g)
+    prim, tex, contrib = oracle_lib.record(osc, ol, lights.params, seed, N, B, 0, 0, 0, N, g)
+    first = tex[:, 0]
+    for j in range(6):
+        vote, grad, _ = oracle_lib.votes(osc, ol, lights.params, seed, N, B, g, 0, j)
+        assert np.allclose(grad, grad_all[0], rtol=1e-12, atol=0)
+        ok = first >= 0
+        ref = np.bincount(first[ok], weights=contrib[ok, j].astype(np.float64), minlength=sc.n_texels)
+        scale = np.abs(contrib[:, j]).astype(np.float64).sum()
+        assert np.all(np.abs(vote - ref) <= 1e-12 * scale)
+        assert abs(vote.sum() - grad[j]) <= 1e-12 * scale
+        assert np.count_nonzero(vote) == np.count_nonzero(np.bincount(first[ok], minlength=sc.n_texels))
+
+
+def test_votes_sit_at_the_first_hit(oracle_lib):
+    """A target that only indirect light reaches: a downward spot under a
+    ceiling, dO/dE non-zero on the ceiling alone.  The contributions are
+    drawn on the floor, where the paths first hit, and none on the ceiling."""
+    sb = li.SceneBuilder()
+    sb.quads([-8.0, -8.0, 0.0], [16.0, 0, 0], [0, 16.0, 0], 0.6, res=(16, 16))
+    sb.quads([-4.0, -4.0, 2.5], [8.0, 0, 0], [0, 8.0, 0], 0.7, res=(16, 16))
+    sc = sb.build("floor_ceiling", fixed_res=(16, 16))
+    p = np.array([[0.5, -0.3, 1.5, 0.2, 0.1, 100.0]], np.float32)
+    lights = make_lights([SPOT], [3.0], [(0, 0)], [0], p)
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    g = np.zeros((1, sc.n_texels), np.float32)
+    g[0, 256:] = 1.0
+    vote, grad, _ = oracle_lib.votes(osc, ol, p, 0x99, 1 << 15, 2, g, 0, 0)
+    assert np.all(vote[256:] == 0.0)
+    assert np.count_nonzero(vote[:256]) > 100
+    assert grad[0] != 0.0 and abs(vote.sum() / grad[0] - 1) < 1e-9
+
+
+@pytest.mark.parametrize("kind", [SPOT, RECT])
+def test_votes_direct_vs_quadrature_per_texel(oracle_lib, kind):
+    """B = 1: the expected map is g_k times the derivative of the texel's
+    expected irradiance (the texel is fixed, so differentiation passes under
+    the integral over it); checked texel by texel against central differences
+    of the independent quadrature, with the per-texel variance estimated from
+    the recorded paths."""
+    half, res, N = 3.0, 16, 1 << 18
+    n = 2.5
+    size = (0.7, 0.4) if kind == RECT else (0, 0)
+    p = np.array([0.3, -0.2, 1.4, 0.3, -0.2, 40.0])
+    sc = li.plane_scene(half=half, res=res)
+    lights = make_lights([kind], [n], [size], [0], [p])
+    A = float(sc.texel_area()[0])
+    g = np.random.default_rng(9).uniform(0.2, 1.0, sc.n_texels).astype(np.float32)
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    seed = 0xE1
+    _, tex, contrib = oracle_lib.record(osc, ol, lights.params, seed, N, 1, 0, 0, 0, N, g[None])
+    first = tex[:, 0]
+    ok = first >= 0
+    counts = np.bincount(first[ok], minlength=sc.n_texels)
+    m = counts >= 200
+    assert m.sum() > 60
+
+    def expected_E(pp):
+        return cf.plane_hit_probability(kind, n, pp, size, half, res, q_tex=5, q_light=5) * pp[5] / A
+
+    zs = []
+    for j in range(6):
+        vote, _, _ = oracle_lib.votes(osc, ol, lights.params, seed, N, 1, g[None], 0, j)
+        h = 1e-4
+        pp, pm = p.copy(), p.copy()
+        pp[j] += h
+        pm[j] -= h
+        ref = g.astype(np.float64) * (expected_E(pp) - expected_E(pm)) / (2 * h)
+        c = contrib[ok, j].astype(np.float64)
+        var = np.bincount(first[ok], weights=c * c, minlength=sc.n_texels) - vote ** 2 / N
+        z = (vote[m] - ref[m]) / np.sqrt(var[m])
+        assert np.abs(z).max() < 5.5, (j, np.abs(z).max())
+        zs.append(z)
+    z = np.concatenate(zs)
+    assert abs(float((z ** 2).mean()) - 1) < 6 * math.sqrt(2 / z.size) + 0.05
+
+
+# --------------------------------------------------------------------------
 # P6: adjoint vs central finite differences with common random numbers
 # --------------------------------------------------------------------------
 
