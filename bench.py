@@ -351,6 +351,22 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    # gradient-contribution map of one luminaire's x coordinate: the adjoint
+    # kernel with the extra per-path FP64 atomic at the first-hit texel
+    vote = torch.empty(K, dtype=torch.float64, device=dev)
+    vcfg = ctx.cfg(seed, N, B)
+    ctx.gradient_votes(p, g, vcfg, 0, 0, vote=vote, grad=grad)
+    torch.cuda.synchronize()
+    ctx.timing_read()
+    ctx.set_timing(True)
+    for i in range(3):
+        ctx.gradient_votes(p, g, vcfg, 0, 0, vote=vote, grad=grad)
+    torch.cuda.synchronize()
+    ctx.set_timing(False)
+    _, _, v_ms, nv = ctx.timing_read()
+    out["gradient_votes"] = {"kernel_ms": round(v_ms / max(nv, 1), 3), "adj_kernel_ms": round(adj_avg, 3),
+                             "light": 0, "param": "x"}
+    log("gradient votes", out["gradient_votes"])
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(scene, lights, seed, N, B, args.cpu_seconds)

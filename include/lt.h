@@ -162,6 +162,18 @@ int lt_objective(lt_ctx* ctx, const float* d_E, const float* d_Etarget, const fl
 int lt_trace_adjoint(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, const float* d_dOdE,
                      float* d_grad, float* d_bin_hist);
 
+/* Gradient-contribution map (Sec. gradVis): the adjoint pass of
+ * lt_trace_adjoint (same arguments, same d_grad [L,6] f32 output), which also
+ * adds each path's contribution to dO/dp_j, j = `param` in 0..5 (x, y, z,
+ * alpha, beta, P), of the global light `light` into the texel of the path's
+ * first surface hit.  d_vote [K] f64 covers the texels of that light's layout,
+ * is 16-byte aligned and is overwritten; it sums to d_grad[light][param] up
+ * to rounding.  Summation order over paths is not fixed, so the map agrees
+ * with a sequential sum to FP64 rounding only.  LT_EINVAL for a light or
+ * parameter out of range. */
+int lt_gradient_votes(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, const float* d_dOdE,
+                      int32_t light, int32_t param, double* d_vote, float* d_grad);
+
 /* Hit sequences of paths [first, first+count) of light `light` (index within
  * its layout `layout`): d_prim / d_texel [count, max_hits] i32, -1 where the
  * path ended.  With d_dOdE, d_contrib [count,6] f32 receives each path's

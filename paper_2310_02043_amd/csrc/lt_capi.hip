@@ -658,6 +658,38 @@ int lt_trace_adjoint(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     return run_seq(c, graph, make_key(c, 2, cfg, {d_params, d_dOdE, d_grad, d_bin_hist}), body);
 }
 
+int lt_gradient_votes(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, const float* d_dOdE,
+                      int32_t light, int32_t param, double* d_vote, float* d_grad)
+{
+    int rc = check_cfg(c, cfg);
+    if (rc) return rc;
+    if (!d_params || !d_dOdE || !d_grad || !d_vote) return fail(c, LT_EINVAL, "NULL device buffer");
+    if ((uintptr_t)d_vote & 15) return fail(c, LT_EINVAL, "d_vote must be 16-byte aligned");
+    if (light < 0 || light >= c->L) return fail(c, LT_EINVAL, "light out of range");
+    if (param < 0 || param > 5) return fail(c, LT_EINVAL, "parameter out of range");
+    HIPCHK(c, hipSetDevice(c->device));
+    const long long blocks = trace_blocks(c);
+    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    if (rc) return rc;
+    TraceArgs a = trace_args(c, cfg);
+    a.g = d_dOdE;
+    a.partials = c->d_partials;
+    a.vote = d_vote;
+    a.vote_light = light;
+    a.vote_param = param;
+    const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
+    auto body = [&](hipStream_t st) -> hipError_t {
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        if (e == hipSuccess) e = launch_clear((long long*)d_vote, c->K, st);
+        if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = launch_grad_reduce(c->d_partials, c->d_range, c->L, d_grad, st);
+        return e;
+    };
+    return run_seq(c, graph,
+                   make_key(c, 4, cfg, {d_params, d_dOdE, d_grad, d_vote, (const void*)(uintptr_t)(light * 8 + param)}),
+                   body);
+}
+
 int lt_record_paths(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int32_t layout, int32_t light,
                     int64_t first, int64_t count, int32_t* d_prim, int32_t* d_texel, const float* d_dOdE,
                     float* d_contrib)

@@ -52,6 +52,10 @@ struct TraceArgs {
     float alpha_plain;
     float* bin_hist;            // adjoint: [L,1024] histogram of |c_r / sigma| (may be null)
     const float* inv_sigma;     // [L,6]
+    // adjoint: gradient-contribution map of one light and parameter (may be null)
+    double* vote;               // [K] texels of the light's layout
+    int vote_light;             // global light index
+    int vote_param;             // 0..5
 };
 
 struct RecordArgs {

@@ -423,9 +423,12 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
     // adjoint per-lane state read once per path (first-hit derivative
     // factors, running contribution sums), kept in LDS instead of registers
     __shared__ float s_adj[ADJ ? WPB * 12 * 64 : 1];
+    // adjoint with a gradient-contribution map: texel of the first hit
+    __shared__ int s_k1[ADJ ? WPB * 64 : 1];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     float* adj = s_adj + (ADJ ? wib * 12 * 64 + lane : 0);
+    int* k1 = s_k1 + (ADJ ? wib * 64 + lane : 0);
     const long long blk = xcd_block(blockIdx.x, gridDim.x, a.xcd_remap);
     const long long gw = blk * WPB + wib;
     if (gw >= a.n_tiles) return;
@@ -447,6 +450,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
         const float* cdf = prop_on ? a.prop_cdf + 1024 * (long long)ti.x : nullptr;
         const int* guide = prop_on ? a.prop_guide + 1025 * (long long)ti.x : nullptr;
         float* hist = (ADJ && a.bin_hist != nullptr && L.type != 0) ? a.bin_hist + 1024 * (long long)ti.x : nullptr;
+        double* vote = (ADJ && a.vote != nullptr && ti.x == a.vote_light) ? a.vote : nullptr;
 
         int next = 0;          // paths of this tile handed out so far (uniform)
         bool alive = false;    // lane holds a path
@@ -539,6 +543,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                             first_hit_dlog(L, hi.x, v3(r.ox, r.oy, r.oz), hi.no, au, av, dl);
 #pragma unroll
                             for (int c = 0; c < 6; ++c) adj[c * 64] = phi_r * dl[c];
+                            if (vote) *k1 = (int)hi.k;
                         }
                     }
                     if (h >= B) {
@@ -566,6 +571,8 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                             }
                         }
                         if (hist && ebin >= 0) atomicAdd(hist + ebin, m2 * wq);
+                        // the path's share of dO/dp_j, placed at its first hit
+                        if (vote) unsafeAtomicAdd(vote + *k1, (double)(s_r * adj[a.vote_param * 64]));
                     }
                     alive = false;
                 }

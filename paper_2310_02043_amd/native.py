@@ -20,7 +20,8 @@ LT_FLAG_GRAPH, LT_FLAG_PROPOSAL = 1, 2
 
 EXPORTED = [
     "lt_create", "lt_destroy", "lt_last_error", "lt_set_stream", "lt_sync", "lt_scene_upload",
-    "lt_set_lights", "lt_trace_forward", "lt_objective", "lt_trace_adjoint", "lt_record_paths",
+    "lt_set_lights", "lt_trace_forward", "lt_objective", "lt_trace_adjoint", "lt_gradient_votes",
+    "lt_record_paths",
     "lt_trace_stats", "lt_get_tuning", "lt_set_tuning", "lt_autotune", "lt_info_get", "lt_set_timing",
     "lt_timing_read", "lt_proposal_set_table", "lt_proposal_get_table", "lt_proposal_set_scale",
     "lt_proposal_mlp_infer",
@@ -83,6 +84,7 @@ def load():
     L.lt_trace_forward.argtypes = [P, C.POINTER(TraceCfg), P, P, P]
     L.lt_objective.argtypes = [P, P, P, P, I64, P, P]
     L.lt_trace_adjoint.argtypes = [P, C.POINTER(TraceCfg), P, P, P, P]
+    L.lt_gradient_votes.argtypes = [P, C.POINTER(TraceCfg), P, P, I32, I32, P, P]
     L.lt_record_paths.argtypes = [P, C.POINTER(TraceCfg), P, I32, I32, I64, I64, P, P, P, P]
     L.lt_trace_stats.argtypes = [P, C.POINTER(TraceCfg), P, P, C.POINTER(I64)]
     L.lt_get_tuning.argtypes = [P, C.POINTER(Tuning)]
@@ -222,6 +224,23 @@ class Context:
         self._check(self.lib.lt_trace_adjoint(self.h, C.byref(cfg), _ptr(params), _ptr(dOdE), _ptr(grad),
                                               _ptr(bin_hist)))
         return grad
+
+    def gradient_votes(self, params, dOdE, cfg, light, param, vote=None, grad=None):
+        """Gradient-contribution map of global light `light` and parameter
+        `param` (0..5): returns (vote [K] float64, grad [L,6] float32)."""
+        torch = self._torch
+        self._dev(params, torch.float32, (self.n_lights, 6))
+        self._dev(dOdE, torch.float32, (self.n_layouts, self.n_texels))
+        if vote is None:
+            vote = torch.empty(self.n_texels, dtype=torch.float64, device=params.device)
+        self._dev(vote, torch.float64, (self.n_texels,))
+        if grad is None:
+            grad = torch.empty((self.n_lights, 6), dtype=torch.float32, device=params.device)
+        self._dev(grad, torch.float32, (self.n_lights, 6))
+        self._stream()
+        self._check(self.lib.lt_gradient_votes(self.h, C.byref(cfg), _ptr(params), _ptr(dOdE), int(light),
+                                               int(param), _ptr(vote), _ptr(grad)))
+        return vote, grad
 
     def record_paths(self, params, cfg, layout, light, first, count, dOdE=None):
         torch = self._torch
