@@ -34,7 +34,7 @@ LIGHT_DTYPE = np.dtype([
 ], align=True)
 assert LIGHT_DTYPE.itemsize == 20
 
-POINT, SPOT, RECT = 0, 1, 2
+POINT, SPOT, RECT, SOFT = 0, 1, 2, 3   # SOFT: soft-edged spot, size = (inner, outer) cone half-angle
 
 
 @dataclasses.dataclass

@@ -28,6 +28,9 @@
  *     supplement, generalised to a cos^n lobe); at path end
  *     dO/dp += dO/dPhi_r * dPhi_r/dp (Eq. objGradAdjoint, first term; the BRDF
  *     terms vanish for Lambertian surfaces, Eq. dLdp discussion).
+ *   - Luminaires: point, cos^n spot, cos^n rectangle, and the supplement's
+ *     soft-edged spot (quadratic fall-off in cos theta between the inner and
+ *     outer cone, directions uniform over the outer cap, weighted).
  *   - Gradient-contribution map (Sec. gradVis): the same adjoint pass over
  *     one light's paths, each path adding its contribution to dO/dp_j into
  *     the texel of its first surface hit.
@@ -225,9 +228,9 @@ typedef struct {
 } or_scene;
 
 typedef struct {
-    const int32_t* type;      /* [L] 0 point, 1 spot, 2 rectangle */
+    const int32_t* type;      /* [L] 0 point, 1 spot (cos^n), 2 rectangle, 3 soft-edged spot */
     const float* lobe_n;      /* [L] */
-    const float* size;        /* [L,2] */
+    const float* size;        /* [L,2] rectangle w, h; soft-edged spot: inner, outer cone angle */
     const int32_t* layout_offsets; /* [n_layouts+1] */
     int32_t n_lights;
     int32_t n_layouts;
@@ -458,6 +461,7 @@ EXPORT void or_intersect_batch(const or_scene* S, const float* rays, int64_t n, 
 typedef struct {
     int type;
     float n, w, h;
+    float ci, co;          /* soft-edged spot: cosines of the inner and outer cone */
     float c[3], d[3], t[3], b[3];
     float dd_da[3], dd_db[3], dt_db[3], db_da[3], db_db[3];
     float P, phi_r;
@@ -487,6 +491,22 @@ static void light_setup(const or_lights* Ls, const float* params, int gl, int64_
     L->P = p[5];
     L->n_paths = n_paths;
     L->phi_r = p[5] / (float)n_paths;
+    L->ci = 1.0f;
+    L->co = 0.0f;
+    if (L->type == 3) {
+        /* soft-edged spot (supplement, spot light): constant intensity inside
+         * the inner cone, a = ((cos - cos_out) / (cos_in - cos_out))^2 out to
+         * the outer cone, nothing beyond.  Directions are drawn uniformly
+         * over the outer cone's cap and weighted by a, so with P the total
+         * flux, Phi_r = (P / N) a (1 - cos_out) / ((1 - cos_in) + (cos_in - cos_out) / 3). */
+        double si_d, ci_d, so_d, co_d;
+        or_sincos_f64((double)L->w, &si_d, &ci_d);
+        or_sincos_f64((double)L->h, &so_d, &co_d);
+        L->ci = (float)ci_d;
+        L->co = (float)co_d;
+        float kcap = (float)((1.0 - co_d) / ((1.0 - ci_d) + (ci_d - co_d) / 3.0));
+        L->phi_r = L->phi_r * kcap;
+    }
 }
 
 static int64_t paths_of_light(int64_t n_layout, int n_in_layout, int l)
@@ -532,14 +552,24 @@ static void first_hit_dlog(const olight* L, const float* x1, const float* y, con
     }
     float ce = dot3(L->d, w);
     if (ce <= 1e-6f) return;
-    float ka = L->n / (r * ce);
+    /* ka, kd: the derivative of log I along cos(theta) = d.w, divided by r
+     * and not; cos^n lobe: n / cos, soft-edged spot: 2 / (cos - cos_out) in
+     * its fall-off ring and 0 inside the inner cone */
+    float ka, kd;
+    if (L->type == 3) {
+        float lg = (ce > L->co && ce < L->ci) ? 2.0f / (ce - L->co) : 0.0f;
+        ka = lg / r;
+        kd = lg;
+    } else {
+        ka = L->n / (r * ce);
+        kd = L->n / ce;
+    }
     for (int c = 0; c < 3; ++c) {
         float t1 = -((L->d[c] - ce * w[c]) * ka);
         float t2 = (n1[c] + c1 * w[c]) * k1;
         float t3 = w[c] * k3;
         G[c] = (t1 + t2) + t3;
     }
-    float kd = L->n / ce;
     float ra = dot3(L->dd_da, w) * kd;
     float rb = dot3(L->dd_db, w) * kd;
     if (L->type == 2) {
@@ -559,7 +589,7 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
                        int B, const or_proposal* prop_in, path_io* io)
 {
     const uint32_t stream = ((uint32_t)layout << 16) | (uint32_t)l_local;
-    const or_proposal* prop = (prop_in && prop_in->pdf && L->type != 0) ? prop_in : NULL;
+    const or_proposal* prop = (prop_in && prop_in->pdf && (L->type == 1 || L->type == 2)) ? prop_in : NULL;
     float phi_r = L->phi_r;
     int ebin = -1;
     float wq = 0.0f;
@@ -575,6 +605,18 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
         float sp, cp;
         or_sincos2pi(u[3], &sp, &cp);
         dir[0] = rr * cp; dir[1] = rr * sp; dir[2] = z;
+    } else if (L->type == 3) {
+        /* uniform over the outer cone's cap, weighted by the fall-off */
+        float ct = 1.0f - u[2] * (1.0f - L->co);
+        float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+        float sp, cp;
+        or_sincos2pi(u[3], &sp, &cp);
+        float a = st * cp, bb = st * sp;
+        if (ct < L->ci) {
+            float f = (ct - L->co) / (L->ci - L->co);
+            phi_r = phi_r * (f * f);
+        }
+        for (int c = 0; c < 3; ++c) dir[c] = (a * L->t[c] + bb * L->b[c]) + ct * L->d[c];
     } else {
         float ct = 0.0f;
         if (u[2] > 0.0f) ct = or_exp2(or_log2(u[2]) / (L->n + 1.0f));

@@ -5,6 +5,8 @@ written from radiometry: solid angles of rectangles, Gauss-Legendre
 integration of an emitter's irradiance over texels, and the log-irradiance
 of a luminaire at a fixed receiver point (for derivative checks).
 """
+import math
+
 import numpy as np
 
 
@@ -63,15 +65,29 @@ def plane_texels(half, res):
     return X0.ravel(), X1.ravel(), Y0.ravel(), Y1.ravel()
 
 
-def lobe_density(kind, n, d, w):
-    """Direction pdf of a luminaire (per steradian) for unit directions w."""
+def soft_profile(c, th_in, th_out):
+    """Soft-edged spot: relative intensity as a function of cos(theta), and
+    its integral over the sphere divided by 2 pi."""
+    ci, co = math.cos(th_in), math.cos(th_out)
+    a = np.where(c >= ci, 1.0, np.where(c > co, ((c - co) / (ci - co)) ** 2, 0.0))
+    # int_{co}^{1} a dc = (1 - ci) + (ci - co) / 3
+    return a, (1 - ci) + (ci - co) / 3
+
+
+def lobe_density(kind, n, d, w, size=None, profile_power=1):
+    """Direction pdf of a luminaire (per steradian) for unit directions w
+    (soft-edged spot with profile_power 2: its profile squared over the same
+    normalisation, for second moments)."""
     if kind == 0:
         return np.full(w.shape[:-1], 1.0 / (4 * np.pi))
     c = w @ d
+    if kind == 3:
+        a, norm = soft_profile(c, size[0], size[1])
+        return a ** profile_power / (2 * np.pi * norm)
     return np.where(c > 0, (n + 1) / (2 * np.pi) * np.clip(c, 0, None) ** n, 0.0)
 
 
-def plane_hit_probability(kind, n, p, size, half, res, q_tex=6, q_light=4):
+def plane_hit_probability(kind, n, p, size, half, res, q_tex=6, q_light=4, profile_power=1):
     """Probability that one emitted path first hits each texel of the z=0
     plane_scene (texel order k = j*res + i)."""
     c = np.asarray(p[:3], np.float64)
@@ -99,13 +115,13 @@ def plane_hit_probability(kind, n, p, size, half, res, q_tex=6, q_light=4):
         v = np.stack([X - o[0], Y - o[1], -np.full_like(X, o[2])], -1)
         r = np.linalg.norm(v, axis=-1)
         w = v / r[..., None]
-        dens = lobe_density(kind, n, d, w)
+        dens = lobe_density(kind, n, d, w, size, profile_power)
         cos_i = o[2] / r          # receiver normal +z, emitter above
         prob += ow * np.sum(dens * cos_i / r ** 2 * wq[None, :] * area, axis=1)
     return prob
 
 
-def log_irradiance(kind, n, p, x1, n1, au=0.0, av=0.0):
+def log_irradiance(kind, n, p, x1, n1, au=0.0, av=0.0, size=None):
     """log of the first-hit irradiance kernel at receiver x1 with unit normal
     n1 (facing the light), up to p-independent constants: a luminaire of power
     P with direction pdf ~ cos^n about its axis, origin c + a_u t + a_v b."""
@@ -116,6 +132,8 @@ def log_irradiance(kind, n, p, x1, n1, au=0.0, av=0.0):
     r = np.linalg.norm(v)
     w = v / r
     val = np.log(p[5]) + np.log(-np.dot(n1, w)) - 2 * np.log(r)
-    if kind != 0:
+    if kind == 3:
+        val += np.log(soft_profile(np.dot(d, w), size[0], size[1])[0])
+    elif kind != 0:
         val += n * np.log(np.dot(d, w))
     return val

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import lt_inputs as li
-from lt_inputs.scenes import make_lights, POINT, SPOT, RECT
+from lt_inputs.scenes import make_lights, POINT, SPOT, RECT, SOFT
 import closed_forms as cf
 
 
@@ -194,6 +194,54 @@ def test_rect_light_over_plane(oracle_lib):
     _binomial_check(counts, prob, N)
 
 
+def test_soft_spot_over_plane(oracle_lib):
+    """Soft-edged spot: directions uniform over the outer cap, each path's
+    flux weighted by the fall-off.  The flux reaching each texel has mean
+    P * (its share of the normalised intensity profile) and variance
+    (P^2/N) (k_cap m2_k - m_k^2), both by quadrature of the profile."""
+    half, res, N = 2.0, 40, 1 << 20
+    th = (0.3, 0.75)
+    p = [0.4, -0.3, 1.3, 0.25, -0.15, 70.0]
+    sc = li.plane_scene(half=half, res=res)
+    lights = make_lights([SOFT], [0.0], [th], [0], [p])
+    S, _ = oracle_lib.forward(oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights), lights.params,
+                              0x50F7, N, 1)
+    flux = oracle_lib.fixed_to_float(S)[0].astype(np.float64) * sc.texel_area().astype(np.float64)
+    m1 = cf.plane_hit_probability(SOFT, 0.0, p, th, half, res, q_tex=6)
+    # second moment: the same quadrature with the profile squared
+    ci, co = math.cos(th[0]), math.cos(th[1])
+    _, norm = cf.soft_profile(1.0, *th)
+    kcap = (1 - co) / norm
+    m2 = cf.plane_hit_probability(SOFT, 0.0, p, th, half, res, q_tex=6, profile_power=2)
+    var = p[5] ** 2 / N * (kcap * m2 - m1 ** 2)
+    m = m1 * N >= 50
+    assert m.sum() > 300
+    z = (flux[m] - p[5] * m1[m]) / np.sqrt(var[m])
+    assert np.abs(z).max() < 5.5, np.abs(z).max()
+    assert abs(float((z ** 2).sum()) - m.sum()) < 6 * math.sqrt(2 * m.sum())
+
+
+def test_soft_spot_total_flux(oracle_lib):
+    """In a closed box every first hit lands: the splatted flux is the sum of
+    the per-path weights, whose mean is P (the normalisation of the profile)
+    and whose variance is (P^2/N)(k_cap m2 - 1) with the closed forms
+    int a dc = (1 - ci) + (ci - co)/3 and int a^2 dc = (1 - ci) + (ci - co)/5."""
+    N, P = 1 << 20, 30.0
+    for th in ((0.2, 0.6), (0.0, 1.0), (0.5, 0.55)):
+        sc = li.closed_box()
+        lights = make_lights([SOFT], [0.0], [th], [0], [[1.0, 0.75, 0.5, 0.3, -0.2, P]])
+        S, misses = oracle_lib.forward(oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights),
+                                       lights.params, 0x77 + int(th[1] * 100), N, 1)
+        assert misses == 0
+        total = float(np.sum(S[0].astype(np.float64) * 2.0 ** -32 * sc.texel_area().astype(np.float64)))
+        ci, co = math.cos(th[0]), math.cos(th[1])
+        norm = (1 - ci) + (ci - co) / 3
+        m2 = ((1 - ci) + (ci - co) / 5) / norm
+        kcap = (1 - co) / norm
+        sigma = P * math.sqrt((kcap * m2 - 1) / N)
+        assert abs(total - P) < 5 * sigma + 1e-6 * P, (th, total, sigma)
+
+
 def test_cosine_bounce_floor_to_ceiling(oracle_lib):
     """Second hits on a parallel ceiling: floor first-hit density times the
     differential form factor to each ceiling texel (cosine-weighted bounce, rho)."""
@@ -298,12 +346,13 @@ def test_objective_definition(oracle_lib):
 # derivatives: first-hit dlog vs FD of an independent log-irradiance
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("kind", [POINT, SPOT, RECT])
+@pytest.mark.parametrize("kind", [POINT, SPOT, RECT, SOFT])
 def test_first_hit_derivative(oracle_lib, kind):
     rng = np.random.default_rng(10 + kind)
-    n = 0.0 if kind == POINT else 3.5
-    size = (0.6, 0.4) if kind == RECT else (0, 0)
-    for _ in range(20):
+    n = 0.0 if kind in (POINT, SOFT) else 3.5
+    size = {RECT: (0.6, 0.4), SOFT: (0.3, 1.2)}.get(kind, (0, 0))
+    done = 0
+    while done < 20:
         p = [rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(1.5, 2.5),
              rng.uniform(-0.4, 0.4), rng.uniform(-0.4, 0.4), rng.uniform(10, 100)]
         if kind == POINT:
@@ -313,10 +362,16 @@ def test_first_hit_derivative(oracle_lib, kind):
         pf = np.asarray(lights.params[0], np.float64)
         x1 = np.array([rng.uniform(-1.5, 1.5), rng.uniform(-1.5, 1.5), 0.0])
         n1 = np.array([0.0, 0.0, 1.0])
-        au = rng.uniform(-0.5, 0.5) * size[0]
-        av = rng.uniform(-0.5, 0.5) * size[1]
+        au = rng.uniform(-0.5, 0.5) * size[0] if kind == RECT else 0.0
+        av = rng.uniform(-0.5, 0.5) * size[1] if kind == RECT else 0.0
         d, t, b = cf.frame(pf[3], pf[4])
         y = pf[:3] + au * t + av * b
+        if kind == SOFT:
+            # inside the outer cone and away from the inner cone's kink
+            cw = float(np.dot(d, (x1 - y) / np.linalg.norm(x1 - y)))
+            if cw <= math.cos(size[1]) + 1e-3 or abs(cw - math.cos(size[0])) < 1e-3:
+                continue
+        done += 1
         dl = oracle_lib.first_hit_dlog(ol, lights.params, 0, x1.astype(np.float32), y.astype(np.float32),
                                        n1.astype(np.float32), au, av).astype(np.float64)
         for c in range(6):
@@ -324,8 +379,8 @@ def test_first_hit_derivative(oracle_lib, kind):
             pp, pm = pf.copy(), pf.copy()
             pp[c] += hstep
             pm[c] -= hstep
-            fd = (cf.log_irradiance(kind, n, pp, x1, n1, au, av) -
-                  cf.log_irradiance(kind, n, pm, x1, n1, au, av)) / (2 * hstep)
+            fd = (cf.log_irradiance(kind, n, pp, x1, n1, au, av, size) -
+                  cf.log_irradiance(kind, n, pm, x1, n1, au, av, size)) / (2 * hstep)
             if kind == POINT and c in (3, 4):
                 assert dl[c] == 0.0
                 continue
@@ -382,11 +437,11 @@ def test_record_matches_adjoint(oracle_lib):
 # P7: direct-only gradient vs quadrature derivative (plane, B = 1)
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("kind", [POINT, SPOT, RECT])
+@pytest.mark.parametrize("kind", [POINT, SPOT, RECT, SOFT])
 def test_direct_gradient_vs_quadrature(oracle_lib, kind):
     half, res, N = 3.0, 24, 1 << 18
-    n = 0.0 if kind == POINT else 2.5
-    size = (0.7, 0.4) if kind == RECT else (0, 0)
+    n = 2.5 if kind in (SPOT, RECT) else 0.0
+    size = {RECT: (0.7, 0.4), SOFT: (0.35, 0.9)}.get(kind, (0, 0))
     p = np.array([0.3, -0.2, 1.4, 0.3 if kind else 0.0, -0.2 if kind else 0.0, 40.0])
     sc = li.plane_scene(half=half, res=res)
     lights = make_lights([kind], [n], [size], [0], [p])
