@@ -74,7 +74,13 @@ typedef struct {
 /* Static luminaire attributes.  type: 0 isotropic point light (Phi_r = P/N),
  * 1 spot with radiant intensity P (n+1)/(2 pi) cos^n about its axis,
  * 2 rectangle size_w x size_h with the same cos^n lobe per unit area
- * (n = 1 is the paper's cosine area light).  Lights are grouped by layout. */
+ * (n = 1 is the paper's cosine area light), 3 soft-edged spot (supplement,
+ * spot light): constant intensity inside the cone of half-angle size_w,
+ * falling off as ((cos - cos_out) / (cos_in - cos_out))^2 out to size_h
+ * (0 <= size_w < size_h <= pi/2, lobe_n 0), directions uniform over the
+ * outer cone and weighted.  P is always the total emitted flux.  The
+ * learned emission proposal applies to types 1 and 2 only.  Lights are
+ * grouped by layout. */
 typedef struct {
     int32_t type;
     float lobe_n;
@@ -158,7 +164,8 @@ int lt_objective(lt_ctx* ctx, const float* d_E, const float* d_Etarget, const fl
  * `cfg` (same seed = correlated evaluation) with d_dOdE [n_layouts,K] and
  * writes d_grad [L,6] f32 = dO/dp.  d_bin_hist [L,1024] f32 (may be NULL,
  * overwritten) receives per-light adjoint magnitudes binned by emission
- * direction (see lt_proposal_set_scale); rows of point lights stay 0. */
+ * direction (see lt_proposal_set_scale); rows of point lights and
+ * soft-edged spots stay 0. */
 int lt_trace_adjoint(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, const float* d_dOdE,
                      float* d_grad, float* d_bin_hist);
 

@@ -554,10 +554,12 @@ int lt_set_lights(lt_ctx* c, const lt_light_static* h_lights, int32_t n_lights, 
     for (int j = 0; j < n_layouts; ++j)
         for (int l = h_offs[j]; l < h_offs[j + 1]; ++l) {
             const lt_light_static& s = h_lights[l];
-            if (s.type < 0 || s.type > 2) return fail(c, LT_EINVAL, "unknown light type");
+            if (s.type < 0 || s.type > 3) return fail(c, LT_EINVAL, "unknown light type");
             if (s.layout != j) return fail(c, LT_EINVAL, "light layout does not match the offsets");
-            if (!(s.lobe_n >= 0.0f) || !isfinite(s.lobe_n) || (s.type == 0 && s.lobe_n != 0.0f))
+            if (!(s.lobe_n >= 0.0f) || !isfinite(s.lobe_n) || ((s.type == 0 || s.type == 3) && s.lobe_n != 0.0f))
                 return fail(c, LT_EINVAL, "invalid lobe exponent");
+            if (s.type == 3 && !(s.size_w >= 0.0f && s.size_h > s.size_w && s.size_h <= 1.5707963f))
+                return fail(c, LT_EINVAL, "soft-edged spot needs 0 <= inner < outer <= pi/2");
             if (s.type == 2 && !(s.size_w > 0.0f && s.size_h > 0.0f && isfinite(s.size_w) && isfinite(s.size_h)))
                 return fail(c, LT_EINVAL, "invalid rectangle size");
             si[l] = make_int4(s.type, j, l - h_offs[j], 0);

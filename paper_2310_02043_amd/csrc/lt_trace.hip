@@ -209,6 +209,23 @@ __device__ __forceinline__ void emit(const DevLight& L, uint32_t pid, uint32_t s
         dir = v3(rr * cp, rr * sp, z);
         return;
     }
+    if (L.type == 3) {
+        // soft-edged spot: uniform over the outer cone's cap (L.h = its
+        // cosine), the flux weighted by the fall-off towards it (L.w = the
+        // inner cone's cosine)
+        float sp, cp;
+        sincos_2pi(u3, sp, cp);
+        const float ct = 1.0f - u2 * (1.0f - L.h);
+        const float st = __builtin_sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+        const float a = st * cp, bb = st * sp;
+        if (ct < L.w) {
+            const float f = (ct - L.h) / (L.w - L.h);
+            phi = phi * (f * f);
+        }
+        dir = v3((a * L.t[0] + bb * L.b[0]) + ct * L.d[0], (a * L.t[1] + bb * L.b[1]) + ct * L.d[1],
+                 (a * L.t[2] + bb * L.b[2]) + ct * L.d[2]);
+        return;
+    }
     // Component choice first: a sample from the learned cells never needs
     // the plain lobe's direction, only its density.
     bool plain = true;
@@ -333,11 +350,20 @@ __device__ __forceinline__ void first_hit_dlog(const DevLight& L, V3 x1, V3 y, V
     const V3 d = v3(L.d[0], L.d[1], L.d[2]);
     const float ce = dot(d, w);
     if (ce <= 1e-6f) return;
-    const float ka = L.n / (r * ce);
+    // derivative of log I along cos(theta), over r and not: n / cos for the
+    // cos^n lobe; 2 / (cos - cos_out) in the soft-edged spot's fall-off ring
+    float ka, kd;
+    if (L.type == 3) {
+        const float lg = (ce > L.h && ce < L.w) ? 2.0f / (ce - L.h) : 0.0f;
+        ka = lg / r;
+        kd = lg;
+    } else {
+        ka = L.n / (r * ce);
+        kd = L.n / ce;
+    }
     const V3 G = v3((-((d.x - ce * w.x) * ka) + (n1.x + c1 * w.x) * k1) + w.x * k3,
                     (-((d.y - ce * w.y) * ka) + (n1.y + c1 * w.y) * k1) + w.y * k3,
                     (-((d.z - ce * w.z) * ka) + (n1.z + c1 * w.z) * k1) + w.z * k3);
-    const float kd = L.n / ce;
     float ra = dot(v3(L.dd_da[0], L.dd_da[1], L.dd_da[2]), w) * kd;
     float rb = dot(v3(L.dd_db[0], L.dd_db[1], L.dd_db[2]), w) * kd;
     if (L.type == 2) {
@@ -445,11 +471,11 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
         const uint32_t stream_id = ((uint32_t)ti.w << 16) | (uint32_t)L.l_local;
         long long* S = ADJ ? nullptr : a.S + (long long)ti.w * a.K;
         const float* g = ADJ ? a.g + (long long)ti.w * a.K : nullptr;
-        const bool prop_on = a.prop_pdf != nullptr && L.type != 0;
+        const bool prop_on = a.prop_pdf != nullptr && (L.type == 1 || L.type == 2);
         const float* pdf = prop_on ? a.prop_pdf + 1024 * (long long)ti.x : nullptr;
         const float* cdf = prop_on ? a.prop_cdf + 1024 * (long long)ti.x : nullptr;
         const int* guide = prop_on ? a.prop_guide + 1025 * (long long)ti.x : nullptr;
-        float* hist = (ADJ && a.bin_hist != nullptr && L.type != 0) ? a.bin_hist + 1024 * (long long)ti.x : nullptr;
+        float* hist = (ADJ && a.bin_hist != nullptr && (L.type == 1 || L.type == 2)) ? a.bin_hist + 1024 * (long long)ti.x : nullptr;
         double* vote = (ADJ && a.vote != nullptr && ti.x == a.vote_light) ? a.vote : nullptr;
 
         int next = 0;          // paths of this tile handed out so far (uniform)
@@ -631,7 +657,7 @@ __global__ void __launch_bounds__(256) k_record(RecordArgs a)
         float au, av, phi_r;
         int ebin;
         float wq;
-        const bool prop_on = a.prop_pdf != nullptr && L.type != 0;
+        const bool prop_on = a.prop_pdf != nullptr && (L.type == 1 || L.type == 2);
         emit(L, pid, a.stream_id, a.key0, a.key1, prop_on ? a.prop_pdf + 1024 * (long long)a.gl : nullptr,
              prop_on ? a.prop_cdf + 1024 * (long long)a.gl : nullptr,
              prop_on ? a.prop_guide + 1025 * (long long)a.gl : nullptr, a.alpha_plain, false, y, dir, au, av, phi_r,
@@ -710,6 +736,18 @@ __global__ void k_light_setup(const float* __restrict__ params, const int4* __re
     L.w = f4.y;
     L.h = f4.z;
     L.type = i4.x;
+    if (L.type == 3) {
+        // soft-edged spot: w, h carry the cosines of the inner and outer cone
+        // angles; P is the total flux, so Phi_r = (P/N) kcap a(cos) with
+        // kcap = (1 - cos_out) / ((1 - cos_in) + (cos_in - cos_out) / 3)
+        double si_d, ci_d, so_d, co_d;
+        sincos_f64((double)f4.y, si_d, ci_d);
+        sincos_f64((double)f4.z, so_d, co_d);
+        L.w = (float)ci_d;
+        L.h = (float)co_d;
+        const float kcap = (float)((1.0 - co_d) / ((1.0 - ci_d) + (ci_d - co_d) / 3.0));
+        L.phi_r = L.phi_r * kcap;
+    }
     L.layout = i4.y;
     L.l_local = i4.z;
     L.pad0 = 0;

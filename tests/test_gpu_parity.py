@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import lt_inputs as li
-from lt_inputs.scenes import make_lights, POINT, SPOT, RECT
+from lt_inputs.scenes import make_lights, POINT, SPOT, RECT, SOFT
 from tuning_cache import bench_tuning
 
 pytestmark = pytest.mark.gpu
@@ -260,7 +260,7 @@ def test_determinism_and_graph_replay(torch_dev, oracle_lib, graph):
 
 
 @pytest.mark.parametrize("case", ["ragged", "one_path_per_light", "single_hit", "point_closed_box",
-                                  "tiny_scene", "rect_many_lights"])
+                                  "tiny_scene", "rect_many_lights", "soft_spots"])
 def test_edge_cases(torch_dev, oracle_lib, case):
     torch = torch_dev
     if case == "ragged":
@@ -288,6 +288,15 @@ def test_edge_cases(torch_dev, oracle_lib, case):
         sc = sb.build("one_quad", fixed_res=(3, 5))
         lights = make_lights([SPOT], [1.0], [(0, 0)], [0], [[0.0, 0.0, 1.0, 0.0, 0.0, 5.0]])
         ppl, B = 5000, 2
+    elif case == "soft_spots":
+        # the supplement's soft-edged spots: a narrow ring, a pure fall-off
+        # over the hemisphere, a hard-edged cone, beside a cos^n spot
+        sc = li.box_room()["scene"]
+        lights = make_lights([SOFT, SOFT, SOFT, SPOT], [0.0, 0.0, 0.0, 2.0],
+                             [(0.5, 0.55), (0.0, 1.5707963), (0.6, 0.6001), (0, 0)], [0, 0, 0, 0],
+                             [[1.2, 1.1, 2.3, 0.2, -0.1, 40.0], [2.9, 2.0, 1.6, -0.3, 0.2, 25.0],
+                              [2.0, 1.0, 2.4, 0.0, 0.3, 60.0], [3.1, 0.8, 2.2, 0.1, 0.1, 30.0]])
+        ppl, B = (1 << 18) + 3, 4
     else:
         sc = li.box_room()["scene"]
         n = 40

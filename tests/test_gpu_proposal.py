@@ -153,6 +153,49 @@ def test_proposal_sampling_parity(torch_dev, oracle_lib):
     assert err <= 1e-3 and herr <= 1e-4
 
 
+def test_proposal_mixed_light_types(torch_dev, oracle_lib):
+    """Box room with a point light, a cos^n spot, a rectangle and a
+    soft-edged spot under a proposal table: the table applies to the spot and
+    the rectangle only, on both sides; histogram rows of the others stay 0."""
+    from lt_inputs.scenes import make_lights, POINT, SPOT, RECT, SOFT
+    torch = torch_dev
+    sc = li.box_room()["scene"]
+    lights = make_lights([POINT, SPOT, RECT, SOFT], [0.0, 3.0, 1.0, 0.0], [(0, 0), (0, 0), (0.5, 0.3), (0.3, 0.8)],
+                         [0, 0, 0, 0], [[3.0, 2.0, 1.8, 0, 0, 30.0], [1.0, 1.0, 2.2, 0.1, 0.2, 50.0],
+                                        [2.0, 1.5, 2.4, -0.2, 0.3, 70.0], [2.8, 0.9, 2.3, 0.25, -0.1, 40.0]])
+    ctx = office_ctx(torch, sc, lights)
+    rng = np.random.default_rng(8)
+    pdf, cdf = _table(rng, lights.n_lights, lights.static["type"])
+    inv_sigma = rng.uniform(0.5, 2.0, (lights.n_lights, 6)).astype(np.float32)
+    d = lambda a: torch.tensor(a, device="cuda")  # noqa: E731
+    ctx.proposal_set_table(d(pdf), d(cdf))
+    ctx.proposal_set_scale(d(inv_sigma))
+    N, B, seed = 1 << 18, 4, 0x5A5
+    cfg = ctx.cfg(seed, N, B, proposal=True, alpha_plain=0.3)
+    p_d = d(lights.params)
+    E_d, S_d = ctx.trace_forward(p_d, cfg)
+    prop = oracle_lib.Proposal(pdf, cdf, 0.3, inv_sigma=inv_sigma, with_hist=True)
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    S_ref, _ = oracle_lib.forward(osc, ol, lights.params, seed, N, B, proposal=prop)
+    same = float((S_d.cpu().numpy() == S_ref).mean())
+    say(f"  texels bit-identical {same * 100:.4f} %")
+    E_ref = oracle_lib.fixed_to_float(S_ref)
+    assert np.linalg.norm(E_d.cpu().numpy() - E_ref) / np.linalg.norm(E_ref) <= 1e-4
+    _, g_ref = oracle_lib.objective(E_ref, li.painted_target(sc, 2.0)[None], sc.texel_area())
+    grad_ref, _ = oracle_lib.adjoint(osc, ol, lights.params, seed, N, B, g_ref, proposal=prop)
+    hist_d = torch.zeros((lights.n_lights, 1024), device="cuda")
+    grad_d = ctx.trace_adjoint(p_d, d(g_ref), cfg, bin_hist=hist_d)
+    torch.cuda.synchronize()
+    gg = grad_d.cpu().numpy()
+    scale = np.maximum(np.abs(grad_ref), 1e-6 * np.abs(grad_ref).max())
+    err = float(np.max(np.abs(gg - grad_ref) / scale))
+    h = hist_d.cpu().numpy()
+    herr = np.linalg.norm(h - prop.hist) / np.linalg.norm(prop.hist)
+    say(f"  gradient max rel err {err:.2e}; histogram rel-L2 {herr:.2e}")
+    assert err <= 1e-3 and herr <= 1e-4
+    assert not h[0].any() and not h[3].any() and h[1].any() and h[2].any()
+
+
 def test_proposal_unbiased_vs_plain(torch_dev):
     """Mean gradient over 16 seeds with a (deliberately poor) random proposal
     equals the plain tracer's mean within statistical error."""
