@@ -33,7 +33,7 @@ def build(force: bool = True) -> str:
 class _Scene(C.Structure):
     _fields_ = [("verts", C.c_void_p), ("tris", C.c_void_p), ("tri_patch", C.c_void_p),
                 ("n_tris", C.c_int64), ("pf", C.c_void_p), ("pres", C.c_void_p), ("pbase", C.c_void_p),
-                ("n_patches", C.c_int32), ("n_texels", C.c_int64), ("bvh", C.c_void_p)]
+                ("n_patches", C.c_int32), ("n_texels", C.c_int64), ("basis", C.c_int32), ("bvh", C.c_void_p)]
 
 
 class _Proposal(C.Structure):
@@ -109,9 +109,11 @@ def _p(a):
 
 
 class OracleScene:
-    """Holds the scene arrays (and optionally the oracle's own BVH)."""
+    """Holds the scene arrays (and optionally the oracle's own BVH).  basis:
+    "box" (one texel per hit) or "linear" (piecewise-linear nodes at the
+    texel centres, Eq. pwLin)."""
 
-    def __init__(self, scene, use_bvh: bool = False):
+    def __init__(self, scene, use_bvh: bool = False, basis: str = "box"):
         self.scene = scene
         self.verts = np.ascontiguousarray(scene.verts, np.float32)
         self.tris = np.ascontiguousarray(scene.tris, np.int32)
@@ -128,7 +130,8 @@ class OracleScene:
                                            int(self.tris.shape[0]), pad)
         self.c = _Scene(self.verts.ctypes.data, self.tris.ctypes.data, self.tri_patch.ctypes.data,
                         int(self.tris.shape[0]), self.pf.ctypes.data, self.pres.ctypes.data,
-                        self.pbase.ctypes.data, int(self.pf.shape[0]), self.n_texels, self._bvh)
+                        self.pbase.ctypes.data, int(self.pf.shape[0]), self.n_texels,
+                        {"box": 0, "linear": 1}[basis], self._bvh)
 
     def __del__(self):
         if self._bvh is not None and _lib is not None:

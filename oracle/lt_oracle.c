@@ -28,6 +28,9 @@
  *     supplement, generalised to a cos^n lobe); at path end
  *     dO/dp += dO/dPhi_r * dPhi_r/dp (Eq. objGradAdjoint, first term; the BRDF
  *     terms vanish for Lambertian surfaces, Eq. dLdp discussion).
+ *   - Texel basis: box (one texel per hit) or the piecewise-linear basis of
+ *     Eq. pwLin with nodes at the texel centres (bilinear weights, four
+ *     splats per hit, the adjoint gathering with the same weights).
  *   - Luminaires: point, cos^n spot, cos^n rectangle, and the supplement's
  *     soft-edged spot (quadratic fall-off in cos theta between the inner and
  *     outer cone, directions uniform over the outer cap, weighted).
@@ -224,6 +227,7 @@ typedef struct {
     const int64_t* pbase;     /* [P] first texel */
     int32_t n_patches;
     int64_t n_texels;
+    int32_t basis;            /* 0 box (one texel per hit), 1 piecewise-linear nodes at texel centres */
     const void* bvh;          /* or_bvh* or NULL for brute force */
 } or_scene;
 
@@ -711,6 +715,28 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
         if (iv > rv - 1) iv = rv - 1;
         int64_t k = S->pbase[q] + (int64_t)iv * ru + iu;
         float inv_a = pf[15];
+        /* piecewise-linear basis (Eq. pwLin on the texel grid): nodes at the
+         * texel centres, bilinear hats clamped at the patch border so that
+         * they sum to one; the mass-lumped weight of every node is the texel
+         * area (supplement Eq. appdxSpatialCoeffs) */
+        int64_t kb[4];
+        float wb[4];
+        if (S->basis == 1) {
+            float fu = su * (float)ru - 0.5f, fv = sv * (float)rv - 0.5f;
+            float fu0 = floorf(fu), fv0 = floorf(fv);
+            float au1 = fu - fu0, av1 = fv - fv0;
+            float au0 = 1.0f - au1, av0 = 1.0f - av1;
+            int32_t i0 = (int32_t)fu0, j0 = (int32_t)fv0;
+            int32_t i1 = i0 + 1, j1 = j0 + 1;
+            i0 = i0 < 0 ? 0 : (i0 > ru - 1 ? ru - 1 : i0);
+            i1 = i1 < 0 ? 0 : (i1 > ru - 1 ? ru - 1 : i1);
+            j0 = j0 < 0 ? 0 : (j0 > rv - 1 ? rv - 1 : j0);
+            j1 = j1 < 0 ? 0 : (j1 > rv - 1 ? rv - 1 : j1);
+            kb[0] = S->pbase[q] + (int64_t)j0 * ru + i0; wb[0] = au0 * av0;
+            kb[1] = S->pbase[q] + (int64_t)j0 * ru + i1; wb[1] = au1 * av0;
+            kb[2] = S->pbase[q] + (int64_t)j1 * ru + i0; wb[2] = au0 * av1;
+            kb[3] = S->pbase[q] + (int64_t)j1 * ru + i1; wb[3] = au1 * av1;
+        }
         const float* nq = pf + 9;
         float nd = dot3(nq, dir);
         float no[3];
@@ -718,14 +744,27 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
         else { no[0] = -nq[0]; no[1] = -nq[1]; no[2] = -nq[2]; }
         if (io->S) {
             float val = (phi_r * T) * inv_a;
-            long long code = llrintf(val * 4294967296.0f);
+            if (S->basis == 1) {
+                for (int c = 0; c < 4; ++c) {
+                    long long code = llrintf((val * wb[c]) * 4294967296.0f);
 #ifdef _OPENMP
 #pragma omp atomic
 #endif
-            io->S[k] += code;
+                    io->S[kb[c]] += code;
+                }
+            } else {
+                long long code = llrintf(val * 4294967296.0f);
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+                io->S[k] += code;
+            }
         }
         if (io->g) {
-            s_r = s_r + (io->g[k] * inv_a) * T;
+            float gk = io->g[k];
+            if (S->basis == 1)
+                gk = ((wb[0] * io->g[kb[0]] + wb[1] * io->g[kb[1]]) + wb[2] * io->g[kb[2]]) + wb[3] * io->g[kb[3]];
+            s_r = s_r + (gk * inv_a) * T;
             if (h == 1) {
                 k1 = k;
                 float dl[6];

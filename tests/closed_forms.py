@@ -121,6 +121,68 @@ def plane_hit_probability(kind, n, p, size, half, res, q_tex=6, q_light=4, profi
     return prob
 
 
+def linear_node_weights(u, res):
+    """Piecewise-linear hats on a row of `res` texels over [0, 1]: nodes at
+    the texel centres (i + 1/2)/res, the two outermost hats extended flat to
+    the border so that the weights sum to one.  Returns (i0, i1, w0, w1)."""
+    f = u * res - 0.5
+    i0 = np.floor(f)
+    w1 = f - i0
+    i0 = i0.astype(np.int64)
+    return np.clip(i0, 0, res - 1), np.clip(i0 + 1, 0, res - 1), 1.0 - w1, w1
+
+
+def plane_node_moments(kind, n, p, size, half, res, q=4):
+    """First and second moments, per node of the piecewise-linear basis on the
+    z = 0 plane_scene, of one emitted path's first-hit weight w_k(x):
+    m1_k = int phi_k(x) pdf(x) dA, m2_k = int phi_k(x)^2 pdf(x) dA, with pdf
+    the first-hit density per unit area.  Each texel is split at its centre
+    into four cells on which the hats are smooth, each integrated by
+    Gauss-Legendre with q x q points."""
+    c = np.asarray(p[:3], np.float64)
+    d, t, b = frame(p[3], p[4])
+    gx, gw = gauss_legendre(q)
+    h = 2 * half / res
+    # sub-cell corners along one axis: every half texel
+    edges = -half + 0.5 * h * np.arange(2 * res + 1)
+    xs = (edges[:-1, None] + 0.5 * h * gx[None, :]).ravel()          # points along x
+    ws = np.broadcast_to(0.5 * h * gw[None, :], (2 * res, q)).ravel()
+    X, Y = np.meshgrid(xs, xs, indexing="xy")
+    W = np.outer(ws, ws)
+    v = np.stack([X - c[0], Y - c[1], -np.full_like(X, c[2])], -1)
+    r = np.linalg.norm(v, axis=-1)
+    w = v / r[..., None]
+    pdf = lobe_density(kind, n, d, w, size) * (c[2] / r) / r ** 2 * W
+    i0, i1, a0, a1 = linear_node_weights((X + half) / (2 * half), res)
+    j0, j1, b0, b1 = linear_node_weights((Y + half) / (2 * half), res)
+    m1 = np.zeros(res * res)
+    m2 = np.zeros(res * res)
+    for ii, aa in ((i0, a0), (i1, a1)):
+        for jj, bb in ((j0, b0), (j1, b1)):
+            np.add.at(m1, (jj * res + ii).ravel(), (pdf * aa * bb).ravel())
+    # phi_k^2: sum the weights landing on the same node first (clamped borders)
+    for k_of, wt in _node_sums(i0, i1, a0, a1, j0, j1, b0, b1, res):
+        np.add.at(m2, k_of.ravel(), (pdf * wt * wt).ravel())
+    return m1, m2
+
+
+def _node_sums(i0, i1, a0, a1, j0, j1, b0, b1, res):
+    """Per sample point, the (node, total weight) pairs after merging corners
+    that the border clamp maps onto the same node."""
+    ks = [(j * res + i, wa * wb) for i, wa in ((i0, a0), (i1, a1)) for j, wb in ((j0, b0), (j1, b1))]
+    out = []
+    for n_, (k, wk) in enumerate(ks):
+        tot = wk.copy()
+        first = np.ones(k.shape, bool)
+        for m_, (k2, w2) in enumerate(ks):
+            if m_ < n_:
+                first &= k2 != k
+            elif m_ > n_:
+                tot = tot + np.where(k2 == k, w2, 0.0)
+        out.append((k, np.where(first, tot, 0.0)))
+    return out
+
+
 def log_irradiance(kind, n, p, x1, n1, au=0.0, av=0.0, size=None):
     """log of the first-hit irradiance kernel at receiver x1 with unit normal
     n1 (facing the light), up to p-independent constants: a luminaire of power

@@ -242,6 +242,83 @@ def test_soft_spot_total_flux(oracle_lib):
         assert abs(total - P) < 5 * sigma + 1e-6 * P, (th, total, sigma)
 
 
+def test_linear_basis_over_plane(oracle_lib):
+    """Piecewise-linear basis (nodes at texel centres): the flux each node
+    receives has mean P m1_k and variance (P^2/N)(m2_k - m1_k^2), with m1, m2
+    the first-hit density integrated against the hat and its square; and the
+    hats sum to one, so the total equals the box basis' total path by path."""
+    half, res, N = 2.0, 24, 1 << 20
+    p = [0.35, -0.25, 1.2, 0.2, -0.1, 60.0]
+    sc = li.plane_scene(half=half, res=res)
+    lights = make_lights([SPOT], [3.0], [(0, 0)], [0], [p])
+    ol = oracle_lib.OracleLights(lights)
+    S_lin, _ = oracle_lib.forward(oracle_lib.OracleScene(sc, basis="linear"), ol, lights.params, 0x11B, N, 1)
+    S_box, _ = oracle_lib.forward(oracle_lib.OracleScene(sc), ol, lights.params, 0x11B, N, 1)
+    A = sc.texel_area().astype(np.float64)
+    flux = S_lin[0].astype(np.float64) * 2.0 ** -32 * A
+    tot_box = float((S_box[0].astype(np.float64) * 2.0 ** -32 * A).sum())
+    assert abs(flux.sum() / tot_box - 1) < 1e-6
+    m1, m2 = cf.plane_node_moments(SPOT, 3.0, p, None, half, res)
+    m = m1 * N >= 50
+    assert m.sum() > 200
+    z = (flux[m] - p[5] * m1[m]) / np.sqrt(p[5] ** 2 / N * (m2[m] - m1[m] ** 2))
+    assert np.abs(z).max() < 5.5, np.abs(z).max()
+    assert abs(float((z ** 2).sum()) - m.sum()) < 6 * math.sqrt(2 * m.sum())
+
+
+def test_linear_basis_closed_box(oracle_lib):
+    rho, B, N, P = 0.6, 5, 1 << 17, 50.0
+    sc = li.closed_box(albedo=rho)
+    lights = make_lights([POINT, SOFT], [0.0, 0.0], [(0, 0), (0.2, 0.7)], [0, 0],
+                         [[0.7, 0.6, 0.5, 0, 0, P], [1.3, 0.9, 0.8, 0.3, -0.2, 2 * P]])
+    ol = oracle_lib.OracleLights(lights)
+    S, misses = oracle_lib.forward(oracle_lib.OracleScene(sc, basis="linear"), ol, lights.params, 0x98, N, B)
+    S_box, _ = oracle_lib.forward(oracle_lib.OracleScene(sc), ol, lights.params, 0x98, N, B)
+    assert misses == 0
+    A = sc.texel_area().astype(np.float64)
+    total = float(np.sum(A * S[0].astype(np.float64) * 2.0 ** -32))
+    total_box = float(np.sum(A * S_box[0].astype(np.float64) * 2.0 ** -32))
+    assert abs(total / total_box - 1) < 1e-6
+    assert not np.array_equal(S, S_box)
+
+
+def test_linear_basis_direct_gradient_vs_quadrature(oracle_lib):
+    """B = 1 with the linear basis: the adjoint gathers dO/dE with the same
+    hat weights, so its mean is sum_k g_k d/dp (P m1_k(p) / A_k).  Coarse
+    texels under a narrow spot make the hat and box expectations differ by
+    many standard errors, so a gather with box weights would fail."""
+    half, res, N, n = 2.0, 8, 1 << 20, 8.0
+    p = np.array([0.3, -0.2, 1.0, 0.3, -0.2, 40.0])
+    sc = li.plane_scene(half=half, res=res)
+    lights = make_lights([SPOT], [n], [(0, 0)], [0], [p])
+    A = float(sc.texel_area()[0])
+    ii, jj = np.meshgrid(np.arange(res), np.arange(res), indexing="xy")
+    sign = np.where((ii + jj).ravel() % 2 == 0, 1.0, -1.0)
+    g = (sign * np.random.default_rng(17).uniform(0.5, 1.0, sc.n_texels)).astype(np.float32)
+    ref, ref_box = np.zeros(6), np.zeros(6)
+    for c in range(6):
+        h = 1e-4
+        pp, pm = p.copy(), p.copy()
+        pp[c] += h
+        pm[c] -= h
+        Ep = cf.plane_node_moments(SPOT, n, pp, None, half, res, q=8)[0] * pp[5] / A
+        Em = cf.plane_node_moments(SPOT, n, pm, None, half, res, q=8)[0] * pm[5] / A
+        ref[c] = np.dot(g.astype(np.float64), (Ep - Em) / (2 * h))
+        Bp = cf.plane_hit_probability(SPOT, n, pp, None, half, res, q_tex=12) * pp[5] / A
+        Bm = cf.plane_hit_probability(SPOT, n, pm, None, half, res, q_tex=12) * pm[5] / A
+        ref_box[c] = np.dot(g.astype(np.float64), (Bp - Bm) / (2 * h))
+    osc, ol = oracle_lib.OracleScene(sc, basis="linear"), oracle_lib.OracleLights(lights)
+    _, _, contrib = oracle_lib.record(osc, ol, lights.params, 0xD7, N, 1, 0, 0, 0, N, g[None])
+    c64 = contrib.astype(np.float64)
+    est = c64.sum(0)
+    sigma = c64.std(0) * math.sqrt(N)
+    assert np.max(np.abs(ref - ref_box) / sigma) > 10
+    for c in range(6):
+        assert abs(est[c] - ref[c]) < 4.5 * sigma[c] + 1e-3 * abs(ref[c]), (c, est[c], ref[c], sigma[c])
+    grad, _ = oracle_lib.adjoint(osc, ol, lights.params, 0xD7, N, 1, g[None])
+    assert np.allclose(grad[0], est, rtol=1e-9, atol=1e-12 * np.abs(c64).sum())
+
+
 def test_cosine_bounce_floor_to_ceiling(oracle_lib):
     """Second hits on a parallel ceiling: floor first-hit density times the
     differential form factor to each ceiling texel (cosine-weighted bounce, rho)."""
