@@ -44,6 +44,12 @@ extern "C" {
 /* lt_trace_cfg.flags */
 #define LT_FLAG_GRAPH 1u    /* replay the launch sequence as a captured hipGraph */
 #define LT_FLAG_PROPOSAL 2u /* sample emission from the learned proposal (MIS) */
+/* piecewise-linear texel basis (Eq. pwLin with the supplement's mass-lumped
+ * projection): nodes at the texel centres, bilinear hats clamped at each
+ * patch border so that they sum to one; a hit splats into its four nearest
+ * nodes and the adjoint gathers dO/dE with the same weights.  Without it a
+ * hit splats into the one texel that contains it (box basis). */
+#define LT_FLAG_LINEAR 4u
 
 /* lt_sync flags_out bits */
 #define LT_STATUS_OVERFLOW 1u  /* a texel accumulator reached 2^62 */

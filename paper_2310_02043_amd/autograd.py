@@ -22,7 +22,8 @@ class LightTracer:
     per-call configuration of the forward / adjoint passes."""
 
     def __init__(self, scene_arrays, lights_static, layout_offsets, paths_per_layout: int, max_hits: int,
-                 seed: int = 1, correlated: bool = True, graph: bool = False, device: int = 0):
+                 seed: int = 1, correlated: bool = True, graph: bool = False, device: int = 0,
+                 linear: bool = False):
         verts, tris, tri_patch, patches = scene_arrays
         self.ctx = Context(device)
         self.n_texels = self.ctx.upload_scene(verts, tris, tri_patch, patches)
@@ -32,6 +33,7 @@ class LightTracer:
         self.seed = int(seed)
         self.correlated = bool(correlated)
         self.graph = bool(graph)
+        self.linear = bool(linear)      # piecewise-linear texel basis (else box)
         self._S = None
         self.device = torch.device("cuda", device)
         # learned emission proposal (a LearnedProposal); it is trained on the
@@ -44,7 +46,7 @@ class LightTracer:
     def cfg(self, seed=None, adjoint=False):
         prop = self.proposal is not None and (adjoint or self.proposal_forward)
         return self.ctx.cfg(self.seed if seed is None else seed, self.paths_per_layout, self.max_hits,
-                            graph=self.graph, proposal=prop, alpha_plain=self.alpha_plain)
+                            graph=self.graph, proposal=prop, alpha_plain=self.alpha_plain, linear=self.linear)
 
     def adjoint_seed(self, seed=None):
         s = self.seed if seed is None else seed

@@ -240,7 +240,7 @@ int check_cfg(lt_ctx* c, const lt_trace_cfg* cfg)
     for (int j = 0; j < c->n_layouts; ++j)
         if (cfg->paths_per_layout < c->offs[j + 1] - c->offs[j])
             return fail(c, LT_EINVAL, "paths_per_layout smaller than the number of lights of a layout");
-    if (cfg->flags & ~(LT_FLAG_GRAPH | LT_FLAG_PROPOSAL)) return fail(c, LT_EINVAL, "unknown flag");
+    if (cfg->flags & ~(LT_FLAG_GRAPH | LT_FLAG_PROPOSAL | LT_FLAG_LINEAR)) return fail(c, LT_EINVAL, "unknown flag");
     if (cfg->flags & LT_FLAG_PROPOSAL) {
         if (!c->has_proposal) return fail(c, LT_EINVAL, "no emission proposal loaded");
         if (!(cfg->alpha_plain > 0.0f && cfg->alpha_plain <= 1.0f))
@@ -290,6 +290,7 @@ TraceArgs trace_args(lt_ctx* c, const lt_trace_cfg* cfg)
     a.gdepth = std::max(gstack_depth(c), 1);
     a.refill_threshold = c->tune.refill_threshold;
     a.tri_share = c->tune.tri_share;
+    a.linear = (cfg->flags & LT_FLAG_LINEAR) ? 1 : 0;
     a.max_steps = 2 * c->n_nodes + 16;
     a.flags = c->d_flags;
     if (cfg->flags & LT_FLAG_PROPOSAL) {
@@ -728,6 +729,7 @@ int lt_record_paths(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, i
     r.texel = d_texel;
     r.g = d_dOdE;
     r.contrib = d_contrib;
+    r.linear = (cfg->flags & LT_FLAG_LINEAR) ? 1 : 0;
     r.gstack = c->d_gstack;
     r.gdepth = std::max(gstack_depth(c), 1);
     r.max_steps = 2 * c->n_nodes + 16;

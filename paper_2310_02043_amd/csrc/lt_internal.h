@@ -42,6 +42,7 @@ struct TraceArgs {
     int* gstack;                // traversal stack overflow, [waves][gdepth][64]
     int gdepth;
     int refill_threshold;
+    int linear;                 // piecewise-linear texel basis (else box)
     int tri_share;              // eighths of the traversing lanes that select a triangle-test iteration
     int max_steps;              // node visits per segment before the segment is abandoned
     unsigned* flags;            // sticky status bits (2 = traversal step limit hit)
@@ -72,6 +73,7 @@ struct RecordArgs {
     int* texel;
     const float* g;
     float* contrib;
+    int linear;
     int* gstack;
     int gdepth;
     int max_steps;

@@ -409,6 +409,43 @@ __device__ __forceinline__ HitInfo hit_info(const Ray& r, float tb, int qb, cons
     return hi;
 }
 
+// Piecewise-linear basis (Eq. pwLin on the texel grid): the four nodes
+// around the hit (texel centres, indices clamped at the patch border so the
+// hats sum to one) and their bilinear weights.
+__device__ __forceinline__ void linear_nodes(V3 x, int qb, const DevPatch* __restrict__ patches, long long kb[4],
+                                             float wb[4])
+{
+    const DevPatch& P = patches[qb];
+    const float4 o = P.o_inva, eu = P.eu_ilu, ev = P.ev_ilv;
+    const V3 du = sub(x, xyz(o));
+    const float su = dot(du, xyz(eu)) * eu.w;
+    const float sv = dot(du, xyz(ev)) * ev.w;
+    const int ru = P.res_u, rv = P.res_v;
+    const float fu = su * (float)ru - 0.5f, fv = sv * (float)rv - 0.5f;
+    const float fu0 = __builtin_floorf(fu), fv0 = __builtin_floorf(fv);
+    const float au1 = fu - fu0, av1 = fv - fv0;
+    const float au0 = 1.0f - au1, av0 = 1.0f - av1;
+    int i0 = (int)fu0, j0 = (int)fv0;
+    int i1 = i0 + 1, j1 = j0 + 1;
+    i0 = i0 < 0 ? 0 : (i0 > ru - 1 ? ru - 1 : i0);
+    i1 = i1 < 0 ? 0 : (i1 > ru - 1 ? ru - 1 : i1);
+    j0 = j0 < 0 ? 0 : (j0 > rv - 1 ? rv - 1 : j0);
+    j1 = j1 < 0 ? 0 : (j1 > rv - 1 ? rv - 1 : j1);
+    kb[0] = P.base + (long long)j0 * ru + i0;
+    kb[1] = P.base + (long long)j0 * ru + i1;
+    kb[2] = P.base + (long long)j1 * ru + i0;
+    kb[3] = P.base + (long long)j1 * ru + i1;
+    wb[0] = au0 * av0;
+    wb[1] = au1 * av0;
+    wb[2] = au0 * av1;
+    wb[3] = au1 * av1;
+}
+
+__device__ __forceinline__ float linear_gather(const float* __restrict__ g, const long long kb[4], const float wb[4])
+{
+    return ((wb[0] * g[kb[0]] + wb[1] * g[kb[1]]) + wb[2] * g[kb[2]]) + wb[3] * g[kb[3]];
+}
+
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 __device__ __forceinline__ int lanes_below(uint64_t m)
@@ -441,8 +478,10 @@ __device__ __forceinline__ long long xcd_block(long long b, long long nb, int re
 }
 
 // Both variants fit 96 VGPRs (five waves per SIMD); the adjoint keeps its
-// per-path first-hit derivative factors and running sums in LDS.
-template <bool ADJ, bool STATS, int WPB, int LDS_D>
+// per-path first-hit derivative factors and running sums in LDS.  LIN selects
+// the piecewise-linear texel basis (four splats / a four-node gather per
+// hit) at compile time, which leaves the box-basis instances as they were.
+template <bool ADJ, bool STATS, int WPB, int LDS_D, bool LIN>
 __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5))) k_trace(TraceArgs a)
 {
     __shared__ int s_stack[WPB * LDS_D * 64];
@@ -559,11 +598,32 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                     const HitInfo hi = hit_info(r, s.tb, s.qb, a.patches);
                     if (!ADJ) {
                         const float val = (phi_r * T) * hi.inva;
-                        const long long code = (long long)__builtin_rintf(val * 4294967296.0f);
-                        __hip_atomic_fetch_add((unsigned long long*)(S + hi.k), (unsigned long long)code,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (LIN) {
+                            long long kb[4];
+                            float wb[4];
+                            linear_nodes(hi.x, s.qb, a.patches, kb, wb);
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) {
+                                const long long code = (long long)__builtin_rintf((val * wb[c]) * 4294967296.0f);
+                                __hip_atomic_fetch_add((unsigned long long*)(S + kb[c]), (unsigned long long)code,
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            }
+                        } else {
+                            const long long code = (long long)__builtin_rintf(val * 4294967296.0f);
+                            __hip_atomic_fetch_add((unsigned long long*)(S + hi.k), (unsigned long long)code,
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
                     } else {
-                        s_r = s_r + (g[hi.k] * hi.inva) * T;
+                        float gk;
+                        if (LIN) {
+                            long long kb[4];
+                            float wb[4];
+                            linear_nodes(hi.x, s.qb, a.patches, kb, wb);
+                            gk = linear_gather(g, kb, wb);
+                        } else {
+                            gk = g[hi.k];
+                        }
+                        s_r = s_r + (gk * hi.inva) * T;
                         if (h == 1) {
                             float dl[6];
                             first_hit_dlog(L, hi.x, v3(r.ox, r.oy, r.oz), hi.no, au, av, dl);
@@ -683,7 +743,16 @@ __global__ void __launch_bounds__(256) k_record(RecordArgs a)
             a.prim[idx * a.max_hits + h - 1] = s.pb;
             a.texel[idx * a.max_hits + h - 1] = (int)hi.k;
             if (g) {
-                s_r = s_r + (g[hi.k] * hi.inva) * T;
+                float gk;
+                if (a.linear) {
+                    long long kb[4];
+                    float wb[4];
+                    linear_nodes(hi.x, s.qb, a.patches, kb, wb);
+                    gk = linear_gather(g, kb, wb);
+                } else {
+                    gk = g[hi.k];
+                }
+                s_r = s_r + (gk * hi.inva) * T;
                 if (h == 1) {
                     float dl[6];
                     first_hit_dlog(L, hi.x, v3(r.ox, r.oy, r.oz), hi.no, au, av, dl);
@@ -878,10 +947,17 @@ inline int nblocks(long long n, int b, int cap)
 template <bool ADJ, bool STATS, int WPB>
 hipError_t launch_wpb(const TraceArgs& a, int lds_depth, int blocks, hipStream_t st)
 {
-    if (lds_depth == 16)
-        k_trace<ADJ, STATS, WPB, 16><<<blocks, WPB * 64, 0, st>>>(a);
-    else
-        k_trace<ADJ, STATS, WPB, 32><<<blocks, WPB * 64, 0, st>>>(a);
+    if (a.linear && !STATS) {
+        if (lds_depth == 16)
+            k_trace<ADJ, STATS, WPB, 16, true><<<blocks, WPB * 64, 0, st>>>(a);
+        else
+            k_trace<ADJ, STATS, WPB, 32, true><<<blocks, WPB * 64, 0, st>>>(a);
+    } else {
+        if (lds_depth == 16)
+            k_trace<ADJ, STATS, WPB, 16, false><<<blocks, WPB * 64, 0, st>>>(a);
+        else
+            k_trace<ADJ, STATS, WPB, 32, false><<<blocks, WPB * 64, 0, st>>>(a);
+    }
     return hipGetLastError();
 }
 

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblt.so")
 
 LT_OK, LT_EINVAL, LT_ENOMEM, LT_EHIP, LT_ESTATE, LT_EOVERFLOW = 0, -1, -2, -3, -4, -5
-LT_FLAG_GRAPH, LT_FLAG_PROPOSAL = 1, 2
+LT_FLAG_GRAPH, LT_FLAG_PROPOSAL, LT_FLAG_LINEAR = 1, 2, 4
 
 EXPORTED = [
     "lt_create", "lt_destroy", "lt_last_error", "lt_set_stream", "lt_sync", "lt_scene_upload",
@@ -172,8 +172,9 @@ class Context:
 
     # -- tracing -------------------------------------------------------------
     @staticmethod
-    def cfg(seed, paths_per_layout, max_hits, graph=False, proposal=False, alpha_plain=0.2):
-        flags = (LT_FLAG_GRAPH if graph else 0) | (LT_FLAG_PROPOSAL if proposal else 0)
+    def cfg(seed, paths_per_layout, max_hits, graph=False, proposal=False, alpha_plain=0.2, linear=False):
+        flags = (LT_FLAG_GRAPH if graph else 0) | (LT_FLAG_PROPOSAL if proposal else 0) | \
+            (LT_FLAG_LINEAR if linear else 0)
         return TraceCfg(int(seed) & 0xFFFFFFFFFFFFFFFF, int(paths_per_layout), int(max_hits), flags,
                         float(alpha_plain), 0)
 

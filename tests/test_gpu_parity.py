@@ -58,14 +58,14 @@ def grad_rel(g_gpu, g_ref):
 
 
 def run_case(torch, oracle_lib, scene, lights, params, seed, ppl, B, use_bvh, check_grad=True, target=None,
-             graph=False, tuning=None):
+             graph=False, tuning=None, linear=False):
     ctx = make_ctx(torch, scene, lights)
     if tuning:
         ctx.set_tuning(**tuning)
-    osc = oracle_lib.OracleScene(scene, use_bvh=use_bvh)
+    osc = oracle_lib.OracleScene(scene, use_bvh=use_bvh, basis="linear" if linear else "box")
     ol = oracle_lib.OracleLights(lights)
     p_d = torch.tensor(params, device="cuda")
-    cfg = ctx.cfg(seed, ppl, B, graph=graph)
+    cfg = ctx.cfg(seed, ppl, B, graph=graph, linear=linear)
     E_d, S_d = ctx.trace_forward(p_d, cfg)
     assert ctx.sync() == 0
     S_ref, miss_ref = oracle_lib.forward(osc, ol, params, seed, ppl, B)
@@ -91,29 +91,41 @@ def run_case(torch, oracle_lib, scene, lights, params, seed, ppl, B, use_bvh, ch
     return out
 
 
-def test_box_room_full(torch_dev, oracle_lib):
-    """Closed 4x3x2.5 m room + two boxes, spot cos^4, 2^20 paths, 3 hits (full size)."""
+@pytest.mark.parametrize("basis", ["box", "linear"])
+def test_box_room_full(torch_dev, oracle_lib, basis):
+    """Closed 4x3x2.5 m room + two boxes, spot cos^4, 2^20 paths, 3 hits (full
+    size), with the box and the piecewise-linear texel basis."""
     torch = torch_dev
     c1 = li.box_room()
-    say("box_room full: paths", c1["paths"])
+    say("box_room full: paths", c1["paths"], "basis", basis)
     run_case(torch, oracle_lib, c1["scene"], c1["lights"], c1["lights"].params, c1["seed"], c1["paths"],
-             c1["max_hits"], use_bvh=False)
+             c1["max_hits"], use_bvh=False, linear=basis == "linear")
 
 
-def test_box_room_hit_sequences(torch_dev, oracle_lib):
+@pytest.mark.parametrize("basis", ["box", "linear"])
+def test_box_room_hit_sequences(torch_dev, oracle_lib, basis):
+    """Every path of the box room replayed one by one: hit sequences and
+    per-path adjoint contributions (whose gather depends on the basis)."""
     torch = torch_dev
     c1 = li.box_room()
     sc, lights = c1["scene"], c1["lights"]
     ctx = make_ctx(torch, sc, lights)
     p_d = torch.tensor(lights.params, device="cuda")
     N, B = c1["paths"], c1["max_hits"]
-    cfg = ctx.cfg(c1["seed"], N, B)
-    prim_d, tex_d, _ = ctx.record_paths(p_d, cfg, 0, 0, 0, N)
-    prim_ref, tex_ref, _ = oracle_lib.record(oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights),
-                                             lights.params, c1["seed"], N, B, 0, 0, 0, N)
+    lin = basis == "linear"
+    cfg = ctx.cfg(c1["seed"], N, B, linear=lin)
+    g = np.random.default_rng(4).normal(size=(1, sc.n_texels)).astype(np.float32)
+    prim_d, tex_d, con_d = ctx.record_paths(p_d, cfg, 0, 0, 0, N, dOdE=torch.tensor(g, device="cuda"))
+    prim_ref, tex_ref, con_ref = oracle_lib.record(oracle_lib.OracleScene(sc, basis=basis),
+                                                   oracle_lib.OracleLights(lights), lights.params, c1["seed"], N, B,
+                                                   0, 0, 0, N, dOdE=g)
     same = np.all(prim_d.cpu().numpy() == prim_ref, 1) & np.all(tex_d.cpu().numpy() == tex_ref, 1)
     say(f"  identical hit sequences: {same.mean() * 100:.4f} % of {N}")
     assert same.mean() >= PATH_BAR
+    c = con_d.cpu().numpy()
+    r = rel_l2(c[same], con_ref[same])
+    say(f"  per-path contributions rel-L2 {r:.2e}, bit-identical {np.mean(c == con_ref) * 100:.4f} %")
+    assert r <= 1e-5
 
 
 def test_objective_matches(torch_dev, oracle_lib):
@@ -147,10 +159,12 @@ def test_office_reduced_paths(torch_dev, oracle_lib, launch):
              tuning=tuning)
 
 
-def test_office_full_size_sampled(torch_dev, oracle_lib):
+@pytest.mark.parametrize("basis", ["box", "linear"])
+def test_office_full_size_sampled(torch_dev, oracle_lib, basis):
     """Bench launch configuration (2^26 paths, 5 hits): sampled paths vs the
-    oracle one by one, plus the power identity sum_l P_l dO/dP_l = sum_k g_k E_k."""
-    full_size_sampled(torch_dev, oracle_lib, li.office())
+    oracle one by one, plus the power identity sum_l P_l dO/dP_l = sum_k g_k E_k,
+    with the box and the piecewise-linear texel basis."""
+    full_size_sampled(torch_dev, oracle_lib, li.office(), linear=basis == "linear")
 
 
 def test_building_full_size_sampled(torch_dev, oracle_lib):
@@ -168,7 +182,7 @@ def test_room_set_full_size_sampled(torch_dev, oracle_lib):
     full_size_sampled(torch_dev, oracle_lib, li.room_set())
 
 
-def full_size_sampled(torch, oracle_lib, c2):
+def full_size_sampled(torch, oracle_lib, c2, linear=False):
     sc, lights = c2["scene"], c2["lights"]
     ctx = make_ctx(torch, sc, lights)
     N, B = c2["paths"], c2["max_hits"]
@@ -176,9 +190,10 @@ def full_size_sampled(torch, oracle_lib, c2):
     assert tuning is not None
     ctx.set_tuning(**tuning)
     say("  tuning", tuning)
-    osc, ol = oracle_lib.OracleScene(sc, use_bvh=True), oracle_lib.OracleLights(lights)
+    osc = oracle_lib.OracleScene(sc, use_bvh=True, basis="linear" if linear else "box")
+    ol = oracle_lib.OracleLights(lights)
     p_d = torch.tensor(lights.params, device="cuda")
-    cfg = ctx.cfg(c2["seed"], N, B)
+    cfg = ctx.cfg(c2["seed"], N, B, linear=linear)
     E_d, S_d = ctx.trace_forward(p_d, cfg)
     assert ctx.sync() == 0
     nly = lights.n_layouts
@@ -260,7 +275,7 @@ def test_determinism_and_graph_replay(torch_dev, oracle_lib, graph):
 
 
 @pytest.mark.parametrize("case", ["ragged", "one_path_per_light", "single_hit", "point_closed_box",
-                                  "tiny_scene", "rect_many_lights", "soft_spots"])
+                                  "tiny_scene", "rect_many_lights", "soft_spots", "linear_ragged"])
 def test_edge_cases(torch_dev, oracle_lib, case):
     torch = torch_dev
     if case == "ragged":
@@ -288,6 +303,15 @@ def test_edge_cases(torch_dev, oracle_lib, case):
         sc = sb.build("one_quad", fixed_res=(3, 5))
         lights = make_lights([SPOT], [1.0], [(0, 0)], [0], [[0.0, 0.0, 1.0, 0.0, 0.0, 5.0]])
         ppl, B = 5000, 2
+    elif case == "linear_ragged":
+        # piecewise-linear basis on odd patch resolutions and a 1 x n strip
+        sb = li.SceneBuilder()
+        sb.quads([-2.0, -2.0, 0.0], [4.0, 0, 0], [0, 4.0, 0], 0.6, res=(7, 5))
+        sb.quads([-2.0, -2.0, 2.5], [4.0, 0, 0], [0, 4.0, 0], 0.7, res=(1, 9))
+        sc = sb.build("floor_ceiling_ragged")
+        lights = make_lights([SPOT, POINT], [2.0, 0.0], [(0, 0), (0, 0)], [0, 0],
+                             [[0.3, 0.2, 1.5, 0.1, -0.1, 40.0], [-0.5, 0.4, 1.0, 0, 0, 20.0]])
+        ppl, B = 50_001, 3
     elif case == "soft_spots":
         # the supplement's soft-edged spots: a narrow ring, a pure fall-off
         # over the hemisphere, a hard-edged cone, beside a cos^n spot
@@ -306,7 +330,8 @@ def test_edge_cases(torch_dev, oracle_lib, case):
         lights = make_lights([RECT] * n, rng.uniform(1, 6, n), [(0.3, 0.2)] * n, [0] * n, ps)
         ppl, B = 40 * 1000 + 17, 4
     say("edge case", case)
-    out = run_case(torch, oracle_lib, sc, lights, lights.params, 0xE0 + len(case), ppl, B, use_bvh=False)
+    out = run_case(torch, oracle_lib, sc, lights, lights.params, 0xE0 + len(case), ppl, B, use_bvh=False,
+                   linear=case == "linear_ragged")
     if case == "point_closed_box":
         assert out["S_ref"].sum() > 0
 
