@@ -92,6 +92,8 @@ def lib():
         L.or_votes.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int64, C.c_int, P, P, C.c_int,
                                C.c_int, P, P]
         L.or_votes.restype = C.c_int64
+        L.or_pt.argtypes = [P, P, P, C.c_uint64, C.c_int, C.c_int, C.c_int, P, P, P]
+        L.or_pt.restype = None
         L.or_record.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int64,
                                 C.c_int64, P, P, P, P, P]
         L.or_fixed_to_float.argtypes = [P, C.c_int64, P]
@@ -231,6 +233,21 @@ def votes(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layou
                        int(paths_per_layout), int(max_hits), int(limit_per_light), int(n_threads),
                        _prop(proposal), g.ctypes.data, int(light), int(param), vote.ctypes.data, grad.ctypes.data)
     return vote, grad, int(m)
+
+
+def path_trace(osc: OracleScene, ol: OracleLights, params, seed: int, samples_per_texel: int, max_hits: int,
+               dOdE=None, n_threads: int = 0):
+    """Object-space path tracing with next-event estimation: returns
+    (S [n_layouts,K] int64, grad [L,6] float64 or None when dOdE is None)."""
+    prm = np.ascontiguousarray(params, np.float32)
+    S = np.zeros((ol.n_layouts, osc.n_texels), np.int64)
+    g = None if dOdE is None else np.ascontiguousarray(dOdE, np.float32).reshape(ol.n_layouts, osc.n_texels)
+    grad = None if dOdE is None else np.zeros((ol.n_lights, 6), np.float64)
+    if osc.n_texels * samples_per_texel >= 1 << 32:
+        raise ValueError("more than 2^32 samples per layout")
+    lib().or_pt(C.byref(osc.c), C.byref(ol.c), prm.ctypes.data, int(seed) & 0xFFFFFFFFFFFFFFFF,
+                int(samples_per_texel), int(max_hits), int(n_threads), _p(g), S.ctypes.data, _p(grad))
+    return S, grad
 
 
 def record(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,

@@ -34,6 +34,8 @@
  *   - Luminaires: point, cos^n spot, cos^n rectangle, and the supplement's
  *     soft-edged spot (quadratic fall-off in cos theta between the inner and
  *     outer cone, directions uniform over the outer cap, weighted).
+ *   - Object-space path tracing with next-event estimation (the comparison
+ *     estimator of Sec. 6) on the same texels, and its gradient.
  *   - Gradient-contribution map (Sec. gradVis): the same adjoint pass over
  *     one light's paths, each path adding its contribution to dO/dp_j into
  *     the texel of its first surface hit.
@@ -949,6 +951,211 @@ EXPORT int64_t or_votes(const or_scene* S, const or_lights* Ls, const float* par
     }
     grad_out[0] = a0; grad_out[1] = a1; grad_out[2] = a2; grad_out[3] = a3; grad_out[4] = a4; grad_out[5] = a5;
     return m;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Object-space path tracing with next-event estimation: the comparison     */
+/* estimator of Sec. 6 (after Stam 2020), built on the same texels: sample   */
+/* points uniformly in each texel, connect every path vertex to one light   */
+/* chosen uniformly (shadow ray), continue with the light tracer's cosine    */
+/* bounce.  Its gradient differentiates each light connection with the       */
+/* vertex held fixed, which is the first-hit derivative above evaluated at   */
+/* that vertex.                                                               */
+/* ------------------------------------------------------------------------- */
+
+/* radiant intensity of light L towards unit direction w (from its origin),
+ * with L->phi_r = P (or P kcap for the soft-edged spot: n_paths = 1) */
+static float light_intensity(const olight* L, const float* w)
+{
+    if (L->type == 0) return L->phi_r * 0.07957747154594767f;
+    float ce = dot3(L->d, w);
+    if (L->type == 3) {
+        if (!(ce > L->co)) return 0.0f;
+        float a = 1.0f;
+        if (ce < L->ci) {
+            float f = (ce - L->co) / (L->ci - L->co);
+            a = f * f;
+        }
+        return (L->phi_r * a) * (0.15915494309189533f / (1.0f - L->co));
+    }
+    if (!(ce > 0.0f)) return 0.0f;
+    float pw = 1.0f;
+    if (L->n != 0.0f) pw = or_exp2(L->n * or_log2(ce));
+    return L->phi_r * (((L->n + 1.0f) * 0.15915494309189533f) * pw);
+}
+
+/* one light connection from vertex v (patch qv, unit normal nq); side < 0:
+ * either side (the one facing the light), else the side of normal nside.
+ * Returns the unoccluded-or-zero irradiance term I cos / r^2 and, for the
+ * gradient, the light's derivative factors with v fixed. */
+static float connect_light(const or_scene* S, const olight* L, const float* v, int32_t qv, const float* nq,
+                           const float* nside, const float* ul, float dl[6])
+{
+    float y[3] = {L->c[0], L->c[1], L->c[2]};
+    float au = 0.0f, av = 0.0f;
+    if (L->type == 2) {
+        au = (ul[0] - 0.5f) * L->w;
+        av = (ul[1] - 0.5f) * L->h;
+        for (int c = 0; c < 3; ++c) y[c] = (L->c[c] + au * L->t[c]) + av * L->b[c];
+    }
+    float vec[3] = {v[0] - y[0], v[1] - y[1], v[2] - y[2]};
+    float r2 = dot3(vec, vec);
+    if (!(r2 > 1e-12f)) return 0.0f;
+    float r = sqrtf(r2);
+    float inv_r = 1.0f / r;
+    float w[3] = {vec[0] * inv_r, vec[1] * inv_r, vec[2] * inv_r};
+    float n1[3];
+    if (nside) {
+        n1[0] = nside[0]; n1[1] = nside[1]; n1[2] = nside[2];
+    } else if (dot3(nq, w) < 0.0f) {
+        n1[0] = nq[0]; n1[1] = nq[1]; n1[2] = nq[2];
+    } else {
+        n1[0] = -nq[0]; n1[1] = -nq[1]; n1[2] = -nq[2];
+    }
+    float cv = -dot3(n1, w);
+    if (!(cv > 0.0f)) return 0.0f;
+    float I = light_intensity(L, w);
+    if (!(I > 0.0f)) return 0.0f;
+    float C = (I * cv) / r2;
+    /* shadow ray from v towards the light sample */
+    float sd[3] = {-w[0], -w[1], -w[2]};
+    float t;
+    int64_t prim = intersect(S, v, sd, qv, &t);
+    if (prim >= 0 && t < r * 0.9999f) return 0.0f;
+    if (dl) first_hit_dlog(L, v, y, n1, au, av, dl);
+    return C;
+}
+
+/* One layout's samples: M per texel, vertex 0 uniform in the texel, up to
+ * max_hits - 1 bounces.  Forward: S_out [K] int64 (Q31.32 of the texel's
+ * mean irradiance).  With dOdE [K]: grad_out [L,6] FP64 += sum_k dO/dE_k
+ * dE_k/dp. */
+static void pt_layout(const or_scene* S, const or_lights* Ls, const float* params, uint64_t seed, int M,
+                      int max_hits, int j, const int32_t* texel_patch, const float* dOdE, int64_t* S_out,
+                      double* grad_out)
+{
+    int l0 = Ls->layout_offsets[j], l1 = Ls->layout_offsets[j + 1];
+    int nl = l1 - l0;
+    olight* Lt = (olight*)malloc(sizeof(olight) * (size_t)nl);
+    for (int l = 0; l < nl; ++l) light_setup(Ls, params, l0 + l, 1, &Lt[l]);
+    const uint32_t stream = ((uint32_t)j << 16) | 0xFFFFu;
+    const float inv_m = 1.0f / (float)M;
+    const float fl = (float)nl;
+    const int64_t total = S->n_texels * (int64_t)M;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 256)
+#endif
+    for (int64_t i = 0; i < total; ++i) {
+        int64_t k = i / M;
+        int32_t q = texel_patch[k];
+        const float* pf = S->pf + 17 * (int64_t)q;
+        int32_t ru = S->pres[2 * q];
+        int64_t loc = k - S->pbase[q];
+        int32_t iu = (int32_t)(loc % ru), iv = (int32_t)(loc / ru);
+        float u[4];
+        draw4(seed, (uint32_t)i, stream, 0u, u);
+        float su = ((float)iu + u[0]) / (float)ru;
+        float sv = ((float)iv + u[1]) / (float)S->pres[2 * q + 1];
+        float x[3];
+        for (int c = 0; c < 3; ++c) x[c] = (pf[c] + su * pf[3 + c]) + sv * pf[6 + c];
+        const float* nq = pf + 9;
+        float gk = dOdE ? dOdE[k] * inv_m : 0.0f;
+        float e = 0.0f;
+        float T = 1.0f;
+        float v[3] = {x[0], x[1], x[2]};
+        int32_t qv = q;
+        float nside[3];
+        int have_side = 0;
+        for (int h = 0; h < max_hits; ++h) {
+            /* light connection at vertex h */
+            float ul[4];
+            draw4(seed, (uint32_t)i, stream, 1u + 2u * (uint32_t)h, ul);
+            int ls = (int)(ul[0] * fl);
+            if (ls > nl - 1) ls = nl - 1;
+            float dl[6];
+            const float* nqv = S->pf + 17 * (int64_t)qv + 9;
+            float C = connect_light(S, &Lt[ls], v, qv, nqv, have_side ? nside : NULL, ul + 1, dOdE ? dl : NULL);
+            if (C > 0.0f) {
+                float we = (T * fl) * C;
+                e = e + we;
+                if (dOdE) {
+                    double* g = grad_out + 6 * (int64_t)(l0 + ls);
+                    for (int c = 0; c < 6; ++c) {
+                        double cr = (double)((gk * we) * dl[c]);
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+                        g[c] += cr;
+                    }
+                }
+            }
+            if (h == max_hits - 1) break;
+            /* bounce: at vertex 0 a side drawn with probability 1/2 (weight 2),
+             * later the side facing the incoming ray */
+            float no[3];
+            if (!have_side) {
+                float sg = u[2] < 0.5f ? 1.0f : -1.0f;
+                for (int c = 0; c < 3; ++c) no[c] = sg * nq[c];
+                T = T * 2.0f;
+            } else {
+                for (int c = 0; c < 3; ++c) no[c] = nside[c];
+            }
+            float ub[4];
+            draw4(seed, (uint32_t)i, stream, 2u + 2u * (uint32_t)h, ub);
+            float sign = copysignf(1.0f, no[2]);
+            float a = -1.0f / (sign + no[2]);
+            float bxy = (no[0] * no[1]) * a;
+            float b1[3] = {1.0f + ((sign * no[0]) * no[0]) * a, sign * bxy, -(sign * no[0])};
+            float b2[3] = {bxy, sign + (no[1] * no[1]) * a, -no[1]};
+            float rr = sqrtf(ub[0]);
+            float sp, cp;
+            or_sincos2pi(ub[1], &sp, &cp);
+            float lx = rr * cp, ly = rr * sp;
+            float lz = sqrtf(fmaxf(0.0f, 1.0f - ub[0]));
+            float dir[3];
+            for (int c = 0; c < 3; ++c) dir[c] = (lx * b1[c] + ly * b2[c]) + lz * no[c];
+            float t;
+            int64_t prim = intersect(S, v, dir, qv, &t);
+            if (prim < 0) break;
+            float xn[3];
+            for (int c = 0; c < 3; ++c) xn[c] = v[c] + t * dir[c];
+            int32_t qn = S->tri_patch[prim];
+            const float* pn = S->pf + 17 * (int64_t)qn;
+            float nd = dot3(pn + 9, dir);
+            for (int c = 0; c < 3; ++c) nside[c] = nd < 0.0f ? pn[9 + c] : -pn[9 + c];
+            have_side = 1;
+            T = T * pn[16];
+            for (int c = 0; c < 3; ++c) v[c] = xn[c];
+            qv = qn;
+        }
+        if (S_out) {
+            long long code = llrintf((e * inv_m) * 4294967296.0f);
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+            S_out[k] += code;
+        }
+    }
+    free(Lt);
+}
+
+EXPORT void or_pt(const or_scene* S, const or_lights* Ls, const float* params, uint64_t seed, int M, int max_hits,
+                  int n_threads, const float* dOdE, int64_t* S_out, double* grad_out)
+{
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+    int32_t* texel_patch = (int32_t*)malloc(sizeof(int32_t) * (size_t)S->n_texels);
+    for (int32_t q = 0; q < S->n_patches; ++q) {
+        int64_t n = (int64_t)S->pres[2 * q] * S->pres[2 * q + 1];
+        for (int64_t k = 0; k < n; ++k) texel_patch[S->pbase[q] + k] = q;
+    }
+    if (S_out) memset(S_out, 0, (size_t)(S->n_texels * Ls->n_layouts) * sizeof(int64_t));
+    if (grad_out) memset(grad_out, 0, sizeof(double) * 6 * (size_t)Ls->n_lights);
+    for (int j = 0; j < Ls->n_layouts; ++j)
+        pt_layout(S, Ls, params, seed, M, max_hits, j, texel_patch, dOdE ? dOdE + (int64_t)j * S->n_texels : NULL,
+                  S_out ? S_out + (int64_t)j * S->n_texels : NULL, grad_out);
+    free(texel_patch);
 }
 
 /* Hit sequences (primitive and texel per hit, -1 = none) of paths

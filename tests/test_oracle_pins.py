@@ -319,6 +319,91 @@ def test_linear_basis_direct_gradient_vs_quadrature(oracle_lib):
     assert np.allclose(grad[0], est, rtol=1e-9, atol=1e-12 * np.abs(c64).sum())
 
 
+# --------------------------------------------------------------------------
+# object-space path tracing with next-event estimation (comparison estimator)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", [POINT, SPOT, RECT, SOFT])
+def test_path_trace_direct_over_plane(oracle_lib, kind):
+    """One vertex per sample (direct light only): the texel means agree with
+    the quadrature of the emitter's irradiance over each texel, to within the
+    noise that two seeds show."""
+    half, res, M = 3.0, 16, 64
+    n = {SPOT: 3.0, RECT: 1.5}.get(kind, 0.0)
+    size = {RECT: (0.8, 0.5), SOFT: (0.3, 0.8)}.get(kind, (0, 0))
+    p = [0.4, -0.3, 1.3, 0.25 if kind else 0.0, -0.15 if kind else 0.0, 70.0]
+    sc = li.plane_scene(half=half, res=res)
+    lights = make_lights([kind], [n], [size], [0], [p])
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    A = float(sc.texel_area()[0])
+    ref = cf.plane_hit_probability(kind, n, p, size, half, res, q_tex=8, q_light=8) * p[5] / A
+    Es = [oracle_lib.fixed_to_float(oracle_lib.path_trace(osc, ol, lights.params, sd, M, 1)[0])[0].astype(np.float64)
+          for sd in (0x71, 0x72)]
+    err = np.linalg.norm((Es[0] + Es[1]) / 2 - ref)
+    noise = np.linalg.norm(Es[0] - Es[1]) / 2
+    assert err < 1.6 * noise + 1e-4 * np.linalg.norm(ref), (err, noise)
+
+
+def test_path_trace_matches_light_trace(oracle_lib):
+    """Box room with bounces (B = 3) and three luminaires: path tracing and
+    light tracing estimate the same texel irradiance; per-patch flux totals
+    agree within the noise that two seeds of each show."""
+    sc = li.box_room()["scene"]
+    lights = make_lights([SPOT, POINT, RECT], [3.0, 0.0, 1.0], [(0, 0), (0, 0), (0.5, 0.3)], [0, 0, 0],
+                         [[1.0, 1.0, 2.0, 0.1, 0.2, 50.0], [3.0, 2.0, 1.8, 0, 0, 30.0],
+                          [2.0, 1.5, 2.4, -0.2, 0.3, 70.0]])
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    A = sc.texel_area().astype(np.float64)
+    patch = np.repeat(np.arange(sc.n_patches), sc.patch_res().prod(1))
+
+    def patch_flux(S):
+        f = S[0].astype(np.float64) * 2.0 ** -32 * A
+        return np.bincount(patch, weights=f, minlength=sc.n_patches)
+
+    pt = [patch_flux(oracle_lib.path_trace(osc, ol, lights.params, sd, 8, 3)[0]) for sd in (1, 2)]
+    lt = [patch_flux(oracle_lib.forward(osc, ol, lights.params, sd, 1 << 21, 3)[0]) for sd in (3, 4)]
+    err = np.linalg.norm((pt[0] + pt[1]) / 2 - (lt[0] + lt[1]) / 2)
+    noise = math.sqrt(np.sum((pt[0] - pt[1]) ** 2) + np.sum((lt[0] - lt[1]) ** 2)) / 2
+    assert err < 3 * noise, (err, noise)
+    assert np.linalg.norm(pt[0] - lt[0]) < 0.05 * np.linalg.norm(lt[0])
+
+
+def test_path_trace_gradient_is_the_estimators_derivative(oracle_lib):
+    """In a convex room no shadow ray is ever blocked and no sample moves with
+    the lights, so one seed's estimate is a smooth function of p: its
+    gradient of sum_k g_k E_k equals central differences of that sum with the
+    same seed, for every luminaire type and parameter."""
+    sb = li.SceneBuilder()
+    sb.boxes([0, 0, 0], [4.0, 3.0, 2.5], 0.6, res=(12, 12))
+    sc = sb.build("empty_room", fixed_res=(12, 12))
+    p = np.array([[1.2, 1.0, 2.1, 0.2, -0.15, 40.0], [2.9, 1.8, 2.2, -0.1, 0.25, 30.0],
+                  [2.0, 2.2, 2.3, 0.15, 0.1, 50.0], [1.0, 2.1, 1.8, 0.0, 0.0, 20.0]], np.float32)
+    # profiles without kinks (cos^n with n >= 2, a soft-edged spot with no
+    # inner cone), so a difference step never straddles a kink of the intensity
+    lights = make_lights([SPOT, RECT, SOFT, POINT], [3.0, 2.0, 0.0, 0.0], [(0, 0), (0.6, 0.4), (0.0, 0.9), (0, 0)],
+                         [0, 0, 0, 0], p)
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    g = np.random.default_rng(21).normal(size=(1, sc.n_texels)).astype(np.float32)
+    seed, M, B = 0x3C, 4, 3
+    _, grad = oracle_lib.path_trace(osc, ol, p, seed, M, B, dOdE=g)
+
+    def lin(pp):
+        S, _ = oracle_lib.path_trace(osc, ol, pp, seed, M, B)
+        return float(np.dot(g[0].astype(np.float64), S[0].astype(np.float64) * 2.0 ** -32))
+
+    for l in range(4):
+        for c in range(6):
+            if lights.static["type"][l] == POINT and c in (3, 4):
+                assert grad[l, c] == 0.0
+                continue
+            h = {5: 0.2}.get(c, 1e-3)
+            pp, pm = p.copy(), p.copy()
+            pp[l, c] += h
+            pm[l, c] -= h
+            fd = (lin(pp) - lin(pm)) / (float(pp[l, c]) - float(pm[l, c]))
+            assert abs(fd - grad[l, c]) <= 2e-3 * abs(grad[l, c]) + 1e-4 * np.abs(grad).max(), (l, c, fd, grad[l, c])
+
+
 def test_cosine_bounce_floor_to_ceiling(oracle_lib):
     """Second hits on a parallel ceiling: floor first-hit density times the
     differential form factor to each ceiling texel (cosine-weighted bounce, rho)."""
