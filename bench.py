@@ -15,6 +15,7 @@ gradient error x time of the adjoint pass against the plain tracer.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -107,7 +108,7 @@ def cpu_baseline(scene, lights, seed, ppl, B, target_seconds):
                       f"{B} hits, forward+adjoint, {dt2:.1f} s)"}
 
 
-def proposal_study(ctx, wl, N, seeds=32, ref_runs=48, train_iters=30, alpha=0.2, train_every=4):
+def proposal_study(ctx, wl, N, seeds=32, ref_runs=48, train_iters=30, alpha=0.2, train_every=4, pt_seeds=16):
     """Gradient error x time of the adjoint pass, learned proposal vs plain.
 
     The luminaires sit at their perturbed initial parameters, the target
@@ -121,7 +122,10 @@ def proposal_study(ctx, wl, N, seeds=32, ref_runs=48, train_iters=30, alpha=0.2,
     ratio learned / plain is the time ratio at equal relative error.  The
     learned form's time per gradient is its adjoint pass plus, amortised over
     `train_every` optimisation steps, the histogram it accumulates for
-    training and the network's training + inference."""
+    training and the network's training + inference.  The same reference
+    also scores object-space path tracing (next-event estimation, the
+    comparison estimator) with as many samples per texel as fit the plain
+    adjoint pass's time."""
     import torch
     from paper_2310_02043_amd.proposal import LearnedProposal
     lights, B = wl["lights"], wl["max_hits"]
@@ -177,6 +181,28 @@ def proposal_study(ctx, wl, N, seeds=32, ref_runs=48, train_iters=30, alpha=0.2,
     _, t_hist = timed(True, lp.hist, 0x50000, 4)
     t_learn = t_le + (max(t_hist - t_le, 0.0) + upkeep_ms) / train_every
     e2_pl, e2_le = (e_pl ** 2).mean(0), (e_le ** 2).mean(0)
+
+    # object-space path tracing with next-event estimation (the comparison
+    # estimator) against the same reference, at about the light tracer's time
+    def pt_timed(M, seed0, n):
+        cfg = ctx.cfg(seed0, N, B)
+        ctx.pt_adjoint(p0, g, cfg, M)
+        torch.cuda.synchronize()
+        ev_a, ev_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev_a.record()
+        grads = [ctx.pt_adjoint(p0, g, ctx.cfg(seed0 + s, N, B), M).clone() for s in range(n)]
+        ev_b.record()
+        torch.cuda.synchronize()
+        return grads, ev_a.elapsed_time(ev_b) / n
+
+    _, t_pt1 = pt_timed(1, 0x60000, 2)
+    M_pt = max(1, int(round(t_pl / t_pt1)))
+    g_pt, t_pt = pt_timed(M_pt, 0x70000, pt_seeds)
+    e_pt = np.asarray([errs(x) for x in g_pt])
+    e2_pt = (e_pt ** 2).mean(0)
+    mean_pt = torch.stack([x.double() for x in g_pt]).mean(0)
+    bias = float((mean_pt - ref).norm() / ref.norm())
+    bias_se = float(math.sqrt(e2_pt[0] / pt_seeds))
     rng = np.random.default_rng(0)
     bs = [(e_le[rng.integers(0, seeds, seeds), 0] ** 2).mean() / (e_pl[rng.integers(0, seeds, seeds), 0] ** 2).mean()
           for _ in range(2000)]
@@ -194,7 +220,15 @@ def proposal_study(ctx, wl, N, seeds=32, ref_runs=48, train_iters=30, alpha=0.2,
             "variance_ratio": round(float(e2_le[0] / e2_pl[0]), 4),
             "variance_ratio_90ci": [round(float(np.percentile(bs, 5)), 4), round(float(np.percentile(bs, 95)), 4)],
             "eps2_t_ratio": round(float(ratio), 4),
-            "eps2_t_ratio_unit_norm": round(float(e2_le[1] * t_learn / (e2_pl[1] * t_pl)), 4)}
+            "eps2_t_ratio_unit_norm": round(float(e2_le[1] * t_learn / (e2_pl[1] * t_pl)), 4),
+            "path_tracing": {"estimator": "object-space path tracing, next-event estimation, same texels",
+                             "samples_per_texel": M_pt, "seeds": pt_seeds, "adjoint_ms": round(t_pt, 3),
+                             "eps": round(float(e_pt[:, 0].mean()), 6), "eps2": float(e2_pt[0]),
+                             "eps2_unit_norm": float(e2_pt[1]),
+                             "mean_vs_reference": round(bias, 6), "mean_standard_error": round(bias_se, 6),
+                             "eps2_t_ratio_vs_light_tracing": round(float(e2_pt[0] * t_pt / (e2_pl[0] * t_pl)), 3),
+                             "eps2_t_ratio_vs_light_tracing_unit_norm":
+                                 round(float(e2_pt[1] * t_pt / (e2_pl[1] * t_pl)), 3)}}
 
 
 def main():

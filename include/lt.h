@@ -187,6 +187,28 @@ int lt_trace_adjoint(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params
 int lt_gradient_votes(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, const float* d_dOdE,
                       int32_t light, int32_t param, double* d_vote, float* d_grad);
 
+/* Object-space path tracing with next-event estimation: the comparison
+ * estimator of Sec. 6 (after Stam 2020) on the same texels.  Each texel gets
+ * samples_per_texel points drawn uniformly in it; every path vertex (the
+ * point, then up to cfg->max_hits - 1 cosine bounces, the first on a side
+ * drawn with probability 1/2) connects to one luminaire of its layout chosen
+ * uniformly, through a shadow ray.  E_k is the mean over the texel's samples
+ * of the irradiance estimates (both sides of the surface, like the light
+ * tracer's splat).  cfg: seed and max_hits as for light tracing
+ * (paths_per_layout is only checked against the luminaire counts); flags
+ * must be 0.  At most 256 luminaires per layout and fewer than 2^32 samples
+ * per layout (K samples_per_texel).  d_S [n_layouts,K] i64 scratch, d_E
+ * [n_layouts,K] f32 out, as for lt_trace_forward. */
+int lt_pt_forward(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, int32_t samples_per_texel,
+                  int64_t* d_S, float* d_E);
+
+/* Gradient of sum_k dOdE_k E_k for the path tracer above with the same
+ * samples (same seed): every luminaire connection differentiated with its
+ * vertex held fixed (the first-hit derivative factors at that vertex; no
+ * visibility terms).  d_dOdE [n_layouts,K] f32; d_grad [L,6] f32 out. */
+int lt_pt_adjoint(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, int32_t samples_per_texel,
+                  const float* d_dOdE, float* d_grad);
+
 /* Hit sequences of paths [first, first+count) of light `light` (index within
  * its layout `layout`): d_prim / d_texel [count, max_hits] i32, -1 where the
  * path ended.  With d_dOdE, d_contrib [count,6] f32 receives each path's

@@ -75,6 +75,8 @@ struct lt_ctx {
     size_t partials_cap = 0;
     int* d_gstack = nullptr;
     size_t gstack_cap = 0;
+    double* d_ptgrad = nullptr;      // path tracer: FP64 gradient accumulator [L,6]
+    size_t ptgrad_cap = 0;
 
     lt_tuning tune;
     std::vector<GraphEntry> graphs;
@@ -413,7 +415,7 @@ void lt_destroy(lt_ctx* c)
     hipFree(c->d_si); hipFree(c->d_sf); hipFree(c->d_lights);
     hipFree(c->prop_pdf); hipFree(c->prop_cdf); hipFree(c->prop_guide); hipFree(c->inv_sigma); hipFree(c->mlp_scratch);
     hipFree(c->d_misses); hipFree(c->d_flags); hipFree(c->d_stats);
-    hipFree(c->d_objpart); hipFree(c->d_partials); hipFree(c->d_gstack);
+    hipFree(c->d_objpart); hipFree(c->d_partials); hipFree(c->d_gstack); hipFree(c->d_ptgrad);
     if (c->ev_in) hipEventDestroy(c->ev_in);
     if (c->ev_out) hipEventDestroy(c->ev_out);
     if (c->gstream) hipStreamDestroy(c->gstream);
@@ -691,6 +693,101 @@ int lt_gradient_votes(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params,
     return run_seq(c, graph,
                    make_key(c, 4, cfg, {d_params, d_dOdE, d_grad, d_vote, (const void*)(uintptr_t)(light * 8 + param)}),
                    body);
+}
+
+namespace {
+
+int pt_check(lt_ctx* c, const lt_trace_cfg* cfg, int32_t samples_per_texel)
+{
+    int rc = check_cfg(c, cfg);
+    if (rc) return rc;
+    if (cfg->flags != 0) return fail(c, LT_EINVAL, "the path tracer takes no flags");
+    if (samples_per_texel < 1) return fail(c, LT_EINVAL, "samples_per_texel must be >= 1");
+    if (c->K * (long long)samples_per_texel > 0xFFFFFFFFll)
+        return fail(c, LT_EINVAL, "more than 2^32 samples per layout");
+    for (int j = 0; j < c->n_layouts; ++j)
+        if (c->offs[j + 1] - c->offs[j] > kPtMaxLights)
+            return fail(c, LT_EINVAL, "the path tracer takes at most 256 luminaires per layout");
+    return ensure_gstack(c, (long long)kPtBlocks * 4);
+}
+
+PtArgs pt_args(lt_ctx* c, const lt_trace_cfg* cfg, int32_t samples_per_texel, int j)
+{
+    PtArgs a;
+    memset(&a, 0, sizeof(a));
+    a.nodes = c->nodes;
+    a.tris = c->tris;
+    a.patches = c->patches;
+    a.pbase = c->pbase;
+    a.n_patches = c->n_patches;
+    a.lights = c->d_lights + c->offs[j];
+    a.nl = c->offs[j + 1] - c->offs[j];
+    a.layout = j;
+    a.K = c->K;
+    a.M = samples_per_texel;
+    a.max_hits = cfg->max_hits;
+    a.key0 = (uint32_t)cfg->seed;
+    a.key1 = (uint32_t)(cfg->seed >> 32);
+    a.gstack = c->d_gstack;
+    a.gdepth = std::max(gstack_depth(c), 1);
+    a.max_steps = 2 * c->n_nodes + 16;
+    a.flags = c->d_flags;
+    return a;
+}
+
+}  // namespace
+
+int lt_pt_forward(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int32_t samples_per_texel, int64_t* d_S,
+                  float* d_E)
+{
+    if (!c) return LT_EINVAL;
+    if (!d_params || !d_S || !d_E) return fail(c, LT_EINVAL, "NULL device buffer");
+    if (((uintptr_t)d_S & 15) || ((uintptr_t)d_E & 7) || ((uintptr_t)d_params & 3))
+        return fail(c, LT_EINVAL, "d_S must be 16-byte and d_E 8-byte aligned");
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = pt_check(c, cfg, samples_per_texel);
+    if (rc) return rc;
+    const long long n = c->K * c->n_layouts;
+    hipStream_t st = c->stream;
+    HIPCHK(c, launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st));
+    HIPCHK(c, launch_clear((long long*)d_S, n, st));
+    for (int j = 0; j < c->n_layouts; ++j) {
+        PtArgs a = pt_args(c, cfg, samples_per_texel, j);
+        a.S = (long long*)d_S + (long long)j * c->K;
+        HIPCHK(c, launch_pt(false, a, c->tune.lds_depth, st));
+    }
+    HIPCHK(c, launch_finalize((const long long*)d_S, d_E, n, c->d_flags, st));
+    return LT_OK;
+}
+
+int lt_pt_adjoint(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int32_t samples_per_texel,
+                  const float* d_dOdE, float* d_grad)
+{
+    if (!c) return LT_EINVAL;
+    if (!d_params || !d_dOdE || !d_grad) return fail(c, LT_EINVAL, "NULL device buffer");
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = pt_check(c, cfg, samples_per_texel);
+    if (rc) return rc;
+    const size_t need = (size_t)c->L * 6;
+    if (c->ptgrad_cap < need) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        hipFree(c->d_ptgrad);
+        c->d_ptgrad = nullptr;
+        c->ptgrad_cap = 0;
+        HIPCHK(c, hipMalloc(&c->d_ptgrad, sizeof(double) * need));
+        c->ptgrad_cap = need;
+    }
+    hipStream_t st = c->stream;
+    HIPCHK(c, launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st));
+    HIPCHK(c, launch_fill_f32((float*)c->d_ptgrad, (long long)need * 2, 0.0f, st));
+    for (int j = 0; j < c->n_layouts; ++j) {
+        PtArgs a = pt_args(c, cfg, samples_per_texel, j);
+        a.g = d_dOdE + (long long)j * c->K;
+        a.grad = c->d_ptgrad + 6 * (long long)c->offs[j];
+        HIPCHK(c, launch_pt(true, a, c->tune.lds_depth, st));
+    }
+    HIPCHK(c, launch_f64_to_f32(c->d_ptgrad, d_grad, (long long)need, st));
+    return LT_OK;
 }
 
 int lt_record_paths(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int32_t layout, int32_t light,

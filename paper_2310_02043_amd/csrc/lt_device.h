@@ -183,7 +183,8 @@ struct DevLight {
     float c[3], d[3], t[3], b[3];
     float dd_da[3], dd_db[3], dt_db[3], db_da[3], db_db[3];
     float P, phi_r, n, w, h;
-    int type, layout, l_local, pad0;
+    int type, layout, l_local;
+    float kcap;  // soft-edged spot: flux scale of cap sampling (1 otherwise)
     long long n_paths;
     long long pad1;
 };  // 160 B

@@ -9,6 +9,8 @@ namespace lt {
 constexpr int kMaxStackDepth = 128;   // BVH depth bound accepted at upload
 constexpr int kObjBlocks = 1024;      // fixed grid of the objective reduction
 constexpr int kRecordBlocks = 1024;   // grid of the path-recording kernel (4 waves each)
+constexpr int kPtBlocks = 2048;       // grid of the path-tracing kernel (4 waves each)
+constexpr int kPtMaxLights = 256;     // luminaires per layout the path tracer accepts
 constexpr int kPlocRadius = 16;       // nearest-neighbour window of the BVH build
 constexpr int kBvhWidth = 4;          // children per node of the traversed tree
 constexpr int kEmptyChild = (int)0x80000000;  // unused child slot of a wide node
@@ -59,6 +61,29 @@ struct TraceArgs {
     int vote_param;             // 0..5
 };
 
+// Object-space path tracing over the texels of one layout.
+struct PtArgs {
+    const float4* nodes;
+    const float4* tris;
+    const DevPatch* patches;
+    const long long* pbase;     // first texel of each patch (ascending)
+    int n_patches;
+    const DevLight* lights;     // the layout's luminaires: lights[0 .. nl)
+    int nl;
+    int layout;
+    long long K;
+    int M;                      // samples per texel
+    int max_hits;               // path vertices (the texel point and its bounces)
+    uint32_t key0, key1;
+    long long* S;               // forward: [K] Q31.32 texel means (accumulated)
+    const float* g;             // adjoint: [K] dO/dE
+    double* grad;               // adjoint: [nl,6] accumulated
+    int* gstack;
+    int gdepth;
+    int max_steps;
+    unsigned* flags;
+};
+
 struct RecordArgs {
     const float4* nodes;
     const float4* tris;
@@ -94,6 +119,8 @@ hipError_t launch_light_setup(const float* params, const int4* lstat_i, const fl
                               const long long* npaths, int n_lights, DevLight* out, hipStream_t st);
 hipError_t launch_clear(long long* S, long long n_texels_total, hipStream_t st);
 hipError_t launch_fill_f32(float* p, long long n, float v, hipStream_t st);
+hipError_t launch_pt(bool adjoint, const PtArgs& a, int lds_depth, hipStream_t st);
+hipError_t launch_f64_to_f32(const double* in, float* out, long long n, hipStream_t st);
 hipError_t launch_finalize(const long long* S, float* E, long long n, unsigned* flags, hipStream_t st);
 hipError_t launch_objective(const float* E, const float* Et, const float* alpha, const float* A, long long K,
                             long long n, float* g, double* partials, double* O, hipStream_t st);

@@ -304,11 +304,8 @@ __device__ __forceinline__ void emit(const DevLight& L, uint32_t pid, uint32_t s
 
 // Cosine-weighted bounce about the oriented normal (Malley's method in the
 // orthonormal basis of Duff et al. 2017); the flux update is Phi * rho.
-__device__ __forceinline__ V3 bounce_dir(V3 no, uint32_t pid, uint32_t stream_id, uint32_t h, uint32_t k0,
-                                         uint32_t k1)
+__device__ __forceinline__ V3 cosine_dir(V3 no, float u0, float u1)
 {
-    const U4 r = philox10(pid, stream_id, 1u + h, 0u, k0, k1);
-    const float u0 = u24(r.x), u1 = u24(r.y);
     const float sg = __builtin_copysignf(1.0f, no.z);
     const float a = -1.0f / (sg + no.z);
     const float bxy = (no.x * no.y) * a;
@@ -321,6 +318,13 @@ __device__ __forceinline__ V3 bounce_dir(V3 no, uint32_t pid, uint32_t stream_id
     const float lz = __builtin_sqrtf(fmaxf(0.0f, 1.0f - u0));
     return v3((lx * b1.x + ly * b2.x) + lz * no.x, (lx * b1.y + ly * b2.y) + lz * no.y,
               (lx * b1.z + ly * b2.z) + lz * no.z);
+}
+
+__device__ __forceinline__ V3 bounce_dir(V3 no, uint32_t pid, uint32_t stream_id, uint32_t h, uint32_t k0,
+                                         uint32_t k1)
+{
+    const U4 r = philox10(pid, stream_id, 1u + h, 0u, k0, k1);
+    return cosine_dir(no, u24(r.x), u24(r.y));
 }
 
 // dlog of the first-hit irradiance kernel w.r.t. (c, alpha, beta, P) with x_1
@@ -772,6 +776,182 @@ __global__ void __launch_bounds__(256) k_record(RecordArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Object-space path tracing with next-event estimation, the comparison
+// estimator of Sec. 6 (after Stam 2020) on the same texels: M points uniform
+// in each texel; every path vertex connects to one luminaire of the layout
+// chosen uniformly (shadow ray); the path continues with the light tracer's
+// cosine bounce (at the texel point on a side drawn with probability 1/2).
+// The gradient differentiates each connection with its vertex held fixed:
+// the first-hit derivative factors evaluated at that vertex.
+// ---------------------------------------------------------------------------
+
+// radiant intensity towards unit direction w from the luminaire's origin
+__device__ __forceinline__ float light_intensity(const DevLight& L, V3 w)
+{
+    if (L.type == 0) return L.P * 0.07957747154594767f;
+    const float ce = dot(v3(L.d[0], L.d[1], L.d[2]), w);
+    if (L.type == 3) {
+        if (!(ce > L.h)) return 0.0f;
+        float a = 1.0f;
+        if (ce < L.w) {
+            const float f = (ce - L.h) / (L.w - L.h);
+            a = f * f;
+        }
+        return ((L.P * L.kcap) * a) * (0.15915494309189533f / (1.0f - L.h));
+    }
+    if (!(ce > 0.0f)) return 0.0f;
+    float pw = 1.0f;
+    if (L.n != 0.0f) pw = exp2_c(L.n * log2_c(ce));
+    return L.P * (((L.n + 1.0f) * 0.15915494309189533f) * pw);
+}
+
+// closest hit along r (origin patch skipped) with t < tmax; per-lane loop
+template <int LDS_D>
+__device__ __forceinline__ void trace_lane(const Ray& r, int skip, float tmax, Trav& s, const float4* nodes,
+                                           const float4* tris, int* lst, int* gst, int max_steps, bool& overrun)
+{
+    start_segment(s);
+    s.tb = tmax;
+    bool trav = true;
+    unsigned d0 = 0, d1 = 0;
+    while (trav) trav_step<LDS_D, false>(r, skip, s, trav, nodes, tris, lst, gst, d0, d1, max_steps, overrun);
+}
+
+template <bool ADJ, int LDS_D>
+__global__ void __launch_bounds__(256) k_pt(PtArgs a)
+{
+    __shared__ int s_stack[4 * LDS_D * 64];
+    __shared__ double s_grad[ADJ ? kPtMaxLights * 6 : 1];
+    const int lane = threadIdx.x & 63;
+    const int wib = threadIdx.x >> 6;
+    const long long gw = (long long)blockIdx.x * 4 + wib;
+    int* lst = s_stack + wib * LDS_D * 64 + lane;
+    int* gst = a.gstack + gw * (long long)a.gdepth * 64 + lane;
+    if (ADJ) {
+        for (int j = threadIdx.x; j < a.nl * 6; j += 256) s_grad[j] = 0.0;
+        __syncthreads();
+    }
+    const uint32_t stream = ((uint32_t)a.layout << 16) | 0xFFFFu;
+    const float inv_m = 1.0f / (float)a.M;
+    const float fl = (float)a.nl;
+    const long long total = a.K * a.M;
+    const long long stride = (long long)gridDim.x * 256;
+    bool overrun = false;
+    for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < total; idx += stride) {
+        const long long k = idx / a.M;
+        // patch of texel k: the last patch whose first texel is <= k
+        int lo = 0, hi = a.n_patches - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.pbase[mid] <= k) lo = mid;
+            else hi = mid - 1;
+        }
+        const int q = lo;
+        const DevPatch& P = a.patches[q];
+        const long long loc = k - P.base;
+        const int iu = (int)(loc % P.res_u), iv = (int)(loc / P.res_u);
+        const uint32_t pid = (uint32_t)idx;
+        const U4 r0 = philox10(pid, stream, 0u, 0u, a.key0, a.key1);
+        const float su = ((float)iu + u24(r0.x)) / (float)P.res_u;
+        const float sv = ((float)iv + u24(r0.y)) / (float)P.res_v;
+        const float4 o = P.o_inva, eu = P.eu_ilu, ev = P.ev_ilv;
+        V3 v = v3((o.x + su * eu.x) + sv * ev.x, (o.y + su * eu.y) + sv * ev.y, (o.z + su * eu.z) + sv * ev.z);
+        const V3 nq0 = xyz(P.n_rho);
+        const float gk = ADJ ? a.g[k] * inv_m : 0.0f;
+        float e = 0.0f, T = 1.0f;
+        int qv = q;
+        bool have_side = false;
+        V3 nside = nq0;
+        for (int h = 0; h < a.max_hits; ++h) {
+            // connection to one luminaire chosen uniformly
+            const U4 rl = philox10(pid, stream, 1u + 2u * (uint32_t)h, 0u, a.key0, a.key1);
+            int ls = (int)(u24(rl.x) * fl);
+            ls = ls > a.nl - 1 ? a.nl - 1 : ls;
+            const DevLight& L = a.lights[ls];
+            V3 y = v3(L.c[0], L.c[1], L.c[2]);
+            float au = 0.0f, av = 0.0f;
+            if (L.type == 2) {
+                au = (u24(rl.y) - 0.5f) * L.w;
+                av = (u24(rl.z) - 0.5f) * L.h;
+                y = v3((L.c[0] + au * L.t[0]) + av * L.b[0], (L.c[1] + au * L.t[1]) + av * L.b[1],
+                       (L.c[2] + au * L.t[2]) + av * L.b[2]);
+            }
+            const V3 vec = sub(v, y);
+            const float r2 = dot(vec, vec);
+            if (r2 > 1e-12f) {
+                const float rd = __builtin_sqrtf(r2);
+                const float inv_r = 1.0f / rd;
+                const V3 w = v3(vec.x * inv_r, vec.y * inv_r, vec.z * inv_r);
+                const V3 nqv = xyz(a.patches[qv].n_rho);
+                V3 n1;
+                if (have_side) n1 = nside;
+                else n1 = dot(nqv, w) < 0.0f ? nqv : v3(-nqv.x, -nqv.y, -nqv.z);
+                const float cv = -dot(n1, w);
+                const float I = cv > 0.0f ? light_intensity(L, w) : 0.0f;
+                if (I > 0.0f) {
+                    const float C = (I * cv) / r2;
+                    Ray sr;
+                    set_ray(sr, v, v3(-w.x, -w.y, -w.z));
+                    Trav s;
+                    trace_lane<LDS_D>(sr, qv, rd * 0.9999f, s, a.nodes, a.tris, lst, gst, a.max_steps, overrun);
+                    if (s.pb < 0) {
+                        const float we = (T * fl) * C;
+                        e = e + we;
+                        if (ADJ) {
+                            float dl[6];
+                            first_hit_dlog(L, v, y, n1, au, av, dl);
+#pragma unroll
+                            for (int c = 0; c < 6; ++c) atomicAdd(&s_grad[ls * 6 + c], (double)((gk * we) * dl[c]));
+                        }
+                    }
+                }
+            }
+            if (h == a.max_hits - 1) break;
+            // bounce: at the texel point a side drawn with probability 1/2
+            // (weight 2), later the side facing the incoming ray
+            V3 no;
+            if (!have_side) {
+                const float sg = u24(r0.z) < 0.5f ? 1.0f : -1.0f;
+                no = v3(sg * nq0.x, sg * nq0.y, sg * nq0.z);
+                T = T * 2.0f;
+            } else {
+                no = nside;
+            }
+            const U4 rb = philox10(pid, stream, 2u + 2u * (uint32_t)h, 0u, a.key0, a.key1);
+            const V3 dir = cosine_dir(no, u24(rb.x), u24(rb.y));
+            Ray br;
+            set_ray(br, v, dir);
+            Trav s;
+            trace_lane<LDS_D>(br, qv, __builtin_inff(), s, a.nodes, a.tris, lst, gst, a.max_steps, overrun);
+            if (s.pb < 0) break;
+            const HitInfo hn = hit_info(br, s.tb, s.qb, a.patches);
+            T = T * hn.rho;
+            v = hn.x;
+            qv = s.qb;
+            nside = hn.no;
+            have_side = true;
+        }
+        if (!ADJ) {
+            const long long code = (long long)__builtin_rintf((e * inv_m) * 4294967296.0f);
+            __hip_atomic_fetch_add((unsigned long long*)(a.S + k), (unsigned long long)code, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    if (overrun) atomicOr(a.flags, 2u);
+    if (ADJ) {
+        __syncthreads();
+        for (int j = threadIdx.x; j < a.nl * 6; j += 256)
+            if (s_grad[j] != 0.0) atomicAdd(a.grad + j, s_grad[j]);
+    }
+}
+
+__global__ void k_f64_to_f32(const double* __restrict__ in, float* __restrict__ out, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
+}
+
 // Luminaire setup: frame R = R_y(beta) R_x(alpha), derivatives, Phi_r = P/N_l.
 // lstat_i = (type, layout, l_local, -), lstat_f = (n, w, h, N_l as float bits unused).
 __global__ void k_light_setup(const float* __restrict__ params, const int4* __restrict__ si,
@@ -805,6 +985,7 @@ __global__ void k_light_setup(const float* __restrict__ params, const int4* __re
     L.w = f4.y;
     L.h = f4.z;
     L.type = i4.x;
+    L.kcap = 1.0f;
     if (L.type == 3) {
         // soft-edged spot: w, h carry the cosines of the inner and outer cone
         // angles; P is the total flux, so Phi_r = (P/N) kcap a(cos) with
@@ -816,10 +997,10 @@ __global__ void k_light_setup(const float* __restrict__ params, const int4* __re
         L.h = (float)co_d;
         const float kcap = (float)((1.0 - co_d) / ((1.0 - ci_d) + (ci_d - co_d) / 3.0));
         L.phi_r = L.phi_r * kcap;
+        L.kcap = kcap;
     }
     L.layout = i4.y;
     L.l_local = i4.z;
-    L.pad0 = 0;
     L.pad1 = 0;
     out[l] = L;
 }
@@ -979,6 +1160,25 @@ hipError_t launch_trace(bool adjoint, bool stats, const TraceArgs& a, int waves_
     if (adjoint) return launch_t<true, false>(a, waves_per_block, lds_depth, blocks, st);
     if (stats) return launch_t<false, true>(a, waves_per_block, lds_depth, blocks, st);
     return launch_t<false, false>(a, waves_per_block, lds_depth, blocks, st);
+}
+
+hipError_t launch_pt(bool adjoint, const PtArgs& a, int lds_depth, hipStream_t st)
+{
+    const int blocks = nblocks(a.K * a.M, 256, kPtBlocks);
+    if (adjoint) {
+        if (lds_depth == 16) k_pt<true, 16><<<blocks, 256, 0, st>>>(a);
+        else k_pt<true, 32><<<blocks, 256, 0, st>>>(a);
+    } else {
+        if (lds_depth == 16) k_pt<false, 16><<<blocks, 256, 0, st>>>(a);
+        else k_pt<false, 32><<<blocks, 256, 0, st>>>(a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_f64_to_f32(const double* in, float* out, long long n, hipStream_t st)
+{
+    k_f64_to_f32<<<(int)((n + 255) / 256), 256, 0, st>>>(in, out, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_record(const RecordArgs& a, int lds_depth, hipStream_t st)

@@ -21,7 +21,7 @@ LT_FLAG_GRAPH, LT_FLAG_PROPOSAL, LT_FLAG_LINEAR = 1, 2, 4
 EXPORTED = [
     "lt_create", "lt_destroy", "lt_last_error", "lt_set_stream", "lt_sync", "lt_scene_upload",
     "lt_set_lights", "lt_trace_forward", "lt_objective", "lt_trace_adjoint", "lt_gradient_votes",
-    "lt_record_paths",
+    "lt_pt_forward", "lt_pt_adjoint", "lt_record_paths",
     "lt_trace_stats", "lt_get_tuning", "lt_set_tuning", "lt_autotune", "lt_info_get", "lt_set_timing",
     "lt_timing_read", "lt_proposal_set_table", "lt_proposal_get_table", "lt_proposal_set_scale",
     "lt_proposal_mlp_infer",
@@ -85,6 +85,8 @@ def load():
     L.lt_objective.argtypes = [P, P, P, P, I64, P, P]
     L.lt_trace_adjoint.argtypes = [P, C.POINTER(TraceCfg), P, P, P, P]
     L.lt_gradient_votes.argtypes = [P, C.POINTER(TraceCfg), P, P, I32, I32, P, P]
+    L.lt_pt_forward.argtypes = [P, C.POINTER(TraceCfg), P, I32, P, P]
+    L.lt_pt_adjoint.argtypes = [P, C.POINTER(TraceCfg), P, I32, P, P]
     L.lt_record_paths.argtypes = [P, C.POINTER(TraceCfg), P, I32, I32, I64, I64, P, P, P, P]
     L.lt_trace_stats.argtypes = [P, C.POINTER(TraceCfg), P, P, C.POINTER(I64)]
     L.lt_get_tuning.argtypes = [P, C.POINTER(Tuning)]
@@ -242,6 +244,35 @@ class Context:
         self._check(self.lib.lt_gradient_votes(self.h, C.byref(cfg), _ptr(params), _ptr(dOdE), int(light),
                                                int(param), _ptr(vote), _ptr(grad)))
         return vote, grad
+
+    def pt_forward(self, params, cfg, samples_per_texel, S=None, E=None):
+        """Object-space path tracing with next-event estimation: (E, S)."""
+        torch = self._torch
+        n = (self.n_layouts, self.n_texels)
+        self._dev(params, torch.float32, (self.n_lights, 6))
+        if S is None:
+            S = torch.empty(n, dtype=torch.int64, device=params.device)
+        if E is None:
+            E = torch.empty(n, dtype=torch.float32, device=params.device)
+        self._dev(S, torch.int64, n)
+        self._dev(E, torch.float32, n)
+        self._stream()
+        self._check(self.lib.lt_pt_forward(self.h, C.byref(cfg), _ptr(params), int(samples_per_texel), _ptr(S),
+                                           _ptr(E)))
+        return E, S
+
+    def pt_adjoint(self, params, dOdE, cfg, samples_per_texel, grad=None):
+        """Gradient of sum_k dOdE_k E_k for the path tracer: [L,6]."""
+        torch = self._torch
+        self._dev(params, torch.float32, (self.n_lights, 6))
+        self._dev(dOdE, torch.float32, (self.n_layouts, self.n_texels))
+        if grad is None:
+            grad = torch.empty((self.n_lights, 6), dtype=torch.float32, device=params.device)
+        self._dev(grad, torch.float32, (self.n_lights, 6))
+        self._stream()
+        self._check(self.lib.lt_pt_adjoint(self.h, C.byref(cfg), _ptr(params), int(samples_per_texel), _ptr(dOdE),
+                                           _ptr(grad)))
+        return grad
 
     def record_paths(self, params, cfg, layout, light, first, count, dOdE=None):
         torch = self._torch
