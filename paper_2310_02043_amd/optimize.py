@@ -4,7 +4,10 @@ paper uses ADAM with beta1 = 0.9, beta2 = 0.999).
 
 The parameters are optimised in scaled units, p = p0 + q * scale, so one Adam
 step moves every free coordinate by about lr * scale (metres, radians,
-watts).  Coordinates outside `mask` stay fixed (ceiling luminaires keep their
+watts).  With power="quadratic" the power is P = w^2 / 2 and w is the
+optimised coordinate (Sec. 4.4.3 parametrises intensity this way so that it
+cannot turn negative); its scale is then the step in P at the initial
+power.  Coordinates outside `mask` stay fixed (ceiling luminaires keep their
 mounting height), and every step is projected back into [lo, hi].  Each
 iteration traces a fresh seed; the adjoint pass uses a decorrelated seed
 (Sec. 4.3).  With a LearnedProposal attached to the tracer, the adjoint pass
@@ -31,7 +34,7 @@ from .autograd import LightTracer, objective
 def optimize(tracer: LightTracer, params0, target, texel_area, steps: int, lr: float = 0.1, scale=None,
              mask=None, lo=None, hi=None, alpha=None, seed: int = 1, train_every: int = 1,
              proposal_train_steps: int = 4, proposal_warmup: int = 30, warmup_paths: int = 1 << 24,
-             callback=None):
+             callback=None, power: str = "linear"):
     """Minimise O(E(p)) = 1/2 sum_k A_k alpha_k (E_k - E*_k)^2 over the luminaire
     parameters [L,6].  Returns (params, history); history holds each
     iteration's objective (from its own forward pass) and wall time.
@@ -46,6 +49,27 @@ def optimize(tracer: LightTracer, params0, target, texel_area, steps: int, lr: f
     mk = ones if mask is None else torch.as_tensor(mask, dtype=torch.float32, device=dev)
     lo_t = None if lo is None else torch.as_tensor(lo, dtype=torch.float32, device=dev)
     hi_t = None if hi is None else torch.as_tensor(hi, dtype=torch.float32, device=dev)
+    if power not in ("linear", "quadratic"):
+        raise ValueError("power must be 'linear' or 'quadratic'")
+    quad = power == "quadratic"
+    w0 = torch.sqrt(2.0 * p0[:, 5]) if quad else None
+    sw = (sc[5] / w0.clamp_min(1e-6)) if quad else None      # w step per unit of q, per light
+
+    def params_of(qq):
+        p = p0 + qq * sc
+        if quad:
+            w = w0 + qq[:, 5] * sw
+            p = torch.cat([p[:, :5], (0.5 * w * w)[:, None]], 1)
+        return p
+
+    def project(qq):
+        p = torch.maximum(torch.minimum(p0 + qq * sc, hi_t), lo_t)
+        out = (p - p0) / sc
+        if quad:
+            w = (w0 + qq[:, 5] * sw).clamp(torch.sqrt(2.0 * lo_t[5].clamp_min(0.0)), torch.sqrt(2.0 * hi_t[5]))
+            out[:, 5] = (w - w0) / sw
+        return out
+
     q = torch.zeros_like(p0, requires_grad=True)
     opt = torch.optim.Adam([q], lr=lr, betas=(0.9, 0.999))
     prop = tracer.proposal
@@ -68,7 +92,8 @@ def optimize(tracer: LightTracer, params0, target, texel_area, steps: int, lr: f
     for it in range(steps):
         t0 = t_warm if it == 0 else time.perf_counter()
         tracer.seed = seed + 7919 * it
-        p = (p0 + q * sc).contiguous()
+        p = params_of(q).contiguous()
+        p.retain_grad()
         if prop is not None:
             prop.refresh(p)
             prop.collect = (it % train_every) == 0
@@ -77,12 +102,12 @@ def optimize(tracer: LightTracer, params0, target, texel_area, steps: int, lr: f
         opt.zero_grad()
         O.backward()
         with torch.no_grad():
-            grad_p = q.grad / sc
+            grad_p = p.grad.detach().clone()
             q.grad.mul_(mk)
         opt.step()
         with torch.no_grad():
             if lo_t is not None:
-                q.copy_(torch.maximum(torch.minimum(p0 + q * sc, hi_t), lo_t).sub_(p0).div_(sc))
+                q.copy_(project(q))
         if prop is not None and prop.collect:
             prop.update_scale(grad_p, mask=mk)
             prop.train(steps=proposal_train_steps)
@@ -97,7 +122,8 @@ def optimize(tracer: LightTracer, params0, target, texel_area, steps: int, lr: f
     if prop is not None:
         prop.collect = True
     tracer.correlated = correlated
-    return (p0 + q.detach() * sc), hist
+    with torch.no_grad():
+        return params_of(q.detach()), hist
 
 
 def evaluate(tracer: LightTracer, params, target, texel_area, paths: int, seed: int = 0xE7A1):
@@ -132,6 +158,8 @@ def main(argv=None):
     ap.add_argument("--target-paths", type=int, default=1 << 28)
     ap.add_argument("--json", type=str, default="")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--power", choices=["linear", "quadratic"], default="linear",
+                    help="optimise P directly or w with P = w^2 / 2")
     a = ap.parse_args(argv)
     gen, steps, lr, scale, mask = WORKLOADS[a.workload]
     steps = a.steps or steps
@@ -173,7 +201,7 @@ def main(argv=None):
 
     t0 = time.perf_counter()
     p, hist = optimize(tracer, p0, target, area, steps, lr=lr, scale=scale, mask=mask, lo=lo, hi=hi,
-                       seed=wl["seed"], callback=cb)
+                       seed=wl["seed"], callback=cb, power=a.power)
     wall = time.perf_counter() - t0
     O1 = evaluate(tracer, p, target, area, a.eval_paths)
     Opt = evaluate(tracer, pt, target, area, a.eval_paths, seed=0xE7A2)

@@ -68,6 +68,38 @@ def test_optimize_projects_into_bounds():
     assert abs(float(p[0, 3]) - 0.15) < 1e-6 and abs(float(p[0, 4]) + 0.15) < 1e-6
 
 
+def test_optimize_quadratic_power():
+    """P = w^2 / 2 with w optimised (Sec. 4.4.3): recovers the parameters, the
+    power stays positive when the linear form would overshoot below zero, and
+    dO/dP reaches the optimiser through the chain rule (the first step's
+    direction in P matches the linear form's)."""
+    from paper_2310_02043_amd.optimize import optimize
+    g = torch.Generator().manual_seed(1)
+    L, K = 2, 120
+    M = torch.randn(K, 6 * L, generator=g, dtype=torch.float32)
+    p_true = torch.tensor([[1.0, 2.0, 2.85, 0.05, -0.05, 3.0], [2.5, 1.0, 2.85, -0.02, 0.04, 60.0]])
+    target = (M @ p_true.reshape(-1)).reshape(1, -1)
+    p0 = p_true.clone()
+    p0[:, 0] += 0.3
+    p0[:, 5] = torch.tensor([12.0, 45.0])
+    lo = [0.0, 0.0, 0.0, -0.15, -0.15, 0.0]
+    hi = [10.0, 10.0, 3.0, 0.15, 0.15, 200.0]
+    kw = dict(scale=[1, 1, 1, 0.5, 0.5, 10.0], mask=[1, 1, 0, 1, 1, 1], lo=lo, hi=hi)
+    p, hist = optimize(LinearTracer(M), p0, target, torch.ones(K), 600, lr=0.05, power="quadratic", **kw)
+    assert hist[-1]["objective"] < 1e-4 * hist[0]["objective"]
+    assert torch.allclose(p[:, [0, 1, 3, 4, 5]], p_true[:, [0, 1, 3, 4, 5]], atol=3e-2, rtol=1e-3)
+    # one step each way: same sign of the change in P
+    p_lin, _ = optimize(LinearTracer(M), p0, target, torch.ones(K), 1, lr=0.05, **kw)
+    p_quad, _ = optimize(LinearTracer(M), p0, target, torch.ones(K), 1, lr=0.05, power="quadratic", **kw)
+    assert torch.equal(torch.sign(p_lin[:, 5] - p0[:, 5]), torch.sign(p_quad[:, 5] - p0[:, 5]))
+    # a huge step: linear P is clipped at the bound 0, quadratic P stays >= 0 without it
+    lo0 = list(lo)
+    lo0[5] = -1e9
+    p_big, _ = optimize(LinearTracer(M), p0, target, torch.ones(K), 30, lr=3.0, power="quadratic",
+                        scale=kw["scale"], mask=kw["mask"], lo=lo0, hi=hi)
+    assert torch.all(p_big[:, 5] >= 0)
+
+
 def _cell_mass_spherical(n, res=32, nt=400, nph=800):
     """Independent check: integrate (n+1)/(2 pi) cos^n theta over the
     hemisphere in (theta, phi) and bin each direction into its hemi-octahedral
