@@ -31,18 +31,19 @@ def torch_dev():
     return torch
 
 
-def tracer_for(scene, lights, ppl, B, seed):
+def tracer_for(scene, lights, ppl, B, seed, linear=False):
     from paper_2310_02043_amd.autograd import LightTracer
     return LightTracer((scene.verts, scene.tris, scene.tri_patch, scene.patches), lights.static,
-                       lights.layout_offsets, ppl, B, seed=seed)
+                       lights.layout_offsets, ppl, B, seed=seed, linear=linear)
 
 
-def test_autograd_equals_adjoint(torch_dev):
+@pytest.mark.parametrize("basis", ["box", "linear"])
+def test_autograd_equals_adjoint(torch_dev, basis):
     torch = torch_dev
     from paper_2310_02043_amd.autograd import objective
     c1 = li.box_room()
     sc, lights = c1["scene"], c1["lights"]
-    tr = tracer_for(sc, lights, 1 << 20, 3, 5)
+    tr = tracer_for(sc, lights, 1 << 20, 3, 5, linear=basis == "linear")
     A = torch.tensor(sc.texel_area(), device="cuda")
     Et = torch.tensor(li.painted_target(sc, 20.0)[None], device="cuda")
     p = torch.tensor(lights.params, device="cuda", requires_grad=True)

@@ -153,10 +153,12 @@ def test_proposal_sampling_parity(torch_dev, oracle_lib):
     assert err <= 1e-3 and herr <= 1e-4
 
 
-def test_proposal_mixed_light_types(torch_dev, oracle_lib):
+@pytest.mark.parametrize("basis", ["box", "linear"])
+def test_proposal_mixed_light_types(torch_dev, oracle_lib, basis):
     """Box room with a point light, a cos^n spot, a rectangle and a
     soft-edged spot under a proposal table: the table applies to the spot and
-    the rectangle only, on both sides; histogram rows of the others stay 0."""
+    the rectangle only, on both sides; histogram rows of the others stay 0.
+    With the box and the piecewise-linear texel basis."""
     from lt_inputs.scenes import make_lights, POINT, SPOT, RECT, SOFT
     torch = torch_dev
     sc = li.box_room()["scene"]
@@ -171,11 +173,11 @@ def test_proposal_mixed_light_types(torch_dev, oracle_lib):
     ctx.proposal_set_table(d(pdf), d(cdf))
     ctx.proposal_set_scale(d(inv_sigma))
     N, B, seed = 1 << 18, 4, 0x5A5
-    cfg = ctx.cfg(seed, N, B, proposal=True, alpha_plain=0.3)
+    cfg = ctx.cfg(seed, N, B, proposal=True, alpha_plain=0.3, linear=basis == "linear")
     p_d = d(lights.params)
     E_d, S_d = ctx.trace_forward(p_d, cfg)
     prop = oracle_lib.Proposal(pdf, cdf, 0.3, inv_sigma=inv_sigma, with_hist=True)
-    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    osc, ol = oracle_lib.OracleScene(sc, basis=basis), oracle_lib.OracleLights(lights)
     S_ref, _ = oracle_lib.forward(osc, ol, lights.params, seed, N, B, proposal=prop)
     same = float((S_d.cpu().numpy() == S_ref).mean())
     say(f"  texels bit-identical {same * 100:.4f} %")

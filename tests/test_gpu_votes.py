@@ -62,10 +62,11 @@ def target_grad(oracle_lib, osc, ol, scene, lights, params, seed, N, B):
     return oracle_lib.objective(E, Et, scene.texel_area())[1]
 
 
-def compare(torch, oracle_lib, ctx, osc, ol, params, seed, N, B, g, light, params_to_check, graph=False):
+def compare(torch, oracle_lib, ctx, osc, ol, params, seed, N, B, g, light, params_to_check, graph=False,
+            linear=False):
     p_d = torch.tensor(params, device="cuda")
     g_d = torch.tensor(g, device="cuda")
-    cfg = ctx.cfg(seed, N, B, graph=graph)
+    cfg = ctx.cfg(seed, N, B, graph=graph, linear=linear)
     for j in params_to_check:
         v_ref, grad_ref, _ = oracle_lib.votes(osc, ol, params, seed, N, B, g, light, j)
         v_d, grad_d = ctx.gradient_votes(p_d, g_d, cfg, light, j)
@@ -83,15 +84,18 @@ def compare(torch, oracle_lib, ctx, osc, ol, params, seed, N, B, g, light, param
         assert float(rel.max()) <= GRAD_BAR
 
 
-def test_votes_box_room_full(torch_dev, oracle_lib):
-    """Closed room with two boxes at full size (2^20 paths, 3 hits), every parameter."""
+@pytest.mark.parametrize("basis", ["box", "linear"])
+def test_votes_box_room_full(torch_dev, oracle_lib, basis):
+    """Closed room with two boxes at full size (2^20 paths, 3 hits), every
+    parameter, with the box and the piecewise-linear texel basis (the map
+    still names the texel that contains the first hit)."""
     c1 = li.box_room()
     sc, lights = c1["scene"], c1["lights"]
-    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    osc, ol = oracle_lib.OracleScene(sc, basis=basis), oracle_lib.OracleLights(lights)
     g = target_grad(oracle_lib, osc, ol, sc, lights, lights.params, c1["seed"], c1["paths"], c1["max_hits"])
     ctx = make_ctx(sc, lights)
     compare(torch_dev, oracle_lib, ctx, osc, ol, lights.params, c1["seed"], c1["paths"], c1["max_hits"], g, 0,
-            range(6))
+            range(6), linear=basis == "linear")
 
 
 @pytest.mark.parametrize("graph", [False, True])
