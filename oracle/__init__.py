@@ -33,7 +33,8 @@ def build(force: bool = True) -> str:
 class _Scene(C.Structure):
     _fields_ = [("verts", C.c_void_p), ("tris", C.c_void_p), ("tri_patch", C.c_void_p),
                 ("n_tris", C.c_int64), ("pf", C.c_void_p), ("pres", C.c_void_p), ("pbase", C.c_void_p),
-                ("n_patches", C.c_int32), ("n_texels", C.c_int64), ("basis", C.c_int32), ("bvh", C.c_void_p)]
+                ("n_patches", C.c_int32), ("n_texels", C.c_int64), ("basis", C.c_int32), ("bvh", C.c_void_p),
+                ("albedo_rgb", C.c_void_p)]
 
 
 class _Proposal(C.Structure):
@@ -61,7 +62,8 @@ def _prop(p):
 
 class _Lights(C.Structure):
     _fields_ = [("type", C.c_void_p), ("lobe_n", C.c_void_p), ("size", C.c_void_p),
-                ("layout_offsets", C.c_void_p), ("n_lights", C.c_int32), ("n_layouts", C.c_int32)]
+                ("layout_offsets", C.c_void_p), ("n_lights", C.c_int32), ("n_layouts", C.c_int32),
+                ("colour", C.c_void_p)]
 
 
 _lib = None
@@ -87,7 +89,7 @@ def lib():
         L.or_intersect_batch.argtypes = [P, P, C.c_int64, P, P, P]
         L.or_forward.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int64, C.c_int, P, P]
         L.or_forward.restype = C.c_int64
-        L.or_adjoint.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int64, C.c_int, P, P, P]
+        L.or_adjoint.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int64, C.c_int, P, P, P, P]
         L.or_adjoint.restype = C.c_int64
         L.or_votes.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int64, C.c_int, P, P, C.c_int,
                                C.c_int, P, P]
@@ -115,7 +117,7 @@ class OracleScene:
     "box" (one texel per hit) or "linear" (piecewise-linear nodes at the
     texel centres, Eq. pwLin)."""
 
-    def __init__(self, scene, use_bvh: bool = False, basis: str = "box"):
+    def __init__(self, scene, use_bvh: bool = False, basis: str = "box", albedo_rgb=None):
         self.scene = scene
         self.verts = np.ascontiguousarray(scene.verts, np.float32)
         self.tris = np.ascontiguousarray(scene.tris, np.int32)
@@ -134,6 +136,11 @@ class OracleScene:
                         int(self.tris.shape[0]), self.pf.ctypes.data, self.pres.ctypes.data,
                         self.pbase.ctypes.data, int(self.pf.shape[0]), self.n_texels,
                         {"box": 0, "linear": 1}[basis], self._bvh)
+        # per-patch channel albedos for the colour mode (else the scalar albedo)
+        self.albedo_rgb = None if albedo_rgb is None else np.ascontiguousarray(albedo_rgb, np.float32).reshape(-1, 3)
+        if self.albedo_rgb is not None:
+            assert self.albedo_rgb.shape[0] == self.pf.shape[0]
+            self.c.albedo_rgb = self.albedo_rgb.ctypes.data
 
     def __del__(self):
         if self._bvh is not None and _lib is not None:
@@ -142,7 +149,10 @@ class OracleScene:
 
 
 class OracleLights:
-    def __init__(self, lights):
+    """Luminaire statics; with `colour` ([L,3] channel weights of the flux)
+    the tracer runs in colour mode: texel arrays [n_layouts, 3, K]."""
+
+    def __init__(self, lights, colour=None):
         st = lights.static
         self.type = np.ascontiguousarray(st["type"], np.int32)
         self.lobe = np.ascontiguousarray(st["lobe_n"], np.float32)
@@ -152,6 +162,9 @@ class OracleLights:
         self.n_layouts = int(self.offs.shape[0] - 1)
         self.c = _Lights(self.type.ctypes.data, self.lobe.ctypes.data, self.size.ctypes.data,
                          self.offs.ctypes.data, self.n_lights, self.n_layouts)
+        self.colour = None if colour is None else np.ascontiguousarray(colour, np.float32).reshape(self.n_lights, 3)
+        if self.colour is not None:
+            self.c.colour = self.colour.ctypes.data
 
 
 def philox(ctr, key):
@@ -194,9 +207,11 @@ def intersect(osc: OracleScene, rays: np.ndarray, skip=None):
 
 def forward(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,
             limit_per_light: int = 0, n_threads: int = 0, proposal: Proposal = None):
-    """Alg. 1: returns (S [n_layouts,K] int64, misses)."""
+    """Alg. 1: returns (S [n_layouts,K] int64 ([n_layouts,3,K] in colour
+    mode), misses)."""
     prm = np.ascontiguousarray(params, np.float32)
-    S = np.zeros((ol.n_layouts, osc.n_texels), np.int64)
+    shape = (ol.n_layouts, osc.n_texels) if ol.colour is None else (ol.n_layouts, 3, osc.n_texels)
+    S = np.zeros(shape, np.int64)
     m = lib().or_forward(C.byref(osc.c), C.byref(ol.c), prm.ctypes.data, int(seed) & 0xFFFFFFFFFFFFFFFF,
                          int(paths_per_layout), int(max_hits), int(limit_per_light), int(n_threads),
                          _prop(proposal), S.ctypes.data)
@@ -206,7 +221,9 @@ def forward(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_lay
 def adjoint(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,
             dOdE, limit_per_light: int = 0, n_threads: int = 0, proposal: Proposal = None):
     """Alg. 2: returns (grad [L,6] float64, misses); with a proposal holding a
-    histogram, fills proposal.hist."""
+    histogram, fills proposal.hist.  Grey mode only (see adjoint_rgb)."""
+    if ol.colour is not None:
+        raise ValueError("colour mode: use adjoint_rgb")
     prm = np.ascontiguousarray(params, np.float32)
     g = np.ascontiguousarray(dOdE, np.float32).reshape(ol.n_layouts, osc.n_texels)
     out = np.zeros((ol.n_lights, 6), np.float64)
@@ -214,8 +231,26 @@ def adjoint(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_lay
         proposal.hist[:] = 0.0
     m = lib().or_adjoint(C.byref(osc.c), C.byref(ol.c), prm.ctypes.data, int(seed) & 0xFFFFFFFFFFFFFFFF,
                          int(paths_per_layout), int(max_hits), int(limit_per_light), int(n_threads),
-                         _prop(proposal), g.ctypes.data, out.ctypes.data)
+                         _prop(proposal), g.ctypes.data, out.ctypes.data, None)
     return out, int(m)
+
+
+def adjoint_rgb(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,
+                dOdE, limit_per_light: int = 0, n_threads: int = 0, proposal: Proposal = None):
+    """Colour mode, dOdE [n_layouts,3,K]: returns (grad [L,6], grad_colour
+    [L,3] = dO/d(channel weights), misses)."""
+    if ol.colour is None:
+        raise ValueError("grey mode: use adjoint")
+    prm = np.ascontiguousarray(params, np.float32)
+    g = np.ascontiguousarray(dOdE, np.float32).reshape(ol.n_layouts, 3, osc.n_texels)
+    out = np.zeros((ol.n_lights, 6), np.float64)
+    outc = np.zeros((ol.n_lights, 3), np.float64)
+    if proposal is not None and proposal.hist is not None:
+        proposal.hist[:] = 0.0
+    m = lib().or_adjoint(C.byref(osc.c), C.byref(ol.c), prm.ctypes.data, int(seed) & 0xFFFFFFFFFFFFFFFF,
+                         int(paths_per_layout), int(max_hits), int(limit_per_light), int(n_threads),
+                         _prop(proposal), g.ctypes.data, out.ctypes.data, outc.ctypes.data)
+    return out, outc, int(m)
 
 
 def votes(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,
@@ -223,6 +258,8 @@ def votes(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layou
     """Gradient-contribution map (Sec. gradVis) of global light `light` and
     parameter `param`: returns (vote [K] float64 over the texels of the
     light's layout, grad [6] float64 of that light, misses)."""
+    if ol.colour is not None:
+        raise ValueError("the contribution map is grey only")
     prm = np.ascontiguousarray(params, np.float32)
     g = np.ascontiguousarray(dOdE, np.float32).reshape(ol.n_layouts, osc.n_texels)
     vote = np.zeros(osc.n_texels, np.float64)
@@ -238,7 +275,10 @@ def votes(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layou
 def path_trace(osc: OracleScene, ol: OracleLights, params, seed: int, samples_per_texel: int, max_hits: int,
                dOdE=None, n_threads: int = 0):
     """Object-space path tracing with next-event estimation: returns
-    (S [n_layouts,K] int64, grad [L,6] float64 or None when dOdE is None)."""
+    (S [n_layouts,K] int64, grad [L,6] float64 or None when dOdE is None).
+    Grey only."""
+    if ol.colour is not None:
+        raise ValueError("the path tracer is grey only")
     prm = np.ascontiguousarray(params, np.float32)
     S = np.zeros((ol.n_layouts, osc.n_texels), np.int64)
     g = None if dOdE is None else np.ascontiguousarray(dOdE, np.float32).reshape(ol.n_layouts, osc.n_texels)
@@ -252,6 +292,8 @@ def path_trace(osc: OracleScene, ol: OracleLights, params, seed: int, samples_pe
 
 def record(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,
            layout: int, light: int, first: int, count: int, dOdE=None, proposal: Proposal = None):
+    if ol.colour is not None:
+        raise ValueError("path records are grey only")
     prm = np.ascontiguousarray(params, np.float32)
     prim = np.zeros((count, max_hits), np.int32)
     tex = np.zeros((count, max_hits), np.int32)

@@ -31,6 +31,10 @@
  *   - Texel basis: box (one texel per hit) or the piecewise-linear basis of
  *     Eq. pwLin with nodes at the texel centres (bilinear weights, four
  *     splats per hit, the adjoint gathering with the same weights).
+ *   - Colour: per-luminaire channel weights of the flux and per-patch channel
+ *     albedos; three channel-planar texel arrays per layout, one path
+ *     geometry for all channels, and the gradient w.r.t. the channel weights
+ *     (Sec. 4.4.3, intensity and colour).
  *   - Luminaires: point, cos^n spot, cos^n rectangle, and the supplement's
  *     soft-edged spot (quadratic fall-off in cos theta between the inner and
  *     outer cone, directions uniform over the outer cap, weighted).
@@ -231,6 +235,7 @@ typedef struct {
     int64_t n_texels;
     int32_t basis;            /* 0 box (one texel per hit), 1 piecewise-linear nodes at texel centres */
     const void* bvh;          /* or_bvh* or NULL for brute force */
+    const float* albedo_rgb;  /* [P,3] per-channel albedo (colour mode), or NULL: the scalar albedo */
 } or_scene;
 
 typedef struct {
@@ -240,6 +245,7 @@ typedef struct {
     const int32_t* layout_offsets; /* [n_layouts+1] */
     int32_t n_lights;
     int32_t n_layouts;
+    const float* colour;      /* [L,3] channel weights (colour mode: texels [n_layouts,3,K]), or NULL */
 } or_lights;
 
 /* Learned emission proposal (beyond the paper, which leaves importance
@@ -472,6 +478,8 @@ typedef struct {
     float dd_da[3], dd_db[3], dt_db[3], db_da[3], db_db[3];
     float P, phi_r;
     int64_t n_paths;
+    int rgb;               /* colour mode */
+    float col[3];          /* channel weights of the flux */
 } olight;
 
 static void light_setup(const or_lights* Ls, const float* params, int gl, int64_t n_paths, olight* L)
@@ -499,6 +507,8 @@ static void light_setup(const or_lights* Ls, const float* params, int gl, int64_
     L->phi_r = p[5] / (float)n_paths;
     L->ci = 1.0f;
     L->co = 0.0f;
+    L->rgb = Ls->colour != NULL;
+    for (int c = 0; c < 3; ++c) L->col[c] = Ls->colour ? Ls->colour[3 * gl + c] : 1.0f;
     if (L->type == 3) {
         /* soft-edged spot (supplement, spot light): constant intensity inside
          * the inner cone, a = ((cos - cos_out) / (cos_in - cos_out))^2 out to
@@ -525,6 +535,7 @@ typedef struct {
     int64_t* S;            /* forward: texel accumulators of this layout (or NULL) */
     const float* g;        /* adjoint: dO/dE of this layout (or NULL) */
     double* acc;           /* adjoint: per-light gradient accumulator [6] */
+    double* acc_col;       /* adjoint, colour mode: gradient w.r.t. the channel weights [3] */
     float* contrib;        /* record: per-path contribution [6] (or NULL) */
     double* vote;          /* votes: per-texel map of one parameter's contributions (or NULL) */
     int vote_param;        /* votes: which of the six parameters */
@@ -693,6 +704,11 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
     float dphi[6] = {0, 0, 0, 0, 0, 0};
     int hits = 0;
     int64_t k1 = -1;
+    /* colour mode: channel ch carries flux Phi_r col[ch] and throughput Tc[ch];
+     * texel arrays are channel-planar, [3, K] per layout */
+    float Tc[3] = {1.0f, 1.0f, 1.0f};
+    float sc[3] = {0.0f, 0.0f, 0.0f};
+    const int64_t K = S->n_texels;
     for (int h = 1; h <= B; ++h) {
         float t;
         int64_t prim = intersect(S, o, dir, skip, &t);
@@ -744,7 +760,16 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
         float no[3];
         if (nd < 0.0f) { no[0] = nq[0]; no[1] = nq[1]; no[2] = nq[2]; }
         else { no[0] = -nq[0]; no[1] = -nq[1]; no[2] = -nq[2]; }
-        if (io->S) {
+        if (io->S && L->rgb) {
+            for (int ch = 0; ch < 3; ++ch) {
+                float val = ((phi_r * L->col[ch]) * Tc[ch]) * inv_a;
+                long long code = llrintf(val * 4294967296.0f);
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+                io->S[ch * K + k] += code;
+            }
+        } else if (io->S) {
             float val = (phi_r * T) * inv_a;
             if (S->basis == 1) {
                 for (int c = 0; c < 4; ++c) {
@@ -763,10 +788,15 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
             }
         }
         if (io->g) {
-            float gk = io->g[k];
-            if (S->basis == 1)
-                gk = ((wb[0] * io->g[kb[0]] + wb[1] * io->g[kb[1]]) + wb[2] * io->g[kb[2]]) + wb[3] * io->g[kb[3]];
-            s_r = s_r + (gk * inv_a) * T;
+            if (L->rgb) {
+                for (int ch = 0; ch < 3; ++ch) sc[ch] = sc[ch] + (io->g[ch * K + k] * inv_a) * Tc[ch];
+            } else {
+                float gk = io->g[k];
+                if (S->basis == 1)
+                    gk = ((wb[0] * io->g[kb[0]] + wb[1] * io->g[kb[1]]) + wb[2] * io->g[kb[2]]) +
+                         wb[3] * io->g[kb[3]];
+                s_r = s_r + (gk * inv_a) * T;
+            }
             if (h == 1) {
                 k1 = k;
                 float dl[6];
@@ -797,6 +827,15 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
         for (int c = 0; c < 3; ++c) o[c] = x[c];
         skip = q;
         T = T * pf[16];
+        for (int ch = 0; ch < 3; ++ch) Tc[ch] = Tc[ch] * (S->albedo_rgb ? S->albedo_rgb[3 * q + ch] : pf[16]);
+    }
+    if (io->g && hits >= 1 && L->rgb) {
+        /* every channel shares the path's geometry, so dPhi_ch/dp = Phi_ch dlog:
+         * the geometric terms take the colour-weighted adjoint sum, and
+         * dO/dcol_ch = s_ch Phi_r */
+        s_r = (sc[0] * L->col[0] + sc[1] * L->col[1]) + sc[2] * L->col[2];
+        if (io->acc_col)
+            for (int ch = 0; ch < 3; ++ch) io->acc_col[ch] += (double)(sc[ch] * phi_r);
     }
     if (io->g && hits >= 1) {
         float cr[6];
@@ -842,7 +881,9 @@ EXPORT int64_t or_forward(const or_scene* S, const or_lights* Ls, const float* p
                           int64_t paths_per_layout, int max_hits, int64_t limit_per_light, int n_threads,
                           const or_proposal* prop, int64_t* S_out)
 {
-    memset(S_out, 0, (size_t)(S->n_texels * Ls->n_layouts) * sizeof(int64_t));
+    /* colour mode: [n_layouts, 3, K] */
+    const int64_t stride = (Ls->colour ? 3 : 1) * S->n_texels;
+    memset(S_out, 0, (size_t)(stride * Ls->n_layouts) * sizeof(int64_t));
     int64_t misses = 0;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -861,7 +902,7 @@ EXPORT int64_t or_forward(const or_scene* S, const or_lights* Ls, const float* p
             for (int64_t i = 0; i < lim; ++i) {
                 path_io io;
                 memset(&io, 0, sizeof(io));
-                io.S = S_out + (int64_t)j * S->n_texels;
+                io.S = S_out + (int64_t)j * stride;
                 trace_path(S, &L, j, gl - l0, gl, (uint32_t)i, seed, max_hits, prop, &io);
                 m += io.misses;
             }
@@ -871,11 +912,14 @@ EXPORT int64_t or_forward(const or_scene* S, const or_lights* Ls, const float* p
     return misses;
 }
 
-/* Adjoint light tracing (Alg. 2).  dOdE: [n_layouts, K]; grad_out: [L,6] FP64. */
+/* Adjoint light tracing (Alg. 2).  dOdE: [n_layouts, K] ([n_layouts, 3, K]
+ * in colour mode); grad_out: [L,6] FP64; grad_colour: [L,3] FP64 in colour
+ * mode (may be NULL). */
 EXPORT int64_t or_adjoint(const or_scene* S, const or_lights* Ls, const float* params, uint64_t seed,
                           int64_t paths_per_layout, int max_hits, int64_t limit_per_light, int n_threads,
-                          const or_proposal* prop, const float* dOdE, double* grad_out)
+                          const or_proposal* prop, const float* dOdE, double* grad_out, double* grad_colour)
 {
+    const int64_t stride = (Ls->colour ? 3 : 1) * S->n_texels;
     int64_t misses = 0;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -887,23 +931,30 @@ EXPORT int64_t or_adjoint(const or_scene* S, const or_lights* Ls, const float* p
             int64_t nl = paths_of_light(paths_per_layout, l1 - l0, gl - l0);
             light_setup(Ls, params, gl, nl, &L);
             int64_t lim = (limit_per_light > 0 && limit_per_light < nl) ? limit_per_light : nl;
-            double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+            double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, c0 = 0, c1 = 0, c2 = 0;
             int64_t m = 0;
 #ifdef _OPENMP
-#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : a0, a1, a2, a3, a4, a5, m)
+#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : a0, a1, a2, a3, a4, a5, c0, c1, c2, m)
 #endif
             for (int64_t i = 0; i < lim; ++i) {
                 double acc[6] = {0, 0, 0, 0, 0, 0};
+                double accc[3] = {0, 0, 0};
                 path_io io;
                 memset(&io, 0, sizeof(io));
-                io.g = dOdE + (int64_t)j * S->n_texels;
+                io.g = dOdE + (int64_t)j * stride;
                 io.acc = acc;
+                io.acc_col = accc;
                 trace_path(S, &L, j, gl - l0, gl, (uint32_t)i, seed, max_hits, prop, &io);
                 a0 += acc[0]; a1 += acc[1]; a2 += acc[2]; a3 += acc[3]; a4 += acc[4]; a5 += acc[5];
+                c0 += accc[0]; c1 += accc[1]; c2 += accc[2];
                 m += io.misses;
             }
             double* g = grad_out + 6 * (int64_t)gl;
             g[0] = a0; g[1] = a1; g[2] = a2; g[3] = a3; g[4] = a4; g[5] = a5;
+            if (grad_colour) {
+                double* gc = grad_colour + 3 * (int64_t)gl;
+                gc[0] = c0; gc[1] = c1; gc[2] = c2;
+            }
             misses += m;
         }
     }
@@ -921,6 +972,7 @@ EXPORT int64_t or_votes(const or_scene* S, const or_lights* Ls, const float* par
                         const or_proposal* prop, const float* dOdE, int gl, int param, double* vote_out,
                         double* grad_out)
 {
+    if (Ls->colour) return -1;   /* grey only */
     int j = 0;
     while (Ls->layout_offsets[j + 1] <= gl) ++j;
     int l0 = Ls->layout_offsets[j], l1 = Ls->layout_offsets[j + 1];
@@ -1142,6 +1194,7 @@ static void pt_layout(const or_scene* S, const or_lights* Ls, const float* param
 EXPORT void or_pt(const or_scene* S, const or_lights* Ls, const float* params, uint64_t seed, int M, int max_hits,
                   int n_threads, const float* dOdE, int64_t* S_out, double* grad_out)
 {
+    if (Ls->colour) return;   /* grey only */
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
 #endif
@@ -1166,6 +1219,7 @@ EXPORT void or_record(const or_scene* S, const or_lights* Ls, const float* param
                       int64_t count, const or_proposal* prop, int32_t* prim_out, int32_t* texel_out,
                       const float* dOdE, float* contrib)
 {
+    if (Ls->colour) return;   /* grey only */
     int l0 = Ls->layout_offsets[layout], l1 = Ls->layout_offsets[layout + 1];
     int gl = l0 + l_local;
     olight L;

@@ -404,6 +404,94 @@ def test_path_trace_gradient_is_the_estimators_derivative(oracle_lib):
             assert abs(fd - grad[l, c]) <= 2e-3 * abs(grad[l, c]) + 1e-4 * np.abs(grad).max(), (l, c, fd, grad[l, c])
 
 
+# --------------------------------------------------------------------------
+# colour (per-channel flux weights and albedos)
+# --------------------------------------------------------------------------
+
+def test_rgb_closed_box_energy(oracle_lib):
+    """Per channel, a closed box with albedo rho_ch absorbs exactly the flux
+    sum_l P_l c_l,ch (1 - rho_ch^B) / (1 - rho_ch)."""
+    rho = np.array([0.5, 0.6, 0.72])
+    B, N = 5, 1 << 17
+    sc = li.closed_box(albedo=0.6)
+    alb = np.broadcast_to(rho.astype(np.float32), (sc.n_patches, 3)).copy()
+    P = np.array([30.0, 55.0])
+    col = np.array([[0.2, 0.3, 0.5], [0.6, 0.25, 0.15]], np.float32)
+    lights = make_lights([POINT, SPOT], [0.0, 2.0], [(0, 0)] * 2, [0, 0],
+                         [[0.7, 0.6, 0.5, 0, 0, P[0]], [1.3, 0.9, 0.8, 0.3, -0.2, P[1]]])
+    S, misses = oracle_lib.forward(oracle_lib.OracleScene(sc, albedo_rgb=alb), oracle_lib.OracleLights(lights, col),
+                                   lights.params, 0x3B, N, B)
+    assert misses == 0 and S.shape == (1, 3, sc.n_texels)
+    A = sc.texel_area().astype(np.float64)
+    for ch in range(3):
+        total = float(np.sum(A * S[0, ch].astype(np.float64) * 2.0 ** -32))
+        expect = float(np.dot(P, col[:, ch])) * (1 - rho[ch] ** B) / (1 - rho[ch])
+        assert abs(total / expect - 1) < 1e-6, (ch, total, expect)
+
+
+def _rgb_case(oracle_lib):
+    c1 = li.box_room()
+    sc, lights = c1["scene"], c1["lights"]
+    rng = np.random.default_rng(12)
+    alb = rng.uniform(0.3, 0.8, (sc.n_patches, 3)).astype(np.float32)
+    col = np.array([[0.5, 0.3, 0.2]], np.float32)
+    return sc, lights, alb, col
+
+
+def test_rgb_channels_are_grey_runs(oracle_lib):
+    """One path geometry for all channels: channel ch equals c_ch times the
+    grey tracer run with albedo rho_ch, and the geometric gradient is
+    sum_ch c_ch times the grey gradients with dO/dE_ch."""
+    sc, lights, alb, col = _rgb_case(oracle_lib)
+    N, B, seed = 1 << 15, 3, 0x77
+    ol_rgb = oracle_lib.OracleLights(lights, col)
+    S, _ = oracle_lib.forward(oracle_lib.OracleScene(sc, albedo_rgb=alb), ol_rgb, lights.params, seed, N, B)
+    g = np.random.default_rng(2).normal(size=(1, 3, sc.n_texels)).astype(np.float32)
+    grad, grad_c, _ = oracle_lib.adjoint_rgb(oracle_lib.OracleScene(sc, albedo_rgb=alb), ol_rgb, lights.params,
+                                             seed, N, B, g)
+    ol = oracle_lib.OracleLights(lights)
+    ref_grad = np.zeros(6)
+    for ch in range(3):
+        sc_ch = li.scenes.Scene(**{**sc.__dict__})
+        sc_ch.patches = sc.patches.copy()
+        sc_ch.patches["albedo"] = alb[:, ch]
+        osc_ch = oracle_lib.OracleScene(sc_ch)
+        S_g, _ = oracle_lib.forward(osc_ch, ol, lights.params, seed, N, B)
+        E_rgb = S[0, ch].astype(np.float64)
+        E_g = S_g[0].astype(np.float64) * float(col[0, ch])
+        assert np.linalg.norm(E_rgb - E_g) <= 1e-6 * np.linalg.norm(E_g)
+        gr, _ = oracle_lib.adjoint(osc_ch, ol, lights.params, seed, N, B, g[:, ch])
+        ref_grad += float(col[0, ch]) * gr[0]
+    assert np.allclose(grad[0], ref_grad, rtol=1e-5, atol=1e-6 * np.abs(ref_grad).max())
+
+
+def test_rgb_colour_gradient(oracle_lib):
+    """E is linear in the channel weights, so dO/dc of O = sum g E matches
+    central differences exactly (up to rounding); and sum_ch c_ch dO/dc_ch =
+    P dO/dP, both being sum over paths of the colour-weighted adjoint times
+    Phi_r."""
+    sc, lights, alb, col = _rgb_case(oracle_lib)
+    N, B, seed = 1 << 14, 3, 0x5D
+    osc = oracle_lib.OracleScene(sc, albedo_rgb=alb)
+    g = np.random.default_rng(3).normal(size=(1, 3, sc.n_texels)).astype(np.float32)
+    grad, grad_c, _ = oracle_lib.adjoint_rgb(osc, oracle_lib.OracleLights(lights, col), lights.params, seed, N, B, g)
+
+    def lin(cc):
+        S, _ = oracle_lib.forward(osc, oracle_lib.OracleLights(lights, cc), lights.params, seed, N, B)
+        return float(np.sum(g.astype(np.float64) * S.astype(np.float64) * 2.0 ** -32))
+
+    for ch in range(3):
+        h = 0.05
+        cp, cm = col.copy(), col.copy()
+        cp[0, ch] += h
+        cm[0, ch] -= h
+        fd = (lin(cp) - lin(cm)) / (float(cp[0, ch]) - float(cm[0, ch]))
+        assert abs(fd - grad_c[0, ch]) <= 1e-5 * np.abs(grad_c).max(), (ch, fd, grad_c[0, ch])
+    lhs = float(np.dot(col[0].astype(np.float64), grad_c[0]))
+    rhs = float(lights.params[0, 5]) * grad[0, 5]
+    assert abs(lhs / rhs - 1) < 1e-5
+
+
 def test_cosine_bounce_floor_to_ceiling(oracle_lib):
     """Second hits on a parallel ceiling: floor first-hit density times the
     differential form factor to each ceiling texel (cosine-weighted bounce, rho)."""
