@@ -187,6 +187,24 @@ int lt_trace_adjoint(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params
 int lt_gradient_votes(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, const float* d_dOdE,
                       int32_t light, int32_t param, double* d_vote, float* d_grad);
 
+/* Colour (Sec. 4.4.3, intensity and colour).  A luminaire's flux is split
+ * over three channels by weights d_colour [L,3] f32 (channel ch carries
+ * P c_ch; the optimiser may keep r + g + b = 1, the chromaticity
+ * projection); every patch reflects channel ch with its own albedo
+ * (lt_set_albedo_rgb, h_albedo [n_patches,3] in [0,1], host pointer; after
+ * lt_scene_upload each channel takes the patch's scalar albedo).  All
+ * channels share one path geometry.  Texel arrays are channel-planar:
+ * d_S, d_E, d_dOdE [n_layouts,3,K] (lt_objective takes n = n_layouts*3*K).
+ * The adjoint returns d_grad [L,6] for the geometry and power, taking the
+ * colour-weighted adjoint sum, and d_grad_colour [L,3] = dO/dc.  Box basis
+ * only (LT_FLAG_LINEAR is refused); the contribution map, path records and
+ * the path tracer are grey only. */
+int lt_set_albedo_rgb(lt_ctx* ctx, const float* h_albedo);
+int lt_trace_forward_rgb(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, const float* d_colour,
+                         int64_t* d_S, float* d_E);
+int lt_trace_adjoint_rgb(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, const float* d_colour,
+                         const float* d_dOdE, float* d_grad, float* d_grad_colour, float* d_bin_hist);
+
 /* Object-space path tracing with next-event estimation: the comparison
  * estimator of Sec. 6 (after Stam 2020) on the same texels.  Each texel gets
  * samples_per_texel points drawn uniformly in it; every path vertex (the

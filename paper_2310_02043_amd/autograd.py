@@ -3,7 +3,8 @@
 ``LightTraceFn.apply(params, tracer)`` runs the primal light-tracing kernel
 (Alg. 1) and returns texel irradiance E [n_layouts, K]; its backward runs the
 adjoint light-tracing kernel (Alg. 2) with the incoming dL/dE as the adjoint
-source and returns dL/dparams [L, 6].  Whether the adjoint replays the
+source and returns dL/dparams [L, 6].  ``LightTraceRGBFn`` is the colour form
+(channel weights [L, 3] as a second input, E [n_layouts, 3, K]).  Whether the adjoint replays the
 forward's paths (correlated evaluation, as the paper uses for validation) or
 a fresh set (decorrelated, as it uses for optimisation) is the tracer's
 ``correlated`` flag (Sec. 4.3).  Both passes run on the current torch stream.
@@ -71,6 +72,11 @@ class LightTracer:
     def __call__(self, params, seed=None):
         return LightTraceFn.apply(params, self, seed)
 
+    def rgb(self, params, colour, seed=None):
+        """Colour mode: E [n_layouts, 3, K] from luminaire parameters [L,6]
+        and channel weights [L,3], differentiable in both."""
+        return LightTraceRGBFn.apply(params, colour, self, seed)
+
 
 class LightTraceFn(torch.autograd.Function):
     @staticmethod
@@ -92,6 +98,36 @@ class LightTraceFn(torch.autograd.Function):
         grad = tracer.ctx.trace_adjoint(p, g, tracer.cfg(tracer.adjoint_seed(fctx.seed), adjoint=True),
                                          bin_hist=hist)
         return grad, None, None
+
+
+class LightTraceRGBFn(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, params, colour, tracer: LightTracer, seed=None):
+        p = params.detach().contiguous().float()
+        c = colour.detach().contiguous().float()
+        E, _ = tracer.ctx.trace_forward_rgb(p, c, tracer.cfg(seed))
+        fctx.save_for_backward(p, c)
+        fctx.tracer = tracer
+        fctx.seed = seed
+        return E
+
+    @staticmethod
+    def backward(fctx, grad_E):
+        p, c = fctx.saved_tensors
+        tracer = fctx.tracer
+        g = grad_E.contiguous().float()
+        prop = tracer.proposal
+        hist = prop.hist if prop is not None and prop.collect else None
+        grad, grad_c = tracer.ctx.trace_adjoint_rgb(p, c, g, tracer.cfg(tracer.adjoint_seed(fctx.seed), adjoint=True),
+                                                    bin_hist=hist)
+        return grad, grad_c, None, None
+
+
+def chromaticity(colour):
+    """Channel weights projected to r + g + b = 1 (Sec. 4.4.3: optimising
+    chromaticity at constant intensity); differentiating through it applies
+    the projection's Jacobian to the gradient."""
+    return colour / colour.sum(-1, keepdim=True)
 
 
 def objective(E, E_target, texel_area, alpha=None):

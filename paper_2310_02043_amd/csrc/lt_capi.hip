@@ -45,6 +45,7 @@ struct lt_ctx {
     long long* pbase = nullptr;
     float* parea = nullptr;
     float* texel_area = nullptr;
+    float4* rho_rgb = nullptr;       // per-patch channel albedo (colour mode)
     int n_nodes = 0, depth = 0, n_patches = 0;
     long long n_tris = 0, K = 0;
     uint64_t generation = 1;
@@ -77,6 +78,8 @@ struct lt_ctx {
     size_t gstack_cap = 0;
     double* d_ptgrad = nullptr;      // path tracer: FP64 gradient accumulator [L,6]
     size_t ptgrad_cap = 0;
+    double* d_partials_col = nullptr; // colour adjoint: [n_tiles,3] partial sums of dO/dc
+    size_t partials_col_cap = 0;
 
     lt_tuning tune;
     std::vector<GraphEntry> graphs;
@@ -120,9 +123,9 @@ void free_graphs(lt_ctx* c)
 void free_scene(lt_ctx* c)
 {
     hipFree(c->nodes); hipFree(c->tris); hipFree(c->patches); hipFree(c->pbase); hipFree(c->parea);
-    hipFree(c->texel_area);
+    hipFree(c->texel_area); hipFree(c->rho_rgb);
     c->nodes = nullptr; c->tris = nullptr; c->patches = nullptr; c->pbase = nullptr; c->parea = nullptr;
-    c->texel_area = nullptr;
+    c->texel_area = nullptr; c->rho_rgb = nullptr;
     c->has_scene = false;
 }
 
@@ -416,6 +419,7 @@ void lt_destroy(lt_ctx* c)
     hipFree(c->prop_pdf); hipFree(c->prop_cdf); hipFree(c->prop_guide); hipFree(c->inv_sigma); hipFree(c->mlp_scratch);
     hipFree(c->d_misses); hipFree(c->d_flags); hipFree(c->d_stats);
     hipFree(c->d_objpart); hipFree(c->d_partials); hipFree(c->d_gstack); hipFree(c->d_ptgrad);
+    hipFree(c->d_partials_col);
     if (c->ev_in) hipEventDestroy(c->ev_in);
     if (c->ev_out) hipEventDestroy(c->ev_out);
     if (c->gstream) hipStreamDestroy(c->gstream);
@@ -528,6 +532,13 @@ int lt_scene_upload(lt_ctx* c, const float* h_verts, int64_t n_verts, const int3
     HIPCHK(c, hipMemcpy(c->patches, dp.data(), sizeof(DevPatch) * n_patches, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->pbase, base.data(), sizeof(long long) * n_patches, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->parea, area.data(), sizeof(float) * n_patches, hipMemcpyHostToDevice));
+    {
+        // colour mode: every channel takes the patch's albedo until set otherwise
+        std::vector<float4> rr(n_patches);
+        for (int q = 0; q < n_patches; ++q) rr[q] = make_float4(h_patches[q].albedo, h_patches[q].albedo, h_patches[q].albedo, 0.f);
+        HIPCHK(c, hipMalloc(&c->rho_rgb, sizeof(float4) * n_patches));
+        HIPCHK(c, hipMemcpy(c->rho_rgb, rr.data(), sizeof(float4) * n_patches, hipMemcpyHostToDevice));
+    }
     HIPCHK(c, launch_texel_area(c->parea, c->pbase, n_patches, K, c->texel_area, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->n_nodes = n_nodes;
@@ -692,6 +703,99 @@ int lt_gradient_votes(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params,
     };
     return run_seq(c, graph,
                    make_key(c, 4, cfg, {d_params, d_dOdE, d_grad, d_vote, (const void*)(uintptr_t)(light * 8 + param)}),
+                   body);
+}
+
+int lt_set_albedo_rgb(lt_ctx* c, const float* h_albedo)
+{
+    if (!c) return LT_EINVAL;
+    if (!c->has_scene) return fail(c, LT_ESTATE, "no scene uploaded");
+    if (!h_albedo) return fail(c, LT_EINVAL, "NULL albedo table");
+    std::vector<float4> rr(c->n_patches);
+    for (int q = 0; q < c->n_patches; ++q) {
+        const float* a = h_albedo + 3 * (size_t)q;
+        for (int ch = 0; ch < 3; ++ch)
+            if (!(a[ch] >= 0.0f && a[ch] <= 1.0f)) return fail(c, LT_EINVAL, "albedo outside [0, 1]");
+        rr[q] = make_float4(a[0], a[1], a[2], 0.f);
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->rho_rgb, rr.data(), sizeof(float4) * c->n_patches, hipMemcpyHostToDevice));
+    free_graphs(c);
+    return LT_OK;
+}
+
+int lt_trace_forward_rgb(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, const float* d_colour,
+                         int64_t* d_S, float* d_E)
+{
+    int rc = check_cfg(c, cfg);
+    if (rc) return rc;
+    if (!d_params || !d_colour || !d_S || !d_E) return fail(c, LT_EINVAL, "NULL device buffer");
+    if (cfg->flags & LT_FLAG_LINEAR) return fail(c, LT_EINVAL, "colour mode takes the box basis only");
+    if (((uintptr_t)d_S & 15) || ((uintptr_t)d_E & 7) || ((uintptr_t)d_params & 3) || ((uintptr_t)d_colour & 3))
+        return fail(c, LT_EINVAL, "d_S must be 16-byte and d_E 8-byte aligned");
+    HIPCHK(c, hipSetDevice(c->device));
+    const long long blocks = trace_blocks(c);
+    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    if (rc) return rc;
+    TraceArgs a = trace_args(c, cfg);
+    a.S = (long long*)d_S;
+    a.rgb = 1;
+    a.colour = d_colour;
+    a.rho_rgb = c->rho_rgb;
+    const long long n = 3 * c->K * c->n_layouts;
+    const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
+    auto body = [&](hipStream_t st) -> hipError_t {
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        if (e == hipSuccess) e = launch_clear(a.S, n, st);
+        if (e == hipSuccess) e = timed_trace(c, false, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = launch_finalize(a.S, d_E, n, c->d_flags, st);
+        return e;
+    };
+    return run_seq(c, graph, make_key(c, 5, cfg, {d_params, d_colour, d_S, d_E}), body);
+}
+
+int lt_trace_adjoint_rgb(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, const float* d_colour,
+                         const float* d_dOdE, float* d_grad, float* d_grad_colour, float* d_bin_hist)
+{
+    int rc = check_cfg(c, cfg);
+    if (rc) return rc;
+    if (!d_params || !d_colour || !d_dOdE || !d_grad || !d_grad_colour)
+        return fail(c, LT_EINVAL, "NULL device buffer");
+    if (cfg->flags & LT_FLAG_LINEAR) return fail(c, LT_EINVAL, "colour mode takes the box basis only");
+    if (d_bin_hist && ((uintptr_t)d_bin_hist & 15)) return fail(c, LT_EINVAL, "d_bin_hist must be 16-byte aligned");
+    HIPCHK(c, hipSetDevice(c->device));
+    const long long blocks = trace_blocks(c);
+    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    if (rc) return rc;
+    const size_t need = (size_t)std::max(c->n_tiles, 1) * 3;
+    if (c->partials_col_cap < need) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        free_graphs(c);
+        hipFree(c->d_partials_col);
+        c->d_partials_col = nullptr;
+        c->partials_col_cap = 0;
+        HIPCHK(c, hipMalloc(&c->d_partials_col, sizeof(double) * need));
+        c->partials_col_cap = need;
+    }
+    TraceArgs a = trace_args(c, cfg);
+    a.g = d_dOdE;
+    a.partials = c->d_partials;
+    a.bin_hist = d_bin_hist;
+    a.rgb = 1;
+    a.colour = d_colour;
+    a.rho_rgb = c->rho_rgb;
+    a.partials_col = c->d_partials_col;
+    const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
+    auto body = [&](hipStream_t st) -> hipError_t {
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        if (e == hipSuccess && d_bin_hist) e = launch_fill_f32(d_bin_hist, (long long)c->L * 1024, 0.0f, st);
+        if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = launch_grad_reduce(c->d_partials, c->d_range, c->L, d_grad, st);
+        if (e == hipSuccess) e = launch_grad_reduce_col(c->d_partials_col, c->d_range, c->L, d_grad_colour, st);
+        return e;
+    };
+    return run_seq(c, graph, make_key(c, 6, cfg, {d_params, d_colour, d_dOdE, d_grad, d_grad_colour, d_bin_hist}),
                    body);
 }
 

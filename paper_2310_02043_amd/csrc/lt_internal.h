@@ -55,6 +55,12 @@ struct TraceArgs {
     float alpha_plain;
     float* bin_hist;            // adjoint: [L,1024] histogram of |c_r / sigma| (may be null)
     const float* inv_sigma;     // [L,6]
+    // colour mode: [L,3] channel weights, [P] per-patch channel albedo,
+    // adjoint [n_tiles,3] partial sums of dO/dc
+    int rgb;
+    const float* colour;
+    const float4* rho_rgb;
+    double* partials_col;
     // adjoint: gradient-contribution map of one light and parameter (may be null)
     double* vote;               // [K] texels of the light's layout
     int vote_light;             // global light index
@@ -120,6 +126,8 @@ hipError_t launch_light_setup(const float* params, const int4* lstat_i, const fl
 hipError_t launch_clear(long long* S, long long n_texels_total, hipStream_t st);
 hipError_t launch_fill_f32(float* p, long long n, float v, hipStream_t st);
 hipError_t launch_pt(bool adjoint, const PtArgs& a, int lds_depth, hipStream_t st);
+hipError_t launch_grad_reduce_col(const double* partials, const int2* range, int n_lights, float* grad,
+                                  hipStream_t st);
 hipError_t launch_f64_to_f32(const double* in, float* out, long long n, hipStream_t st);
 hipError_t launch_finalize(const long long* S, float* E, long long n, unsigned* flags, hipStream_t st);
 hipError_t launch_objective(const float* E, const float* Et, const float* alpha, const float* A, long long K,

@@ -482,10 +482,13 @@ __device__ __forceinline__ long long xcd_block(long long b, long long nb, int re
 }
 
 // Both variants fit 96 VGPRs (five waves per SIMD); the adjoint keeps its
-// per-path first-hit derivative factors and running sums in LDS.  LIN selects
-// the piecewise-linear texel basis (four splats / a four-node gather per
-// hit) at compile time, which leaves the box-basis instances as they were.
-template <bool ADJ, bool STATS, int WPB, int LDS_D, bool LIN>
+// per-path first-hit derivative factors and running sums in LDS.  MODE
+// selects at compile time, leaving the other instances as they were: 0 the
+// box texel basis, 1 the piecewise-linear basis (four splats / a four-node
+// gather per hit), 2 colour (three channel-planar texel arrays; the green
+// and blue throughputs and adjoint sums live in LDS beside the red ones in
+// registers).
+template <bool ADJ, bool STATS, int WPB, int LDS_D, int MODE>
 __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5))) k_trace(TraceArgs a)
 {
     __shared__ int s_stack[WPB * LDS_D * 64];
@@ -494,10 +497,13 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
     __shared__ float s_adj[ADJ ? WPB * 12 * 64 : 1];
     // adjoint with a gradient-contribution map: texel of the first hit
     __shared__ int s_k1[ADJ ? WPB * 64 : 1];
+    // colour: per lane T_g, T_b, s_g, s_b and the three channel-weight sums
+    __shared__ float s_rgb[MODE == 2 ? WPB * 8 * 64 : 1];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     float* adj = s_adj + (ADJ ? wib * 12 * 64 + lane : 0);
     int* k1 = s_k1 + (ADJ ? wib * 64 + lane : 0);
+    float* rgbs = s_rgb + (MODE == 2 ? wib * 8 * 64 + lane : 0);
     const long long blk = xcd_block(blockIdx.x, gridDim.x, a.xcd_remap);
     const long long gw = blk * WPB + wib;
     if (gw >= a.n_tiles) return;
@@ -512,8 +518,17 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
         const uint32_t first = (uint32_t)ti.y;
         const int count = ti.z;
         const uint32_t stream_id = ((uint32_t)ti.w << 16) | (uint32_t)L.l_local;
-        long long* S = ADJ ? nullptr : a.S + (long long)ti.w * a.K;
-        const float* g = ADJ ? a.g + (long long)ti.w * a.K : nullptr;
+        const long long rowK = (MODE == 2 ? 3 : 1) * a.K;
+        long long* S = ADJ ? nullptr : a.S + (long long)ti.w * rowK;
+        const float* g = ADJ ? a.g + (long long)ti.w * rowK : nullptr;
+        float c0 = 1.0f, c1 = 1.0f, c2 = 1.0f;   // channel weights of the flux
+        if (MODE == 2) {
+            c0 = a.colour[3 * ti.x];
+            c1 = a.colour[3 * ti.x + 1];
+            c2 = a.colour[3 * ti.x + 2];
+#pragma unroll
+            for (int c = 4; c < 7; ++c) rgbs[c * 64] = 0.0f;
+        }
         const bool prop_on = a.prop_pdf != nullptr && (L.type == 1 || L.type == 2);
         const float* pdf = prop_on ? a.prop_pdf + 1024 * (long long)ti.x : nullptr;
         const float* cdf = prop_on ? a.prop_cdf + 1024 * (long long)ti.x : nullptr;
@@ -558,6 +573,12 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                     skip = -1;
                     T = 1.0f;
                     s_r = 0.0f;
+                    if (MODE == 2) {
+                        rgbs[0] = 1.0f;
+                        rgbs[64] = 1.0f;
+                        rgbs[128] = 0.0f;
+                        rgbs[192] = 0.0f;
+                    }
                     if (STATS) ++n_seg;
                 }
                 next += __popcll(m);
@@ -600,9 +621,22 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                     ++h;
                     if (STATS) ++n_hits;
                     const HitInfo hi = hit_info(r, s.tb, s.qb, a.patches);
-                    if (!ADJ) {
+                    if (!ADJ && MODE == 2) {
+                        const float v0 = ((phi_r * c0) * T) * hi.inva;
+                        const float v1 = ((phi_r * c1) * rgbs[0]) * hi.inva;
+                        const float v2 = ((phi_r * c2) * rgbs[64]) * hi.inva;
+                        const long long q0 = (long long)__builtin_rintf(v0 * 4294967296.0f);
+                        const long long q1 = (long long)__builtin_rintf(v1 * 4294967296.0f);
+                        const long long q2 = (long long)__builtin_rintf(v2 * 4294967296.0f);
+                        __hip_atomic_fetch_add((unsigned long long*)(S + hi.k), (unsigned long long)q0,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_fetch_add((unsigned long long*)(S + a.K + hi.k), (unsigned long long)q1,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_fetch_add((unsigned long long*)(S + 2 * a.K + hi.k), (unsigned long long)q2,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    } else if (!ADJ) {
                         const float val = (phi_r * T) * hi.inva;
-                        if (LIN) {
+                        if (MODE == 1) {
                             long long kb[4];
                             float wb[4];
                             linear_nodes(hi.x, s.qb, a.patches, kb, wb);
@@ -619,7 +653,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                         }
                     } else {
                         float gk;
-                        if (LIN) {
+                        if (MODE == 1) {
                             long long kb[4];
                             float wb[4];
                             linear_nodes(hi.x, s.qb, a.patches, kb, wb);
@@ -628,6 +662,10 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                             gk = g[hi.k];
                         }
                         s_r = s_r + (gk * hi.inva) * T;
+                        if (MODE == 2) {
+                            rgbs[128] = rgbs[128] + (g[a.K + hi.k] * hi.inva) * rgbs[0];
+                            rgbs[192] = rgbs[192] + (g[2 * a.K + hi.k] * hi.inva) * rgbs[64];
+                        }
                         if (h == 1) {
                             float dl[6];
                             first_hit_dlog(L, hi.x, v3(r.ox, r.oy, r.oz), hi.no, au, av, dl);
@@ -644,16 +682,33 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                         skip = s.qb;
                         start_segment(s);
                         trav = true;
-                        T = T * hi.rho;
+                        if (MODE == 2) {
+                            const float4 rho = a.rho_rgb[skip];
+                            T = T * rho.x;
+                            rgbs[0] = rgbs[0] * rho.y;
+                            rgbs[64] = rgbs[64] * rho.z;
+                        } else {
+                            T = T * hi.rho;
+                        }
                         if (STATS) ++n_seg;
                     }
                 }
                 if (end_path) {
                     if (ADJ && h >= 1) {
+                        // colour: every channel shares the path, so the
+                        // geometric terms take the colour-weighted adjoint
+                        // sum, and dO/dc_ch gathers s_ch Phi_r
+                        float se = s_r;
+                        if (MODE == 2) {
+                            se = (s_r * c0 + rgbs[128] * c1) + rgbs[192] * c2;
+                            rgbs[256] += s_r * phi_r;
+                            rgbs[320] += rgbs[128] * phi_r;
+                            rgbs[384] += rgbs[192] * phi_r;
+                        }
                         float m2 = 0.0f;
 #pragma unroll
                         for (int c = 0; c < 6; ++c) {
-                            const float cr = s_r * adj[c * 64];
+                            const float cr = se * adj[c * 64];
                             adj[(6 + c) * 64] += cr;
                             if (hist) {
                                 const float z = cr * a.inv_sigma[6 * ti.x + c];
@@ -662,7 +717,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                         }
                         if (hist && ebin >= 0) atomicAdd(hist + ebin, m2 * wq);
                         // the path's share of dO/dp_j, placed at its first hit
-                        if (vote) unsafeAtomicAdd(vote + *k1, (double)(s_r * adj[a.vote_param * 64]));
+                        if (vote) unsafeAtomicAdd(vote + *k1, (double)(se * adj[a.vote_param * 64]));
                     }
                     alive = false;
                 }
@@ -675,6 +730,15 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
             if (lane == 0) {
 #pragma unroll
                 for (int c = 0; c < 6; ++c) a.partials[(long long)tile * 6 + c] = acc[c];
+            }
+            if (MODE == 2) {
+                double accc[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) accc[c] = wave_sum((double)rgbs[(4 + c) * 64]);
+                if (lane == 0) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) a.partials_col[(long long)tile * 3 + c] = accc[c];
+                }
             }
         }
         const unsigned wm = wave_sum(miss);
@@ -1086,6 +1150,7 @@ __global__ void __launch_bounds__(256) k_objective_final(const double* __restric
 }
 
 // Per-light gradient: ordered sum of the light's tile partials (one wave per light).
+template <int NC>
 __global__ void __launch_bounds__(64) k_grad_reduce(const double* __restrict__ partials,
                                                    const int2* __restrict__ range, int n_lights,
                                                    float* __restrict__ grad)
@@ -1093,12 +1158,13 @@ __global__ void __launch_bounds__(64) k_grad_reduce(const double* __restrict__ p
     const int l = blockIdx.x;
     if (l >= n_lights) return;
     const int2 rg = range[l];
-    double acc[6] = {0, 0, 0, 0, 0, 0};
+    double acc[NC];
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
     for (int t = rg.x + (int)threadIdx.x; t < rg.y; t += 64)
-        for (int c = 0; c < 6; ++c) acc[c] += partials[(long long)t * 6 + c];
-    for (int c = 0; c < 6; ++c) acc[c] = wave_sum(acc[c]);
+        for (int c = 0; c < NC; ++c) acc[c] += partials[(long long)t * NC + c];
+    for (int c = 0; c < NC; ++c) acc[c] = wave_sum(acc[c]);
     if (threadIdx.x == 0)
-        for (int c = 0; c < 6; ++c) grad[6 * l + c] = (float)acc[c];
+        for (int c = 0; c < NC; ++c) grad[NC * l + c] = (float)acc[c];
 }
 
 // Per-texel area A_k from the patch table (binary search of texel_base).
@@ -1128,16 +1194,21 @@ inline int nblocks(long long n, int b, int cap)
 template <bool ADJ, bool STATS, int WPB>
 hipError_t launch_wpb(const TraceArgs& a, int lds_depth, int blocks, hipStream_t st)
 {
-    if (a.linear && !STATS) {
+    if (a.rgb && !STATS) {
         if (lds_depth == 16)
-            k_trace<ADJ, STATS, WPB, 16, true><<<blocks, WPB * 64, 0, st>>>(a);
+            k_trace<ADJ, STATS, WPB, 16, 2><<<blocks, WPB * 64, 0, st>>>(a);
         else
-            k_trace<ADJ, STATS, WPB, 32, true><<<blocks, WPB * 64, 0, st>>>(a);
+            k_trace<ADJ, STATS, WPB, 32, 2><<<blocks, WPB * 64, 0, st>>>(a);
+    } else if (a.linear && !STATS) {
+        if (lds_depth == 16)
+            k_trace<ADJ, STATS, WPB, 16, 1><<<blocks, WPB * 64, 0, st>>>(a);
+        else
+            k_trace<ADJ, STATS, WPB, 32, 1><<<blocks, WPB * 64, 0, st>>>(a);
     } else {
         if (lds_depth == 16)
-            k_trace<ADJ, STATS, WPB, 16, false><<<blocks, WPB * 64, 0, st>>>(a);
+            k_trace<ADJ, STATS, WPB, 16, 0><<<blocks, WPB * 64, 0, st>>>(a);
         else
-            k_trace<ADJ, STATS, WPB, 32, false><<<blocks, WPB * 64, 0, st>>>(a);
+            k_trace<ADJ, STATS, WPB, 32, 0><<<blocks, WPB * 64, 0, st>>>(a);
     }
     return hipGetLastError();
 }
@@ -1227,7 +1298,14 @@ hipError_t launch_objective(const float* E, const float* Et, const float* alpha,
 hipError_t launch_grad_reduce(const double* partials, const int2* range, int n_lights, float* grad,
                               hipStream_t st)
 {
-    k_grad_reduce<<<n_lights, 64, 0, st>>>(partials, range, n_lights, grad);
+    k_grad_reduce<6><<<n_lights, 64, 0, st>>>(partials, range, n_lights, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce_col(const double* partials, const int2* range, int n_lights, float* grad,
+                                  hipStream_t st)
+{
+    k_grad_reduce<3><<<n_lights, 64, 0, st>>>(partials, range, n_lights, grad);
     return hipGetLastError();
 }
 

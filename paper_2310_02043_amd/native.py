@@ -21,7 +21,8 @@ LT_FLAG_GRAPH, LT_FLAG_PROPOSAL, LT_FLAG_LINEAR = 1, 2, 4
 EXPORTED = [
     "lt_create", "lt_destroy", "lt_last_error", "lt_set_stream", "lt_sync", "lt_scene_upload",
     "lt_set_lights", "lt_trace_forward", "lt_objective", "lt_trace_adjoint", "lt_gradient_votes",
-    "lt_pt_forward", "lt_pt_adjoint", "lt_record_paths",
+    "lt_pt_forward", "lt_pt_adjoint", "lt_set_albedo_rgb", "lt_trace_forward_rgb", "lt_trace_adjoint_rgb",
+    "lt_record_paths",
     "lt_trace_stats", "lt_get_tuning", "lt_set_tuning", "lt_autotune", "lt_info_get", "lt_set_timing",
     "lt_timing_read", "lt_proposal_set_table", "lt_proposal_get_table", "lt_proposal_set_scale",
     "lt_proposal_mlp_infer",
@@ -86,6 +87,9 @@ def load():
     L.lt_trace_adjoint.argtypes = [P, C.POINTER(TraceCfg), P, P, P, P]
     L.lt_gradient_votes.argtypes = [P, C.POINTER(TraceCfg), P, P, I32, I32, P, P]
     L.lt_pt_forward.argtypes = [P, C.POINTER(TraceCfg), P, I32, P, P]
+    L.lt_set_albedo_rgb.argtypes = [P, P]
+    L.lt_trace_forward_rgb.argtypes = [P, C.POINTER(TraceCfg), P, P, P, P]
+    L.lt_trace_adjoint_rgb.argtypes = [P, C.POINTER(TraceCfg), P, P, P, P, P, P]
     L.lt_pt_adjoint.argtypes = [P, C.POINTER(TraceCfg), P, I32, P, P]
     L.lt_record_paths.argtypes = [P, C.POINTER(TraceCfg), P, I32, I32, I64, I64, P, P, P, P]
     L.lt_trace_stats.argtypes = [P, C.POINTER(TraceCfg), P, P, C.POINTER(I64)]
@@ -244,6 +248,45 @@ class Context:
         self._check(self.lib.lt_gradient_votes(self.h, C.byref(cfg), _ptr(params), _ptr(dOdE), int(light),
                                                int(param), _ptr(vote), _ptr(grad)))
         return vote, grad
+
+    def set_albedo_rgb(self, albedo):
+        """Per-patch channel albedos [n_patches,3] for the colour mode (host)."""
+        import numpy as np
+        a = np.ascontiguousarray(albedo, np.float32)
+        self._check(self.lib.lt_set_albedo_rgb(self.h, a.ctypes.data))
+
+    def trace_forward_rgb(self, params, colour, cfg, S=None, E=None):
+        """Colour mode: channel weights colour [L,3]; returns (E, S) with
+        texels [n_layouts,3,K]."""
+        torch = self._torch
+        n = (self.n_layouts, 3, self.n_texels)
+        self._dev(params, torch.float32, (self.n_lights, 6))
+        self._dev(colour, torch.float32, (self.n_lights, 3))
+        if S is None:
+            S = torch.empty(n, dtype=torch.int64, device=params.device)
+        if E is None:
+            E = torch.empty(n, dtype=torch.float32, device=params.device)
+        self._dev(S, torch.int64, n)
+        self._dev(E, torch.float32, n)
+        self._stream()
+        self._check(self.lib.lt_trace_forward_rgb(self.h, C.byref(cfg), _ptr(params), _ptr(colour), _ptr(S),
+                                                  _ptr(E)))
+        return E, S
+
+    def trace_adjoint_rgb(self, params, colour, dOdE, cfg, grad=None, grad_colour=None, bin_hist=None):
+        """Colour mode adjoint: returns (grad [L,6], grad_colour [L,3])."""
+        torch = self._torch
+        self._dev(params, torch.float32, (self.n_lights, 6))
+        self._dev(colour, torch.float32, (self.n_lights, 3))
+        self._dev(dOdE, torch.float32, (self.n_layouts, 3, self.n_texels))
+        if grad is None:
+            grad = torch.empty((self.n_lights, 6), dtype=torch.float32, device=params.device)
+        if grad_colour is None:
+            grad_colour = torch.empty((self.n_lights, 3), dtype=torch.float32, device=params.device)
+        self._stream()
+        self._check(self.lib.lt_trace_adjoint_rgb(self.h, C.byref(cfg), _ptr(params), _ptr(colour), _ptr(dOdE),
+                                                  _ptr(grad), _ptr(grad_colour), _ptr(bin_hist)))
+        return grad, grad_colour
 
     def pt_forward(self, params, cfg, samples_per_texel, S=None, E=None):
         """Object-space path tracing with next-event estimation: (E, S)."""
