@@ -29,6 +29,9 @@ TUNING_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2
 METRIC = "light paths/s (forward+adjoint); gradient-error×time vs plain tracer"
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
+# one non-packed FP32 operation per lane per cycle: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz (the rate the traversal's comparisons and min/max can reach)
+UNPACKED_LANE_OPS_T = 256 * 4 * 16 * 2.4e9 / 1e12
 # Algorithmic work per unit (see the design notes): one node visit = four box
 # tests of 20 ops and a 128 B node (4-wide tree); one triangle test = 40 ops and
 # a 48 B record; one hit = an 80 B patch record plus an 8 B atomic (forward) or
@@ -364,6 +367,10 @@ def main():
     roofline = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
                 "kernel": f"k_trace ({dominant})", "kernel_ms": round(max(fwd_avg, adj_avg), 3),
+                "unpacked_issue": {"peak": round(UNPACKED_LANE_OPS_T, 1), "unit": "Tops/s",
+                                   "frac": round(tflops / UNPACKED_LANE_OPS_T, 4),
+                                   "note": "one non-packed FP32 op per lane per cycle, 256 CU x 4 SIMD x 16 "
+                                           "lanes x 2.4 GHz"},
                 "ops_per_launch": int(ops),
                 "hbm": {"achieved": None if traffic is None else round(traffic / dur_s / 1e9, 1),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
