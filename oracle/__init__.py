@@ -34,7 +34,8 @@ class _Scene(C.Structure):
     _fields_ = [("verts", C.c_void_p), ("tris", C.c_void_p), ("tri_patch", C.c_void_p),
                 ("n_tris", C.c_int64), ("pf", C.c_void_p), ("pres", C.c_void_p), ("pbase", C.c_void_p),
                 ("n_patches", C.c_int32), ("n_texels", C.c_int64), ("basis", C.c_int32), ("bvh", C.c_void_p),
-                ("albedo_rgb", C.c_void_p)]
+                ("albedo_rgb", C.c_void_p), ("glossy", C.c_void_p), ("dir_order", C.c_int32),
+                ("dir_samples", C.c_int32)]
 
 
 class _Proposal(C.Structure):
@@ -96,6 +97,10 @@ def lib():
         L.or_votes.restype = C.c_int64
         L.or_pt.argtypes = [P, P, P, C.c_uint64, C.c_int, C.c_int, C.c_int, P, P, P]
         L.or_pt.restype = None
+        L.or_hsh.argtypes = [C.c_int, C.c_float, C.c_float, C.c_float, P]
+        L.or_hsh.restype = C.c_int
+        L.or_brdf.argtypes = [C.c_float, C.c_float, C.c_float, P, P, P]
+        L.or_brdf.restype = C.c_float
         L.or_record.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int64,
                                 C.c_int64, P, P, P, P, P]
         L.or_fixed_to_float.argtypes = [P, C.c_int64, P]
@@ -117,7 +122,8 @@ class OracleScene:
     "box" (one texel per hit) or "linear" (piecewise-linear nodes at the
     texel centres, Eq. pwLin)."""
 
-    def __init__(self, scene, use_bvh: bool = False, basis: str = "box", albedo_rgb=None):
+    def __init__(self, scene, use_bvh: bool = False, basis: str = "box", albedo_rgb=None, glossy=None,
+                 dir_order: int = -1, dir_samples: int = 4):
         self.scene = scene
         self.verts = np.ascontiguousarray(scene.verts, np.float32)
         self.tris = np.ascontiguousarray(scene.tris, np.int32)
@@ -141,6 +147,16 @@ class OracleScene:
         if self.albedo_rgb is not None:
             assert self.albedo_rgb.shape[0] == self.pf.shape[0]
             self.c.albedo_rgb = self.albedo_rgb.ctypes.data
+        # directional texels (HSH order 0..2, N' local samples) and a glossy BRDF
+        # (per patch: specular albedo, Phong exponent)
+        self.glossy = None if glossy is None else np.ascontiguousarray(glossy, np.float32).reshape(-1, 2)
+        if self.glossy is not None:
+            self.c.glossy = self.glossy.ctypes.data
+        assert -1 <= dir_order <= 2 and dir_samples >= 1
+        self.dir_order = int(dir_order)
+        self.n_coef = (dir_order + 1) ** 2 if dir_order >= 0 else 0
+        self.c.dir_order = int(dir_order)
+        self.c.dir_samples = int(dir_samples)
 
     def __del__(self):
         if self._bvh is not None and _lib is not None:
@@ -211,6 +227,8 @@ def forward(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_lay
     mode), misses)."""
     prm = np.ascontiguousarray(params, np.float32)
     shape = (ol.n_layouts, osc.n_texels) if ol.colour is None else (ol.n_layouts, 3, osc.n_texels)
+    if osc.dir_order >= 0:
+        shape = (ol.n_layouts, osc.n_coef, osc.n_texels)
     S = np.zeros(shape, np.int64)
     m = lib().or_forward(C.byref(osc.c), C.byref(ol.c), prm.ctypes.data, int(seed) & 0xFFFFFFFFFFFFFFFF,
                          int(paths_per_layout), int(max_hits), int(limit_per_light), int(n_threads),
@@ -225,7 +243,8 @@ def adjoint(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_lay
     if ol.colour is not None:
         raise ValueError("colour mode: use adjoint_rgb")
     prm = np.ascontiguousarray(params, np.float32)
-    g = np.ascontiguousarray(dOdE, np.float32).reshape(ol.n_layouts, osc.n_texels)
+    per = osc.n_coef if osc.dir_order >= 0 else 1
+    g = np.ascontiguousarray(dOdE, np.float32).reshape(ol.n_layouts, per * osc.n_texels)
     out = np.zeros((ol.n_lights, 6), np.float64)
     if proposal is not None and proposal.hist is not None:
         proposal.hist[:] = 0.0
@@ -303,6 +322,22 @@ def record(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layo
                     int(paths_per_layout), int(max_hits), int(layout), int(light), int(first), int(count),
                     _prop(proposal), prim.ctypes.data, tex.ctypes.data, _p(g), _p(contrib))
     return prim, tex, contrib
+
+
+def hsh(order: int, ct, cp, sp):
+    """The oracle's hemispherical harmonics at one direction (local frame)."""
+    out = np.zeros(9, np.float32)
+    n = lib().or_hsh(int(order), float(ct), float(cp), float(sp), out.ctypes.data)
+    return out[:n]
+
+
+def brdf(rho_d, rho_s, e, wi, wo):
+    """The oracle's BRDF and its gradient w.r.t. wi (local frame)."""
+    a = np.ascontiguousarray(wi, np.float32)
+    b = np.ascontiguousarray(wo, np.float32)
+    gr = np.zeros(3, np.float32)
+    f = lib().or_brdf(float(rho_d), float(rho_s), float(e), a.ctypes.data, b.ctypes.data, gr.ctypes.data)
+    return float(f), gr
 
 
 def fixed_to_float(S):

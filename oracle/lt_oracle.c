@@ -31,6 +31,13 @@
  *   - Texel basis: box (one texel per hit) or the piecewise-linear basis of
  *     Eq. pwLin with nodes at the texel centres (bilinear weights, four
  *     splats per hit, the adjoint gathering with the same weights).
+ *   - Directional texels (Eq. directionalCoeffs with n = 1, 2): each hit
+ *     projects its reflected radiance, (Phi / A) f(w_in, w), on 2pi-normalised
+ *     hemispherical harmonics with N' uniform local samples; a glossy
+ *     (Lambertian + normalised Phong) BRDF; the bounce stays cosine-sampled
+ *     with weight pi f; the adjoint adds the first hit's BRDF terms (Eq. dLdp:
+ *     its projection and its bounce weight change with the incident
+ *     direction while x_1 stays fixed).
  *   - Colour: per-luminaire channel weights of the flux and per-patch channel
  *     albedos; three channel-planar texel arrays per layout, one path
  *     geometry for all channels, and the gradient w.r.t. the channel weights
@@ -236,6 +243,9 @@ typedef struct {
     int32_t basis;            /* 0 box (one texel per hit), 1 piecewise-linear nodes at texel centres */
     const void* bvh;          /* or_bvh* or NULL for brute force */
     const float* albedo_rgb;  /* [P,3] per-channel albedo (colour mode), or NULL: the scalar albedo */
+    const float* glossy;      /* [P,2] specular albedo, Phong exponent (directional mode), or NULL */
+    int32_t dir_order;        /* directional texels: HSH order 0..2, or -1 (irradiance texels) */
+    int32_t dir_samples;      /* local exitant samples per hit (directional mode) */
 } or_scene;
 
 typedef struct {
@@ -602,6 +612,68 @@ static void first_hit_dlog(const olight* L, const float* x1, const float* y, con
     dl[3] = ra; dl[4] = rb;
 }
 
+/* ---- directional texels and a glossy BRDF -------------------------------- */
+
+/* 2pi-normalised hemispherical harmonics (the integral of H^2 over the
+ * hemisphere is 2 pi, H_0^0 = 1) up to order 2, as associated Legendre
+ * functions of x = 2 cos(theta) - 1 times cos / sin of m phi; index
+ * l^2 + l + m.  Returns the number of functions. */
+EXPORT int or_hsh(int order, float ct, float cp, float sp, float* H)
+{
+    float x = 2.0f * ct - 1.0f;
+    float s1 = sqrtf(fmaxf(0.0f, 1.0f - x * x));
+    H[0] = 1.0f;
+    if (order >= 1) {
+        H[1] = (1.7320508075688772f * s1) * sp;
+        H[2] = 1.7320508075688772f * x;
+        H[3] = (1.7320508075688772f * s1) * cp;
+    }
+    if (order >= 2) {
+        float c2 = 2.0f * (cp * cp) - 1.0f, s2 = 2.0f * (sp * cp);
+        float q = 1.0f - x * x;
+        H[4] = (1.9364916731037085f * q) * s2;
+        H[5] = ((3.872983346207417f * x) * s1) * sp;
+        H[6] = 2.23606797749979f * ((3.0f * (x * x) - 1.0f) * 0.5f);
+        H[7] = ((3.872983346207417f * x) * s1) * cp;
+        H[8] = (1.9364916731037085f * q) * c2;
+    }
+    return (order + 1) * (order + 1);
+}
+
+/* Lambertian plus normalised Phong lobe, in the local frame (normal = z):
+ * f = rho_d / pi + rho_s (e + 2) / (2 pi) max(0, r.wo)^e with r the mirror
+ * direction of wi; grad = df/dwi (wi as a free vector). */
+EXPORT float or_brdf(float rho_d, float rho_s, float e, const float* wi, const float* wo, float* grad)
+{
+    float f = rho_d * 0.3183098861837907f;
+    if (grad) grad[0] = grad[1] = grad[2] = 0.0f;
+    if (rho_s > 0.0f) {
+        float ro = (-(wi[0] * wo[0]) - wi[1] * wo[1]) + wi[2] * wo[2];
+        if (ro > 0.0f) {
+            float ks = (rho_s * (e + 2.0f)) * 0.15915494309189533f;
+            float pw = or_exp2(e * or_log2(ro));
+            f = f + ks * pw;
+            if (grad) {
+                float gk = (ks * e) * (pw / ro);
+                grad[0] = -(gk * wo[0]);
+                grad[1] = -(gk * wo[1]);
+                grad[2] = gk * wo[2];
+            }
+        }
+    }
+    return f;
+}
+
+/* the bounce's orthonormal basis about the oriented normal (Duff et al. 2017) */
+static void local_frame(const float* no, float* b1, float* b2)
+{
+    float sign = copysignf(1.0f, no[2]);
+    float a = -1.0f / (sign + no[2]);
+    float bxy = (no[0] * no[1]) * a;
+    b1[0] = 1.0f + ((sign * no[0]) * no[0]) * a; b1[1] = sign * bxy; b1[2] = -(sign * no[0]);
+    b2[0] = bxy; b2[1] = sign + (no[1] * no[1]) * a; b2[2] = -no[1];
+}
+
 static void trace_path(const or_scene* S, const olight* L, int layout, int l_local, int gl, uint32_t i, uint64_t seed,
                        int B, const or_proposal* prop_in, path_io* io)
 {
@@ -709,6 +781,16 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
     float Tc[3] = {1.0f, 1.0f, 1.0f};
     float sc[3] = {0.0f, 0.0f, 0.0f};
     const int64_t K = S->n_texels;
+    /* directional mode: exitant radiance coefficients per texel; the bounce
+     * weight is pi f; the adjoint also carries the BRDF terms of the first
+     * hit (its projection and its bounce weight depend on the incident
+     * direction, which moves with the light while x_1 stays fixed) */
+    const int dirm = S->dir_order >= 0;
+    const int NC = dirm ? (S->dir_order + 1) * (S->dir_order + 1) : 1;
+    const float inv_np = dirm ? 1.0f / (float)S->dir_samples : 0.0f;
+    float T2 = 1.0f, Rd = 0.0f;
+    float Qw[3] = {0, 0, 0}, Dw[3] = {0, 0, 0}, om1[3] = {0, 0, 0}, inv_r1 = 0.0f;
+    float wi_loc[3] = {0, 0, 0}, fb1[3] = {0, 0, 0}, fb2[3] = {0, 0, 0};
     for (int h = 1; h <= B; ++h) {
         float t;
         int64_t prim = intersect(S, o, dir, skip, &t);
@@ -760,7 +842,65 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
         float no[3];
         if (nd < 0.0f) { no[0] = nq[0]; no[1] = nq[1]; no[2] = nq[2]; }
         else { no[0] = -nq[0]; no[1] = -nq[1]; no[2] = -nq[2]; }
-        if (io->S && L->rgb) {
+        if (dirm) {
+            const float* gl_ = S->glossy ? S->glossy + 2 * (int64_t)q : NULL;
+            float rs = gl_ ? gl_[0] : 0.0f, ex = gl_ ? gl_[1] : 1.0f;
+            local_frame(no, fb1, fb2);
+            float wiw[3] = {-dir[0], -dir[1], -dir[2]};
+            wi_loc[0] = dot3(fb1, wiw); wi_loc[1] = dot3(fb2, wiw); wi_loc[2] = dot3(no, wiw);
+            float acc_c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            float pd = 0.0f, ql[3] = {0, 0, 0};
+            for (int j = 0; j < S->dir_samples; ++j) {
+                float us[4];
+                draw4(seed, i, stream, 0x100u + 16u * (uint32_t)h + (uint32_t)(j >> 1), us);
+                float ua = (j & 1) ? us[2] : us[0], ub = (j & 1) ? us[3] : us[1];
+                float ct = ua;
+                float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+                float sp, cp;
+                or_sincos2pi(ub, &sp, &cp);
+                float wo[3] = {st * cp, st * sp, ct};
+                float H[9];
+                or_hsh(S->dir_order, ct, cp, sp, H);
+                float gr[3];
+                float f = or_brdf(pf[16], rs, ex, wi_loc, wo, (io->g && h == 1) ? gr : NULL);
+                if (io->S)
+                    for (int c = 0; c < NC; ++c) acc_c[c] = acc_c[c] + f * H[c];
+                if (io->g) {
+                    float G = 0.0f;
+                    for (int c = 0; c < NC; ++c) G = G + io->g[c * K + k] * H[c];
+                    pd = pd + f * G;
+                    if (h == 1)
+                        for (int c = 0; c < 3; ++c) ql[c] = ql[c] + G * gr[c];
+                }
+            }
+            if (io->S) {
+                float base = (phi_r * T) * inv_a;
+                for (int c = 0; c < NC; ++c) {
+                    long long code = llrintf(((base * acc_c[c]) * inv_np) * 4294967296.0f);
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+                    io->S[c * K + k] += code;
+                }
+            }
+            if (io->g) {
+                float P = (pd * inv_np) * inv_a;
+                s_r = s_r + P * T;
+                if (h >= 2) Rd = Rd + P * T2;
+                if (h == 1) {
+                    k1 = k;
+                    float dl[6];
+                    first_hit_dlog(L, x, y, no, au, av, dl);
+                    for (int c = 0; c < 6; ++c) dphi[c] = phi_r * dl[c];
+                    float sq = (inv_np * inv_a);
+                    for (int c = 0; c < 3; ++c) Qw[c] = ((ql[0] * sq) * fb1[c] + (ql[1] * sq) * fb2[c]) + (ql[2] * sq) * no[c];
+                    float v1[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
+                    float r1 = sqrtf(dot3(v1, v1));
+                    inv_r1 = 1.0f / r1;
+                    for (int c = 0; c < 3; ++c) om1[c] = v1[c] * inv_r1;
+                }
+            }
+        } else if (io->S && L->rgb) {
             for (int ch = 0; ch < 3; ++ch) {
                 float val = ((phi_r * L->col[ch]) * Tc[ch]) * inv_a;
                 long long code = llrintf(val * 4294967296.0f);
@@ -787,7 +927,7 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
                 io->S[k] += code;
             }
         }
-        if (io->g) {
+        if (io->g && !dirm) {
             if (L->rgb) {
                 for (int ch = 0; ch < 3; ++ch) sc[ch] = sc[ch] + (io->g[ch * K + k] * inv_a) * Tc[ch];
             } else {
@@ -826,7 +966,23 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
         for (int c = 0; c < 3; ++c) dir[c] = (lx * b1[c] + ly * b2[c]) + lz * no[c];
         for (int c = 0; c < 3; ++c) o[c] = x[c];
         skip = q;
-        T = T * pf[16];
+        if (dirm) {
+            const float* gl_ = S->glossy ? S->glossy + 2 * (int64_t)q : NULL;
+            float wo[3] = {dot3(fb1, dir), dot3(fb2, dir), dot3(no, dir)};
+            float gr[3];
+            float fbv = or_brdf(pf[16], gl_ ? gl_[0] : 0.0f, gl_ ? gl_[1] : 1.0f, wi_loc, wo, gr);
+            float wb = fbv * 3.14159265358979f;
+            if (h == 1) {
+                for (int c = 0; c < 3; ++c)
+                    Dw[c] = ((gr[0] * 3.14159265358979f) * fb1[c] + (gr[1] * 3.14159265358979f) * fb2[c]) +
+                            (gr[2] * 3.14159265358979f) * no[c];
+            } else {
+                T2 = T2 * wb;
+            }
+            T = T * wb;
+        } else {
+            T = T * pf[16];
+        }
         for (int ch = 0; ch < 3; ++ch) Tc[ch] = Tc[ch] * (S->albedo_rgb ? S->albedo_rgb[3 * q + ch] : pf[16]);
     }
     if (io->g && hits >= 1 && L->rgb) {
@@ -839,8 +995,25 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
     }
     if (io->g && hits >= 1) {
         float cr[6];
+        float ub_[3] = {0, 0, 0};
+        float dya[3] = {0, 0, 0}, dyb[3] = {0, 0, 0};
+        if (dirm) {
+            /* d/dy of the first hit's projection and bounce weight through the
+             * incident direction om1 = (y - x_1)/|y - x_1| */
+            float v[3];
+            for (int c = 0; c < 3; ++c) v[c] = Qw[c] + Rd * Dw[c];
+            float wv = dot3(om1, v);
+            for (int c = 0; c < 3; ++c) ub_[c] = (v[c] - om1[c] * wv) * inv_r1;
+            if (L->type == 2)
+                for (int c = 0; c < 3; ++c) {
+                    dya[c] = av * L->db_da[c];
+                    dyb[c] = au * L->dt_db[c] + av * L->db_db[c];
+                }
+        }
+        float extra[6] = {ub_[0], ub_[1], ub_[2], dot3(ub_, dya), dot3(ub_, dyb), 0.0f};
         for (int c = 0; c < 6; ++c) {
             cr[c] = s_r * dphi[c];
+            if (dirm) cr[c] = cr[c] + phi_r * extra[c];
             if (io->acc) io->acc[c] += (double)cr[c];
             if (io->contrib) io->contrib[c] = cr[c];
         }
@@ -882,7 +1055,8 @@ EXPORT int64_t or_forward(const or_scene* S, const or_lights* Ls, const float* p
                           const or_proposal* prop, int64_t* S_out)
 {
     /* colour mode: [n_layouts, 3, K] */
-    const int64_t stride = (Ls->colour ? 3 : 1) * S->n_texels;
+    const int64_t stride = (S->dir_order >= 0 ? (S->dir_order + 1) * (S->dir_order + 1) : (Ls->colour ? 3 : 1)) *
+                           S->n_texels;
     memset(S_out, 0, (size_t)(stride * Ls->n_layouts) * sizeof(int64_t));
     int64_t misses = 0;
 #ifdef _OPENMP
@@ -919,7 +1093,8 @@ EXPORT int64_t or_adjoint(const or_scene* S, const or_lights* Ls, const float* p
                           int64_t paths_per_layout, int max_hits, int64_t limit_per_light, int n_threads,
                           const or_proposal* prop, const float* dOdE, double* grad_out, double* grad_colour)
 {
-    const int64_t stride = (Ls->colour ? 3 : 1) * S->n_texels;
+    const int64_t stride = (S->dir_order >= 0 ? (S->dir_order + 1) * (S->dir_order + 1) : (Ls->colour ? 3 : 1)) *
+                           S->n_texels;
     int64_t misses = 0;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);

@@ -183,6 +183,68 @@ def _node_sums(i0, i1, a0, a1, j0, j1, b0, b1, res):
     return out
 
 
+def hsh_basis(order, ct, phi):
+    """2pi-normalised hemispherical harmonics (integral of H^2 over the
+    hemisphere = 2 pi) from scipy's associated Legendre functions of
+    x = 2 cos(theta) - 1, with the Condon-Shortley phase removed; index
+    l^2 + l + m, cos(m phi) for m > 0, sin(|m| phi) for m < 0."""
+    from scipy.special import lpmv
+    x = 2.0 * np.asarray(ct, np.float64) - 1.0
+    out = []
+    for l in range(order + 1):
+        for m in range(-l, l + 1):
+            am = abs(m)
+            P = lpmv(am, l, x) * (-1.0) ** am
+            if m == 0:
+                K = math.sqrt(2 * l + 1)
+                out.append(K * P)
+            else:
+                K = math.sqrt(2 * (2 * l + 1) * math.factorial(l - am) / math.factorial(l + am))
+                out.append(K * P * (np.cos(am * phi) if m > 0 else np.sin(am * phi)))
+    return np.stack(out, -1)
+
+
+def phong_brdf(rho_d, rho_s, e, wi, wo):
+    """Lambertian + normalised Phong, normal = z: f = rho_d/pi + rho_s (e+2)/(2 pi)
+    max(0, r.wo)^e with r the mirror direction of wi."""
+    r = np.stack([-wi[..., 0], -wi[..., 1], wi[..., 2]], -1)
+    ro = np.clip(np.sum(r * wo, -1), 0.0, None)
+    return rho_d / math.pi + rho_s * (e + 2) / (2 * math.pi) * ro ** e
+
+
+def plane_direct_coefficients(n_lobe, p, half, res, rho_d, rho_s, e, order, q_tex=4, q_ct=24, n_phi=48):
+    """Expected exitant-radiance coefficients per texel of the z = 0 plane
+    (normal +z, local frame = world) under a cos^n spot, direct light only,
+    times A_k / P: int_texel pdf(x) F_lm(w_in(x)) dA with pdf the first-hit
+    density per unit area and F_lm(w_in) = 1/(2 pi) int f(w_in, w) H_lm(w) dw,
+    both by quadrature."""
+    c = np.asarray(p[:3], np.float64)
+    d, t, b = frame(p[3], p[4])
+    gx, gw = gauss_legendre(q_tex)
+    x0, x1, y0, y1 = plane_texels(half, res)
+    fu, fv = np.meshgrid(gx, gx, indexing="ij")
+    wq = np.outer(gw, gw).ravel()
+    X = x0[:, None] + (x1 - x0)[:, None] * fu.ravel()[None, :]
+    Y = y0[:, None] + (y1 - y0)[:, None] * fv.ravel()[None, :]
+    area = ((x1 - x0) * (y1 - y0))[:, None]
+    v = np.stack([X - c[0], Y - c[1], -np.full_like(X, c[2])], -1)
+    r = np.linalg.norm(v, axis=-1)
+    w = v / r[..., None]
+    pdf = lobe_density(1, n_lobe, d, w) * (c[2] / r) / r ** 2            # per unit area
+    wi = -w                                                             # towards the light
+    cg, cw = gauss_legendre(q_ct)
+    ph = (np.arange(n_phi) + 0.5) * 2 * math.pi / n_phi
+    CT, PH = np.meshgrid(cg, ph, indexing="ij")
+    ST = np.sqrt(1 - CT ** 2)
+    wo = np.stack([ST * np.cos(PH), ST * np.sin(PH), CT], -1).reshape(-1, 3)
+    ww = (np.repeat(cw, n_phi) * (2 * math.pi / n_phi))                   # dw = d(ct) dphi
+    H = hsh_basis(order, CT.ravel(), PH.ravel())                          # [Q, NC]
+    f = phong_brdf(rho_d, rho_s, e, wi.reshape(-1, 1, 3), wo[None, :, :])  # [texels*q, Q]
+    F = (f * ww[None, :]) @ H / (2 * math.pi)                            # [texels*q, NC]
+    F = F.reshape(X.shape[0], X.shape[1], -1)
+    return np.einsum("kq,kqc->kc", pdf * wq[None, :] * area, F)          # [K, NC] per unit flux
+
+
 def log_irradiance(kind, n, p, x1, n1, au=0.0, av=0.0, size=None):
     """log of the first-hit irradiance kernel at receiver x1 with unit normal
     n1 (facing the light), up to p-independent constants: a luminaire of power

@@ -492,6 +492,170 @@ def test_rgb_colour_gradient(oracle_lib):
     assert abs(lhs / rhs - 1) < 1e-5
 
 
+# --------------------------------------------------------------------------
+# directional texels (hemispherical harmonics) and a glossy BRDF
+# --------------------------------------------------------------------------
+
+def test_hsh_orthonormal(oracle_lib):
+    """The oracle's harmonics: integral of H_i H_j over the hemisphere is
+    2 pi delta_ij, and they agree with scipy's associated Legendre functions."""
+    cg, cw = cf.gauss_legendre(16)
+    n_phi = 64
+    ph = (np.arange(n_phi) + 0.5) * 2 * math.pi / n_phi
+    Hs, W = [], []
+    for ct, w in zip(cg, cw):
+        for f in ph:
+            Hs.append(oracle_lib.hsh(2, ct, math.cos(f), math.sin(f)).astype(np.float64))
+            W.append(w * 2 * math.pi / n_phi)
+    Hs, W = np.array(Hs), np.array(W)
+    G = (Hs * W[:, None]).T @ Hs
+    assert np.allclose(G, 2 * math.pi * np.eye(9), atol=2e-5)
+    CT, PH = np.meshgrid(cg, ph, indexing="ij")
+    ref = cf.hsh_basis(2, CT.ravel(), PH.ravel())
+    assert np.allclose(Hs, ref, atol=2e-6)
+
+
+def test_brdf_normalisation_and_gradient(oracle_lib):
+    """At normal incidence the normalised Phong lobe reflects exactly rho_s
+    (int (e+2)/(2 pi) cos^e cos dw = 1); the gradient w.r.t. w_in matches
+    central differences."""
+    cg, cw = cf.gauss_legendre(64)
+    n_phi = 32
+    tot = 0.0
+    for ct, w in zip(cg, cw):
+        st = math.sqrt(1 - ct * ct)
+        for k in range(n_phi):
+            f = (k + 0.5) * 2 * math.pi / n_phi
+            fv, _ = oracle_lib.brdf(0.3, 0.5, 12.0, [0, 0, 1], [st * math.cos(f), st * math.sin(f), ct])
+            tot += fv * ct * w * 2 * math.pi / n_phi
+    assert abs(tot - 0.8) < 1e-4
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        wi = rng.normal(size=3); wi[2] = abs(wi[2]) + 0.3; wi /= np.linalg.norm(wi)
+        wo = np.array([-wi[0], -wi[1], wi[2]]) + 0.2 * rng.normal(size=3); wo[2] = abs(wo[2]); wo /= np.linalg.norm(wo)
+        f0, gr = oracle_lib.brdf(0.2, 0.6, 7.0, wi, wo)
+        for c in range(3):
+            h = 1e-3
+            a, b = wi.copy(), wi.copy()
+            a[c] += h
+            b[c] -= h
+            fd = (oracle_lib.brdf(0.2, 0.6, 7.0, a, wo)[0] - oracle_lib.brdf(0.2, 0.6, 7.0, b, wo)[0]) / (2 * h)
+            assert abs(fd - gr[c]) < 2e-3 * (abs(fd) + 1.0), (c, fd, gr[c])
+
+
+def test_directional_lambertian_is_irradiance(oracle_lib):
+    """With a Lambertian surface the exitant radiance is isotropic: the
+    order-0 coefficient is (rho / pi) E_k of the irradiance tracer on the same
+    paths, and the higher ones average out."""
+    c1 = li.box_room()
+    sc, lights = c1["scene"], c1["lights"]
+    N, B, seed = 1 << 15, 3, 0x61
+    ol = oracle_lib.OracleLights(lights)
+    S_d, _ = oracle_lib.forward(oracle_lib.OracleScene(sc, dir_order=2, dir_samples=4), ol, lights.params, seed, N, B)
+    S_e, _ = oracle_lib.forward(oracle_lib.OracleScene(sc), ol, lights.params, seed, N, B)
+    rho = np.repeat(sc.patches["albedo"].astype(np.float64), sc.patch_res().prod(1))
+    L0 = S_d[0, 0].astype(np.float64)
+    ref = rho / math.pi * S_e[0].astype(np.float64)
+    assert np.linalg.norm(L0 - ref) <= 2e-6 * np.linalg.norm(ref)
+    hi = S_d[0, 1:].astype(np.float64)
+    assert abs(hi.sum()) < 0.02 * np.abs(hi).sum()
+
+
+def _glossy_plane(half, res):
+    sc = li.plane_scene(half=half, res=res, albedo=0.3)
+    return sc, np.array([[0.5, 16.0]], np.float32)
+
+
+def test_directional_glossy_direct_over_plane(oracle_lib):
+    """Direct light on a glossy plane: every coefficient's texel mean agrees
+    with the quadrature of the reflected radiance's projection, within the
+    noise two seeds show."""
+    half, res, N = 2.0, 8, 1 << 18
+    sc, gl = _glossy_plane(half, res)
+    p = [0.3, -0.2, 1.2, 0.3, -0.15, 50.0]
+    lights = make_lights([SPOT], [3.0], [(0, 0)], [0], [p])
+    osc = oracle_lib.OracleScene(sc, glossy=gl, dir_order=2, dir_samples=8)
+    ol = oracle_lib.OracleLights(lights)
+    A = float(sc.texel_area()[0])
+    ref = cf.plane_direct_coefficients(3.0, p, half, res, 0.3, 0.5, 16.0, 2).T * p[5] / A   # [9, K]
+    Ls = [oracle_lib.fixed_to_float(oracle_lib.forward(osc, ol, lights.params, sd, N, 1)[0])[0].astype(np.float64)
+          for sd in (0x91, 0x92)]
+    err = np.linalg.norm((Ls[0] + Ls[1]) / 2 - ref)
+    noise = np.linalg.norm(Ls[0] - Ls[1]) / 2
+    assert err < 1.6 * noise + 1e-4 * np.linalg.norm(ref), (err, noise)
+
+
+def test_directional_glossy_direct_gradient(oracle_lib):
+    """Direct light on a glossy plane: the adjoint's mean over seeds matches
+    the derivative of the quadrature expectation of sum g_lm,k L_lm,k; the
+    first hit's BRDF projection term carries most of the position gradient."""
+    half, res, N, n_seeds = 2.0, 8, 1 << 16, 8
+    sc, gl = _glossy_plane(half, res)
+    p = np.array([0.3, -0.2, 1.2, 0.3, -0.15, 50.0])
+    lights = make_lights([SPOT], [3.0], [(0, 0)], [0], [p])
+    osc = oracle_lib.OracleScene(sc, glossy=gl, dir_order=2, dir_samples=8)
+    ol = oracle_lib.OracleLights(lights)
+    A = float(sc.texel_area()[0])
+    g = np.random.default_rng(6).normal(size=(9, sc.n_texels)).astype(np.float32)
+    ref = np.zeros(6)
+    for c in range(6):
+        h = 1e-4
+        pp, pm = p.copy(), p.copy()
+        pp[c] += h
+        pm[c] -= h
+        Ep = cf.plane_direct_coefficients(3.0, pp, half, res, 0.3, 0.5, 16.0, 2).T * pp[5] / A
+        Em = cf.plane_direct_coefficients(3.0, pm, half, res, 0.3, 0.5, 16.0, 2).T * pm[5] / A
+        ref[c] = float(np.sum(g.astype(np.float64) * (Ep - Em))) / (2 * h)
+    grads = np.array([oracle_lib.adjoint(osc, ol, lights.params, 0xA0 + s, N, 1, g[None])[0][0]
+                      for s in range(n_seeds)])
+    mean, se = grads.mean(0), grads.std(0, ddof=1) / math.sqrt(n_seeds)
+    for c in range(6):
+        assert abs(mean[c] - ref[c]) < 5 * se[c] + 3e-3 * abs(ref[c]), (c, mean[c], ref[c], se[c])
+
+
+def test_directional_glossy_bounce_gradient(oracle_lib):
+    """Light reflected by a glossy floor onto a Lambertian ceiling, dO/dL on
+    the ceiling only (B = 2): the floor's bounce weight pi f(w_in, w_out)
+    changes with the incident direction while the floor point stays fixed,
+    so the adjoint needs the BRDF term.  Its mean over seeds matches
+    seed-averaged central differences with common random numbers."""
+    sb = li.SceneBuilder()
+    sb.quads([-2.0, -2.0, 0.0], [4.0, 0, 0], [0, 4.0, 0], 0.3, res=(1, 1))
+    sb.quads([-2.0, -2.0, 2.5], [4.0, 0, 0], [0, 4.0, 0], 0.7, res=(2, 2))
+    sc = sb.build("glossy_floor_ceiling")
+    gl = np.array([[0.5, 10.0], [0.0, 1.0]], np.float32)
+    p = np.array([[0.2, -0.1, 1.4, 0.25, -0.1, 60.0]], np.float32)
+    lights = make_lights([SPOT], [3.0], [(0, 0)], [0], p)
+    osc = oracle_lib.OracleScene(sc, glossy=gl, dir_order=1, dir_samples=2)
+    ol = oracle_lib.OracleLights(lights)
+    g = np.zeros((1, 4, sc.n_texels), np.float32)
+    g[0, 0, 1:] = np.array([1.0, 0.7, 1.3, 0.9], np.float32)
+    N, B, n_seeds = 1 << 16, 2, 16
+
+    def lin(pp, seed):
+        S, _ = oracle_lib.forward(osc, ol, pp, seed, N, B)
+        return float(np.sum(g.astype(np.float64) * S.astype(np.float64) * 2.0 ** -32))
+
+    diffs, adjs = [], []
+    for s_ in range(n_seeds):
+        seed = 0xC0 + 31 * s_
+        adj = oracle_lib.adjoint(osc, ol, p, seed, N, B, g)[0][0]
+        fd = np.zeros(5)
+        for c in range(5):
+            h = 2e-3
+            pp, pm = p.copy(), p.copy()
+            pp[0, c] += h
+            pm[0, c] -= h
+            fd[c] = (lin(pp, seed) - lin(pm, seed)) / (float(pp[0, c]) - float(pm[0, c]))
+        diffs.append(fd - adj[:5])
+        adjs.append(adj[:5])
+    D, G = np.array(diffs), np.array(adjs)
+    se = D.std(0, ddof=1) / math.sqrt(n_seeds)
+    gm = np.abs(G.mean(0))
+    for c in range(5):
+        assert abs(D[:, c].mean()) < 4.5 * se[c] + 0.02 * gm[c], (c, D[:, c].mean(), se[c], gm[c])
+
+
 def test_cosine_bounce_floor_to_ceiling(oracle_lib):
     """Second hits on a parallel ceiling: floor first-hit density times the
     differential form factor to each ceiling texel (cosine-weighted bounce, rho)."""
