@@ -205,6 +205,29 @@ int lt_trace_forward_rgb(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_pa
 int lt_trace_adjoint_rgb(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, const float* d_colour,
                          const float* d_dOdE, float* d_grad, float* d_grad_colour, float* d_bin_hist);
 
+/* Directional texels (Eq. directionalCoeffs with n = 1, 2; Sec. 4.1) with a
+ * glossy BRDF.  Each texel holds NC = (order+1)^2 coefficients of its
+ * reflected radiance in 2pi-normalised hemispherical harmonics (the
+ * integral of H^2 over the hemisphere is 2 pi, H_0^0 = 1; associated
+ * Legendre functions of 2 cos(theta) - 1, index l^2 + l + m, cos m phi for
+ * m > 0, sin |m| phi for m < 0), in the local frame of the side the light
+ * arrives on (normal = z, tangents of the bounce's orthonormal basis, Duff et
+ * al. 2017).  Each hit projects (Phi / A) f(w_in, w) with `samples` uniform
+ * local directions.  BRDF per patch: Lambertian albedo (lt_patch.albedo)
+ * plus a normalised Phong lobe rho_s (e+2)/(2 pi) cos^e about the mirror
+ * direction (lt_set_glossy, h_glossy [n_patches,2] = (rho_s, e), host
+ * pointer; Lambertian after lt_scene_upload).  Bounces stay cosine-sampled,
+ * the throughput taking pi f.  Texel arrays d_S, d_E, d_dOdE
+ * [n_layouts,NC,K]; lt_objective takes n = n_layouts*NC*K.  The adjoint
+ * adds the first hit's BRDF terms: its projection and its bounce weight
+ * depend on the incident direction, which moves with the luminaire while
+ * x_1 stays fixed (Eq. dLdp).  order 0..2, samples 1..64, box basis, grey. */
+int lt_set_glossy(lt_ctx* ctx, const float* h_glossy);
+int lt_trace_forward_dir(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, int32_t order, int32_t samples,
+                         int64_t* d_S, float* d_E);
+int lt_trace_adjoint_dir(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, int32_t order, int32_t samples,
+                         const float* d_dOdE, float* d_grad, float* d_bin_hist);
+
 /* Object-space path tracing with next-event estimation: the comparison
  * estimator of Sec. 6 (after Stam 2020) on the same texels.  Each texel gets
  * samples_per_texel points drawn uniformly in it; every path vertex (the

@@ -46,6 +46,7 @@ struct lt_ctx {
     float* parea = nullptr;
     float* texel_area = nullptr;
     float4* rho_rgb = nullptr;       // per-patch channel albedo (colour mode)
+    float2* glossy = nullptr;        // per-patch (specular albedo, Phong exponent) (directional mode)
     int n_nodes = 0, depth = 0, n_patches = 0;
     long long n_tris = 0, K = 0;
     uint64_t generation = 1;
@@ -123,9 +124,9 @@ void free_graphs(lt_ctx* c)
 void free_scene(lt_ctx* c)
 {
     hipFree(c->nodes); hipFree(c->tris); hipFree(c->patches); hipFree(c->pbase); hipFree(c->parea);
-    hipFree(c->texel_area); hipFree(c->rho_rgb);
+    hipFree(c->texel_area); hipFree(c->rho_rgb); hipFree(c->glossy);
     c->nodes = nullptr; c->tris = nullptr; c->patches = nullptr; c->pbase = nullptr; c->parea = nullptr;
-    c->texel_area = nullptr; c->rho_rgb = nullptr;
+    c->texel_area = nullptr; c->rho_rgb = nullptr; c->glossy = nullptr;
     c->has_scene = false;
 }
 
@@ -296,6 +297,7 @@ TraceArgs trace_args(lt_ctx* c, const lt_trace_cfg* cfg)
     a.refill_threshold = c->tune.refill_threshold;
     a.tri_share = c->tune.tri_share;
     a.linear = (cfg->flags & LT_FLAG_LINEAR) ? 1 : 0;
+    a.dir_order = -1;
     a.max_steps = 2 * c->n_nodes + 16;
     a.flags = c->d_flags;
     if (cfg->flags & LT_FLAG_PROPOSAL) {
@@ -538,6 +540,10 @@ int lt_scene_upload(lt_ctx* c, const float* h_verts, int64_t n_verts, const int3
         for (int q = 0; q < n_patches; ++q) rr[q] = make_float4(h_patches[q].albedo, h_patches[q].albedo, h_patches[q].albedo, 0.f);
         HIPCHK(c, hipMalloc(&c->rho_rgb, sizeof(float4) * n_patches));
         HIPCHK(c, hipMemcpy(c->rho_rgb, rr.data(), sizeof(float4) * n_patches, hipMemcpyHostToDevice));
+        // directional mode: Lambertian until set otherwise
+        std::vector<float2> gg(n_patches, make_float2(0.0f, 1.0f));
+        HIPCHK(c, hipMalloc(&c->glossy, sizeof(float2) * n_patches));
+        HIPCHK(c, hipMemcpy(c->glossy, gg.data(), sizeof(float2) * n_patches, hipMemcpyHostToDevice));
     }
     HIPCHK(c, launch_texel_area(c->parea, c->pbase, n_patches, K, c->texel_area, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -796,6 +802,100 @@ int lt_trace_adjoint_rgb(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_para
         return e;
     };
     return run_seq(c, graph, make_key(c, 6, cfg, {d_params, d_colour, d_dOdE, d_grad, d_grad_colour, d_bin_hist}),
+                   body);
+}
+
+int lt_set_glossy(lt_ctx* c, const float* h_glossy)
+{
+    if (!c) return LT_EINVAL;
+    if (!c->has_scene) return fail(c, LT_ESTATE, "no scene uploaded");
+    if (!h_glossy) return fail(c, LT_EINVAL, "NULL glossy table");
+    std::vector<float2> gg(c->n_patches);
+    for (int q = 0; q < c->n_patches; ++q) {
+        const float rs = h_glossy[2 * (size_t)q], e = h_glossy[2 * (size_t)q + 1];
+        if (!(rs >= 0.0f && rs <= 1.0f) || !(e >= 0.0f && e <= 1e4f))
+            return fail(c, LT_EINVAL, "specular albedo outside [0, 1] or exponent outside [0, 1e4]");
+        gg[q] = make_float2(rs, e);
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->glossy, gg.data(), sizeof(float2) * c->n_patches, hipMemcpyHostToDevice));
+    return LT_OK;
+}
+
+namespace {
+
+int dir_check(lt_ctx* c, const lt_trace_cfg* cfg, int32_t order, int32_t samples)
+{
+    int rc = check_cfg(c, cfg);
+    if (rc) return rc;
+    if (order < 0 || order > 2) return fail(c, LT_EINVAL, "hemispherical-harmonic order must be 0, 1 or 2");
+    if (samples < 1 || samples > 64) return fail(c, LT_EINVAL, "local samples per hit must be in [1, 64]");
+    if (cfg->flags & LT_FLAG_LINEAR) return fail(c, LT_EINVAL, "directional texels take the box basis only");
+    if (cfg->max_hits > 64) return fail(c, LT_EINVAL, "max_hits too large for the local-sample counters");
+    return LT_OK;
+}
+
+}  // namespace
+
+int lt_trace_forward_dir(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int32_t order, int32_t samples,
+                         int64_t* d_S, float* d_E)
+{
+    int rc = dir_check(c, cfg, order, samples);
+    if (rc) return rc;
+    if (!d_params || !d_S || !d_E) return fail(c, LT_EINVAL, "NULL device buffer");
+    if (((uintptr_t)d_S & 15) || ((uintptr_t)d_E & 7) || ((uintptr_t)d_params & 3))
+        return fail(c, LT_EINVAL, "d_S must be 16-byte and d_E 8-byte aligned");
+    HIPCHK(c, hipSetDevice(c->device));
+    const long long blocks = trace_blocks(c);
+    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    if (rc) return rc;
+    TraceArgs a = trace_args(c, cfg);
+    a.S = (long long*)d_S;
+    a.dir_order = order;
+    a.dir_samples = samples;
+    a.glossy = c->glossy;
+    const long long n = (long long)(order + 1) * (order + 1) * c->K * c->n_layouts;
+    const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
+    auto body = [&](hipStream_t st) -> hipError_t {
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        if (e == hipSuccess) e = launch_clear(a.S, n, st);
+        if (e == hipSuccess) e = timed_trace(c, false, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = launch_finalize(a.S, d_E, n, c->d_flags, st);
+        return e;
+    };
+    return run_seq(c, graph, make_key(c, 7, cfg, {d_params, d_S, d_E, (const void*)(uintptr_t)(order * 256 + samples)}),
+                   body);
+}
+
+int lt_trace_adjoint_dir(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int32_t order, int32_t samples,
+                         const float* d_dOdE, float* d_grad, float* d_bin_hist)
+{
+    int rc = dir_check(c, cfg, order, samples);
+    if (rc) return rc;
+    if (!d_params || !d_dOdE || !d_grad) return fail(c, LT_EINVAL, "NULL device buffer");
+    if (d_bin_hist && ((uintptr_t)d_bin_hist & 15)) return fail(c, LT_EINVAL, "d_bin_hist must be 16-byte aligned");
+    HIPCHK(c, hipSetDevice(c->device));
+    const long long blocks = trace_blocks(c);
+    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    if (rc) return rc;
+    TraceArgs a = trace_args(c, cfg);
+    a.g = d_dOdE;
+    a.partials = c->d_partials;
+    a.bin_hist = d_bin_hist;
+    a.dir_order = order;
+    a.dir_samples = samples;
+    a.glossy = c->glossy;
+    const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
+    auto body = [&](hipStream_t st) -> hipError_t {
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        if (e == hipSuccess && d_bin_hist) e = launch_fill_f32(d_bin_hist, (long long)c->L * 1024, 0.0f, st);
+        if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = launch_grad_reduce(c->d_partials, c->d_range, c->L, d_grad, st);
+        return e;
+    };
+    return run_seq(c, graph,
+                   make_key(c, 8, cfg, {d_params, d_dOdE, d_grad, d_bin_hist, (const void*)(uintptr_t)(order * 256 + samples)}),
                    body);
 }
 

@@ -55,6 +55,11 @@ struct TraceArgs {
     float alpha_plain;
     float* bin_hist;            // adjoint: [L,1024] histogram of |c_r / sigma| (may be null)
     const float* inv_sigma;     // [L,6]
+    // directional texels: HSH order 0..2 (-1: irradiance texels), local
+    // samples per hit, [P] per-patch (specular albedo, Phong exponent)
+    int dir_order;
+    int dir_samples;
+    const float2* glossy;
     // colour mode: [L,3] channel weights, [P] per-patch channel albedo,
     // adjoint [n_tiles,3] partial sums of dO/dc
     int rgb;

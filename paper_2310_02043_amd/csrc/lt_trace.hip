@@ -450,6 +450,60 @@ __device__ __forceinline__ float linear_gather(const float* __restrict__ g, cons
     return ((wb[0] * g[kb[0]] + wb[1] * g[kb[1]]) + wb[2] * g[kb[2]]) + wb[3] * g[kb[3]];
 }
 
+// Directional texels: 2pi-normalised hemispherical harmonics up to order 2
+// (associated Legendre functions of x = 2 cos(theta) - 1 times cos / sin of
+// m phi, index l^2 + l + m), and a Lambertian + normalised Phong BRDF in the
+// local frame (normal = z) with its gradient w.r.t. the incident direction.
+__device__ __forceinline__ void hsh_eval(int order, float ct, float cp, float sp, float H[9])
+{
+    const float x = 2.0f * ct - 1.0f;
+    const float s1 = __builtin_sqrtf(fmaxf(0.0f, 1.0f - x * x));
+    H[0] = 1.0f;
+    if (order >= 1) {
+        H[1] = (1.7320508075688772f * s1) * sp;
+        H[2] = 1.7320508075688772f * x;
+        H[3] = (1.7320508075688772f * s1) * cp;
+    }
+    if (order >= 2) {
+        const float c2 = 2.0f * (cp * cp) - 1.0f, s2 = 2.0f * (sp * cp);
+        const float q = 1.0f - x * x;
+        H[4] = (1.9364916731037085f * q) * s2;
+        H[5] = ((3.872983346207417f * x) * s1) * sp;
+        H[6] = 2.23606797749979f * ((3.0f * (x * x) - 1.0f) * 0.5f);
+        H[7] = ((3.872983346207417f * x) * s1) * cp;
+        H[8] = (1.9364916731037085f * q) * c2;
+    }
+}
+
+__device__ __forceinline__ float brdf_local(float rho_d, float rho_s, float e, V3 wi, V3 wo, bool want_grad, V3& grad)
+{
+    float f = rho_d * 0.3183098861837907f;
+    grad = v3(0.0f, 0.0f, 0.0f);
+    if (rho_s > 0.0f) {
+        const float ro = (-(wi.x * wo.x) - wi.y * wo.y) + wi.z * wo.z;
+        if (ro > 0.0f) {
+            const float ks = (rho_s * (e + 2.0f)) * 0.15915494309189533f;
+            const float pw = exp2_c(e * log2_c(ro));
+            f = f + ks * pw;
+            if (want_grad) {
+                const float gk = (ks * e) * (pw / ro);
+                grad = v3(-(gk * wo.x), -(gk * wo.y), gk * wo.z);
+            }
+        }
+    }
+    return f;
+}
+
+// the bounce's orthonormal basis about the oriented normal
+__device__ __forceinline__ void local_frame(V3 no, V3& b1, V3& b2)
+{
+    const float sg = __builtin_copysignf(1.0f, no.z);
+    const float a = -1.0f / (sg + no.z);
+    const float bxy = (no.x * no.y) * a;
+    b1 = v3(1.0f + ((sg * no.x) * no.x) * a, sg * bxy, -(sg * no.x));
+    b2 = v3(bxy, sg + (no.y * no.y) * a, -no.y);
+}
+
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 __device__ __forceinline__ int lanes_below(uint64_t m)
@@ -487,7 +541,9 @@ __device__ __forceinline__ long long xcd_block(long long b, long long nb, int re
 // box texel basis, 1 the piecewise-linear basis (four splats / a four-node
 // gather per hit), 2 colour (three channel-planar texel arrays; the green
 // and blue throughputs and adjoint sums live in LDS beside the red ones in
-// registers).
+// registers), 3 directional texels (hemispherical-harmonic coefficients of
+// the reflected radiance and a glossy BRDF; the adjoint's first-hit BRDF
+// terms live in LDS).
 template <bool ADJ, bool STATS, int WPB, int LDS_D, int MODE>
 __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5))) k_trace(TraceArgs a)
 {
@@ -499,11 +555,14 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
     __shared__ int s_k1[ADJ ? WPB * 64 : 1];
     // colour: per lane T_g, T_b, s_g, s_b and the three channel-weight sums
     __shared__ float s_rgb[MODE == 2 ? WPB * 8 * 64 : 1];
+    // directional adjoint: T2, R, Q[3], D[3], w_in1[3], 1/r1
+    __shared__ float s_dir[(MODE == 3 && ADJ) ? WPB * 12 * 64 : 1];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     float* adj = s_adj + (ADJ ? wib * 12 * 64 + lane : 0);
     int* k1 = s_k1 + (ADJ ? wib * 64 + lane : 0);
     float* rgbs = s_rgb + (MODE == 2 ? wib * 8 * 64 + lane : 0);
+    float* dst = s_dir + ((MODE == 3 && ADJ) ? wib * 12 * 64 + lane : 0);
     const long long blk = xcd_block(blockIdx.x, gridDim.x, a.xcd_remap);
     const long long gw = blk * WPB + wib;
     if (gw >= a.n_tiles) return;
@@ -518,7 +577,9 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
         const uint32_t first = (uint32_t)ti.y;
         const int count = ti.z;
         const uint32_t stream_id = ((uint32_t)ti.w << 16) | (uint32_t)L.l_local;
-        const long long rowK = (MODE == 2 ? 3 : 1) * a.K;
+        const int NC = MODE == 3 ? (a.dir_order + 1) * (a.dir_order + 1) : 1;
+        const long long rowK = (MODE == 2 ? 3 : (MODE == 3 ? NC : 1)) * a.K;
+        const float inv_np = MODE == 3 ? 1.0f / (float)a.dir_samples : 0.0f;
         long long* S = ADJ ? nullptr : a.S + (long long)ti.w * rowK;
         const float* g = ADJ ? a.g + (long long)ti.w * rowK : nullptr;
         float c0 = 1.0f, c1 = 1.0f, c2 = 1.0f;   // channel weights of the flux
@@ -579,6 +640,11 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                         rgbs[128] = 0.0f;
                         rgbs[192] = 0.0f;
                     }
+                    if (MODE == 3 && ADJ) {
+                        dst[0] = 1.0f;
+#pragma unroll
+                        for (int c = 1; c < 8; ++c) dst[c * 64] = 0.0f;
+                    }
                     if (STATS) ++n_seg;
                 }
                 next += __popcll(m);
@@ -621,7 +687,82 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                     ++h;
                     if (STATS) ++n_hits;
                     const HitInfo hi = hit_info(r, s.tb, s.qb, a.patches);
-                    if (!ADJ && MODE == 2) {
+                    V3 fb1 = v3(0, 0, 0), fb2 = v3(0, 0, 0), wil = v3(0, 0, 0);
+                    float2 gls = make_float2(0.0f, 1.0f);
+                    if (MODE == 3) {
+                        gls = a.glossy[s.qb];
+                        local_frame(hi.no, fb1, fb2);
+                        const V3 wiw = v3(-r.dx, -r.dy, -r.dz);
+                        wil = v3(dot(fb1, wiw), dot(fb2, wiw), dot(hi.no, wiw));
+                        float accd[9];
+#pragma unroll
+                        for (int c = 0; c < 9; ++c) accd[c] = 0.0f;
+                        float pd = 0.0f;
+                        V3 ql = v3(0, 0, 0);
+                        U4 us = {0u, 0u, 0u, 0u};
+                        for (int j = 0; j < a.dir_samples; ++j) {
+                            if ((j & 1) == 0)
+                                us = philox10(pid, stream_id, 0x100u + 16u * (uint32_t)h + (uint32_t)(j >> 1), 0u, a.key0,
+                                              a.key1);
+                            const float ua = (j & 1) ? u24(us.z) : u24(us.x);
+                            const float ub = (j & 1) ? u24(us.w) : u24(us.y);
+                            const float ct = ua;
+                            const float st = __builtin_sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+                            float sp, cp;
+                            sincos_2pi(ub, sp, cp);
+                            const V3 wo = v3(st * cp, st * sp, ct);
+                            float H[9];
+                            hsh_eval(a.dir_order, ct, cp, sp, H);
+                            V3 gr;
+                            const float f = brdf_local(hi.rho, gls.x, gls.y, wil, wo, ADJ && h == 1, gr);
+                            if (!ADJ) {
+#pragma unroll
+                                for (int c = 0; c < 9; ++c)
+                                    if (c < NC) accd[c] = accd[c] + f * H[c];
+                            } else {
+                                float G = 0.0f;
+#pragma unroll
+                                for (int c = 0; c < 9; ++c)
+                                    if (c < NC) G = G + g[c * a.K + hi.k] * H[c];
+                                pd = pd + f * G;
+                                if (h == 1) ql = v3(ql.x + G * gr.x, ql.y + G * gr.y, ql.z + G * gr.z);
+                            }
+                        }
+                        if (!ADJ) {
+                            const float base = (phi_r * T) * hi.inva;
+#pragma unroll
+                            for (int c = 0; c < 9; ++c)
+                                if (c < NC) {
+                                    const long long qc =
+                                        (long long)__builtin_rintf(((base * accd[c]) * inv_np) * 4294967296.0f);
+                                    __hip_atomic_fetch_add((unsigned long long*)(S + c * a.K + hi.k),
+                                                           (unsigned long long)qc, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT);
+                                }
+                        } else {
+                            const float P = (pd * inv_np) * hi.inva;
+                            s_r = s_r + P * T;
+                            if (h >= 2) dst[64] = dst[64] + P * dst[0];
+                            if (h == 1) {
+                                float dl[6];
+                                first_hit_dlog(L, hi.x, v3(r.ox, r.oy, r.oz), hi.no, au, av, dl);
+#pragma unroll
+                                for (int c = 0; c < 6; ++c) adj[c * 64] = phi_r * dl[c];
+                                if (vote) *k1 = (int)hi.k;
+                                const float sq = inv_np * hi.inva;
+                                dst[128] = ((ql.x * sq) * fb1.x + (ql.y * sq) * fb2.x) + (ql.z * sq) * hi.no.x;
+                                dst[192] = ((ql.x * sq) * fb1.y + (ql.y * sq) * fb2.y) + (ql.z * sq) * hi.no.y;
+                                dst[256] = ((ql.x * sq) * fb1.z + (ql.y * sq) * fb2.z) + (ql.z * sq) * hi.no.z;
+                                const V3 v1 = v3(r.ox - hi.x.x, r.oy - hi.x.y, r.oz - hi.x.z);
+                                const float r1 = __builtin_sqrtf(dot(v1, v1));
+                                const float ir1 = 1.0f / r1;
+                                dst[512] = v1.x * ir1;
+                                dst[576] = v1.y * ir1;
+                                dst[640] = v1.z * ir1;
+                                dst[704] = ir1;
+                            }
+                        }
+                    } else if (!ADJ && MODE == 2) {
                         const float v0 = ((phi_r * c0) * T) * hi.inva;
                         const float v1 = ((phi_r * c1) * rgbs[0]) * hi.inva;
                         const float v2 = ((phi_r * c2) * rgbs[64]) * hi.inva;
@@ -651,7 +792,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                             __hip_atomic_fetch_add((unsigned long long*)(S + hi.k), (unsigned long long)code,
                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         }
-                    } else {
+                    } else if (MODE != 3) {
                         float gk;
                         if (MODE == 1) {
                             long long kb[4];
@@ -687,6 +828,22 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                             T = T * rho.x;
                             rgbs[0] = rgbs[0] * rho.y;
                             rgbs[64] = rgbs[64] * rho.z;
+                        } else if (MODE == 3) {
+                            const V3 wo = v3(dot(fb1, nd), dot(fb2, nd), dot(hi.no, nd));
+                            V3 gr;
+                            const float fbv = brdf_local(hi.rho, gls.x, gls.y, wil, wo, ADJ && h == 1, gr);
+                            const float wb = fbv * 3.14159265358979f;
+                            if (ADJ) {
+                                if (h == 1) {
+                                    const float pi = 3.14159265358979f;
+                                    dst[320] = ((gr.x * pi) * fb1.x + (gr.y * pi) * fb2.x) + (gr.z * pi) * hi.no.x;
+                                    dst[384] = ((gr.x * pi) * fb1.y + (gr.y * pi) * fb2.y) + (gr.z * pi) * hi.no.y;
+                                    dst[448] = ((gr.x * pi) * fb1.z + (gr.y * pi) * fb2.z) + (gr.z * pi) * hi.no.z;
+                                } else {
+                                    dst[0] = dst[0] * wb;
+                                }
+                            }
+                            T = T * wb;
                         } else {
                             T = T * hi.rho;
                         }
@@ -705,10 +862,33 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                             rgbs[320] += rgbs[128] * phi_r;
                             rgbs[384] += rgbs[192] * phi_r;
                         }
+                        // directional: d/dy of the first hit's projection and
+                        // bounce weight through w_in1 = (y - x_1)/|y - x_1|
+                        float ext[6] = {0, 0, 0, 0, 0, 0};
+                        if (MODE == 3) {
+                            const float Rd = dst[64];
+                            const V3 v = v3(dst[128] + Rd * dst[320], dst[192] + Rd * dst[384], dst[256] + Rd * dst[448]);
+                            const V3 om = v3(dst[512], dst[576], dst[640]);
+                            const float ir1 = dst[704];
+                            const float wv = dot(om, v);
+                            const V3 u = v3((v.x - om.x * wv) * ir1, (v.y - om.y * wv) * ir1, (v.z - om.z * wv) * ir1);
+                            V3 dya = v3(0, 0, 0), dyb = v3(0, 0, 0);
+                            if (L.type == 2) {
+                                dya = v3(av * L.db_da[0], av * L.db_da[1], av * L.db_da[2]);
+                                dyb = v3(au * L.dt_db[0] + av * L.db_db[0], au * L.dt_db[1] + av * L.db_db[1],
+                                         au * L.dt_db[2] + av * L.db_db[2]);
+                            }
+                            ext[0] = u.x;
+                            ext[1] = u.y;
+                            ext[2] = u.z;
+                            ext[3] = dot(u, dya);
+                            ext[4] = dot(u, dyb);
+                        }
                         float m2 = 0.0f;
 #pragma unroll
                         for (int c = 0; c < 6; ++c) {
-                            const float cr = se * adj[c * 64];
+                            float cr = se * adj[c * 64];
+                            if (MODE == 3) cr = cr + phi_r * ext[c];
                             adj[(6 + c) * 64] += cr;
                             if (hist) {
                                 const float z = cr * a.inv_sigma[6 * ti.x + c];
@@ -717,7 +897,11 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                         }
                         if (hist && ebin >= 0) atomicAdd(hist + ebin, m2 * wq);
                         // the path's share of dO/dp_j, placed at its first hit
-                        if (vote) unsafeAtomicAdd(vote + *k1, (double)(se * adj[a.vote_param * 64]));
+                        if (vote) {
+                            float cv = se * adj[a.vote_param * 64];
+                            if (MODE == 3) cv = cv + phi_r * ext[a.vote_param];
+                            unsafeAtomicAdd(vote + *k1, (double)cv);
+                        }
                     }
                     alive = false;
                 }
@@ -1194,7 +1378,12 @@ inline int nblocks(long long n, int b, int cap)
 template <bool ADJ, bool STATS, int WPB>
 hipError_t launch_wpb(const TraceArgs& a, int lds_depth, int blocks, hipStream_t st)
 {
-    if (a.rgb && !STATS) {
+    if (a.dir_order >= 0 && !STATS) {
+        if (lds_depth == 16)
+            k_trace<ADJ, STATS, WPB, 16, 3><<<blocks, WPB * 64, 0, st>>>(a);
+        else
+            k_trace<ADJ, STATS, WPB, 32, 3><<<blocks, WPB * 64, 0, st>>>(a);
+    } else if (a.rgb && !STATS) {
         if (lds_depth == 16)
             k_trace<ADJ, STATS, WPB, 16, 2><<<blocks, WPB * 64, 0, st>>>(a);
         else

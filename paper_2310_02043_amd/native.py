@@ -22,6 +22,7 @@ EXPORTED = [
     "lt_create", "lt_destroy", "lt_last_error", "lt_set_stream", "lt_sync", "lt_scene_upload",
     "lt_set_lights", "lt_trace_forward", "lt_objective", "lt_trace_adjoint", "lt_gradient_votes",
     "lt_pt_forward", "lt_pt_adjoint", "lt_set_albedo_rgb", "lt_trace_forward_rgb", "lt_trace_adjoint_rgb",
+    "lt_set_glossy", "lt_trace_forward_dir", "lt_trace_adjoint_dir",
     "lt_record_paths",
     "lt_trace_stats", "lt_get_tuning", "lt_set_tuning", "lt_autotune", "lt_info_get", "lt_set_timing",
     "lt_timing_read", "lt_proposal_set_table", "lt_proposal_get_table", "lt_proposal_set_scale",
@@ -88,6 +89,9 @@ def load():
     L.lt_gradient_votes.argtypes = [P, C.POINTER(TraceCfg), P, P, I32, I32, P, P]
     L.lt_pt_forward.argtypes = [P, C.POINTER(TraceCfg), P, I32, P, P]
     L.lt_set_albedo_rgb.argtypes = [P, P]
+    L.lt_set_glossy.argtypes = [P, P]
+    L.lt_trace_forward_dir.argtypes = [P, C.POINTER(TraceCfg), P, I32, I32, P, P]
+    L.lt_trace_adjoint_dir.argtypes = [P, C.POINTER(TraceCfg), P, I32, I32, P, P, P]
     L.lt_trace_forward_rgb.argtypes = [P, C.POINTER(TraceCfg), P, P, P, P]
     L.lt_trace_adjoint_rgb.argtypes = [P, C.POINTER(TraceCfg), P, P, P, P, P, P]
     L.lt_pt_adjoint.argtypes = [P, C.POINTER(TraceCfg), P, I32, P, P]
@@ -287,6 +291,42 @@ class Context:
         self._check(self.lib.lt_trace_adjoint_rgb(self.h, C.byref(cfg), _ptr(params), _ptr(colour), _ptr(dOdE),
                                                   _ptr(grad), _ptr(grad_colour), _ptr(bin_hist)))
         return grad, grad_colour
+
+    def set_glossy(self, glossy):
+        """Per-patch (specular albedo, Phong exponent) [n_patches,2] for the
+        directional texels (host)."""
+        import numpy as np
+        a = np.ascontiguousarray(glossy, np.float32)
+        self._check(self.lib.lt_set_glossy(self.h, a.ctypes.data))
+
+    def trace_forward_dir(self, params, cfg, order, samples, S=None, E=None):
+        """Directional texels: returns (L, S), [n_layouts, (order+1)^2, K]
+        hemispherical-harmonic coefficients of the reflected radiance."""
+        torch = self._torch
+        n = (self.n_layouts, (order + 1) ** 2, self.n_texels)
+        self._dev(params, torch.float32, (self.n_lights, 6))
+        if S is None:
+            S = torch.empty(n, dtype=torch.int64, device=params.device)
+        if E is None:
+            E = torch.empty(n, dtype=torch.float32, device=params.device)
+        self._dev(S, torch.int64, n)
+        self._dev(E, torch.float32, n)
+        self._stream()
+        self._check(self.lib.lt_trace_forward_dir(self.h, C.byref(cfg), _ptr(params), int(order), int(samples),
+                                                  _ptr(S), _ptr(E)))
+        return E, S
+
+    def trace_adjoint_dir(self, params, dOdE, cfg, order, samples, grad=None, bin_hist=None):
+        """Directional adjoint: dOdE [n_layouts, (order+1)^2, K] -> grad [L,6]."""
+        torch = self._torch
+        self._dev(params, torch.float32, (self.n_lights, 6))
+        self._dev(dOdE, torch.float32, (self.n_layouts, (order + 1) ** 2, self.n_texels))
+        if grad is None:
+            grad = torch.empty((self.n_lights, 6), dtype=torch.float32, device=params.device)
+        self._stream()
+        self._check(self.lib.lt_trace_adjoint_dir(self.h, C.byref(cfg), _ptr(params), int(order), int(samples),
+                                                  _ptr(dOdE), _ptr(grad), _ptr(bin_hist)))
+        return grad
 
     def pt_forward(self, params, cfg, samples_per_texel, S=None, E=None):
         """Object-space path tracing with next-event estimation: (E, S)."""
