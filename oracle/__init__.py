@@ -64,7 +64,7 @@ def _prop(p):
 class _Lights(C.Structure):
     _fields_ = [("type", C.c_void_p), ("lobe_n", C.c_void_p), ("size", C.c_void_p),
                 ("layout_offsets", C.c_void_p), ("n_lights", C.c_int32), ("n_layouts", C.c_int32),
-                ("colour", C.c_void_p)]
+                ("colour", C.c_void_p), ("rotvec", C.c_int32)]
 
 
 _lib = None
@@ -101,6 +101,9 @@ def lib():
         L.or_hsh.restype = C.c_int
         L.or_brdf.argtypes = [C.c_float, C.c_float, C.c_float, P, P, P]
         L.or_brdf.restype = C.c_float
+        L.or_adjoint_rv.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int, P, P]
+        L.or_adjoint_rv.restype = C.c_int64
+        L.or_rotvec.argtypes = [P, P, P]
         L.or_record.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int64,
                                 C.c_int64, P, P, P, P, P]
         L.or_fixed_to_float.argtypes = [P, C.c_int64, P]
@@ -168,7 +171,7 @@ class OracleLights:
     """Luminaire statics; with `colour` ([L,3] channel weights of the flux)
     the tracer runs in colour mode: texel arrays [n_layouts, 3, K]."""
 
-    def __init__(self, lights, colour=None):
+    def __init__(self, lights, colour=None, rotvec: bool = False):
         st = lights.static
         self.type = np.ascontiguousarray(st["type"], np.int32)
         self.lobe = np.ascontiguousarray(st["lobe_n"], np.float32)
@@ -181,6 +184,9 @@ class OracleLights:
         self.colour = None if colour is None else np.ascontiguousarray(colour, np.float32).reshape(self.n_lights, 3)
         if self.colour is not None:
             self.c.colour = self.colour.ctypes.data
+        # orientation as a rotation vector: params [L,7] = x, y, z, theta, P
+        self.rotvec = bool(rotvec)
+        self.c.rotvec = int(self.rotvec)
 
 
 def philox(ctr, key):
@@ -242,6 +248,8 @@ def adjoint(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_lay
     histogram, fills proposal.hist.  Grey mode only (see adjoint_rgb)."""
     if ol.colour is not None:
         raise ValueError("colour mode: use adjoint_rgb")
+    if ol.rotvec:
+        raise ValueError("rotation vectors: use adjoint_rv")
     prm = np.ascontiguousarray(params, np.float32)
     per = osc.n_coef if osc.dir_order >= 0 else 1
     g = np.ascontiguousarray(dOdE, np.float32).reshape(ol.n_layouts, per * osc.n_texels)
@@ -277,8 +285,8 @@ def votes(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layou
     """Gradient-contribution map (Sec. gradVis) of global light `light` and
     parameter `param`: returns (vote [K] float64 over the texels of the
     light's layout, grad [6] float64 of that light, misses)."""
-    if ol.colour is not None:
-        raise ValueError("the contribution map is grey only")
+    if ol.colour is not None or ol.rotvec:
+        raise ValueError("the contribution map takes grey light with tilt angles only")
     prm = np.ascontiguousarray(params, np.float32)
     g = np.ascontiguousarray(dOdE, np.float32).reshape(ol.n_layouts, osc.n_texels)
     vote = np.zeros(osc.n_texels, np.float64)
@@ -296,8 +304,8 @@ def path_trace(osc: OracleScene, ol: OracleLights, params, seed: int, samples_pe
     """Object-space path tracing with next-event estimation: returns
     (S [n_layouts,K] int64, grad [L,6] float64 or None when dOdE is None).
     Grey only."""
-    if ol.colour is not None:
-        raise ValueError("the path tracer is grey only")
+    if ol.colour is not None or ol.rotvec:
+        raise ValueError("the path tracer takes grey light with tilt angles only")
     prm = np.ascontiguousarray(params, np.float32)
     S = np.zeros((ol.n_layouts, osc.n_texels), np.int64)
     g = None if dOdE is None else np.ascontiguousarray(dOdE, np.float32).reshape(ol.n_layouts, osc.n_texels)
@@ -309,10 +317,33 @@ def path_trace(osc: OracleScene, ol: OracleLights, params, seed: int, samples_pe
     return S, grad
 
 
+def adjoint_rv(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,
+               dOdE, n_threads: int = 0):
+    """Rotation-vector orientation (params [L,7] = x, y, z, theta, P):
+    returns (grad [L,7] float64, misses)."""
+    if not ol.rotvec:
+        raise ValueError("build OracleLights with rotvec=True")
+    prm = np.ascontiguousarray(params, np.float32)
+    g = np.ascontiguousarray(dOdE, np.float32).reshape(ol.n_layouts, osc.n_texels)
+    out = np.zeros((ol.n_lights, 7), np.float64)
+    m = lib().or_adjoint_rv(C.byref(osc.c), C.byref(ol.c), prm.ctypes.data, int(seed) & 0xFFFFFFFFFFFFFFFF,
+                            int(paths_per_layout), int(max_hits), int(n_threads), g.ctypes.data, out.ctypes.data)
+    return out, int(m)
+
+
+def rotvec(theta):
+    """The oracle's rotation matrix and exponential-map Jacobian of theta."""
+    th = np.ascontiguousarray(theta, np.float64)
+    R = np.zeros(9)
+    J = np.zeros(9)
+    lib().or_rotvec(th.ctypes.data, R.ctypes.data, J.ctypes.data)
+    return R.reshape(3, 3), J.reshape(3, 3)
+
+
 def record(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,
            layout: int, light: int, first: int, count: int, dOdE=None, proposal: Proposal = None):
-    if ol.colour is not None:
-        raise ValueError("path records are grey only")
+    if ol.colour is not None or ol.rotvec:
+        raise ValueError("path records take grey light with tilt angles only")
     prm = np.ascontiguousarray(params, np.float32)
     prim = np.zeros((count, max_hits), np.int32)
     tex = np.zeros((count, max_hits), np.int32)
@@ -365,9 +396,11 @@ def light_frames(ol: OracleLights, params, paths_per_layout: int):
 
 
 def first_hit_dlog(ol: OracleLights, params, light: int, x1, y, n1, au=0.0, av=0.0):
+    """dlog of the first-hit kernel: [6] (x, y, z, alpha, beta, P), or [7]
+    (x, y, z, world rotation, P) with rotation-vector orientation."""
     prm = np.ascontiguousarray(params, np.float32)
     a = [np.ascontiguousarray(v, np.float32) for v in (x1, y, n1)]
-    out = np.zeros(6, np.float32)
+    out = np.zeros(7 if ol.rotvec else 6, np.float32)
     lib().or_first_hit_dlog(C.byref(ol.c), prm.ctypes.data, int(light), a[0].ctypes.data, a[1].ctypes.data,
                             a[2].ctypes.data, float(au), float(av), out.ctypes.data)
     return out

@@ -38,6 +38,10 @@
  *     with weight pi f; the adjoint adds the first hit's BRDF terms (Eq. dLdp:
  *     its projection and its bounce weight change with the incident
  *     direction while x_1 stays fixed).
+ *   - Orientation as a rotation vector (Sec. 4.4.2, Rodrigues' formula with
+ *     the small-angle form near zero): the first-hit derivative w.r.t. a
+ *     world rotation of the luminaire, mapped to the rotation vector by the
+ *     transposed Jacobian of the exponential map.
  *   - Colour: per-luminaire channel weights of the flux and per-patch channel
  *     albedos; three channel-planar texel arrays per layout, one path
  *     geometry for all channels, and the gradient w.r.t. the channel weights
@@ -256,6 +260,7 @@ typedef struct {
     int32_t n_lights;
     int32_t n_layouts;
     const float* colour;      /* [L,3] channel weights (colour mode: texels [n_layouts,3,K]), or NULL */
+    int32_t rotvec;           /* orientation as a rotation vector: params [L,7] = x, y, z, theta, P */
 } or_lights;
 
 /* Learned emission proposal (beyond the paper, which leaves importance
@@ -490,11 +495,51 @@ typedef struct {
     int64_t n_paths;
     int rgb;               /* colour mode */
     float col[3];          /* channel weights of the flux */
+    int rv;                /* rotation-vector orientation (7 parameters) */
 } olight;
+
+/* Rodrigues' formula R = I + sin(phi)/phi K + (1 - cos(phi))/phi^2 K^2, K = [theta]x,
+ * phi = |theta|, with the linear small-angle form I + K near zero (Sec. 4.4.2). */
+static void rodrigues(const double* th, double R[9])
+{
+    double K[9] = {0, -th[2], th[1], th[2], 0, -th[0], -th[1], th[0], 0};
+    double K2[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) K2[3 * i + j] = K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j] + K[3 * i + 2] * K[6 + j];
+    double f2 = th[0] * th[0] + th[1] * th[1] + th[2] * th[2];
+    double A = 1.0, Bc = 0.0;
+    if (f2 >= 1e-12) {
+        double f = sqrt(f2), sf, cf;
+        or_sincos_f64(f, &sf, &cf);
+        A = sf / f;
+        Bc = (1.0 - cf) / f2;
+    }
+    for (int i = 0; i < 9; ++i) R[i] = ((i % 4 == 0) ? 1.0 : 0.0) + A * K[i] + Bc * K2[i];
+}
+
+/* d theta of a world rotation: R(theta + dtheta) = exp([J dtheta]x) R(theta) with
+ * J = I + (1 - cos phi)/phi^2 K + (phi - sin phi)/phi^3 K^2 (I near zero, where the
+ * small-angle form is used); gradients map as g_theta = J^T g_omega. */
+static void rot_jacobian(const double* th, double J[9])
+{
+    double K[9] = {0, -th[2], th[1], th[2], 0, -th[0], -th[1], th[0], 0};
+    double K2[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) K2[3 * i + j] = K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j] + K[3 * i + 2] * K[6 + j];
+    double f2 = th[0] * th[0] + th[1] * th[1] + th[2] * th[2];
+    double a = 0.0, b = 0.0;
+    if (f2 >= 1e-12) {
+        double f = sqrt(f2), sf, cf;
+        or_sincos_f64(f, &sf, &cf);
+        a = (1.0 - cf) / f2;
+        b = (f - sf) / (f2 * f);
+    }
+    for (int i = 0; i < 9; ++i) J[i] = ((i % 4 == 0) ? 1.0 : 0.0) + a * K[i] + b * K2[i];
+}
 
 static void light_setup(const or_lights* Ls, const float* params, int gl, int64_t n_paths, olight* L)
 {
-    const float* p = params + 6 * gl;
+    const float* p = params + (Ls->rotvec ? 7 : 6) * gl;
     L->type = Ls->type[gl];
     L->n = Ls->lobe_n[gl];
     L->w = Ls->size[2 * gl];
@@ -512,9 +557,22 @@ static void light_setup(const or_lights* Ls, const float* params, int gl, int64_
     L->dt_db[0] = -sb; L->dt_db[1] = 0.0f; L->dt_db[2] = -cb;
     L->db_da[0] = sb * ca; L->db_da[1] = -sa; L->db_da[2] = cb * ca;
     L->db_db[0] = cb * sa; L->db_db[1] = 0.0f; L->db_db[2] = -(sb * sa);
-    L->P = p[5];
+    L->rv = Ls->rotvec != 0;
+    if (L->rv) {
+        /* world frame from the rotation vector: d = R(0,0,-1), t = R e_x, b = R e_y */
+        double th[3] = {(double)p[3], (double)p[4], (double)p[5]}, R[9];
+        rodrigues(th, R);
+        for (int c = 0; c < 3; ++c) {
+            L->d[c] = (float)(-R[3 * c + 2]);
+            L->t[c] = (float)R[3 * c];
+            L->b[c] = (float)R[3 * c + 1];
+            L->dd_da[c] = L->dd_db[c] = L->dt_db[c] = L->db_da[c] = L->db_db[c] = 0.0f;
+        }
+    }
+    const float Pw = p[L->rv ? 6 : 5];
+    L->P = Pw;
     L->n_paths = n_paths;
-    L->phi_r = p[5] / (float)n_paths;
+    L->phi_r = Pw / (float)n_paths;
     L->ci = 1.0f;
     L->co = 0.0f;
     L->rgb = Ls->colour != NULL;
@@ -557,10 +615,12 @@ typedef struct {
 /* dlog of the first-hit irradiance kernel w.r.t. (c, alpha, beta, P), x_1 fixed:
  * log E = log P + n log(d.w) + log(-n1.w) - 2 log r + const, w = (x1 - y)/r. */
 static void first_hit_dlog(const olight* L, const float* x1, const float* y, const float* n1, float au,
-                           float av, float dl[6])
+                           float av, float* dl)
 {
-    for (int c = 0; c < 5; ++c) dl[c] = 0.0f;
-    dl[5] = 1.0f / L->P;
+    /* rotation-vector mode: dl[7] = (position, world-rotation, power) */
+    const int np = L->rv ? 7 : 6;
+    for (int c = 0; c < np - 1; ++c) dl[c] = 0.0f;
+    dl[np - 1] = 1.0f / L->P;
     float v[3] = {x1[0] - y[0], x1[1] - y[1], x1[2] - y[2]};
     float r2 = dot3(v, v);
     if (r2 <= 1e-12f) return;
@@ -596,6 +656,24 @@ static void first_hit_dlog(const olight* L, const float* x1, const float* y, con
         float t2 = (n1[c] + c1 * w[c]) * k1;
         float t3 = w[c] * k3;
         G[c] = (t1 + t2) + t3;
+    }
+    if (L->rv) {
+        /* rotating the luminaire about its centre by d_omega turns d into
+         * d + d_omega x d and moves the origin by d_omega x (y - c):
+         * dlog/d_omega = kd (d x w) + (y - c) x G */
+        float yc[3], dw[3], yg[3];
+        for (int c = 0; c < 3; ++c) yc[c] = L->type == 2 ? au * L->t[c] + av * L->b[c] : 0.0f;
+        dw[0] = L->d[1] * w[2] - L->d[2] * w[1];
+        dw[1] = L->d[2] * w[0] - L->d[0] * w[2];
+        dw[2] = L->d[0] * w[1] - L->d[1] * w[0];
+        yg[0] = yc[1] * G[2] - yc[2] * G[1];
+        yg[1] = yc[2] * G[0] - yc[0] * G[2];
+        yg[2] = yc[0] * G[1] - yc[1] * G[0];
+        for (int c = 0; c < 3; ++c) {
+            dl[c] = G[c];
+            dl[3 + c] = dw[c] * kd + yg[c];
+        }
+        return;
     }
     float ra = dot3(L->dd_da, w) * kd;
     float rb = dot3(L->dd_db, w) * kd;
@@ -773,7 +851,8 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
     int32_t skip = -1;
     float T = 1.0f;
     float s_r = 0.0f;
-    float dphi[6] = {0, 0, 0, 0, 0, 0};
+    float dphi[7] = {0, 0, 0, 0, 0, 0, 0};
+    const int NP = L->rv ? 7 : 6;
     int hits = 0;
     int64_t k1 = -1;
     /* colour mode: channel ch carries flux Phi_r col[ch] and throughput Tc[ch];
@@ -889,9 +968,9 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
                 if (h >= 2) Rd = Rd + P * T2;
                 if (h == 1) {
                     k1 = k;
-                    float dl[6];
+                    float dl[7];
                     first_hit_dlog(L, x, y, no, au, av, dl);
-                    for (int c = 0; c < 6; ++c) dphi[c] = phi_r * dl[c];
+                    for (int c = 0; c < NP; ++c) dphi[c] = phi_r * dl[c];
                     float sq = (inv_np * inv_a);
                     for (int c = 0; c < 3; ++c) Qw[c] = ((ql[0] * sq) * fb1[c] + (ql[1] * sq) * fb2[c]) + (ql[2] * sq) * no[c];
                     float v1[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
@@ -939,9 +1018,9 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
             }
             if (h == 1) {
                 k1 = k;
-                float dl[6];
+                float dl[7];
                 first_hit_dlog(L, x, y, no, au, av, dl);
-                for (int c = 0; c < 6; ++c) dphi[c] = phi_r * dl[c];
+                for (int c = 0; c < NP; ++c) dphi[c] = phi_r * dl[c];
             }
         }
         if (io->rec_prim) {
@@ -994,7 +1073,7 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
             for (int ch = 0; ch < 3; ++ch) io->acc_col[ch] += (double)(sc[ch] * phi_r);
     }
     if (io->g && hits >= 1) {
-        float cr[6];
+        float cr[7];
         float ub_[3] = {0, 0, 0};
         float dya[3] = {0, 0, 0}, dyb[3] = {0, 0, 0};
         if (dirm) {
@@ -1011,11 +1090,11 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
                 }
         }
         float extra[6] = {ub_[0], ub_[1], ub_[2], dot3(ub_, dya), dot3(ub_, dyb), 0.0f};
-        for (int c = 0; c < 6; ++c) {
+        for (int c = 0; c < NP; ++c) {
             cr[c] = s_r * dphi[c];
             if (dirm) cr[c] = cr[c] + phi_r * extra[c];
             if (io->acc) io->acc[c] += (double)cr[c];
-            if (io->contrib) io->contrib[c] = cr[c];
+            if (io->contrib && c < 6) io->contrib[c] = cr[c];
         }
         if (io->vote) {
             /* the path's share of dO/dp_j goes to the texel of its first
@@ -1095,6 +1174,7 @@ EXPORT int64_t or_adjoint(const or_scene* S, const or_lights* Ls, const float* p
 {
     const int64_t stride = (S->dir_order >= 0 ? (S->dir_order + 1) * (S->dir_order + 1) : (Ls->colour ? 3 : 1)) *
                            S->n_texels;
+    if (Ls->rotvec) return -1;   /* or_adjoint_rv */
     int64_t misses = 0;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -1134,6 +1214,58 @@ EXPORT int64_t or_adjoint(const or_scene* S, const or_lights* Ls, const float* p
         }
     }
     return misses;
+}
+
+/* Adjoint light tracing with rotation-vector orientation (Sec. 4.4.2):
+ * params [L,7] = (x, y, z, theta, P); grad_out [L,7] FP64 = dO/d(x, y, z,
+ * theta, P), the per-path world-rotation derivatives mapped through J^T. */
+EXPORT int64_t or_adjoint_rv(const or_scene* S, const or_lights* Ls, const float* params, uint64_t seed,
+                             int64_t paths_per_layout, int max_hits, int n_threads, const float* dOdE,
+                             double* grad_out)
+{
+    if (!Ls->rotvec || Ls->colour || S->dir_order >= 0) return -1;
+    int64_t misses = 0;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+    for (int j = 0; j < Ls->n_layouts; ++j) {
+        int l0 = Ls->layout_offsets[j], l1 = Ls->layout_offsets[j + 1];
+        for (int gl = l0; gl < l1; ++gl) {
+            olight L;
+            int64_t nl = paths_of_light(paths_per_layout, l1 - l0, gl - l0);
+            light_setup(Ls, params, gl, nl, &L);
+            double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0;
+            int64_t m = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : a0, a1, a2, a3, a4, a5, a6, m)
+#endif
+            for (int64_t i = 0; i < nl; ++i) {
+                double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+                path_io io;
+                memset(&io, 0, sizeof(io));
+                io.g = dOdE + (int64_t)j * S->n_texels;
+                io.acc = acc;
+                trace_path(S, &L, j, gl - l0, gl, (uint32_t)i, seed, max_hits, NULL, &io);
+                a0 += acc[0]; a1 += acc[1]; a2 += acc[2]; a3 += acc[3]; a4 += acc[4]; a5 += acc[5]; a6 += acc[6];
+                m += io.misses;
+            }
+            const float* p = params + 7 * gl;
+            double th[3] = {(double)p[3], (double)p[4], (double)p[5]}, J[9];
+            rot_jacobian(th, J);
+            double* g = grad_out + 7 * (int64_t)gl;
+            g[0] = a0; g[1] = a1; g[2] = a2; g[6] = a6;
+            for (int c = 0; c < 3; ++c) g[3 + c] = (J[c] * a3 + J[3 + c] * a4) + J[6 + c] * a5;
+            misses += m;
+        }
+    }
+    return misses;
+}
+
+/* the rotation-vector frame and Jacobian, for the pins */
+EXPORT void or_rotvec(const double* th, double* R, double* J)
+{
+    rodrigues(th, R);
+    rot_jacobian(th, J);
 }
 
 /* Gradient-contribution map of one light gl and one parameter j (Sec.

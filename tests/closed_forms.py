@@ -245,12 +245,15 @@ def plane_direct_coefficients(n_lobe, p, half, res, rho_d, rho_s, e, order, q_te
     return np.einsum("kq,kqc->kc", pdf * wq[None, :] * area, F)          # [K, NC] per unit flux
 
 
-def log_irradiance(kind, n, p, x1, n1, au=0.0, av=0.0, size=None):
+def log_irradiance(kind, n, p, x1, n1, au=0.0, av=0.0, size=None, R=None):
     """log of the first-hit irradiance kernel at receiver x1 with unit normal
     n1 (facing the light), up to p-independent constants: a luminaire of power
     P with direction pdf ~ cos^n about its axis, origin c + a_u t + a_v b."""
     c = np.asarray(p[:3], np.float64)
-    d, t, b = frame(p[3], p[4])
+    if R is None:
+        d, t, b = frame(p[3], p[4])
+    else:       # an explicit frame: axis -R e_z, tangents R e_x, R e_y
+        d, t, b = -R[:, 2], R[:, 0], R[:, 1]
     y = c + au * t + av * b
     v = np.asarray(x1, np.float64) - y
     r = np.linalg.norm(v)

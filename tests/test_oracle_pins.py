@@ -656,6 +656,113 @@ def test_directional_glossy_bounce_gradient(oracle_lib):
         assert abs(D[:, c].mean()) < 4.5 * se[c] + 0.02 * gm[c], (c, D[:, c].mean(), se[c], gm[c])
 
 
+# --------------------------------------------------------------------------
+# orientation as a rotation vector (Rodrigues)
+# --------------------------------------------------------------------------
+
+def test_rotvec_frame_and_jacobian(oracle_lib):
+    """The oracle's Rodrigues matrix equals scipy's rotation of the same
+    vector, and its Jacobian maps a change of theta to the world rotation it
+    causes: R(theta + h e_i) R(theta)^T = exp([h J e_i]x) to first order."""
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(30)
+    for th in [np.array([0.3, -0.2, 0.5]), rng.normal(size=3) * 1.2, np.array([2.5, 0.1, -0.4])]:
+        R, J = oracle_lib.rotvec(th)
+        assert np.allclose(R, Rotation.from_rotvec(th).as_matrix(), atol=1e-12)
+        for i in range(3):
+            h = 1e-6
+            tp, tm = th.copy(), th.copy()
+            tp[i] += h
+            tm[i] -= h
+            dw = (Rotation.from_rotvec(tp) * Rotation.from_rotvec(tm).inv()).as_rotvec() / (2 * h)
+            assert np.allclose(dw, J[:, i], atol=1e-7), (th, i, dw, J[:, i])
+    R0, J0 = oracle_lib.rotvec(np.zeros(3))
+    assert np.array_equal(R0, np.eye(3)) and np.array_equal(J0, np.eye(3))
+
+
+@pytest.mark.parametrize("kind", [SPOT, RECT, SOFT])
+def test_rotvec_first_hit_derivative(oracle_lib, kind):
+    """dlog of the first-hit kernel w.r.t. the rotation vector (the world
+    rotation terms mapped by J^T) vs central differences of an independent
+    log-irradiance whose frame comes from scipy's rotation of theta."""
+    from scipy.spatial.transform import Rotation
+    rng = np.random.default_rng(40 + kind)
+    n = {SPOT: 3.5, RECT: 1.5}.get(kind, 0.0)
+    size = {RECT: (0.6, 0.4), SOFT: (0.0, 1.2)}.get(kind, (0, 0))
+    done = 0
+    while done < 20:
+        th = rng.normal(size=3) * 0.3      # tilts the default axis -z
+        p7 = np.array([rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(1.5, 2.5), *th, rng.uniform(10, 100)])
+        lights = make_lights([kind], [n], [size], [0], [p7[:6]])
+        ol = oracle_lib.OracleLights(lights, rotvec=True)
+        x1 = np.array([rng.uniform(-1.5, 1.5), rng.uniform(-1.5, 1.5), 0.0])
+        n1 = np.array([0.0, 0.0, 1.0])
+        au = rng.uniform(-0.5, 0.5) * size[0] if kind == RECT else 0.0
+        av = rng.uniform(-0.5, 0.5) * size[1] if kind == RECT else 0.0
+        R = Rotation.from_rotvec(p7[3:6]).as_matrix()
+        d, t, b = -R[:, 2], R[:, 0], R[:, 1]
+        y = p7[:3] + au * t + av * b
+        cw = float(np.dot(d, (x1 - y) / np.linalg.norm(x1 - y)))
+        if cw < 0.2:
+            continue
+        done += 1
+        pp7 = p7.astype(np.float32)[None]
+        dl = oracle_lib.first_hit_dlog(ol, pp7, 0, x1.astype(np.float32), y.astype(np.float32),
+                                       n1.astype(np.float32), au, av).astype(np.float64)
+        _, J = oracle_lib.rotvec(pp7[0, 3:6].astype(np.float64))
+        dth = J.T @ dl[3:6]
+        pf = pp7[0].astype(np.float64)
+
+        def logE(q):
+            Rq = Rotation.from_rotvec(q[3:6]).as_matrix()
+            return cf.log_irradiance(kind, n, [q[0], q[1], q[2], 0.0, 0.0, q[6]], x1, n1, au, av, size, R=Rq)
+
+        for c in range(7):
+            h = 1e-6 * max(1.0, abs(pf[c]))
+            qp, qm = pf.copy(), pf.copy()
+            qp[c] += h
+            qm[c] -= h
+            fd = (logE(qp) - logE(qm)) / (2 * h)
+            got = dth[c - 3] if 3 <= c < 6 else dl[c]
+            assert abs(got - fd) <= 3e-4 * (abs(fd) + 1.0), (kind, c, got, fd)
+
+
+def test_rotvec_agrees_with_tilt_angles(oracle_lib):
+    """The same frame given as tilt angles and as a rotation vector traces
+    the same paths: equal texels, and the tilt derivatives are the world-
+    rotation gradient along the rotations the tilts generate (R_y(beta) e_x
+    for alpha, e_y for beta)."""
+    from scipy.spatial.transform import Rotation
+    c1 = li.box_room()
+    sc = c1["scene"]
+    p6 = np.array([[1.2, 1.0, 2.1, 0.25, -0.2, 40.0], [2.8, 1.9, 2.3, -0.1, 0.3, 60.0]], np.float32)
+    lights = make_lights([SPOT, RECT], [3.0, 1.0], [(0, 0), (0.5, 0.3)], [0, 0], p6)
+    p7 = np.zeros((2, 7), np.float32)
+    for l in range(2):
+        R = cf.rot_y(float(p6[l, 4])) @ cf.rot_x(float(p6[l, 3]))
+        p7[l, :3] = p6[l, :3]
+        p7[l, 3:6] = Rotation.from_matrix(R).as_rotvec()
+        p7[l, 6] = p6[l, 5]
+    osc = oracle_lib.OracleScene(sc)
+    ol6, ol7 = oracle_lib.OracleLights(lights), oracle_lib.OracleLights(lights, rotvec=True)
+    N, B, seed = 1 << 16, 3, 0x7E
+    S6, _ = oracle_lib.forward(osc, ol6, p6, seed, N, B)
+    S7, _ = oracle_lib.forward(osc, ol7, p7, seed, N, B)
+    E6, E7 = oracle_lib.fixed_to_float(S6), oracle_lib.fixed_to_float(S7)
+    assert np.linalg.norm(E7 - E6) <= 1e-4 * np.linalg.norm(E6)
+    g = np.random.default_rng(5).normal(size=(1, sc.n_texels)).astype(np.float32)
+    G6, _ = oracle_lib.adjoint(osc, ol6, p6, seed, N, B, g)
+    G7, _ = oracle_lib.adjoint_rv(osc, ol7, p7, seed, N, B, g)
+    scale = np.abs(G6).max()
+    assert np.allclose(G7[:, :3], G6[:, :3], atol=2e-3 * scale) and np.allclose(G7[:, 6], G6[:, 5], rtol=1e-3)
+    for l in range(2):
+        _, J = oracle_lib.rotvec(p7[l, 3:6].astype(np.float64))
+        gw = np.linalg.solve(J.T, G7[l, 3:6])
+        ax_a = cf.rot_y(float(p6[l, 4])) @ np.array([1.0, 0, 0])
+        assert abs(gw @ ax_a - G6[l, 3]) <= 2e-3 * scale, (l, gw @ ax_a, G6[l, 3])
+        assert abs(gw[1] - G6[l, 4]) <= 2e-3 * scale, (l, gw[1], G6[l, 4])
+
+
 def test_cosine_bounce_floor_to_ceiling(oracle_lib):
     """Second hits on a parallel ceiling: floor first-hit density times the
     differential form factor to each ceiling texel (cosine-weighted bounce, rho)."""
