@@ -223,6 +223,20 @@ int lt_trace_adjoint_rgb(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_pa
  * depend on the incident direction, which moves with the luminaire while
  * x_1 stays fixed (Eq. dLdp).  order 0..2, samples 1..64, box basis, grey. */
 int lt_set_glossy(lt_ctx* ctx, const float* h_glossy);
+
+/* Orientation as a rotation vector (Sec. 4.4.2): d_params [L,7] = (x, y, z,
+ * theta_x, theta_y, theta_z, P); the luminaire frame is R(theta) applied to
+ * the default frame (axis -z, tangents +x, +y), R by Rodrigues' formula
+ * (the linear small-angle form I + [theta]x below |theta| = 1e-6).  The
+ * adjoint differentiates each path's first-hit kernel w.r.t. a world
+ * rotation of the luminaire about its centre and maps the per-luminaire sum
+ * to theta with the transposed Jacobian of the exponential map; d_grad
+ * [L,7].  A rectangle's roll about its normal is a free direction here,
+ * which the two tilt angles cannot express.  Plain emission and the box
+ * basis only (LT_FLAG_PROPOSAL and LT_FLAG_LINEAR are refused); grey. */
+int lt_trace_forward_rv(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, int64_t* d_S, float* d_E);
+int lt_trace_adjoint_rv(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, const float* d_dOdE,
+                        float* d_grad);
 int lt_trace_forward_dir(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, int32_t order, int32_t samples,
                          int64_t* d_S, float* d_E);
 int lt_trace_adjoint_dir(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, int32_t order, int32_t samples,

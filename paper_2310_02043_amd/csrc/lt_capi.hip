@@ -81,6 +81,8 @@ struct lt_ctx {
     size_t ptgrad_cap = 0;
     double* d_partials_col = nullptr; // colour adjoint: [n_tiles,3] partial sums of dO/dc
     size_t partials_col_cap = 0;
+    double* d_partials7 = nullptr;    // rotation-vector adjoint: [n_tiles,7] partial sums
+    size_t partials7_cap = 0;
 
     lt_tuning tune;
     std::vector<GraphEntry> graphs;
@@ -421,7 +423,7 @@ void lt_destroy(lt_ctx* c)
     hipFree(c->prop_pdf); hipFree(c->prop_cdf); hipFree(c->prop_guide); hipFree(c->inv_sigma); hipFree(c->mlp_scratch);
     hipFree(c->d_misses); hipFree(c->d_flags); hipFree(c->d_stats);
     hipFree(c->d_objpart); hipFree(c->d_partials); hipFree(c->d_gstack); hipFree(c->d_ptgrad);
-    hipFree(c->d_partials_col);
+    hipFree(c->d_partials_col); hipFree(c->d_partials7);
     if (c->ev_in) hipEventDestroy(c->ev_in);
     if (c->ev_out) hipEventDestroy(c->ev_out);
     if (c->gstream) hipStreamDestroy(c->gstream);
@@ -803,6 +805,68 @@ int lt_trace_adjoint_rgb(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_para
     };
     return run_seq(c, graph, make_key(c, 6, cfg, {d_params, d_colour, d_dOdE, d_grad, d_grad_colour, d_bin_hist}),
                    body);
+}
+
+int lt_trace_forward_rv(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int64_t* d_S, float* d_E)
+{
+    int rc = check_cfg(c, cfg);
+    if (rc) return rc;
+    if (!d_params || !d_S || !d_E) return fail(c, LT_EINVAL, "NULL device buffer");
+    if (cfg->flags & (LT_FLAG_PROPOSAL | LT_FLAG_LINEAR))
+        return fail(c, LT_EINVAL, "rotation vectors take the plain emission and the box basis only");
+    if (((uintptr_t)d_S & 15) || ((uintptr_t)d_E & 7) || ((uintptr_t)d_params & 3))
+        return fail(c, LT_EINVAL, "d_S must be 16-byte and d_E 8-byte aligned");
+    HIPCHK(c, hipSetDevice(c->device));
+    const long long blocks = trace_blocks(c);
+    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    if (rc) return rc;
+    TraceArgs a = trace_args(c, cfg);
+    a.S = (long long*)d_S;
+    const long long n = c->K * c->n_layouts;
+    const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
+    auto body = [&](hipStream_t st) -> hipError_t {
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st, 1);
+        if (e == hipSuccess) e = launch_clear(a.S, n, st);
+        if (e == hipSuccess) e = timed_trace(c, false, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = launch_finalize(a.S, d_E, n, c->d_flags, st);
+        return e;
+    };
+    return run_seq(c, graph, make_key(c, 9, cfg, {d_params, d_S, d_E}), body);
+}
+
+int lt_trace_adjoint_rv(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, const float* d_dOdE, float* d_grad)
+{
+    int rc = check_cfg(c, cfg);
+    if (rc) return rc;
+    if (!d_params || !d_dOdE || !d_grad) return fail(c, LT_EINVAL, "NULL device buffer");
+    if (cfg->flags & (LT_FLAG_PROPOSAL | LT_FLAG_LINEAR))
+        return fail(c, LT_EINVAL, "rotation vectors take the plain emission and the box basis only");
+    HIPCHK(c, hipSetDevice(c->device));
+    const long long blocks = trace_blocks(c);
+    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    if (rc) return rc;
+    const size_t need = (size_t)std::max(c->n_tiles, 1) * 7;
+    if (c->partials7_cap < need) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        free_graphs(c);
+        hipFree(c->d_partials7);
+        c->d_partials7 = nullptr;
+        c->partials7_cap = 0;
+        HIPCHK(c, hipMalloc(&c->d_partials7, sizeof(double) * need));
+        c->partials7_cap = need;
+    }
+    TraceArgs a = trace_args(c, cfg);
+    a.g = d_dOdE;
+    a.partials = c->d_partials7;
+    a.rotvec = 1;
+    const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
+    auto body = [&](hipStream_t st) -> hipError_t {
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st, 1);
+        if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = launch_grad_reduce_rv(c->d_partials7, c->d_range, d_params, c->L, d_grad, st);
+        return e;
+    };
+    return run_seq(c, graph, make_key(c, 10, cfg, {d_params, d_dOdE, d_grad}), body);
 }
 
 int lt_set_glossy(lt_ctx* c, const float* h_glossy)

@@ -55,6 +55,8 @@ struct TraceArgs {
     float alpha_plain;
     float* bin_hist;            // adjoint: [L,1024] histogram of |c_r / sigma| (may be null)
     const float* inv_sigma;     // [L,6]
+    // orientation as a rotation vector (adjoint: [n_tiles,7] partials)
+    int rotvec;
     // directional texels: HSH order 0..2 (-1: irradiance texels), local
     // samples per hit, [P] per-patch (specular albedo, Phong exponent)
     int dir_order;
@@ -127,7 +129,9 @@ hipError_t launch_trace(bool adjoint, bool stats, const TraceArgs& a, int waves_
                         int blocks, hipStream_t st);
 hipError_t launch_record(const RecordArgs& a, int lds_depth, hipStream_t st);
 hipError_t launch_light_setup(const float* params, const int4* lstat_i, const float4* lstat_f,
-                              const long long* npaths, int n_lights, DevLight* out, hipStream_t st);
+                              const long long* npaths, int n_lights, DevLight* out, hipStream_t st, int rv = 0);
+hipError_t launch_grad_reduce_rv(const double* partials, const int2* range, const float* params, int n_lights,
+                                 float* grad, hipStream_t st);
 hipError_t launch_clear(long long* S, long long n_texels_total, hipStream_t st);
 hipError_t launch_fill_f32(float* p, long long n, float v, hipStream_t st);
 hipError_t launch_pt(bool adjoint, const PtArgs& a, int lds_depth, hipStream_t st);

@@ -330,11 +330,15 @@ __device__ __forceinline__ V3 bounce_dir(V3 no, uint32_t pid, uint32_t stream_id
 // dlog of the first-hit irradiance kernel w.r.t. (c, alpha, beta, P) with x_1
 // fixed (Sec. 4.3 constant sample; Eq. posDeriv generalised to a cos^n lobe,
 // plus the rotation terms and the area-light origin shift of the supplement).
+// RV: orientation as a rotation vector, dl[7] = (position, derivative w.r.t.
+// a world rotation of the luminaire about its centre, power).
+template <bool RV = false>
 __device__ __forceinline__ void first_hit_dlog(const DevLight& L, V3 x1, V3 y, V3 n1, float au, float av,
-                                               float dl[6])
+                                               float* dl)
 {
-    for (int c = 0; c < 5; ++c) dl[c] = 0.0f;
-    dl[5] = 1.0f / L.P;
+    constexpr int NPAR = RV ? 7 : 6;
+    for (int c = 0; c < NPAR - 1; ++c) dl[c] = 0.0f;
+    dl[NPAR - 1] = 1.0f / L.P;
     const V3 v = sub(x1, y);
     const float r2 = dot(v, v);
     if (r2 <= 1e-12f) return;
@@ -368,6 +372,21 @@ __device__ __forceinline__ void first_hit_dlog(const DevLight& L, V3 x1, V3 y, V
     const V3 G = v3((-((d.x - ce * w.x) * ka) + (n1.x + c1 * w.x) * k1) + w.x * k3,
                     (-((d.y - ce * w.y) * ka) + (n1.y + c1 * w.y) * k1) + w.y * k3,
                     (-((d.z - ce * w.z) * ka) + (n1.z + c1 * w.z) * k1) + w.z * k3);
+    if (RV) {
+        // rotating by d_omega turns d into d + d_omega x d and moves the
+        // origin by d_omega x (y - c): dlog/d_omega = kd (d x w) + (y - c) x G
+        const V3 yc = L.type == 2 ? v3(au * L.t[0] + av * L.b[0], au * L.t[1] + av * L.b[1], au * L.t[2] + av * L.b[2])
+                                  : v3(0.0f, 0.0f, 0.0f);
+        const V3 dw = v3(d.y * w.z - d.z * w.y, d.z * w.x - d.x * w.z, d.x * w.y - d.y * w.x);
+        const V3 yg = v3(yc.y * G.z - yc.z * G.y, yc.z * G.x - yc.x * G.z, yc.x * G.y - yc.y * G.x);
+        dl[0] = G.x;
+        dl[1] = G.y;
+        dl[2] = G.z;
+        dl[3] = dw.x * kd + yg.x;
+        dl[4] = dw.y * kd + yg.y;
+        dl[5] = dw.z * kd + yg.z;
+        return;
+    }
     float ra = dot(v3(L.dd_da[0], L.dd_da[1], L.dd_da[2]), w) * kd;
     float rb = dot(v3(L.dd_db[0], L.dd_db[1], L.dd_db[2]), w) * kd;
     if (L.type == 2) {
@@ -550,7 +569,8 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
     __shared__ int s_stack[WPB * LDS_D * 64];
     // adjoint per-lane state read once per path (first-hit derivative
     // factors, running contribution sums), kept in LDS instead of registers
-    __shared__ float s_adj[ADJ ? WPB * 12 * 64 : 1];
+    constexpr int NPAR = MODE == 4 ? 7 : 6;   // 4: rotation-vector orientation
+    __shared__ float s_adj[ADJ ? WPB * 2 * NPAR * 64 : 1];
     // adjoint with a gradient-contribution map: texel of the first hit
     __shared__ int s_k1[ADJ ? WPB * 64 : 1];
     // colour: per lane T_g, T_b, s_g, s_b and the three channel-weight sums
@@ -559,7 +579,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
     __shared__ float s_dir[(MODE == 3 && ADJ) ? WPB * 12 * 64 : 1];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
-    float* adj = s_adj + (ADJ ? wib * 12 * 64 + lane : 0);
+    float* adj = s_adj + (ADJ ? wib * 2 * NPAR * 64 + lane : 0);
     int* k1 = s_k1 + (ADJ ? wib * 64 + lane : 0);
     float* rgbs = s_rgb + (MODE == 2 ? wib * 8 * 64 + lane : 0);
     float* dst = s_dir + ((MODE == 3 && ADJ) ? wib * 12 * 64 + lane : 0);
@@ -605,7 +625,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
         float T = 1.0f, s_r = 0.0f, au = 0.0f, av = 0.0f, phi_r = 0.0f, wq = 0.0f;
         if (ADJ) {
 #pragma unroll
-            for (int c = 0; c < 12; ++c) adj[c * 64] = 0.0f;
+            for (int c = 0; c < 2 * NPAR; ++c) adj[c * 64] = 0.0f;
         }
         unsigned miss = 0, n_seg = 0, n_nodes = 0, n_tris = 0, n_hits = 0;
         unsigned n_iter = 0, n_active = 0, n_phase = 0;   // wave-uniform counters
@@ -808,10 +828,10 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                             rgbs[192] = rgbs[192] + (g[2 * a.K + hi.k] * hi.inva) * rgbs[64];
                         }
                         if (h == 1) {
-                            float dl[6];
-                            first_hit_dlog(L, hi.x, v3(r.ox, r.oy, r.oz), hi.no, au, av, dl);
+                            float dl[NPAR];
+                            first_hit_dlog<MODE == 4>(L, hi.x, v3(r.ox, r.oy, r.oz), hi.no, au, av, dl);
 #pragma unroll
-                            for (int c = 0; c < 6; ++c) adj[c * 64] = phi_r * dl[c];
+                            for (int c = 0; c < NPAR; ++c) adj[c * 64] = phi_r * dl[c];
                             if (vote) *k1 = (int)hi.k;
                         }
                     }
@@ -886,11 +906,11 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                         }
                         float m2 = 0.0f;
 #pragma unroll
-                        for (int c = 0; c < 6; ++c) {
+                        for (int c = 0; c < NPAR; ++c) {
                             float cr = se * adj[c * 64];
-                            if (MODE == 3) cr = cr + phi_r * ext[c];
-                            adj[(6 + c) * 64] += cr;
-                            if (hist) {
+                            if (MODE == 3) cr = cr + phi_r * ext[c < 6 ? c : 0];
+                            adj[(NPAR + c) * 64] += cr;
+                            if (hist && c < 6) {
                                 const float z = cr * a.inv_sigma[6 * ti.x + c];
                                 m2 = m2 + z * z;
                             }
@@ -908,12 +928,12 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
             }
         }
         if (ADJ) {
-            double acc[6];
+            double acc[NPAR];
 #pragma unroll
-            for (int c = 0; c < 6; ++c) acc[c] = wave_sum((double)adj[(6 + c) * 64]);
+            for (int c = 0; c < NPAR; ++c) acc[c] = wave_sum((double)adj[(NPAR + c) * 64]);
             if (lane == 0) {
 #pragma unroll
-                for (int c = 0; c < 6; ++c) a.partials[(long long)tile * 6 + c] = acc[c];
+                for (int c = 0; c < NPAR; ++c) a.partials[(long long)tile * NPAR + c] = acc[c];
             }
             if (MODE == 2) {
                 double accc[3];
@@ -1202,13 +1222,52 @@ __global__ void k_f64_to_f32(const double* __restrict__ in, float* __restrict__ 
 
 // Luminaire setup: frame R = R_y(beta) R_x(alpha), derivatives, Phi_r = P/N_l.
 // lstat_i = (type, layout, l_local, -), lstat_f = (n, w, h, N_l as float bits unused).
+// Rodrigues' formula in FP64, R = I + sin(phi)/phi K + (1 - cos(phi))/phi^2 K^2,
+// K = [theta]x, with the linear small-angle form I + K near zero (Sec. 4.4.2).
+__device__ void rodrigues_f64(const double th[3], double R[9])
+{
+    const double K[9] = {0, -th[2], th[1], th[2], 0, -th[0], -th[1], th[0], 0};
+    double K2[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) K2[3 * i + j] = K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j] + K[3 * i + 2] * K[6 + j];
+    const double f2 = th[0] * th[0] + th[1] * th[1] + th[2] * th[2];
+    double A = 1.0, Bc = 0.0;
+    if (f2 >= 1e-12) {
+        const double f = __builtin_sqrt(f2);
+        double sf, cf;
+        sincos_f64(f, sf, cf);
+        A = sf / f;
+        Bc = (1.0 - cf) / f2;
+    }
+    for (int i = 0; i < 9; ++i) R[i] = ((i % 4 == 0) ? 1.0 : 0.0) + A * K[i] + Bc * K2[i];
+}
+
+// Jacobian of the exponential map: R(theta + dtheta) = exp([J dtheta]x) R(theta)
+__device__ void rot_jacobian_f64(const double th[3], double J[9])
+{
+    const double K[9] = {0, -th[2], th[1], th[2], 0, -th[0], -th[1], th[0], 0};
+    double K2[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) K2[3 * i + j] = K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j] + K[3 * i + 2] * K[6 + j];
+    const double f2 = th[0] * th[0] + th[1] * th[1] + th[2] * th[2];
+    double a = 0.0, b = 0.0;
+    if (f2 >= 1e-12) {
+        const double f = __builtin_sqrt(f2);
+        double sf, cf;
+        sincos_f64(f, sf, cf);
+        a = (1.0 - cf) / f2;
+        b = (f - sf) / (f2 * f);
+    }
+    for (int i = 0; i < 9; ++i) J[i] = ((i % 4 == 0) ? 1.0 : 0.0) + a * K[i] + b * K2[i];
+}
+
 __global__ void k_light_setup(const float* __restrict__ params, const int4* __restrict__ si,
                               const float4* __restrict__ sf, const long long* __restrict__ npaths, int n,
-                              DevLight* __restrict__ out)
+                              DevLight* __restrict__ out, int rv)
 {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= n) return;
-    const float* p = params + 6 * l;
+    const float* p = params + (rv ? 7 : 6) * l;
     double sa_d, ca_d, sb_d, cb_d;
     sincos_f64((double)p[3], sa_d, ca_d);
     sincos_f64((double)p[4], sb_d, cb_d);
@@ -1226,9 +1285,22 @@ __global__ void k_light_setup(const float* __restrict__ params, const int4* __re
     const int4 i4 = si[l];
     const float4 f4 = sf[l];
     const long long nl = npaths[l];
-    L.P = p[5];
+    if (rv) {
+        // world frame from the rotation vector: d = R(0,0,-1), t = R e_x, b = R e_y
+        const double th[3] = {(double)p[3], (double)p[4], (double)p[5]};
+        double R[9];
+        rodrigues_f64(th, R);
+        for (int c = 0; c < 3; ++c) {
+            L.d[c] = (float)(-R[3 * c + 2]);
+            L.t[c] = (float)R[3 * c];
+            L.b[c] = (float)R[3 * c + 1];
+            L.dd_da[c] = L.dd_db[c] = L.dt_db[c] = L.db_da[c] = L.db_db[c] = 0.0f;
+        }
+    }
+    const float Pw = p[rv ? 6 : 5];
+    L.P = Pw;
     L.n_paths = nl;
-    L.phi_r = p[5] / (float)nl;
+    L.phi_r = Pw / (float)nl;
     L.n = f4.x;
     L.w = f4.y;
     L.h = f4.z;
@@ -1378,7 +1450,12 @@ inline int nblocks(long long n, int b, int cap)
 template <bool ADJ, bool STATS, int WPB>
 hipError_t launch_wpb(const TraceArgs& a, int lds_depth, int blocks, hipStream_t st)
 {
-    if (a.dir_order >= 0 && !STATS) {
+    if (a.rotvec && ADJ) {
+        if (lds_depth == 16)
+            k_trace<ADJ, STATS, WPB, 16, 4><<<blocks, WPB * 64, 0, st>>>(a);
+        else
+            k_trace<ADJ, STATS, WPB, 32, 4><<<blocks, WPB * 64, 0, st>>>(a);
+    } else if (a.dir_order >= 0 && !STATS) {
         if (lds_depth == 16)
             k_trace<ADJ, STATS, WPB, 16, 3><<<blocks, WPB * 64, 0, st>>>(a);
         else
@@ -1452,9 +1529,42 @@ hipError_t launch_record(const RecordArgs& a, int lds_depth, hipStream_t st)
 }
 
 hipError_t launch_light_setup(const float* params, const int4* si, const float4* sf, const long long* npaths,
-                              int n_lights, DevLight* out, hipStream_t st)
+                              int n_lights, DevLight* out, hipStream_t st, int rv)
 {
-    k_light_setup<<<nblocks(n_lights, 64, 1 << 20), 64, 0, st>>>(params, si, sf, npaths, n_lights, out);
+    k_light_setup<<<nblocks(n_lights, 64, 1 << 20), 64, 0, st>>>(params, si, sf, npaths, n_lights, out, rv);
+    return hipGetLastError();
+}
+
+// per light: the seven partial sums of its tiles (FP64), the world-rotation
+// components mapped to the rotation vector by J^T, written as f32
+__global__ void __launch_bounds__(64) k_grad_reduce_rv(const double* __restrict__ partials,
+                                                       const int2* __restrict__ range, const float* __restrict__ params,
+                                                       int n_lights, float* __restrict__ grad)
+{
+    const int l = blockIdx.x;
+    if (l >= n_lights) return;
+    const int2 rg = range[l];
+    double acc[7];
+    for (int c = 0; c < 7; ++c) acc[c] = 0.0;
+    for (int t = rg.x + (int)threadIdx.x; t < rg.y; t += 64)
+        for (int c = 0; c < 7; ++c) acc[c] += partials[(long long)t * 7 + c];
+    for (int c = 0; c < 7; ++c) acc[c] = wave_sum(acc[c]);
+    if (threadIdx.x == 0) {
+        const double th[3] = {(double)params[7 * l + 3], (double)params[7 * l + 4], (double)params[7 * l + 5]};
+        double J[9];
+        rot_jacobian_f64(th, J);
+        grad[7 * l + 0] = (float)acc[0];
+        grad[7 * l + 1] = (float)acc[1];
+        grad[7 * l + 2] = (float)acc[2];
+        for (int c = 0; c < 3; ++c) grad[7 * l + 3 + c] = (float)((J[c] * acc[3] + J[3 + c] * acc[4]) + J[6 + c] * acc[5]);
+        grad[7 * l + 6] = (float)acc[6];
+    }
+}
+
+hipError_t launch_grad_reduce_rv(const double* partials, const int2* range, const float* params, int n_lights,
+                                 float* grad, hipStream_t st)
+{
+    k_grad_reduce_rv<<<n_lights, 64, 0, st>>>(partials, range, params, n_lights, grad);
     return hipGetLastError();
 }
 

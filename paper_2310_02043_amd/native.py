@@ -22,7 +22,7 @@ EXPORTED = [
     "lt_create", "lt_destroy", "lt_last_error", "lt_set_stream", "lt_sync", "lt_scene_upload",
     "lt_set_lights", "lt_trace_forward", "lt_objective", "lt_trace_adjoint", "lt_gradient_votes",
     "lt_pt_forward", "lt_pt_adjoint", "lt_set_albedo_rgb", "lt_trace_forward_rgb", "lt_trace_adjoint_rgb",
-    "lt_set_glossy", "lt_trace_forward_dir", "lt_trace_adjoint_dir",
+    "lt_set_glossy", "lt_trace_forward_dir", "lt_trace_adjoint_dir", "lt_trace_forward_rv", "lt_trace_adjoint_rv",
     "lt_record_paths",
     "lt_trace_stats", "lt_get_tuning", "lt_set_tuning", "lt_autotune", "lt_info_get", "lt_set_timing",
     "lt_timing_read", "lt_proposal_set_table", "lt_proposal_get_table", "lt_proposal_set_scale",
@@ -90,6 +90,8 @@ def load():
     L.lt_pt_forward.argtypes = [P, C.POINTER(TraceCfg), P, I32, P, P]
     L.lt_set_albedo_rgb.argtypes = [P, P]
     L.lt_set_glossy.argtypes = [P, P]
+    L.lt_trace_forward_rv.argtypes = [P, C.POINTER(TraceCfg), P, P, P]
+    L.lt_trace_adjoint_rv.argtypes = [P, C.POINTER(TraceCfg), P, P, P]
     L.lt_trace_forward_dir.argtypes = [P, C.POINTER(TraceCfg), P, I32, I32, P, P]
     L.lt_trace_adjoint_dir.argtypes = [P, C.POINTER(TraceCfg), P, I32, I32, P, P, P]
     L.lt_trace_forward_rgb.argtypes = [P, C.POINTER(TraceCfg), P, P, P, P]
@@ -291,6 +293,33 @@ class Context:
         self._check(self.lib.lt_trace_adjoint_rgb(self.h, C.byref(cfg), _ptr(params), _ptr(colour), _ptr(dOdE),
                                                   _ptr(grad), _ptr(grad_colour), _ptr(bin_hist)))
         return grad, grad_colour
+
+    def trace_forward_rv(self, params, cfg, S=None, E=None):
+        """Rotation-vector orientation, params [L,7] = (x, y, z, theta, P): (E, S)."""
+        torch = self._torch
+        n = (self.n_layouts, self.n_texels)
+        self._dev(params, torch.float32, (self.n_lights, 7))
+        if S is None:
+            S = torch.empty(n, dtype=torch.int64, device=params.device)
+        if E is None:
+            E = torch.empty(n, dtype=torch.float32, device=params.device)
+        self._dev(S, torch.int64, n)
+        self._dev(E, torch.float32, n)
+        self._stream()
+        self._check(self.lib.lt_trace_forward_rv(self.h, C.byref(cfg), _ptr(params), _ptr(S), _ptr(E)))
+        return E, S
+
+    def trace_adjoint_rv(self, params, dOdE, cfg, grad=None):
+        """Rotation-vector adjoint: dO/d(x, y, z, theta, P) [L,7]."""
+        torch = self._torch
+        self._dev(params, torch.float32, (self.n_lights, 7))
+        self._dev(dOdE, torch.float32, (self.n_layouts, self.n_texels))
+        if grad is None:
+            grad = torch.empty((self.n_lights, 7), dtype=torch.float32, device=params.device)
+        self._dev(grad, torch.float32, (self.n_lights, 7))
+        self._stream()
+        self._check(self.lib.lt_trace_adjoint_rv(self.h, C.byref(cfg), _ptr(params), _ptr(dOdE), _ptr(grad)))
+        return grad
 
     def set_glossy(self, glossy):
         """Per-patch (specular albedo, Phong exponent) [n_patches,2] for the
