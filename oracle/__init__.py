@@ -101,6 +101,8 @@ def lib():
         L.or_hsh.restype = C.c_int
         L.or_brdf.argtypes = [C.c_float, C.c_float, C.c_float, P, P, P]
         L.or_brdf.restype = C.c_float
+        L.or_tangent.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int, P]
+        L.or_tangent.restype = C.c_int64
         L.or_adjoint_rv.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int, P, P]
         L.or_adjoint_rv.restype = C.c_int64
         L.or_rotvec.argtypes = [P, P, P]
@@ -329,6 +331,21 @@ def adjoint_rv(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_
     m = lib().or_adjoint_rv(C.byref(osc.c), C.byref(ol.c), prm.ctypes.data, int(seed) & 0xFFFFFFFFFFFFFFFF,
                             int(paths_per_layout), int(max_hits), int(n_threads), g.ctypes.data, out.ctypes.data)
     return out, int(m)
+
+
+def tangent(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,
+            light: int, param: int, n_threads: int = 0):
+    """Direct-differentiation map of global light `light` and parameter
+    `param`: dE_k/dp_j [K] int64 Q31.32 over the texels of its layout."""
+    if ol.colour is not None or ol.rotvec or osc.dir_order >= 0:
+        raise ValueError("the direct-differentiation map takes grey light, tilt angles, irradiance texels")
+    if not (0 <= light < ol.n_lights and 0 <= param < 6):
+        raise ValueError("light or parameter out of range")
+    prm = np.ascontiguousarray(params, np.float32)
+    T = np.zeros(osc.n_texels, np.int64)
+    lib().or_tangent(C.byref(osc.c), C.byref(ol.c), prm.ctypes.data, int(seed) & 0xFFFFFFFFFFFFFFFF,
+                     int(paths_per_layout), int(max_hits), int(n_threads), int(light), int(param), T.ctypes.data)
+    return T
 
 
 def rotvec(theta):

@@ -51,6 +51,8 @@
  *     outer cone, directions uniform over the outer cap, weighted).
  *   - Object-space path tracing with next-event estimation (the comparison
  *     estimator of Sec. 6) on the same texels, and its gradient.
+ *   - Direct-differentiation map, the comparison beside it: dE_k/dp_j with
+ *     the first hits held fixed, splatted at every hit.
  *   - Gradient-contribution map (Sec. gradVis): the same adjoint pass over
  *     one light's paths, each path adding its contribution to dO/dp_j into
  *     the texel of its first surface hit.
@@ -606,6 +608,8 @@ typedef struct {
     double* acc_col;       /* adjoint, colour mode: gradient w.r.t. the channel weights [3] */
     float* contrib;        /* record: per-path contribution [6] (or NULL) */
     double* vote;          /* votes: per-texel map of one parameter's contributions (or NULL) */
+    int64_t* tangent;      /* direct differentiation: dE_k/dp_j splats of this layout (or NULL) */
+    int tangent_param;
     int vote_param;        /* votes: which of the six parameters */
     int32_t* rec_prim;     /* record: [B] (or NULL) */
     int32_t* rec_texel;    /* record: [B] */
@@ -853,6 +857,7 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
     float s_r = 0.0f;
     float dphi[7] = {0, 0, 0, 0, 0, 0, 0};
     const int NP = L->rv ? 7 : 6;
+    float tdl = 0.0f;      /* direct differentiation: dlog_j of the first hit */
     int hits = 0;
     int64_t k1 = -1;
     /* colour mode: channel ch carries flux Phi_r col[ch] and throughput Tc[ch];
@@ -1005,6 +1010,21 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
 #endif
                 io->S[k] += code;
             }
+        }
+        if (io->tangent) {
+            /* direct (forward-mode) differentiation with x_1 held fixed: every
+             * hit of the path adds d(Phi_h / A)/dp_j = (Phi_h / A) dlog_j of
+             * its first hit, in its own texel */
+            if (h == 1) {
+                float dl[7];
+                first_hit_dlog(L, x, y, no, au, av, dl);
+                tdl = dl[io->tangent_param];
+            }
+            long long code = llrintf((((phi_r * T) * inv_a) * tdl) * 4294967296.0f);
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+            io->tangent[k] += code;
         }
         if (io->g && !dirm) {
             if (L->rgb) {
@@ -1259,6 +1279,40 @@ EXPORT int64_t or_adjoint_rv(const or_scene* S, const or_lights* Ls, const float
         }
     }
     return misses;
+}
+
+/* Direct-differentiation map (the comparison of Sec. gradVis): dE_k/dp_j of
+ * light gl's paths with every first hit held fixed, as Q31.32 fixed point in
+ * tangent_out [K] (texels of the light's layout), overwritten.  Summed
+ * against dO/dE it gives the adjoint gradient dO/dp_j of that light. */
+EXPORT int64_t or_tangent(const or_scene* S, const or_lights* Ls, const float* params, uint64_t seed,
+                          int64_t paths_per_layout, int max_hits, int n_threads, int gl, int param,
+                          int64_t* tangent_out)
+{
+    if (Ls->colour || Ls->rotvec || S->dir_order >= 0 || S->basis != 0) return -1;
+    int j = 0;
+    while (Ls->layout_offsets[j + 1] <= gl) ++j;
+    int l0 = Ls->layout_offsets[j], l1 = Ls->layout_offsets[j + 1];
+    memset(tangent_out, 0, (size_t)S->n_texels * sizeof(int64_t));
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+    olight L;
+    int64_t nl = paths_of_light(paths_per_layout, l1 - l0, gl - l0);
+    light_setup(Ls, params, gl, nl, &L);
+    int64_t m = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : m)
+#endif
+    for (int64_t i = 0; i < nl; ++i) {
+        path_io io;
+        memset(&io, 0, sizeof(io));
+        io.tangent = tangent_out;
+        io.tangent_param = param;
+        trace_path(S, &L, j, gl - l0, gl, (uint32_t)i, seed, max_hits, NULL, &io);
+        m += io.misses;
+    }
+    return m;
 }
 
 /* the rotation-vector frame and Jacobian, for the pins */

@@ -763,6 +763,69 @@ def test_rotvec_agrees_with_tilt_angles(oracle_lib):
         assert abs(gw[1] - G6[l, 4]) <= 2e-3 * scale, (l, gw[1], G6[l, 4])
 
 
+# --------------------------------------------------------------------------
+# direct-differentiation map (the comparison beside the contribution map)
+# --------------------------------------------------------------------------
+
+def test_tangent_dotted_with_g_is_the_adjoint(oracle_lib):
+    """sum_k g_k dE_k/dp_j over the direct-differentiation map of light l is
+    the adjoint gradient dO/dp_j of that light: both sum, over the light's
+    paths, (Phi_h / A) g at every hit times the first hit's dlog_j."""
+    c1 = li.box_room()
+    sc, lights = c1["scene"], c1["lights"]
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    N, B, seed = 1 << 15, 3, 0x2E
+    g = np.random.default_rng(8).normal(size=(1, sc.n_texels)).astype(np.float32)
+    grad, _ = oracle_lib.adjoint(osc, ol, lights.params, seed, N, B, g)
+    for j in range(6):
+        T = oracle_lib.tangent(osc, ol, lights.params, seed, N, B, 0, j).astype(np.float64) * 2.0 ** -32
+        lhs = float(np.dot(g[0].astype(np.float64), T))
+        assert abs(lhs - grad[0, j]) <= 1e-5 * abs(grad[0, j]) + 1e-9 * np.abs(grad[0]).max(), (j, lhs, grad[0, j])
+
+
+def test_tangent_direct_vs_quadrature(oracle_lib):
+    """Direct light on a plane: the map's texel means are the derivative of
+    the texel's expected irradiance (quadrature, central differences)."""
+    half, res, N = 3.0, 16, 1 << 18
+    p = np.array([0.3, -0.2, 1.4, 0.3, -0.2, 40.0])
+    sc = li.plane_scene(half=half, res=res)
+    lights = make_lights([SPOT], [2.5], [(0, 0)], [0], [p])
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    A = float(sc.texel_area()[0])
+    for j in (0, 3, 5):
+        h = 1e-4
+        pp, pm = p.copy(), p.copy()
+        pp[j] += h
+        pm[j] -= h
+        ref = (cf.plane_hit_probability(SPOT, 2.5, pp, None, half, res, q_tex=5) * pp[5] -
+               cf.plane_hit_probability(SPOT, 2.5, pm, None, half, res, q_tex=5) * pm[5]) / (2 * h * A)
+        Ts = [oracle_lib.tangent(osc, ol, lights.params, sd, N, 1, 0, j).astype(np.float64) * 2.0 ** -32
+              for sd in (0x31, 0x32)]
+        err = np.linalg.norm((Ts[0] + Ts[1]) / 2 - ref)
+        noise = np.linalg.norm(Ts[0] - Ts[1]) / 2
+        assert err < 1.6 * noise + 1e-4 * np.linalg.norm(ref), (j, err, noise)
+
+
+def test_tangent_responds_at_the_target(oracle_lib):
+    """Indirect-only target (downward spot under a ceiling, B = 2): the direct
+    differentiation map responds on the ceiling, where the light arrives,
+    while the adjoint contribution map sits on the floor (the paper's
+    contrast between the two)."""
+    sb = li.SceneBuilder()
+    sb.quads([-8.0, -8.0, 0.0], [16.0, 0, 0], [0, 16.0, 0], 0.6, res=(16, 16))
+    sb.quads([-4.0, -4.0, 2.5], [8.0, 0, 0], [0, 8.0, 0], 0.7, res=(16, 16))
+    sc = sb.build("floor_ceiling", fixed_res=(16, 16))
+    p = np.array([[0.5, -0.3, 1.5, 0.2, 0.1, 100.0]], np.float32)
+    lights = make_lights([SPOT], [3.0], [(0, 0)], [0], p)
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    g = np.zeros((1, sc.n_texels), np.float32)
+    g[0, 256:] = 1.0
+    T = oracle_lib.tangent(osc, ol, p, 0x99, 1 << 15, 2, 0, 0).astype(np.float64)
+    vote, grad, _ = oracle_lib.votes(osc, ol, p, 0x99, 1 << 15, 2, g, 0, 0)
+    assert np.count_nonzero(T[256:]) > 100 and np.all(vote[256:] == 0.0)
+    assert abs(float(np.dot(g[0], T * 2.0 ** -32)) / vote.sum() - 1) < 1e-5
+
+
 def test_cosine_bounce_floor_to_ceiling(oracle_lib):
     """Second hits on a parallel ceiling: floor first-hit density times the
     differential form factor to each ceiling texel (cosine-weighted bounce, rho)."""
