@@ -408,6 +408,20 @@ def main():
     out["gradient_votes"] = {"kernel_ms": round(v_ms / max(nv, 1), 3), "adj_kernel_ms": round(adj_avg, 3),
                              "light": 0, "param": "x"}
     log("gradient votes", out["gradient_votes"])
+    # direct-differentiation map of the same luminaire and parameter: the
+    # forward kernel over that luminaire's paths only
+    ctx.trace_tangent(p, vcfg, 0, 0)
+    torch.cuda.synchronize()
+    ctx.timing_read()
+    ctx.set_timing(True)
+    for i in range(3):
+        ctx.trace_tangent(p, vcfg, 0, 0)
+    torch.cuda.synchronize()
+    ctx.set_timing(False)
+    t_ms, nt, _, _ = ctx.timing_read()
+    out["direct_differentiation"] = {"kernel_ms": round(t_ms / max(nt, 1), 3), "fwd_kernel_ms": round(fwd_avg, 3),
+                                     "light": 0, "param": "x"}
+    log("direct differentiation", out["direct_differentiation"])
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(scene, lights, seed, N, B, args.cpu_seconds)

@@ -187,6 +187,20 @@ int lt_trace_adjoint(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params
 int lt_gradient_votes(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, const float* d_dOdE,
                       int32_t light, int32_t param, double* d_vote, float* d_grad);
 
+/* Direct-differentiation map, the comparison the paper sets beside the
+ * contribution map (Sec. gradVis): d_D [K] f32 = dE_k/dp_j over the texels
+ * of the layout of global light `light`, j = `param`, from that light's
+ * paths with every first hit held fixed (each hit adds (Phi_h / A) times its
+ * path's first-hit dlog_j to its own texel).  d_T [K] i64 scratch (Q31.32,
+ * 16-byte aligned).  Unlike the contribution map it responds where light
+ * arrives; sum_k dO/dE_k d_D[k] equals the adjoint's dO/dp_j of the light up
+ * to rounding.  Plain emission, box basis, grey light, orientation as tilt
+ * angles (j = 0..5 as in the parameter vector).  LT_EINVAL for proposal or
+ * linear-basis flags, a light or parameter out of range, misaligned or NULL
+ * buffers. */
+int lt_trace_tangent(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, int32_t light, int32_t param,
+                     int64_t* d_T, float* d_D);
+
 /* Colour (Sec. 4.4.3, intensity and colour).  A luminaire's flux is split
  * over three channels by weights d_colour [L,3] f32 (channel ch carries
  * P c_ch; the optimiser may keep r + g + b = 1, the chromaticity

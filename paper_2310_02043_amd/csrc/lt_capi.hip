@@ -807,6 +807,37 @@ int lt_trace_adjoint_rgb(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_para
                    body);
 }
 
+int lt_trace_tangent(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int32_t light, int32_t param,
+                     int64_t* d_T, float* d_D)
+{
+    int rc = check_cfg(c, cfg);
+    if (rc) return rc;
+    if (!d_params || !d_T || !d_D) return fail(c, LT_EINVAL, "NULL device buffer");
+    if (cfg->flags & (LT_FLAG_PROPOSAL | LT_FLAG_LINEAR))
+        return fail(c, LT_EINVAL, "the direct-differentiation map takes the plain emission and the box basis only");
+    if (light < 0 || light >= c->L) return fail(c, LT_EINVAL, "light out of range");
+    if (param < 0 || param > 5) return fail(c, LT_EINVAL, "parameter out of range");
+    if (((uintptr_t)d_T & 15) || ((uintptr_t)d_D & 7)) return fail(c, LT_EINVAL, "d_T must be 16-byte and d_D 8-byte aligned");
+    HIPCHK(c, hipSetDevice(c->device));
+    const long long blocks = trace_blocks(c);
+    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    if (rc) return rc;
+    TraceArgs a = trace_args(c, cfg);
+    a.tangent = (long long*)d_T;
+    a.tan_light = light;
+    a.tan_param = param;
+    const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
+    auto body = [&](hipStream_t st) -> hipError_t {
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        if (e == hipSuccess) e = launch_clear(a.tangent, c->K, st);
+        if (e == hipSuccess) e = timed_trace(c, false, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = launch_finalize(a.tangent, d_D, c->K, c->d_flags, st);
+        return e;
+    };
+    return run_seq(c, graph,
+                   make_key(c, 11, cfg, {d_params, d_T, d_D, (const void*)(uintptr_t)(light * 8 + param)}), body);
+}
+
 int lt_trace_forward_rv(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int64_t* d_S, float* d_E)
 {
     int rc = check_cfg(c, cfg);

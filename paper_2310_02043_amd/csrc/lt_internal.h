@@ -55,6 +55,10 @@ struct TraceArgs {
     float alpha_plain;
     float* bin_hist;            // adjoint: [L,1024] histogram of |c_r / sigma| (may be null)
     const float* inv_sigma;     // [L,6]
+    // direct-differentiation map of one luminaire and parameter: [K] Q31.32
+    long long* tangent;
+    int tan_light;
+    int tan_param;
     // orientation as a rotation vector (adjoint: [n_tiles,7] partials)
     int rotvec;
     // directional texels: HSH order 0..2 (-1: irradiance texels), local

@@ -562,7 +562,8 @@ __device__ __forceinline__ long long xcd_block(long long b, long long nb, int re
 // and blue throughputs and adjoint sums live in LDS beside the red ones in
 // registers), 3 directional texels (hemispherical-harmonic coefficients of
 // the reflected radiance and a glossy BRDF; the adjoint's first-hit BRDF
-// terms live in LDS).
+// terms live in LDS), 4 rotation-vector orientation (seven derivatives),
+// 5 the direct-differentiation map of one luminaire (forward only).
 template <bool ADJ, bool STATS, int WPB, int LDS_D, int MODE>
 __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5))) k_trace(TraceArgs a)
 {
@@ -591,6 +592,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
     const int B = a.max_hits;
     const int thresh = a.refill_threshold;
     const int tile = (int)gw;
+    if (MODE == 5 && a.tiles[tile].x != a.tan_light) return;   // other luminaires add nothing
     {
         const int4 ti = a.tiles[tile];
         const DevLight& L = a.lights[ti.x];
@@ -623,6 +625,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
         uint32_t pid = 0;
         int h = 0, skip = -1, ebin = -1;
         float T = 1.0f, s_r = 0.0f, au = 0.0f, av = 0.0f, phi_r = 0.0f, wq = 0.0f;
+        float tdl = 0.0f;      // direct differentiation: dlog_j of the first hit
         if (ADJ) {
 #pragma unroll
             for (int c = 0; c < 2 * NPAR; ++c) adj[c * 64] = 0.0f;
@@ -709,7 +712,18 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                     const HitInfo hi = hit_info(r, s.tb, s.qb, a.patches);
                     V3 fb1 = v3(0, 0, 0), fb2 = v3(0, 0, 0), wil = v3(0, 0, 0);
                     float2 gls = make_float2(0.0f, 1.0f);
-                    if (MODE == 3) {
+                    if (MODE == 5) {
+                        // d(Phi_h / A)/dp_j with the first hit held fixed
+                        if (h == 1) {
+                            float dl[6];
+                            first_hit_dlog(L, hi.x, v3(r.ox, r.oy, r.oz), hi.no, au, av, dl);
+                            tdl = dl[a.tan_param];
+                        }
+                        const long long qt =
+                            (long long)__builtin_rintf((((phi_r * T) * hi.inva) * tdl) * 4294967296.0f);
+                        __hip_atomic_fetch_add((unsigned long long*)(a.tangent + hi.k), (unsigned long long)qt,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    } else if (MODE == 3) {
                         gls = a.glossy[s.qb];
                         local_frame(hi.no, fb1, fb2);
                         const V3 wiw = v3(-r.dx, -r.dy, -r.dz);
@@ -1450,7 +1464,12 @@ inline int nblocks(long long n, int b, int cap)
 template <bool ADJ, bool STATS, int WPB>
 hipError_t launch_wpb(const TraceArgs& a, int lds_depth, int blocks, hipStream_t st)
 {
-    if (a.rotvec && ADJ) {
+    if (a.tangent != nullptr && !ADJ && !STATS) {
+        if (lds_depth == 16)
+            k_trace<ADJ, STATS, WPB, 16, 5><<<blocks, WPB * 64, 0, st>>>(a);
+        else
+            k_trace<ADJ, STATS, WPB, 32, 5><<<blocks, WPB * 64, 0, st>>>(a);
+    } else if (a.rotvec && ADJ) {
         if (lds_depth == 16)
             k_trace<ADJ, STATS, WPB, 16, 4><<<blocks, WPB * 64, 0, st>>>(a);
         else

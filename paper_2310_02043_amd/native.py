@@ -23,6 +23,7 @@ EXPORTED = [
     "lt_set_lights", "lt_trace_forward", "lt_objective", "lt_trace_adjoint", "lt_gradient_votes",
     "lt_pt_forward", "lt_pt_adjoint", "lt_set_albedo_rgb", "lt_trace_forward_rgb", "lt_trace_adjoint_rgb",
     "lt_set_glossy", "lt_trace_forward_dir", "lt_trace_adjoint_dir", "lt_trace_forward_rv", "lt_trace_adjoint_rv",
+    "lt_trace_tangent",
     "lt_record_paths",
     "lt_trace_stats", "lt_get_tuning", "lt_set_tuning", "lt_autotune", "lt_info_get", "lt_set_timing",
     "lt_timing_read", "lt_proposal_set_table", "lt_proposal_get_table", "lt_proposal_set_scale",
@@ -91,6 +92,7 @@ def load():
     L.lt_set_albedo_rgb.argtypes = [P, P]
     L.lt_set_glossy.argtypes = [P, P]
     L.lt_trace_forward_rv.argtypes = [P, C.POINTER(TraceCfg), P, P, P]
+    L.lt_trace_tangent.argtypes = [P, C.POINTER(TraceCfg), P, I32, I32, P, P]
     L.lt_trace_adjoint_rv.argtypes = [P, C.POINTER(TraceCfg), P, P, P]
     L.lt_trace_forward_dir.argtypes = [P, C.POINTER(TraceCfg), P, I32, I32, P, P]
     L.lt_trace_adjoint_dir.argtypes = [P, C.POINTER(TraceCfg), P, I32, I32, P, P, P]
@@ -293,6 +295,18 @@ class Context:
         self._check(self.lib.lt_trace_adjoint_rgb(self.h, C.byref(cfg), _ptr(params), _ptr(colour), _ptr(dOdE),
                                                   _ptr(grad), _ptr(grad_colour), _ptr(bin_hist)))
         return grad, grad_colour
+
+    def trace_tangent(self, params, cfg, light, param):
+        """Direct-differentiation map dE/dp_j of global light `light` over the
+        texels of its layout: ([K] float32, [K] int64 Q31.32 sums)."""
+        torch = self._torch
+        self._dev(params, torch.float32, (self.n_lights, 6))
+        T = torch.empty(self.n_texels, dtype=torch.int64, device=params.device)
+        D = torch.empty(self.n_texels, dtype=torch.float32, device=params.device)
+        self._stream()
+        self._check(self.lib.lt_trace_tangent(self.h, C.byref(cfg), _ptr(params), int(light), int(param), _ptr(T),
+                                              _ptr(D)))
+        return D, T
 
     def trace_forward_rv(self, params, cfg, S=None, E=None):
         """Rotation-vector orientation, params [L,7] = (x, y, z, theta, P): (E, S)."""

@@ -1,0 +1,110 @@
+"""Direct-differentiation map on the GPU vs the CPU oracle (Sec. 5, the
+comparison set beside the gradient-contribution map): dE_k/dp_j of one
+luminaire with first hits held fixed, through the C ABI.
+
+Both sides replay the same paths and splat the same Q31.32 codes, so the
+integer sums must agree bit for bit; the map dotted with dO/dE must equal
+the adjoint gradient of that luminaire and parameter (1e-4 relative, plus
+1e-6 of sum |g D| for cancellation: FP64 partial sums of FP32 path terms
+against the fixed-point map)."""
+import sys
+
+import numpy as np
+import pytest
+
+import lt_inputs as li
+from tuning_cache import bench_tuning
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def run_tangent(torch, oracle_lib, scene, lights, seed, N, B, use_bvh, cases, tuning=None):
+    from paper_2310_02043_amd import Context
+    ctx = Context(0)
+    ctx.upload_scene(scene.verts, scene.tris, scene.tri_patch, scene.patches)
+    ctx.set_lights(lights.static, lights.layout_offsets)
+    if tuning:
+        ctx.set_tuning(**tuning)
+    osc, ol = oracle_lib.OracleScene(scene, use_bvh=use_bvh), oracle_lib.OracleLights(lights)
+    p_d = torch.tensor(lights.params, device="cuda")
+    cfg = ctx.cfg(seed, N, B)
+    g = np.random.default_rng(seed).normal(size=(lights.n_layouts, scene.n_texels)).astype(np.float32)
+    grad = ctx.trace_adjoint(p_d, torch.tensor(g, device="cuda"), cfg)
+    assert ctx.sync() == 0
+    grad = grad.cpu().numpy()
+    layout_of = np.searchsorted(np.asarray(lights.layout_offsets), np.arange(lights.n_lights), side="right") - 1
+    for l, j in cases:
+        say(f"  light {l} parameter {j}")
+        D_d, T_d = ctx.trace_tangent(p_d, cfg, l, j)
+        assert ctx.sync() == 0
+        T_ref = oracle_lib.tangent(osc, ol, lights.params, seed, N, B, l, j)
+        T_d = T_d.cpu().numpy()
+        same = np.mean(T_d == T_ref) * 100
+        say(f"    map: bit-identical {same:.4f} %, nonzero texels {np.count_nonzero(T_ref)}")
+        assert np.array_equal(T_d, T_ref)
+        assert np.array_equal(D_d.cpu().numpy(), oracle_lib.fixed_to_float(T_ref))
+        gl = g[layout_of[l]].astype(np.float64)
+        D = T_ref.astype(np.float64) * 2.0 ** -32
+        lhs = float(np.dot(gl, D))
+        mag = float(np.dot(np.abs(gl), np.abs(D)))
+        err = abs(lhs - float(grad[l, j]))
+        say(f"    g . map {lhs:.6e} vs adjoint {grad[l, j]:.6e}: |diff| / sum|g D| {err / max(mag, 1e-300):.2e}")
+        assert err <= 1e-4 * abs(grad[l, j]) + 1e-6 * mag
+
+
+def test_tangent_box_room_full(torch_dev, oracle_lib):
+    """Closed room with two boxes at full size (2^20 paths, 3 hits), every
+    parameter of the spot."""
+    c1 = li.box_room()
+    run_tangent(torch_dev, oracle_lib, c1["scene"], c1["lights"], c1["seed"], c1["paths"], c1["max_hits"], False,
+                [(0, j) for j in range(6)])
+
+
+def test_tangent_office_reduced(torch_dev, oracle_lib):
+    """The 200k-triangle office at 2^18 paths per layout, 5 hits, with the
+    launch tuning bench.py uses: two of the 16 area lights."""
+    c2 = li.office()
+    sc, lights = c2["scene"], c2["lights"]
+    run_tangent(torch_dev, oracle_lib, sc, lights, c2["seed"], 1 << 18, c2["max_hits"], True,
+                [(3, 3), (11, 1)], tuning=bench_tuning(sc, lights, c2["paths"], c2["max_hits"]))
+
+
+def test_tangent_batched_layouts(torch_dev, oracle_lib):
+    """Room set: 64 layouts of 4..48 lights in one launch, 2^14 paths per
+    layout: a spot's tilt and a point light's x in the first layout, and
+    the last light of the last layout."""
+    c3 = li.room_set()
+    lights = c3["lights"]
+    run_tangent(torch_dev, oracle_lib, c3["scene"], lights, c3["seed"], 1 << 14, c3["max_hits"], True,
+                [(2, 4), (1, 0), (lights.n_lights - 1, 0)])
+
+
+def test_tangent_invalid_arguments(torch_dev):
+    torch = torch_dev
+    from paper_2310_02043_amd import Context
+    from paper_2310_02043_amd.native import LtError
+    c1 = li.box_room()
+    sc, lights = c1["scene"], c1["lights"]
+    ctx = Context(0)
+    ctx.upload_scene(sc.verts, sc.tris, sc.tri_patch, sc.patches)
+    ctx.set_lights(lights.static, lights.layout_offsets)
+    p_d = torch.tensor(lights.params, device="cuda")
+    with pytest.raises(LtError):
+        ctx.trace_tangent(p_d, ctx.cfg(1, 1 << 12, 3), lights.n_lights, 0)     # light out of range
+    with pytest.raises(LtError):
+        ctx.trace_tangent(p_d, ctx.cfg(1, 1 << 12, 3), 0, 6)                   # parameter out of range
+    with pytest.raises(LtError):
+        ctx.trace_tangent(p_d, ctx.cfg(1, 1 << 12, 3, linear=True), 0, 0)      # box basis only
