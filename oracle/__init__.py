@@ -152,12 +152,12 @@ class OracleScene:
         if self.albedo_rgb is not None:
             assert self.albedo_rgb.shape[0] == self.pf.shape[0]
             self.c.albedo_rgb = self.albedo_rgb.ctypes.data
-        # directional texels (HSH order 0..2, N' local samples) and a glossy BRDF
+        # directional texels (HSH order 0..3, N' local samples) and a glossy BRDF
         # (per patch: specular albedo, Phong exponent)
         self.glossy = None if glossy is None else np.ascontiguousarray(glossy, np.float32).reshape(-1, 2)
         if self.glossy is not None:
             self.c.glossy = self.glossy.ctypes.data
-        assert -1 <= dir_order <= 2 and dir_samples >= 1
+        assert -1 <= dir_order <= 3 and dir_samples >= 1
         self.dir_order = int(dir_order)
         self.n_coef = (dir_order + 1) ** 2 if dir_order >= 0 else 0
         self.c.dir_order = int(dir_order)
@@ -374,7 +374,7 @@ def record(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layo
 
 def hsh(order: int, ct, cp, sp):
     """The oracle's hemispherical harmonics at one direction (local frame)."""
-    out = np.zeros(9, np.float32)
+    out = np.zeros(16, np.float32)
     n = lib().or_hsh(int(order), float(ct), float(cp), float(sp), out.ctypes.data)
     return out[:n]
 

@@ -250,7 +250,7 @@ typedef struct {
     const void* bvh;          /* or_bvh* or NULL for brute force */
     const float* albedo_rgb;  /* [P,3] per-channel albedo (colour mode), or NULL: the scalar albedo */
     const float* glossy;      /* [P,2] specular albedo, Phong exponent (directional mode), or NULL */
-    int32_t dir_order;        /* directional texels: HSH order 0..2, or -1 (irradiance texels) */
+    int32_t dir_order;        /* directional texels: HSH order 0..3, or -1 (irradiance texels) */
     int32_t dir_samples;      /* local exitant samples per hit (directional mode) */
 } or_scene;
 
@@ -710,14 +710,28 @@ EXPORT int or_hsh(int order, float ct, float cp, float sp, float* H)
         H[2] = 1.7320508075688772f * x;
         H[3] = (1.7320508075688772f * s1) * cp;
     }
+    /* cos/sin of 2 phi and 3 phi by the angle-addition formulas */
+    float c2 = 2.0f * (cp * cp) - 1.0f, s2 = 2.0f * (sp * cp);
+    float q = 1.0f - x * x;
     if (order >= 2) {
-        float c2 = 2.0f * (cp * cp) - 1.0f, s2 = 2.0f * (sp * cp);
-        float q = 1.0f - x * x;
         H[4] = (1.9364916731037085f * q) * s2;
         H[5] = ((3.872983346207417f * x) * s1) * sp;
         H[6] = 2.23606797749979f * ((3.0f * (x * x) - 1.0f) * 0.5f);
         H[7] = ((3.872983346207417f * x) * s1) * cp;
         H[8] = (1.9364916731037085f * q) * c2;
+    }
+    if (order >= 3) {
+        /* l = 3: P3 = (5x^3 - 3x)/2, P3^1 = 3/2 (5x^2 - 1) s1, P3^2 = 15 x q,
+         * P3^3 = 15 q s1 (no Condon-Shortley sign), each times its norm */
+        float c3 = c2 * cp - s2 * sp, s3 = s2 * cp + c2 * sp;
+        float w1 = 5.0f * (x * x) - 1.0f;
+        H[9] = ((2.091650066335189f * q) * s1) * s3;
+        H[10] = ((5.123475382979799f * x) * q) * s2;
+        H[11] = ((1.620185174601965f * w1) * s1) * sp;
+        H[12] = 2.6457513110645907f * (((5.0f * (x * x) - 3.0f) * x) * 0.5f);
+        H[13] = ((1.620185174601965f * w1) * s1) * cp;
+        H[14] = ((5.123475382979799f * x) * q) * c2;
+        H[15] = ((2.091650066335189f * q) * s1) * c3;
     }
     return (order + 1) * (order + 1);
 }
@@ -932,7 +946,7 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
             local_frame(no, fb1, fb2);
             float wiw[3] = {-dir[0], -dir[1], -dir[2]};
             wi_loc[0] = dot3(fb1, wiw); wi_loc[1] = dot3(fb2, wiw); wi_loc[2] = dot3(no, wiw);
-            float acc_c[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            float acc_c[16] = {0};
             float pd = 0.0f, ql[3] = {0, 0, 0};
             for (int j = 0; j < S->dir_samples; ++j) {
                 float us[4];
@@ -943,7 +957,7 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
                 float sp, cp;
                 or_sincos2pi(ub, &sp, &cp);
                 float wo[3] = {st * cp, st * sp, ct};
-                float H[9];
+                float H[16];
                 or_hsh(S->dir_order, ct, cp, sp, H);
                 float gr[3];
                 float f = or_brdf(pf[16], rs, ex, wi_loc, wo, (io->g && h == 1) ? gr : NULL);

@@ -505,14 +505,17 @@ def test_hsh_orthonormal(oracle_lib):
     Hs, W = [], []
     for ct, w in zip(cg, cw):
         for f in ph:
-            Hs.append(oracle_lib.hsh(2, ct, math.cos(f), math.sin(f)).astype(np.float64))
+            Hs.append(oracle_lib.hsh(3, ct, math.cos(f), math.sin(f)).astype(np.float64))
             W.append(w * 2 * math.pi / n_phi)
     Hs, W = np.array(Hs), np.array(W)
     G = (Hs * W[:, None]).T @ Hs
-    assert np.allclose(G, 2 * math.pi * np.eye(9), atol=2e-5)
+    assert np.allclose(G, 2 * math.pi * np.eye(16), atol=4e-5)
     CT, PH = np.meshgrid(cg, ph, indexing="ij")
-    ref = cf.hsh_basis(2, CT.ravel(), PH.ravel())
-    assert np.allclose(Hs, ref, atol=2e-6)
+    ref = cf.hsh_basis(3, CT.ravel(), PH.ravel())
+    assert np.allclose(Hs, ref, atol=4e-6)
+    for order in range(3):     # lower orders are prefixes
+        n = (order + 1) ** 2
+        assert np.array_equal(oracle_lib.hsh(order, 0.3, 0.6, 0.8), oracle_lib.hsh(3, 0.3, 0.6, 0.8)[:n])
 
 
 def test_brdf_normalisation_and_gradient(oracle_lib):
@@ -567,22 +570,25 @@ def _glossy_plane(half, res):
 
 
 def test_directional_glossy_direct_over_plane(oracle_lib):
-    """Direct light on a glossy plane: every coefficient's texel mean agrees
-    with the quadrature of the reflected radiance's projection, within the
-    noise two seeds show."""
+    """Direct light on a glossy plane: every coefficient's texel mean (order
+    3, 16 harmonics) agrees with the quadrature of the reflected radiance's
+    projection, within the noise two seeds show, in total and order by order."""
     half, res, N = 2.0, 8, 1 << 18
     sc, gl = _glossy_plane(half, res)
     p = [0.3, -0.2, 1.2, 0.3, -0.15, 50.0]
     lights = make_lights([SPOT], [3.0], [(0, 0)], [0], [p])
-    osc = oracle_lib.OracleScene(sc, glossy=gl, dir_order=2, dir_samples=8)
+    osc = oracle_lib.OracleScene(sc, glossy=gl, dir_order=3, dir_samples=8)
     ol = oracle_lib.OracleLights(lights)
     A = float(sc.texel_area()[0])
-    ref = cf.plane_direct_coefficients(3.0, p, half, res, 0.3, 0.5, 16.0, 2).T * p[5] / A   # [9, K]
+    ref = cf.plane_direct_coefficients(3.0, p, half, res, 0.3, 0.5, 16.0, 3).T * p[5] / A   # [16, K]
     Ls = [oracle_lib.fixed_to_float(oracle_lib.forward(osc, ol, lights.params, sd, N, 1)[0])[0].astype(np.float64)
           for sd in (0x91, 0x92)]
-    err = np.linalg.norm((Ls[0] + Ls[1]) / 2 - ref)
-    noise = np.linalg.norm(Ls[0] - Ls[1]) / 2
-    assert err < 1.6 * noise + 1e-4 * np.linalg.norm(ref), (err, noise)
+    # all coefficients, then each order's block on its own
+    for sl in (slice(0, 16), slice(0, 1), slice(1, 4), slice(4, 9), slice(9, 16)):
+        err = np.linalg.norm((Ls[0][sl] + Ls[1][sl]) / 2 - ref[sl])
+        noise = np.linalg.norm(Ls[0][sl] - Ls[1][sl]) / 2
+        assert err < 1.6 * noise + 1e-4 * np.linalg.norm(ref[sl]), (sl, err, noise)
+    assert np.linalg.norm(ref[9:]) > 0.05 * np.linalg.norm(ref)     # order 3 carries signal here
 
 
 def test_directional_glossy_direct_gradient(oracle_lib):
