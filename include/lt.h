@@ -219,7 +219,7 @@ int lt_trace_forward_rgb(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_pa
 int lt_trace_adjoint_rgb(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, const float* d_colour,
                          const float* d_dOdE, float* d_grad, float* d_grad_colour, float* d_bin_hist);
 
-/* Directional texels (Eq. directionalCoeffs with n = 1, 2; Sec. 4.1) with a
+/* Directional texels (Eq. directionalCoeffs with n = 1 to 3; Sec. 4.1) with a
  * glossy BRDF.  Each texel holds NC = (order+1)^2 coefficients of its
  * reflected radiance in 2pi-normalised hemispherical harmonics (the
  * integral of H^2 over the hemisphere is 2 pi, H_0^0 = 1; associated
@@ -235,7 +235,7 @@ int lt_trace_adjoint_rgb(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_pa
  * [n_layouts,NC,K]; lt_objective takes n = n_layouts*NC*K.  The adjoint
  * adds the first hit's BRDF terms: its projection and its bounce weight
  * depend on the incident direction, which moves with the luminaire while
- * x_1 stays fixed (Eq. dLdp).  order 0..2, samples 1..64, box basis, grey. */
+ * x_1 stays fixed (Eq. dLdp).  order 0..3, samples 1..64, box basis, grey. */
 int lt_set_glossy(lt_ctx* ctx, const float* h_glossy);
 
 /* Orientation as a rotation vector (Sec. 4.4.2): d_params [L,7] = (x, y, z,

@@ -924,7 +924,7 @@ int dir_check(lt_ctx* c, const lt_trace_cfg* cfg, int32_t order, int32_t samples
 {
     int rc = check_cfg(c, cfg);
     if (rc) return rc;
-    if (order < 0 || order > 2) return fail(c, LT_EINVAL, "hemispherical-harmonic order must be 0, 1 or 2");
+    if (order < 0 || order > 3) return fail(c, LT_EINVAL, "hemispherical-harmonic order must be 0 to 3");
     if (samples < 1 || samples > 64) return fail(c, LT_EINVAL, "local samples per hit must be in [1, 64]");
     if (cfg->flags & LT_FLAG_LINEAR) return fail(c, LT_EINVAL, "directional texels take the box basis only");
     if (cfg->max_hits > 64) return fail(c, LT_EINVAL, "max_hits too large for the local-sample counters");

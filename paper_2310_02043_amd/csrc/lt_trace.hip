@@ -473,7 +473,7 @@ __device__ __forceinline__ float linear_gather(const float* __restrict__ g, cons
 // (associated Legendre functions of x = 2 cos(theta) - 1 times cos / sin of
 // m phi, index l^2 + l + m), and a Lambertian + normalised Phong BRDF in the
 // local frame (normal = z) with its gradient w.r.t. the incident direction.
-__device__ __forceinline__ void hsh_eval(int order, float ct, float cp, float sp, float H[9])
+__device__ __forceinline__ void hsh_eval(int order, float ct, float cp, float sp, float H[16])
 {
     const float x = 2.0f * ct - 1.0f;
     const float s1 = __builtin_sqrtf(fmaxf(0.0f, 1.0f - x * x));
@@ -483,14 +483,26 @@ __device__ __forceinline__ void hsh_eval(int order, float ct, float cp, float sp
         H[2] = 1.7320508075688772f * x;
         H[3] = (1.7320508075688772f * s1) * cp;
     }
+    const float c2 = 2.0f * (cp * cp) - 1.0f, s2 = 2.0f * (sp * cp);
+    const float q = 1.0f - x * x;
     if (order >= 2) {
-        const float c2 = 2.0f * (cp * cp) - 1.0f, s2 = 2.0f * (sp * cp);
-        const float q = 1.0f - x * x;
         H[4] = (1.9364916731037085f * q) * s2;
         H[5] = ((3.872983346207417f * x) * s1) * sp;
         H[6] = 2.23606797749979f * ((3.0f * (x * x) - 1.0f) * 0.5f);
         H[7] = ((3.872983346207417f * x) * s1) * cp;
         H[8] = (1.9364916731037085f * q) * c2;
+    }
+    if (order >= 3) {
+        // l = 3 with the (2l+1)-scaled norms: P3, 3/2 (5x^2-1) s1, 15 x q, 15 q s1
+        const float c3 = c2 * cp - s2 * sp, s3 = s2 * cp + c2 * sp;
+        const float w1 = 5.0f * (x * x) - 1.0f;
+        H[9] = ((2.091650066335189f * q) * s1) * s3;
+        H[10] = ((5.123475382979799f * x) * q) * s2;
+        H[11] = ((1.620185174601965f * w1) * s1) * sp;
+        H[12] = 2.6457513110645907f * (((5.0f * (x * x) - 3.0f) * x) * 0.5f);
+        H[13] = ((1.620185174601965f * w1) * s1) * cp;
+        H[14] = ((5.123475382979799f * x) * q) * c2;
+        H[15] = ((2.091650066335189f * q) * s1) * c3;
     }
 }
 
@@ -565,7 +577,7 @@ __device__ __forceinline__ long long xcd_block(long long b, long long nb, int re
 // terms live in LDS), 4 rotation-vector orientation (seven derivatives),
 // 5 the direct-differentiation map of one luminaire (forward only).
 template <bool ADJ, bool STATS, int WPB, int LDS_D, int MODE>
-__global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5))) k_trace(TraceArgs a)
+__global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(MODE == 3 ? 4 : 5))) k_trace(TraceArgs a)
 {
     __shared__ int s_stack[WPB * LDS_D * 64];
     // adjoint per-lane state read once per path (first-hit derivative
@@ -576,14 +588,16 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
     __shared__ int s_k1[ADJ ? WPB * 64 : 1];
     // colour: per lane T_g, T_b, s_g, s_b and the three channel-weight sums
     __shared__ float s_rgb[MODE == 2 ? WPB * 8 * 64 : 1];
-    // directional adjoint: T2, R, Q[3], D[3], w_in1[3], 1/r1
-    __shared__ float s_dir[(MODE == 3 && ADJ) ? WPB * 12 * 64 : 1];
+    // directional: forward, the hit's 16 coefficient sums; adjoint T2, R,
+    // Q[3], D[3], w_in1[3], 1/r1 and the hit texel's 16 dO/dL values
+    constexpr int DIRW = ADJ ? 28 : 16;
+    __shared__ float s_dir[MODE == 3 ? WPB * DIRW * 64 : 1];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     float* adj = s_adj + (ADJ ? wib * 2 * NPAR * 64 + lane : 0);
     int* k1 = s_k1 + (ADJ ? wib * 64 + lane : 0);
     float* rgbs = s_rgb + (MODE == 2 ? wib * 8 * 64 + lane : 0);
-    float* dst = s_dir + ((MODE == 3 && ADJ) ? wib * 12 * 64 + lane : 0);
+    float* dst = s_dir + (MODE == 3 ? wib * DIRW * 64 + lane : 0);
     const long long blk = xcd_block(blockIdx.x, gridDim.x, a.xcd_remap);
     const long long gw = blk * WPB + wib;
     if (gw >= a.n_tiles) return;
@@ -728,9 +742,14 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                         local_frame(hi.no, fb1, fb2);
                         const V3 wiw = v3(-r.dx, -r.dy, -r.dz);
                         wil = v3(dot(fb1, wiw), dot(fb2, wiw), dot(hi.no, wiw));
-                        float accd[9];
 #pragma unroll
-                        for (int c = 0; c < 9; ++c) accd[c] = 0.0f;
+                        for (int c = 0; c < 16; ++c)
+                            if (c < NC) {
+                                if (ADJ)
+                                    dst[(12 + c) * 64] = g[c * a.K + hi.k];
+                                else
+                                    dst[c * 64] = 0.0f;
+                            }
                         float pd = 0.0f;
                         V3 ql = v3(0, 0, 0);
                         U4 us = {0u, 0u, 0u, 0u};
@@ -745,19 +764,19 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                             float sp, cp;
                             sincos_2pi(ub, sp, cp);
                             const V3 wo = v3(st * cp, st * sp, ct);
-                            float H[9];
+                            float H[16];
                             hsh_eval(a.dir_order, ct, cp, sp, H);
                             V3 gr;
                             const float f = brdf_local(hi.rho, gls.x, gls.y, wil, wo, ADJ && h == 1, gr);
                             if (!ADJ) {
 #pragma unroll
-                                for (int c = 0; c < 9; ++c)
-                                    if (c < NC) accd[c] = accd[c] + f * H[c];
+                                for (int c = 0; c < 16; ++c)
+                                    if (c < NC) dst[c * 64] = dst[c * 64] + f * H[c];
                             } else {
                                 float G = 0.0f;
 #pragma unroll
-                                for (int c = 0; c < 9; ++c)
-                                    if (c < NC) G = G + g[c * a.K + hi.k] * H[c];
+                                for (int c = 0; c < 16; ++c)
+                                    if (c < NC) G = G + dst[(12 + c) * 64] * H[c];
                                 pd = pd + f * G;
                                 if (h == 1) ql = v3(ql.x + G * gr.x, ql.y + G * gr.y, ql.z + G * gr.z);
                             }
@@ -765,10 +784,10 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(5
                         if (!ADJ) {
                             const float base = (phi_r * T) * hi.inva;
 #pragma unroll
-                            for (int c = 0; c < 9; ++c)
+                            for (int c = 0; c < 16; ++c)
                                 if (c < NC) {
                                     const long long qc =
-                                        (long long)__builtin_rintf(((base * accd[c]) * inv_np) * 4294967296.0f);
+                                        (long long)__builtin_rintf(((base * dst[c * 64]) * inv_np) * 4294967296.0f);
                                     __hip_atomic_fetch_add((unsigned long long*)(S + c * a.K + hi.k),
                                                            (unsigned long long)qc, __ATOMIC_RELAXED,
                                                            __HIP_MEMORY_SCOPE_AGENT);

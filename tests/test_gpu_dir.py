@@ -1,5 +1,5 @@
 """Directional texels with a glossy BRDF on the GPU vs the CPU oracle
-(Eq. directionalCoeffs with n = 1, 2 and the first hit's BRDF terms of the
+(Eq. directionalCoeffs with n = 1 to 3 and the first hit's BRDF terms of the
 adjoint), through the C ABI.  Bars as for the irradiance texels: texel
 coefficients rel-L2 <= 1e-4, gradients 1e-3 relative; the tests report how
 close they are.
@@ -80,11 +80,13 @@ def run_dir(torch, oracle_lib, scene, lights, seed, N, B, order, samples, use_bv
     assert e <= GRAD_BAR
 
 
-def test_dir_box_room_full(torch_dev, oracle_lib):
+@pytest.mark.parametrize("order", [2, 3])
+def test_dir_box_room_full(torch_dev, oracle_lib, order):
     """Closed room with two boxes at full size (2^20 paths, 3 hits), glossy
-    patches, order 2, 4 local samples per hit."""
+    patches, orders 2 and 3, 4 local samples per hit."""
     c1 = li.box_room()
-    run_dir(torch_dev, oracle_lib, c1["scene"], c1["lights"], c1["seed"], c1["paths"], c1["max_hits"], 2, 4, False)
+    run_dir(torch_dev, oracle_lib, c1["scene"], c1["lights"], c1["seed"], c1["paths"], c1["max_hits"], order, 4,
+            False)
 
 
 def test_dir_mixed_lights_order1(torch_dev, oracle_lib):
@@ -98,11 +100,11 @@ def test_dir_mixed_lights_order1(torch_dev, oracle_lib):
 
 
 def test_dir_office_reduced(torch_dev, oracle_lib):
-    """The 200k-triangle office at 2^18 paths, 5 hits, order 2, 2 local
+    """The 200k-triangle office at 2^18 paths, 5 hits, order 3, 2 local
     samples, with the launch tuning bench.py uses."""
     c2 = li.office()
     sc, lights = c2["scene"], c2["lights"]
-    run_dir(torch_dev, oracle_lib, sc, lights, c2["seed"], 1 << 18, c2["max_hits"], 2, 2, True,
+    run_dir(torch_dev, oracle_lib, sc, lights, c2["seed"], 1 << 18, c2["max_hits"], 3, 2, True,
             tuning=bench_tuning(sc, lights, c2["paths"], c2["max_hits"]))
 
 
@@ -118,7 +120,7 @@ def test_dir_invalid_arguments(torch_dev):
     p_d = torch.tensor(lights.params, device="cuda")
     cfg = ctx.cfg(1, 1 << 12, 3)
     with pytest.raises(LtError):
-        ctx.trace_forward_dir(p_d, cfg, 3, 4)                                   # order above 2
+        ctx.trace_forward_dir(p_d, cfg, 4, 4)                                   # order above 3
     with pytest.raises(LtError):
         ctx.trace_forward_dir(p_d, cfg, 1, 0)                                   # no local samples
     with pytest.raises(LtError):
