@@ -4,7 +4,9 @@
 (Alg. 1) and returns texel irradiance E [n_layouts, K]; its backward runs the
 adjoint light-tracing kernel (Alg. 2) with the incoming dL/dE as the adjoint
 source and returns dL/dparams [L, 6].  ``LightTraceRGBFn`` is the colour form
-(channel weights [L, 3] as a second input, E [n_layouts, 3, K]).  Whether the adjoint replays the
+(channel weights [L, 3] as a second input, E [n_layouts, 3, K]) and
+``LightTraceDirFn`` the directional form (hemispherical-harmonic
+coefficients of the reflected radiance, E [n_layouts, (order+1)^2, K]).  Whether the adjoint replays the
 forward's paths (correlated evaluation, as the paper uses for validation) or
 a fresh set (decorrelated, as it uses for optimisation) is the tracer's
 ``correlated`` flag (Sec. 4.3).  Both passes run on the current torch stream.
@@ -77,6 +79,12 @@ class LightTracer:
         and channel weights [L,3], differentiable in both."""
         return LightTraceRGBFn.apply(params, colour, self, seed)
 
+    def directional(self, params, order: int, samples: int, seed=None):
+        """Directional texels: hemispherical-harmonic coefficients of the
+        reflected radiance [n_layouts, (order+1)^2, K] (glossy BRDF per patch
+        from ctx.set_glossy), differentiable in the luminaire parameters."""
+        return LightTraceDirFn.apply(params, self, int(order), int(samples), seed)
+
 
 class LightTraceFn(torch.autograd.Function):
     @staticmethod
@@ -123,6 +131,46 @@ class LightTraceRGBFn(torch.autograd.Function):
         return grad, grad_c, None, None
 
 
+class LightTraceDirFn(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, params, tracer: LightTracer, order, samples, seed=None):
+        p = params.detach().contiguous().float()
+        E, _ = tracer.ctx.trace_forward_dir(p, tracer.cfg(seed), order, samples)
+        fctx.save_for_backward(p)
+        fctx.tracer = tracer
+        fctx.seed = seed
+        fctx.order, fctx.samples = order, samples
+        return E
+
+    @staticmethod
+    def backward(fctx, grad_E):
+        (p,) = fctx.saved_tensors
+        tracer = fctx.tracer
+        g = grad_E.contiguous().float()
+        prop = tracer.proposal
+        hist = prop.hist if prop is not None and prop.collect else None
+        grad = tracer.ctx.trace_adjoint_dir(p, g, tracer.cfg(tracer.adjoint_seed(fctx.seed), adjoint=True),
+                                            fctx.order, fctx.samples, bin_hist=hist)
+        return grad, None, None, None, None
+
+
+def band_weights(order: int, w00: float = 0.1, device=None):
+    """Per-coefficient weights alpha_l of Eq. objective for directional texels,
+    [(order+1)^2]: the order-0 band (undirected light) weighted w00 against
+    1 for the directional bands (the paper's glossy-coin example uses 0.1)."""
+    n = (order + 1) ** 2
+    w = torch.ones(n, dtype=torch.float32, device=device)
+    w[0] = w00
+    return w
+
+
+def directional_alpha(band, alpha_k, n_layouts: int):
+    """alpha_l [NC] times alpha_k [K], expanded to the directional texel
+    layout [n_layouts, NC, K]: the per-element weight lt_objective takes."""
+    K = alpha_k.shape[-1]
+    return (band[None, :, None] * alpha_k.reshape(1, 1, K)).expand(n_layouts, band.numel(), K).contiguous()
+
+
 def chromaticity(colour):
     """Channel weights projected to r + g + b = 1 (Sec. 4.4.3: optimising
     chromaticity at constant intensity); differentiating through it applies
@@ -131,7 +179,8 @@ def chromaticity(colour):
 
 
 def objective(E, E_target, texel_area, alpha=None):
-    """O = 1/2 sum_k A_k alpha_k (E_k - E*_k)^2 (Eq. objective, alpha_l = 1) in torch."""
+    """O = 1/2 sum_k A_k alpha_k (E_k - E*_k)^2 (Eq. objective) in torch; alpha
+    broadcasts against E (per texel, or alpha_k alpha_l for directional texels)."""
     w = texel_area if alpha is None else texel_area * alpha
     d = E - E_target
     return 0.5 * torch.sum(w * d * d, dtype=torch.float64)

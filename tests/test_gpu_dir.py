@@ -127,3 +127,89 @@ def test_dir_invalid_arguments(torch_dev):
         ctx.trace_forward_dir(p_d, ctx.cfg(1, 1 << 12, 3, linear=True), 1, 4)   # box basis only
     with pytest.raises(LtError):
         ctx.set_glossy(np.full((sc.n_patches, 2), 2.0, np.float32))             # specular albedo above 1
+
+
+def _glossy_tracer(torch, scene, lights, paths, B, seed=9):
+    from paper_2310_02043_amd.autograd import LightTracer
+    gl = np.stack([np.full(scene.n_patches, 0.4), np.full(scene.n_patches, 16.0)], 1)
+    gl[:, 0] = np.minimum(gl[:, 0], 0.95 - scene.patches["albedo"])
+    tr = LightTracer((scene.verts, scene.tris, scene.tri_patch, scene.patches), lights.static, lights.layout_offsets,
+                     paths, B, seed=seed, correlated=False)
+    tr.ctx.set_glossy(gl.astype(np.float32))
+    return tr
+
+
+def test_dir_autograd_band_weights(torch_dev):
+    """The directional autograd function's backward equals the direct
+    directional adjoint with dO/dL = A alpha_k alpha_l (L - L*); the objective
+    kernel with the expanded band weights (order-0 band at 0.1) agrees with
+    the torch objective, and its order-0 dO/dL is 0.1 of the unweighted one."""
+    torch = torch_dev
+    from paper_2310_02043_amd.autograd import band_weights, directional_alpha, objective
+    c1 = li.box_room()
+    sc, lights = c1["scene"], c1["lights"]
+    tr = _glossy_tracer(torch, sc, lights, 1 << 20, 3)
+    order, ns = 2, 4
+    A = torch.tensor(sc.texel_area(), device="cuda")
+    band = band_weights(order, 0.1, device="cuda")
+    alpha = directional_alpha(band, torch.ones_like(A), 1)
+    p = torch.tensor(lights.params, device="cuda", requires_grad=True)
+    E = tr.directional(p, order, ns)
+    Et = (E.detach() * 1.3 + 1e-3).contiguous()
+    O = objective(E, Et, A, alpha=band[:, None])
+    O.backward()
+    g = (A * band[:, None] * (E.detach() - Et)).contiguous()
+    ref = tr.ctx.trace_adjoint_dir(p.detach(), g, tr.cfg(tr.adjoint_seed(), adjoint=True), order, ns)
+    torch.cuda.synchronize()
+    rel = (p.grad - ref).abs().max().item() / ref.abs().max().item()
+    say("  autograd vs direct directional adjoint:", rel)
+    assert rel < 1e-5
+    O_d, g_d = tr.ctx.objective(E.detach().contiguous(), Et, alpha)
+    _, g_1 = tr.ctx.objective(E.detach().contiguous(), Et)
+    torch.cuda.synchronize()
+    assert abs(O_d.item() / O.item() - 1) < 1e-5
+    assert torch.allclose(g_d, g, rtol=1e-6, atol=1e-7 * g.abs().max().item())
+    assert torch.allclose(g_d[:, 0], 0.1 * g_1[:, 0], rtol=1e-6, atol=1e-7 * g_1.abs().max().item())
+    assert torch.equal(g_d[:, 1:], g_1[:, 1:])
+
+
+def test_dir_adam_recovers_spot(torch_dev):
+    """Inverse directional lighting in the box room (glossy surfaces, order 2,
+    order-0 band weighted 0.1): from a spot moved by 0.36 m and tilted by
+    0.13 rad, Adam on the light-tracing gradients (fresh paths per step,
+    decorrelated adjoint) brings the objective to within 1.5x of its value at
+    the true parameters and the position to within 0.1 m."""
+    torch = torch_dev
+    from paper_2310_02043_amd.autograd import band_weights, objective
+    c1 = li.box_room()
+    sc, lights = c1["scene"], c1["lights"]
+    order, ns, B = 2, 4, 3
+    tr = _glossy_tracer(torch, sc, lights, 1 << 18, B)
+    A = torch.tensor(sc.texel_area(), device="cuda")
+    band = band_weights(order, 0.1, device="cuda")[:, None]
+    pt = torch.tensor(lights.params, device="cuda")
+    with torch.no_grad():
+        Et = tr.directional(pt, order, ns, seed=0x77).clone()
+        O_true = objective(tr.directional(pt, order, ns, seed=999), Et, A, band).item()
+    p0 = pt.clone()
+    p0[0, 0] += 0.3
+    p0[0, 1] -= 0.25
+    p0[0, 3] += 0.12
+    p = p0.clone().requires_grad_(True)
+    lr = torch.tensor([0.02, 0.02, 0.02, 0.01, 0.01, 0.0], device="cuda")
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    O_first = None
+    for it in range(80):
+        p.grad = None
+        O = objective(tr.directional(p, order, ns, seed=100 + it), Et, A, band)
+        O.backward()
+        O_first = O.item() if O_first is None else O_first
+        with torch.no_grad():
+            m.mul_(0.9).add_(0.1 * p.grad)
+            v.mul_(0.999).add_(0.001 * p.grad * p.grad)
+            p -= lr * (m / (1 - 0.9 ** (it + 1))) / ((v / (1 - 0.999 ** (it + 1))).sqrt() + 1e-8)
+    pos_err = (p.detach() - pt)[0, :3].norm().item()
+    say(f"  objective {O_first:.2f} -> {O.item():.2f} (true parameters {O_true:.2f}), position error "
+        f"{(p0 - pt)[0, :3].norm().item():.3f} -> {pos_err:.3f} m")
+    assert O.item() < 1.5 * O_true and pos_err < 0.1
