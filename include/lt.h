@@ -201,6 +201,20 @@ int lt_gradient_votes(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_param
 int lt_trace_tangent(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, int32_t light, int32_t param,
                      int64_t* d_T, float* d_D);
 
+/* Central-difference map, the third image of the paper's gradient
+ * comparison (Sec. gradVis): two primal passes with the same seed (common
+ * random numbers) at p_j + h and p_j - h of global light `light` (FP32 sums),
+ * d_F [K] f32 = (E_k(p+) - E_k(p-)) / ((p_j + h) - (p_j - h)) over the texels
+ * of the light's layout, the step taken in FP64 from the two FP32 values and
+ * the difference taken exactly on the int64 sums.  d_Sp, d_Sm [n_layouts,K]
+ * i64 scratch (16-byte aligned), holding the two passes' sums afterwards.
+ * Unlike the direct-differentiation map, hits move with p, so texels where a
+ * shadow or patch edge sweeps respond too.  Plain emission, box basis, grey,
+ * tilt angles; LT_EINVAL for h <= 0 or not finite, a light or parameter out
+ * of range, proposal or linear-basis flags. */
+int lt_fd_map(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, int32_t light, int32_t param, float h,
+              int64_t* d_Sp, int64_t* d_Sm, float* d_F);
+
 /* Colour (Sec. 4.4.3, intensity and colour).  A luminaire's flux is split
  * over three channels by weights d_colour [L,3] f32 (channel ch carries
  * P c_ch; the optimiser may keep r + g + b = 1, the chromaticity

@@ -82,6 +82,8 @@ struct lt_ctx {
     double* d_partials_col = nullptr; // colour adjoint: [n_tiles,3] partial sums of dO/dc
     size_t partials_col_cap = 0;
     double* d_partials7 = nullptr;    // rotation-vector adjoint: [n_tiles,7] partial sums
+    float* d_pfd = nullptr;           // central differences: p+ [L,6], p- [L,6], step (f64)
+    int pfd_cap = 0;                  // lights d_pfd holds
     size_t partials7_cap = 0;
 
     lt_tuning tune;
@@ -423,7 +425,7 @@ void lt_destroy(lt_ctx* c)
     hipFree(c->prop_pdf); hipFree(c->prop_cdf); hipFree(c->prop_guide); hipFree(c->inv_sigma); hipFree(c->mlp_scratch);
     hipFree(c->d_misses); hipFree(c->d_flags); hipFree(c->d_stats);
     hipFree(c->d_objpart); hipFree(c->d_partials); hipFree(c->d_gstack); hipFree(c->d_ptgrad);
-    hipFree(c->d_partials_col); hipFree(c->d_partials7);
+    hipFree(c->d_partials_col); hipFree(c->d_partials7); hipFree(c->d_pfd);
     if (c->ev_in) hipEventDestroy(c->ev_in);
     if (c->ev_out) hipEventDestroy(c->ev_out);
     if (c->gstream) hipStreamDestroy(c->gstream);
@@ -836,6 +838,59 @@ int lt_trace_tangent(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     };
     return run_seq(c, graph,
                    make_key(c, 11, cfg, {d_params, d_T, d_D, (const void*)(uintptr_t)(light * 8 + param)}), body);
+}
+
+int lt_fd_map(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int32_t light, int32_t param, float h,
+              int64_t* d_Sp, int64_t* d_Sm, float* d_F)
+{
+    int rc = check_cfg(c, cfg);
+    if (rc) return rc;
+    if (!d_params || !d_Sp || !d_Sm || !d_F) return fail(c, LT_EINVAL, "NULL device buffer");
+    if (cfg->flags & (LT_FLAG_PROPOSAL | LT_FLAG_LINEAR))
+        return fail(c, LT_EINVAL, "the central-difference map takes the plain emission and the box basis only");
+    if (light < 0 || light >= c->L) return fail(c, LT_EINVAL, "light out of range");
+    if (param < 0 || param > 5) return fail(c, LT_EINVAL, "parameter out of range");
+    if (!(h > 0.0f) || !__builtin_isfinite(h)) return fail(c, LT_EINVAL, "h must be positive and finite");
+    if (((uintptr_t)d_Sp & 15) || ((uintptr_t)d_Sm & 15) || ((uintptr_t)d_params & 3))
+        return fail(c, LT_EINVAL, "d_Sp and d_Sm must be 16-byte aligned");
+    HIPCHK(c, hipSetDevice(c->device));
+    const long long blocks = trace_blocks(c);
+    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    if (rc) return rc;
+    if (c->pfd_cap < c->L) {
+        free_graphs(c);
+        hipFree(c->d_pfd);
+        c->d_pfd = nullptr;
+        c->pfd_cap = 0;
+        HIPCHK(c, hipMalloc(&c->d_pfd, sizeof(float) * 12 * c->L + 16));
+        c->pfd_cap = c->L;
+    }
+    float* pp = c->d_pfd;
+    float* pm = c->d_pfd + 6 * c->pfd_cap;
+    double* den = (double*)(c->d_pfd + 12 * c->pfd_cap);   // 48 L bytes in: 16-byte aligned
+    int layout = 0;
+    while (c->offs[layout + 1] <= light) ++layout;
+    const long long n = c->K * c->n_layouts;
+    const long long row = (long long)layout * c->K;
+    TraceArgs ap = trace_args(c, cfg), am = trace_args(c, cfg);
+    ap.S = (long long*)d_Sp;
+    am.S = (long long*)d_Sm;
+    const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
+    auto body = [&](hipStream_t st) -> hipError_t {
+        hipError_t e = launch_fd_params(d_params, 6 * c->L, 6 * light + param, h, pp, pm, den, st);
+        if (e == hipSuccess) e = launch_light_setup(pp, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        if (e == hipSuccess) e = launch_clear(ap.S, n, st);
+        if (e == hipSuccess) e = timed_trace(c, false, graph, ap, (int)blocks, st);
+        if (e == hipSuccess) e = launch_light_setup(pm, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        if (e == hipSuccess) e = launch_clear(am.S, n, st);
+        if (e == hipSuccess) e = timed_trace(c, false, graph, am, (int)blocks, st);
+        if (e == hipSuccess) e = launch_fd_diff(ap.S + row, am.S + row, c->K, den, d_F, st);
+        return e;
+    };
+    return run_seq(c, graph,
+                   make_key(c, 12, cfg, {d_params, d_Sp, d_Sm, d_F, (const void*)(uintptr_t)(light * 8 + param),
+                                         (const void*)(uintptr_t)__builtin_bit_cast(uint32_t, h)}),
+                   body);
 }
 
 int lt_trace_forward_rv(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int64_t* d_S, float* d_E)

@@ -142,6 +142,10 @@ hipError_t launch_pt(bool adjoint, const PtArgs& a, int lds_depth, hipStream_t s
 hipError_t launch_grad_reduce_col(const double* partials, const int2* range, int n_lights, float* grad,
                                   hipStream_t st);
 hipError_t launch_f64_to_f32(const double* in, float* out, long long n, hipStream_t st);
+hipError_t launch_fd_params(const float* p, int n, int idx, float h, float* pp, float* pm, double* den,
+                            hipStream_t st);
+hipError_t launch_fd_diff(const long long* Sp, const long long* Sm, long long K, const double* den, float* F,
+                          hipStream_t st);
 hipError_t launch_finalize(const long long* S, float* E, long long n, unsigned* flags, hipStream_t st);
 hipError_t launch_objective(const float* E, const float* Et, const float* alpha, const float* A, long long K,
                             long long n, float* g, double* partials, double* O, hipStream_t st);

@@ -1253,6 +1253,31 @@ __global__ void k_f64_to_f32(const double* __restrict__ in, float* __restrict__ 
     if (i < n) out[i] = (float)in[i];
 }
 
+// Central differences: the two parameter sets p +- h e_idx (FP32 sums) and
+// the step actually taken, (p + h) - (p - h) in FP64.
+__global__ void k_fd_params(const float* __restrict__ p, int n, int idx, float h, float* __restrict__ pp,
+                            float* __restrict__ pm, double* __restrict__ den)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float v = p[i];
+    const float vp = i == idx ? v + h : v;
+    const float vm = i == idx ? v - h : v;
+    pp[i] = vp;
+    pm[i] = vm;
+    if (i == idx) den[0] = (double)vp - (double)vm;
+}
+
+// F_k = (S+_k - S-_k) 2^-32 / den: the difference is exact on the fixed-point sums.
+__global__ void k_fd_diff(const long long* __restrict__ Sp, const long long* __restrict__ Sm, long long K,
+                          const double* __restrict__ den, float* __restrict__ F)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const double d = den[0];
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < K; k += stride)
+        F[k] = (float)(((double)(Sp[k] - Sm[k]) * 0x1p-32) / d);
+}
+
 // Luminaire setup: frame R = R_y(beta) R_x(alpha), derivatives, Phi_r = P/N_l.
 // lstat_i = (type, layout, l_local, -), lstat_f = (n, w, h, N_l as float bits unused).
 // Rodrigues' formula in FP64, R = I + sin(phi)/phi K + (1 - cos(phi))/phi^2 K^2,
@@ -1547,6 +1572,20 @@ hipError_t launch_pt(bool adjoint, const PtArgs& a, int lds_depth, hipStream_t s
         if (lds_depth == 16) k_pt<false, 16><<<blocks, 256, 0, st>>>(a);
         else k_pt<false, 32><<<blocks, 256, 0, st>>>(a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fd_params(const float* p, int n, int idx, float h, float* pp, float* pm, double* den,
+                            hipStream_t st)
+{
+    k_fd_params<<<(n + 255) / 256, 256, 0, st>>>(p, n, idx, h, pp, pm, den);
+    return hipGetLastError();
+}
+
+hipError_t launch_fd_diff(const long long* Sp, const long long* Sm, long long K, const double* den, float* F,
+                          hipStream_t st)
+{
+    k_fd_diff<<<nblocks(K, 256, 4096), 256, 0, st>>>(Sp, Sm, K, den, F);
     return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ EXPORTED = [
     "lt_set_lights", "lt_trace_forward", "lt_objective", "lt_trace_adjoint", "lt_gradient_votes",
     "lt_pt_forward", "lt_pt_adjoint", "lt_set_albedo_rgb", "lt_trace_forward_rgb", "lt_trace_adjoint_rgb",
     "lt_set_glossy", "lt_trace_forward_dir", "lt_trace_adjoint_dir", "lt_trace_forward_rv", "lt_trace_adjoint_rv",
-    "lt_trace_tangent",
+    "lt_trace_tangent", "lt_fd_map",
     "lt_record_paths",
     "lt_trace_stats", "lt_get_tuning", "lt_set_tuning", "lt_autotune", "lt_info_get", "lt_set_timing",
     "lt_timing_read", "lt_proposal_set_table", "lt_proposal_get_table", "lt_proposal_set_scale",
@@ -93,6 +93,7 @@ def load():
     L.lt_set_glossy.argtypes = [P, P]
     L.lt_trace_forward_rv.argtypes = [P, C.POINTER(TraceCfg), P, P, P]
     L.lt_trace_tangent.argtypes = [P, C.POINTER(TraceCfg), P, I32, I32, P, P]
+    L.lt_fd_map.argtypes = [P, C.POINTER(TraceCfg), P, I32, I32, C.c_float, P, P, P]
     L.lt_trace_adjoint_rv.argtypes = [P, C.POINTER(TraceCfg), P, P, P]
     L.lt_trace_forward_dir.argtypes = [P, C.POINTER(TraceCfg), P, I32, I32, P, P]
     L.lt_trace_adjoint_dir.argtypes = [P, C.POINTER(TraceCfg), P, I32, I32, P, P, P]
@@ -307,6 +308,21 @@ class Context:
         self._check(self.lib.lt_trace_tangent(self.h, C.byref(cfg), _ptr(params), int(light), int(param), _ptr(T),
                                               _ptr(D)))
         return D, T
+
+    def fd_map(self, params, cfg, light, param, h):
+        """Central-difference map (E(p_j + h) - E(p_j - h)) / step of global
+        light `light` over the texels of its layout, common random numbers:
+        [K] float32."""
+        torch = self._torch
+        self._dev(params, torch.float32, (self.n_lights, 6))
+        n = (self.n_layouts, self.n_texels)
+        Sp = torch.empty(n, dtype=torch.int64, device=params.device)
+        Sm = torch.empty(n, dtype=torch.int64, device=params.device)
+        F = torch.empty(self.n_texels, dtype=torch.float32, device=params.device)
+        self._stream()
+        self._check(self.lib.lt_fd_map(self.h, C.byref(cfg), _ptr(params), int(light), int(param), float(h), _ptr(Sp),
+                                       _ptr(Sm), _ptr(F)))
+        return F
 
     def trace_forward_rv(self, params, cfg, S=None, E=None):
         """Rotation-vector orientation, params [L,7] = (x, y, z, theta, P): (E, S)."""

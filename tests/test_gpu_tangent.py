@@ -108,3 +108,65 @@ def test_tangent_invalid_arguments(torch_dev):
         ctx.trace_tangent(p_d, ctx.cfg(1, 1 << 12, 3), 0, 6)                   # parameter out of range
     with pytest.raises(LtError):
         ctx.trace_tangent(p_d, ctx.cfg(1, 1 << 12, 3, linear=True), 0, 0)      # box basis only
+
+
+def fd_reference(oracle_lib, osc, ol, params, seed, N, B, light, param, h, layout):
+    """Central differences from two oracle primal passes, in the arithmetic
+    the map states: FP32 p +- h, FP64 step, exact int64 difference."""
+    pp, pm = params.astype(np.float32).copy(), params.astype(np.float32).copy()
+    pp[light, param] = pp[light, param] + np.float32(h)
+    pm[light, param] = pm[light, param] - np.float32(h)
+    Sp, _ = oracle_lib.forward(osc, ol, pp, seed, N, B)
+    Sm, _ = oracle_lib.forward(osc, ol, pm, seed, N, B)
+    step = np.float64(pp[light, param]) - np.float64(pm[light, param])
+    return (((Sp[layout] - Sm[layout]).astype(np.float64) * 2.0 ** -32) / step).astype(np.float32)
+
+
+@pytest.mark.parametrize("case", ["box_room", "office_reduced"])
+def test_fd_map_matches_oracle(torch_dev, oracle_lib, case):
+    """Central-difference map on the GPU vs two oracle primal passes:
+    bit-identical (box room at full size, a spot's x and tilt; the office at
+    2^18 paths, one area light's y, with the bench.py launch tuning)."""
+    torch = torch_dev
+    from paper_2310_02043_amd import Context
+    if case == "box_room":
+        c = li.box_room()
+        N, use_bvh, cases, tuning = c["paths"], False, [(0, 0, 0.05), (0, 3, 0.02)], None
+    else:
+        c = li.office()
+        N, use_bvh, cases = 1 << 18, True, [(6, 1, 0.05)]
+        tuning = bench_tuning(c["scene"], c["lights"], c["paths"], c["max_hits"])
+    sc, lights, seed, B = c["scene"], c["lights"], c["seed"], c["max_hits"]
+    ctx = Context(0)
+    ctx.upload_scene(sc.verts, sc.tris, sc.tri_patch, sc.patches)
+    ctx.set_lights(lights.static, lights.layout_offsets)
+    if tuning:
+        ctx.set_tuning(**tuning)
+    osc, ol = oracle_lib.OracleScene(sc, use_bvh=use_bvh), oracle_lib.OracleLights(lights)
+    p_d = torch.tensor(lights.params, device="cuda")
+    cfg = ctx.cfg(seed, N, B)
+    layout_of = np.searchsorted(np.asarray(lights.layout_offsets), np.arange(lights.n_lights), side="right") - 1
+    for l, j, h in cases:
+        F_d = ctx.fd_map(p_d, cfg, l, j, h)
+        assert ctx.sync() == 0
+        F_ref = fd_reference(oracle_lib, osc, ol, lights.params, seed, N, B, l, j, h, layout_of[l])
+        F_d = F_d.cpu().numpy()
+        say(f"  light {l} parameter {j} h {h}: bit-identical {np.mean(F_d == F_ref) * 100:.4f} %, "
+            f"nonzero {np.count_nonzero(F_ref)}")
+        assert np.array_equal(F_d, F_ref)
+
+
+def test_fd_map_invalid_arguments(torch_dev):
+    torch = torch_dev
+    from paper_2310_02043_amd import Context
+    from paper_2310_02043_amd.native import LtError
+    c1 = li.box_room()
+    sc, lights = c1["scene"], c1["lights"]
+    ctx = Context(0)
+    ctx.upload_scene(sc.verts, sc.tris, sc.tri_patch, sc.patches)
+    ctx.set_lights(lights.static, lights.layout_offsets)
+    p_d = torch.tensor(lights.params, device="cuda")
+    cfg = ctx.cfg(1, 1 << 12, 3)
+    for args in ((0, 0, 0.0), (0, 0, float("nan")), (0, 0, -1e-2), (lights.n_lights, 0, 1e-2), (0, 6, 1e-2)):
+        with pytest.raises(LtError):
+            ctx.fd_map(p_d, cfg, *args)

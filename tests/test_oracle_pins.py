@@ -1363,3 +1363,42 @@ def test_mlp_backprop_matches_finite_differences():
         assert abs(fd - gx[r, c]) < 1e-6 + 1e-5 * abs(gx[r, c])
     # a softmax cross-entropy lower bound: loss >= entropy of the target
     assert loss >= float(-(t * np.log(t)).sum() / L) - 1e-9
+
+
+def test_tangent_vs_central_differences_convex_room(oracle_lib):
+    """In a convex room (no shadow edges to sweep) the direct-differentiation
+    map and central differences of the primal with common random numbers
+    estimate the same derivative: their seed means agree patch by patch
+    within the noise the seeds show, for a spot's x and tilt, while the
+    derivative itself stands well above that noise."""
+    sb = li.SceneBuilder()
+    sb.boxes([0, 0, 0], [4.0, 3.0, 2.5], 0.6, res=(12, 12))
+    sc = sb.build("empty_room", fixed_res=(12, 12))
+    p = np.array([[1.6, 1.2, 2.0, 0.3, -0.2, 40.0]], np.float32)
+    lights = make_lights([SPOT], [3.0], [(0, 0)], [0], p)
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    N, B, n_seeds = 1 << 16, 3, 8
+    ends = np.cumsum(sc.patch_res().prod(1))
+    starts = np.concatenate([[0], ends[:-1]])
+    A = sc.texel_area().astype(np.float64)
+
+    def per_patch(E):           # d(flux)/dp of each patch
+        return np.add.reduceat(E * A, starts)
+
+    for j, h in ((0, 0.05), (3, 0.02)):
+        T, F = [], []
+        for s in range(n_seeds):
+            seed = 0x600 + s
+            T.append(per_patch(oracle_lib.tangent(osc, ol, p, seed, N, B, 0, j).astype(np.float64) * 2.0 ** -32))
+            pp, pm = p.copy(), p.copy()
+            pp[0, j] += h
+            pm[0, j] -= h
+            Sp, _ = oracle_lib.forward(osc, ol, pp, seed, N, B)
+            Sm, _ = oracle_lib.forward(osc, ol, pm, seed, N, B)
+            step = float(np.float64(pp[0, j]) - np.float64(pm[0, j]))
+            F.append(per_patch((Sp[0] - Sm[0]).astype(np.float64) * 2.0 ** -32 / step))
+        T, F = np.array(T), np.array(F)
+        noise = math.sqrt(np.sum(T.var(0, ddof=1) + F.var(0, ddof=1)) / n_seeds)
+        err = np.linalg.norm(T.mean(0) - F.mean(0))
+        assert err < 3 * noise, (j, err, noise)
+        assert np.linalg.norm(T.mean(0)) > 5 * noise, (j, np.linalg.norm(T.mean(0)), noise)
