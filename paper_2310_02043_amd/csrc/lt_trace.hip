@@ -469,7 +469,7 @@ __device__ __forceinline__ float linear_gather(const float* __restrict__ g, cons
     return ((wb[0] * g[kb[0]] + wb[1] * g[kb[1]]) + wb[2] * g[kb[2]]) + wb[3] * g[kb[3]];
 }
 
-// Directional texels: 2pi-normalised hemispherical harmonics up to order 2
+// Directional texels: 2pi-normalised hemispherical harmonics up to order 3
 // (associated Legendre functions of x = 2 cos(theta) - 1 times cos / sin of
 // m phi, index l^2 + l + m), and a Lambertian + normalised Phong BRDF in the
 // local frame (normal = z) with its gradient w.r.t. the incident direction.
