@@ -105,6 +105,9 @@ def lib():
         L.or_tangent.restype = C.c_int64
         L.or_adjoint_rv.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int, P, P]
         L.or_adjoint_rv.restype = C.c_int64
+        L.or_adjoint_cone.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int, P, P, P]
+        L.or_adjoint_cone.restype = C.c_int64
+        L.or_first_hit_dlog_cone.argtypes = [P, P, C.c_int, P, P, P, P]
         L.or_rotvec.argtypes = [P, P, P]
         L.or_record.argtypes = [P, P, P, C.c_uint64, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int64,
                                 C.c_int64, P, P, P, P, P]
@@ -421,6 +424,33 @@ def first_hit_dlog(ol: OracleLights, params, light: int, x1, y, n1, au=0.0, av=0
     lib().or_first_hit_dlog(C.byref(ol.c), prm.ctypes.data, int(light), a[0].ctypes.data, a[1].ctypes.data,
                             a[2].ctypes.data, float(au), float(av), out.ctypes.data)
     return out
+
+
+def first_hit_dlog_cone(ol: OracleLights, params, light: int, x1, y, n1):
+    """dlog of the first-hit kernel with the cone angles: [8] (x, y, z, alpha,
+    beta, P, theta_in, theta_out); the last two are 0 unless soft-edged spot."""
+    prm = np.ascontiguousarray(params, np.float32)
+    a = [np.ascontiguousarray(v, np.float32) for v in (x1, y, n1)]
+    out = np.zeros(8, np.float32)
+    lib().or_first_hit_dlog_cone(C.byref(ol.c), prm.ctypes.data, int(light), a[0].ctypes.data, a[1].ctypes.data,
+                                 a[2].ctypes.data, out.ctypes.data)
+    return out
+
+
+def adjoint_cone(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,
+                 dOdE, n_threads: int = 0):
+    """Adjoint with the soft-edged spots' cone angles: (grad [L,6],
+    grad_cone [L,2] = dO/d(theta_in, theta_out), misses)."""
+    if ol.colour is not None or ol.rotvec or osc.dir_order >= 0 or osc.c.basis != 0:
+        raise ValueError("cone-angle gradients take grey light, tilt angles, box irradiance texels")
+    prm = np.ascontiguousarray(params, np.float32)
+    g = np.ascontiguousarray(dOdE, np.float32)
+    grad = np.zeros((ol.n_lights, 6))
+    gc = np.zeros((ol.n_lights, 2))
+    m = lib().or_adjoint_cone(C.byref(osc.c), C.byref(ol.c), prm.ctypes.data, int(seed) & 0xFFFFFFFFFFFFFFFF,
+                              int(paths_per_layout), int(max_hits), int(n_threads), g.ctypes.data,
+                              grad.ctypes.data, gc.ctypes.data)
+    return grad, gc, m
 
 
 def num_threads() -> int:

@@ -498,6 +498,9 @@ typedef struct {
     int rgb;               /* colour mode */
     float col[3];          /* channel weights of the flux */
     int rv;                /* rotation-vector orientation (7 parameters) */
+    int cone;              /* soft-edged spot: also differentiate the cone angles (dl[6], dl[7]) */
+    float ki, ko;          /* dlog I_e / d(theta_in), d(theta_out) at constant power */
+    float kri, kq, so;     /* 2 sin(theta_in) / (ci - co), 2 / (ci - co), sin(theta_out) */
 } olight;
 
 /* Rodrigues' formula R = I + sin(phi)/phi K + (1 - cos(phi))/phi^2 K^2, K = [theta]x,
@@ -542,6 +545,7 @@ static void rot_jacobian(const double* th, double J[9])
 static void light_setup(const or_lights* Ls, const float* params, int gl, int64_t n_paths, olight* L)
 {
     const float* p = params + (Ls->rotvec ? 7 : 6) * gl;
+    L->cone = 0;
     L->type = Ls->type[gl];
     L->n = Ls->lobe_n[gl];
     L->w = Ls->size[2 * gl];
@@ -590,8 +594,17 @@ static void light_setup(const or_lights* Ls, const float* params, int gl, int64_
         or_sincos_f64((double)L->h, &so_d, &co_d);
         L->ci = (float)ci_d;
         L->co = (float)co_d;
-        float kcap = (float)((1.0 - co_d) / ((1.0 - ci_d) + (ci_d - co_d) / 3.0));
+        double den = (1.0 - ci_d) + (ci_d - co_d) / 3.0;
+        float kcap = (float)((1.0 - co_d) / den);
         L->phi_r = L->phi_r * kcap;
+        /* cone-angle derivatives at constant P: I_e = P / (2 pi den) gives
+         * dlog I_e/dci = (2/3)/den and dlog I_e/dco = (1/3)/den; with
+         * dci = -sin(theta_in) dtheta_in, dco = -sin(theta_out) dtheta_out */
+        L->ki = (float)(-(si_d * (2.0 / 3.0)) / den);
+        L->ko = (float)(-(so_d * (1.0 / 3.0)) / den);
+        L->kq = (float)(2.0 / (ci_d - co_d));
+        L->kri = (float)(2.0 * si_d / (ci_d - co_d));
+        L->so = (float)so_d;
     }
 }
 
@@ -625,12 +638,22 @@ static void first_hit_dlog(const olight* L, const float* x1, const float* y, con
     const int np = L->rv ? 7 : 6;
     for (int c = 0; c < np - 1; ++c) dl[c] = 0.0f;
     dl[np - 1] = 1.0f / L->P;
+    if (L->cone) dl[6] = dl[7] = 0.0f;
     float v[3] = {x1[0] - y[0], x1[1] - y[1], x1[2] - y[2]};
     float r2 = dot3(v, v);
     if (r2 <= 1e-12f) return;
     float r = sqrtf(r2);
     float inv_r = 1.0f / r;
     float w[3] = {v[0] * inv_r, v[1] * inv_r, v[2] * inv_r};
+    if (L->cone && L->type == 3) {
+        /* log a = 2 log(ce - co) - 2 log(ci - co) in the fall-off ring, 0
+         * inside the inner cone; the intensity's log-derivatives in the
+         * direction of x_1, which stays fixed */
+        float cw = dot3(L->d, w);
+        int ring = cw > L->co && cw < L->ci;
+        dl[6] = ring ? L->ki + L->kri : L->ki;
+        dl[7] = ring ? L->ko + L->so * (2.0f / (cw - L->co) - L->kq) : L->ko;
+    }
     float c1 = -dot3(n1, w);
     if (c1 <= 1e-6f) return;
     float k1 = 1.0f / (r * c1);
@@ -869,8 +892,8 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
     int32_t skip = -1;
     float T = 1.0f;
     float s_r = 0.0f;
-    float dphi[7] = {0, 0, 0, 0, 0, 0, 0};
-    const int NP = L->rv ? 7 : 6;
+    float dphi[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int NP = L->rv ? 7 : (L->cone ? 8 : 6);
     float tdl = 0.0f;      /* direct differentiation: dlog_j of the first hit */
     int hits = 0;
     int64_t k1 = -1;
@@ -987,7 +1010,7 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
                 if (h >= 2) Rd = Rd + P * T2;
                 if (h == 1) {
                     k1 = k;
-                    float dl[7];
+                    float dl[8];
                     first_hit_dlog(L, x, y, no, au, av, dl);
                     for (int c = 0; c < NP; ++c) dphi[c] = phi_r * dl[c];
                     float sq = (inv_np * inv_a);
@@ -1030,7 +1053,7 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
              * hit of the path adds d(Phi_h / A)/dp_j = (Phi_h / A) dlog_j of
              * its first hit, in its own texel */
             if (h == 1) {
-                float dl[7];
+                float dl[8];
                 first_hit_dlog(L, x, y, no, au, av, dl);
                 tdl = dl[io->tangent_param];
             }
@@ -1052,7 +1075,7 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
             }
             if (h == 1) {
                 k1 = k;
-                float dl[7];
+                float dl[8];
                 first_hit_dlog(L, x, y, no, au, av, dl);
                 for (int c = 0; c < NP; ++c) dphi[c] = phi_r * dl[c];
             }
@@ -1107,7 +1130,7 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
             for (int ch = 0; ch < 3; ++ch) io->acc_col[ch] += (double)(sc[ch] * phi_r);
     }
     if (io->g && hits >= 1) {
-        float cr[7];
+        float cr[8];
         float ub_[3] = {0, 0, 0};
         float dya[3] = {0, 0, 0}, dyb[3] = {0, 0, 0};
         if (dirm) {
@@ -1253,6 +1276,61 @@ EXPORT int64_t or_adjoint(const or_scene* S, const or_lights* Ls, const float* p
 /* Adjoint light tracing with rotation-vector orientation (Sec. 4.4.2):
  * params [L,7] = (x, y, z, theta, P); grad_out [L,7] FP64 = dO/d(x, y, z,
  * theta, P), the per-path world-rotation derivatives mapped through J^T. */
+/* Adjoint with the soft-edged spots' cone angles: grad_out [L,6] as
+ * or_adjoint, grad_cone [L,2] = dO/d(theta_in, theta_out) (0 for other
+ * luminaire types).  Grey, box basis, irradiance texels, tilt angles. */
+EXPORT int64_t or_adjoint_cone(const or_scene* S, const or_lights* Ls, const float* params, uint64_t seed,
+                               int64_t paths_per_layout, int max_hits, int n_threads, const float* dOdE,
+                               double* grad_out, double* grad_cone)
+{
+    if (Ls->rotvec || Ls->colour || S->dir_order >= 0 || S->basis != 0) return -1;
+    int64_t misses = 0;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+    for (int j = 0; j < Ls->n_layouts; ++j) {
+        int l0 = Ls->layout_offsets[j], l1 = Ls->layout_offsets[j + 1];
+        for (int gl = l0; gl < l1; ++gl) {
+            olight L;
+            int64_t nl = paths_of_light(paths_per_layout, l1 - l0, gl - l0);
+            light_setup(Ls, params, gl, nl, &L);
+            L.cone = 1;
+            double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, a6 = 0, a7 = 0;
+            int64_t m = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : a0, a1, a2, a3, a4, a5, a6, a7, m)
+#endif
+            for (int64_t i = 0; i < nl; ++i) {
+                double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+                path_io io;
+                memset(&io, 0, sizeof(io));
+                io.g = dOdE + (int64_t)j * S->n_texels;
+                io.acc = acc;
+                trace_path(S, &L, j, gl - l0, gl, (uint32_t)i, seed, max_hits, NULL, &io);
+                a0 += acc[0]; a1 += acc[1]; a2 += acc[2]; a3 += acc[3];
+                a4 += acc[4]; a5 += acc[5]; a6 += acc[6]; a7 += acc[7];
+                m += io.misses;
+            }
+            a[0] = a0; a[1] = a1; a[2] = a2; a[3] = a3; a[4] = a4; a[5] = a5; a[6] = a6; a[7] = a7;
+            for (int c = 0; c < 6; ++c) grad_out[6 * (int64_t)gl + c] = a[c];
+            grad_cone[2 * (int64_t)gl] = a[6];
+            grad_cone[2 * (int64_t)gl + 1] = a[7];
+            misses += m;
+        }
+    }
+    return misses;
+}
+
+EXPORT void or_first_hit_dlog_cone(const or_lights* Ls, const float* params, int gl, const float* x1,
+                                   const float* y, const float* n1, float* dl)
+{
+    olight L;
+    light_setup(Ls, params, gl, 1, &L);
+    L.cone = 1;
+    first_hit_dlog(&L, x1, y, n1, 0.0f, 0.0f, dl);
+}
+
 EXPORT int64_t or_adjoint_rv(const or_scene* S, const or_lights* Ls, const float* params, uint64_t seed,
                              int64_t paths_per_layout, int max_hits, int n_threads, const float* dOdE,
                              double* grad_out)

@@ -260,7 +260,9 @@ def log_irradiance(kind, n, p, x1, n1, au=0.0, av=0.0, size=None, R=None):
     w = v / r
     val = np.log(p[5]) + np.log(-np.dot(n1, w)) - 2 * np.log(r)
     if kind == 3:
-        val += np.log(soft_profile(np.dot(d, w), size[0], size[1])[0])
+        # intensity P a(cos) / (2 pi norm): the normalisation depends on the cones
+        a, norm = soft_profile(np.dot(d, w), size[0], size[1])
+        val += np.log(a) - np.log(norm)
     elif kind != 0:
         val += n * np.log(np.dot(d, w))
     return val

@@ -1402,3 +1402,94 @@ def test_tangent_vs_central_differences_convex_room(oracle_lib):
         err = np.linalg.norm(T.mean(0) - F.mean(0))
         assert err < 3 * noise, (j, err, noise)
         assert np.linalg.norm(T.mean(0)) > 5 * noise, (j, np.linalg.norm(T.mean(0)), noise)
+
+
+# --------------------------------------------------------------------------
+# soft-edged spot: derivatives w.r.t. the cone angles
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("size", [(0.3, 1.2), (0.0, 0.7), (0.5, 0.55)])
+def test_cone_first_hit_derivative(oracle_lib, size):
+    """dlog of the first-hit kernel w.r.t. (theta_in, theta_out) at constant
+    power vs central differences of an independent log-intensity (profile and
+    normalisation) in the fixed direction of x_1, in the fall-off ring and
+    inside the inner cone; the other six entries are those of the plain call."""
+    rng = np.random.default_rng(int(size[1] * 100))
+    ci, co = math.cos(size[0]), math.cos(size[1])
+    done, ring = 0, 0
+    while done < 24:
+        p = [rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(1.5, 2.5),
+             rng.uniform(-0.4, 0.4), rng.uniform(-0.4, 0.4), rng.uniform(10, 100)]
+        lights = make_lights([SOFT], [0.0], [size], [0], [p])
+        ol = oracle_lib.OracleLights(lights)
+        pf = np.asarray(lights.params[0], np.float64)
+        d, t, b = cf.frame(pf[3], pf[4])
+        y = pf[:3]
+        # a direction inside the outer cone (half of them in the ring), a
+        # receiver along it facing back towards the light
+        ct = rng.uniform(co, ci) if (done % 3 != 2 or size[0] == 0) else rng.uniform(ci, 1.0)
+        if ct <= co + 1e-3 or abs(ct - ci) < 1e-3:
+            continue
+        ph = rng.uniform(0, 2 * math.pi)
+        st = math.sqrt(1 - ct * ct)
+        w = ct * d + st * (math.cos(ph) * t + math.sin(ph) * b)
+        x1 = y + rng.uniform(0.5, 3.0) * w
+        n1 = -w + rng.normal(size=3) * 0.2
+        n1 /= np.linalg.norm(n1)
+        cw = float(np.dot(d, (x1 - y) / np.linalg.norm(x1 - y)))
+        done += 1
+        ring += cw < math.cos(size[0])
+        args = (x1.astype(np.float32), y.astype(np.float32), n1.astype(np.float32))
+        dl = oracle_lib.first_hit_dlog_cone(ol, lights.params, 0, *args).astype(np.float64)
+        assert np.array_equal(dl[:6], oracle_lib.first_hit_dlog(ol, lights.params, 0, *args))
+        for c in range(2):
+            h = 1e-6
+            sp, sm = list(size), list(size)
+            sp[c] += h
+            sm[c] -= h
+            if sm[0] < 0:           # theta_in = 0: one-sided
+                sm[0] = 0.0
+            fd = (cf.log_irradiance(SOFT, 0.0, pf, x1, n1, size=sp) -
+                  cf.log_irradiance(SOFT, 0.0, pf, x1, n1, size=sm)) / (sp[c] - sm[c])
+            assert abs(dl[6 + c] - fd) <= 2e-4 * (abs(fd) + 1.0), (size, c, cw, dl[6 + c], fd)
+    assert ring == 16 if size[0] > 0 else ring == done
+
+
+def test_cone_gradient_vs_quadrature(oracle_lib):
+    """Direct light of a soft-edged spot on a plane: the seed mean of the
+    adjoint's dO/d(theta_in, theta_out) matches central differences of the
+    quadrature expectation of O's linear part sum_k g_k E_k in the cone
+    angles (at constant power), and the position and tilt gradients of the
+    cone call equal the plain adjoint's."""
+    half, res, N, n_seeds = 3.0, 12, 1 << 16, 8
+    sc = li.plane_scene(half=half, res=res)
+    p = np.array([0.3, -0.2, 1.4, 0.25, -0.15, 40.0])
+    size = (0.35, 0.9)
+    lights = make_lights([SOFT], [0.0], [size], [0], [p])
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    A = float(sc.texel_area()[0])
+    # weight on the texels near the axis: widening either cone at constant
+    # power moves flux away from them
+    d, _, _ = cf.frame(p[3], p[4])
+    xa = p[:2] + d[:2] * (p[2] / -d[2])
+    x0, x1, y0, y1 = cf.plane_texels(half, res)
+    cx, cy = (x0 + x1) / 2, (y0 + y1) / 2
+    g = np.exp(-((cx - xa[0]) ** 2 + (cy - xa[1]) ** 2) / 0.5).astype(np.float32)[None]
+    ref = np.zeros(2)
+    for c in range(2):
+        h = 1e-4
+        sp, sm = list(size), list(size)
+        sp[c] += h
+        sm[c] -= h
+        # the inner cone's kink crosses texels: a fine rule (converged to 1e-3)
+        Ep = cf.plane_hit_probability(SOFT, 0.0, p, sp, half, res, q_tex=64) * p[5] / A
+        Em = cf.plane_hit_probability(SOFT, 0.0, p, sm, half, res, q_tex=64) * p[5] / A
+        ref[c] = float(np.dot(g[0].astype(np.float64), Ep - Em)) / (2 * h)
+    runs = [oracle_lib.adjoint_cone(osc, ol, lights.params, 0xC0 + s, N, 1, g) for s in range(n_seeds)]
+    gc = np.array([r[1][0] for r in runs])
+    mean, se = gc.mean(0), gc.std(0, ddof=1) / math.sqrt(n_seeds)
+    for c in range(2):
+        assert abs(mean[c] - ref[c]) < 4 * se[c] + 2e-3 * abs(ref[c]), (c, mean[c], ref[c], se[c])
+        assert abs(ref[c]) > 8 * se[c], (c, ref[c], se[c])
+    g0, _ = oracle_lib.adjoint(osc, ol, lights.params, 0xC0, N, 1, g)
+    assert np.allclose(runs[0][0], g0, rtol=1e-9, atol=0)      # FP64 sums in thread order
