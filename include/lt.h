@@ -215,6 +215,15 @@ int lt_trace_tangent(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params
 int lt_fd_map(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, int32_t light, int32_t param, float h,
               int64_t* d_Sp, int64_t* d_Sm, float* d_F);
 
+/* Adjoint with the soft-edged spots' cone angles (supplement, spot light:
+ * the derivatives of the fall-off w.r.t. the cone angles, with x_1 fixed).
+ * d_grad [L,6] f32 as lt_trace_adjoint (the same sums); d_grad_cone [L,2] f32
+ * = dO/d(theta_in, theta_out) in radians at constant total power P, 0 for
+ * other luminaire types.  The angles themselves are the size_w / size_h of
+ * lt_set_lights.  Plain emission, box basis, grey, tilt angles. */
+int lt_trace_adjoint_cone(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, const float* d_dOdE,
+                          float* d_grad, float* d_grad_cone);
+
 /* Colour (Sec. 4.4.3, intensity and colour).  A luminaire's flux is split
  * over three channels by weights d_colour [L,3] f32 (channel ch carries
  * P c_ch; the optimiser may keep r + g + b = 1, the chromaticity

@@ -84,6 +84,10 @@ struct lt_ctx {
     double* d_partials7 = nullptr;    // rotation-vector adjoint: [n_tiles,7] partial sums
     float* d_pfd = nullptr;           // central differences: p+ [L,6], p- [L,6], step (f64)
     int pfd_cap = 0;                  // lights d_pfd holds
+    double* d_partials8 = nullptr;    // cone-angle adjoint: [n_tiles,8] partial sums
+    size_t partials8_cap = 0;
+    float* d_cone = nullptr;          // cone-angle adjoint: [L,5] per-light constants
+    int cone_cap = 0;
     size_t partials7_cap = 0;
 
     lt_tuning tune;
@@ -426,6 +430,7 @@ void lt_destroy(lt_ctx* c)
     hipFree(c->d_misses); hipFree(c->d_flags); hipFree(c->d_stats);
     hipFree(c->d_objpart); hipFree(c->d_partials); hipFree(c->d_gstack); hipFree(c->d_ptgrad);
     hipFree(c->d_partials_col); hipFree(c->d_partials7); hipFree(c->d_pfd);
+    hipFree(c->d_partials8); hipFree(c->d_cone);
     if (c->ev_in) hipEventDestroy(c->ev_in);
     if (c->ev_out) hipEventDestroy(c->ev_out);
     if (c->gstream) hipStreamDestroy(c->gstream);
@@ -858,6 +863,7 @@ int lt_fd_map(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int32_t
     rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
     if (rc) return rc;
     if (c->pfd_cap < c->L) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
         free_graphs(c);
         hipFree(c->d_pfd);
         c->d_pfd = nullptr;
@@ -953,6 +959,53 @@ int lt_trace_adjoint_rv(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_param
         return e;
     };
     return run_seq(c, graph, make_key(c, 10, cfg, {d_params, d_dOdE, d_grad}), body);
+}
+
+int lt_trace_adjoint_cone(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, const float* d_dOdE,
+                          float* d_grad, float* d_grad_cone)
+{
+    int rc = check_cfg(c, cfg);
+    if (rc) return rc;
+    if (!d_params || !d_dOdE || !d_grad || !d_grad_cone) return fail(c, LT_EINVAL, "NULL device buffer");
+    if (cfg->flags & (LT_FLAG_PROPOSAL | LT_FLAG_LINEAR))
+        return fail(c, LT_EINVAL, "cone-angle gradients take the plain emission and the box basis only");
+    HIPCHK(c, hipSetDevice(c->device));
+    const long long blocks = trace_blocks(c);
+    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    if (rc) return rc;
+    const size_t need = (size_t)std::max(c->n_tiles, 1) * 8;
+    if (c->partials8_cap < need || c->cone_cap < c->L) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        free_graphs(c);
+        if (c->partials8_cap < need) {
+            hipFree(c->d_partials8);
+            c->d_partials8 = nullptr;
+            c->partials8_cap = 0;
+            HIPCHK(c, hipMalloc(&c->d_partials8, sizeof(double) * need));
+            c->partials8_cap = need;
+        }
+        if (c->cone_cap < c->L) {
+            hipFree(c->d_cone);
+            c->d_cone = nullptr;
+            c->cone_cap = 0;
+            HIPCHK(c, hipMalloc(&c->d_cone, sizeof(float) * 5 * c->L));
+            c->cone_cap = c->L;
+        }
+    }
+    TraceArgs a = trace_args(c, cfg);
+    a.g = d_dOdE;
+    a.partials = c->d_partials8;
+    a.cone = c->d_cone;
+    const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
+    auto body = [&](hipStream_t st) -> hipError_t {
+        hipError_t e =
+            launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st, 0, c->d_cone);
+        if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
+        if (e == hipSuccess)
+            e = launch_grad_reduce_cone(c->d_partials8, c->d_range, c->L, d_grad, d_grad_cone, st);
+        return e;
+    };
+    return run_seq(c, graph, make_key(c, 13, cfg, {d_params, d_dOdE, d_grad, d_grad_cone}), body);
 }
 
 int lt_set_glossy(lt_ctx* c, const float* h_glossy)

@@ -59,6 +59,9 @@ struct TraceArgs {
     long long* tangent;
     int tan_light;
     int tan_param;
+    // soft-edged spots' cone angles (adjoint: [n_tiles,8] partials), [L,5]
+    // per-light constants written by the light setup, may be null
+    const float* cone;
     // orientation as a rotation vector (adjoint: [n_tiles,7] partials)
     int rotvec;
     // directional texels: HSH order 0..2 (-1: irradiance texels), local
@@ -133,7 +136,10 @@ hipError_t launch_trace(bool adjoint, bool stats, const TraceArgs& a, int waves_
                         int blocks, hipStream_t st);
 hipError_t launch_record(const RecordArgs& a, int lds_depth, hipStream_t st);
 hipError_t launch_light_setup(const float* params, const int4* lstat_i, const float4* lstat_f,
-                              const long long* npaths, int n_lights, DevLight* out, hipStream_t st, int rv = 0);
+                              const long long* npaths, int n_lights, DevLight* out, hipStream_t st, int rv = 0,
+                              float* cone = nullptr);
+hipError_t launch_grad_reduce_cone(const double* partials, const int2* range, int n_lights, float* grad,
+                                   float* gcone, hipStream_t st);
 hipError_t launch_grad_reduce_rv(const double* partials, const int2* range, const float* params, int n_lights,
                                  float* grad, hipStream_t st);
 hipError_t launch_clear(long long* S, long long n_texels_total, hipStream_t st);

@@ -469,6 +469,28 @@ __device__ __forceinline__ float linear_gather(const float* __restrict__ g, cons
     return ((wb[0] * g[kb[0]] + wb[1] * g[kb[1]]) + wb[2] * g[kb[2]]) + wb[3] * g[kb[3]];
 }
 
+// Soft-edged spot: dlog of the intensity in the fixed direction of x_1 w.r.t.
+// the inner and outer cone angles at constant power.  cone = (dlog I_e/dtheta_in,
+// dlog I_e/dtheta_out, 2/(ci - co), 2 sin(theta_in)/(ci - co), sin(theta_out));
+// in the fall-off ring log a = 2 log(cos - co) - 2 log(ci - co) adds its terms.
+__device__ __forceinline__ void cone_dlog(const DevLight& L, const float* __restrict__ cone, V3 x1, V3 y,
+                                          float& d_in, float& d_out)
+{
+    d_in = 0.0f;
+    d_out = 0.0f;
+    if (L.type != 3) return;
+    const V3 v = sub(x1, y);
+    const float r2 = dot(v, v);
+    if (r2 <= 1e-12f) return;
+    const float r = __builtin_sqrtf(r2);
+    const float inv_r = 1.0f / r;
+    const V3 w = v3(v.x * inv_r, v.y * inv_r, v.z * inv_r);
+    const float cw = dot(v3(L.d[0], L.d[1], L.d[2]), w);
+    const bool ring = cw > L.h && cw < L.w;
+    d_in = ring ? cone[0] + cone[3] : cone[0];
+    d_out = ring ? cone[1] + cone[4] * (2.0f / (cw - L.h) - cone[2]) : cone[1];
+}
+
 // Directional texels: 2pi-normalised hemispherical harmonics up to order 3
 // (associated Legendre functions of x = 2 cos(theta) - 1 times cos / sin of
 // m phi, index l^2 + l + m), and a Lambertian + normalised Phong BRDF in the
@@ -575,14 +597,15 @@ __device__ __forceinline__ long long xcd_block(long long b, long long nb, int re
 // registers), 3 directional texels (hemispherical-harmonic coefficients of
 // the reflected radiance and a glossy BRDF; the adjoint's first-hit BRDF
 // terms live in LDS), 4 rotation-vector orientation (seven derivatives),
-// 5 the direct-differentiation map of one luminaire (forward only).
+// 5 the direct-differentiation map of one luminaire (forward only), 6 the
+// soft-edged spots' cone angles (adjoint, eight derivatives).
 template <bool ADJ, bool STATS, int WPB, int LDS_D, int MODE>
 __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(MODE == 3 ? 4 : 5))) k_trace(TraceArgs a)
 {
     __shared__ int s_stack[WPB * LDS_D * 64];
     // adjoint per-lane state read once per path (first-hit derivative
     // factors, running contribution sums), kept in LDS instead of registers
-    constexpr int NPAR = MODE == 4 ? 7 : 6;   // 4: rotation-vector orientation
+    constexpr int NPAR = MODE == 4 ? 7 : (MODE == 6 ? 8 : 6);   // 4: rotation vector, 6: cone angles
     __shared__ float s_adj[ADJ ? WPB * 2 * NPAR * 64 : 1];
     // adjoint with a gradient-contribution map: texel of the first hit
     __shared__ int s_k1[ADJ ? WPB * 64 : 1];
@@ -863,6 +886,8 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(M
                         if (h == 1) {
                             float dl[NPAR];
                             first_hit_dlog<MODE == 4>(L, hi.x, v3(r.ox, r.oy, r.oz), hi.no, au, av, dl);
+                            if constexpr (MODE == 6)
+                                cone_dlog(L, a.cone + 5 * ti.x, hi.x, v3(r.ox, r.oy, r.oz), dl[6], dl[7]);
 #pragma unroll
                             for (int c = 0; c < NPAR; ++c) adj[c * 64] = phi_r * dl[c];
                             if (vote) *k1 = (int)hi.k;
@@ -1321,7 +1346,7 @@ __device__ void rot_jacobian_f64(const double th[3], double J[9])
 
 __global__ void k_light_setup(const float* __restrict__ params, const int4* __restrict__ si,
                               const float4* __restrict__ sf, const long long* __restrict__ npaths, int n,
-                              DevLight* __restrict__ out, int rv)
+                              DevLight* __restrict__ out, int rv, float* __restrict__ cone)
 {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= n) return;
@@ -1376,6 +1401,16 @@ __global__ void k_light_setup(const float* __restrict__ params, const int4* __re
         const float kcap = (float)((1.0 - co_d) / ((1.0 - ci_d) + (ci_d - co_d) / 3.0));
         L.phi_r = L.phi_r * kcap;
         L.kcap = kcap;
+        if (cone != nullptr) {
+            // cone-angle derivatives at constant P: I_e = P / (2 pi den),
+            // dlog I_e/dci = (2/3)/den, dlog I_e/dco = (1/3)/den, dci = -sin dtheta
+            const double den = (1.0 - ci_d) + (ci_d - co_d) / 3.0;
+            cone[5 * l + 0] = (float)(-(si_d * (2.0 / 3.0)) / den);
+            cone[5 * l + 1] = (float)(-(so_d * (1.0 / 3.0)) / den);
+            cone[5 * l + 2] = (float)(2.0 / (ci_d - co_d));
+            cone[5 * l + 3] = (float)(2.0 * si_d / (ci_d - co_d));
+            cone[5 * l + 4] = (float)so_d;
+        }
     }
     L.layout = i4.y;
     L.l_local = i4.z;
@@ -1513,6 +1548,11 @@ hipError_t launch_wpb(const TraceArgs& a, int lds_depth, int blocks, hipStream_t
             k_trace<ADJ, STATS, WPB, 16, 5><<<blocks, WPB * 64, 0, st>>>(a);
         else
             k_trace<ADJ, STATS, WPB, 32, 5><<<blocks, WPB * 64, 0, st>>>(a);
+    } else if (a.cone != nullptr && ADJ && !STATS) {
+        if (lds_depth == 16)
+            k_trace<ADJ, STATS, WPB, 16, 6><<<blocks, WPB * 64, 0, st>>>(a);
+        else
+            k_trace<ADJ, STATS, WPB, 32, 6><<<blocks, WPB * 64, 0, st>>>(a);
     } else if (a.rotvec && ADJ) {
         if (lds_depth == 16)
             k_trace<ADJ, STATS, WPB, 16, 4><<<blocks, WPB * 64, 0, st>>>(a);
@@ -1606,9 +1646,9 @@ hipError_t launch_record(const RecordArgs& a, int lds_depth, hipStream_t st)
 }
 
 hipError_t launch_light_setup(const float* params, const int4* si, const float4* sf, const long long* npaths,
-                              int n_lights, DevLight* out, hipStream_t st, int rv)
+                              int n_lights, DevLight* out, hipStream_t st, int rv, float* cone)
 {
-    k_light_setup<<<nblocks(n_lights, 64, 1 << 20), 64, 0, st>>>(params, si, sf, npaths, n_lights, out, rv);
+    k_light_setup<<<nblocks(n_lights, 64, 1 << 20), 64, 0, st>>>(params, si, sf, npaths, n_lights, out, rv, cone);
     return hipGetLastError();
 }
 
@@ -1636,6 +1676,34 @@ __global__ void __launch_bounds__(64) k_grad_reduce_rv(const double* __restrict_
         for (int c = 0; c < 3; ++c) grad[7 * l + 3 + c] = (float)((J[c] * acc[3] + J[3 + c] * acc[4]) + J[6 + c] * acc[5]);
         grad[7 * l + 6] = (float)acc[6];
     }
+}
+
+// per light: the eight partial sums of its tiles (FP64) -> grad [L,6] and the
+// cone-angle gradient [L,2]
+__global__ void __launch_bounds__(64) k_grad_reduce_cone(const double* __restrict__ partials,
+                                                         const int2* __restrict__ range, int n_lights,
+                                                         float* __restrict__ grad, float* __restrict__ gcone)
+{
+    const int l = blockIdx.x;
+    if (l >= n_lights) return;
+    const int2 rg = range[l];
+    double acc[8];
+    for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+    for (int t = rg.x + (int)threadIdx.x; t < rg.y; t += 64)
+        for (int c = 0; c < 8; ++c) acc[c] += partials[(long long)t * 8 + c];
+    for (int c = 0; c < 8; ++c) acc[c] = wave_sum(acc[c]);
+    if (threadIdx.x == 0) {
+        for (int c = 0; c < 6; ++c) grad[6 * l + c] = (float)acc[c];
+        gcone[2 * l] = (float)acc[6];
+        gcone[2 * l + 1] = (float)acc[7];
+    }
+}
+
+hipError_t launch_grad_reduce_cone(const double* partials, const int2* range, int n_lights, float* grad,
+                                   float* gcone, hipStream_t st)
+{
+    k_grad_reduce_cone<<<n_lights, 64, 0, st>>>(partials, range, n_lights, grad, gcone);
+    return hipGetLastError();
 }
 
 hipError_t launch_grad_reduce_rv(const double* partials, const int2* range, const float* params, int n_lights,

@@ -23,7 +23,7 @@ EXPORTED = [
     "lt_set_lights", "lt_trace_forward", "lt_objective", "lt_trace_adjoint", "lt_gradient_votes",
     "lt_pt_forward", "lt_pt_adjoint", "lt_set_albedo_rgb", "lt_trace_forward_rgb", "lt_trace_adjoint_rgb",
     "lt_set_glossy", "lt_trace_forward_dir", "lt_trace_adjoint_dir", "lt_trace_forward_rv", "lt_trace_adjoint_rv",
-    "lt_trace_tangent", "lt_fd_map",
+    "lt_trace_tangent", "lt_fd_map", "lt_trace_adjoint_cone",
     "lt_record_paths",
     "lt_trace_stats", "lt_get_tuning", "lt_set_tuning", "lt_autotune", "lt_info_get", "lt_set_timing",
     "lt_timing_read", "lt_proposal_set_table", "lt_proposal_get_table", "lt_proposal_set_scale",
@@ -94,6 +94,7 @@ def load():
     L.lt_trace_forward_rv.argtypes = [P, C.POINTER(TraceCfg), P, P, P]
     L.lt_trace_tangent.argtypes = [P, C.POINTER(TraceCfg), P, I32, I32, P, P]
     L.lt_fd_map.argtypes = [P, C.POINTER(TraceCfg), P, I32, I32, C.c_float, P, P, P]
+    L.lt_trace_adjoint_cone.argtypes = [P, C.POINTER(TraceCfg), P, P, P, P]
     L.lt_trace_adjoint_rv.argtypes = [P, C.POINTER(TraceCfg), P, P, P]
     L.lt_trace_forward_dir.argtypes = [P, C.POINTER(TraceCfg), P, I32, I32, P, P]
     L.lt_trace_adjoint_dir.argtypes = [P, C.POINTER(TraceCfg), P, I32, I32, P, P, P]
@@ -308,6 +309,19 @@ class Context:
         self._check(self.lib.lt_trace_tangent(self.h, C.byref(cfg), _ptr(params), int(light), int(param), _ptr(T),
                                               _ptr(D)))
         return D, T
+
+    def trace_adjoint_cone(self, params, dOdE, cfg):
+        """Adjoint with the soft-edged spots' cone angles: (grad [L,6],
+        grad_cone [L,2] = dO/d(theta_in, theta_out))."""
+        torch = self._torch
+        self._dev(params, torch.float32, (self.n_lights, 6))
+        self._dev(dOdE, torch.float32, (self.n_layouts, self.n_texels))
+        grad = torch.empty((self.n_lights, 6), dtype=torch.float32, device=params.device)
+        gcone = torch.empty((self.n_lights, 2), dtype=torch.float32, device=params.device)
+        self._stream()
+        self._check(self.lib.lt_trace_adjoint_cone(self.h, C.byref(cfg), _ptr(params), _ptr(dOdE), _ptr(grad),
+                                                   _ptr(gcone)))
+        return grad, gcone
 
     def fd_map(self, params, cfg, light, param, h):
         """Central-difference map (E(p_j + h) - E(p_j - h)) / step of global
