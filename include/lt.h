@@ -139,7 +139,8 @@ int lt_sync(lt_ctx* ctx, uint32_t* flags_out);
  * takes from ray-tracing hardware, Sec. 6).  Host arrays: h_verts [n_verts,3]
  * f32, h_tris [n_tris,3] i32 vertex indices, h_tri_patch [n_tris] i32,
  * h_patches [n_patches].  Texel ranges of the patches must tile
- * [0, n_texels) in order; at most 2^28 triangles.  Builds the BVH on the
+ * [0, n_texels) in order; at most 2^26 triangles and 2^25 BVH nodes (the
+ * traversal addresses both by 32-bit byte offsets).  Builds the BVH on the
  * device (Morton order, PLOC clustering, collapse to a 4-wide tree) and the
  * per-texel area table; replaces any previous scene.  *n_texels_out
  * receives K. */

@@ -468,7 +468,8 @@ int lt_scene_upload(lt_ctx* c, const float* h_verts, int64_t n_verts, const int3
     if (!c) return LT_EINVAL;
     if (!h_verts || !h_tris || !h_tri_patch || !h_patches) return fail(c, LT_EINVAL, "NULL scene array");
     if (n_verts < 3 || n_tris < 1 || n_patches < 1) return fail(c, LT_EINVAL, "empty scene");
-    if (n_tris > (1ll << 28) || n_verts > (1ll << 31) - 1) return fail(c, LT_EINVAL, "scene too large");
+    // the traversal addresses triangles (48 B) and nodes (128 B) by 32-bit byte offsets
+    if (n_tris > (1ll << 26) || n_verts > (1ll << 31) - 1) return fail(c, LT_EINVAL, "scene too large");
     double amax = 0.0, lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int64_t v = 0; v < n_verts; ++v) {
         if (!finite3(h_verts + 3 * v)) return fail(c, LT_EINVAL, "non-finite vertex");
@@ -535,6 +536,10 @@ int lt_scene_upload(lt_ctx* c, const float* h_verts, int64_t n_verts, const int3
     if (3 * depth + 1 > kMaxStackDepth) {
         free_scene(c);
         return fail(c, LT_EINVAL, "BVH deeper than the traversal stack bound");
+    }
+    if ((long long)n_nodes > (1ll << 25)) {
+        free_scene(c);
+        return fail(c, LT_EINVAL, "BVH larger than 2^32 bytes");
     }
     HIPCHK(c, hipMalloc(&c->patches, sizeof(DevPatch) * n_patches));
     HIPCHK(c, hipMalloc(&c->pbase, sizeof(long long) * n_patches));

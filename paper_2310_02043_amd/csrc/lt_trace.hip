@@ -89,7 +89,7 @@ __device__ __forceinline__ void trav_step(const Ray& r, int skip, Trav& s, bool&
     if (s.lmask != 0) {
         const int k = __builtin_ctz((unsigned)s.lmask);
         const int ref = k == 0 ? s.lq0 : (k == 1 ? s.lq1 : (k == 2 ? s.lq2 : s.lq3));
-        const float4* tp = tris + 3 * (~ref);
+        const float4* tp = (const float4*)((const char*)tris + (unsigned)(~ref) * 48u);   // < 2^32 bytes
         tri_test(tp[0], tp[1], tp[2], v3(r.ox, r.oy, r.oz), v3(r.dx, r.dy, r.dz), skip, s.tb, s.pb, s.qb);
         if (STATS) ++n_tris;
         s.lmask &= s.lmask - 1;
@@ -104,12 +104,18 @@ __device__ __forceinline__ void trav_step(const Ray& r, int skip, Trav& s, bool&
         s.qb = -1;
         return;
     }
-    const float4* nd = nodes + 8 * s.node;
+    // 32-bit byte offsets from the uniform node base (128 B per node; the
+    // upload keeps the tree under 2^32 bytes), so loads take the scalar-base
+    // form and no 64-bit address arithmetic
+    const char* nb = (const char*)nodes;
+    const unsigned ob = (unsigned)s.node << 7;
     // rows of the near planes: lo (even row) for a positive direction, hi otherwise
-    const int nx = (int)(__float_as_uint(r.ix) >> 31), ny = 2 + (int)(__float_as_uint(r.iy) >> 31),
-              nz = 4 + (int)(__float_as_uint(r.iz) >> 31);
-    const float4 xn = nd[nx], xf = nd[nx ^ 1], yn = nd[ny], yf = nd[ny ^ 1], zn = nd[nz], zf = nd[nz ^ 1];
-    const float4 cr = nd[6];
+    const unsigned nx = (__float_as_uint(r.ix) >> 31) << 4, ny = 32u + ((__float_as_uint(r.iy) >> 31) << 4),
+                   nz = 64u + ((__float_as_uint(r.iz) >> 31) << 4);
+    const float4 xn = *(const float4*)(nb + (ob + nx)), xf = *(const float4*)(nb + (ob + (nx ^ 16u)));
+    const float4 yn = *(const float4*)(nb + (ob + ny)), yf = *(const float4*)(nb + (ob + (ny ^ 16u)));
+    const float4 zn = *(const float4*)(nb + (ob + nz)), zf = *(const float4*)(nb + (ob + (nz ^ 16u)));
+    const float4 cr = *(const float4*)(nb + (ob + 96u));
     if (STATS) ++n_nodes;
     float t[4] = {slab_nf(r, xn.x, xf.x, yn.x, yf.x, zn.x, zf.x, s.tb), slab_nf(r, xn.y, xf.y, yn.y, yf.y, zn.y, zf.y, s.tb),
                   slab_nf(r, xn.z, xf.z, yn.z, yf.z, zn.z, zf.z, s.tb), slab_nf(r, xn.w, xf.w, yn.w, yf.w, zn.w, zf.w, s.tb)};
