@@ -235,8 +235,9 @@ __global__ void k_ploc_write(int nc, int n_int, int node_base, const int* __rest
 // ---- collapse of the binary tree into a 4-wide tree ------------------------
 // Node of the wide tree, 128 B: lo.x, hi.x, lo.y, hi.y, lo.z, hi.z of the four
 // children (float4 each, one lane per child), then the child references
-// (>= 0 wide node, < 0 leaf ~triangle, kEmptyChild unused, with an inverted
-// box that no slab test hits) and padding.
+// (>= 0 wide node, < 0 leaf ~(3 x triangle slot), the triangle's first
+// float4 row, kEmptyChild unused, with an inverted box that no slab test
+// hits) and padding.
 __device__ __forceinline__ void ref_box(int c, const float4* nlo, const float4* nhi, const int* vals,
                                         const float4* tlo, const float4* thi, float4& lo, float4& hi)
 {
@@ -394,7 +395,7 @@ __global__ void k_collapse_write(int n_level, int out_base, int next_base, const
             ref[q] = w;
             ++rank;
         } else {
-            ref[q] = c;
+            ref[q] = ~(3 * (~c));   // leaf: ~(first float4 row of its triangle)
         }
     }
     float4* nd = wide + 8 * (size_t)(out_base + i);

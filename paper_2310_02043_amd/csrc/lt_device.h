@@ -162,10 +162,10 @@ __device__ __forceinline__ V3 xyz(float4 v) { return V3{v.x, v.y, v.z}; }
 // ---------------------------------------------------------------------------
 // Data layouts in HBM.
 // ---------------------------------------------------------------------------
-// BVH node, 64 B: bounds of both children inline (one node fetch tests two
-// boxes).  w0 = (c0.lo.x, c0.hi.x, c0.lo.y, c0.hi.y), w1 = same for child 1,
-// w2 = (c0.lo.z, c0.hi.z, c1.lo.z, c1.hi.z), w3 = (child0, child1, -, -) as
-// int bits: >= 0 internal node, < 0 leaf triangle ~index.
+// BVH node of the 4-wide tree, 128 B = 8 float4 rows: lo.x, hi.x, lo.y, hi.y,
+// lo.z, hi.z of the four children (one component per child), then the four
+// child references as int bits (>= 0 node index, < 0 leaf = ~(first float4
+// row of its triangle), an unused slot holds an inverted box), then padding.
 // Triangle, 48 B: (v0, original id), (e1 = v1 - v0, patch), (e2 = v2 - v0, 0).
 
 // Patch record, 80 B.

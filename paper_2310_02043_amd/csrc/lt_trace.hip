@@ -59,7 +59,7 @@ struct Trav {
     int node, sp;   // node < 0: nothing left to visit
     int steps;
     int lmask;      // children of the last node step whose leaf triangle awaits its test
-    int lq0, lq1, lq2, lq3;   // that node's child references (leaf = ~triangle)
+    int lq0, lq1, lq2, lq3;   // that node's child references (leaf = ~(3 x triangle))
 };
 
 __device__ __forceinline__ void cswap(float& ta, int& ca, float& tb, int& cb)
@@ -88,8 +88,10 @@ __device__ __forceinline__ void trav_step(const Ray& r, int skip, Trav& s, bool&
     if (mode == 2 && s.lmask != 0) return;
     if (s.lmask != 0) {
         const int k = __builtin_ctz((unsigned)s.lmask);
-        const int ref = k == 0 ? s.lq0 : (k == 1 ? s.lq1 : (k == 2 ? s.lq2 : s.lq3));
-        const float4* tp = (const float4*)((const char*)tris + (unsigned)(~ref) * 48u);   // < 2^32 bytes
+        const int r01 = (k & 1) ? s.lq1 : s.lq0, r23 = (k & 1) ? s.lq3 : s.lq2;
+        const int ref = (k & 2) ? r23 : r01;
+        // a leaf reference is ~(its triangle's first float4 row); < 2^32 bytes
+        const float4* tp = (const float4*)((const char*)tris + ((unsigned)(~ref) << 4));
         tri_test(tp[0], tp[1], tp[2], v3(r.ox, r.oy, r.oz), v3(r.dx, r.dy, r.dz), skip, s.tb, s.pb, s.qb);
         if (STATS) ++n_tris;
         s.lmask &= s.lmask - 1;
