@@ -6,7 +6,9 @@ adjoint light-tracing kernel (Alg. 2) with the incoming dL/dE as the adjoint
 source and returns dL/dparams [L, 6].  ``LightTraceRGBFn`` is the colour form
 (channel weights [L, 3] as a second input, E [n_layouts, 3, K]) and
 ``LightTraceDirFn`` the directional form (hemispherical-harmonic
-coefficients of the reflected radiance, E [n_layouts, (order+1)^2, K]).  Whether the adjoint replays the
+coefficients of the reflected radiance, E [n_layouts, (order+1)^2, K]);
+``LightTraceRVFn`` takes the orientation as a rotation vector (params
+[L, 7] = x, y, z, theta, P; Sec. 4.4.2).  Whether the adjoint replays the
 forward's paths (correlated evaluation, as the paper uses for validation) or
 a fresh set (decorrelated, as it uses for optimisation) is the tracer's
 ``correlated`` flag (Sec. 4.3).  Both passes run on the current torch stream.
@@ -79,6 +81,11 @@ class LightTracer:
         and channel weights [L,3], differentiable in both."""
         return LightTraceRGBFn.apply(params, colour, self, seed)
 
+    def rotvec(self, params7, seed=None):
+        """Orientation as a rotation vector: E [n_layouts, K] from params
+        [L,7] = (x, y, z, theta, P), differentiable in all seven."""
+        return LightTraceRVFn.apply(params7, self, seed)
+
     def directional(self, params, order: int, samples: int, seed=None):
         """Directional texels: hemispherical-harmonic coefficients of the
         reflected radiance [n_layouts, (order+1)^2, K] (glossy BRDF per patch
@@ -129,6 +136,25 @@ class LightTraceRGBFn(torch.autograd.Function):
         grad, grad_c = tracer.ctx.trace_adjoint_rgb(p, c, g, tracer.cfg(tracer.adjoint_seed(fctx.seed), adjoint=True),
                                                     bin_hist=hist)
         return grad, grad_c, None, None
+
+
+class LightTraceRVFn(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, params, tracer: LightTracer, seed=None):
+        p = params.detach().contiguous().float()
+        E, _ = tracer.ctx.trace_forward_rv(p, tracer.cfg(seed), S=tracer.scratch())
+        fctx.save_for_backward(p)
+        fctx.tracer = tracer
+        fctx.seed = seed
+        return E
+
+    @staticmethod
+    def backward(fctx, grad_E):
+        (p,) = fctx.saved_tensors
+        tracer = fctx.tracer
+        g = grad_E.contiguous().float()
+        grad = tracer.ctx.trace_adjoint_rv(p, g, tracer.cfg(tracer.adjoint_seed(fctx.seed), adjoint=True))
+        return grad, None, None
 
 
 class LightTraceDirFn(torch.autograd.Function):

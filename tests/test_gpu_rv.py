@@ -117,3 +117,60 @@ def test_rv_invalid_arguments(torch_dev):
     p_d[:, 6] = 10.0
     with pytest.raises(LtError):
         ctx.trace_forward_rv(p_d, ctx.cfg(1, 1 << 12, 3, linear=True))      # box basis only
+
+
+def test_rv_autograd_adam(torch_dev):
+    """The rotation-vector autograd function: its backward equals the direct
+    rotation-vector adjoint, and Adam on (x, y, z, theta) brings a spot moved
+    by 0.2 m and turned by 0.15 rad back (fresh paths per step, decorrelated
+    adjoint): the objective within 1.5x of its value at the true parameters,
+    the axis within 0.05 rad (the roll about a round spot's axis is free)."""
+    torch = torch_dev
+    from scipy.spatial.transform import Rotation
+    from paper_2310_02043_amd.autograd import LightTracer, objective
+    c1 = li.box_room()
+    sc, lights = c1["scene"], c1["lights"]
+    p6 = lights.params[0].astype(np.float64)
+    th = Rotation.from_matrix(Rotation.from_euler("YX", [p6[4], p6[3]]).as_matrix()).as_rotvec()
+    pt_np = np.array([[*p6[:3], *th, p6[5]]], np.float32)
+    tr = LightTracer((sc.verts, sc.tris, sc.tri_patch, sc.patches), lights.static, lights.layout_offsets,
+                     1 << 18, 3, seed=5, correlated=False)
+    A = torch.tensor(sc.texel_area(), device="cuda")
+    pt = torch.tensor(pt_np, device="cuda")
+    with torch.no_grad():
+        Et = tr.rotvec(pt, seed=0x77).clone()
+        O_true = objective(tr.rotvec(pt, seed=999), Et, A).item()
+    p0 = pt_np.copy()
+    p0[0, 3:6] = (Rotation.from_rotvec([0.12, -0.1, 0.05]) * Rotation.from_rotvec(th)).as_rotvec()
+    p0[0, 0] += 0.2
+    p = torch.tensor(p0, device="cuda", requires_grad=True)
+    E = tr.rotvec(p, seed=100)
+    objective(E, Et, A).backward()
+    g = (A * (E.detach() - Et)).contiguous()
+    ref = tr.ctx.trace_adjoint_rv(p.detach(), g, tr.cfg(tr.adjoint_seed(100), adjoint=True))
+    torch.cuda.synchronize()
+    rel = (p.grad - ref).abs().max().item() / ref.abs().max().item()
+    say("  autograd vs direct rotation-vector adjoint:", rel)
+    assert rel < 1e-6
+
+    def axis(q):
+        return -Rotation.from_rotvec(np.asarray(q, np.float64)).as_matrix()[:, 2]
+
+    lr = torch.tensor([0.02, 0.02, 0.02, 0.01, 0.01, 0.01, 0.0], device="cuda")
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    for it in range(80):
+        p.grad = None
+        O = objective(tr.rotvec(p, seed=100 + it), Et, A)
+        O.backward()
+        with torch.no_grad():
+            m.mul_(0.9).add_(0.1 * p.grad)
+            v.mul_(0.999).add_(0.001 * p.grad * p.grad)
+            p -= lr * (m / (1 - 0.9 ** (it + 1))) / ((v / (1 - 0.999 ** (it + 1))).sqrt() + 1e-8)
+    q = p.detach().cpu().numpy()[0]
+    ax0 = float(np.arccos(np.clip(np.dot(axis(p0[0, 3:6]), axis(th)), -1, 1)))
+    ax1 = float(np.arccos(np.clip(np.dot(axis(q[3:6]), axis(th)), -1, 1)))
+    pos = float(np.linalg.norm(q[:3] - pt_np[0, :3]))
+    say(f"  objective -> {O.item():.2f} (true parameters {O_true:.2f}), axis error {ax0:.3f} -> {ax1:.3f} rad, "
+        f"position error {pos:.3f} m")
+    assert O.item() < 1.5 * O_true and ax1 < 0.05 and pos < 0.05
