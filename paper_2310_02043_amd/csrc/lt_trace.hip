@@ -602,14 +602,16 @@ __device__ __forceinline__ long long xcd_block(long long b, long long nb, int re
 // box texel basis, 1 the piecewise-linear basis (four splats / a four-node
 // gather per hit), 2 colour (three channel-planar texel arrays; the green
 // and blue throughputs and adjoint sums live in LDS beside the red ones in
-// registers), 3 directional texels (hemispherical-harmonic coefficients of
-// the reflected radiance and a glossy BRDF; the adjoint's first-hit BRDF
-// terms live in LDS), 4 rotation-vector orientation (seven derivatives),
-// 5 the direct-differentiation map of one luminaire (forward only), 6 the
+// registers), 30 + n directional texels of harmonic order n
+// (hemispherical-harmonic coefficients of the reflected radiance and a
+// glossy BRDF; the adjoint's first-hit BRDF terms live in LDS), 4
+// rotation-vector orientation (seven derivatives), 5 the direct-differentiation map of one luminaire (forward only), 6 the
 // soft-edged spots' cone angles (adjoint, eight derivatives).
 template <bool ADJ, bool STATS, int WPB, int LDS_D, int MODE>
-__global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(MODE == 3 ? 4 : 5))) k_trace(TraceArgs a)
+__global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(MODE >= 30 ? 4 : 5))) k_trace(TraceArgs a)
 {
+    constexpr bool DIR = MODE >= 30;               // directional texels of order MODE - 30
+    constexpr int DORD = DIR ? MODE - 30 : 0;
     __shared__ int s_stack[WPB * LDS_D * 64];
     // adjoint per-lane state read once per path (first-hit derivative
     // factors, running contribution sums), kept in LDS instead of registers
@@ -622,13 +624,13 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(M
     // directional: forward, the hit's 16 coefficient sums; adjoint T2, R,
     // Q[3], D[3], w_in1[3], 1/r1 and the hit texel's 16 dO/dL values
     constexpr int DIRW = ADJ ? 28 : 16;
-    __shared__ float s_dir[MODE == 3 ? WPB * DIRW * 64 : 1];
+    __shared__ float s_dir[DIR ? WPB * DIRW * 64 : 1];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     float* adj = s_adj + (ADJ ? wib * 2 * NPAR * 64 + lane : 0);
     int* k1 = s_k1 + (ADJ ? wib * 64 + lane : 0);
     float* rgbs = s_rgb + (MODE == 2 ? wib * 8 * 64 + lane : 0);
-    float* dst = s_dir + (MODE == 3 ? wib * DIRW * 64 + lane : 0);
+    float* dst = s_dir + (DIR ? wib * DIRW * 64 + lane : 0);
     const long long blk = xcd_block(blockIdx.x, gridDim.x, a.xcd_remap);
     const long long gw = blk * WPB + wib;
     if (gw >= a.n_tiles) return;
@@ -644,9 +646,9 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(M
         const uint32_t first = (uint32_t)ti.y;
         const int count = ti.z;
         const uint32_t stream_id = ((uint32_t)ti.w << 16) | (uint32_t)L.l_local;
-        const int NC = MODE == 3 ? (a.dir_order + 1) * (a.dir_order + 1) : 1;
-        const long long rowK = (MODE == 2 ? 3 : (MODE == 3 ? NC : 1)) * a.K;
-        const float inv_np = MODE == 3 ? 1.0f / (float)a.dir_samples : 0.0f;
+        constexpr int NC = DIR ? (DORD + 1) * (DORD + 1) : 1;
+        const long long rowK = (MODE == 2 ? 3 : (DIR ? NC : 1)) * a.K;
+        const float inv_np = DIR ? 1.0f / (float)a.dir_samples : 0.0f;
         long long* S = ADJ ? nullptr : a.S + (long long)ti.w * rowK;
         const float* g = ADJ ? a.g + (long long)ti.w * rowK : nullptr;
         float c0 = 1.0f, c1 = 1.0f, c2 = 1.0f;   // channel weights of the flux
@@ -708,7 +710,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(M
                         rgbs[128] = 0.0f;
                         rgbs[192] = 0.0f;
                     }
-                    if (MODE == 3 && ADJ) {
+                    if (DIR && ADJ) {
                         dst[0] = 1.0f;
 #pragma unroll
                         for (int c = 1; c < 8; ++c) dst[c * 64] = 0.0f;
@@ -768,7 +770,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(M
                             (long long)__builtin_rintf((((phi_r * T) * hi.inva) * tdl) * 4294967296.0f);
                         __hip_atomic_fetch_add((unsigned long long*)(a.tangent + hi.k), (unsigned long long)qt,
                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    } else if (MODE == 3) {
+                    } else if (DIR) {
                         gls = a.glossy[s.qb];
                         local_frame(hi.no, fb1, fb2);
                         const V3 wiw = v3(-r.dx, -r.dy, -r.dz);
@@ -796,7 +798,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(M
                             sincos_2pi(ub, sp, cp);
                             const V3 wo = v3(st * cp, st * sp, ct);
                             float H[16];
-                            hsh_eval(a.dir_order, ct, cp, sp, H);
+                            hsh_eval(DORD, ct, cp, sp, H);
                             V3 gr;
                             const float f = brdf_local(hi.rho, gls.x, gls.y, wil, wo, ADJ && h == 1, gr);
                             if (!ADJ) {
@@ -876,7 +878,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(M
                             __hip_atomic_fetch_add((unsigned long long*)(S + hi.k), (unsigned long long)code,
                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         }
-                    } else if (MODE != 3) {
+                    } else if (!DIR) {
                         float gk;
                         if (MODE == 1) {
                             long long kb[4];
@@ -914,7 +916,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(M
                             T = T * rho.x;
                             rgbs[0] = rgbs[0] * rho.y;
                             rgbs[64] = rgbs[64] * rho.z;
-                        } else if (MODE == 3) {
+                        } else if (DIR) {
                             const V3 wo = v3(dot(fb1, nd), dot(fb2, nd), dot(hi.no, nd));
                             V3 gr;
                             const float fbv = brdf_local(hi.rho, gls.x, gls.y, wil, wo, ADJ && h == 1, gr);
@@ -951,7 +953,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(M
                         // directional: d/dy of the first hit's projection and
                         // bounce weight through w_in1 = (y - x_1)/|y - x_1|
                         float ext[6] = {0, 0, 0, 0, 0, 0};
-                        if (MODE == 3) {
+                        if (DIR) {
                             const float Rd = dst[64];
                             const V3 v = v3(dst[128] + Rd * dst[320], dst[192] + Rd * dst[384], dst[256] + Rd * dst[448]);
                             const V3 om = v3(dst[512], dst[576], dst[640]);
@@ -974,7 +976,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(M
 #pragma unroll
                         for (int c = 0; c < NPAR; ++c) {
                             float cr = se * adj[c * 64];
-                            if (MODE == 3) cr = cr + phi_r * ext[c < 6 ? c : 0];
+                            if (DIR) cr = cr + phi_r * ext[c < 6 ? c : 0];
                             adj[(NPAR + c) * 64] += cr;
                             if (hist && c < 6) {
                                 const float z = cr * a.inv_sigma[6 * ti.x + c];
@@ -985,7 +987,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(M
                         // the path's share of dO/dp_j, placed at its first hit
                         if (vote) {
                             float cv = se * adj[a.vote_param * 64];
-                            if (MODE == 3) cv = cv + phi_r * ext[a.vote_param];
+                            if (DIR) cv = cv + phi_r * ext[a.vote_param];
                             unsafeAtomicAdd(vote + *k1, (double)cv);
                         }
                     }
@@ -1548,6 +1550,15 @@ inline int nblocks(long long n, int b, int cap)
     return (int)x;
 }
 
+template <bool ADJ, int WPB, int MODE>
+void launch_dir(const TraceArgs& a, int lds_depth, int blocks, hipStream_t st)
+{
+    if (lds_depth == 16)
+        k_trace<ADJ, false, WPB, 16, MODE><<<blocks, WPB * 64, 0, st>>>(a);
+    else
+        k_trace<ADJ, false, WPB, 32, MODE><<<blocks, WPB * 64, 0, st>>>(a);
+}
+
 template <bool ADJ, bool STATS, int WPB>
 hipError_t launch_wpb(const TraceArgs& a, int lds_depth, int blocks, hipStream_t st)
 {
@@ -1567,10 +1578,15 @@ hipError_t launch_wpb(const TraceArgs& a, int lds_depth, int blocks, hipStream_t
         else
             k_trace<ADJ, STATS, WPB, 32, 4><<<blocks, WPB * 64, 0, st>>>(a);
     } else if (a.dir_order >= 0 && !STATS) {
-        if (lds_depth == 16)
-            k_trace<ADJ, STATS, WPB, 16, 3><<<blocks, WPB * 64, 0, st>>>(a);
-        else
-            k_trace<ADJ, STATS, WPB, 32, 3><<<blocks, WPB * 64, 0, st>>>(a);
+        if constexpr (!STATS) {
+            // the harmonic order as a compile-time constant: MODE 30 + order
+            switch (a.dir_order) {
+                case 0: launch_dir<ADJ, WPB, 30>(a, lds_depth, blocks, st); break;
+                case 1: launch_dir<ADJ, WPB, 31>(a, lds_depth, blocks, st); break;
+                case 2: launch_dir<ADJ, WPB, 32>(a, lds_depth, blocks, st); break;
+                default: launch_dir<ADJ, WPB, 33>(a, lds_depth, blocks, st); break;
+            }
+        }
     } else if (a.rgb && !STATS) {
         if (lds_depth == 16)
             k_trace<ADJ, STATS, WPB, 16, 2><<<blocks, WPB * 64, 0, st>>>(a);
