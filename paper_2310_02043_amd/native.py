@@ -298,41 +298,55 @@ class Context:
                                                   _ptr(grad), _ptr(grad_colour), _ptr(bin_hist)))
         return grad, grad_colour
 
-    def trace_tangent(self, params, cfg, light, param):
+    def trace_tangent(self, params, cfg, light, param, D=None, T=None):
         """Direct-differentiation map dE/dp_j of global light `light` over the
         texels of its layout: ([K] float32, [K] int64 Q31.32 sums)."""
         torch = self._torch
         self._dev(params, torch.float32, (self.n_lights, 6))
-        T = torch.empty(self.n_texels, dtype=torch.int64, device=params.device)
-        D = torch.empty(self.n_texels, dtype=torch.float32, device=params.device)
+        if T is None:
+            T = torch.empty(self.n_texels, dtype=torch.int64, device=params.device)
+        if D is None:
+            D = torch.empty(self.n_texels, dtype=torch.float32, device=params.device)
+        self._dev(T, torch.int64, (self.n_texels,))
+        self._dev(D, torch.float32, (self.n_texels,))
         self._stream()
         self._check(self.lib.lt_trace_tangent(self.h, C.byref(cfg), _ptr(params), int(light), int(param), _ptr(T),
                                               _ptr(D)))
         return D, T
 
-    def trace_adjoint_cone(self, params, dOdE, cfg):
+    def trace_adjoint_cone(self, params, dOdE, cfg, grad=None, gcone=None):
         """Adjoint with the soft-edged spots' cone angles: (grad [L,6],
         grad_cone [L,2] = dO/d(theta_in, theta_out))."""
         torch = self._torch
         self._dev(params, torch.float32, (self.n_lights, 6))
         self._dev(dOdE, torch.float32, (self.n_layouts, self.n_texels))
-        grad = torch.empty((self.n_lights, 6), dtype=torch.float32, device=params.device)
-        gcone = torch.empty((self.n_lights, 2), dtype=torch.float32, device=params.device)
+        if grad is None:
+            grad = torch.empty((self.n_lights, 6), dtype=torch.float32, device=params.device)
+        if gcone is None:
+            gcone = torch.empty((self.n_lights, 2), dtype=torch.float32, device=params.device)
+        self._dev(grad, torch.float32, (self.n_lights, 6))
+        self._dev(gcone, torch.float32, (self.n_lights, 2))
         self._stream()
         self._check(self.lib.lt_trace_adjoint_cone(self.h, C.byref(cfg), _ptr(params), _ptr(dOdE), _ptr(grad),
                                                    _ptr(gcone)))
         return grad, gcone
 
-    def fd_map(self, params, cfg, light, param, h):
+    def fd_map(self, params, cfg, light, param, h, F=None, Sp=None, Sm=None):
         """Central-difference map (E(p_j + h) - E(p_j - h)) / step of global
         light `light` over the texels of its layout, common random numbers:
         [K] float32."""
         torch = self._torch
         self._dev(params, torch.float32, (self.n_lights, 6))
         n = (self.n_layouts, self.n_texels)
-        Sp = torch.empty(n, dtype=torch.int64, device=params.device)
-        Sm = torch.empty(n, dtype=torch.int64, device=params.device)
-        F = torch.empty(self.n_texels, dtype=torch.float32, device=params.device)
+        if Sp is None:
+            Sp = torch.empty(n, dtype=torch.int64, device=params.device)
+        if Sm is None:
+            Sm = torch.empty(n, dtype=torch.int64, device=params.device)
+        if F is None:
+            F = torch.empty(self.n_texels, dtype=torch.float32, device=params.device)
+        self._dev(Sp, torch.int64, n)
+        self._dev(Sm, torch.int64, n)
+        self._dev(F, torch.float32, (self.n_texels,))
         self._stream()
         self._check(self.lib.lt_fd_map(self.h, C.byref(cfg), _ptr(params), int(light), int(param), float(h), _ptr(Sp),
                                        _ptr(Sm), _ptr(F)))

@@ -170,3 +170,39 @@ def test_fd_map_invalid_arguments(torch_dev):
     for args in ((0, 0, 0.0), (0, 0, float("nan")), (0, 0, -1e-2), (lights.n_lights, 0, 1e-2), (0, 6, 1e-2)):
         with pytest.raises(LtError):
             ctx.fd_map(p_d, cfg, *args)
+
+
+def test_maps_graph_replay(torch_dev):
+    """The direct-differentiation, central-difference and cone-angle entries
+    captured as graphs and replayed three times into the same buffers, with
+    eager calls in between: every replay equals the eager result exactly."""
+    torch = torch_dev
+    from paper_2310_02043_amd import Context
+    from lt_inputs.scenes import make_lights, SPOT, SOFT
+    sc = li.box_room()["scene"]
+    lights = make_lights([SOFT, SPOT], [0.0, 3.0], [(0.3, 0.8), (0, 0)], [0, 0],
+                         [[2.8, 0.9, 2.3, 0.25, -0.1, 40.0], [1.0, 1.0, 2.0, 0.1, 0.2, 50.0]])
+    ctx = Context(0)
+    ctx.upload_scene(sc.verts, sc.tris, sc.tri_patch, sc.patches)
+    ctx.set_lights(lights.static, lights.layout_offsets)
+    p = torch.tensor(lights.params, device="cuda")
+    g = torch.randn((1, sc.n_texels), device="cuda")
+    eager, graph = ctx.cfg(0x5A, 1 << 18, 3), ctx.cfg(0x5A, 1 << 18, 3, graph=True)
+    D0, _ = ctx.trace_tangent(p, eager, 0, 3)
+    F0 = ctx.fd_map(p, eager, 1, 0, 0.02)
+    G0, C0 = ctx.trace_adjoint_cone(p, g, eager)
+    D0, F0, G0, C0 = D0.clone(), F0.clone(), G0.clone(), C0.clone()
+    D, T = torch.empty_like(D0), torch.empty(sc.n_texels, dtype=torch.int64, device="cuda")
+    F = torch.empty_like(F0)
+    Sp = torch.empty((1, sc.n_texels), dtype=torch.int64, device="cuda")
+    Sm = torch.empty_like(Sp)
+    G, C = torch.empty_like(G0), torch.empty_like(C0)
+    for rep in range(3):
+        ctx.trace_tangent(p, graph, 0, 3, D=D, T=T)
+        ctx.fd_map(p, graph, 1, 0, 0.02, F=F, Sp=Sp, Sm=Sm)
+        ctx.trace_adjoint_cone(p, g, graph, grad=G, gcone=C)
+        assert ctx.sync() == 0
+        say(f"  replay {rep}")
+        assert torch.equal(D, D0) and torch.equal(F, F0) and torch.equal(G, G0) and torch.equal(C, C0)
+        ctx.trace_forward(p, eager)           # eager work between the replays
+        torch.cuda.synchronize()
