@@ -58,10 +58,8 @@
  *     the texel of its first surface hit.
  *
  * Pins (tests/test_oracle_pins.py): closed forms, invariants, brute force and
- * finite differences for every step above.  Parity unpinned: agreement of
- * the generator with the canonical Philox4x32-10 stream (no published vectors
- * are at hand; its uniformity, serial independence and avalanche behaviour
- * are pinned instead).
+ * finite differences for every step above; the generator against the
+ * published Philox4x32-10 known-answer vectors.
  *
  * Floating point: path arithmetic is FP32 because the kernels compute in FP32
  * and FP32 decides integers here (which triangle is hit, which texel, the

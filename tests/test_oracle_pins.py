@@ -22,6 +22,18 @@ import closed_forms as cf
 # generator and own transcendentals
 # --------------------------------------------------------------------------
 
+def test_philox_known_answers(oracle_lib):
+    """The generator is the canonical Philox4x32-10: the known-answer vectors
+    published with it (Salmon, Moraes, Dror and Shaw, SC'11, Random123 test
+    suite) for an all-zero, an all-ones and a pi-digit counter and key."""
+    kat = [((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+           ((0xFFFFFFFF,) * 4, (0xFFFFFFFF,) * 2, (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+           ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+            (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1))]
+    for ctr, key, out in kat:
+        assert [int(x) for x in oracle_lib.philox(list(ctr), list(key))] == list(out), (ctr, key)
+
+
 def test_philox_avalanche(oracle_lib):
     """Counter-based generation needs outputs of neighbouring counters and
     keys to be unrelated: flipping any one counter or key bit flips each
