@@ -4,9 +4,8 @@ None of these compares the oracle with another implementation of itself:
 each check is fixed by radiometry or mathematics (solid angles, form factors,
 energy conservation, linearity in power, finite differences of an
 independently written irradiance function, brute-force intersection,
-statistical properties of the generator).  The generator's agreement with
-the canonical Philox4x32-10 stream is parity unpinned: only its uniformity,
-serial independence and avalanche behaviour are pinned.
+statistical properties of the generator, and the generator's published
+known-answer vectors).
 """
 import math
 
