@@ -422,6 +422,32 @@ def main():
     out["direct_differentiation"] = {"kernel_ms": round(t_ms / max(nt, 1), 3), "fwd_kernel_ms": round(fwd_avg, 3),
                                      "light": 0, "param": "x"}
     log("direct differentiation", out["direct_differentiation"])
+    if args.workload == "office":
+        # directional texels at the paper's Table 1 order (3, 16 coefficients
+        # per texel), 4 local samples, glossy surfaces (rho_s 0.3, e 20)
+        order, ns = 3, 4
+        nc = (order + 1) ** 2
+        ctx.set_glossy(np.stack([np.full(scene.n_patches, 0.3), np.full(scene.n_patches, 20.0)], 1)
+                       .astype(np.float32))
+        Sd = torch.empty((n_layouts, nc, K), dtype=torch.int64, device=dev)
+        Ed = torch.empty((n_layouts, nc, K), dtype=torch.float32, device=dev)
+        gd = torch.randn((n_layouts, nc, K), device=dev)
+        gradd = torch.empty_like(grad)
+        ctx.trace_forward_dir(p, vcfg, order, ns, S=Sd, E=Ed)
+        ctx.trace_adjoint_dir(p, gd, vcfg, order, ns, grad=gradd)
+        torch.cuda.synchronize()
+        ctx.timing_read()
+        ctx.set_timing(True)
+        for i in range(2):
+            ctx.trace_forward_dir(p, vcfg, order, ns, S=Sd, E=Ed)
+            ctx.trace_adjoint_dir(p, gd, vcfg, order, ns, grad=gradd)
+        torch.cuda.synchronize()
+        ctx.set_timing(False)
+        f_ms, nf, a_ms, na = ctx.timing_read()
+        out["directional"] = {"order": order, "local_samples": ns, "fwd_kernel_ms": round(f_ms / max(nf, 1), 3),
+                              "adj_kernel_ms": round(a_ms / max(na, 1), 3)}
+        log("directional texels", out["directional"])
+        del Sd, Ed, gd
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(scene, lights, seed, N, B, args.cpu_seconds)
