@@ -6,7 +6,8 @@
 * the plain lobe's hemi-octahedral cell masses against an independent
   quadrature in spherical coordinates;
 * the proposal network's training target: normalisation, running average,
-  square root and plain-lobe floor.
+  square root and plain-lobe floor;
+* the directional objective's band weights and the chromaticity projection.
 """
 import math
 
@@ -147,3 +148,25 @@ def test_training_target():
     assert torch.allclose(avg2, a)
     assert torch.allclose(t2, 0.7 * r2 / r2.sum(1, keepdim=True) + 0.3 * pm)
     assert torch.allclose(t2.sum(1), torch.ones(2, dtype=torch.float64))
+
+
+def test_band_weights_and_chromaticity():
+    """Per-band objective weights: order-0 band at w00, the rest 1, expanded
+    as alpha_k alpha_l over [layouts, (order+1)^2, K]; the torch objective with
+    them equals the weighted sum written out.  The chromaticity projection
+    sums to one and is invariant to scaling the colour."""
+    from paper_2310_02043_amd.autograd import band_weights, chromaticity, directional_alpha, objective
+    w = band_weights(2, 0.1)
+    assert w.shape == (9,) and float(w[0]) == pytest.approx(0.1) and torch.all(w[1:] == 1.0)
+    ak = torch.linspace(0.5, 2.0, 7)
+    al = directional_alpha(w, ak, 2)
+    assert al.shape == (2, 9, 7) and al.is_contiguous()
+    assert torch.allclose(al[1, 0], 0.1 * ak) and torch.equal(al[0, 4], ak)
+    g = torch.Generator().manual_seed(3)
+    E, Et, A = torch.rand(2, 9, 7, generator=g), torch.rand(2, 9, 7, generator=g), torch.rand(7, generator=g)
+    ref = 0.5 * sum(float(A[k] * al[j, c, k] * (E[j, c, k] - Et[j, c, k]) ** 2)
+                    for j in range(2) for c in range(9) for k in range(7))
+    assert float(objective(E, Et, A, alpha=al)) == pytest.approx(ref, rel=1e-6)
+    c = torch.tensor([[0.9, 0.7, 0.4], [2.0, 1.0, 1.0]])
+    cp = chromaticity(c)
+    assert torch.allclose(cp.sum(-1), torch.ones(2)) and torch.allclose(chromaticity(3.0 * c), cp)
