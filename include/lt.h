@@ -54,6 +54,10 @@ extern "C" {
 /* lt_sync flags_out bits */
 #define LT_STATUS_OVERFLOW 1u  /* a texel accumulator reached 2^62 */
 #define LT_STATUS_TRAVERSAL 2u /* a traversal exceeded its node-visit bound (malformed BVH) */
+/* a luminaire parameter passed to a trace call was NaN or infinite, or its
+ * power P was not positive; that luminaire traced no path (zero texel
+ * contribution, zero gradient row) */
+#define LT_STATUS_PARAMS 4u
 
 typedef struct lt_ctx lt_ctx;
 
@@ -132,7 +136,10 @@ const char* lt_last_error(const lt_ctx* ctx);
 int lt_set_stream(lt_ctx* ctx, void* hip_stream);
 
 /* Wait for the context's stream; report sticky device status bits
- * (LT_STATUS_OVERFLOW) and clear them.  Returns LT_EOVERFLOW if set. */
+ * (LT_STATUS_*) and clear them.  Returns LT_EINVAL if LT_STATUS_PARAMS is
+ * set (the parameter check of every trace call happens on the device, so a
+ * rejected luminaire surfaces here), else LT_EOVERFLOW for LT_STATUS_OVERFLOW,
+ * else LT_EHIP for LT_STATUS_TRAVERSAL. */
 int lt_sync(lt_ctx* ctx, uint32_t* flags_out);
 
 /* Scene upload and BVH build (supplies the acceleration structure the paper
@@ -157,7 +164,10 @@ int lt_set_lights(lt_ctx* ctx, const lt_light_static* h_lights, int32_t n_lights
 
 /* Primal light tracing (Alg. 1, Eq. indirectFlux, Eq. directionalCoeffs with
  * n = 0): d_params [L,6] f32; d_S [n_layouts,K] i64 scratch (Q31.32 fixed-point
- * sums, zeroed by the call); d_E [n_layouts,K] f32 irradiance E_k = S_k 2^-32. */
+ * sums, zeroed by the call); d_E [n_layouts,K] f32 irradiance E_k = S_k 2^-32.
+ * Every trace call checks the parameters on the device: a luminaire with a
+ * NaN or infinite parameter or a power P <= 0 traces no path and raises
+ * LT_STATUS_PARAMS, which lt_sync reports as LT_EINVAL. */
 int lt_trace_forward(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, int64_t* d_S, float* d_E);
 
 /* Objective (Eq. objective, alpha_l = 1): O = 1/2 sum A_k alpha_k (E_k - E*_k)^2

@@ -117,6 +117,8 @@ def lib():
         L.or_light_frames.argtypes = [P, P, C.c_int64, P]
         L.or_first_hit_dlog.argtypes = [P, P, C.c_int, P, P, P, C.c_float, C.c_float, P]
         L.or_num_threads.restype = C.c_int
+        L.or_dir_block.argtypes = [C.c_uint32, C.c_uint32]
+        L.or_dir_block.restype = C.c_uint32
         _lib = L
     return _lib
 
@@ -200,6 +202,11 @@ def philox(ctr, key):
     out = np.zeros(4, np.uint32)
     lib().or_philox(c.ctypes.data, k.ctypes.data, out.ctypes.data)
     return out
+
+
+def dir_block(h: int, j: int) -> int:
+    """Generator block of the directional mode's local sample j at hit h."""
+    return int(lib().or_dir_block(h, j))
 
 
 def sincos2pi(u):

@@ -113,6 +113,13 @@ static void draw4(uint64_t seed, uint32_t i, uint32_t stream, uint32_t block, fl
     for (int c = 0; c < 4; ++c) u[c] = unit_float(r[c]);
 }
 
+/* Generator block of the directional mode's local sample j at hit h (the N'
+ * local samples of Alg. 1): one Philox draw serves two samples, and each hit
+ * owns 32 consecutive blocks from 0x100 on, so up to 64 samples per hit never
+ * share uniforms with another hit's samples, with the emission (0), proposal
+ * (1) or bounce (1 + h) draws. */
+EXPORT uint32_t or_dir_block(uint32_t h, uint32_t j) { return 0x100u + 32u * h + (j >> 1); }
+
 /* ------------------------------------------------------------------------- */
 /* Own transcendentals (FP32 contract).                                       */
 /* ------------------------------------------------------------------------- */
@@ -971,7 +978,7 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
             float pd = 0.0f, ql[3] = {0, 0, 0};
             for (int j = 0; j < S->dir_samples; ++j) {
                 float us[4];
-                draw4(seed, i, stream, 0x100u + 16u * (uint32_t)h + (uint32_t)(j >> 1), us);
+                draw4(seed, i, stream, or_dir_block((uint32_t)h, (uint32_t)j), us);
                 float ua = (j & 1) ? us[2] : us[0], ub = (j & 1) ? us[3] : us[1];
                 float ct = ua;
                 float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));

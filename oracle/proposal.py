@@ -56,6 +56,61 @@ def infer(w, x):
     return z, p
 
 
+def _bf16_choices(v, a, mag, tol):
+    """The bfloat16 values a hidden unit may round to.  v is the float64
+    activation after ReLU, a the pre-activation, mag the sum of the absolute
+    terms of its dot product: FP32 accumulation in any order stays within
+    tol * mag of the exact sum, so when a rounding tie (or, through ReLU, zero)
+    lies that close both neighbouring values are admissible."""
+    def rnd(t):
+        return float(bf16_round(np.float32(t))[0])
+    out = {rnd(v)}
+    if abs(a) <= tol * mag:
+        out |= {0.0, rnd(max(a + tol * mag, 0.0))}
+    if v > 0.0:
+        for d in (-tol * mag, tol * mag):
+            out.add(rnd(max(v + d, 0.0)))
+    return sorted(out)
+
+
+def infer_alternatives(w, x, tol=2.0 ** -18, max_alternatives=1024):
+    """Per light, the logits and cell probabilities for every admissible
+    bfloat16 rounding of its hidden activations (see _bf16_choices); tol
+    2^-18 bounds FP32 accumulation over the 64 terms of a hidden unit.  A
+    light with more than max_alternatives combinations gets None."""
+    wb = bf16_round(np.asarray(w, np.float32)).astype(np.float64)
+    W1, b1, W2, b2, W3, b3 = unpack(wb)
+    xb = bf16_round(np.asarray(x, np.float32)).astype(np.float64)
+    rows = []
+    for r in range(xb.shape[0]):
+        def layer(hin, W, b):
+            a = W @ hin + b
+            mag = np.abs(W) @ np.abs(hin) + np.abs(b)
+            return [_bf16_choices(max(a[i], 0.0), a[i], mag[i], tol) for i in range(a.size)]
+
+        def expand(choices, limit):
+            combos = [[]]
+            for c in choices:
+                combos = [cc + [v] for cc in combos for v in c]
+                if len(combos) > limit:
+                    return None
+            return [np.asarray(cc) for cc in combos]
+
+        h1s = expand(layer(xb[r], W1, b1), max_alternatives)
+        outs = []
+        for h1 in (h1s or []):
+            h2s = expand(layer(h1, W2, b2), max_alternatives)
+            if h2s is None or len(outs) + len(h2s) > max_alternatives:
+                outs = None
+                break
+            for h2 in h2s:
+                z = W3 @ h2 + b3
+                e = np.exp(z - z.max())
+                outs.append((z, e / e.sum()))
+        rows.append(outs if h1s is not None and outs else None)
+    return rows
+
+
 def loss_and_grad(w, x, target):
     """Mean cross-entropy over lights and its gradient w.r.t. the weights and
     the embedding columns of x (full precision)."""

@@ -123,8 +123,11 @@ int fail(lt_ctx* c, int code, const std::string& msg)
                         std::string(#expr) + ": " + hipGetErrorString(e_));                    \
     } while (0)
 
+// An executable graph may still run on the capture stream; wait for it
+// before destroying any (or freeing a buffer a graph refers to).
 void free_graphs(lt_ctx* c)
 {
+    if (c->gstream && !c->graphs.empty()) hipStreamSynchronize(c->gstream);
     for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
     c->graphs.clear();
 }
@@ -348,6 +351,7 @@ int run_seq(lt_ctx* c, bool graph, const std::vector<uint64_t>& key, F body)
         hipGraphDestroy(graph_h);
         if (e3 != hipSuccess) return fail(c, LT_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e3));
         if (c->graphs.size() >= 16) {
+            hipStreamSynchronize(c->gstream);
             hipGraphExecDestroy(c->graphs.front().exec);
             c->graphs.erase(c->graphs.begin());
         }
@@ -456,6 +460,9 @@ int lt_sync(lt_ctx* c, uint32_t* flags_out)
     HIPCHK(c, hipMemcpy(&f, c->d_flags, sizeof(unsigned), hipMemcpyDeviceToHost));
     if (f) HIPCHK(c, hipMemset(c->d_flags, 0, sizeof(unsigned)));
     if (flags_out) *flags_out = f;
+    if (f & LT_STATUS_PARAMS)
+        return fail(c, LT_EINVAL, "a luminaire parameter was not finite or its power not positive "
+                                  "(that luminaire contributed nothing)");
     if (f & LT_STATUS_OVERFLOW) return fail(c, LT_EOVERFLOW, "texel accumulator overflow (|S| >= 2^62)");
     if (f & LT_STATUS_TRAVERSAL) return fail(c, LT_EHIP, "BVH traversal exceeded its step bound");
     return LT_OK;
@@ -647,7 +654,7 @@ int lt_trace_forward(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     const long long n = c->K * c->n_layouts;
     const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
     auto body = [&](hipStream_t st) -> hipError_t {
-        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess) e = launch_clear(a.S, n, st);
         if (e == hipSuccess) e = timed_trace(c, false, graph, a, (int)blocks, st);
         if (e == hipSuccess) e = launch_finalize(a.S, d_E, n, c->d_flags, st);
@@ -685,7 +692,7 @@ int lt_trace_adjoint(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     a.bin_hist = d_bin_hist;
     const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
     auto body = [&](hipStream_t st) -> hipError_t {
-        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess && d_bin_hist) e = launch_fill_f32(d_bin_hist, (long long)c->L * 1024, 0.0f, st);
         if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
         if (e == hipSuccess) e = launch_grad_reduce(c->d_partials, c->d_range, c->L, d_grad, st);
@@ -715,7 +722,7 @@ int lt_gradient_votes(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params,
     a.vote_param = param;
     const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
     auto body = [&](hipStream_t st) -> hipError_t {
-        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess) e = launch_clear((long long*)d_vote, c->K, st);
         if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
         if (e == hipSuccess) e = launch_grad_reduce(c->d_partials, c->d_range, c->L, d_grad, st);
@@ -766,7 +773,7 @@ int lt_trace_forward_rgb(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_para
     const long long n = 3 * c->K * c->n_layouts;
     const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
     auto body = [&](hipStream_t st) -> hipError_t {
-        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess) e = launch_clear(a.S, n, st);
         if (e == hipSuccess) e = timed_trace(c, false, graph, a, (int)blocks, st);
         if (e == hipSuccess) e = launch_finalize(a.S, d_E, n, c->d_flags, st);
@@ -808,7 +815,7 @@ int lt_trace_adjoint_rgb(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_para
     a.partials_col = c->d_partials_col;
     const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
     auto body = [&](hipStream_t st) -> hipError_t {
-        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess && d_bin_hist) e = launch_fill_f32(d_bin_hist, (long long)c->L * 1024, 0.0f, st);
         if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
         if (e == hipSuccess) e = launch_grad_reduce(c->d_partials, c->d_range, c->L, d_grad, st);
@@ -840,7 +847,7 @@ int lt_trace_tangent(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     a.tan_param = param;
     const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
     auto body = [&](hipStream_t st) -> hipError_t {
-        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess) e = launch_clear(a.tangent, c->K, st);
         if (e == hipSuccess) e = timed_trace(c, false, graph, a, (int)blocks, st);
         if (e == hipSuccess) e = launch_finalize(a.tangent, d_D, c->K, c->d_flags, st);
@@ -889,10 +896,10 @@ int lt_fd_map(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int32_t
     const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
     auto body = [&](hipStream_t st) -> hipError_t {
         hipError_t e = launch_fd_params(d_params, 6 * c->L, 6 * light + param, h, pp, pm, den, st);
-        if (e == hipSuccess) e = launch_light_setup(pp, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        if (e == hipSuccess) e = launch_light_setup(pp, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess) e = launch_clear(ap.S, n, st);
         if (e == hipSuccess) e = timed_trace(c, false, graph, ap, (int)blocks, st);
-        if (e == hipSuccess) e = launch_light_setup(pm, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        if (e == hipSuccess) e = launch_light_setup(pm, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess) e = launch_clear(am.S, n, st);
         if (e == hipSuccess) e = timed_trace(c, false, graph, am, (int)blocks, st);
         if (e == hipSuccess) e = launch_fd_diff(ap.S + row, am.S + row, c->K, den, d_F, st);
@@ -922,7 +929,7 @@ int lt_trace_forward_rv(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_param
     const long long n = c->K * c->n_layouts;
     const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
     auto body = [&](hipStream_t st) -> hipError_t {
-        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st, 1);
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st, 1);
         if (e == hipSuccess) e = launch_clear(a.S, n, st);
         if (e == hipSuccess) e = timed_trace(c, false, graph, a, (int)blocks, st);
         if (e == hipSuccess) e = launch_finalize(a.S, d_E, n, c->d_flags, st);
@@ -958,7 +965,7 @@ int lt_trace_adjoint_rv(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_param
     a.rotvec = 1;
     const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
     auto body = [&](hipStream_t st) -> hipError_t {
-        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st, 1);
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st, 1);
         if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
         if (e == hipSuccess) e = launch_grad_reduce_rv(c->d_partials7, c->d_range, d_params, c->L, d_grad, st);
         return e;
@@ -1004,7 +1011,7 @@ int lt_trace_adjoint_cone(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_par
     const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
     auto body = [&](hipStream_t st) -> hipError_t {
         hipError_t e =
-            launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st, 0, c->d_cone);
+            launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st, 0, c->d_cone);
         if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
         if (e == hipSuccess)
             e = launch_grad_reduce_cone(c->d_partials8, c->d_range, c->L, d_grad, d_grad_cone, st);
@@ -1066,7 +1073,7 @@ int lt_trace_forward_dir(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_para
     const long long n = (long long)(order + 1) * (order + 1) * c->K * c->n_layouts;
     const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
     auto body = [&](hipStream_t st) -> hipError_t {
-        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess) e = launch_clear(a.S, n, st);
         if (e == hipSuccess) e = timed_trace(c, false, graph, a, (int)blocks, st);
         if (e == hipSuccess) e = launch_finalize(a.S, d_E, n, c->d_flags, st);
@@ -1096,7 +1103,7 @@ int lt_trace_adjoint_dir(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_para
     a.glossy = c->glossy;
     const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
     auto body = [&](hipStream_t st) -> hipError_t {
-        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st);
+        hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess && d_bin_hist) e = launch_fill_f32(d_bin_hist, (long long)c->L * 1024, 0.0f, st);
         if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
         if (e == hipSuccess) e = launch_grad_reduce(c->d_partials, c->d_range, c->L, d_grad, st);
@@ -1161,7 +1168,7 @@ int lt_pt_forward(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int
     if (rc) return rc;
     const long long n = c->K * c->n_layouts;
     hipStream_t st = c->stream;
-    HIPCHK(c, launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st));
+    HIPCHK(c, launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st));
     HIPCHK(c, launch_clear((long long*)d_S, n, st));
     for (int j = 0; j < c->n_layouts; ++j) {
         PtArgs a = pt_args(c, cfg, samples_per_texel, j);
@@ -1190,7 +1197,7 @@ int lt_pt_adjoint(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int
         c->ptgrad_cap = need;
     }
     hipStream_t st = c->stream;
-    HIPCHK(c, launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, st));
+    HIPCHK(c, launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st));
     HIPCHK(c, launch_fill_f32((float*)c->d_ptgrad, (long long)need * 2, 0.0f, st));
     for (int j = 0; j < c->n_layouts; ++j) {
         PtArgs a = pt_args(c, cfg, samples_per_texel, j);
@@ -1249,7 +1256,7 @@ int lt_record_paths(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, i
         r.prop_guide = c->prop_guide;
         r.alpha_plain = cfg->alpha_plain;
     }
-    HIPCHK(c, launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->stream));
+    HIPCHK(c, launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, c->stream));
     HIPCHK(c, launch_record(r, c->tune.lds_depth, c->stream));
     return LT_OK;
 }
@@ -1267,7 +1274,7 @@ int lt_trace_stats(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, in
     TraceArgs a = trace_args(c, cfg);
     a.S = (long long*)d_S;
     HIPCHK(c, hipMemsetAsync(c->d_stats, 0, sizeof(unsigned long long) * 8, c->stream));
-    HIPCHK(c, launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->stream));
+    HIPCHK(c, launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, c->stream));
     HIPCHK(c, launch_clear(a.S, c->K * c->n_layouts, c->stream));
     HIPCHK(c, launch_trace(false, true, a, c->tune.waves_per_block, c->tune.lds_depth, (int)blocks, c->stream));
     unsigned long long h[8];

@@ -186,7 +186,8 @@ struct DevLight {
     int type, layout, l_local;
     float kcap;  // soft-edged spot: flux scale of cap sampling (1 otherwise)
     long long n_paths;
-    long long pad1;
+    int invalid;  // parameters not finite or power not positive: the light adds nothing
+    int pad1;
 };  // 160 B
 
 // Moeller-Trumbore with the contract's order; barycentric bounds widened by

@@ -15,6 +15,11 @@ constexpr int kPlocRadius = 16;       // nearest-neighbour window of the BVH bui
 constexpr int kBvhWidth = 4;          // children per node of the traversed tree
 constexpr int kEmptyChild = (int)0x80000000;  // unused child slot of a wide node
 
+// sticky device status bits (the LT_STATUS_* values of the C ABI)
+constexpr unsigned kStatusOverflow = 1u;   // a texel accumulator reached 2^62
+constexpr unsigned kStatusTraversal = 2u;  // a segment exceeded its node-visit bound
+constexpr unsigned kStatusParams = 4u;     // a luminaire parameter was not finite or its power not positive
+
 // emission-proposal MLP: x [32] -> 64 -> 64 -> 1024 cells
 constexpr int kMlpParams = 6, kMlpEmbed = 16, kMlpIn = 32, kMlpHidden = 64, kMlpBins = 1024;
 constexpr int kMlpOffW1 = 0;                                    // [64][32]
@@ -136,8 +141,8 @@ hipError_t launch_trace(bool adjoint, bool stats, const TraceArgs& a, int waves_
                         int blocks, hipStream_t st);
 hipError_t launch_record(const RecordArgs& a, int lds_depth, hipStream_t st);
 hipError_t launch_light_setup(const float* params, const int4* lstat_i, const float4* lstat_f,
-                              const long long* npaths, int n_lights, DevLight* out, hipStream_t st, int rv = 0,
-                              float* cone = nullptr);
+                              const long long* npaths, int n_lights, DevLight* out, unsigned* flags,
+                              hipStream_t st, int rv = 0, float* cone = nullptr);
 hipError_t launch_grad_reduce_cone(const double* partials, const int2* range, int n_lights, float* grad,
                                    float* gcone, hipStream_t st);
 hipError_t launch_grad_reduce_rv(const double* partials, const int2* range, const float* params, int n_lights,

@@ -644,7 +644,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(M
         const int4 ti = a.tiles[tile];
         const DevLight& L = a.lights[ti.x];
         const uint32_t first = (uint32_t)ti.y;
-        const int count = ti.z;
+        const int count = L.invalid ? 0 : ti.z;   // a rejected luminaire traces nothing
         const uint32_t stream_id = ((uint32_t)ti.w << 16) | (uint32_t)L.l_local;
         constexpr int NC = DIR ? (DORD + 1) * (DORD + 1) : 1;
         const long long rowK = (MODE == 2 ? 3 : (DIR ? NC : 1)) * a.K;
@@ -788,7 +788,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(M
                         U4 us = {0u, 0u, 0u, 0u};
                         for (int j = 0; j < a.dir_samples; ++j) {
                             if ((j & 1) == 0)
-                                us = philox10(pid, stream_id, 0x100u + 16u * (uint32_t)h + (uint32_t)(j >> 1), 0u, a.key0,
+                                us = philox10(pid, stream_id, 0x100u + 32u * (uint32_t)h + (uint32_t)(j >> 1), 0u, a.key0,
                                               a.key1);
                             const float ua = (j & 1) ? u24(us.z) : u24(us.x);
                             const float ub = (j & 1) ? u24(us.w) : u24(us.y);
@@ -1015,7 +1015,7 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(M
         }
         const unsigned wm = wave_sum(miss);
         if (lane == 0 && wm) atomicAdd(a.misses, (unsigned long long)wm);
-        if (overrun) atomicOr(a.flags, 2u);
+        if (overrun) atomicOr(a.flags, kStatusTraversal);
         if (STATS) {
             const unsigned c0 = wave_sum(n_seg), c1 = wave_sum(n_nodes), c2 = wave_sum(n_tris),
                            c3 = wave_sum(n_hits);
@@ -1052,6 +1052,11 @@ __global__ void __launch_bounds__(256) k_record(RecordArgs a)
         for (int hh = 0; hh < a.max_hits; ++hh) {
             a.prim[idx * a.max_hits + hh] = -1;
             a.texel[idx * a.max_hits + hh] = -1;
+        }
+        if (L.invalid) {
+            if (a.contrib)
+                for (int c = 0; c < 6; ++c) a.contrib[idx * 6 + c] = 0.0f;
+            continue;
         }
         V3 y, dir;
         float au, av, phi_r;
@@ -1108,7 +1113,7 @@ __global__ void __launch_bounds__(256) k_record(RecordArgs a)
         if (a.contrib) {
             for (int c = 0; c < 6; ++c) a.contrib[idx * 6 + c] = (g && h >= 1) ? s_r * dphi[c] : 0.0f;
         }
-        if (overrun) atomicOr(a.flags, 2u);
+        if (overrun) atomicOr(a.flags, kStatusTraversal);
     }
 }
 
@@ -1224,7 +1229,7 @@ __global__ void __launch_bounds__(256) k_pt(PtArgs a)
                 if (have_side) n1 = nside;
                 else n1 = dot(nqv, w) < 0.0f ? nqv : v3(-nqv.x, -nqv.y, -nqv.z);
                 const float cv = -dot(n1, w);
-                const float I = cv > 0.0f ? light_intensity(L, w) : 0.0f;
+                const float I = (cv > 0.0f && !L.invalid) ? light_intensity(L, w) : 0.0f;
                 if (I > 0.0f) {
                     const float C = (I * cv) / r2;
                     Ray sr;
@@ -1274,7 +1279,7 @@ __global__ void __launch_bounds__(256) k_pt(PtArgs a)
                                    __HIP_MEMORY_SCOPE_AGENT);
         }
     }
-    if (overrun) atomicOr(a.flags, 2u);
+    if (overrun) atomicOr(a.flags, kStatusTraversal);
     if (ADJ) {
         __syncthreads();
         for (int j = threadIdx.x; j < a.nl * 6; j += 256)
@@ -1356,11 +1361,29 @@ __device__ void rot_jacobian_f64(const double th[3], double J[9])
 
 __global__ void k_light_setup(const float* __restrict__ params, const int4* __restrict__ si,
                               const float4* __restrict__ sf, const long long* __restrict__ npaths, int n,
-                              DevLight* __restrict__ out, int rv, float* __restrict__ cone)
+                              DevLight* __restrict__ out, unsigned* __restrict__ flags, int rv,
+                              float* __restrict__ cone)
 {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= n) return;
-    const float* p = params + (rv ? 7 : 6) * l;
+    // a luminaire whose parameters are not all finite, or whose power is not
+    // positive, raises the sticky parameter status and is set up from benign
+    // stand-in values (origin 0, default frame, unit power) with no paths'
+    // worth of flux: its work tiles then trace nothing, so no NaN or
+    // out-of-range value reaches a fixed-point splat or a gradient sum
+    const int np = rv ? 7 : 6;
+    float p[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    bool ok = true;
+    for (int c = 0; c < np; ++c) {
+        p[c] = params[np * l + c];
+        ok = ok && __builtin_isfinite(p[c]);
+    }
+    ok = ok && p[np - 1] > 0.0f;
+    if (!ok) {
+        atomicOr(flags, kStatusParams);
+        for (int c = 0; c < np; ++c) p[c] = 0.0f;
+        p[np - 1] = 1.0f;
+    }
     double sa_d, ca_d, sb_d, cb_d;
     sincos_f64((double)p[3], sa_d, ca_d);
     sincos_f64((double)p[4], sb_d, cb_d);
@@ -1424,6 +1447,8 @@ __global__ void k_light_setup(const float* __restrict__ params, const int4* __re
     }
     L.layout = i4.y;
     L.l_local = i4.z;
+    L.invalid = ok ? 0 : 1;
+    if (!ok) L.phi_r = 0.0f;
     L.pad1 = 0;
     out[l] = L;
 }
@@ -1463,7 +1488,7 @@ __global__ void k_finalize(const long long* __restrict__ S, float* __restrict__ 
         ovf |= (v >= (1ll << 62)) | (v <= -(1ll << 62));
         E[n - 1] = (float)((double)v * 0x1p-32);
     }
-    if (ovf) atomicOr(flags, 1u);
+    if (ovf) atomicOr(flags, kStatusOverflow);
 }
 
 // O = 1/2 sum A_k alpha_k (E_k - E*_k)^2 (FP64, fixed grid + fixed tree),
@@ -1670,9 +1695,10 @@ hipError_t launch_record(const RecordArgs& a, int lds_depth, hipStream_t st)
 }
 
 hipError_t launch_light_setup(const float* params, const int4* si, const float4* sf, const long long* npaths,
-                              int n_lights, DevLight* out, hipStream_t st, int rv, float* cone)
+                              int n_lights, DevLight* out, unsigned* flags, hipStream_t st, int rv, float* cone)
 {
-    k_light_setup<<<nblocks(n_lights, 64, 1 << 20), 64, 0, st>>>(params, si, sf, npaths, n_lights, out, rv, cone);
+    k_light_setup<<<nblocks(n_lights, 64, 1 << 20), 64, 0, st>>>(params, si, sf, npaths, n_lights, out, flags, rv,
+                                                                 cone);
     return hipGetLastError();
 }
 
@@ -1691,7 +1717,11 @@ __global__ void __launch_bounds__(64) k_grad_reduce_rv(const double* __restrict_
         for (int c = 0; c < 7; ++c) acc[c] += partials[(long long)t * 7 + c];
     for (int c = 0; c < 7; ++c) acc[c] = wave_sum(acc[c]);
     if (threadIdx.x == 0) {
-        const double th[3] = {(double)params[7 * l + 3], (double)params[7 * l + 4], (double)params[7 * l + 5]};
+        double th[3] = {(double)params[7 * l + 3], (double)params[7 * l + 4], (double)params[7 * l + 5]};
+        // a rejected luminaire (non-finite parameters) has zero partials; keep
+        // its Jacobian finite so that its gradient row is zero, not NaN
+        if (!(__builtin_isfinite(th[0]) && __builtin_isfinite(th[1]) && __builtin_isfinite(th[2])))
+            th[0] = th[1] = th[2] = 0.0;
         double J[9];
         rot_jacobian_f64(th, J);
         grad[7 * l + 0] = (float)acc[0];

@@ -1,11 +1,17 @@
 """torch.autograd.Function over the light tracer: backward = the adjoint kernel.
 
-Checked (a) against a direct adjoint call with the same dO/dE, and (b)
-against central finite differences of the objective with common random
-numbers (h = 1e-3 m / 1e-3 rad), averaged over seeds, on batched room-set
-layouts: first without furniture (no moving shadows, tight bound), then with
-furniture, where the moving-shadow terms the method leaves out (Sec. 4.3)
-add a bias, reported and bounded loosely.
+Checked (a) against the CPU oracle end to end: the E the function returns
+is bit-identical to the oracle's primal pass, and the gradient its backward
+leaves in params.grad matches the oracle's adjoint pass at g = A (E - E*),
+with the forward's seed (correlated evaluation) and with the decorrelated
+seed (Sec. 4.3); three steps of the Adam loop driven by the GPU match three
+steps driven by oracle gradients; (b) against a direct adjoint call with the
+same dO/dE; and (c) against central finite differences of the objective with
+common random numbers (h = 1e-3 m / 1e-3 rad), averaged over seeds, on
+batched room-set layouts: first without furniture (no moving shadows, 2 %
+on the dominant components, the oracle pin's bar), then with furniture,
+where the moving-shadow terms the method leaves out (Sec. 4.3) add a bias,
+reported and bounded loosely.
 """
 import math
 import sys
@@ -35,6 +41,115 @@ def tracer_for(scene, lights, ppl, B, seed, linear=False):
     from paper_2310_02043_amd.autograd import LightTracer
     return LightTracer((scene.verts, scene.tris, scene.tri_patch, scene.patches), lights.static,
                        lights.layout_offsets, ppl, B, seed=seed, linear=linear)
+
+
+def _oracle_case(case):
+    """(scene, lights, paths per layout, hits, seed, target [n_layouts, K])"""
+    if case == "box_room":
+        c1 = li.box_room()
+        sc, lights = c1["scene"], c1["lights"]
+        return sc, lights, c1["paths"], c1["max_hits"], c1["seed"], li.painted_target(sc, 20.0)[None]
+    c3 = li.room_set(n_layouts=3, min_lights=4, max_lights=9)
+    sc, lights = c3["scene"], c3["lights"]
+    Et = np.stack([li.painted_target(sc, 3.0, seed=j) for j in range(lights.n_layouts)])
+    return sc, lights, 1 << 16, c3["max_hits"], c3["seed"], Et
+
+
+@pytest.mark.parametrize("correlated", [True, False])
+@pytest.mark.parametrize("case", ["box_room", "room_set_3_layouts"])
+def test_autograd_matches_oracle(torch_dev, oracle_lib, case, correlated):
+    """LightTraceFn end to end against the oracle: E bit-identical to the
+    oracle's primal pass (Alg. 1) and params.grad after O.backward() within
+    1e-3 of the oracle's adjoint pass (Alg. 2) at g = A (E - E*), replayed
+    with the forward's seed or with the decorrelated seed."""
+    torch = torch_dev
+    from paper_2310_02043_amd.autograd import DECORRELATE, objective
+    sc, lights, ppl, B, seed, Et = _oracle_case(case)
+    say(f"autograd vs oracle: {case}, {lights.n_layouts} layout(s), {lights.n_lights} lights, {ppl} paths, "
+        f"correlated={correlated}")
+    tr = tracer_for(sc, lights, ppl, B, seed)
+    tr.correlated = correlated
+    A = torch.tensor(sc.texel_area(), device="cuda")
+    p = torch.tensor(lights.params, device="cuda", requires_grad=True)
+    E = tr(p)
+    O = objective(E, torch.tensor(Et, device="cuda"), A)
+    O.backward()
+    torch.cuda.synchronize()
+    assert tr.ctx.sync() == 0
+    osc = oracle_lib.OracleScene(sc, use_bvh=case != "box_room")
+    ol = oracle_lib.OracleLights(lights)
+    S_ref, _ = oracle_lib.forward(osc, ol, lights.params, seed, ppl, B)
+    E_ref = oracle_lib.fixed_to_float(S_ref)
+    E_gpu = E.detach().cpu().numpy()
+    assert E_gpu.shape == E_ref.shape
+    same = float((E_gpu == E_ref).mean())
+    say(f"  E bit-identical on {same * 100:.4f} % of texels")
+    assert np.array_equal(E_gpu, E_ref)
+    O_ref, g_ref = oracle_lib.objective(E_ref, Et, sc.texel_area())
+    say(f"  O {O.item():.9g} vs oracle {O_ref:.9g}")
+    assert abs(O.item() - O_ref) <= 1e-9 * abs(O_ref)
+    aseed = seed if correlated else seed ^ DECORRELATE
+    grad_ref, _ = oracle_lib.adjoint(osc, ol, lights.params, aseed, ppl, B, g_ref)
+    G = p.grad.detach().cpu().numpy().astype(np.float64)
+    scale = np.maximum(np.abs(grad_ref), 1e-6 * np.abs(grad_ref).max())
+    err = float(np.max(np.abs(G - grad_ref) / scale))
+    say(f"  params.grad vs oracle adjoint: max rel err {err:.3e}")
+    assert err <= 1e-3
+    if not correlated:
+        # the decorrelated replay really traced other paths
+        grad_cor, _ = oracle_lib.adjoint(osc, ol, lights.params, seed, ppl, B, g_ref)
+        assert np.max(np.abs(G - grad_cor) / scale) > 1e-3
+
+
+def test_adam_steps_match_oracle(torch_dev, oracle_lib):
+    """Three steps of the optimisation loop (Adam, beta 0.9 / 0.999, scaled
+    and masked coordinates, projection, a fresh seed per step and the
+    decorrelated adjoint seed; Sec. 6 with Sec. 4.3) on the GPU against the
+    same three steps driven by the oracle's primal and adjoint passes with
+    torch's Adam on the CPU: the parameters agree within 1e-5."""
+    torch = torch_dev
+    from paper_2310_02043_amd.autograd import DECORRELATE
+    from paper_2310_02043_amd.optimize import optimize
+    c1 = li.box_room()
+    sc, lights = c1["scene"], c1["lights"]
+    ppl, B, seed, steps, lr = 1 << 18, c1["max_hits"], 31, 3, 0.05
+    scale = [1.0, 1.0, 1.0, 0.5, 0.5, 10.0]
+    mask = [1, 1, 1, 1, 1, 1]
+    lo, hi = [0.2, 0.2, 0.5, -0.5, -0.5, 1.0], [3.8, 2.8, 2.4, 0.5, 0.5, 500.0]
+    Et = li.painted_target(sc, 20.0)[None]
+    A_np = sc.texel_area()
+    tr = tracer_for(sc, lights, ppl, B, seed)
+    A = torch.tensor(A_np, device="cuda")
+    p0 = torch.tensor(lights.params, device="cuda")
+    p_gpu, hist = optimize(tr, p0, torch.tensor(Et, device="cuda"), A, steps, lr=lr, scale=scale, mask=mask,
+                           lo=lo, hi=hi, seed=seed)
+    p_gpu = p_gpu.cpu().numpy().astype(np.float64)
+    # the same loop on the CPU, every gradient from the oracle
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    p0c = torch.tensor(lights.params)
+    sc_t, mk = torch.tensor(scale), torch.tensor(mask, dtype=torch.float32)
+    lo_t, hi_t = torch.tensor(lo), torch.tensor(hi)
+    q = torch.zeros_like(p0c, requires_grad=True)
+    opt = torch.optim.Adam([q], lr=lr, betas=(0.9, 0.999))
+    for it in range(steps):
+        s = seed + 7919 * it
+        p = (p0c + q.detach() * sc_t).numpy().astype(np.float32)
+        S_ref, _ = oracle_lib.forward(osc, ol, p, s, ppl, B)
+        O_ref, g_ref = oracle_lib.objective(oracle_lib.fixed_to_float(S_ref), Et, A_np)
+        say(f"  step {it}: O gpu {hist[it]['objective']:.9g} oracle {O_ref:.9g}")
+        assert abs(hist[it]["objective"] - O_ref) <= 1e-6 * abs(O_ref)
+        grad_ref, _ = oracle_lib.adjoint(osc, ol, p, s ^ DECORRELATE, ppl, B, g_ref)
+        opt.zero_grad()
+        q.grad = (torch.tensor(grad_ref, dtype=torch.float32) * sc_t) * mk
+        opt.step()
+        with torch.no_grad():
+            q.copy_((torch.maximum(torch.minimum(p0c + q * sc_t, hi_t), lo_t) - p0c) / sc_t)
+    p_ref = (p0c + q.detach() * sc_t).numpy().astype(np.float64)
+    moved = np.abs(p_ref - lights.params).max()
+    err = (np.abs(p_gpu - p_ref) / np.maximum(1.0, np.abs(p_ref))).max()
+    say(f"  parameters after {steps} steps: max |gpu - oracle| / max(1, |p|) {err:.3e} (moved up to {moved:.3e})")
+    assert moved > lr
+    assert err <= 1e-5
 
 
 @pytest.mark.parametrize("basis", ["box", "linear"])
@@ -129,14 +244,17 @@ def test_autograd_finite_differences(torch_dev, furnished):
                 continue
             m = D[:, l, c].mean()
             se = D[:, l, c].std(ddof=1) / math.sqrt(n_seeds)
-            ref = Gm[l, c] if c == 5 else scale
+            # occluder-free: 2 % of the component itself where it is a
+            # dominant one (at least a tenth of the light's largest
+            # geometric component), 2 % of that tenth otherwise
+            ref = Gm[l, c] if c == 5 else max(Gm[l, c], 0.1 * scale)
             rel = abs(m) / max(ref, 1e-12)
             worst = max(worst, rel)
             say(f"  light {l} p{c}: grad {Gm[l, c]:.4e}  fd-adj {m:+.3e} (se {se:.1e}, rel {rel:.3f})")
             if not furnished:
-                assert abs(m) < 4.5 * se + 0.03 * ref
+                assert abs(m) < 4.5 * se + 0.02 * ref
             else:
-                assert abs(m) < 4.5 * se + 0.25 * ref
+                assert abs(m) < 4.5 * se + 0.25 * (Gm[l, c] if c == 5 else scale)
     say("  worst relative mean difference:", worst)
 
 

@@ -253,25 +253,114 @@ def test_batched_layouts_reduced(torch_dev, oracle_lib, launch):
              c3["max_hits"], use_bvh=True, tuning=tuning)
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_determinism_and_graph_replay(torch_dev, oracle_lib, graph):
+@pytest.mark.parametrize("case", ["box_room", "room_set_64_layouts"])
+def test_graph_replay_matches_eager_and_oracle(torch_dev, oracle_lib, case):
+    """The forward and adjoint sequences captured as hipGraphs and replayed
+    into fixed buffers (so every call after the first replays the cached
+    graph): S, E and the gradient bit-identical to an eager run on every
+    replay, with unrelated eager work between replays, and the eager run
+    bit-identical (texels) / within 1e-3 (gradient) of the oracle.  Inputs
+    changed in place between replays (dO/dE doubled, a luminaire moved) must
+    be seen by the replay, so a graph holding stale pointers or sizes fails."""
+    torch = torch_dev
+    if case == "box_room":
+        c = li.box_room()
+        ppl, use_bvh = 1 << 18, False
+    else:
+        c = li.room_set()
+        ppl, use_bvh = 1 << 14, True
+    sc, lights, B, seed = c["scene"], c["lights"], c["max_hits"], 77
+    say(f"graph replay: {case}, {lights.n_layouts} layouts, {ppl} paths per layout")
+    ctx = make_ctx(torch, sc, lights)
+    nl, K = lights.n_layouts, sc.n_texels
+    p_d = torch.tensor(lights.params, device="cuda")
+    S = torch.empty((nl, K), dtype=torch.int64, device="cuda")
+    E = torch.empty((nl, K), dtype=torch.float32, device="cuda")
+    grad = torch.empty((lights.n_lights, 6), dtype=torch.float32, device="cuda")
+    # eager reference and the oracle
+    cfg_e, cfg_g = ctx.cfg(seed, ppl, B), ctx.cfg(seed, ppl, B, graph=True)
+    ctx.trace_forward(p_d, cfg_e, S=S, E=E)
+    S_e, E_e = S.clone(), E.clone()
+    osc, ol = oracle_lib.OracleScene(sc, use_bvh=use_bvh), oracle_lib.OracleLights(lights)
+    S_ref, _ = oracle_lib.forward(osc, ol, lights.params, seed, ppl, B)
+    assert np.array_equal(S_e.cpu().numpy(), S_ref)
+    Et = np.stack([li.painted_target(sc, float(np.mean(oracle_lib.fixed_to_float(S_ref)[j])) * 1.5 + 1e-3, seed=j)
+                   for j in range(nl)])
+    _, g_ref = oracle_lib.objective(oracle_lib.fixed_to_float(S_ref), Et, sc.texel_area())
+    g = torch.tensor(g_ref, device="cuda")
+    ctx.trace_adjoint(p_d, g, cfg_e, grad=grad)
+    G_e = grad.clone()
+    grad_ref, _ = oracle_lib.adjoint(osc, ol, lights.params, seed, ppl, B, g_ref)
+    e = grad_rel(G_e.cpu().numpy(), grad_ref)
+    say(f"  eager gradient vs oracle: max rel err {e:.3e}")
+    assert e <= GRAD_BAR
+    for rep in range(4):
+        S.fill_(-1)
+        E.fill_(float("nan"))
+        grad.fill_(float("nan"))
+        ctx.trace_forward(p_d, cfg_g, S=S, E=E)
+        torch.cuda.synchronize()
+        assert torch.equal(S, S_e) and torch.equal(E, E_e), rep
+        ctx.trace_adjoint(p_d, g, cfg_g, grad=grad)
+        torch.cuda.synchronize()
+        assert torch.equal(grad, G_e), rep
+        _ = (E * 2).sum().item()   # unrelated eager work between replays
+    assert ctx.sync() == 0
+    # the replay reads its inputs through the captured pointers: new contents
+    # are seen (the adjoint is linear in dO/dE and doubling is exact in FP32)
+    g.mul_(2.0)
+    ctx.trace_adjoint(p_d, g, cfg_g, grad=grad)
+    torch.cuda.synchronize()
+    assert torch.equal(grad, 2.0 * G_e)
+    p_d[0, 0] += 0.05
+    ctx.trace_forward(p_d, cfg_g, S=S, E=E)
+    S_moved = S.clone()
+    ctx.trace_forward(p_d, cfg_e, S=S, E=E)
+    torch.cuda.synchronize()
+    assert torch.equal(S_moved, S) and not torch.equal(S_moved, S_e)
+    assert ctx.sync() == 0
+
+
+def test_autotune_search_parity(torch_dev, oracle_lib, tmp_path):
+    """lt_autotune's coordinate search (no cache entry) on the box room picks
+    a launch shape; traced with it, texels are bit-identical to the oracle's
+    and the gradient within 1e-3; the choice is written to the cache file and
+    a second context reads it back instead of searching."""
     torch = torch_dev
     c1 = li.box_room()
-    ctx = make_ctx(torch, c1["scene"], c1["lights"])
-    p_d = torch.tensor(c1["lights"].params, device="cuda")
-    cfg = ctx.cfg(77, 1 << 18, 3, graph=graph)
-    E0, S0 = ctx.trace_forward(p_d, cfg)
-    S0 = S0.clone()
-    g = torch.randn_like(E0)
-    G0 = ctx.trace_adjoint(p_d, g, cfg).clone()
-    for rep in range(3):
-        E1, S1 = ctx.trace_forward(p_d, cfg)
-        torch.cuda.synchronize()
-        assert torch.equal(S0, S1)
-        G1 = ctx.trace_adjoint(p_d, g, cfg)
-        torch.cuda.synchronize()
-        assert torch.equal(G0, G1)
-        _ = (E1 * 2).sum().item()   # unrelated eager work between replays
+    sc, lights, B, seed = c1["scene"], c1["lights"], c1["max_hits"], c1["seed"]
+    ppl = c1["paths"]
+    ctx = make_ctx(torch, sc, lights)
+    p_d = torch.tensor(lights.params, device="cuda")
+    S = torch.empty((1, sc.n_texels), dtype=torch.int64, device="cuda")
+    E = torch.empty((1, sc.n_texels), dtype=torch.float32, device="cuda")
+    g = torch.randn((1, sc.n_texels), device="cuda")
+    grad = torch.empty((lights.n_lights, 6), dtype=torch.float32, device="cuda")
+    cache = str(tmp_path / "tuning.cache")
+    before = ctx.get_tuning().as_dict()
+    best = ctx.autotune(p_d, ctx.cfg(seed, ppl, B), S, E, g, grad, cache_path=cache)
+    chosen = ctx.get_tuning().as_dict()
+    say(f"  autotune: {before} -> {chosen} ({best:.3f} ms fwd+adj)")
+    assert best > 0.0
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1
+    cfg = ctx.cfg(seed, ppl, B)
+    ctx.trace_forward(p_d, cfg, S=S, E=E)
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    S_ref, _ = oracle_lib.forward(osc, ol, lights.params, seed, ppl, B)
+    assert np.array_equal(S.cpu().numpy(), S_ref)
+    E_ref = oracle_lib.fixed_to_float(S_ref)
+    _, g_ref = oracle_lib.objective(E_ref, li.painted_target(sc, 20.0)[None], sc.texel_area())
+    grad_ref, _ = oracle_lib.adjoint(osc, ol, lights.params, seed, ppl, B, g_ref)
+    gr = ctx.trace_adjoint(p_d, torch.tensor(g_ref, device="cuda"), cfg)
+    assert ctx.sync() == 0
+    e = grad_rel(gr.cpu().numpy(), grad_ref)
+    say(f"  tuned launch: texels bit-identical, gradient max rel err {e:.3e}")
+    assert e <= GRAD_BAR
+    ctx2 = make_ctx(torch, sc, lights)
+    best2 = ctx2.autotune(p_d, ctx2.cfg(seed, ppl, B), S, E, g, grad, cache_path=cache)
+    assert ctx2.get_tuning().as_dict() == chosen and abs(best2 - best) < 1e-2
+    assert len(open(cache).read().strip().splitlines()) == 1
 
 
 @pytest.mark.parametrize("case", ["ragged", "one_path_per_light", "single_hit", "point_closed_box",
@@ -352,3 +441,66 @@ def test_invalid_arguments_raise(torch_dev):
     bad["texel_base"][1] += 1
     with pytest.raises(LtError):
         ctx.upload_scene(c1["scene"].verts, c1["scene"].tris, c1["scene"].tri_patch, bad)
+
+
+@pytest.mark.parametrize("bad", ["negative_power", "nan_position", "inf_tilt", "zero_power"])
+def test_invalid_luminaire_parameters_flagged(torch_dev, oracle_lib, bad):
+    """Luminaire parameters are checked on the device by every trace call: a
+    NaN or infinite parameter or a power P <= 0 raises the parameter status,
+    which lt_sync reports as LT_EINVAL (once: the status is then cleared), and
+    that luminaire traces nothing.  Texels equal the oracle's with that
+    luminaire's power set to zero (bit-identical), the other luminaires'
+    gradients match the oracle's, and its own gradient row is exactly zero."""
+    torch = torch_dev
+    from paper_2310_02043_amd.native import LtError, LT_EINVAL
+    sc = li.box_room()["scene"]
+    params = np.array([[1.0, 1.0, 2.0, 0.1, 0.2, 50.0], [3.0, 2.0, 1.8, 0, 0, 30.0],
+                       [2.0, 1.5, 2.4, -0.2, 0.3, 70.0]], np.float32)
+    lights = make_lights([SPOT, POINT, RECT], [3.0, 0.0, 2.0], [(0, 0), (0, 0), (0.5, 0.3)], [0, 0, 0], params)
+    bad_light = {"negative_power": 1, "nan_position": 2, "inf_tilt": 0, "zero_power": 2}[bad]
+    p_bad = params.copy()
+    if bad == "negative_power":
+        p_bad[1, 5] = -30.0
+    elif bad == "nan_position":
+        p_bad[2, 0] = np.nan
+    elif bad == "inf_tilt":
+        p_bad[0, 3] = np.inf
+    else:
+        p_bad[2, 5] = 0.0
+    say(f"invalid luminaire: {bad} on light {bad_light}")
+    ctx = make_ctx(torch, sc, lights)
+    ppl, B, seed = 30_001, 3, 0x1BAD
+    cfg = ctx.cfg(seed, ppl, B)
+    p_d = torch.tensor(p_bad, device="cuda")
+    E_d, S_d = ctx.trace_forward(p_d, cfg)
+    with pytest.raises(LtError) as ei:
+        ctx.sync()
+    assert ei.value.code == LT_EINVAL
+    assert ctx.sync() == 0
+    p_ref = params.copy()
+    p_ref[bad_light, 5] = 0.0
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    S_ref, _ = oracle_lib.forward(osc, ol, p_ref, seed, ppl, B)
+    assert np.array_equal(S_d.cpu().numpy(), S_ref)
+    assert np.isfinite(E_d.cpu().numpy()).all()
+    E_ref = oracle_lib.fixed_to_float(S_ref)
+    _, g_ref = oracle_lib.objective(E_ref, li.painted_target(sc, 10.0)[None], sc.texel_area())
+    grad = ctx.trace_adjoint(p_d, torch.tensor(g_ref, device="cuda"), cfg).cpu().numpy()
+    with pytest.raises(LtError):
+        ctx.sync()
+    assert np.all(grad[bad_light] == 0.0)
+    grad_ref, _ = oracle_lib.adjoint(osc, ol, p_ref, seed, ppl, B, g_ref)
+    ok = [l for l in range(3) if l != bad_light]
+    e = grad_rel(grad[ok], grad_ref[ok])
+    say(f"  other luminaires' gradients: max rel err {e:.3e}")
+    assert e <= GRAD_BAR
+    # the rotation-vector form: a non-finite rotation vector gives a zero row, not NaN
+    p7 = np.concatenate([params[:, :3], np.zeros((3, 3), np.float32), params[:, 5:]], 1)
+    p7[bad_light, 3] = np.nan
+    g7 = ctx.trace_adjoint_rv(torch.tensor(p7, device="cuda"), torch.tensor(g_ref, device="cuda"), cfg).cpu().numpy()
+    with pytest.raises(LtError):
+        ctx.sync()
+    assert np.all(g7[bad_light] == 0.0) and np.isfinite(g7).all()
+    # valid parameters again: no status
+    ctx.trace_forward(torch.tensor(params, device="cuda"), cfg)
+    assert ctx.sync() == 0

@@ -51,27 +51,57 @@ def _inputs(rng, L):
     return x
 
 
-def test_mlp_inference_matches_oracle(torch_dev):
+def _ctx_with_lights(torch, n):
+    """Box room with n cos^n spots (the network's batch is one row per light)."""
+    from lt_inputs.scenes import make_lights, SPOT
+    from paper_2310_02043_amd import Context
+    sc = li.box_room()["scene"]
+    rng = np.random.default_rng(n)
+    ps = [[rng.uniform(0.5, 3.5), rng.uniform(0.5, 2.5), rng.uniform(1.5, 2.4), rng.uniform(-0.3, 0.3),
+           rng.uniform(-0.3, 0.3), rng.uniform(5, 20)] for _ in range(n)]
+    lights = make_lights([SPOT] * n, rng.uniform(1, 6, n), [(0, 0)] * n, [0] * n, ps)
+    ctx = Context(0)
+    ctx.upload_scene(sc.verts, sc.tris, sc.tri_patch, sc.patches)
+    ctx.set_lights(lights.static, lights.layout_offsets)
+    return ctx
+
+
+@pytest.mark.parametrize("L", [13, 16, 128])
+def test_mlp_inference_matches_oracle(torch_dev, L):
+    """MFMA inference (16-row blocks, so 13 is one partial block and 128 the
+    building floor's eight) against the numpy network with the same bfloat16
+    rounding points: logits within 1e-5 of the row's largest and cell
+    probabilities within 1e-5 in L1, per light.  Where FP32 accumulation may
+    legitimately round a hidden activation to the other bfloat16 neighbour
+    (the exact value lies within the accumulation bound of a tie), every such
+    rounding is admissible and the GPU must match one of them; a truncating
+    conversion or a dropped tail row fails."""
     torch = torch_dev
     from oracle import proposal as op
-    c2 = li.office(target_tris=20_000, target_texels=200_000)
-    ctx = office_ctx(torch, c2["scene"], c2["lights"])
-    rng = np.random.default_rng(0)
-    L = ctx.n_lights
+    ctx = _ctx_with_lights(torch, L)
+    rng = np.random.default_rng(L)
     w = _weights(rng)
     x = _inputs(rng, L)
     wb = torch.tensor(op.bf16_bits(w).view(np.int16), device="cuda")
-    logits = torch.empty((L, 1024), dtype=torch.float32, device="cuda")
+    logits = torch.full((L, 1024), float("nan"), dtype=torch.float32, device="cuda")
     ctx.mlp_infer(wb, torch.tensor(x, device="cuda"), logits)
     pdf_d, cdf_d = ctx.proposal_get_table()
     torch.cuda.synchronize()
-    z_ref, p_ref = op.infer(w, x)
-    z = logits.cpu().numpy()
-    err = np.abs(z - z_ref).max() / np.abs(z_ref).max()
-    say("  logits max rel err", err)
-    assert err < 5e-3
-    pdf = pdf_d.cpu().numpy()
-    assert np.abs(pdf - p_ref).sum(1).max() < 2e-2
+    z = logits.cpu().numpy().astype(np.float64)
+    pdf = pdf_d.cpu().numpy().astype(np.float64)
+    alts = op.infer_alternatives(w, x)
+    checked, multi, worst_z, worst_p = 0, 0, 0.0, 0.0
+    for r in range(L):
+        assert alts[r] is not None, f"row {r}: too many admissible roundings"
+        best = min(alts[r], key=lambda zp: np.abs(z[r] - zp[0]).max())
+        ez = float(np.abs(z[r] - best[0]).max() / np.abs(best[0]).max())
+        ep = float(np.abs(pdf[r] - best[1]).sum())
+        worst_z, worst_p = max(worst_z, ez), max(worst_p, ep)
+        checked += 1
+        multi += len(alts[r]) > 1
+        assert ez <= 1e-5 and ep <= 1e-5, (r, ez, ep, len(alts[r]))
+    say(f"  L={L}: logits max rel err {worst_z:.2e}, pdf L1 {worst_p:.2e} "
+        f"({multi} of {checked} rows with an ambiguous bf16 rounding)")
     cdf = cdf_d.cpu().numpy()
     assert np.all(cdf[:, -1] == 1.0) and np.all(np.diff(cdf, axis=1) >= 0)
     assert np.allclose(pdf.sum(1), 1.0, atol=1e-5)

@@ -73,6 +73,31 @@ def test_philox_uniformity(oracle_lib):
     assert abs(r) < 5 / math.sqrt(u.size)
 
 
+def test_directional_sample_uniforms_do_not_repeat(oracle_lib):
+    """The directional mode's local samples (up to 64 per hit, two per
+    generator draw) take their own generator blocks at every hit: over all
+    hits a path can have (1..64) and all sample indices, the (block, half)
+    pairs are distinct and never coincide with the emission (0), proposal (1)
+    or bounce (1 + h) blocks, and the uniform pairs drawn for one path are all
+    different.  Consecutive hits sharing samples would correlate a path's
+    bounces (no bias, more variance)."""
+    seen = set()
+    for h in range(1, 65):
+        for j in range(64):
+            b = oracle_lib.dir_block(h, j)
+            assert b > 65
+            seen.add((b, j & 1))
+    assert len(seen) == 64 * 64
+    key = [0x1234567, 0x89ABCDE]
+    pairs = set()
+    for h in range(1, 9):
+        for j in range(0, 64, 2):
+            x = oracle_lib.philox([42, (3 << 16) | 5, oracle_lib.dir_block(h, j), 0], key)
+            pairs.add((int(x[0]), int(x[1])))
+            pairs.add((int(x[2]), int(x[3])))
+    assert len(pairs) == 8 * 64
+
+
 def test_sincos2pi(oracle_lib):
     us = np.concatenate([np.arange(0, 1 << 24, 997) * 2.0 ** -24, [0.0, 0.25, 0.5, 0.75, 1 - 2.0 ** -24]])
     for u in us[::7]:
@@ -1374,6 +1399,37 @@ def test_mlp_backprop_matches_finite_differences():
         assert abs(fd - gx[r, c]) < 1e-6 + 1e-5 * abs(gx[r, c])
     # a softmax cross-entropy lower bound: loss >= entropy of the target
     assert loss >= float(-(t * np.log(t)).sum() / L) - 1e-9
+
+
+def test_mlp_admissible_roundings():
+    """The set of admissible bfloat16 roundings of the hidden activations
+    (what FP32 accumulation in an unknown order may produce) always holds
+    the nominal round-to-nearest-even network, and is exactly it when the
+    accumulation bound is zero; a network that truncates its activations to
+    bfloat16 instead is admissible for almost no light."""
+    from oracle import proposal as op
+    rng = np.random.default_rng(9)
+    L = 24
+    w = rng.normal(0, 0.15, op.N_WEIGHTS).astype(np.float32)
+    x = np.zeros((L, op.IN), np.float32)
+    x[:, :op.NPAR + op.NEMB] = rng.normal(0, 1, (L, op.NPAR + op.NEMB))
+    z, p = op.infer(w, x)
+    alts = op.infer_alternatives(w, x)
+    exact = op.infer_alternatives(w, x, tol=0.0)
+    for r in range(L):
+        assert min(np.abs(zz - z[r]).max() for zz, _ in alts[r]) < 1e-12
+        assert len(exact[r]) == 1 and np.abs(exact[r][0][0] - z[r]).max() < 1e-12
+    # truncation instead of rounding to nearest even
+    def trunc(a):
+        u = np.ascontiguousarray(a, np.float32).view(np.uint32) & np.uint32(0xFFFF0000)
+        return u.view(np.float32).astype(np.float64)
+    W1, b1, W2, b2, W3, b3 = op.unpack(op.bf16_round(w).astype(np.float64))
+    xb = op.bf16_round(x).astype(np.float64)
+    h1 = trunc(np.maximum(xb @ W1.T + b1, 0.0).astype(np.float32))
+    h2 = trunc(np.maximum(h1 @ W2.T + b2, 0.0).astype(np.float32))
+    zt = h2 @ W3.T + b3
+    ok = sum(min(np.abs(zz - zt[r]).max() / np.abs(zz).max() for zz, _ in alts[r]) <= 1e-5 for r in range(L))
+    assert ok <= 1
 
 
 def test_tangent_vs_central_differences_convex_room(oracle_lib):
