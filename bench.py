@@ -151,8 +151,7 @@ def proposal_study(ctx, wl, N, seeds=32, ref_runs=48, train_iters=30, alpha=0.2,
         e = gh.double() - ref
         return float(e.norm() / ref.norm()), float((e / unit).norm() / (ref / unit).norm())
 
-    lp = LearnedProposal(ctx, [0, 0, 2.5, -0.6, -0.6, 0], [30, 20, 3.0, 0.6, 0.6, 80], alpha_plain=alpha,
-                         lobe_n=lights.static["lobe_n"])
+    lp = LearnedProposal(ctx, [0, 0, 2.5, -0.6, -0.6, 0], [30, 20, 3.0, 0.6, 0.6, 80], alpha_plain=alpha)
     lp.refresh(p0)
     losses = []
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

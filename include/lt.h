@@ -381,6 +381,51 @@ int lt_proposal_mlp_train(lt_ctx* ctx, float* d_w, float* d_mw, float* d_vw, uin
                           float* d_mx, float* d_vx, const float* d_target, int32_t step, float lr, float* d_loss,
                           float* d_grad_out);
 
+/* The proposal network held by the context, so that a training step takes
+ * only the adjoint histogram.  lt_proposal_set copies the FP32 master
+ * weights d_w [LT_MLP_WEIGHTS] (layout as above) and the per-light
+ * embeddings d_embed [L,16] into the context, zeroes the Adam moments,
+ * derives the BF16 copy and computes the plain cos^n lobe's probability of
+ * every cell (midpoint rule, 8 x 8 points per cell, FP64) for the training
+ * target's floor; it replaces any earlier network and is dropped by
+ * lt_set_lights.  cfg: the box that maps each parameter to the network input
+ * 2 (p - lo)/(hi - lo) - 1 (finite, lo < hi), the running-average weights of
+ * the histogram and of the squared gradients (in [0, 1)), and the plain
+ * lobe's share of the target (in [0, 1]). */
+typedef struct {
+    float param_lo[6], param_hi[6];
+    float hist_decay;   /* weight of the old average of the normalised histogram */
+    float plain_floor;  /* share of the plain lobe's cell masses in the target */
+    float sigma_decay;  /* weight of the old mean squared gradient component */
+    int32_t reserved;
+} lt_proposal_cfg;
+int lt_proposal_set(lt_ctx* ctx, const float* d_w, const float* d_embed, const lt_proposal_cfg* cfg);
+/* Network inputs from the luminaire parameters d_params [L,6] (the box of
+ * lt_proposal_set), then inference into the sampling tables as
+ * lt_proposal_mlp_infer. */
+int lt_proposal_refresh(lt_ctx* ctx, const float* d_params);
+/* Histogram units from one adjoint gradient d_grad [L,6]: the running mean
+ * s of each squared component (the first call starts it), then the scale
+ * 1/sqrt(s + 1e-30) times h_mask[c] (host [6], NULL = all ones; a component
+ * with mask 0 does not enter the histogram), as lt_proposal_set_scale. */
+int lt_proposal_update_scale(lt_ctx* ctx, const float* d_grad, const float* h_mask);
+/* One training round from the adjoint histogram d_bin_hist [L,1024]
+ * (lt_trace_adjoint): each light's row is normalised (an empty row counts as
+ * uniform) and folded into the running average (the first call starts it);
+ * the target is the normalised square root of that average (the
+ * variance-optimal cell probabilities, see lt_proposal_set_scale), mixed with
+ * the plain lobe's cell masses by plain_floor; then `steps` (0..1000) Adam
+ * steps of lt_proposal_mlp_train toward it with learning rate lr on the
+ * context's network (step count continuing across calls).  d_loss (one f32,
+ * the last step's loss) and d_target_out [L,1024] f32 may be NULL.
+ * Call lt_proposal_refresh afterwards to sample from the trained network. */
+int lt_proposal_train_step(lt_ctx* ctx, const float* d_bin_hist, float lr, int32_t steps, float* d_loss,
+                           float* d_target_out);
+/* Copy the context's FP32 master weights d_w [LT_MLP_WEIGHTS] and network
+ * inputs d_x [L,32] (normalised parameters, embeddings, zero padding) out;
+ * either may be NULL. */
+int lt_proposal_get_net(lt_ctx* ctx, float* d_w, float* d_x);
+
 int lt_get_tuning(const lt_ctx* ctx, lt_tuning* out);
 int lt_set_tuning(lt_ctx* ctx, const lt_tuning* t);
 

@@ -9,7 +9,12 @@ writes the network out plainly in float64:
 * inference mirrors the kernel's rounding points (weights, inputs and hidden
   activations rounded to bfloat16, accumulation in higher precision);
 * a training step is cross-entropy to a target distribution, backpropagated
-  by hand, followed by Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+  by hand, followed by Adam (beta1 0.9, beta2 0.999, eps 1e-8);
+* the training target from an adjoint histogram of the scaled gradient's
+  second moment per cell: the variance-optimal cell probabilities are
+  proportional to the square root of that moment, averaged over passes and
+  mixed with the plain cos^n lobe's cell masses (a midpoint quadrature of
+  the lobe over each cell of the hemi-octahedral map).
 """
 from __future__ import annotations
 
@@ -156,3 +161,42 @@ def cdf_table(pdf):
     out = c.astype(np.float32)
     out[:, -1] = 1.0
     return out
+
+
+def plain_cell_mass(lobe_n, sub: int = 8):
+    """Probability of each 32 x 32 hemi-octahedral cell (index v * 32 + u)
+    under the plain lobe (n + 1)/(2 pi) cos^n(theta) d(omega), with
+    d(omega) = du dv / (2 |p|^3) for p = ((u+v)/2, (u-v)/2, 1-|.|-|.|):
+    midpoint rule on sub x sub points per cell, each light's row normalised."""
+    out = []
+    h = 1.0 / (16.0 * sub)
+    c = -1.0 + (np.arange(32 * sub) + 0.5) * h
+    v, u = np.meshgrid(c, c, indexing="ij")
+    x, y = (u + v) / 2.0, (u - v) / 2.0
+    z = 1.0 - np.abs(x) - np.abs(y)
+    r = np.sqrt(x * x + y * y + z * z)
+    dw = h * h / (2.0 * r ** 3)
+    for n in np.atleast_1d(np.asarray(lobe_n, np.float64)):
+        dens = (n + 1.0) / (2.0 * np.pi) * (z / r) ** n * dw
+        m = dens.reshape(32, sub, 32, sub).sum(axis=(1, 3)).reshape(1024)
+        out.append(m / m.sum())
+    return np.asarray(out)
+
+
+def training_target(hist, h_avg, decay, plain_mass=None, floor=0.0):
+    """Target cell probabilities from one adjoint histogram hist [L,1024]
+    (per cell, an estimate of the second moment of the scaled gradient
+    integrand).  Each row is normalised (an empty row counts as uniform) and
+    folded into the running average h_avg with weight `decay` on the old
+    average (h_avg None: the first pass); the target is the normalised square
+    root of the average, mixed with the plain lobe's masses by `floor`.
+    Returns (target, new h_avg), float64."""
+    h = np.asarray(hist, np.float64)
+    tot = h.sum(axis=1, keepdims=True)
+    hn = np.where(tot > 0, h / np.where(tot > 0, tot, 1.0), 1.0 / h.shape[1])
+    a = hn if h_avg is None else decay * np.asarray(h_avg, np.float64) + (1.0 - decay) * hn
+    r = np.sqrt(a)
+    t = r / r.sum(axis=1, keepdims=True)
+    if plain_mass is not None and floor > 0:
+        t = (1.0 - floor) * t + floor * np.asarray(plain_mass, np.float64)
+    return t, a

@@ -102,6 +102,20 @@ struct lt_ctx {
     float* mlp_scratch = nullptr;
     size_t mlp_scratch_cap = 0;
 
+    // proposal network owned by the context (lt_proposal_set): FP32 master
+    // weights, Adam moments, BF16 copy, inputs [L,32] with the embeddings,
+    // running histogram average and plain-lobe cell masses [L,1024] (FP64),
+    // the last training target [L,1024], running squared gradients [L,6]
+    bool has_net = false;
+    float *net_w = nullptr, *net_mw = nullptr, *net_vw = nullptr;
+    uint16_t* net_wb = nullptr;
+    float *net_x = nullptr, *net_mx = nullptr, *net_vx = nullptr;
+    double *net_havg = nullptr, *net_pmass = nullptr;
+    float *net_target = nullptr, *net_sig2 = nullptr;
+    int net_step = 0;
+    bool net_havg_ok = false, net_sig2_ok = false;
+    lt_proposal_cfg net_cfg;
+
     // kernel timing (events around trace kernels launched outside graphs)
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> t_fwd, t_adj;
@@ -130,6 +144,19 @@ void free_graphs(lt_ctx* c)
     if (c->gstream && !c->graphs.empty()) hipStreamSynchronize(c->gstream);
     for (auto& g : c->graphs) hipGraphExecDestroy(g.exec);
     c->graphs.clear();
+}
+
+void free_net(lt_ctx* c)
+{
+    hipFree(c->net_w); hipFree(c->net_mw); hipFree(c->net_vw); hipFree(c->net_wb);
+    hipFree(c->net_x); hipFree(c->net_mx); hipFree(c->net_vx);
+    hipFree(c->net_havg); hipFree(c->net_pmass); hipFree(c->net_target); hipFree(c->net_sig2);
+    c->net_w = c->net_mw = c->net_vw = nullptr;
+    c->net_wb = nullptr;
+    c->net_x = c->net_mx = c->net_vx = nullptr;
+    c->net_havg = c->net_pmass = nullptr;
+    c->net_target = c->net_sig2 = nullptr;
+    c->has_net = false;
 }
 
 void free_scene(lt_ctx* c)
@@ -431,6 +458,7 @@ void lt_destroy(lt_ctx* c)
     free_tiles(c);
     hipFree(c->d_si); hipFree(c->d_sf); hipFree(c->d_lights);
     hipFree(c->prop_pdf); hipFree(c->prop_cdf); hipFree(c->prop_guide); hipFree(c->inv_sigma); hipFree(c->mlp_scratch);
+    free_net(c);
     hipFree(c->d_misses); hipFree(c->d_flags); hipFree(c->d_stats);
     hipFree(c->d_objpart); hipFree(c->d_partials); hipFree(c->d_gstack); hipFree(c->d_ptgrad);
     hipFree(c->d_partials_col); hipFree(c->d_partials7); hipFree(c->d_pfd);
@@ -614,6 +642,7 @@ int lt_set_lights(lt_ctx* c, const lt_light_static* h_lights, int32_t n_lights, 
     hipFree(c->prop_pdf); hipFree(c->prop_cdf); hipFree(c->prop_guide); hipFree(c->inv_sigma);
     c->d_si = nullptr; c->d_sf = nullptr; c->d_lights = nullptr;
     c->prop_pdf = nullptr; c->prop_cdf = nullptr; c->prop_guide = nullptr; c->inv_sigma = nullptr;
+    free_net(c);
     c->has_lights = false;
     c->has_proposal = false;
     HIPCHK(c, hipMalloc(&c->d_si, sizeof(int4) * n_lights));
@@ -1396,6 +1425,139 @@ int lt_proposal_mlp_train(lt_ctx* c, float* d_w, float* d_mw, float* d_vw, uint1
     }
     HIPCHK(c, launch_mlp_train(d_w, d_mw, d_vw, d_w_bf16, d_x, d_mx, d_vx, d_target, c->L, step, lr, c->mlp_scratch,
                                d_loss, d_grad_out, c->stream));
+    return LT_OK;
+}
+
+int lt_proposal_set(lt_ctx* c, const float* d_w, const float* d_embed, const lt_proposal_cfg* cfg)
+{
+    if (!c) return LT_EINVAL;
+    if (!c->has_lights) return fail(c, LT_ESTATE, "no luminaires set");
+    if (!d_w || !d_embed || !cfg) return fail(c, LT_EINVAL, "NULL argument");
+    for (int k = 0; k < 6; ++k)
+        if (!isfinite(cfg->param_lo[k]) || !isfinite(cfg->param_hi[k]) || !(cfg->param_hi[k] > cfg->param_lo[k]))
+            return fail(c, LT_EINVAL, "parameter box needs finite lo < hi");
+    if (!(cfg->hist_decay >= 0.0f && cfg->hist_decay < 1.0f) || !(cfg->sigma_decay >= 0.0f && cfg->sigma_decay < 1.0f))
+        return fail(c, LT_EINVAL, "decays must lie in [0, 1)");
+    if (!(cfg->plain_floor >= 0.0f && cfg->plain_floor <= 1.0f)) return fail(c, LT_EINVAL, "plain_floor outside [0, 1]");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    free_net(c);
+    const size_t L = (size_t)c->L, nw = kMlpWeights;
+    HIPCHK(c, hipMalloc(&c->net_w, sizeof(float) * nw));
+    HIPCHK(c, hipMalloc(&c->net_mw, sizeof(float) * nw));
+    HIPCHK(c, hipMalloc(&c->net_vw, sizeof(float) * nw));
+    HIPCHK(c, hipMalloc(&c->net_wb, sizeof(uint16_t) * nw));
+    HIPCHK(c, hipMalloc(&c->net_x, sizeof(float) * L * kMlpIn));
+    HIPCHK(c, hipMalloc(&c->net_mx, sizeof(float) * L * kMlpIn));
+    HIPCHK(c, hipMalloc(&c->net_vx, sizeof(float) * L * kMlpIn));
+    HIPCHK(c, hipMalloc(&c->net_havg, sizeof(double) * L * kMlpBins));
+    HIPCHK(c, hipMalloc(&c->net_pmass, sizeof(double) * L * kMlpBins));
+    HIPCHK(c, hipMalloc(&c->net_target, sizeof(float) * L * kMlpBins));
+    HIPCHK(c, hipMalloc(&c->net_sig2, sizeof(float) * L * 6));
+    HIPCHK(c, hipMemcpyAsync(c->net_w, d_w, sizeof(float) * nw, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->net_mw, 0, sizeof(float) * nw, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->net_vw, 0, sizeof(float) * nw, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->net_x, 0, sizeof(float) * L * kMlpIn, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->net_mx, 0, sizeof(float) * L * kMlpIn, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->net_vx, 0, sizeof(float) * L * kMlpIn, c->stream));
+    HIPCHK(c, hipMemcpy2DAsync(c->net_x + kMlpParams, sizeof(float) * kMlpIn, d_embed, sizeof(float) * kMlpEmbed,
+                               sizeof(float) * kMlpEmbed, L, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, launch_to_bf16(c->net_w, c->net_wb, (int)nw, c->stream));
+    // the plain lobe's cell masses (the training target's floor)
+    std::vector<float> lobe(L);
+    for (size_t l = 0; l < L; ++l) lobe[l] = c->lights[l].lobe_n;
+    float* d_lobe = nullptr;
+    HIPCHK(c, hipMalloc(&d_lobe, sizeof(float) * L));
+    HIPCHK(c, hipMemcpy(d_lobe, lobe.data(), sizeof(float) * L, hipMemcpyHostToDevice));
+    hipError_t e = launch_plain_mass(d_lobe, c->L, c->net_pmass, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    hipFree(d_lobe);
+    HIPCHK(c, e);
+    c->net_cfg = *cfg;
+    c->net_step = 0;
+    c->net_havg_ok = false;
+    c->net_sig2_ok = false;
+    c->has_net = true;
+    return LT_OK;
+}
+
+int lt_proposal_refresh(lt_ctx* c, const float* d_params)
+{
+    if (!c) return LT_EINVAL;
+    if (!c->has_net) return fail(c, LT_ESTATE, "no proposal network (lt_proposal_set)");
+    if (!d_params) return fail(c, LT_EINVAL, "NULL device buffer");
+    HIPCHK(c, hipSetDevice(c->device));
+    ParamBox box;
+    for (int k = 0; k < 6; ++k) {
+        box.lo[k] = c->net_cfg.param_lo[k];
+        box.hi[k] = c->net_cfg.param_hi[k];
+    }
+    HIPCHK(c, launch_proposal_inputs(d_params, c->L, box, c->net_x, c->stream));
+    HIPCHK(c, launch_mlp_infer(c->net_wb, c->net_x, c->L, nullptr, c->prop_pdf, c->prop_cdf, c->stream));
+    HIPCHK(c, launch_guide_build(c->prop_cdf, c->L, c->prop_guide, c->stream));
+    c->has_proposal = true;
+    return LT_OK;
+}
+
+int lt_proposal_update_scale(lt_ctx* c, const float* d_grad, const float* h_mask)
+{
+    if (!c) return LT_EINVAL;
+    if (!c->has_net) return fail(c, LT_ESTATE, "no proposal network (lt_proposal_set)");
+    if (!d_grad) return fail(c, LT_EINVAL, "NULL device buffer");
+    Param6 m;
+    for (int k = 0; k < 6; ++k) {
+        m.v[k] = h_mask ? h_mask[k] : 1.0f;
+        if (!isfinite(m.v[k])) return fail(c, LT_EINVAL, "non-finite mask");
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_proposal_scale(d_grad, c->L, c->net_sig2, c->net_sig2_ok ? 0 : 1, c->net_cfg.sigma_decay, m,
+                                    c->inv_sigma, c->stream));
+    c->net_sig2_ok = true;
+    return LT_OK;
+}
+
+int lt_proposal_train_step(lt_ctx* c, const float* d_bin_hist, float lr, int32_t steps, float* d_loss,
+                           float* d_target_out)
+{
+    if (!c) return LT_EINVAL;
+    if (!c->has_net) return fail(c, LT_ESTATE, "no proposal network (lt_proposal_set)");
+    if (!d_bin_hist) return fail(c, LT_EINVAL, "NULL device buffer");
+    if (!(lr > 0.0f) || !isfinite(lr)) return fail(c, LT_EINVAL, "invalid learning rate");
+    if (steps < 0 || steps > 1000) return fail(c, LT_EINVAL, "steps must be in [0, 1000]");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_proposal_target(d_bin_hist, c->L, c->net_havg, c->net_pmass, c->net_havg_ok ? 0 : 1,
+                                     (double)c->net_cfg.hist_decay, (double)c->net_cfg.plain_floor, c->net_target,
+                                     c->stream));
+    c->net_havg_ok = true;
+    if (d_target_out)
+        HIPCHK(c, hipMemcpyAsync(d_target_out, c->net_target, sizeof(float) * 1024 * (size_t)c->L,
+                                 hipMemcpyDeviceToDevice, c->stream));
+    const size_t need = mlp_train_scratch_floats(c->L);
+    if (need > c->mlp_scratch_cap) {
+        hipFree(c->mlp_scratch);
+        c->mlp_scratch = nullptr;
+        c->mlp_scratch_cap = 0;
+        HIPCHK(c, hipMalloc(&c->mlp_scratch, sizeof(float) * need));
+        c->mlp_scratch_cap = need;
+    }
+    for (int s = 0; s < steps; ++s) {
+        ++c->net_step;
+        HIPCHK(c, launch_mlp_train(c->net_w, c->net_mw, c->net_vw, c->net_wb, c->net_x, c->net_mx, c->net_vx,
+                                   c->net_target, c->L, c->net_step, lr, c->mlp_scratch, d_loss, nullptr, c->stream));
+    }
+    return LT_OK;
+}
+
+int lt_proposal_get_net(lt_ctx* c, float* d_w, float* d_x)
+{
+    if (!c) return LT_EINVAL;
+    if (!c->has_net) return fail(c, LT_ESTATE, "no proposal network (lt_proposal_set)");
+    HIPCHK(c, hipSetDevice(c->device));
+    if (d_w)
+        HIPCHK(c, hipMemcpyAsync(d_w, c->net_w, sizeof(float) * kMlpWeights, hipMemcpyDeviceToDevice, c->stream));
+    if (d_x)
+        HIPCHK(c, hipMemcpyAsync(d_x, c->net_x, sizeof(float) * kMlpIn * (size_t)c->L, hipMemcpyDeviceToDevice,
+                                 c->stream));
     return LT_OK;
 }
 

@@ -162,7 +162,22 @@ hipError_t launch_objective(const float* E, const float* Et, const float* alpha,
                             long long n, float* g, double* partials, double* O, hipStream_t st);
 hipError_t launch_grad_reduce(const double* partials, const int2* tile_range, int n_lights, float* grad,
                               hipStream_t st);
+// the box [lo, hi] that maps luminaire parameters to network inputs, and a
+// per-parameter factor, passed by value
+struct ParamBox {
+    float lo[6], hi[6];
+};
+struct Param6 {
+    float v[6];
+};
 size_t mlp_train_scratch_floats(int L);
+hipError_t launch_plain_mass(const float* lobe_n, int L, double* mass, hipStream_t st);
+hipError_t launch_to_bf16(const float* w, uint16_t* wb, int n, hipStream_t st);
+hipError_t launch_proposal_target(const float* hist, int L, double* h_avg, const double* pmass, int first,
+                                  double decay, double floor_w, float* target, hipStream_t st);
+hipError_t launch_proposal_inputs(const float* params, int L, const ParamBox& box, float* x, hipStream_t st);
+hipError_t launch_proposal_scale(const float* grad, int L, float* sig2, int first, float decay, const Param6& mask,
+                                 float* inv_sigma, hipStream_t st);
 hipError_t launch_guide_build(const float* cdf, int L, int* guide, hipStream_t st);
 hipError_t launch_mlp_infer(const uint16_t* wb, const float* x, int L, float* logits, float* pdf, float* cdf,
                             hipStream_t st);

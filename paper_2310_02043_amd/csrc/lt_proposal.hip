@@ -285,7 +285,156 @@ __global__ void __launch_bounds__(1024) k_mlp_train(float* __restrict__ w, float
     for (int i = tid; i < kMlpWeights; i += nt) wb[i] = to_bf16(w[i]);
 }
 
+// ---------------------------------------------------------------------------
+// Training target and network inputs, computed where the tables live.
+// ---------------------------------------------------------------------------
+// Block-wide FP64 sum over 256 threads (fixed tree, so the result is
+// reproducible).
+__device__ __forceinline__ double block_sum256(double v, double* red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double out = red[0];
+    __syncthreads();
+    return out;
+}
+
+// Cell masses of the plain cos^n lobe: midpoint rule on kPlainSub^2 points
+// per cell of (n + 1)/(2 pi) cos^n(theta) d(omega), d(omega) = du dv / (2 |p|^3)
+// on the hemi-octahedral map, normalised per light.  One block per light,
+// four cells per thread, FP64.
+constexpr int kPlainSub = 8;
+__global__ void __launch_bounds__(256) k_plain_mass(const float* __restrict__ lobe_n, double* __restrict__ mass)
+{
+    __shared__ double red[256];
+    const int l = blockIdx.x;
+    const double n = (double)lobe_n[l];
+    const double h = 1.0 / (16.0 * kPlainSub);
+    double m[4], tot = 0.0;
+    for (int c = 0; c < 4; ++c) {
+        const int b = (int)threadIdx.x + 256 * c;
+        const int iu = b & 31, iv = b >> 5;
+        double acc = 0.0;
+        for (int sv = 0; sv < kPlainSub; ++sv)
+            for (int su = 0; su < kPlainSub; ++su) {
+                const double u = -1.0 + ((double)(iu * kPlainSub + su) + 0.5) * h;
+                const double v = -1.0 + ((double)(iv * kPlainSub + sv) + 0.5) * h;
+                const double x = 0.5 * (u + v), y = 0.5 * (u - v);
+                const double z = 1.0 - fabs(x) - fabs(y);
+                const double r = sqrt(x * x + y * y + z * z);
+                acc += (n + 1.0) * 0.15915494309189533577 * pow(z / r, n) * (h * h / (2.0 * r * r * r));
+            }
+        m[c] = acc;
+        tot += acc;
+    }
+    tot = block_sum256(tot, red);
+    for (int c = 0; c < 4; ++c) mass[1024 * (long long)l + threadIdx.x + 256 * c] = m[c] / tot;
+}
+
+// Training target of one pass: per light, the histogram row normalised (an
+// empty row counts as uniform), folded into the running average (weight
+// `decay` on the old one; `first` starts it), square root, normalised, then
+// mixed with the plain lobe's cell masses by `floor`.  One block per light.
+__global__ void __launch_bounds__(256) k_proposal_target(const float* __restrict__ hist, double* __restrict__ h_avg,
+                                                        const double* __restrict__ pmass, int first, double decay,
+                                                        double floor_w, float* __restrict__ target)
+{
+    __shared__ double red[256];
+    const long long row = 1024 * (long long)blockIdx.x;
+    double hv[4], tot = 0.0;
+    for (int c = 0; c < 4; ++c) {
+        hv[c] = (double)hist[row + threadIdx.x + 256 * c];
+        tot += hv[c];
+    }
+    tot = block_sum256(tot, red);
+    double r[4], rs = 0.0;
+    for (int c = 0; c < 4; ++c) {
+        const long long k = row + threadIdx.x + 256 * c;
+        const double hn = tot > 0.0 ? hv[c] / tot : 1.0 / 1024.0;
+        const double a = first ? hn : decay * h_avg[k] + (1.0 - decay) * hn;
+        h_avg[k] = a;
+        r[c] = sqrt(a);
+        rs += r[c];
+    }
+    rs = block_sum256(rs, red);
+    for (int c = 0; c < 4; ++c) {
+        const long long k = row + threadIdx.x + 256 * c;
+        double t = r[c] / rs;
+        if (floor_w > 0.0) t = (1.0 - floor_w) * t + floor_w * pmass[k];
+        target[k] = (float)t;
+    }
+}
+
+// Network inputs: the six parameters mapped to [-1, 1] by the box [lo, hi].
+__global__ void k_proposal_inputs(const float* __restrict__ params, int L, ParamBox box, float* __restrict__ x)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L * kMlpParams) return;
+    const int l = i / kMlpParams, c = i % kMlpParams;
+    x[l * kMlpIn + c] = (2.0f * (params[i] - box.lo[c])) / (box.hi[c] - box.lo[c]) - 1.0f;
+}
+
+// Histogram units: running mean of each light's squared gradient components
+// (weight `decay` on the old mean), then 1/sqrt(mean + 1e-30) times the
+// component mask (non-finite values become 0).
+__global__ void k_proposal_scale(const float* __restrict__ grad, int n, float* __restrict__ sig2, int first,
+                                 float decay, Param6 mask, float* __restrict__ inv_sigma)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float g2 = grad[i] * grad[i];
+    const float s = first ? g2 : decay * sig2[i] + (1.0f - decay) * g2;
+    sig2[i] = s;
+    float inv = 1.0f / __builtin_sqrtf(s + 1e-30f);
+    if (!__builtin_isfinite(inv)) inv = 0.0f;
+    inv_sigma[i] = inv * mask.v[i % kMlpParams];
+}
+
+__global__ void k_to_bf16(const float* __restrict__ w, uint16_t* __restrict__ wb, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) wb[i] = to_bf16(w[i]);
+}
+
 }  // namespace
+
+hipError_t launch_to_bf16(const float* w, uint16_t* wb, int n, hipStream_t st)
+{
+    k_to_bf16<<<(n + 255) / 256, 256, 0, st>>>(w, wb, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_mass(const float* lobe_n, int L, double* mass, hipStream_t st)
+{
+    k_plain_mass<<<L, 256, 0, st>>>(lobe_n, mass);
+    return hipGetLastError();
+}
+
+hipError_t launch_proposal_target(const float* hist, int L, double* h_avg, const double* pmass, int first,
+                                  double decay, double floor_w, float* target, hipStream_t st)
+{
+    k_proposal_target<<<L, 256, 0, st>>>(hist, h_avg, pmass, first, decay, floor_w, target);
+    return hipGetLastError();
+}
+
+hipError_t launch_proposal_inputs(const float* params, int L, const ParamBox& box, float* x, hipStream_t st)
+{
+    const int n = L * kMlpParams;
+    k_proposal_inputs<<<(n + 255) / 256, 256, 0, st>>>(params, L, box, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_proposal_scale(const float* grad, int L, float* sig2, int first, float decay, const Param6& mask,
+                                 float* inv_sigma, hipStream_t st)
+{
+    const int n = L * kMlpParams;
+    k_proposal_scale<<<(n + 255) / 256, 256, 0, st>>>(grad, n, sig2, first, decay, mask, inv_sigma);
+    return hipGetLastError();
+}
 
 size_t mlp_train_scratch_floats(int L) { return (size_t)L * (4 * kMlpHidden + kMlpBins + kMlpEmbed); }
 

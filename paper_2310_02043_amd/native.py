@@ -28,7 +28,8 @@ EXPORTED = [
     "lt_trace_stats", "lt_get_tuning", "lt_set_tuning", "lt_autotune", "lt_info_get", "lt_set_timing",
     "lt_timing_read", "lt_proposal_set_table", "lt_proposal_get_table", "lt_proposal_set_scale",
     "lt_proposal_mlp_infer",
-    "lt_proposal_mlp_train",
+    "lt_proposal_mlp_train", "lt_proposal_set", "lt_proposal_refresh", "lt_proposal_update_scale",
+    "lt_proposal_train_step", "lt_proposal_get_net",
 ]
 MLP_WEIGHTS, MLP_IN, MLP_BINS = 72832, 32, 1024
 
@@ -55,6 +56,11 @@ class Tuning(C.Structure):
     def as_dict(self):
         return {k: getattr(self, k) for k in ("waves_per_block", "xcd_remap", "tile_paths",
                                                "refill_threshold", "lds_depth", "tri_share")}
+
+
+class ProposalCfg(C.Structure):
+    _fields_ = [("param_lo", C.c_float * 6), ("param_hi", C.c_float * 6), ("hist_decay", C.c_float),
+                ("plain_floor", C.c_float), ("sigma_decay", C.c_float), ("reserved", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -113,6 +119,11 @@ def load():
     L.lt_proposal_get_table.argtypes = [P, P, P]
     L.lt_proposal_mlp_infer.argtypes = [P, P, P, P]
     L.lt_proposal_mlp_train.argtypes = [P, P, P, P, P, P, P, P, P, I32, C.c_float, P, P]
+    L.lt_proposal_set.argtypes = [P, P, P, C.POINTER(ProposalCfg)]
+    L.lt_proposal_refresh.argtypes = [P, P]
+    L.lt_proposal_update_scale.argtypes = [P, P, P]
+    L.lt_proposal_train_step.argtypes = [P, P, C.c_float, I32, P, P]
+    L.lt_proposal_get_net.argtypes = [P, P, P]
     L.lt_timing_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(I32), C.POINTER(C.c_double), C.POINTER(I32)]
     for name in EXPORTED:
         if name not in ("lt_destroy", "lt_last_error"):
@@ -533,6 +544,46 @@ class Context:
         self._check(self.lib.lt_proposal_mlp_train(self.h, _ptr(w), _ptr(mw), _ptr(vw), _ptr(w_bf16), _ptr(x),
                                                    _ptr(mx), _ptr(vx), _ptr(target), int(step), float(lr),
                                                    _ptr(loss), _ptr(grad_out)))
+
+    def proposal_set(self, w, embed, param_lo, param_hi, hist_decay=0.9, plain_floor=0.3, sigma_decay=0.9):
+        """Hand the network (FP32 weights [MLP_WEIGHTS], embeddings [L,16]) to the context."""
+        torch = self._torch
+        self._dev(w, torch.float32, (MLP_WEIGHTS,))
+        self._dev(embed, torch.float32, (self.n_lights, 16))
+        cfg = ProposalCfg()
+        cfg.param_lo[:] = [float(v) for v in param_lo]
+        cfg.param_hi[:] = [float(v) for v in param_hi]
+        cfg.hist_decay, cfg.plain_floor, cfg.sigma_decay = float(hist_decay), float(plain_floor), float(sigma_decay)
+        self._stream()
+        self._check(self.lib.lt_proposal_set(self.h, _ptr(w), _ptr(embed), C.byref(cfg)))
+
+    def proposal_refresh(self, params):
+        self._dev(params, self._torch.float32, (self.n_lights, 6))
+        self._stream()
+        self._check(self.lib.lt_proposal_refresh(self.h, _ptr(params)))
+
+    def proposal_update_scale(self, grad, mask=None):
+        self._dev(grad, self._torch.float32, (self.n_lights, 6))
+        m = None if mask is None else (C.c_float * 6)(*[float(v) for v in mask])
+        self._stream()
+        self._check(self.lib.lt_proposal_update_scale(self.h, _ptr(grad), m))
+
+    def proposal_train_step(self, hist, lr, steps, loss=None, target_out=None):
+        torch = self._torch
+        self._dev(hist, torch.float32, (self.n_lights, MLP_BINS))
+        if target_out is not None:
+            self._dev(target_out, torch.float32, (self.n_lights, MLP_BINS))
+        self._stream()
+        self._check(self.lib.lt_proposal_train_step(self.h, _ptr(hist), float(lr), int(steps), _ptr(loss),
+                                                    _ptr(target_out)))
+
+    def proposal_get_net(self):
+        torch = self._torch
+        w = torch.empty(MLP_WEIGHTS, dtype=torch.float32, device=f"cuda:{self.device}")
+        x = torch.empty((self.n_lights, MLP_IN), dtype=torch.float32, device=f"cuda:{self.device}")
+        self._stream()
+        self._check(self.lib.lt_proposal_get_net(self.h, _ptr(w), _ptr(x)))
+        return w, x
 
     def set_timing(self, enable: bool):
         self._check(self.lib.lt_set_timing(self.h, 1 if enable else 0))

@@ -185,8 +185,7 @@ def main(argv=None):
     lo = [0.5, 0.5, 0.0, -0.15, -0.15, 1.0]
     hi = [W - 0.5, D - 0.5, H, 0.15, 0.15, 200.0]
     if a.proposal:
-        tracer.proposal = LearnedProposal(tracer.ctx, lo, hi, alpha_plain=a.alpha_plain,
-                                          lobe_n=lights.static["lobe_n"])
+        tracer.proposal = LearnedProposal(tracer.ctx, lo, hi, alpha_plain=a.alpha_plain)
         tracer.alpha_plain = a.alpha_plain
     p0 = torch.tensor(lights.params, device=dev)
     if not a.no_autotune:

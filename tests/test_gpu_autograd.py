@@ -278,7 +278,7 @@ def test_adam_lighting_optimisation(torch_dev, learned):
     # tilts within +-0.15 rad keep the 0.6 m luminaires 6 cm or more below the ceiling
     lo, hi = [0.5, 0.5, 0.0, -0.15, -0.15, 1.0], [29.5, 19.5, 3.0, 0.15, 0.15, 200.0]
     if learned:
-        tr.proposal = LearnedProposal(tr.ctx, lo, hi, lobe_n=lights.static["lobe_n"])
+        tr.proposal = LearnedProposal(tr.ctx, lo, hi)
     p0 = torch.tensor(lights.params, device="cuda")
     O0 = evaluate(tr, p0, target, A, 1 << 24)
     p, hist = optimize(tr, p0, target, A, 40, lr=0.05, scale=[1, 1, 1, 0.5, 0.5, 10.0], mask=[1, 1, 0, 1, 1, 1],

@@ -140,6 +140,85 @@ def test_mlp_training_step_matches_oracle(torch_dev):
     assert np.array_equal(wb.cpu().numpy().view(np.uint16), op.bf16_bits(wd.cpu().numpy()))
 
 
+def test_proposal_train_step_matches_oracle(torch_dev, oracle_lib):
+    """The context-held network (lt_proposal_set / refresh / update_scale /
+    train_step): inputs normalised from the parameters, the training target
+    from two successive histograms (running average, square root, plain-lobe
+    floor; one light's row empty) within 1e-6 of the oracle's, one Adam step
+    toward it equal to the oracle's backprop + Adam, and the histogram scale
+    from two successive gradients driving an adjoint histogram equal to the
+    oracle's."""
+    torch = torch_dev
+    from oracle import proposal as op
+    c2 = li.office(target_tris=20_000, target_texels=200_000)
+    sc, lights = c2["scene"], c2["lights"]
+    ctx = office_ctx(torch, sc, lights)
+    L = ctx.n_lights
+    rng = np.random.default_rng(12)
+    d = lambda a: torch.tensor(a, device="cuda")  # noqa: E731
+    w = _weights(rng, 0.1)
+    emb = rng.normal(0, 0.5, (L, 16)).astype(np.float32)
+    lo = np.array([0, 0, 2.5, -0.6, -0.6, 0], np.float32)
+    hi = np.array([30, 20, 3.0, 0.6, 0.6, 80], np.float32)
+    decay, floor, sdecay, lr = 0.8, 0.3, 0.9, 1e-3
+    ctx.proposal_set(d(w), d(emb), lo, hi, hist_decay=decay, plain_floor=floor, sigma_decay=sdecay)
+    p = lights.params.astype(np.float32)
+    ctx.proposal_refresh(d(p))
+    w0, x0 = (t.cpu().numpy() for t in ctx.proposal_get_net())
+    x_ref = np.zeros((L, 32), np.float32)
+    x_ref[:, :6] = (np.float32(2.0) * (p - lo)) / (hi - lo) - np.float32(1.0)
+    x_ref[:, 6:22] = emb
+    assert np.array_equal(w0, w) and np.array_equal(x0, x_ref)
+    pm = op.plain_cell_mass(lights.static["lobe_n"])
+    h1 = rng.gamma(0.3, 1.0, (L, 1024)).astype(np.float32)
+    h1[3] = 0.0
+    h2 = rng.gamma(0.3, 1.0, (L, 1024)).astype(np.float32)
+    loss = torch.zeros(1, device="cuda")
+    tgt = torch.empty((L, 1024), device="cuda")
+    ctx.proposal_train_step(d(h1), lr, 1, loss=loss, target_out=tgt)
+    t1 = tgt.cpu().numpy()
+    t1_ref, avg = op.training_target(h1, None, decay, pm, floor)
+    e1 = np.abs(t1 - t1_ref).max() / t1_ref.max()
+    w1 = ctx.proposal_get_net()[0].cpu().numpy()
+    loss_ref, g_ref, _ = op.loss_and_grad(w, x_ref, t1)
+    w1_ref, _, _ = op.adam(w.astype(np.float64), 0.0, 0.0, g_ref, 1, lr)
+    big = np.abs(g_ref) > 1e-4 * np.abs(g_ref).max()
+    say(f"  target rel err {e1:.2e}; loss {loss.item():.6f} vs {loss_ref:.6f}")
+    assert e1 <= 1e-6 and np.allclose(t1.sum(1), 1.0, atol=1e-5)
+    assert abs(loss.item() / loss_ref - 1) < 1e-5
+    assert np.allclose(w1[big], w1_ref[big], atol=1e-6 + 1e-3 * lr)
+    ctx.proposal_train_step(d(h2), lr, 0, target_out=tgt)
+    t2_ref, _ = op.training_target(h2, avg, decay, pm, floor)
+    e2 = np.abs(tgt.cpu().numpy() - t2_ref).max() / t2_ref.max()
+    say(f"  second target (running average) rel err {e2:.2e}")
+    assert e2 <= 1e-6
+    # histogram units from two gradients, seen through the adjoint histogram
+    mask = [1, 1, 0, 1, 1, 1]
+    g1 = rng.normal(0, 3, (L, 6)).astype(np.float32)
+    g2 = rng.normal(0, 3, (L, 6)).astype(np.float32)
+    ctx.proposal_update_scale(d(g1), mask)
+    ctx.proposal_update_scale(d(g2), mask)
+    s2 = np.float32(sdecay) * (g1 * g1) + (np.float32(1.0) - np.float32(sdecay)) * (g2 * g2)
+    inv_sigma = (np.float32(1.0) / np.sqrt(s2 + np.float32(1e-30))) * np.array(mask, np.float32)
+    ctx.proposal_refresh(d(p))
+    pdf, cdf = (t.cpu().numpy() for t in ctx.proposal_get_table())
+    N, B, seed = 1 << 16, c2["max_hits"], 0x77
+    cfg = ctx.cfg(seed, N, B, proposal=True, alpha_plain=0.2)
+    prop = oracle_lib.Proposal(pdf, cdf, 0.2, inv_sigma=inv_sigma, with_hist=True)
+    osc, ol = oracle_lib.OracleScene(sc, use_bvh=True), oracle_lib.OracleLights(lights)
+    S_ref, _ = oracle_lib.forward(osc, ol, p, seed, N, B, proposal=prop)
+    _, g_ref2 = oracle_lib.objective(oracle_lib.fixed_to_float(S_ref), li.painted_target(sc, 0.5)[None],
+                                     sc.texel_area())
+    prop.hist[:] = 0.0
+    oracle_lib.adjoint(osc, ol, p, seed, N, B, g_ref2, proposal=prop)
+    hist_d = torch.zeros((L, 1024), device="cuda")
+    ctx.trace_adjoint(d(p), d(g_ref2), cfg, bin_hist=hist_d)
+    torch.cuda.synchronize()
+    herr = np.linalg.norm(hist_d.cpu().numpy() - prop.hist) / np.linalg.norm(prop.hist)
+    say(f"  adjoint histogram with the context's scale: rel-L2 {herr:.2e}")
+    assert herr <= 1e-4
+
+
 def _table(rng, L, types):
     from oracle.proposal import cdf_table
     logits = rng.normal(0, 2.5, (L, 1024))

@@ -101,55 +101,6 @@ def test_optimize_quadratic_power():
     assert torch.all(p_big[:, 5] >= 0)
 
 
-def _cell_mass_spherical(n, res=32, nt=400, nph=800):
-    """Independent check: integrate (n+1)/(2 pi) cos^n theta over the
-    hemisphere in (theta, phi) and bin each direction into its hemi-octahedral
-    cell (u = x' + y', v = x' - y' with (x', y') = (x, y) / (|x| + |y| + z))."""
-    th = (np.arange(nt) + 0.5) * (math.pi / 2) / nt
-    ph = (np.arange(nph) + 0.5) * (2 * math.pi) / nph
-    T, P = np.meshgrid(th, ph, indexing="ij")
-    x, y, z = np.sin(T) * np.cos(P), np.sin(T) * np.sin(P), np.cos(T)
-    s = np.abs(x) + np.abs(y) + z
-    u, v = (x + y) / s, (x - y) / s
-    iu = np.clip(np.floor((u + 1) * res / 2).astype(int), 0, res - 1)
-    iv = np.clip(np.floor((v + 1) * res / 2).astype(int), 0, res - 1)
-    w = (n + 1) / (2 * math.pi) * z ** n * np.sin(T) * (math.pi / 2 / nt) * (2 * math.pi / nph)
-    m = np.zeros(res * res)
-    np.add.at(m, (iv * res + iu).ravel(), w.ravel())
-    return m
-
-
-@pytest.mark.parametrize("n", [0.0, 1.0, 4.0])
-def test_plain_cell_mass(n):
-    from paper_2310_02043_amd.proposal import plain_cell_mass
-    m = plain_cell_mass([n], sub=16)[0]
-    ref = _cell_mass_spherical(n)
-    assert abs(m.sum() - 1) < 1e-12 and abs(ref.sum() - 1) < 2e-3
-    # coarse 4x4 blocks agree (the spherical grid's binning is the rougher one)
-    mb = m.reshape(8, 4, 8, 4).sum((1, 3))
-    rb = ref.reshape(8, 4, 8, 4).sum((1, 3))
-    assert np.max(np.abs(mb - rb)) < 2e-3
-
-
-def test_training_target():
-    from paper_2310_02043_amd.proposal import training_target
-    h = torch.zeros(2, 4, dtype=torch.float64)
-    h[0] = torch.tensor([4.0, 0.0, 1.0, 11.0])
-    t, avg = training_target(h, None, 0.5)
-    r = torch.sqrt(torch.tensor([4.0, 0.0, 1.0, 11.0], dtype=torch.float64) / 16)
-    assert torch.allclose(t[0], r / r.sum())
-    assert torch.allclose(t[1], torch.full((4,), 0.25, dtype=torch.float64))      # empty histogram: uniform
-    # running average, then the plain-lobe floor
-    h2 = torch.tensor([[0.0, 0.0, 0.0, 8.0], [1.0, 1.0, 1.0, 1.0]], dtype=torch.float64)
-    pm = torch.tensor([[0.1, 0.2, 0.3, 0.4]] * 2, dtype=torch.float64)
-    t2, avg2 = training_target(h2, avg, 0.75, pm, 0.3)
-    a = 0.75 * avg + 0.25 * (h2 / h2.sum(1, keepdim=True))
-    r2 = torch.sqrt(a)
-    assert torch.allclose(avg2, a)
-    assert torch.allclose(t2, 0.7 * r2 / r2.sum(1, keepdim=True) + 0.3 * pm)
-    assert torch.allclose(t2.sum(1), torch.ones(2, dtype=torch.float64))
-
-
 def test_band_weights_and_chromaticity():
     """Per-band objective weights: order-0 band at w00, the rest 1, expanded
     as alpha_k alpha_l over [layouts, (order+1)^2, K]; the torch objective with

@@ -1401,6 +1401,88 @@ def test_mlp_backprop_matches_finite_differences():
     assert loss >= float(-(t * np.log(t)).sum() / L) - 1e-9
 
 
+def _cell_mass_spherical(n, res=32, nt=400, nph=800):
+    """Independent check: integrate (n+1)/(2 pi) cos^n theta over the
+    hemisphere in (theta, phi) and bin each direction into its hemi-octahedral
+    cell (u = x' + y', v = x' - y' with (x', y') = (x, y) / (|x| + |y| + z))."""
+    th = (np.arange(nt) + 0.5) * (math.pi / 2) / nt
+    ph = (np.arange(nph) + 0.5) * (2 * math.pi) / nph
+    T, P = np.meshgrid(th, ph, indexing="ij")
+    x, y, z = np.sin(T) * np.cos(P), np.sin(T) * np.sin(P), np.cos(T)
+    s = np.abs(x) + np.abs(y) + z
+    u, v = (x + y) / s, (x - y) / s
+    iu = np.clip(np.floor((u + 1) * res / 2).astype(int), 0, res - 1)
+    iv = np.clip(np.floor((v + 1) * res / 2).astype(int), 0, res - 1)
+    w = (n + 1) / (2 * math.pi) * z ** n * np.sin(T) * (math.pi / 2 / nt) * (2 * math.pi / nph)
+    m = np.zeros(res * res)
+    np.add.at(m, (iv * res + iu).ravel(), w.ravel())
+    return m
+
+
+@pytest.mark.parametrize("n", [0.0, 1.0, 4.0])
+def test_plain_cell_mass(n):
+    """The plain lobe's cell masses (midpoint rule on the hemi-octahedral
+    map, its Jacobian 1/(2|p|^3)) against an independent integration of the
+    lobe over the hemisphere in (theta, phi), each direction binned into its
+    cell: rows sum to one and 4 x 4 blocks of cells agree."""
+    from oracle import proposal as op
+    m = op.plain_cell_mass([n], sub=16)[0]
+    ref = _cell_mass_spherical(n)
+    assert abs(m.sum() - 1) < 1e-12 and abs(ref.sum() - 1) < 2e-3
+    mb = m.reshape(8, 4, 8, 4).sum((1, 3))
+    rb = ref.reshape(8, 4, 8, 4).sum((1, 3))
+    assert np.max(np.abs(mb - rb)) < 2e-3
+
+
+def test_plain_cell_mass_vs_sampled_lobe():
+    """Directions drawn from the cos^n lobe by inverting its CDF (cos theta =
+    u^(1/(n+1))) fall into the cells with the quadrature's probabilities
+    (chi-square over the cells)."""
+    from oracle import proposal as op
+    rng = np.random.default_rng(17)
+    for n in (1.0, 5.0):
+        N = 2_000_000
+        ct = rng.uniform(0, 1, N) ** (1.0 / (n + 1.0))
+        ph = rng.uniform(0, 2 * math.pi, N)
+        st = np.sqrt(1 - ct * ct)
+        x, y = st * np.cos(ph), st * np.sin(ph)
+        s = np.abs(x) + np.abs(y) + ct
+        iu = np.clip(np.floor((x / s + y / s + 1) * 16).astype(int), 0, 31)
+        iv = np.clip(np.floor((x / s - y / s + 1) * 16).astype(int), 0, 31)
+        cnt = np.bincount(iv * 32 + iu, minlength=1024)
+        e = op.plain_cell_mass([n])[0] * N
+        keep = e > 20
+        chi2 = ((cnt[keep] - e[keep]) ** 2 / e[keep]).sum()
+        dof = keep.sum() - 1
+        assert abs(chi2 - dof) < 6 * math.sqrt(2 * dof), (n, chi2, dof)
+
+
+def test_training_target():
+    """The proposal's training target: per light, the normalised square root
+    of the running average of the normalised histogram (the variance-optimal
+    cell probabilities for a second-moment histogram), an empty row counting
+    as uniform, mixed with the plain lobe's masses; a histogram equal to the
+    plain masses squared gives back the plain masses for any mixing share."""
+    from oracle import proposal as op
+    h = np.zeros((2, 4))
+    h[0] = [4.0, 0.0, 1.0, 11.0]
+    t, avg = op.training_target(h, None, 0.5)
+    r = np.sqrt(np.array([4.0, 0.0, 1.0, 11.0]) / 16)
+    assert np.allclose(t[0], r / r.sum()) and np.allclose(t[1], 0.25)
+    h2 = np.array([[0.0, 0.0, 0.0, 8.0], [1.0, 1.0, 1.0, 1.0]])
+    pm = np.array([[0.1, 0.2, 0.3, 0.4]] * 2)
+    t2, avg2 = op.training_target(h2, avg, 0.75, pm, 0.3)
+    a = 0.75 * avg + 0.25 * (h2 / h2.sum(1, keepdims=True))
+    r2 = np.sqrt(a)
+    assert np.allclose(avg2, a)
+    assert np.allclose(t2, 0.7 * r2 / r2.sum(1, keepdims=True) + 0.3 * pm)
+    assert np.allclose(t2.sum(1), 1.0)
+    pmc = op.plain_cell_mass([0.0, 3.0])
+    for floor in (0.0, 0.3, 1.0):
+        t3, _ = op.training_target(7.0 * pmc ** 2, None, 0.9, pmc, floor)
+        assert np.allclose(t3, pmc, rtol=1e-12, atol=0)
+
+
 def test_mlp_admissible_roundings():
     """The set of admissible bfloat16 roundings of the hidden activations
     (what FP32 accumulation in an unknown order may produce) always holds
