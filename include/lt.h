@@ -110,8 +110,9 @@ typedef struct {
 
 /* Launch tuning (chosen by lt_autotune or set by hand). */
 typedef struct {
-    int32_t waves_per_block;   /* 1, 2 or 4 (one wave per work tile) */
-    int32_t xcd_remap;         /* 1: blocks of one XCD take a contiguous tile range */
+    int32_t waves_per_block;   /* 1, 2 or 4 waves per workgroup of the persistent trace launch */
+    int32_t xcd_remap;         /* 1: eight work queues, one contiguous share of the tiles per XCD; a wave
+                                  drains its XCD's queue first, then helps the others */
     int32_t tile_paths;        /* paths per work tile (multiple of 64), 0 = automatic */
     int32_t refill_threshold;  /* lanes that must finish a segment before hit processing */
     int32_t lds_depth;         /* traversal stack entries kept in LDS: 16 or 32 */

@@ -36,6 +36,8 @@ struct lt_ctx {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::string err;
     int n_cu = 256;
+    int waves_per_cu = 32;           // hardware wave slots per CU
+    unsigned* d_queue = nullptr;     // work-queue ticket counters of the persistent trace kernels [8]
 
     // scene
     bool has_scene = false;
@@ -190,12 +192,10 @@ lt_tuning default_tuning()
     return t;
 }
 
-// waves of the trace launch: one per work tile, rounded up to whole blocks
-long long trace_blocks(const lt_ctx* c)
-{
-    const int w = c->tune.waves_per_block;
-    return std::max<long long>(1, (c->n_tiles + w - 1) / w);
-}
+// Waves the device can hold resident at once (every CU full): the persistent
+// trace kernels never launch more, so their traversal-stack overflow area is
+// sized by this, not by the number of work tiles.
+long long resident_waves(const lt_ctx* c) { return (long long)c->n_cu * c->waves_per_cu; }
 
 long long paths_of_light(long long ppl, int n_in_layout, int l)
 {
@@ -295,7 +295,7 @@ int check_cfg(lt_ctx* c, const lt_trace_cfg* cfg)
 
 // Launch a trace kernel; with timing on (and outside graph capture) bracket
 // it by events on the same stream.
-hipError_t timed_trace(lt_ctx* c, bool adjoint, bool capture, const TraceArgs& a, int blocks, hipStream_t st)
+hipError_t timed_trace(lt_ctx* c, bool adjoint, bool capture, const TraceArgs& a, hipStream_t st)
 {
     const bool t = c->timing && !capture;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -305,7 +305,7 @@ hipError_t timed_trace(lt_ctx* c, bool adjoint, bool capture, const TraceArgs& a
         if (e == hipSuccess) e = hipEventRecord(e0, st);
         if (e != hipSuccess) return e;
     }
-    hipError_t e = launch_trace(adjoint, false, a, c->tune.waves_per_block, c->tune.lds_depth, blocks, st);
+    hipError_t e = launch_trace(adjoint, false, a, c->tune.waves_per_block, c->tune.lds_depth, c->n_cu, st);
     if (t) {
         if (e == hipSuccess) e = hipEventRecord(e1, st);
         (adjoint ? c->t_adj : c->t_fwd).push_back({e0, e1});
@@ -332,6 +332,16 @@ TraceArgs trace_args(lt_ctx* c, const lt_trace_cfg* cfg)
     a.stats = c->d_stats;
     a.gstack = c->d_gstack;
     a.gdepth = std::max(gstack_depth(c), 1);
+    a.gstack_waves = (long long)(c->gstack_cap / ((size_t)a.gdepth * 64));
+    // work queues: one over all tiles, or with XCD remapping eight contiguous
+    // shares, one per XCD (workgroup b runs on XCD b % 8)
+    a.queue = c->d_queue;
+    a.n_queues = c->tune.xcd_remap ? 8 : 1;
+    for (int q = 0; q < 8; ++q) {
+        const long long lo = (long long)c->n_tiles * q / a.n_queues, hi = (long long)c->n_tiles * (q + 1) / a.n_queues;
+        a.q_first[q] = q < a.n_queues ? (int)lo : 0;
+        a.q_len[q] = q < a.n_queues ? (int)(hi - lo) : 0;
+    }
     a.refill_threshold = c->tune.refill_threshold;
     a.tri_share = c->tune.tri_share;
     a.linear = (cfg->flags & LT_FLAG_LINEAR) ? 1 : 0;
@@ -430,12 +440,15 @@ int lt_create(int device, void* hip_stream, lt_ctx** out)
     c->stream = (hipStream_t)hip_stream;
     c->tune = default_tuning();
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0) {
         c->n_cu = prop.multiProcessorCount;
+        if (prop.maxThreadsPerMultiProcessor >= 64) c->waves_per_cu = prop.maxThreadsPerMultiProcessor / 64;
+    }
     if (hipMalloc(&c->d_misses, sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&c->d_flags, sizeof(unsigned)) != hipSuccess ||
         hipMalloc(&c->d_stats, sizeof(unsigned long long) * 8) != hipSuccess ||
-        hipMalloc(&c->d_objpart, sizeof(double) * kObjBlocks) != hipSuccess) {
+        hipMalloc(&c->d_objpart, sizeof(double) * kObjBlocks) != hipSuccess ||
+        hipMalloc(&c->d_queue, sizeof(unsigned) * 8) != hipSuccess) {
         lt_destroy(c);
         return LT_ENOMEM;
     }
@@ -459,7 +472,7 @@ void lt_destroy(lt_ctx* c)
     hipFree(c->d_si); hipFree(c->d_sf); hipFree(c->d_lights);
     hipFree(c->prop_pdf); hipFree(c->prop_cdf); hipFree(c->prop_guide); hipFree(c->inv_sigma); hipFree(c->mlp_scratch);
     free_net(c);
-    hipFree(c->d_misses); hipFree(c->d_flags); hipFree(c->d_stats);
+    hipFree(c->d_misses); hipFree(c->d_flags); hipFree(c->d_stats); hipFree(c->d_queue);
     hipFree(c->d_objpart); hipFree(c->d_partials); hipFree(c->d_gstack); hipFree(c->d_ptgrad);
     hipFree(c->d_partials_col); hipFree(c->d_partials7); hipFree(c->d_pfd);
     hipFree(c->d_partials8); hipFree(c->d_cone);
@@ -675,8 +688,7 @@ int lt_trace_forward(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     if (((uintptr_t)d_S & 15) || ((uintptr_t)d_E & 7) || ((uintptr_t)d_params & 3))
         return fail(c, LT_EINVAL, "d_S must be 16-byte and d_E 8-byte aligned");
     HIPCHK(c, hipSetDevice(c->device));
-    const long long blocks = trace_blocks(c);
-    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    rc = ensure_gstack(c, resident_waves(c));
     if (rc) return rc;
     TraceArgs a = trace_args(c, cfg);
     a.S = (long long*)d_S;
@@ -685,7 +697,7 @@ int lt_trace_forward(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     auto body = [&](hipStream_t st) -> hipError_t {
         hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess) e = launch_clear(a.S, n, st);
-        if (e == hipSuccess) e = timed_trace(c, false, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = timed_trace(c, false, graph, a, st);
         if (e == hipSuccess) e = launch_finalize(a.S, d_E, n, c->d_flags, st);
         return e;
     };
@@ -712,8 +724,7 @@ int lt_trace_adjoint(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     if (!d_params || !d_dOdE || !d_grad) return fail(c, LT_EINVAL, "NULL device buffer");
     if (d_bin_hist && ((uintptr_t)d_bin_hist & 15)) return fail(c, LT_EINVAL, "d_bin_hist must be 16-byte aligned");
     HIPCHK(c, hipSetDevice(c->device));
-    const long long blocks = trace_blocks(c);
-    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    rc = ensure_gstack(c, resident_waves(c));
     if (rc) return rc;
     TraceArgs a = trace_args(c, cfg);
     a.g = d_dOdE;
@@ -723,7 +734,7 @@ int lt_trace_adjoint(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     auto body = [&](hipStream_t st) -> hipError_t {
         hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess && d_bin_hist) e = launch_fill_f32(d_bin_hist, (long long)c->L * 1024, 0.0f, st);
-        if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = timed_trace(c, true, graph, a, st);
         if (e == hipSuccess) e = launch_grad_reduce(c->d_partials, c->d_range, c->L, d_grad, st);
         return e;
     };
@@ -740,8 +751,7 @@ int lt_gradient_votes(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params,
     if (light < 0 || light >= c->L) return fail(c, LT_EINVAL, "light out of range");
     if (param < 0 || param > 5) return fail(c, LT_EINVAL, "parameter out of range");
     HIPCHK(c, hipSetDevice(c->device));
-    const long long blocks = trace_blocks(c);
-    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    rc = ensure_gstack(c, resident_waves(c));
     if (rc) return rc;
     TraceArgs a = trace_args(c, cfg);
     a.g = d_dOdE;
@@ -753,7 +763,7 @@ int lt_gradient_votes(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params,
     auto body = [&](hipStream_t st) -> hipError_t {
         hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess) e = launch_clear((long long*)d_vote, c->K, st);
-        if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = timed_trace(c, true, graph, a, st);
         if (e == hipSuccess) e = launch_grad_reduce(c->d_partials, c->d_range, c->L, d_grad, st);
         return e;
     };
@@ -791,8 +801,7 @@ int lt_trace_forward_rgb(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_para
     if (((uintptr_t)d_S & 15) || ((uintptr_t)d_E & 7) || ((uintptr_t)d_params & 3) || ((uintptr_t)d_colour & 3))
         return fail(c, LT_EINVAL, "d_S must be 16-byte and d_E 8-byte aligned");
     HIPCHK(c, hipSetDevice(c->device));
-    const long long blocks = trace_blocks(c);
-    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    rc = ensure_gstack(c, resident_waves(c));
     if (rc) return rc;
     TraceArgs a = trace_args(c, cfg);
     a.S = (long long*)d_S;
@@ -804,7 +813,7 @@ int lt_trace_forward_rgb(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_para
     auto body = [&](hipStream_t st) -> hipError_t {
         hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess) e = launch_clear(a.S, n, st);
-        if (e == hipSuccess) e = timed_trace(c, false, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = timed_trace(c, false, graph, a, st);
         if (e == hipSuccess) e = launch_finalize(a.S, d_E, n, c->d_flags, st);
         return e;
     };
@@ -821,8 +830,7 @@ int lt_trace_adjoint_rgb(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_para
     if (cfg->flags & LT_FLAG_LINEAR) return fail(c, LT_EINVAL, "colour mode takes the box basis only");
     if (d_bin_hist && ((uintptr_t)d_bin_hist & 15)) return fail(c, LT_EINVAL, "d_bin_hist must be 16-byte aligned");
     HIPCHK(c, hipSetDevice(c->device));
-    const long long blocks = trace_blocks(c);
-    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    rc = ensure_gstack(c, resident_waves(c));
     if (rc) return rc;
     const size_t need = (size_t)std::max(c->n_tiles, 1) * 3;
     if (c->partials_col_cap < need) {
@@ -846,7 +854,7 @@ int lt_trace_adjoint_rgb(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_para
     auto body = [&](hipStream_t st) -> hipError_t {
         hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess && d_bin_hist) e = launch_fill_f32(d_bin_hist, (long long)c->L * 1024, 0.0f, st);
-        if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = timed_trace(c, true, graph, a, st);
         if (e == hipSuccess) e = launch_grad_reduce(c->d_partials, c->d_range, c->L, d_grad, st);
         if (e == hipSuccess) e = launch_grad_reduce_col(c->d_partials_col, c->d_range, c->L, d_grad_colour, st);
         return e;
@@ -867,8 +875,7 @@ int lt_trace_tangent(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     if (param < 0 || param > 5) return fail(c, LT_EINVAL, "parameter out of range");
     if (((uintptr_t)d_T & 15) || ((uintptr_t)d_D & 7)) return fail(c, LT_EINVAL, "d_T must be 16-byte and d_D 8-byte aligned");
     HIPCHK(c, hipSetDevice(c->device));
-    const long long blocks = trace_blocks(c);
-    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    rc = ensure_gstack(c, resident_waves(c));
     if (rc) return rc;
     TraceArgs a = trace_args(c, cfg);
     a.tangent = (long long*)d_T;
@@ -878,7 +885,7 @@ int lt_trace_tangent(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     auto body = [&](hipStream_t st) -> hipError_t {
         hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess) e = launch_clear(a.tangent, c->K, st);
-        if (e == hipSuccess) e = timed_trace(c, false, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = timed_trace(c, false, graph, a, st);
         if (e == hipSuccess) e = launch_finalize(a.tangent, d_D, c->K, c->d_flags, st);
         return e;
     };
@@ -900,8 +907,7 @@ int lt_fd_map(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int32_t
     if (((uintptr_t)d_Sp & 15) || ((uintptr_t)d_Sm & 15) || ((uintptr_t)d_params & 3))
         return fail(c, LT_EINVAL, "d_Sp and d_Sm must be 16-byte aligned");
     HIPCHK(c, hipSetDevice(c->device));
-    const long long blocks = trace_blocks(c);
-    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    rc = ensure_gstack(c, resident_waves(c));
     if (rc) return rc;
     if (c->pfd_cap < c->L) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -927,10 +933,10 @@ int lt_fd_map(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, int32_t
         hipError_t e = launch_fd_params(d_params, 6 * c->L, 6 * light + param, h, pp, pm, den, st);
         if (e == hipSuccess) e = launch_light_setup(pp, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess) e = launch_clear(ap.S, n, st);
-        if (e == hipSuccess) e = timed_trace(c, false, graph, ap, (int)blocks, st);
+        if (e == hipSuccess) e = timed_trace(c, false, graph, ap, st);
         if (e == hipSuccess) e = launch_light_setup(pm, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess) e = launch_clear(am.S, n, st);
-        if (e == hipSuccess) e = timed_trace(c, false, graph, am, (int)blocks, st);
+        if (e == hipSuccess) e = timed_trace(c, false, graph, am, st);
         if (e == hipSuccess) e = launch_fd_diff(ap.S + row, am.S + row, c->K, den, d_F, st);
         return e;
     };
@@ -950,8 +956,7 @@ int lt_trace_forward_rv(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_param
     if (((uintptr_t)d_S & 15) || ((uintptr_t)d_E & 7) || ((uintptr_t)d_params & 3))
         return fail(c, LT_EINVAL, "d_S must be 16-byte and d_E 8-byte aligned");
     HIPCHK(c, hipSetDevice(c->device));
-    const long long blocks = trace_blocks(c);
-    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    rc = ensure_gstack(c, resident_waves(c));
     if (rc) return rc;
     TraceArgs a = trace_args(c, cfg);
     a.S = (long long*)d_S;
@@ -960,7 +965,7 @@ int lt_trace_forward_rv(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_param
     auto body = [&](hipStream_t st) -> hipError_t {
         hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st, 1);
         if (e == hipSuccess) e = launch_clear(a.S, n, st);
-        if (e == hipSuccess) e = timed_trace(c, false, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = timed_trace(c, false, graph, a, st);
         if (e == hipSuccess) e = launch_finalize(a.S, d_E, n, c->d_flags, st);
         return e;
     };
@@ -975,8 +980,7 @@ int lt_trace_adjoint_rv(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_param
     if (cfg->flags & (LT_FLAG_PROPOSAL | LT_FLAG_LINEAR))
         return fail(c, LT_EINVAL, "rotation vectors take the plain emission and the box basis only");
     HIPCHK(c, hipSetDevice(c->device));
-    const long long blocks = trace_blocks(c);
-    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    rc = ensure_gstack(c, resident_waves(c));
     if (rc) return rc;
     const size_t need = (size_t)std::max(c->n_tiles, 1) * 7;
     if (c->partials7_cap < need) {
@@ -995,7 +999,7 @@ int lt_trace_adjoint_rv(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_param
     const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
     auto body = [&](hipStream_t st) -> hipError_t {
         hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st, 1);
-        if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = timed_trace(c, true, graph, a, st);
         if (e == hipSuccess) e = launch_grad_reduce_rv(c->d_partials7, c->d_range, d_params, c->L, d_grad, st);
         return e;
     };
@@ -1011,8 +1015,7 @@ int lt_trace_adjoint_cone(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_par
     if (cfg->flags & (LT_FLAG_PROPOSAL | LT_FLAG_LINEAR))
         return fail(c, LT_EINVAL, "cone-angle gradients take the plain emission and the box basis only");
     HIPCHK(c, hipSetDevice(c->device));
-    const long long blocks = trace_blocks(c);
-    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    rc = ensure_gstack(c, resident_waves(c));
     if (rc) return rc;
     const size_t need = (size_t)std::max(c->n_tiles, 1) * 8;
     if (c->partials8_cap < need || c->cone_cap < c->L) {
@@ -1041,7 +1044,7 @@ int lt_trace_adjoint_cone(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_par
     auto body = [&](hipStream_t st) -> hipError_t {
         hipError_t e =
             launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st, 0, c->d_cone);
-        if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = timed_trace(c, true, graph, a, st);
         if (e == hipSuccess)
             e = launch_grad_reduce_cone(c->d_partials8, c->d_range, c->L, d_grad, d_grad_cone, st);
         return e;
@@ -1091,8 +1094,7 @@ int lt_trace_forward_dir(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_para
     if (((uintptr_t)d_S & 15) || ((uintptr_t)d_E & 7) || ((uintptr_t)d_params & 3))
         return fail(c, LT_EINVAL, "d_S must be 16-byte and d_E 8-byte aligned");
     HIPCHK(c, hipSetDevice(c->device));
-    const long long blocks = trace_blocks(c);
-    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    rc = ensure_gstack(c, resident_waves(c));
     if (rc) return rc;
     TraceArgs a = trace_args(c, cfg);
     a.S = (long long*)d_S;
@@ -1104,7 +1106,7 @@ int lt_trace_forward_dir(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_para
     auto body = [&](hipStream_t st) -> hipError_t {
         hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess) e = launch_clear(a.S, n, st);
-        if (e == hipSuccess) e = timed_trace(c, false, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = timed_trace(c, false, graph, a, st);
         if (e == hipSuccess) e = launch_finalize(a.S, d_E, n, c->d_flags, st);
         return e;
     };
@@ -1120,8 +1122,7 @@ int lt_trace_adjoint_dir(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_para
     if (!d_params || !d_dOdE || !d_grad) return fail(c, LT_EINVAL, "NULL device buffer");
     if (d_bin_hist && ((uintptr_t)d_bin_hist & 15)) return fail(c, LT_EINVAL, "d_bin_hist must be 16-byte aligned");
     HIPCHK(c, hipSetDevice(c->device));
-    const long long blocks = trace_blocks(c);
-    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    rc = ensure_gstack(c, resident_waves(c));
     if (rc) return rc;
     TraceArgs a = trace_args(c, cfg);
     a.g = d_dOdE;
@@ -1134,7 +1135,7 @@ int lt_trace_adjoint_dir(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_para
     auto body = [&](hipStream_t st) -> hipError_t {
         hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess && d_bin_hist) e = launch_fill_f32(d_bin_hist, (long long)c->L * 1024, 0.0f, st);
-        if (e == hipSuccess) e = timed_trace(c, true, graph, a, (int)blocks, st);
+        if (e == hipSuccess) e = timed_trace(c, true, graph, a, st);
         if (e == hipSuccess) e = launch_grad_reduce(c->d_partials, c->d_range, c->L, d_grad, st);
         return e;
     };
@@ -1297,15 +1298,14 @@ int lt_trace_stats(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, in
     if (!d_params || !d_S || !h_counts) return fail(c, LT_EINVAL, "NULL buffer");
     if ((uintptr_t)d_S & 15) return fail(c, LT_EINVAL, "d_S must be 16-byte aligned");
     HIPCHK(c, hipSetDevice(c->device));
-    const long long blocks = trace_blocks(c);
-    rc = ensure_gstack(c, blocks * c->tune.waves_per_block);
+    rc = ensure_gstack(c, resident_waves(c));
     if (rc) return rc;
     TraceArgs a = trace_args(c, cfg);
     a.S = (long long*)d_S;
     HIPCHK(c, hipMemsetAsync(c->d_stats, 0, sizeof(unsigned long long) * 8, c->stream));
     HIPCHK(c, launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, c->stream));
     HIPCHK(c, launch_clear(a.S, c->K * c->n_layouts, c->stream));
-    HIPCHK(c, launch_trace(false, true, a, c->tune.waves_per_block, c->tune.lds_depth, (int)blocks, c->stream));
+    HIPCHK(c, launch_trace(false, true, a, c->tune.waves_per_block, c->tune.lds_depth, c->n_cu, c->stream));
     unsigned long long h[8];
     HIPCHK(c, hipMemcpyAsync(h, c->d_stats, sizeof(h), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));

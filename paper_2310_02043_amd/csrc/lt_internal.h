@@ -38,7 +38,13 @@ struct TraceArgs {
     const int4* tiles;          // (global light, first path, count, layout)
     int n_tiles;
     int max_hits;
-    int xcd_remap;              // map blocks of one XCD to a contiguous tile range
+    // work queues: queue q hands out tiles q_first[q] .. q_first[q] + q_len[q] - 1
+    // through the ticket counter queue[q] (zeroed before every launch); one
+    // queue, or eight contiguous shares (one per XCD) with XCD remapping
+    unsigned* queue;
+    int n_queues;
+    int q_first[8], q_len[8];
+    int xcd_remap;
     uint32_t key0, key1;
     long long* S;               // forward: [n_layouts, K]
     const float* g;             // adjoint: [n_layouts, K]
@@ -46,8 +52,9 @@ struct TraceArgs {
     double* partials;           // adjoint: [n_tiles, 6]
     unsigned long long* misses;
     unsigned long long* stats;  // instrumented kernel: 5 counters
-    int* gstack;                // traversal stack overflow, [waves][gdepth][64]
+    int* gstack;                // traversal stack overflow, [gstack_waves][gdepth][64]
     int gdepth;
+    long long gstack_waves;     // persistent wave slots the overflow area covers
     int refill_threshold;
     int linear;                 // piecewise-linear texel basis (else box)
     int tri_share;              // eighths of the traversing lanes that select a triangle-test iteration
@@ -137,8 +144,10 @@ struct RecordArgs {
 hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_patch, int n, float pad,
                      hipStream_t st, float4** nodes_out, float4** tris_out, int* n_nodes_out, int* depth_out);
 
-hipError_t launch_trace(bool adjoint, bool stats, const TraceArgs& a, int waves_per_block, int lds_depth,
-                        int blocks, hipStream_t st);
+// persistent launch: min(tiles, resident waves of the instance on n_cu CUs)
+// waves, never more than a.gstack_waves; zeroes the queue counters first
+hipError_t launch_trace(bool adjoint, bool stats, const TraceArgs& a, int waves_per_block, int lds_depth, int n_cu,
+                        hipStream_t st);
 hipError_t launch_record(const RecordArgs& a, int lds_depth, hipStream_t st);
 hipError_t launch_light_setup(const float* params, const int4* lstat_i, const float4* lstat_f,
                               const long long* npaths, int n_lights, DevLight* out, unsigned* flags,

@@ -12,6 +12,9 @@
 // both passes are deterministic.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
+
 #include "lt_device.h"
 #include "lt_internal.h"
 
@@ -581,20 +584,14 @@ __device__ __forceinline__ T wave_sum(T v)
 }
 
 // ---------------------------------------------------------------------------
-// The forward / adjoint kernel: one wave per work tile, all tiles of all
-// layouts in one launch.  The hardware dispatcher drains the tile grid; no
-// loop carries lane-divergent code across its back edge, so every wave-wide
-// operation (ballot, shuffle) runs on a converged wave.
+// The forward / adjoint kernel: one persistent launch over the work tiles of
+// every layout.  The grid holds as many waves as the chip keeps resident;
+// each wave takes one tile at a time from a work queue (an atomic ticket per
+// tile) until the queue is drained, so the traversal-stack overflow area is
+// sized by resident waves, not by tiles.  No loop carries lane-divergent
+// code across its back edge, so every wave-wide operation (ballot, shuffle)
+// runs on a converged wave.
 // ---------------------------------------------------------------------------
-
-// Block b of nb runs on XCD b % 8; give each XCD a contiguous range of tiles
-// (a bijection of [0, nb)) so rays of one luminaire share an L2.
-__device__ __forceinline__ long long xcd_block(long long b, long long nb, int remap)
-{
-    if (!remap) return b;
-    const long long x = b & 7, i = b >> 3, q = nb >> 3, r = nb & 7;
-    return x * q + (x < r ? x : r) + i;
-}
 
 // Both variants fit 96 VGPRs (five waves per SIMD); the adjoint keeps its
 // per-path first-hit derivative factors and running sums in LDS.  MODE
@@ -631,15 +628,27 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(M
     int* k1 = s_k1 + (ADJ ? wib * 64 + lane : 0);
     float* rgbs = s_rgb + (MODE == 2 ? wib * 8 * 64 + lane : 0);
     float* dst = s_dir + (DIR ? wib * DIRW * 64 + lane : 0);
-    const long long blk = xcd_block(blockIdx.x, gridDim.x, a.xcd_remap);
-    const long long gw = blk * WPB + wib;
-    if (gw >= a.n_tiles) return;
+    // persistent wave: its slot owns one traversal-stack overflow area, and
+    // it takes work tiles from the queue(s) until they are drained
+    const long long gw = (long long)blockIdx.x * WPB + wib;
+    if (gw >= a.gstack_waves) return;
     int* lst = s_stack + wib * LDS_D * 64 + lane;
     int* gst = a.gstack + gw * (long long)a.gdepth * 64 + lane;
     const int B = a.max_hits;
     const int thresh = a.refill_threshold;
-    const int tile = (int)gw;
-    if (MODE == 5 && a.tiles[tile].x != a.tan_light) return;   // other luminaires add nothing
+    // with XCD-aware queues, workgroup b runs on XCD b % 8 and starts on that
+    // XCD's contiguous share of the tiles, then helps with the others
+    const int nq = a.n_queues;
+    const int q0 = nq > 1 ? (int)(blockIdx.x % (unsigned)nq) : 0;
+    for (int qi = 0; qi < nq; ++qi) {
+    const int q = (q0 + qi) % nq;
+    for (;;) {
+    int ticket = 0;
+    if (lane == 0) ticket = (int)atomicAdd(a.queue + q, 1u);
+    ticket = __builtin_amdgcn_readfirstlane(ticket);
+    if (ticket >= a.q_len[q]) break;
+    const int tile = a.q_first[q] + ticket;
+    if (MODE == 5 && a.tiles[tile].x != a.tan_light) continue;   // other luminaires add nothing
     {
         const int4 ti = a.tiles[tile];
         const DevLight& L = a.lights[ti.x];
@@ -1031,6 +1040,8 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(M
             }
         }
     }
+    }   // tiles of queue q
+    }   // queues
 }
 
 // One path per thread (grid-stride): hit sequences and per-path adjoint
@@ -1575,80 +1586,109 @@ inline int nblocks(long long n, int b, int cap)
     return (int)x;
 }
 
+// Persistent grid of one trace-kernel instance: as many waves as stay
+// resident on n_cu CUs (its occupancy, queried once), no more than there are
+// tiles or overflow-stack slots.
+template <bool ADJ, bool STATS, int WPB, int LDS_D, int MODE>
+void launch_persistent(const TraceArgs& a, int n_cu, hipStream_t st)
+{
+    static int per_cu = -1;
+    if (per_cu < 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_trace<ADJ, STATS, WPB, LDS_D, MODE>, WPB * 64, 0) !=
+                hipSuccess || nb < 1)
+            nb = 1;
+        per_cu = nb;
+    }
+    long long blocks = ((long long)a.n_tiles + WPB - 1) / WPB;
+    blocks = std::min<long long>(blocks, (long long)n_cu * per_cu);
+    blocks = std::min<long long>(blocks, a.gstack_waves / WPB);
+    if (blocks < 1) blocks = 1;
+    k_trace<ADJ, STATS, WPB, LDS_D, MODE><<<(unsigned)blocks, WPB * 64, 0, st>>>(a);
+}
+
+__global__ void k_queue_reset(unsigned* __restrict__ q)
+{
+    if (threadIdx.x < 8) q[threadIdx.x] = 0u;
+}
+
 template <bool ADJ, int WPB, int MODE>
-void launch_dir(const TraceArgs& a, int lds_depth, int blocks, hipStream_t st)
+void launch_dir(const TraceArgs& a, int lds_depth, int n_cu, hipStream_t st)
 {
     if (lds_depth == 16)
-        k_trace<ADJ, false, WPB, 16, MODE><<<blocks, WPB * 64, 0, st>>>(a);
+        launch_persistent<ADJ, false, WPB, 16, MODE>(a, n_cu, st);
     else
-        k_trace<ADJ, false, WPB, 32, MODE><<<blocks, WPB * 64, 0, st>>>(a);
+        launch_persistent<ADJ, false, WPB, 32, MODE>(a, n_cu, st);
 }
 
 template <bool ADJ, bool STATS, int WPB>
-hipError_t launch_wpb(const TraceArgs& a, int lds_depth, int blocks, hipStream_t st)
+hipError_t launch_wpb(const TraceArgs& a, int lds_depth, int n_cu, hipStream_t st)
 {
     if (a.tangent != nullptr && !ADJ && !STATS) {
         if (lds_depth == 16)
-            k_trace<ADJ, STATS, WPB, 16, 5><<<blocks, WPB * 64, 0, st>>>(a);
+            launch_persistent<ADJ, STATS, WPB, 16, 5>(a, n_cu, st);
         else
-            k_trace<ADJ, STATS, WPB, 32, 5><<<blocks, WPB * 64, 0, st>>>(a);
+            launch_persistent<ADJ, STATS, WPB, 32, 5>(a, n_cu, st);
     } else if (a.cone != nullptr && ADJ && !STATS) {
         if (lds_depth == 16)
-            k_trace<ADJ, STATS, WPB, 16, 6><<<blocks, WPB * 64, 0, st>>>(a);
+            launch_persistent<ADJ, STATS, WPB, 16, 6>(a, n_cu, st);
         else
-            k_trace<ADJ, STATS, WPB, 32, 6><<<blocks, WPB * 64, 0, st>>>(a);
+            launch_persistent<ADJ, STATS, WPB, 32, 6>(a, n_cu, st);
     } else if (a.rotvec && ADJ) {
         if (lds_depth == 16)
-            k_trace<ADJ, STATS, WPB, 16, 4><<<blocks, WPB * 64, 0, st>>>(a);
+            launch_persistent<ADJ, STATS, WPB, 16, 4>(a, n_cu, st);
         else
-            k_trace<ADJ, STATS, WPB, 32, 4><<<blocks, WPB * 64, 0, st>>>(a);
+            launch_persistent<ADJ, STATS, WPB, 32, 4>(a, n_cu, st);
     } else if (a.dir_order >= 0 && !STATS) {
         if constexpr (!STATS) {
             // the harmonic order as a compile-time constant: MODE 30 + order
             switch (a.dir_order) {
-                case 0: launch_dir<ADJ, WPB, 30>(a, lds_depth, blocks, st); break;
-                case 1: launch_dir<ADJ, WPB, 31>(a, lds_depth, blocks, st); break;
-                case 2: launch_dir<ADJ, WPB, 32>(a, lds_depth, blocks, st); break;
-                default: launch_dir<ADJ, WPB, 33>(a, lds_depth, blocks, st); break;
+                case 0: launch_dir<ADJ, WPB, 30>(a, lds_depth, n_cu, st); break;
+                case 1: launch_dir<ADJ, WPB, 31>(a, lds_depth, n_cu, st); break;
+                case 2: launch_dir<ADJ, WPB, 32>(a, lds_depth, n_cu, st); break;
+                default: launch_dir<ADJ, WPB, 33>(a, lds_depth, n_cu, st); break;
             }
         }
     } else if (a.rgb && !STATS) {
         if (lds_depth == 16)
-            k_trace<ADJ, STATS, WPB, 16, 2><<<blocks, WPB * 64, 0, st>>>(a);
+            launch_persistent<ADJ, STATS, WPB, 16, 2>(a, n_cu, st);
         else
-            k_trace<ADJ, STATS, WPB, 32, 2><<<blocks, WPB * 64, 0, st>>>(a);
+            launch_persistent<ADJ, STATS, WPB, 32, 2>(a, n_cu, st);
     } else if (a.linear && !STATS) {
         if (lds_depth == 16)
-            k_trace<ADJ, STATS, WPB, 16, 1><<<blocks, WPB * 64, 0, st>>>(a);
+            launch_persistent<ADJ, STATS, WPB, 16, 1>(a, n_cu, st);
         else
-            k_trace<ADJ, STATS, WPB, 32, 1><<<blocks, WPB * 64, 0, st>>>(a);
+            launch_persistent<ADJ, STATS, WPB, 32, 1>(a, n_cu, st);
     } else {
         if (lds_depth == 16)
-            k_trace<ADJ, STATS, WPB, 16, 0><<<blocks, WPB * 64, 0, st>>>(a);
+            launch_persistent<ADJ, STATS, WPB, 16, 0>(a, n_cu, st);
         else
-            k_trace<ADJ, STATS, WPB, 32, 0><<<blocks, WPB * 64, 0, st>>>(a);
+            launch_persistent<ADJ, STATS, WPB, 32, 0>(a, n_cu, st);
     }
     return hipGetLastError();
 }
 
 template <bool ADJ, bool STATS>
-hipError_t launch_t(const TraceArgs& a, int wpb, int lds_depth, int blocks, hipStream_t st)
+hipError_t launch_t(const TraceArgs& a, int wpb, int lds_depth, int n_cu, hipStream_t st)
 {
     switch (wpb) {
-        case 1: return launch_wpb<ADJ, STATS, 1>(a, lds_depth, blocks, st);
-        case 2: return launch_wpb<ADJ, STATS, 2>(a, lds_depth, blocks, st);
-        default: return launch_wpb<ADJ, STATS, 4>(a, lds_depth, blocks, st);
+        case 1: return launch_wpb<ADJ, STATS, 1>(a, lds_depth, n_cu, st);
+        case 2: return launch_wpb<ADJ, STATS, 2>(a, lds_depth, n_cu, st);
+        default: return launch_wpb<ADJ, STATS, 4>(a, lds_depth, n_cu, st);
     }
 }
 
 }  // namespace
 
-hipError_t launch_trace(bool adjoint, bool stats, const TraceArgs& a, int waves_per_block, int lds_depth,
-                        int blocks, hipStream_t st)
+hipError_t launch_trace(bool adjoint, bool stats, const TraceArgs& a, int waves_per_block, int lds_depth, int n_cu,
+                        hipStream_t st)
 {
-    if (adjoint) return launch_t<true, false>(a, waves_per_block, lds_depth, blocks, st);
-    if (stats) return launch_t<false, true>(a, waves_per_block, lds_depth, blocks, st);
-    return launch_t<false, false>(a, waves_per_block, lds_depth, blocks, st);
+    k_queue_reset<<<1, 64, 0, st>>>(a.queue);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (adjoint) return launch_t<true, false>(a, waves_per_block, lds_depth, n_cu, st);
+    if (stats) return launch_t<false, true>(a, waves_per_block, lds_depth, n_cu, st);
+    return launch_t<false, false>(a, waves_per_block, lds_depth, n_cu, st);
 }
 
 hipError_t launch_pt(bool adjoint, const PtArgs& a, int lds_depth, hipStream_t st)

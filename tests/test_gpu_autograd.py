@@ -87,7 +87,8 @@ def test_autograd_matches_oracle(torch_dev, oracle_lib, case, correlated):
     assert np.array_equal(E_gpu, E_ref)
     O_ref, g_ref = oracle_lib.objective(E_ref, Et, sc.texel_area())
     say(f"  O {O.item():.9g} vs oracle {O_ref:.9g}")
-    assert abs(O.item() - O_ref) <= 1e-9 * abs(O_ref)
+    # the torch objective forms A (E - E*)^2 in FP32 before its FP64 sum
+    assert abs(O.item() - O_ref) <= 1e-6 * abs(O_ref)
     aseed = seed if correlated else seed ^ DECORRELATE
     grad_ref, _ = oracle_lib.adjoint(osc, ol, lights.params, aseed, ppl, B, g_ref)
     G = p.grad.detach().cpu().numpy().astype(np.float64)
