@@ -640,12 +640,20 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(M
     // XCD's contiguous share of the tiles, then helps with the others
     const int nq = a.n_queues;
     const int q0 = nq > 1 ? (int)(blockIdx.x % (unsigned)nq) : 0;
+    int taken = 0;   // tiles this wave took: never more than exist, so the loop always ends
     for (int qi = 0; qi < nq; ++qi) {
     const int q = (q0 + qi) % nq;
     for (;;) {
-    int ticket = 0;
-    if (lane == 0) ticket = (int)atomicAdd(a.queue + q, 1u);
-    ticket = __builtin_amdgcn_readfirstlane(ticket);
+    if (++taken > a.n_tiles) {
+        if (lane == 0) atomicOr(a.flags, kStatusTraversal);
+        break;
+    }
+    // one ticket per wave: every lane takes part in the atomic (lane 0 adds
+    // 1, the others 0), so no lane-divergent branch precedes the read of
+    // lane 0's result; a branch there lets the compiler thread the other
+    // lanes' path into the loop and read the ticket under a partial mask
+    const unsigned old_q = atomicAdd(a.queue + q, lane == 0 ? 1u : 0u);
+    const int ticket = __builtin_amdgcn_readfirstlane((int)old_q);
     if (ticket >= a.q_len[q]) break;
     const int tile = a.q_first[q] + ticket;
     if (MODE == 5 && a.tiles[tile].x != a.tan_light) continue;   // other luminaires add nothing

@@ -504,3 +504,42 @@ def test_invalid_luminaire_parameters_flagged(torch_dev, oracle_lib, bad):
     # valid parameters again: no status
     ctx.trace_forward(torch.tensor(params, device="cuda"), cfg)
     assert ctx.sync() == 0
+
+
+@pytest.mark.parametrize("case", ["box_room", "plane_two_lights"])
+def test_trace_stats_counts(torch_dev, oracle_lib, case):
+    """The instrumented forward kernel (lt_trace_stats, the algorithmic work
+    counts the roofline uses) computes the same texels as the oracle and
+    counts exactly the oracle's hits and misses (segments = hits + misses),
+    with node visits and triangle tests recorded."""
+    torch = torch_dev
+    if case == "box_room":
+        c1 = li.box_room()
+        sc, lights, ppl, B = c1["scene"], c1["lights"], 1 << 16, c1["max_hits"]
+    else:
+        sc = li.plane_scene(half=2.0, res=16)
+        lights = make_lights([SPOT, POINT], [2.0, 0.0], [(0, 0), (0, 0)], [0, 0],
+                             [[0.2, -0.1, 1.5, 0.2, 0.1, 20.0], [-0.5, 0.4, 1.0, 0, 0, 10.0]])
+        ppl, B = 20_011, 2
+    say(f"trace stats: {case}, {ppl} paths, {B} hits")
+    ctx = make_ctx(torch, sc, lights)
+    p_d = torch.tensor(lights.params, device="cuda")
+    seed = 0x57A7
+    cfg = ctx.cfg(seed, ppl, B)
+    S = torch.empty((1, sc.n_texels), dtype=torch.int64, device="cuda")
+    st = ctx.trace_stats(p_d, cfg, S)
+    assert ctx.sync() == 0
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    S_ref, miss_ref = oracle_lib.forward(osc, ol, lights.params, seed, ppl, B)
+    assert np.array_equal(S.cpu().numpy(), S_ref)
+    hits = 0
+    off = lights.layout_offsets
+    for l in range(lights.n_lights):
+        n_l = ppl // (off[1] - off[0]) + (l < ppl % (off[1] - off[0]))
+        prim, _, _ = oracle_lib.record(osc, ol, lights.params, seed, ppl, B, 0, l, 0, n_l)
+        hits += int((prim >= 0).sum())
+    say(f"  {st}; oracle hits {hits}, misses {int(miss_ref)}")
+    assert st["hits"] == hits and st["misses"] == int(miss_ref)
+    assert st["segments"] == hits + int(miss_ref)
+    assert st["nodes"] > 0 and st["tri_tests"] >= hits and st["wave_iters"] > 0
+    assert 0 < st["active_lanes"] <= 64 * st["wave_iters"]
