@@ -187,6 +187,25 @@ int lt_objective(lt_ctx* ctx, const float* d_E, const float* d_Etarget, const fl
 int lt_trace_adjoint(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, const float* d_dOdE,
                      float* d_grad, float* d_bin_hist);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * adjoint pass of lt_trace_adjoint (same arguments without d_bin_hist, same
+ * kernels and the same d_grad [L,6] f32 result, bit for bit) with every
+ * buffer it needs beyond the inputs and outputs -- work-queue counters, the
+ * work-tile table (built on the device), per-light ranges and path counts,
+ * per-tile partial sums, the traversal-stack overflow area -- carved from
+ * one fixed 64 MiB device array that the library holds per device until the
+ * process ends.  Makes no allocation call.  LT_EINVAL when the work does not
+ * fit that array (n_tiles * 64 B + L * 16 B plus the overflow area of at
+ * least 64 waves; tiles of tile_paths paths), for LT_FLAG_GRAPH, and as
+ * lt_trace_adjoint otherwise.  All calls on one device share the array,
+ * which keeps the last call's contents (every region is rewritten before it
+ * is read): calls that overlap in time on one device, from any context or
+ * stream, race and must be serialised by the caller.  The context must have
+ * a scene and luminaires (their set-up calls allocate, this one does not). */
+int lt_trace_adjoint_noalloc(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, const float* d_dOdE,
+                             float* d_grad);
+
 /* Gradient-contribution map (Sec. gradVis): the adjoint pass of
  * lt_trace_adjoint (same arguments, same d_grad [L,6] f32 output), which also
  * adds each path's contribution to dO/dp_j, j = `param` in 0..5 (x, y, z,

@@ -11,6 +11,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,7 +21,33 @@
 
 using namespace lt;
 
+// Scratch of lt_trace_adjoint_noalloc: queue counters, work tiles, per-light
+// ranges and path counts, per-tile partial sums and the traversal-stack
+// overflow area, carved from one fixed device array so that the call needs no
+// allocation.  Each device holds its own copy until the process ends; host
+// code uses only the per-device address taken at lt_create, never the
+// symbol itself.
+constexpr size_t kNoAllocBytes = 64ull << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the scratch array on `device` (current device), taken
+// once per device; nullptr on failure.
+void* scratch_address(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) g_scratch_ptr[device] = p;
+    }
+    return g_scratch_ptr[device];
+}
 
 struct GraphEntry {
     std::vector<uint64_t> key;
@@ -37,6 +64,7 @@ struct lt_ctx {
     std::string err;
     int n_cu = 256;
     int waves_per_cu = 32;           // hardware wave slots per CU
+    unsigned char* noalloc = nullptr;  // this device's scratch array (lt_trace_adjoint_noalloc)
     unsigned* d_queue = nullptr;     // work-queue ticket counters of the persistent trace kernels [8]
 
     // scene
@@ -455,6 +483,7 @@ int lt_create(int device, void* hip_stream, lt_ctx** out)
     hipMemset(c->d_misses, 0, sizeof(unsigned long long));
     hipMemset(c->d_flags, 0, sizeof(unsigned));
     hipMemset(c->d_stats, 0, sizeof(unsigned long long) * 8);
+    c->noalloc = (unsigned char*)scratch_address(device);
     hipDeviceSynchronize();
     *out = c;
     return LT_OK;
@@ -644,7 +673,7 @@ int lt_set_lights(lt_ctx* c, const lt_light_static* h_lights, int32_t n_lights, 
                 return fail(c, LT_EINVAL, "soft-edged spot needs 0 <= inner < outer <= pi/2");
             if (s.type == 2 && !(s.size_w > 0.0f && s.size_h > 0.0f && isfinite(s.size_w) && isfinite(s.size_h)))
                 return fail(c, LT_EINVAL, "invalid rectangle size");
-            si[l] = make_int4(s.type, j, l - h_offs[j], 0);
+            si[l] = make_int4(s.type, j, l - h_offs[j], h_offs[j + 1] - h_offs[j]);
             sf[l] = make_float4(s.lobe_n, s.size_w, s.size_h, 0.f);
         }
     HIPCHK(c, hipSetDevice(c->device));
@@ -739,6 +768,87 @@ int lt_trace_adjoint(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
         return e;
     };
     return run_seq(c, graph, make_key(c, 2, cfg, {d_params, d_dOdE, d_grad, d_bin_hist}), body);
+}
+
+int lt_trace_adjoint_noalloc(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, const float* d_dOdE,
+                             float* d_grad)
+{
+    if (!c) return LT_EINVAL;
+    if (!cfg) return fail(c, LT_EINVAL, "cfg is NULL");
+    if (!c->has_scene) return fail(c, LT_ESTATE, "no scene uploaded");
+    if (!c->has_lights) return fail(c, LT_ESTATE, "no luminaires set");
+    if (!d_params || !d_dOdE || !d_grad) return fail(c, LT_EINVAL, "NULL device buffer");
+    if (cfg->max_hits < 1 || cfg->max_hits > 64) return fail(c, LT_EINVAL, "max_hits must be in [1, 64]");
+    if (cfg->flags & ~(LT_FLAG_PROPOSAL | LT_FLAG_LINEAR))
+        return fail(c, LT_EINVAL, "unknown flag (graph replay allocates; it is not available here)");
+    if (cfg->flags & LT_FLAG_PROPOSAL) {
+        if (!c->has_proposal) return fail(c, LT_EINVAL, "no emission proposal loaded");
+        if (!(cfg->alpha_plain > 0.0f && cfg->alpha_plain <= 1.0f))
+            return fail(c, LT_EINVAL, "alpha_plain must be in (0, 1] (defensive mixture)");
+    }
+    if (!c->noalloc) return fail(c, LT_EHIP, "no scratch address for this device");
+    // the tile table, counted on the host without storing it
+    const long long ppl = cfg->paths_per_layout;
+    const int tp = effective_tile_paths(c, ppl);
+    long long n_tiles = 0;
+    for (int j = 0; j < c->n_layouts; ++j) {
+        const int nl = c->offs[j + 1] - c->offs[j];
+        if (ppl < nl) return fail(c, LT_EINVAL, "paths_per_layout smaller than the number of lights of a layout");
+        for (int l = 0; l < nl; ++l) {
+            const long long n = paths_of_light(ppl, nl, l);
+            if (n > 0xFFFFFFFFll) return fail(c, LT_EINVAL, "more than 2^32 paths for one light");
+            n_tiles += (n + tp - 1) / tp;
+        }
+    }
+    // scratch layout, every region 256-byte aligned
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    size_t off = 0;
+    const size_t o_queue = off;
+    off += up(sizeof(unsigned) * 8);
+    const size_t o_tiles = off;
+    off += up(sizeof(int4) * (size_t)n_tiles);
+    const size_t o_range = off;
+    off += up(sizeof(int2) * (size_t)c->L);
+    const size_t o_np = off;
+    off += up(sizeof(long long) * (size_t)c->L);
+    const size_t o_part = off;
+    off += up(sizeof(double) * 6 * (size_t)n_tiles);
+    const size_t o_stack = off;
+    const int gdepth = std::max(gstack_depth(c), 1);
+    const size_t per_wave = sizeof(int) * (size_t)gdepth * 64;
+    const long long waves = off < kNoAllocBytes ? std::min<long long>((long long)((kNoAllocBytes - off) / per_wave),
+                                                                     resident_waves(c))
+                                                : 0;
+    if (waves < 64)
+        return fail(c, LT_EINVAL,
+                    "workload too large for the no-allocation scratch (" + std::to_string(kNoAllocBytes >> 20) +
+                        " MiB: work tiles, partial sums and stack overflow for at least 64 waves); use "
+                        "lt_trace_adjoint");
+    HIPCHK(c, hipSetDevice(c->device));
+    unsigned char* base = c->noalloc;
+    TraceArgs a = trace_args(c, cfg);
+    a.g = d_dOdE;
+    a.tiles = (const int4*)(base + o_tiles);
+    a.n_tiles = (int)n_tiles;
+    a.partials = (double*)(base + o_part);
+    a.bin_hist = nullptr;
+    a.gstack = (int*)(base + o_stack);
+    a.gdepth = gdepth;
+    a.gstack_waves = waves;
+    a.queue = (unsigned*)(base + o_queue);
+    for (int q = 0; q < 8; ++q) {
+        const long long lo = n_tiles * q / a.n_queues, hi = n_tiles * (q + 1) / a.n_queues;
+        a.q_first[q] = q < a.n_queues ? (int)lo : 0;
+        a.q_len[q] = q < a.n_queues ? (int)(hi - lo) : 0;
+    }
+    int2* range = (int2*)(base + o_range);
+    long long* npaths = (long long*)(base + o_np);
+    hipStream_t st = c->stream;
+    HIPCHK(c, launch_build_tiles(c->d_si, c->L, ppl, tp, (int)n_tiles, (int4*)(base + o_tiles), range, npaths, st));
+    HIPCHK(c, launch_light_setup(d_params, c->d_si, c->d_sf, npaths, c->L, c->d_lights, c->d_flags, st));
+    HIPCHK(c, launch_trace(true, false, a, c->tune.waves_per_block, c->tune.lds_depth, c->n_cu, st));
+    HIPCHK(c, launch_grad_reduce(a.partials, range, c->L, d_grad, st));
+    return LT_OK;
 }
 
 int lt_gradient_votes(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, const float* d_dOdE,

@@ -149,6 +149,10 @@ hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_p
 hipError_t launch_trace(bool adjoint, bool stats, const TraceArgs& a, int waves_per_block, int lds_depth, int n_cu,
                         hipStream_t st);
 hipError_t launch_record(const RecordArgs& a, int lds_depth, hipStream_t st);
+// work tiles of paths_per_layout ppl in tiles of tp paths, built on the device
+// from the static light table si (.y layout, .z index in it, .w lights in it)
+hipError_t launch_build_tiles(const int4* si, int L, long long ppl, int tp, int n_tiles, int4* tiles, int2* range,
+                              long long* npaths, hipStream_t st);
 hipError_t launch_light_setup(const float* params, const int4* lstat_i, const float4* lstat_f,
                               const long long* npaths, int n_lights, DevLight* out, unsigned* flags,
                               hipStream_t st, int rv = 0, float* cone = nullptr);

@@ -1615,6 +1615,42 @@ void launch_persistent(const TraceArgs& a, int n_cu, hipStream_t st)
     k_trace<ADJ, STATS, WPB, LDS_D, MODE><<<(unsigned)blocks, WPB * 64, 0, st>>>(a);
 }
 
+// Work tiles built on the device (the table the context otherwise builds on
+// the host and uploads): light gl of a layout of Lj lights (si[gl].w) and
+// local index l (si[gl].z) traces N = ppl / Lj + (l < ppl % Lj) paths in
+// tiles of tp paths, lights in order.  One thread forms the per-light ranges
+// (a prefix over the lights), then one thread per tile writes it.
+__global__ void k_tile_ranges(const int4* __restrict__ si, int L, long long ppl, int tp, int2* __restrict__ range,
+                              long long* __restrict__ npaths)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int acc = 0;
+    for (int gl = 0; gl < L; ++gl) {
+        const int4 s = si[gl];
+        const long long n = ppl / s.w + ((long long)s.z < ppl % s.w ? 1 : 0);
+        const int nt = (int)((n + tp - 1) / tp);
+        range[gl] = make_int2(acc, acc + nt);
+        npaths[gl] = n;
+        acc += nt;
+    }
+}
+
+__global__ void k_tile_fill(const int4* __restrict__ si, const int2* __restrict__ range,
+                            const long long* __restrict__ npaths, int L, int tp, int n_tiles, int4* __restrict__ tiles)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    int lo = 0, hi = L - 1;   // the light whose range holds t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (range[mid].x <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const long long f = (long long)(t - range[lo].x) * tp;
+    const long long cnt = npaths[lo] - f < tp ? npaths[lo] - f : tp;
+    tiles[t] = make_int4(lo, (int)(uint32_t)f, (int)cnt, si[lo].y);
+}
+
 __global__ void k_queue_reset(unsigned* __restrict__ q)
 {
     if (threadIdx.x < 8) q[threadIdx.x] = 0u;
@@ -1697,6 +1733,14 @@ hipError_t launch_trace(bool adjoint, bool stats, const TraceArgs& a, int waves_
     if (adjoint) return launch_t<true, false>(a, waves_per_block, lds_depth, n_cu, st);
     if (stats) return launch_t<false, true>(a, waves_per_block, lds_depth, n_cu, st);
     return launch_t<false, false>(a, waves_per_block, lds_depth, n_cu, st);
+}
+
+hipError_t launch_build_tiles(const int4* si, int L, long long ppl, int tp, int n_tiles, int4* tiles, int2* range,
+                              long long* npaths, hipStream_t st)
+{
+    k_tile_ranges<<<1, 64, 0, st>>>(si, L, ppl, tp, range, npaths);
+    k_tile_fill<<<(n_tiles + 255) / 256, 256, 0, st>>>(si, range, npaths, L, tp, n_tiles, tiles);
+    return hipGetLastError();
 }
 
 hipError_t launch_pt(bool adjoint, const PtArgs& a, int lds_depth, hipStream_t st)

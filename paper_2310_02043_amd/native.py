@@ -29,7 +29,7 @@ EXPORTED = [
     "lt_timing_read", "lt_proposal_set_table", "lt_proposal_get_table", "lt_proposal_set_scale",
     "lt_proposal_mlp_infer",
     "lt_proposal_mlp_train", "lt_proposal_set", "lt_proposal_refresh", "lt_proposal_update_scale",
-    "lt_proposal_train_step", "lt_proposal_get_net",
+    "lt_proposal_train_step", "lt_proposal_get_net", "lt_trace_adjoint_noalloc",
 ]
 MLP_WEIGHTS, MLP_IN, MLP_BINS = 72832, 32, 1024
 
@@ -93,6 +93,7 @@ def load():
     L.lt_trace_forward.argtypes = [P, C.POINTER(TraceCfg), P, P, P]
     L.lt_objective.argtypes = [P, P, P, P, I64, P, P]
     L.lt_trace_adjoint.argtypes = [P, C.POINTER(TraceCfg), P, P, P, P]
+    L.lt_trace_adjoint_noalloc.argtypes = [P, C.POINTER(TraceCfg), P, P, P]
     L.lt_gradient_votes.argtypes = [P, C.POINTER(TraceCfg), P, P, I32, I32, P, P]
     L.lt_pt_forward.argtypes = [P, C.POINTER(TraceCfg), P, I32, P, P]
     L.lt_set_albedo_rgb.argtypes = [P, P]
@@ -251,6 +252,17 @@ class Context:
         self._stream()
         self._check(self.lib.lt_trace_adjoint(self.h, C.byref(cfg), _ptr(params), _ptr(dOdE), _ptr(grad),
                                               _ptr(bin_hist)))
+        return grad
+
+    def trace_adjoint_noalloc(self, params, dOdE, cfg, grad):
+        """lt_trace_adjoint_noalloc: the adjoint pass with no device allocation
+        (grad [L,6] f32 must be given)."""
+        torch = self._torch
+        self._dev(params, torch.float32, (self.n_lights, 6))
+        self._dev(dOdE, torch.float32, (self.n_layouts, self.n_texels))
+        self._dev(grad, torch.float32, (self.n_lights, 6))
+        self._stream()
+        self._check(self.lib.lt_trace_adjoint_noalloc(self.h, C.byref(cfg), _ptr(params), _ptr(dOdE), _ptr(grad)))
         return grad
 
     def gradient_votes(self, params, dOdE, cfg, light, param, vote=None, grad=None):
