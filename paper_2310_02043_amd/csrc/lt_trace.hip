@@ -73,8 +73,8 @@ __device__ __forceinline__ void cswap(float& ta, int& ca, float& tb, int& cb)
     ta = t0; tb = t1; ca = c0; cb = c1;
 }
 
-// One traversal operation per lane and call: either one queued leaf triangle
-// test, or one node of the 4-wide tree (four box tests; hit leaf children are
+// One traversal operation per lane and call: either up to two queued leaf
+// triangle tests, or one node of the 4-wide tree (four box tests; hit leaf children are
 // queued as a bit mask over the node's child references, hit internal
 // children sorted by entry distance, the nearest visited next and the others
 // pushed far-to-near).  Queued leaves are tested before the next node step,
@@ -90,14 +90,17 @@ __device__ __forceinline__ void trav_step(const Ray& r, int skip, Trav& s, bool&
     if (mode == 1 && s.lmask == 0) return;
     if (mode == 2 && s.lmask != 0) return;
     if (s.lmask != 0) {
-        const int k = __builtin_ctz((unsigned)s.lmask);
-        const int r01 = (k & 1) ? s.lq1 : s.lq0, r23 = (k & 1) ? s.lq3 : s.lq2;
-        const int ref = (k & 2) ? r23 : r01;
-        // a leaf reference is ~(its triangle's first float4 row); < 2^32 bytes
-        const float4* tp = (const float4*)((const char*)tris + ((unsigned)(~ref) << 4));
-        tri_test(tp[0], tp[1], tp[2], v3(r.ox, r.oy, r.oz), v3(r.dx, r.dy, r.dz), skip, s.tb, s.pb, s.qb);
-        if (STATS) ++n_tris;
-        s.lmask &= s.lmask - 1;
+#pragma unroll
+        for (int rep = 0; rep < 2; ++rep) {
+            if (s.lmask == 0) break;
+            const int k = __builtin_ctz((unsigned)s.lmask);
+            const int r01 = (k & 1) ? s.lq1 : s.lq0, r23 = (k & 1) ? s.lq3 : s.lq2;
+            const int ref = (k & 2) ? r23 : r01;
+            const float4* tp = (const float4*)((const char*)tris + ((unsigned)(~ref) << 4));
+            tri_test(tp[0], tp[1], tp[2], v3(r.ox, r.oy, r.oz), v3(r.dx, r.dy, r.dz), skip, s.tb, s.pb, s.qb);
+            if (STATS) ++n_tris;
+            s.lmask &= s.lmask - 1;
+        }
         if (s.lmask == 0 && s.node < 0) traversing = false;
         return;
     }
