@@ -8,8 +8,9 @@
 // within a window of the Morton order, mutual nearest neighbours merge, the
 // cluster list is compacted by a prefix sum, until one cluster is left.
 // Internal nodes are numbered from the root (0) in reverse creation order.
-// Output nodes hold both child boxes inline (64 B, one fetch = two box
-// tests); leaves are single triangles stored in Morton order as (v0, id),
+// The binary tree is collapsed into a 4-wide tree whose nodes keep the four
+// child boxes as f16 offsets from a node origin (80 B, five loads per node
+// step); leaves are single triangles stored in Morton order as (v0, id),
 // (v1 - v0, patch), (v2 - v0, 0).
 #include <hip/hip_runtime.h>
 #include <utility>
@@ -233,11 +234,14 @@ __global__ void k_ploc_write(int nc, int n_int, int node_base, const int* __rest
 }
 
 // ---- collapse of the binary tree into a 4-wide tree ------------------------
-// Node of the wide tree, 128 B: lo.x, hi.x, lo.y, hi.y, lo.z, hi.z of the four
-// children (float4 each, one lane per child), then the child references
-// (>= 0 wide node, < 0 leaf ~(3 x triangle slot), the triangle's first
-// float4 row, kEmptyChild unused, with an inverted box that no slab test
-// hits) and padding.
+// Node of the wide tree, 80 B = 5 rows of 16 B (kNodeRows): the node origin
+// (f32 x, y, z: the least lower bound of its children, then 0); for x, y and
+// z a row of the four children's lower planes then their upper planes as f16
+// offsets from the origin, rounded outward (lower down, upper up) so that the
+// stored box contains the child's box; then the child references (>= 0 wide
+// node: 5 x node index, its first row; < 0 leaf ~(3 x triangle slot), the
+// triangle's first row; kEmptyChild unused, with an inverted box, offsets
+// +inf / -inf, that no slab test hits).
 __device__ __forceinline__ void ref_box(int c, const float4* nlo, const float4* nhi, const int* vals,
                                         const float4* tlo, const float4* thi, float4& lo, float4& hi)
 {
@@ -364,6 +368,30 @@ __global__ void k_collapse_open(int n_level, const int* __restrict__ level, cons
     cnt[i] = n_int;
 }
 
+// Conservative conversions of a non-negative offset to f16: the largest f16
+// not above x, and the smallest not below it (offsets beyond the f16 range
+// become 65504 and +inf).
+__device__ __forceinline__ unsigned short f16_down(double x)
+{
+    _Float16 h = (_Float16)(float)x;
+    unsigned short b = __builtin_bit_cast(unsigned short, h);
+    while ((double)__builtin_bit_cast(_Float16, b) > x) --b;   // x >= 0: positive encodings step down by one
+    return b;
+}
+
+__device__ __forceinline__ unsigned short f16_up(double x)
+{
+    _Float16 h = (_Float16)(float)x;
+    unsigned short b = __builtin_bit_cast(unsigned short, h);
+    while ((double)__builtin_bit_cast(_Float16, b) < x) ++b;   // up to 0x7C00 = +inf
+    return b;
+}
+
+__device__ __forceinline__ unsigned pack_f16(unsigned short a, unsigned short b)
+{
+    return (unsigned)a | ((unsigned)b << 16);
+}
+
 // Write the wide nodes of a level; internal children become the next level.
 __global__ void k_collapse_write(int n_level, int out_base, int next_base, const int* __restrict__ kids,
                                  const unsigned long long* __restrict__ off, const float4* __restrict__ nlo,
@@ -392,22 +420,42 @@ __global__ void k_collapse_write(int n_level, int out_base, int next_base, const
         if (c >= 0) {
             const int w = next_base + base + rank;
             next_level[base + rank] = c;
-            ref[q] = w;
+            ref[q] = kNodeRows * w;
             ++rank;
         } else {
             ref[q] = ~(3 * (~c));   // leaf: ~(first float4 row of its triangle)
         }
     }
-    float4* nd = wide + 8 * (size_t)(out_base + i);
-    nd[0] = make_float4(lx[0], lx[1], lx[2], lx[3]);
-    nd[1] = make_float4(hx[0], hx[1], hx[2], hx[3]);
-    nd[2] = make_float4(ly[0], ly[1], ly[2], ly[3]);
-    nd[3] = make_float4(hy[0], hy[1], hy[2], hy[3]);
-    nd[4] = make_float4(lz[0], lz[1], lz[2], lz[3]);
-    nd[5] = make_float4(hz[0], hz[1], hz[2], hz[3]);
-    nd[6] = make_float4(__int_as_float(ref[0]), __int_as_float(ref[1]), __int_as_float(ref[2]),
+    // origin: the least lower bound over the used slots
+    float o[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+    for (int q = 0; q < 4; ++q)
+        if (ref[q] != kEmptyChild) {
+            o[0] = fminf(o[0], lx[q]);
+            o[1] = fminf(o[1], ly[q]);
+            o[2] = fminf(o[2], lz[q]);
+        }
+    for (int k = 0; k < 3; ++k)
+        if (o[k] == __builtin_inff()) o[k] = 0.0f;
+    unsigned short ql[3][4], qh[3][4];
+    for (int q = 0; q < 4; ++q) {
+        const float l3[3] = {lx[q], ly[q], lz[q]}, h3[3] = {hx[q], hy[q], hz[q]};
+        for (int k = 0; k < 3; ++k) {
+            if (ref[q] == kEmptyChild) {
+                ql[k][q] = 0x7C00;   // +inf
+                qh[k][q] = 0xFC00;   // -inf
+            } else {
+                ql[k][q] = f16_down((double)l3[k] - (double)o[k]);
+                qh[k][q] = f16_up((double)h3[k] - (double)o[k]);
+            }
+        }
+    }
+    float4* nd = wide + kNodeRows * (size_t)(out_base + i);
+    nd[0] = make_float4(o[0], o[1], o[2], 0.f);
+    for (int k = 0; k < 3; ++k)
+        nd[1 + k] = make_float4(__uint_as_float(pack_f16(ql[k][0], ql[k][1])), __uint_as_float(pack_f16(ql[k][2], ql[k][3])),
+                                __uint_as_float(pack_f16(qh[k][0], qh[k][1])), __uint_as_float(pack_f16(qh[k][2], qh[k][3])));
+    nd[4] = make_float4(__int_as_float(ref[0]), __int_as_float(ref[1]), __int_as_float(ref[2]),
                         __int_as_float(ref[3]));
-    nd[7] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 // ---- exclusive prefix sum of u64 (block-local, block sums, add) --------------
@@ -521,7 +569,7 @@ hipError_t scan_u64(const unsigned long long* in, unsigned long long* out, unsig
 
 }  // namespace
 
-// Builds the 4-wide nodes [n_nodes * 8 float4] and leaf triangles [n * 3 float4];
+// Builds the 4-wide nodes [n_nodes * kNodeRows float4] and leaf triangles [n * 3 float4];
 // *depth_out = number of wide levels.
 // Device inputs: d_verts [V*3], d_tris [n*3], d_tri_patch [n].
 hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_patch, int n, float pad,
@@ -552,7 +600,7 @@ hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_p
     LT_TRY(keys.alloc(n_pow2)); LT_TRY(vals.alloc(n_pow2));
     LT_TRY(child.alloc(n_int)); LT_TRY(pint.alloc(n_int)); LT_TRY(pleaf.alloc(n));
     LT_TRY(nlo.alloc(n_int)); LT_TRY(nhi.alloc(n_int));
-    LT_TRY(nodes.alloc(8 * (size_t)n_int)); LT_TRY(otris.alloc(3 * (size_t)n));
+    LT_TRY(nodes.alloc(kNodeRows * (size_t)n_int)); LT_TRY(otris.alloc(3 * (size_t)n));
 
     k_tri_setup<<<blocks_for(n, 256), 256, 0, st>>>(d_verts, d_tris, n, pad, tlo.p, thi.p, cen.p);
     k_bounds_partial<<<n_part, 256, 0, st>>>(cen.p, n, part.p);

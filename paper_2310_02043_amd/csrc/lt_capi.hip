@@ -545,7 +545,7 @@ int lt_scene_upload(lt_ctx* c, const float* h_verts, int64_t n_verts, const int3
     if (!c) return LT_EINVAL;
     if (!h_verts || !h_tris || !h_tri_patch || !h_patches) return fail(c, LT_EINVAL, "NULL scene array");
     if (n_verts < 3 || n_tris < 1 || n_patches < 1) return fail(c, LT_EINVAL, "empty scene");
-    // the traversal addresses triangles (48 B) and nodes (128 B) by 32-bit byte offsets
+    // the traversal addresses triangles (48 B) and nodes (80 B) by 32-bit byte offsets
     if (n_tris > (1ll << 26) || n_verts > (1ll << 31) - 1) return fail(c, LT_EINVAL, "scene too large");
     double amax = 0.0, lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int64_t v = 0; v < n_verts; ++v) {
@@ -614,7 +614,7 @@ int lt_scene_upload(lt_ctx* c, const float* h_verts, int64_t n_verts, const int3
         free_scene(c);
         return fail(c, LT_EINVAL, "BVH deeper than the traversal stack bound");
     }
-    if ((long long)n_nodes > (1ll << 25)) {
+    if ((long long)n_nodes * 16 * kNodeRows > (1ll << 32)) {
         free_scene(c);
         return fail(c, LT_EINVAL, "BVH larger than 2^32 bytes");
     }
@@ -1457,7 +1457,7 @@ int lt_info_get(const lt_ctx* c, lt_info* out)
     out->n_texels = c->K;
     out->bvh_nodes = c->n_nodes;
     out->bvh_depth = c->depth;
-    out->device_bytes = (int64_t)c->n_nodes * 128 + c->n_tris * 48 + (int64_t)c->n_patches * sizeof(DevPatch) +
+    out->device_bytes = (int64_t)c->n_nodes * 16 * kNodeRows + c->n_tris * 48 + (int64_t)c->n_patches * sizeof(DevPatch) +
                         c->K * 4 + (int64_t)c->gstack_cap * 4 + (int64_t)c->partials_cap * 8;
     out->n_lights = c->L;
     out->n_layouts = c->n_layouts;

@@ -42,17 +42,24 @@ __device__ __forceinline__ void set_ray(Ray& r, V3 o, V3 d)
     r.oiz = o.z * r.iz;
 }
 
-// Entry distance of a box from its near and far planes along the ray
-// (chosen per ray by the signs of the reciprocal direction), interval
-// [0, tmax]; +inf for a miss.  Same result as taking min / max of both planes
-// of every axis, with six fewer instructions per box.
-__device__ __forceinline__ float slab_nf(const Ray& r, float xn, float xf, float yn, float yf, float zn, float zf,
-                                         float tmax)
+// f16 halves of a packed word, widened exactly (the fma then takes the f16
+// operand directly, v_fma_mix_f32)
+__device__ __forceinline__ float f16lo(unsigned w) { return (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xFFFFu)); }
+__device__ __forceinline__ float f16hi(unsigned w) { return (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16)); }
+
+// Entry distance of a child box along the ray, interval [0, tmax], +inf for
+// a miss.  The planes are offsets h from the node origin, so a plane's
+// distance is h * ix + b with b = origin * ix - o * ix per axis; xn/xf are
+// the near and far planes for the ray's direction signs, so no per-axis
+// min / max is needed.  The build pads every box by a scene-relative margin
+// far above the rounding of this form, so the test stays conservative.
+__device__ __forceinline__ float slab16(const Ray& r, float xn, float xf, float yn, float yf, float zn, float zf,
+                                        float bx, float by, float bz, float tmax)
 {
-    const float t0 = fmaxf(fmaxf(__builtin_fmaf(xn, r.ix, -r.oix), __builtin_fmaf(yn, r.iy, -r.oiy)),
-                           fmaxf(__builtin_fmaf(zn, r.iz, -r.oiz), 0.0f));
-    const float t1 = fminf(fminf(__builtin_fmaf(xf, r.ix, -r.oix), __builtin_fmaf(yf, r.iy, -r.oiy)),
-                           fminf(__builtin_fmaf(zf, r.iz, -r.oiz), tmax));
+    const float t0 = fmaxf(fmaxf(__builtin_fmaf(xn, r.ix, bx), __builtin_fmaf(yn, r.iy, by)),
+                           fmaxf(__builtin_fmaf(zn, r.iz, bz), 0.0f));
+    const float t1 = fminf(fminf(__builtin_fmaf(xf, r.ix, bx), __builtin_fmaf(yf, r.iy, by)),
+                           fminf(__builtin_fmaf(zf, r.iz, bz), tmax));
     return t0 <= t1 ? t0 : __builtin_inff();
 }
 
@@ -112,21 +119,28 @@ __device__ __forceinline__ void trav_step(const Ray& r, int skip, Trav& s, bool&
         s.qb = -1;
         return;
     }
-    // 32-bit byte offsets from the uniform node base (128 B per node; the
-    // upload keeps the tree under 2^32 bytes), so loads take the scalar-base
-    // form and no 64-bit address arithmetic
-    const char* nb = (const char*)nodes;
-    const unsigned ob = (unsigned)s.node << 7;
-    // rows of the near planes: lo (even row) for a positive direction, hi otherwise
-    const unsigned nx = (__float_as_uint(r.ix) >> 31) << 4, ny = 32u + ((__float_as_uint(r.iy) >> 31) << 4),
-                   nz = 64u + ((__float_as_uint(r.iz) >> 31) << 4);
-    const float4 xn = *(const float4*)(nb + (ob + nx)), xf = *(const float4*)(nb + (ob + (nx ^ 16u)));
-    const float4 yn = *(const float4*)(nb + (ob + ny)), yf = *(const float4*)(nb + (ob + (ny ^ 16u)));
-    const float4 zn = *(const float4*)(nb + (ob + nz)), zf = *(const float4*)(nb + (ob + (nz ^ 16u)));
-    const float4 cr = *(const float4*)(nb + (ob + 96u));
+    // 32-bit byte offsets from the uniform node base (a reference is the
+    // node's first 16-byte row; the upload keeps the tree under 2^32 bytes),
+    // so the five loads share one address with immediate offsets
+    const char* nd = (const char*)nodes + ((unsigned)s.node << 4);
+    const float4 org = *(const float4*)nd;
+    const uint4 px = *(const uint4*)(nd + 16);
+    const uint4 py = *(const uint4*)(nd + 32);
+    const uint4 pz = *(const uint4*)(nd + 48);
+    const float4 cr = *(const float4*)(nd + 64);
     if (STATS) ++n_nodes;
-    float t[4] = {slab_nf(r, xn.x, xf.x, yn.x, yf.x, zn.x, zf.x, s.tb), slab_nf(r, xn.y, xf.y, yn.y, yf.y, zn.y, zf.y, s.tb),
-                  slab_nf(r, xn.z, xf.z, yn.z, yf.z, zn.z, zf.z, s.tb), slab_nf(r, xn.w, xf.w, yn.w, yf.w, zn.w, zf.w, s.tb)};
+    // near and far planes per axis: the lower planes for a positive
+    // direction component, the upper ones otherwise (two children per word)
+    const bool sx = __float_as_int(r.ix) < 0, sy = __float_as_int(r.iy) < 0, sz = __float_as_int(r.iz) < 0;
+    const unsigned xn0 = sx ? px.z : px.x, xn1 = sx ? px.w : px.y, xf0 = sx ? px.x : px.z, xf1 = sx ? px.y : px.w;
+    const unsigned yn0 = sy ? py.z : py.x, yn1 = sy ? py.w : py.y, yf0 = sy ? py.x : py.z, yf1 = sy ? py.y : py.w;
+    const unsigned zn0 = sz ? pz.z : pz.x, zn1 = sz ? pz.w : pz.y, zf0 = sz ? pz.x : pz.z, zf1 = sz ? pz.y : pz.w;
+    const float bx = __builtin_fmaf(org.x, r.ix, -r.oix), by = __builtin_fmaf(org.y, r.iy, -r.oiy),
+                bz = __builtin_fmaf(org.z, r.iz, -r.oiz);
+    float t[4] = {slab16(r, f16lo(xn0), f16lo(xf0), f16lo(yn0), f16lo(yf0), f16lo(zn0), f16lo(zf0), bx, by, bz, s.tb),
+                  slab16(r, f16hi(xn0), f16hi(xf0), f16hi(yn0), f16hi(yf0), f16hi(zn0), f16hi(zf0), bx, by, bz, s.tb),
+                  slab16(r, f16lo(xn1), f16lo(xf1), f16lo(yn1), f16lo(yf1), f16lo(zn1), f16lo(zf1), bx, by, bz, s.tb),
+                  slab16(r, f16hi(xn1), f16hi(xf1), f16hi(yn1), f16hi(yf1), f16hi(zn1), f16hi(zf1), bx, by, bz, s.tb)};
     int c[4] = {__float_as_int(cr.x), __float_as_int(cr.y), __float_as_int(cr.z), __float_as_int(cr.w)};
     // hit leaf children are queued by mask (their references stay in lq0..3);
     // only hit internal children keep a finite entry distance for the sort
