@@ -9,9 +9,9 @@
 // cluster list is compacted by a prefix sum, until one cluster is left.
 // Internal nodes are numbered from the root (0) in reverse creation order.
 // The binary tree is collapsed into a 4-wide tree whose nodes keep the four
-// child boxes as f16 offsets from a node origin (80 B, five loads per node
-// step); leaves are single triangles stored in Morton order as (v0, id),
-// (v1 - v0, patch), (v2 - v0, 0).
+// child boxes as f16 offsets from a node origin (64 B, four loads per node
+// step); leaves are single triangles, stored so that the leaves of each wide
+// node are consecutive, as (v0, id), (v1 - v0, patch), (v2 - v0, 0).
 #include <hip/hip_runtime.h>
 #include <utility>
 #include <vector>
@@ -234,14 +234,16 @@ __global__ void k_ploc_write(int nc, int n_int, int node_base, const int* __rest
 }
 
 // ---- collapse of the binary tree into a 4-wide tree ------------------------
-// Node of the wide tree, 80 B = 5 rows of 16 B (kNodeRows): the node origin
-// (f32 x, y, z: the least lower bound of its children, then 0); for x, y and
-// z a row of the four children's lower planes then their upper planes as f16
-// offsets from the origin, rounded outward (lower down, upper up) so that the
-// stored box contains the child's box; then the child references (>= 0 wide
-// node: 5 x node index, its first row; < 0 leaf ~(3 x triangle slot), the
-// triangle's first row; kEmptyChild unused, with an inverted box, offsets
-// +inf / -inf, that no slab test hits).
+// Node of the wide tree, 64 B = 4 rows of 16 B (kNodeRows).  Its slots hold
+// the internal children first, then the leaves, then unused slots.  Rows 0-2:
+// for x, y and z the four slots' lower planes then their upper planes as f16
+// offsets from the node origin, rounded outward (lower down, upper up) so
+// that the stored box contains the child's box; unused slots hold +inf /
+// -inf, a box no slab test hits.  Row 3: the origin as bf16 x, y, z (rounded
+// down, at or below every child box; x | y << 16, then z | counts << 16 with
+// counts = internal children | leaves << 4), the index of the first internal
+// child (the others follow it), the slot of the first leaf triangle (the
+// others follow it).
 __device__ __forceinline__ void ref_box(int c, const float4* nlo, const float4* nhi, const int* vals,
                                         const float4* tlo, const float4* thi, float4& lo, float4& hi)
 {
@@ -360,12 +362,13 @@ __global__ void k_collapse_open(int n_level, const int* __restrict__ level, cons
             sn[top] = cc.x; ss[top] = d; ++top;
         }
     }
-    unsigned long long n_int = 0;
+    unsigned long long n_int = 0, n_leaf = 0;
     for (int q = 0; q < 4; ++q) {
         kids[4 * i + q] = k[q];
         n_int += (k[q] >= 0) ? 1ull : 0ull;
+        n_leaf += (k[q] < 0 && k[q] != kEmptyChild) ? 1ull : 0ull;
     }
-    cnt[i] = n_int;
+    cnt[i] = n_int | (n_leaf << 32);   // the prefix sum adds both halves
 }
 
 // Conservative conversions of a non-negative offset to f16: the largest f16
@@ -392,70 +395,79 @@ __device__ __forceinline__ unsigned pack_f16(unsigned short a, unsigned short b)
     return (unsigned)a | ((unsigned)b << 16);
 }
 
-// Write the wide nodes of a level; internal children become the next level.
-__global__ void k_collapse_write(int n_level, int out_base, int next_base, const int* __restrict__ kids,
+// The largest bf16 not above x (x finite): the upper half of its bits, one
+// step further from zero for a negative x with a non-zero lower half.
+__device__ __forceinline__ unsigned short bf16_down(float x)
+{
+    const unsigned u = __float_as_uint(x);
+    unsigned short b = (unsigned short)(u >> 16);
+    if ((int)u < 0 && (u & 0xFFFFu) != 0u) ++b;
+    return b;
+}
+
+// Write the wide nodes of a level; internal children become the next level
+// (from next_base + the node's internal-child offset), leaves take the
+// triangle slots from leaf_base + the node's leaf offset (leaf_order[slot] =
+// the leaf's Morton position).
+__global__ void k_collapse_write(int n_level, int out_base, int next_base, int leaf_base, const int* __restrict__ kids,
                                  const unsigned long long* __restrict__ off, const float4* __restrict__ nlo,
                                  const float4* __restrict__ nhi, const int* __restrict__ vals,
                                  const float4* __restrict__ tlo, const float4* __restrict__ thi,
-                                 float4* __restrict__ wide, int* __restrict__ next_level)
+                                 float4* __restrict__ wide, int* __restrict__ next_level, int* __restrict__ leaf_order)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_level) return;
-    float lx[4], hx[4], ly[4], hy[4], lz[4], hz[4];
-    int ref[4];
-    int rank = 0;
-    const int base = (int)off[i];
+    const int ibase = (int)(off[i] & 0xffffffffull), lbase = (int)(off[i] >> 32);
+    // slot order: internal children, leaves, unused
+    int ord[4];
+    int no = 0;
+    for (int q = 0; q < 4; ++q)
+        if (kids[4 * i + q] >= 0) ord[no++] = kids[4 * i + q];
+    const int ni = no;
     for (int q = 0; q < 4; ++q) {
         const int c = kids[4 * i + q];
-        if (c == kEmptyChild) {
-            // an inverted box: every slab test misses it
-            lx[q] = ly[q] = lz[q] = __builtin_inff();
-            hx[q] = hy[q] = hz[q] = -__builtin_inff();
-            ref[q] = kEmptyChild;
-            continue;
-        }
-        float4 lo, hi;
-        ref_box(c, nlo, nhi, vals, tlo, thi, lo, hi);
-        lx[q] = lo.x; hx[q] = hi.x; ly[q] = lo.y; hy[q] = hi.y; lz[q] = lo.z; hz[q] = hi.z;
-        if (c >= 0) {
-            const int w = next_base + base + rank;
-            next_level[base + rank] = c;
-            ref[q] = kNodeRows * w;
-            ++rank;
-        } else {
-            ref[q] = ~(3 * (~c));   // leaf: ~(first float4 row of its triangle)
-        }
+        if (c < 0 && c != kEmptyChild) ord[no++] = c;
     }
-    // origin: the least lower bound over the used slots
-    float o[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
-    for (int q = 0; q < 4; ++q)
-        if (ref[q] != kEmptyChild) {
-            o[0] = fminf(o[0], lx[q]);
-            o[1] = fminf(o[1], ly[q]);
-            o[2] = fminf(o[2], lz[q]);
-        }
-    for (int k = 0; k < 3; ++k)
-        if (o[k] == __builtin_inff()) o[k] = 0.0f;
-    unsigned short ql[3][4], qh[3][4];
+    const int nl = no - ni;
+    while (no < 4) ord[no++] = kEmptyChild;
+    float lo3[4][3], hi3[4][3];
     for (int q = 0; q < 4; ++q) {
-        const float l3[3] = {lx[q], ly[q], lz[q]}, h3[3] = {hx[q], hy[q], hz[q]};
+        if (ord[q] == kEmptyChild) continue;
+        float4 lo, hi;
+        ref_box(ord[q], nlo, nhi, vals, tlo, thi, lo, hi);
+        lo3[q][0] = lo.x; lo3[q][1] = lo.y; lo3[q][2] = lo.z;
+        hi3[q][0] = hi.x; hi3[q][1] = hi.y; hi3[q][2] = hi.z;
+    }
+    for (int r = 0; r < ni; ++r) next_level[ibase + r] = ord[r];
+    for (int j = 0; j < nl; ++j) leaf_order[leaf_base + lbase + j] = ~ord[ni + j];
+    // origin: the least lower bound over the used slots, rounded down to bf16
+    unsigned short ob[3];
+    float o[3];
+    for (int k = 0; k < 3; ++k) {
+        float m = __builtin_inff();
+        for (int q = 0; q < ni + nl; ++q) m = fminf(m, lo3[q][k]);
+        if (m == __builtin_inff()) m = 0.0f;
+        ob[k] = bf16_down(m);
+        o[k] = __uint_as_float((unsigned)ob[k] << 16);
+    }
+    unsigned short ql[3][4], qh[3][4];
+    for (int q = 0; q < 4; ++q)
         for (int k = 0; k < 3; ++k) {
-            if (ref[q] == kEmptyChild) {
+            if (q >= ni + nl) {
                 ql[k][q] = 0x7C00;   // +inf
                 qh[k][q] = 0xFC00;   // -inf
             } else {
-                ql[k][q] = f16_down((double)l3[k] - (double)o[k]);
-                qh[k][q] = f16_up((double)h3[k] - (double)o[k]);
+                ql[k][q] = f16_down((double)lo3[q][k] - (double)o[k]);
+                qh[k][q] = f16_up((double)hi3[q][k] - (double)o[k]);
             }
         }
-    }
     float4* nd = wide + kNodeRows * (size_t)(out_base + i);
-    nd[0] = make_float4(o[0], o[1], o[2], 0.f);
     for (int k = 0; k < 3; ++k)
-        nd[1 + k] = make_float4(__uint_as_float(pack_f16(ql[k][0], ql[k][1])), __uint_as_float(pack_f16(ql[k][2], ql[k][3])),
-                                __uint_as_float(pack_f16(qh[k][0], qh[k][1])), __uint_as_float(pack_f16(qh[k][2], qh[k][3])));
-    nd[4] = make_float4(__int_as_float(ref[0]), __int_as_float(ref[1]), __int_as_float(ref[2]),
-                        __int_as_float(ref[3]));
+        nd[k] = make_float4(__uint_as_float(pack_f16(ql[k][0], ql[k][1])), __uint_as_float(pack_f16(ql[k][2], ql[k][3])),
+                            __uint_as_float(pack_f16(qh[k][0], qh[k][1])), __uint_as_float(pack_f16(qh[k][2], qh[k][3])));
+    const unsigned counts = (unsigned)ni | ((unsigned)nl << 4);
+    nd[3] = make_float4(__uint_as_float(pack_f16(ob[0], ob[1])), __uint_as_float(pack_f16(ob[2], (unsigned short)counts)),
+                        __int_as_float(next_base + ibase), __int_as_float(leaf_base + lbase));
 }
 
 // ---- exclusive prefix sum of u64 (block-local, block sums, add) --------------
@@ -522,13 +534,13 @@ __global__ void __launch_bounds__(256) k_scan_add(unsigned long long* __restrict
         if (base + k < n) out[base + k] += s;
 }
 
-__global__ void k_write_tris(int n, const int* __restrict__ vals, const float* __restrict__ verts,
-                             const int* __restrict__ tris, const int* __restrict__ tri_patch,
-                             float4* __restrict__ out)
+__global__ void k_write_tris(int n, const int* __restrict__ leaf_order, const int* __restrict__ vals,
+                             const float* __restrict__ verts, const int* __restrict__ tris,
+                             const int* __restrict__ tri_patch, float4* __restrict__ out)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    const int t = vals[s];
+    const int t = vals[leaf_order[s]];
     const int a = tris[3 * t], b = tris[3 * t + 1], c = tris[3 * t + 2];
     const float v0x = verts[3 * a], v0y = verts[3 * a + 1], v0z = verts[3 * a + 2];
     out[3 * s + 0] = make_float4(v0x, v0y, v0z, __int_as_float(t));
@@ -569,7 +581,8 @@ hipError_t scan_u64(const unsigned long long* in, unsigned long long* out, unsig
 
 }  // namespace
 
-// Builds the 4-wide nodes [n_nodes * kNodeRows float4] and leaf triangles [n * 3 float4];
+// Builds the 4-wide nodes [n_nodes * kNodeRows float4] and leaf triangles
+// [n * 3 float4, 2 * 3 for a single triangle, which the root holds twice];
 // *depth_out = number of wide levels.
 // Device inputs: d_verts [V*3], d_tris [n*3], d_tri_patch [n].
 hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_patch, int n, float pad,
@@ -600,7 +613,8 @@ hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_p
     LT_TRY(keys.alloc(n_pow2)); LT_TRY(vals.alloc(n_pow2));
     LT_TRY(child.alloc(n_int)); LT_TRY(pint.alloc(n_int)); LT_TRY(pleaf.alloc(n));
     LT_TRY(nlo.alloc(n_int)); LT_TRY(nhi.alloc(n_int));
-    LT_TRY(nodes.alloc(kNodeRows * (size_t)n_int)); LT_TRY(otris.alloc(3 * (size_t)n));
+    const int n_leaves = n > 1 ? n : 2;   // every triangle is one leaf; a single one fills both root slots
+    LT_TRY(nodes.alloc(kNodeRows * (size_t)n_int)); LT_TRY(otris.alloc(3 * (size_t)n_leaves));
 
     k_tri_setup<<<blocks_for(n, 256), 256, 0, st>>>(d_verts, d_tris, n, pad, tlo.p, thi.p, cen.p);
     k_bounds_partial<<<n_part, 256, 0, st>>>(cen.p, n, part.p);
@@ -647,7 +661,7 @@ hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_p
     if (rounds.empty()) rounds.push_back(std::make_pair(0, 1));
     // collapse into the wide tree, level by level from the root
     {
-        DevBuf<int> lvl[2], kids, dec;
+        DevBuf<int> lvl[2], kids, dec, leaf_order;
         DevBuf<float4> dp;
         DevBuf<unsigned long long> cnt, off;
         LT_TRY(dec.alloc(n_int)); LT_TRY(dp.alloc(n_int));
@@ -659,12 +673,13 @@ hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_p
         }
         LT_TRY(hipGetLastError());
         LT_TRY(lvl[0].alloc(n_int)); LT_TRY(lvl[1].alloc(n_int)); LT_TRY(kids.alloc(4 * (size_t)n_int));
-        LT_TRY(cnt.alloc(n_int)); LT_TRY(off.alloc(n_int));
+        LT_TRY(cnt.alloc(n_int)); LT_TRY(off.alloc(n_int)); LT_TRY(leaf_order.alloc(n_leaves));
         if (!sums.p) LT_TRY(sums.alloc(blocks_for(n_int, kScanItems)));
         if (!total.p) LT_TRY(total.alloc(1));
         const int root = 0;
         LT_TRY(hipMemcpyAsync(lvl[0].p, &root, sizeof(int), hipMemcpyHostToDevice, st));
         int n_level = 1, out_base = 0, cur = 0, levels = 0;
+        long long leaf_base = 0;
         while (n_level > 0) {
             if (++levels > n_int + 1) return hipErrorUnknown;
             k_collapse_open<<<blocks_for(n_level, 256), 256, 0, st>>>(n_level, lvl[cur].p, child.p, dec.p, kids.p,
@@ -674,19 +689,24 @@ hipError_t build_bvh(const float* d_verts, const int* d_tris, const int* d_tri_p
             LT_TRY(hipMemcpyAsync(&tot, total.p, sizeof(tot), hipMemcpyDeviceToHost, st));
             LT_TRY(hipStreamSynchronize(st));
             const int next_base = out_base + n_level;
-            if (next_base + (long long)tot > n_int) return hipErrorUnknown;   // before any write
-            k_collapse_write<<<blocks_for(n_level, 256), 256, 0, st>>>(n_level, out_base, next_base, kids.p, off.p,
-                                                                       nlo.p, nhi.p, vals.p, tlo.p, thi.p, nodes.p,
-                                                                       lvl[cur ^ 1].p);
+            const long long n_next = (long long)(tot & 0xffffffffull), n_lv = (long long)(tot >> 32);
+            // before any write
+            if (next_base + n_next > n_int || leaf_base + n_lv > n_leaves) return hipErrorUnknown;
+            k_collapse_write<<<blocks_for(n_level, 256), 256, 0, st>>>(n_level, out_base, next_base, (int)leaf_base,
+                                                                       kids.p, off.p, nlo.p, nhi.p, vals.p, tlo.p,
+                                                                       thi.p, nodes.p, lvl[cur ^ 1].p, leaf_order.p);
             LT_TRY(hipGetLastError());
             out_base = next_base;
-            n_level = (int)tot;
+            leaf_base += n_lv;
+            n_level = (int)n_next;
             cur ^= 1;
         }
+        if (leaf_base != n_leaves) return hipErrorUnknown;   // every leaf slot written once
         n_wide = out_base;
         wide_levels = levels;
+        k_write_tris<<<blocks_for(n_leaves, 256), 256, 0, st>>>(n_leaves, leaf_order.p, vals.p, d_verts, d_tris,
+                                                                d_tri_patch, otris.p);
     }
-    k_write_tris<<<blocks_for(n, 256), 256, 0, st>>>(n, vals.p, d_verts, d_tris, d_tri_patch, otris.p);
     int depth = wide_levels;
     LT_TRY(hipGetLastError());
     LT_TRY(hipStreamSynchronize(st));

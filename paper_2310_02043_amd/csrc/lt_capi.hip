@@ -545,7 +545,7 @@ int lt_scene_upload(lt_ctx* c, const float* h_verts, int64_t n_verts, const int3
     if (!c) return LT_EINVAL;
     if (!h_verts || !h_tris || !h_tri_patch || !h_patches) return fail(c, LT_EINVAL, "NULL scene array");
     if (n_verts < 3 || n_tris < 1 || n_patches < 1) return fail(c, LT_EINVAL, "empty scene");
-    // the traversal addresses triangles (48 B) and nodes (80 B) by 32-bit byte offsets
+    // the traversal addresses triangles (48 B) and nodes (64 B) by 32-bit byte offsets
     if (n_tris > (1ll << 26) || n_verts > (1ll << 31) - 1) return fail(c, LT_EINVAL, "scene too large");
     double amax = 0.0, lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int64_t v = 0; v < n_verts; ++v) {

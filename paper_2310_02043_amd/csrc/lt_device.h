@@ -162,12 +162,12 @@ __device__ __forceinline__ V3 xyz(float4 v) { return V3{v.x, v.y, v.z}; }
 // ---------------------------------------------------------------------------
 // Data layouts in HBM.
 // ---------------------------------------------------------------------------
-// BVH node of the 4-wide tree, 80 B = 5 rows of 16 B: the node origin (f32
-// x, y, z, 0); per axis x, y, z the four children's lower then upper planes
-// as f16 offsets from the origin (rounded outward); the four child
-// references as int bits (>= 0 first row of a wide node = 5 x its index,
-// < 0 leaf = ~(first float4 row of its triangle); an unused slot holds an
-// inverted box).
+// BVH node of the 4-wide tree, 64 B = 4 rows of 16 B, slots ordered internal
+// children, leaves, unused: per axis x, y, z the four slots' lower then upper
+// planes as f16 offsets from the node origin (rounded outward; unused slots
+// +inf / -inf); then the origin as bf16 x, y, z, the slot counts (internal |
+// leaves << 4), the first internal child's node index and the first leaf's
+// triangle slot (a node's children and its leaf triangles are consecutive).
 // Triangle, 48 B: (v0, original id), (e1 = v1 - v0, patch), (e2 = v2 - v0, 0).
 
 // Patch record, 80 B.

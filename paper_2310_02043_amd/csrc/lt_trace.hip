@@ -47,45 +47,21 @@ __device__ __forceinline__ void set_ray(Ray& r, V3 o, V3 d)
 __device__ __forceinline__ float f16lo(unsigned w) { return (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xFFFFu)); }
 __device__ __forceinline__ float f16hi(unsigned w) { return (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16)); }
 
-// Entry distance of a child box along the ray, interval [0, tmax], +inf for
-// a miss.  The planes are offsets h from the node origin, so a plane's
-// distance is h * ix + b with b = origin * ix - o * ix per axis; xn/xf are
-// the near and far planes for the ray's direction signs, so no per-axis
-// min / max is needed.  The build pads every box by a scene-relative margin
-// far above the rounding of this form, so the test stays conservative.
-__device__ __forceinline__ float slab16(const Ray& r, float xn, float xf, float yn, float yf, float zn, float zf,
-                                        float bx, float by, float bz, float tmax)
-{
-    const float t0 = fmaxf(fmaxf(__builtin_fmaf(xn, r.ix, bx), __builtin_fmaf(yn, r.iy, by)),
-                           fmaxf(__builtin_fmaf(zn, r.iz, bz), 0.0f));
-    const float t1 = fminf(fminf(__builtin_fmaf(xf, r.ix, bx), __builtin_fmaf(yf, r.iy, by)),
-                           fminf(__builtin_fmaf(zf, r.iz, bz), tmax));
-    return t0 <= t1 ? t0 : __builtin_inff();
-}
-
 struct Trav {
     float tb;
     int pb, qb;
     int node, sp;   // node < 0: nothing left to visit
     int steps;
-    int lmask;      // children of the last node step whose leaf triangle awaits its test
-    int lq0, lq1, lq2, lq3;   // that node's child references (leaf = ~(3 x triangle))
+    int lmask;      // slots of the last node step whose leaf triangle awaits its test
+    int lrow;       // that node's first leaf-triangle row, less 3 x its internal-child count
 };
 
-__device__ __forceinline__ void cswap(float& ta, int& ca, float& tb, int& cb)
-{
-    const bool sw = tb < ta;
-    const float t0 = sw ? tb : ta, t1 = sw ? ta : tb;
-    const int c0 = sw ? cb : ca, c1 = sw ? ca : cb;
-    ta = t0; tb = t1; ca = c0; cb = c1;
-}
-
 // One traversal operation per lane and call: either up to two queued leaf
-// triangle tests, or one node of the 4-wide tree (four box tests; hit leaf children are
-// queued as a bit mask over the node's child references, hit internal
-// children sorted by entry distance, the nearest visited next and the others
-// pushed far-to-near).  Queued leaves are tested before the next node step,
-// so the closest-hit bound tightens as early as before.
+// triangle tests, or one node of the 4-wide tree (four box tests; hit leaf
+// slots are queued as a bit mask, hit internal children sorted by entry
+// distance, the nearest visited next and the others pushed far-to-near).
+// Queued leaves are tested before the next node step, so the closest-hit
+// bound tightens as early as before.
 // mode 1 runs only a queued triangle test, mode 2 only a node step, mode 0
 // whichever the lane has next.
 template <int LDS_D, bool STATS>
@@ -100,10 +76,9 @@ __device__ __forceinline__ void trav_step(const Ray& r, int skip, Trav& s, bool&
 #pragma unroll
         for (int rep = 0; rep < 2; ++rep) {
             if (s.lmask == 0) break;
+            // leaf slot k holds the triangle at row lrow + 3 k (48 B each)
             const int k = __builtin_ctz((unsigned)s.lmask);
-            const int r01 = (k & 1) ? s.lq1 : s.lq0, r23 = (k & 1) ? s.lq3 : s.lq2;
-            const int ref = (k & 2) ? r23 : r01;
-            const float4* tp = (const float4*)((const char*)tris + ((unsigned)(~ref) << 4));
+            const float4* tp = (const float4*)((const char*)tris + ((unsigned)(s.lrow + 3 * k) << 4));
             tri_test(tp[0], tp[1], tp[2], v3(r.ox, r.oy, r.oz), v3(r.dx, r.dy, r.dz), skip, s.tb, s.pb, s.qb);
             if (STATS) ++n_tris;
             s.lmask &= s.lmask - 1;
@@ -119,51 +94,59 @@ __device__ __forceinline__ void trav_step(const Ray& r, int skip, Trav& s, bool&
         s.qb = -1;
         return;
     }
-    // 32-bit byte offsets from the uniform node base (a reference is the
-    // node's first 16-byte row; the upload keeps the tree under 2^32 bytes),
-    // so the five loads share one address with immediate offsets
-    const char* nd = (const char*)nodes + ((unsigned)s.node << 4);
-    const float4 org = *(const float4*)nd;
-    const uint4 px = *(const uint4*)(nd + 16);
-    const uint4 py = *(const uint4*)(nd + 32);
-    const uint4 pz = *(const uint4*)(nd + 48);
-    const float4 cr = *(const float4*)(nd + 64);
+    // 32-bit byte offsets from the uniform node base (64 B per node; the
+    // upload keeps the tree under 2^32 bytes), so the four loads share one
+    // address with immediate offsets
+    const char* nd = (const char*)nodes + ((unsigned)s.node << 6);
+    const uint4 px = *(const uint4*)nd;
+    const uint4 py = *(const uint4*)(nd + 16);
+    const uint4 pz = *(const uint4*)(nd + 32);
+    const uint4 hd = *(const uint4*)(nd + 48);
     if (STATS) ++n_nodes;
     // near and far planes per axis: the lower planes for a positive
-    // direction component, the upper ones otherwise (two children per word)
+    // direction component, the upper ones otherwise (two slots per word)
     const bool sx = __float_as_int(r.ix) < 0, sy = __float_as_int(r.iy) < 0, sz = __float_as_int(r.iz) < 0;
     const unsigned xn0 = sx ? px.z : px.x, xn1 = sx ? px.w : px.y, xf0 = sx ? px.x : px.z, xf1 = sx ? px.y : px.w;
     const unsigned yn0 = sy ? py.z : py.x, yn1 = sy ? py.w : py.y, yf0 = sy ? py.x : py.z, yf1 = sy ? py.y : py.w;
     const unsigned zn0 = sz ? pz.z : pz.x, zn1 = sz ? pz.w : pz.y, zf0 = sz ? pz.x : pz.z, zf1 = sz ? pz.y : pz.w;
-    const float bx = __builtin_fmaf(org.x, r.ix, -r.oix), by = __builtin_fmaf(org.y, r.iy, -r.oiy),
-                bz = __builtin_fmaf(org.z, r.iz, -r.oiz);
-    float t[4] = {slab16(r, f16lo(xn0), f16lo(xf0), f16lo(yn0), f16lo(yf0), f16lo(zn0), f16lo(zf0), bx, by, bz, s.tb),
-                  slab16(r, f16hi(xn0), f16hi(xf0), f16hi(yn0), f16hi(yf0), f16hi(zn0), f16hi(zf0), bx, by, bz, s.tb),
-                  slab16(r, f16lo(xn1), f16lo(xf1), f16lo(yn1), f16lo(yf1), f16lo(zn1), f16lo(zf1), bx, by, bz, s.tb),
-                  slab16(r, f16hi(xn1), f16hi(xf1), f16hi(yn1), f16hi(yf1), f16hi(zn1), f16hi(zf1), bx, by, bz, s.tb)};
-    int c[4] = {__float_as_int(cr.x), __float_as_int(cr.y), __float_as_int(cr.z), __float_as_int(cr.w)};
-    // hit leaf children are queued by mask (their references stay in lq0..3);
-    // only hit internal children keep a finite entry distance for the sort
+    const float xn[4] = {f16lo(xn0), f16hi(xn0), f16lo(xn1), f16hi(xn1)}, xf[4] = {f16lo(xf0), f16hi(xf0), f16lo(xf1), f16hi(xf1)};
+    const float yn[4] = {f16lo(yn0), f16hi(yn0), f16lo(yn1), f16hi(yn1)}, yf[4] = {f16lo(yf0), f16hi(yf0), f16lo(yf1), f16hi(yf1)};
+    const float zn[4] = {f16lo(zn0), f16hi(zn0), f16lo(zn1), f16hi(zn1)}, zf[4] = {f16lo(zf0), f16hi(zf0), f16lo(zf1), f16hi(zf1)};
+    // a plane at origin + h lies at distance h * ix + b, b = origin * ix - o * ix
+    const float bx = __builtin_fmaf(__uint_as_float(hd.x << 16), r.ix, -r.oix);
+    const float by = __builtin_fmaf(__uint_as_float(hd.x & 0xFFFF0000u), r.iy, -r.oiy);
+    const float bz = __builtin_fmaf(__uint_as_float(hd.y << 16), r.iz, -r.oiz);
+    const int ni = (int)((hd.y >> 16) & 15u);   // internal children, in the first slots
+    const float tb = s.tb;
+    // per slot: the entry distance as an unsigned key (non-negative floats
+    // order as their bit patterns) with the slot in bits 8-9, all ones unless
+    // the slot is an internal child whose box the ray enters; hit leaf slots
+    // are queued by mask.  The build pads every box by a scene-relative
+    // margin far above the rounding of this form, so the test is conservative.
+    unsigned key[4];
     int lm = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        // empty slots hold inverted boxes, so a hit child is never empty
-        const bool hit = t[k] != __builtin_inff();
-        const bool leaf = c[k] < 0;
+        const float t0 = fmaxf(fmaxf(__builtin_fmaf(xn[k], r.ix, bx), __builtin_fmaf(yn[k], r.iy, by)),
+                               fmaxf(__builtin_fmaf(zn[k], r.iz, bz), 0.0f));
+        const float t1 = fminf(fminf(__builtin_fmaf(xf[k], r.ix, bx), __builtin_fmaf(yf[k], r.iy, by)),
+                               fminf(__builtin_fmaf(zf[k], r.iz, bz), tb));
+        const bool hit = t0 <= t1;   // unused slots hold inverted boxes
+        const bool leaf = k >= ni;
         lm |= (hit && leaf) ? (1 << k) : 0;
-        t[k] = leaf ? __builtin_inff() : t[k];
+        key[k] = (hit && !leaf) ? ((__float_as_uint(t0) & ~0x300u) | ((unsigned)k << 8)) : 0xFFFFFFFFu;
     }
-    s.lq0 = c[0];
-    s.lq1 = c[1];
-    s.lq2 = c[2];
-    s.lq3 = c[3];
     s.lmask = lm;
-    cswap(t[0], c[0], t[1], c[1]);
-    cswap(t[2], c[2], t[3], c[3]);
-    cswap(t[0], c[0], t[2], c[2]);
-    cswap(t[1], c[1], t[3], c[3]);
-    cswap(t[1], c[1], t[2], c[2]);
-    if (t[0] == __builtin_inff()) {
+    s.lrow = 3 * ((int)hd.w - ni);
+    // ascending sort of the four keys (five compare-exchanges)
+    const unsigned a0 = min(key[0], key[1]), a1 = max(key[0], key[1]);
+    const unsigned a2 = min(key[2], key[3]), a3 = max(key[2], key[3]);
+    const unsigned e0 = min(a0, a2), p2 = max(a0, a2);
+    const unsigned p1 = min(a1, a3), e3 = max(a1, a3);
+    const unsigned e1 = min(p1, p2), e2 = max(p1, p2);
+    const unsigned none = 0xFFFFFFFFu;
+    const int first = (int)hd.z;   // internal child in slot k: node first + k
+    if (e0 == none) {
         if (s.sp == 0) {
             s.node = -1;
         } else {
@@ -171,21 +154,24 @@ __device__ __forceinline__ void trav_step(const Ray& r, int skip, Trav& s, bool&
             s.node = s.sp < LDS_D ? lst[s.sp * 64] : gst[(s.sp - LDS_D) * 64];
         }
     } else {
-        s.node = c[0];
+        s.node = first + (int)((e0 >> 8) & 3u);
+        // the others far-to-near
+        const unsigned ek[3] = {e3, e2, e1};
         if (s.sp + 3 <= LDS_D) {
 #pragma unroll
-            for (int k = 3; k >= 1; --k) {
-                if (t[k] != __builtin_inff()) {
-                    lst[s.sp * 64] = c[k];
+            for (int k = 0; k < 3; ++k) {
+                if (ek[k] != none) {
+                    lst[s.sp * 64] = first + (int)((ek[k] >> 8) & 3u);
                     ++s.sp;
                 }
             }
         } else {
 #pragma unroll
-            for (int k = 3; k >= 1; --k) {
-                if (t[k] != __builtin_inff()) {
-                    if (s.sp < LDS_D) lst[s.sp * 64] = c[k];
-                    else gst[(s.sp - LDS_D) * 64] = c[k];
+            for (int k = 0; k < 3; ++k) {
+                if (ek[k] != none) {
+                    const int cv = first + (int)((ek[k] >> 8) & 3u);
+                    if (s.sp < LDS_D) lst[s.sp * 64] = cv;
+                    else gst[(s.sp - LDS_D) * 64] = cv;
                     ++s.sp;
                 }
             }
@@ -203,7 +189,7 @@ __device__ __forceinline__ void start_segment(Trav& s)
     s.sp = 0;
     s.steps = 0;
     s.lmask = 0;
-    s.lq0 = s.lq1 = s.lq2 = s.lq3 = 0;
+    s.lrow = 0;
 }
 
 // Emission (Alg. 1 "generate exitant ray"): origin y, direction, area
