@@ -36,14 +36,22 @@ FP32_PEAK_TFLOPS = 157.3
 # lanes x 2.4 GHz (the rate the traversal's comparisons and min/max can reach)
 UNPACKED_LANE_OPS_T = 256 * 4 * 16 * 2.4e9 / 1e12
 # Algorithmic work per unit (see the design notes): one node visit = four box
-# tests of 20 ops and a 128 B node (4-wide tree); one triangle test = 40 ops and
+# tests of 20 ops and a 64 B node (4-wide tree); one triangle test = 40 ops and
 # a 48 B record; one hit = an 80 B patch record plus an 8 B atomic (forward) or
 # a 4 B gather (adjoint).
 BOXES_PER_NODE, OPS_PER_BOX, OPS_PER_TRI = 4, 20, 40
 # the same work in VALU issue slots (an FMA is one slot): a box test is 6 FMA,
 # 6 min/max and 2 compares; a triangle test's 40 operations have no FMA
 SLOTS_PER_BOX, SLOTS_PER_TRI = 14, 40
-NODE_BYTES, TRI_BYTES, PATCH_BYTES = 128, 48, 80
+NODE_BYTES, TRI_BYTES, PATCH_BYTES = 64, 48, 80
+# Per-lane vector-memory requests (one 16 B row each): a node visit loads its
+# four rows, a triangle test three, a hit the five rows of its patch record
+# plus one atomic (forward) or one gather (adjoint).  Every lane's request
+# falls in a different cache line, and the counters (TA/TD busy ~100 %, one
+# TD cycle per lane request) show the vector-memory path serving one such
+# request per CU per clock: 256 CUs x 2.4 GHz.
+REQ_PER_NODE, REQ_PER_TRI, REQ_PER_HIT = 4, 3, 6
+VMEM_REQ_PEAK_G = 256 * 2.4e9 / 1e9
 
 
 def log(*a):
@@ -352,11 +360,14 @@ def throughput(name, args, paths=0, steps=None, warmup=None):
         (PATCH_BYTES + (4 if dominant == "adjoint" else 8)) * stats["hits"]
     tflops = ops / dur_s / 1e12
     gbs = byt / dur_s / 1e9
+    reqs = REQ_PER_NODE * stats["nodes"] + REQ_PER_TRI * stats["tri_tests"] + REQ_PER_HIT * stats["hits"]
     traffic = measured_traffic(name, dominant, ctx.get_tuning().as_dict(), N)
-    # The traversal is bound by VALU issue (the SQ counters in the committed
-    # profiles put its wave-level VALU instructions at ~80 % of the issue
-    # rate, while HBM carries ~10 % of its peak), so the roofline is the ALU
-    # one: algorithmic box and triangle operations against the FP32 vector peak.
+    # The traversal is bound on the chip's issue side, not by HBM (~10 % of
+    # its peak): the committed profiles show wave-level VALU issue at ~100 %
+    # of the wave64 rate and the vector-memory path (TA/TD) busy ~100 %, so
+    # the headline roofline is the ALU one (algorithmic box and triangle
+    # operations against the FP32 vector peak), with the per-lane request
+    # rate of the vector-memory path beside it.
     roofline = {"bound": "alu", "achieved": round(tflops, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
                 "kernel": f"k_trace ({dominant})", "kernel_ms": round(max(fwd_avg, adj_avg), 3),
@@ -366,6 +377,11 @@ def throughput(name, args, paths=0, steps=None, warmup=None):
                                    "note": f"algorithmic VALU issue slots (box test {SLOTS_PER_BOX}, triangle "
                                            f"test {SLOTS_PER_TRI}; an FMA is one slot) against one non-packed "
                                            "FP32 slot per lane per cycle, 256 CU x 4 SIMD x 16 lanes x 2.4 GHz"},
+                "vmem_requests": {"achieved": round(reqs / dur_s / 1e9, 1), "peak": round(VMEM_REQ_PEAK_G, 1),
+                                  "unit": "G lane-requests/s", "frac": round(reqs / dur_s / 1e9 / VMEM_REQ_PEAK_G, 4),
+                                  "per_launch": int(reqs),
+                                  "note": f"per-lane 16 B loads: {REQ_PER_NODE} per node visit, {REQ_PER_TRI} per "
+                                          f"triangle test, {REQ_PER_HIT} per hit; one per CU per clock, 256 CU x 2.4 GHz"},
                 "ops_per_launch": int(ops),
                 "hbm": {"achieved": None if traffic is None else round(traffic / dur_s / 1e9, 1),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
