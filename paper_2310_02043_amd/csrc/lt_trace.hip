@@ -202,12 +202,12 @@ __device__ __forceinline__ void start_segment(Trav& s)
 // the density it was drawn from: the adjoint histogram adds |c_r / sigma|^2 wq,
 // whose expectation per cell does not depend on the sampler and is
 // proportional to the square of the variance-optimal cell probability.
-__device__ __forceinline__ void emit(const DevLight& L, uint32_t pid, uint32_t stream_id, uint32_t k0, uint32_t k1,
-                                     const float* __restrict__ pdf, const float* __restrict__ cdf,
-                                     const int* __restrict__ guide, float alpha, bool want_bin, V3& y, V3& dir,
-                                     float& au, float& av, float& phi, int& ebin, float& wq)
+// r: the path's generator output at counter (pid, stream, 0, 0).
+__device__ __forceinline__ void emit_from(const DevLight& L, const U4 r, uint32_t pid, uint32_t stream_id, uint32_t k0,
+                                          uint32_t k1, const float* __restrict__ pdf, const float* __restrict__ cdf,
+                                          const int* __restrict__ guide, float alpha, bool want_bin, V3& y, V3& dir,
+                                          float& au, float& av, float& phi, int& ebin, float& wq)
 {
-    const U4 r = philox10(pid, stream_id, 0u, 0u, k0, k1);
     const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
     y = v3(L.c[0], L.c[1], L.c[2]);
     au = 0.0f;
@@ -314,6 +314,15 @@ __device__ __forceinline__ void emit(const DevLight& L, uint32_t pid, uint32_t s
         y = v3((L.c[0] + au * L.t[0]) + av * L.b[0], (L.c[1] + au * L.t[1]) + av * L.b[1],
                (L.c[2] + au * L.t[2]) + av * L.b[2]);
     }
+}
+
+__device__ __forceinline__ void emit(const DevLight& L, uint32_t pid, uint32_t stream_id, uint32_t k0, uint32_t k1,
+                                     const float* __restrict__ pdf, const float* __restrict__ cdf,
+                                     const int* __restrict__ guide, float alpha, bool want_bin, V3& y, V3& dir,
+                                     float& au, float& av, float& phi, int& ebin, float& wq)
+{
+    emit_from(L, philox10(pid, stream_id, 0u, 0u, k0, k1), pid, stream_id, k0, k1, pdf, cdf, guide, alpha, want_bin, y,
+              dir, au, av, phi, ebin, wq);
 }
 
 // Cosine-weighted bounce about the oriented normal (Malley's method in the
@@ -608,7 +617,11 @@ __device__ __forceinline__ T wave_sum(T v)
 // rotation-vector orientation (seven derivatives), 5 the direct-differentiation map of one luminaire (forward only), 6 the
 // soft-edged spots' cone angles (adjoint, eight derivatives).
 template <bool ADJ, bool STATS, int WPB, int LDS_D, int MODE>
-__global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(MODE >= 30 ? 4 : 5))) k_trace(TraceArgs a)
+// Occupancy floor per instance: the plain forward pass fits seven waves per
+// SIMD (72 VGPRs, no spill), the other instances five, the directional ones
+// four.
+__global__ void __launch_bounds__(WPB * 64)
+    __attribute__((amdgpu_waves_per_eu(MODE >= 30 ? 4 : (!ADJ && !STATS && MODE == 0 ? 7 : 5)))) k_trace(TraceArgs a)
 {
     constexpr bool DIR = MODE >= 30;               // directional texels of order MODE - 30
     constexpr int DORD = DIR ? MODE - 30 : 0;
@@ -705,39 +718,60 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(M
         start_segment(s);
         set_ray(r, v3(0, 0, 0), v3(0, 0, 1));
 
+        // a lane that bounced at the last hit keeps its oriented normal (and
+        // its ray and hit distance, which give the hit point) until the
+        // phase's shared ray generation
+        bool bnc = false;
+        V3 bn = v3(0, 0, 1);
         for (;;) {
             // refill lanes without a path (ballot + prefix count)
             const bool need = !alive;
             const uint64_t m = ballot(need);
+            bool newp = false;
             if (m != 0 && next < count) {
                 const int slot = next + lanes_below(m);
                 if (need && slot < count) {
                     pid = first + (uint32_t)slot;
-                    V3 y, dir;
-                    emit(L, pid, stream_id, a.key0, a.key1, pdf, cdf, guide, a.alpha_plain, hist != nullptr, y, dir, au, av,
-                         phi_r, ebin, wq);
-                    set_ray(r, y, dir);
-                    start_segment(s);
-                    alive = true;
-                    trav = true;
-                    h = 0;
-                    skip = -1;
-                    T = 1.0f;
-                    s_r = 0.0f;
-                    if (MODE == 2) {
-                        rgbs[0] = 1.0f;
-                        rgbs[64] = 1.0f;
-                        rgbs[128] = 0.0f;
-                        rgbs[192] = 0.0f;
-                    }
-                    if (DIR && ADJ) {
-                        dst[0] = 1.0f;
-#pragma unroll
-                        for (int c = 1; c < 8; ++c) dst[c * 64] = 0.0f;
-                    }
-                    if (STATS) ++n_seg;
+                    newp = true;
                 }
                 next += __popcll(m);
+            }
+            // every lane starting a segment, a new path or a bounce, draws its
+            // generator block once here: counter 0 for the emission, 1 + h for
+            // the bounce after hit h
+            if (newp || bnc) {
+                const U4 ru = philox10(pid, stream_id, newp ? 0u : 1u + (uint32_t)h, 0u, a.key0, a.key1);
+                V3 y, dir;
+                if (newp) {
+                    emit_from(L, ru, pid, stream_id, a.key0, a.key1, pdf, cdf, guide, a.alpha_plain, hist != nullptr, y,
+                              dir, au, av, phi_r, ebin, wq);
+                } else {
+                    y = v3(r.ox + s.tb * r.dx, r.oy + s.tb * r.dy, r.oz + s.tb * r.dz);   // as in hit_info
+                    dir = cosine_dir(bn, u24(ru.x), u24(ru.y));
+                }
+                set_ray(r, y, dir);
+                start_segment(s);
+                trav = true;
+                bnc = false;
+            }
+            if (newp) {
+                alive = true;
+                h = 0;
+                skip = -1;
+                T = 1.0f;
+                s_r = 0.0f;
+                if (MODE == 2) {
+                    rgbs[0] = 1.0f;
+                    rgbs[64] = 1.0f;
+                    rgbs[128] = 0.0f;
+                    rgbs[192] = 0.0f;
+                }
+                if (DIR && ADJ) {
+                    dst[0] = 1.0f;
+#pragma unroll
+                    for (int c = 1; c < 8; ++c) dst[c * 64] = 0.0f;
+                }
+                if (STATS) ++n_seg;
             }
             // lanes holding a path: fixed while the traversal loop runs
             const uint64_t am = ballot(alive);
@@ -925,6 +959,20 @@ __global__ void __launch_bounds__(WPB * 64) __attribute__((amdgpu_waves_per_eu(M
                     }
                     if (h >= B) {
                         end_path = true;
+                    } else if (!DIR) {
+                        // the new direction is drawn with the phase's emissions
+                        bnc = true;
+                        bn = hi.no;
+                        skip = s.qb;
+                        if (MODE == 2) {
+                            const float4 rho = a.rho_rgb[skip];
+                            T = T * rho.x;
+                            rgbs[0] = rgbs[0] * rho.y;
+                            rgbs[64] = rgbs[64] * rho.z;
+                        } else {
+                            T = T * hi.rho;
+                        }
+                        if (STATS) ++n_seg;
                     } else {
                         const V3 nd = bounce_dir(hi.no, pid, stream_id, (uint32_t)h, a.key0, a.key1);
                         set_ray(r, hi.x, nd);
