@@ -425,6 +425,69 @@ def test_edge_cases(torch_dev, oracle_lib, case):
         assert out["S_ref"].sum() > 0
 
 
+def _translated(scene, off):
+    """The same scene moved by off (vertices and patch origins)."""
+    import dataclasses
+    patches = scene.patches.copy()
+    patches["origin"] = (patches["origin"].astype(np.float64) + off).astype(np.float32)
+    verts = (scene.verts.astype(np.float64) + off).astype(np.float32)
+    return dataclasses.replace(scene, verts=verts, patches=patches)
+
+
+def _two_far_rooms(dx):
+    """Two closed box rooms dx apart along x, one spot in each."""
+    import dataclasses
+    a = li.box_room()["scene"]
+    b = _translated(a, np.array([dx, 0.0, 0.0]))
+    patches = np.concatenate([a.patches, b.patches])
+    patches["texel_base"][a.n_patches:] += a.n_texels
+    return dataclasses.replace(a, name="two_far_rooms", verts=np.concatenate([a.verts, b.verts]),
+                               tris=np.concatenate([a.tris, b.tris + a.verts.shape[0]]),
+                               tri_patch=np.concatenate([a.tri_patch, b.tri_patch + a.n_patches]),
+                               patches=patches, n_texels=2 * a.n_texels)
+
+
+@pytest.mark.parametrize("case", ["office_far_from_origin", "rooms_90km_apart"])
+def test_compact_node_precision(torch_dev, oracle_lib, case):
+    """The wide nodes keep child planes as f16 offsets from a bf16 origin,
+    rounded outward.  Scenes that stress that encoding must still give the
+    oracle's hits: an office of 20k triangles moved 4.6 km from the origin
+    (bf16 origin steps of 16-32 m, f16 offsets up to tens of metres), and two
+    rooms 90 km apart (the root's offsets beyond the f16 range, stored as
+    65504 / +inf).  Texels, gradients and sampled hit sequences vs the oracle."""
+    torch = torch_dev
+    if case == "office_far_from_origin":
+        c = li.office(target_tris=20_000, target_texels=200_000, n_lights=4)
+        off = np.array([4096.3, -2048.7, 517.1])
+        sc = _translated(c["scene"], off)
+        prm = c["lights"].params.astype(np.float64)
+        prm[:, :3] += off
+        lights = make_lights([RECT] * 4, c["lights"].static["lobe_n"], [(0.6, 0.6)] * 4, [0] * 4,
+                             prm.astype(np.float32))
+        ppl, B, use_bvh = 1 << 16, 4, True
+    else:
+        sc = _two_far_rooms(90_000.0)
+        lights = make_lights([SPOT, SPOT], [3.0, 2.0], [(0, 0), (0, 0)], [0, 0],
+                             [[1.0, 1.0, 2.0, 0.1, 0.2, 50.0], [90_002.0, 1.5, 2.2, -0.1, 0.2, 40.0]])
+        ppl, B, use_bvh = 1 << 16, 3, False
+    say("compact-node precision case", case, sc.n_tris, "triangles")
+    out = run_case(torch, oracle_lib, sc, lights, lights.params, 0xC0DE, ppl, B, use_bvh=use_bvh)
+    ctx, p_d = out["ctx"], out["p_d"]
+    cfg = ctx.cfg(0xC0DE, ppl, B)
+    g = out["g_ref"]
+    n_same = n_tot = 0
+    for l in range(lights.n_lights):
+        prim_d, tex_d, _ = ctx.record_paths(p_d, cfg, 0, l, 0, 2048, dOdE=torch.tensor(g, device="cuda"))
+        prim_r, tex_r, _ = oracle_lib.record(out["osc"], out["ol"], lights.params, 0xC0DE, ppl, B, 0, l, 0, 2048,
+                                             dOdE=g)
+        same = np.all(prim_d.cpu().numpy() == prim_r, 1) & np.all(tex_d.cpu().numpy() == tex_r, 1)
+        n_same += int(same.sum())
+        n_tot += same.size
+    say(f"  identical hit sequences: {n_same}/{n_tot}")
+    assert n_same / n_tot >= PATH_BAR
+    assert out["S_ref"].sum() > 0
+
+
 def test_invalid_arguments_raise(torch_dev):
     torch = torch_dev
     from paper_2310_02043_amd.native import LtError
