@@ -798,20 +798,62 @@ static void local_frame(const float* no, float* b1, float* b2)
     b2[0] = bxy; b2[1] = sign + (no[1] * no[1]) * a; b2[2] = -no[1];
 }
 
-static void trace_path(const or_scene* S, const olight* L, int layout, int l_local, int gl, uint32_t i, uint64_t seed,
-                       int B, const or_proposal* prop_in, path_io* io)
+/* The state a light path carries from hit to hit. */
+typedef struct {
+    float o[3], dir[3];    /* current ray */
+    int32_t skip;          /* patch the ray leaves (never hit again by it) */
+    float y[3];            /* emission point */
+    float au, av;          /* area light: the emission point's offsets along t and b */
+    float phi_r;           /* flux the path carries from the light (Phi_r) */
+    int ebin;              /* proposal: cell of the emission direction (or -1) */
+    float wq;              /* proposal: density of the emission over its cell's (u, v) measure */
+    float T;               /* throughput, Phi_h / Phi_r */
+    float Tc[3];           /* colour: channel throughputs */
+    float s_r;             /* adjoint: sum over hits of g_k Phi_h / (A_k Phi_r) */
+    float sc[3];           /* colour adjoint: the same per channel */
+    float dphi[8];         /* adjoint: Phi_r dlog/dp_j of the first hit */
+    float tdl;             /* direct differentiation: dlog/dp_j of the first hit */
+    int hits;
+    int64_t k1;            /* texel of the first hit */
+    /* directional texels: T2 the bounce-weight product after the first hit,
+     * Rd the adjoint sum of the later hits weighted by it, Qw / Dw the
+     * first hit's projection and bounce-weight derivatives w.r.t. the
+     * incident direction, om1 / inv_r1 that direction and 1 / distance, and
+     * the current hit's incident direction and local frame */
+    float T2, Rd;
+    float Qw[3], Dw[3], om1[3], inv_r1;
+    float wi_loc[3], fb1[3], fb2[3];
+} path_state;
+
+/* A surface hit: position, the normal facing the incident ray, patch, texel
+ * (box basis) and, for the piecewise-linear basis, the four nodes and their
+ * bilinear weights. */
+typedef struct {
+    float x[3], no[3];
+    int32_t q;
+    const float* pf;       /* the patch's float record */
+    int64_t k;
+    float inv_a;
+    int64_t kb[4];
+    float wb[4];
+} hit_point;
+
+/* Emission (Alg. 1 "generate exitant ray"): origin y, direction, flux
+ * Phi_r; with a proposal the direction comes from the plain cos^n lobe with
+ * probability alpha, else from the binned proposal, and Phi_r = (P/N)
+ * p_plain / q (one-sample MIS). */
+static void emit_path(const olight* L, uint64_t seed, uint32_t i, uint32_t stream, int gl, const or_proposal* prop,
+                      path_state* ps)
 {
-    const uint32_t stream = ((uint32_t)layout << 16) | (uint32_t)l_local;
-    const or_proposal* prop = (prop_in && prop_in->pdf && (L->type == 1 || L->type == 2)) ? prop_in : NULL;
-    float phi_r = L->phi_r;
-    int ebin = -1;
-    float wq = 0.0f;
+    ps->phi_r = L->phi_r;
+    ps->ebin = -1;
+    ps->wq = 0.0f;
     float u[4];
     draw4(seed, i, stream, 0u, u);
-    /* emission: origin y, direction w0 (Alg. 1 "generate exitant ray") */
-    float y[3] = {L->c[0], L->c[1], L->c[2]};
-    float dir[3];
-    float au = 0.0f, av = 0.0f;
+    for (int c = 0; c < 3; ++c) ps->y[c] = L->c[c];
+    ps->au = 0.0f;
+    ps->av = 0.0f;
+    float* dir = ps->dir;
     if (L->type == 0) {
         float z = 1.0f - 2.0f * u[2];
         float rr = sqrtf(fmaxf(0.0f, 1.0f - z * z));
@@ -827,7 +869,7 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
         float a = st * cp, bb = st * sp;
         if (ct < L->ci) {
             float f = (ct - L->co) / (L->ci - L->co);
-            phi_r = phi_r * (f * f);
+            ps->phi_r = ps->phi_r * (f * f);
         }
         for (int c = 0; c < 3; ++c) dir[c] = (a * L->t[c] + bb * L->b[c]) + ct * L->d[c];
     } else {
@@ -838,14 +880,14 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
         or_sincos2pi(u[3], &sp, &cp);
         float a = st * cp, bb = st * sp;
         if (prop) {
-            /* one-sample MIS between the plain lobe (probability alpha) and
-             * the binned proposal; Phi_r = (P/N) p_plain / q */
             float w[4];
             draw4(seed, i, stream, 1u, w);
             const float* pdf = prop->pdf + 1024 * (int64_t)gl;
             const float* cdf = prop->cdf + 1024 * (int64_t)gl;
             float lz, pl3;
             if (w[0] < prop->alpha) {
+                /* the plain lobe's direction, and its cell of the
+                 * hemi-octahedral map */
                 lz = ct;
                 float s = (fabsf(a) + fabsf(bb)) + lz;
                 float xp = a / s, yp = bb / s;
@@ -855,16 +897,17 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
                 if (iu > 31) iu = 31;
                 if (iv < 0) iv = 0;
                 if (iv > 31) iv = 31;
-                ebin = iv * 32 + iu;
+                ps->ebin = iv * 32 + iu;
                 pl3 = 1.0f / ((s * s) * s);
             } else {
+                /* a cell by inverse CDF, a uniform point in it */
                 int lo = 0, hi = 1023;
                 while (lo < hi) {
                     int mid = (lo + hi) >> 1;
                     if (w[1] < cdf[mid]) hi = mid;
                     else lo = mid + 1;
                 }
-                ebin = lo;
+                ps->ebin = lo;
                 float uu = -1.0f + ((float)(lo & 31) + w[2]) * 0.0625f;
                 float vv = -1.0f + ((float)(lo >> 5) + w[3]) * 0.0625f;
                 float xp = (uu + vv) * 0.5f, yp = (uu - vv) * 0.5f;
@@ -880,281 +923,272 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
             float pw = 1.0f;
             if (L->n != 0.0f) pw = lz > 0.0f ? or_exp2(L->n * or_log2(lz)) : 0.0f;
             float p_plain = ((L->n + 1.0f) * (float)0.15915494309189533577) * pw;
-            float p_learn = (pdf[ebin] * 512.0f) * pl3;
+            float p_learn = (pdf[ps->ebin] * 512.0f) * pl3;
             float q = prop->alpha * p_plain + (1.0f - prop->alpha) * p_learn;
-            phi_r = q > 0.0f ? phi_r * (p_plain / q) : 0.0f;
-            /* the sampling density over the (u, v) measure of the cell */
-            wq = q / (512.0f * pl3);
+            ps->phi_r = q > 0.0f ? ps->phi_r * (p_plain / q) : 0.0f;
+            ps->wq = q / (512.0f * pl3);
         }
         for (int c = 0; c < 3; ++c) dir[c] = (a * L->t[c] + bb * L->b[c]) + ct * L->d[c];
         if (L->type == 2) {
-            au = (u[0] - 0.5f) * L->w;
-            av = (u[1] - 0.5f) * L->h;
-            for (int c = 0; c < 3; ++c) y[c] = (L->c[c] + au * L->t[c]) + av * L->b[c];
+            ps->au = (u[0] - 0.5f) * L->w;
+            ps->av = (u[1] - 0.5f) * L->h;
+            for (int c = 0; c < 3; ++c) ps->y[c] = (L->c[c] + ps->au * L->t[c]) + ps->av * L->b[c];
         }
     }
-    float o[3] = {y[0], y[1], y[2]};
-    int32_t skip = -1;
-    float T = 1.0f;
-    float s_r = 0.0f;
-    float dphi[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+}
+
+/* The hit point of the ray at distance t on triangle prim: its patch, texel
+ * (box basis), piecewise-linear nodes (Eq. pwLin on the texel grid: nodes at
+ * the texel centres, bilinear hats clamped at the patch border so that they
+ * sum to one; the mass-lumped weight of every node is the texel area,
+ * supplement Eq. appdxSpatialCoeffs) and the normal facing the ray. */
+static void locate_hit(const or_scene* S, const float* o, const float* dir, float t, int64_t prim, hit_point* hp)
+{
+    for (int c = 0; c < 3; ++c) hp->x[c] = o[c] + t * dir[c];
+    const int32_t q = S->tri_patch[prim];
+    const float* pf = S->pf + 17 * (int64_t)q;
+    hp->q = q;
+    hp->pf = pf;
+    float du[3] = {hp->x[0] - pf[0], hp->x[1] - pf[1], hp->x[2] - pf[2]};
+    float su = dot3(du, pf + 3) * pf[12];
+    float sv = dot3(du, pf + 6) * pf[13];
+    int32_t ru = S->pres[2 * q], rv = S->pres[2 * q + 1];
+    int32_t iu = (int32_t)floorf(su * (float)ru);
+    int32_t iv = (int32_t)floorf(sv * (float)rv);
+    if (iu < 0) iu = 0;
+    if (iu > ru - 1) iu = ru - 1;
+    if (iv < 0) iv = 0;
+    if (iv > rv - 1) iv = rv - 1;
+    hp->k = S->pbase[q] + (int64_t)iv * ru + iu;
+    hp->inv_a = pf[15];
+    if (S->basis == 1) {
+        float fu = su * (float)ru - 0.5f, fv = sv * (float)rv - 0.5f;
+        float fu0 = floorf(fu), fv0 = floorf(fv);
+        float au1 = fu - fu0, av1 = fv - fv0;
+        float au0 = 1.0f - au1, av0 = 1.0f - av1;
+        int32_t i0 = (int32_t)fu0, j0 = (int32_t)fv0;
+        int32_t i1 = i0 + 1, j1 = j0 + 1;
+        i0 = i0 < 0 ? 0 : (i0 > ru - 1 ? ru - 1 : i0);
+        i1 = i1 < 0 ? 0 : (i1 > ru - 1 ? ru - 1 : i1);
+        j0 = j0 < 0 ? 0 : (j0 > rv - 1 ? rv - 1 : j0);
+        j1 = j1 < 0 ? 0 : (j1 > rv - 1 ? rv - 1 : j1);
+        hp->kb[0] = S->pbase[q] + (int64_t)j0 * ru + i0; hp->wb[0] = au0 * av0;
+        hp->kb[1] = S->pbase[q] + (int64_t)j0 * ru + i1; hp->wb[1] = au1 * av0;
+        hp->kb[2] = S->pbase[q] + (int64_t)j1 * ru + i0; hp->wb[2] = au0 * av1;
+        hp->kb[3] = S->pbase[q] + (int64_t)j1 * ru + i1; hp->wb[3] = au1 * av1;
+    }
+    const float* nq = pf + 9;
+    float nd = dot3(nq, dir);
+    if (nd < 0.0f) { hp->no[0] = nq[0]; hp->no[1] = nq[1]; hp->no[2] = nq[2]; }
+    else { hp->no[0] = -nq[0]; hp->no[1] = -nq[1]; hp->no[2] = -nq[2]; }
+}
+
+static void splat(int64_t* S, int64_t k, float val)
+{
+    long long code = llrintf(val * 4294967296.0f);
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+    S[k] += code;
+}
+
+/* Directional texels at hit h: exitant radiance coefficients (HSH of order
+ * dir_order, N' local samples of the BRDF lobe) splatted, and for the
+ * adjoint the projected dO/dL sum and, at the first hit, the BRDF terms
+ * that move with the incident direction. */
+static void directional_hit(const or_scene* S, const olight* L, uint64_t seed, uint32_t i, uint32_t stream, int h,
+                            const hit_point* hp, path_io* io, path_state* ps)
+{
+    const int64_t K = S->n_texels, k = hp->k;
+    const int NC = (S->dir_order + 1) * (S->dir_order + 1);
+    const float inv_np = 1.0f / (float)S->dir_samples;
     const int NP = L->rv ? 7 : (L->cone ? 8 : 6);
-    float tdl = 0.0f;      /* direct differentiation: dlog_j of the first hit */
-    int hits = 0;
-    int64_t k1 = -1;
-    /* colour mode: channel ch carries flux Phi_r col[ch] and throughput Tc[ch];
-     * texel arrays are channel-planar, [3, K] per layout */
-    float Tc[3] = {1.0f, 1.0f, 1.0f};
-    float sc[3] = {0.0f, 0.0f, 0.0f};
-    const int64_t K = S->n_texels;
-    /* directional mode: exitant radiance coefficients per texel; the bounce
-     * weight is pi f; the adjoint also carries the BRDF terms of the first
-     * hit (its projection and its bounce weight depend on the incident
-     * direction, which moves with the light while x_1 stays fixed) */
-    const int dirm = S->dir_order >= 0;
-    const int NC = dirm ? (S->dir_order + 1) * (S->dir_order + 1) : 1;
-    const float inv_np = dirm ? 1.0f / (float)S->dir_samples : 0.0f;
-    float T2 = 1.0f, Rd = 0.0f;
-    float Qw[3] = {0, 0, 0}, Dw[3] = {0, 0, 0}, om1[3] = {0, 0, 0}, inv_r1 = 0.0f;
-    float wi_loc[3] = {0, 0, 0}, fb1[3] = {0, 0, 0}, fb2[3] = {0, 0, 0};
-    for (int h = 1; h <= B; ++h) {
-        float t;
-        int64_t prim = intersect(S, o, dir, skip, &t);
-        if (prim < 0) {
-            io->misses++;
-            break;
-        }
-        hits = h;
-        float x[3];
-        for (int c = 0; c < 3; ++c) x[c] = o[c] + t * dir[c];
-        int32_t q = S->tri_patch[prim];
-        const float* pf = S->pf + 17 * (int64_t)q;
-        float du[3] = {x[0] - pf[0], x[1] - pf[1], x[2] - pf[2]};
-        float su = dot3(du, pf + 3) * pf[12];
-        float sv = dot3(du, pf + 6) * pf[13];
-        int32_t ru = S->pres[2 * q], rv = S->pres[2 * q + 1];
-        int32_t iu = (int32_t)floorf(su * (float)ru);
-        int32_t iv = (int32_t)floorf(sv * (float)rv);
-        if (iu < 0) iu = 0;
-        if (iu > ru - 1) iu = ru - 1;
-        if (iv < 0) iv = 0;
-        if (iv > rv - 1) iv = rv - 1;
-        int64_t k = S->pbase[q] + (int64_t)iv * ru + iu;
-        float inv_a = pf[15];
-        /* piecewise-linear basis (Eq. pwLin on the texel grid): nodes at the
-         * texel centres, bilinear hats clamped at the patch border so that
-         * they sum to one; the mass-lumped weight of every node is the texel
-         * area (supplement Eq. appdxSpatialCoeffs) */
-        int64_t kb[4];
-        float wb[4];
-        if (S->basis == 1) {
-            float fu = su * (float)ru - 0.5f, fv = sv * (float)rv - 0.5f;
-            float fu0 = floorf(fu), fv0 = floorf(fv);
-            float au1 = fu - fu0, av1 = fv - fv0;
-            float au0 = 1.0f - au1, av0 = 1.0f - av1;
-            int32_t i0 = (int32_t)fu0, j0 = (int32_t)fv0;
-            int32_t i1 = i0 + 1, j1 = j0 + 1;
-            i0 = i0 < 0 ? 0 : (i0 > ru - 1 ? ru - 1 : i0);
-            i1 = i1 < 0 ? 0 : (i1 > ru - 1 ? ru - 1 : i1);
-            j0 = j0 < 0 ? 0 : (j0 > rv - 1 ? rv - 1 : j0);
-            j1 = j1 < 0 ? 0 : (j1 > rv - 1 ? rv - 1 : j1);
-            kb[0] = S->pbase[q] + (int64_t)j0 * ru + i0; wb[0] = au0 * av0;
-            kb[1] = S->pbase[q] + (int64_t)j0 * ru + i1; wb[1] = au1 * av0;
-            kb[2] = S->pbase[q] + (int64_t)j1 * ru + i0; wb[2] = au0 * av1;
-            kb[3] = S->pbase[q] + (int64_t)j1 * ru + i1; wb[3] = au1 * av1;
-        }
-        const float* nq = pf + 9;
-        float nd = dot3(nq, dir);
-        float no[3];
-        if (nd < 0.0f) { no[0] = nq[0]; no[1] = nq[1]; no[2] = nq[2]; }
-        else { no[0] = -nq[0]; no[1] = -nq[1]; no[2] = -nq[2]; }
-        if (dirm) {
-            const float* gl_ = S->glossy ? S->glossy + 2 * (int64_t)q : NULL;
-            float rs = gl_ ? gl_[0] : 0.0f, ex = gl_ ? gl_[1] : 1.0f;
-            local_frame(no, fb1, fb2);
-            float wiw[3] = {-dir[0], -dir[1], -dir[2]};
-            wi_loc[0] = dot3(fb1, wiw); wi_loc[1] = dot3(fb2, wiw); wi_loc[2] = dot3(no, wiw);
-            float acc_c[16] = {0};
-            float pd = 0.0f, ql[3] = {0, 0, 0};
-            for (int j = 0; j < S->dir_samples; ++j) {
-                float us[4];
-                draw4(seed, i, stream, or_dir_block((uint32_t)h, (uint32_t)j), us);
-                float ua = (j & 1) ? us[2] : us[0], ub = (j & 1) ? us[3] : us[1];
-                float ct = ua;
-                float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
-                float sp, cp;
-                or_sincos2pi(ub, &sp, &cp);
-                float wo[3] = {st * cp, st * sp, ct};
-                float H[16];
-                or_hsh(S->dir_order, ct, cp, sp, H);
-                float gr[3];
-                float f = or_brdf(pf[16], rs, ex, wi_loc, wo, (io->g && h == 1) ? gr : NULL);
-                if (io->S)
-                    for (int c = 0; c < NC; ++c) acc_c[c] = acc_c[c] + f * H[c];
-                if (io->g) {
-                    float G = 0.0f;
-                    for (int c = 0; c < NC; ++c) G = G + io->g[c * K + k] * H[c];
-                    pd = pd + f * G;
-                    if (h == 1)
-                        for (int c = 0; c < 3; ++c) ql[c] = ql[c] + G * gr[c];
-                }
-            }
-            if (io->S) {
-                float base = (phi_r * T) * inv_a;
-                for (int c = 0; c < NC; ++c) {
-                    long long code = llrintf(((base * acc_c[c]) * inv_np) * 4294967296.0f);
-#ifdef _OPENMP
-#pragma omp atomic
-#endif
-                    io->S[c * K + k] += code;
-                }
-            }
-            if (io->g) {
-                float P = (pd * inv_np) * inv_a;
-                s_r = s_r + P * T;
-                if (h >= 2) Rd = Rd + P * T2;
-                if (h == 1) {
-                    k1 = k;
-                    float dl[8];
-                    first_hit_dlog(L, x, y, no, au, av, dl);
-                    for (int c = 0; c < NP; ++c) dphi[c] = phi_r * dl[c];
-                    float sq = (inv_np * inv_a);
-                    for (int c = 0; c < 3; ++c) Qw[c] = ((ql[0] * sq) * fb1[c] + (ql[1] * sq) * fb2[c]) + (ql[2] * sq) * no[c];
-                    float v1[3] = {y[0] - x[0], y[1] - x[1], y[2] - x[2]};
-                    float r1 = sqrtf(dot3(v1, v1));
-                    inv_r1 = 1.0f / r1;
-                    for (int c = 0; c < 3; ++c) om1[c] = v1[c] * inv_r1;
-                }
-            }
-        } else if (io->S && L->rgb) {
-            for (int ch = 0; ch < 3; ++ch) {
-                float val = ((phi_r * L->col[ch]) * Tc[ch]) * inv_a;
-                long long code = llrintf(val * 4294967296.0f);
-#ifdef _OPENMP
-#pragma omp atomic
-#endif
-                io->S[ch * K + k] += code;
-            }
-        } else if (io->S) {
-            float val = (phi_r * T) * inv_a;
-            if (S->basis == 1) {
-                for (int c = 0; c < 4; ++c) {
-                    long long code = llrintf((val * wb[c]) * 4294967296.0f);
-#ifdef _OPENMP
-#pragma omp atomic
-#endif
-                    io->S[kb[c]] += code;
-                }
-            } else {
-                long long code = llrintf(val * 4294967296.0f);
-#ifdef _OPENMP
-#pragma omp atomic
-#endif
-                io->S[k] += code;
-            }
-        }
-        if (io->tangent) {
-            /* direct (forward-mode) differentiation with x_1 held fixed: every
-             * hit of the path adds d(Phi_h / A)/dp_j = (Phi_h / A) dlog_j of
-             * its first hit, in its own texel */
-            if (h == 1) {
-                float dl[8];
-                first_hit_dlog(L, x, y, no, au, av, dl);
-                tdl = dl[io->tangent_param];
-            }
-            long long code = llrintf((((phi_r * T) * inv_a) * tdl) * 4294967296.0f);
-#ifdef _OPENMP
-#pragma omp atomic
-#endif
-            io->tangent[k] += code;
-        }
-        if (io->g && !dirm) {
-            if (L->rgb) {
-                for (int ch = 0; ch < 3; ++ch) sc[ch] = sc[ch] + (io->g[ch * K + k] * inv_a) * Tc[ch];
-            } else {
-                float gk = io->g[k];
-                if (S->basis == 1)
-                    gk = ((wb[0] * io->g[kb[0]] + wb[1] * io->g[kb[1]]) + wb[2] * io->g[kb[2]]) +
-                         wb[3] * io->g[kb[3]];
-                s_r = s_r + (gk * inv_a) * T;
-            }
-            if (h == 1) {
-                k1 = k;
-                float dl[8];
-                first_hit_dlog(L, x, y, no, au, av, dl);
-                for (int c = 0; c < NP; ++c) dphi[c] = phi_r * dl[c];
-            }
-        }
-        if (io->rec_prim) {
-            io->rec_prim[h - 1] = (int32_t)prim;
-            io->rec_texel[h - 1] = (int32_t)k;
-        }
-        if (h == B) break;
-        /* cosine-weighted bounce about the oriented normal (Malley's method in
-         * the Duff et al. 2017 orthonormal basis); Phi_{i+1} = Phi_i rho. */
-        float ub[4];
-        draw4(seed, i, stream, 1u + (uint32_t)h, ub);
-        float sign = copysignf(1.0f, no[2]);
-        float a = -1.0f / (sign + no[2]);
-        float bxy = (no[0] * no[1]) * a;
-        float b1[3] = {1.0f + ((sign * no[0]) * no[0]) * a, sign * bxy, -(sign * no[0])};
-        float b2[3] = {bxy, sign + (no[1] * no[1]) * a, -no[1]};
-        float rr = sqrtf(ub[0]);
+    const float* gl_ = S->glossy ? S->glossy + 2 * (int64_t)hp->q : NULL;
+    float rs = gl_ ? gl_[0] : 0.0f, ex = gl_ ? gl_[1] : 1.0f;
+    local_frame(hp->no, ps->fb1, ps->fb2);
+    float wiw[3] = {-ps->dir[0], -ps->dir[1], -ps->dir[2]};
+    ps->wi_loc[0] = dot3(ps->fb1, wiw); ps->wi_loc[1] = dot3(ps->fb2, wiw); ps->wi_loc[2] = dot3(hp->no, wiw);
+    float acc_c[16] = {0};
+    float pd = 0.0f, ql[3] = {0, 0, 0};
+    for (int j = 0; j < S->dir_samples; ++j) {
+        float us[4];
+        draw4(seed, i, stream, or_dir_block((uint32_t)h, (uint32_t)j), us);
+        float ua = (j & 1) ? us[2] : us[0], ub = (j & 1) ? us[3] : us[1];
+        float ct = ua;
+        float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
         float sp, cp;
-        or_sincos2pi(ub[1], &sp, &cp);
-        float lx = rr * cp, ly = rr * sp;
-        float lz = sqrtf(fmaxf(0.0f, 1.0f - ub[0]));
-        for (int c = 0; c < 3; ++c) dir[c] = (lx * b1[c] + ly * b2[c]) + lz * no[c];
-        for (int c = 0; c < 3; ++c) o[c] = x[c];
-        skip = q;
-        if (dirm) {
-            const float* gl_ = S->glossy ? S->glossy + 2 * (int64_t)q : NULL;
-            float wo[3] = {dot3(fb1, dir), dot3(fb2, dir), dot3(no, dir)};
-            float gr[3];
-            float fbv = or_brdf(pf[16], gl_ ? gl_[0] : 0.0f, gl_ ? gl_[1] : 1.0f, wi_loc, wo, gr);
-            float wb = fbv * 3.14159265358979f;
-            if (h == 1) {
-                for (int c = 0; c < 3; ++c)
-                    Dw[c] = ((gr[0] * 3.14159265358979f) * fb1[c] + (gr[1] * 3.14159265358979f) * fb2[c]) +
-                            (gr[2] * 3.14159265358979f) * no[c];
-            } else {
-                T2 = T2 * wb;
-            }
-            T = T * wb;
-        } else {
-            T = T * pf[16];
+        or_sincos2pi(ub, &sp, &cp);
+        float wo[3] = {st * cp, st * sp, ct};
+        float H[16];
+        or_hsh(S->dir_order, ct, cp, sp, H);
+        float gr[3];
+        float f = or_brdf(hp->pf[16], rs, ex, ps->wi_loc, wo, (io->g && h == 1) ? gr : NULL);
+        if (io->S)
+            for (int c = 0; c < NC; ++c) acc_c[c] = acc_c[c] + f * H[c];
+        if (io->g) {
+            float G = 0.0f;
+            for (int c = 0; c < NC; ++c) G = G + io->g[c * K + k] * H[c];
+            pd = pd + f * G;
+            if (h == 1)
+                for (int c = 0; c < 3; ++c) ql[c] = ql[c] + G * gr[c];
         }
-        for (int ch = 0; ch < 3; ++ch) Tc[ch] = Tc[ch] * (S->albedo_rgb ? S->albedo_rgb[3 * q + ch] : pf[16]);
     }
-    if (io->g && hits >= 1 && L->rgb) {
-        /* every channel shares the path's geometry, so dPhi_ch/dp = Phi_ch dlog:
-         * the geometric terms take the colour-weighted adjoint sum, and
-         * dO/dcol_ch = s_ch Phi_r */
-        s_r = (sc[0] * L->col[0] + sc[1] * L->col[1]) + sc[2] * L->col[2];
+    if (io->S) {
+        float base = (ps->phi_r * ps->T) * hp->inv_a;
+        for (int c = 0; c < NC; ++c) splat(io->S, c * K + k, (base * acc_c[c]) * inv_np);
+    }
+    if (io->g) {
+        float P = (pd * inv_np) * hp->inv_a;
+        ps->s_r = ps->s_r + P * ps->T;
+        if (h >= 2) ps->Rd = ps->Rd + P * ps->T2;
+        if (h == 1) {
+            ps->k1 = k;
+            float dl[8];
+            first_hit_dlog(L, hp->x, ps->y, hp->no, ps->au, ps->av, dl);
+            for (int c = 0; c < NP; ++c) ps->dphi[c] = ps->phi_r * dl[c];
+            float sq = (inv_np * hp->inv_a);
+            for (int c = 0; c < 3; ++c)
+                ps->Qw[c] = ((ql[0] * sq) * ps->fb1[c] + (ql[1] * sq) * ps->fb2[c]) + (ql[2] * sq) * hp->no[c];
+            float v1[3] = {ps->y[0] - hp->x[0], ps->y[1] - hp->x[1], ps->y[2] - hp->x[2]};
+            float r1 = sqrtf(dot3(v1, v1));
+            ps->inv_r1 = 1.0f / r1;
+            for (int c = 0; c < 3; ++c) ps->om1[c] = v1[c] * ps->inv_r1;
+        }
+    }
+}
+
+/* Irradiance splats of a hit (Alg. 1): Phi_h / A_k into the hit texel, or
+ * its bilinear shares into the four nodes; in colour, one per channel. */
+static void splat_hit(const or_scene* S, const olight* L, const hit_point* hp, path_io* io, const path_state* ps)
+{
+    const int64_t K = S->n_texels;
+    if (L->rgb) {
+        for (int ch = 0; ch < 3; ++ch) splat(io->S, ch * K + hp->k, ((ps->phi_r * L->col[ch]) * ps->Tc[ch]) * hp->inv_a);
+    } else {
+        float val = (ps->phi_r * ps->T) * hp->inv_a;
+        if (S->basis == 1) {
+            for (int c = 0; c < 4; ++c) splat(io->S, hp->kb[c], val * hp->wb[c]);
+        } else {
+            splat(io->S, hp->k, val);
+        }
+    }
+}
+
+/* Direct (forward-mode) differentiation with x_1 held fixed: every hit of
+ * the path adds d(Phi_h / A)/dp_j = (Phi_h / A) dlog_j of its first hit, in
+ * its own texel. */
+static void tangent_hit(const olight* L, int h, const hit_point* hp, path_io* io, path_state* ps)
+{
+    if (h == 1) {
+        float dl[8];
+        first_hit_dlog(L, hp->x, ps->y, hp->no, ps->au, ps->av, dl);
+        ps->tdl = dl[io->tangent_param];
+    }
+    splat(io->tangent, hp->k, ((ps->phi_r * ps->T) * hp->inv_a) * ps->tdl);
+}
+
+/* Adjoint at a hit (Alg. 2, Eq. adjointFlux): g_k Phi_h / (A_k Phi_r) added
+ * to the path's sum (bilinear gather for the linear basis, per channel in
+ * colour); at the first hit, dlog Phi_r/dp with x_1 held fixed. */
+static void adjoint_hit(const or_scene* S, const olight* L, int h, const hit_point* hp, path_io* io,
+                        path_state* ps)
+{
+    const int64_t K = S->n_texels, k = hp->k;
+    const int NP = L->rv ? 7 : (L->cone ? 8 : 6);
+    if (L->rgb) {
+        for (int ch = 0; ch < 3; ++ch) ps->sc[ch] = ps->sc[ch] + (io->g[ch * K + k] * hp->inv_a) * ps->Tc[ch];
+    } else {
+        float gk = io->g[k];
+        if (S->basis == 1)
+            gk = ((hp->wb[0] * io->g[hp->kb[0]] + hp->wb[1] * io->g[hp->kb[1]]) + hp->wb[2] * io->g[hp->kb[2]]) +
+                 hp->wb[3] * io->g[hp->kb[3]];
+        ps->s_r = ps->s_r + (gk * hp->inv_a) * ps->T;
+    }
+    if (h == 1) {
+        ps->k1 = k;
+        float dl[8];
+        first_hit_dlog(L, hp->x, ps->y, hp->no, ps->au, ps->av, dl);
+        for (int c = 0; c < NP; ++c) ps->dphi[c] = ps->phi_r * dl[c];
+    }
+}
+
+/* Cosine-weighted bounce about the oriented normal (Malley's method in the
+ * Duff et al. 2017 orthonormal basis); Phi_{h+1} = Phi_h rho, or the glossy
+ * BRDF's bounce weight pi f for directional texels. */
+static void bounce(const or_scene* S, uint64_t seed, uint32_t i, uint32_t stream, int h, const hit_point* hp,
+                   path_state* ps)
+{
+    const float* no = hp->no;
+    float ub[4];
+    draw4(seed, i, stream, 1u + (uint32_t)h, ub);
+    float sign = copysignf(1.0f, no[2]);
+    float a = -1.0f / (sign + no[2]);
+    float bxy = (no[0] * no[1]) * a;
+    float b1[3] = {1.0f + ((sign * no[0]) * no[0]) * a, sign * bxy, -(sign * no[0])};
+    float b2[3] = {bxy, sign + (no[1] * no[1]) * a, -no[1]};
+    float rr = sqrtf(ub[0]);
+    float sp, cp;
+    or_sincos2pi(ub[1], &sp, &cp);
+    float lx = rr * cp, ly = rr * sp;
+    float lz = sqrtf(fmaxf(0.0f, 1.0f - ub[0]));
+    for (int c = 0; c < 3; ++c) ps->dir[c] = (lx * b1[c] + ly * b2[c]) + lz * no[c];
+    for (int c = 0; c < 3; ++c) ps->o[c] = hp->x[c];
+    ps->skip = hp->q;
+    if (S->dir_order >= 0) {
+        const float* gl_ = S->glossy ? S->glossy + 2 * (int64_t)hp->q : NULL;
+        float wo[3] = {dot3(ps->fb1, ps->dir), dot3(ps->fb2, ps->dir), dot3(no, ps->dir)};
+        float gr[3];
+        float fbv = or_brdf(hp->pf[16], gl_ ? gl_[0] : 0.0f, gl_ ? gl_[1] : 1.0f, ps->wi_loc, wo, gr);
+        float wb = fbv * 3.14159265358979f;
+        if (h == 1) {
+            for (int c = 0; c < 3; ++c)
+                ps->Dw[c] = ((gr[0] * 3.14159265358979f) * ps->fb1[c] + (gr[1] * 3.14159265358979f) * ps->fb2[c]) +
+                            (gr[2] * 3.14159265358979f) * no[c];
+        } else {
+            ps->T2 = ps->T2 * wb;
+        }
+        ps->T = ps->T * wb;
+    } else {
+        ps->T = ps->T * hp->pf[16];
+    }
+    for (int ch = 0; ch < 3; ++ch) ps->Tc[ch] = ps->Tc[ch] * (S->albedo_rgb ? S->albedo_rgb[3 * hp->q + ch] : hp->pf[16]);
+}
+
+/* End of a path (Eq. objGradAdjoint, first term): dO/dp_j += s_r Phi_r
+ * dlog_j (plus, for directional texels, the first hit's BRDF terms through
+ * the incident direction); in colour the geometric terms take the
+ * colour-weighted sum and dO/dcol_ch = s_ch Phi_r; the contribution map and
+ * the proposal's histogram take the path's share. */
+static void finish_path(const olight* L, int gl, const or_proposal* prop, const or_scene* S, path_io* io,
+                        path_state* ps)
+{
+    const int NP = L->rv ? 7 : (L->cone ? 8 : 6);
+    if (io->g && ps->hits >= 1 && L->rgb) {
+        ps->s_r = (ps->sc[0] * L->col[0] + ps->sc[1] * L->col[1]) + ps->sc[2] * L->col[2];
         if (io->acc_col)
-            for (int ch = 0; ch < 3; ++ch) io->acc_col[ch] += (double)(sc[ch] * phi_r);
+            for (int ch = 0; ch < 3; ++ch) io->acc_col[ch] += (double)(ps->sc[ch] * ps->phi_r);
     }
-    if (io->g && hits >= 1) {
+    if (io->g && ps->hits >= 1) {
         float cr[8];
         float ub_[3] = {0, 0, 0};
         float dya[3] = {0, 0, 0}, dyb[3] = {0, 0, 0};
-        if (dirm) {
+        if (S->dir_order >= 0) {
             /* d/dy of the first hit's projection and bounce weight through the
              * incident direction om1 = (y - x_1)/|y - x_1| */
             float v[3];
-            for (int c = 0; c < 3; ++c) v[c] = Qw[c] + Rd * Dw[c];
-            float wv = dot3(om1, v);
-            for (int c = 0; c < 3; ++c) ub_[c] = (v[c] - om1[c] * wv) * inv_r1;
+            for (int c = 0; c < 3; ++c) v[c] = ps->Qw[c] + ps->Rd * ps->Dw[c];
+            float wv = dot3(ps->om1, v);
+            for (int c = 0; c < 3; ++c) ub_[c] = (v[c] - ps->om1[c] * wv) * ps->inv_r1;
             if (L->type == 2)
                 for (int c = 0; c < 3; ++c) {
-                    dya[c] = av * L->db_da[c];
-                    dyb[c] = au * L->dt_db[c] + av * L->db_db[c];
+                    dya[c] = ps->av * L->db_da[c];
+                    dyb[c] = ps->au * L->dt_db[c] + ps->av * L->db_db[c];
                 }
         }
         float extra[6] = {ub_[0], ub_[1], ub_[2], dot3(ub_, dya), dot3(ub_, dyb), 0.0f};
         for (int c = 0; c < NP; ++c) {
-            cr[c] = s_r * dphi[c];
-            if (dirm) cr[c] = cr[c] + phi_r * extra[c];
+            cr[c] = ps->s_r * ps->dphi[c];
+            if (S->dir_order >= 0) cr[c] = cr[c] + ps->phi_r * extra[c];
             if (io->acc) io->acc[c] += (double)cr[c];
             if (io->contrib && c < 6) io->contrib[c] = cr[c];
         }
@@ -1164,24 +1198,67 @@ static void trace_path(const or_scene* S, const olight* L, int layout, int l_loc
 #ifdef _OPENMP
 #pragma omp atomic
 #endif
-            io->vote[k1] += (double)cr[io->vote_param];
+            io->vote[ps->k1] += (double)cr[io->vote_param];
         }
-        if (prop && prop->hist && ebin >= 0) {
+        if (prop && prop->hist && ps->ebin >= 0) {
             const float* is = prop->inv_sigma + 6 * (int64_t)gl;
             float m2 = 0.0f;
             for (int c = 0; c < 6; ++c) {
                 float z = cr[c] * is[c];
                 m2 = m2 + z * z;
             }
-            double v = (double)(m2 * wq);
+            double v = (double)(m2 * ps->wq);
 #ifdef _OPENMP
 #pragma omp atomic
 #endif
-            prop->hist[1024 * (int64_t)gl + ebin] += v;
+            prop->hist[1024 * (int64_t)gl + ps->ebin] += v;
         }
     } else if (io->contrib) {
         for (int c = 0; c < 6; ++c) io->contrib[c] = 0.0f;
     }
+}
+
+/* One light path of light gl: emission, then up to B hits, each splatting
+ * its flux (forward), adding its share of the adjoint sum (adjoint), its
+ * direct-differentiation splat or its record, then bouncing; the adjoint
+ * quantities are accumulated at the end of the path. */
+static void trace_path(const or_scene* S, const olight* L, int layout, int l_local, int gl, uint32_t i, uint64_t seed,
+                       int B, const or_proposal* prop_in, path_io* io)
+{
+    const uint32_t stream = ((uint32_t)layout << 16) | (uint32_t)l_local;
+    const or_proposal* prop = (prop_in && prop_in->pdf && (L->type == 1 || L->type == 2)) ? prop_in : NULL;
+    path_state ps;
+    memset(&ps, 0, sizeof(ps));
+    emit_path(L, seed, i, stream, gl, prop, &ps);
+    for (int c = 0; c < 3; ++c) ps.o[c] = ps.y[c];
+    ps.skip = -1;
+    ps.T = 1.0f;
+    ps.k1 = -1;
+    ps.T2 = 1.0f;
+    for (int ch = 0; ch < 3; ++ch) ps.Tc[ch] = 1.0f;
+    const int dirm = S->dir_order >= 0;
+    for (int h = 1; h <= B; ++h) {
+        float t;
+        int64_t prim = intersect(S, ps.o, ps.dir, ps.skip, &t);
+        if (prim < 0) {
+            io->misses++;
+            break;
+        }
+        ps.hits = h;
+        hit_point hp;
+        locate_hit(S, ps.o, ps.dir, t, prim, &hp);
+        if (dirm) directional_hit(S, L, seed, i, stream, h, &hp, io, &ps);
+        else if (io->S) splat_hit(S, L, &hp, io, &ps);
+        if (io->tangent) tangent_hit(L, h, &hp, io, &ps);
+        if (io->g && !dirm) adjoint_hit(S, L, h, &hp, io, &ps);
+        if (io->rec_prim) {
+            io->rec_prim[h - 1] = (int32_t)prim;
+            io->rec_texel[h - 1] = (int32_t)hp.k;
+        }
+        if (h == B) break;
+        bounce(S, seed, i, stream, h, &hp, &ps);
+    }
+    finish_path(L, gl, prop, S, io, &ps);
 }
 
 /* ------------------------------------------------------------------------- */
