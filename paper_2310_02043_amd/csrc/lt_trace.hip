@@ -625,15 +625,21 @@ __global__ void __launch_bounds__(WPB * 64)
 {
     constexpr bool DIR = MODE >= 30;               // directional texels of order MODE - 30
     constexpr int DORD = DIR ? MODE - 30 : 0;
-    __shared__ int s_stack[WPB * LDS_D * 64];
+    // the colour adjoint keeps kColourLdsDepth stack entries in LDS: its
+    // per-lane colour state takes the rest of the budget of five waves per
+    // SIMD (the overflow part of the stack is sized for it)
+    constexpr int LDS_S = (ADJ && MODE == 2 && LDS_D > kColourLdsDepth) ? kColourLdsDepth : LDS_D;
+    __shared__ int s_stack[WPB * LDS_S * 64];
     // adjoint per-lane state read once per path (first-hit derivative
     // factors, running contribution sums), kept in LDS instead of registers
     constexpr int NPAR = MODE == 4 ? 7 : (MODE == 6 ? 8 : 6);   // 4: rotation vector, 6: cone angles
     __shared__ float s_adj[ADJ ? WPB * 2 * NPAR * 64 : 1];
-    // adjoint with a gradient-contribution map: texel of the first hit
-    __shared__ int s_k1[ADJ ? WPB * 64 : 1];
+    // adjoint with a gradient-contribution map (grey irradiance, box or
+    // linear basis): texel of the first hit
+    constexpr bool VOTES = ADJ && MODE <= 1;
+    __shared__ int s_k1[VOTES ? WPB * 64 : 1];
     // colour: per lane T_g, T_b, s_g, s_b and the three channel-weight sums
-    __shared__ float s_rgb[MODE == 2 ? WPB * 8 * 64 : 1];
+    __shared__ float s_rgb[MODE == 2 ? WPB * 7 * 64 : 1];
     // directional: forward, the hit's 16 coefficient sums; adjoint T2, R,
     // Q[3], D[3], w_in1[3], 1/r1 and the hit texel's 16 dO/dL values
     constexpr int DIRW = ADJ ? 28 : 16;
@@ -641,14 +647,15 @@ __global__ void __launch_bounds__(WPB * 64)
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     float* adj = s_adj + (ADJ ? wib * 2 * NPAR * 64 + lane : 0);
-    int* k1 = s_k1 + (ADJ ? wib * 64 + lane : 0);
-    float* rgbs = s_rgb + (MODE == 2 ? wib * 8 * 64 + lane : 0);
+    int k1_reg = 0;
+    int* k1 = VOTES ? s_k1 + wib * 64 + lane : &k1_reg;
+    float* rgbs = s_rgb + (MODE == 2 ? wib * 7 * 64 + lane : 0);
     float* dst = s_dir + (DIR ? wib * DIRW * 64 + lane : 0);
     // persistent wave: its slot owns one traversal-stack overflow area, and
     // it takes work tiles from the queue(s) until they are drained
     const long long gw = (long long)blockIdx.x * WPB + wib;
     if (gw >= a.gstack_waves) return;
-    int* lst = s_stack + wib * LDS_D * 64 + lane;
+    int* lst = s_stack + wib * LDS_S * 64 + lane;
     int* gst = a.gstack + gw * (long long)a.gdepth * 64 + lane;
     const int B = a.max_hits;
     const int thresh = a.refill_threshold;
@@ -796,7 +803,7 @@ __global__ void __launch_bounds__(WPB * 64)
                     mode = (nq > 0 && (nq == nt || nq * 8 >= nt * a.tri_share)) ? 1 : 2;
                 }
                 if (trav)
-                    trav_step<LDS_D, STATS>(r, skip, s, trav, a.nodes, a.tris, lst, gst, n_nodes, n_tris,
+                    trav_step<LDS_S, STATS>(r, skip, s, trav, a.nodes, a.tris, lst, gst, n_nodes, n_tris,
                                             a.max_steps, overrun, mode);
             }
 
