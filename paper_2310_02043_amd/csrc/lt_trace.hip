@@ -617,11 +617,11 @@ __device__ __forceinline__ T wave_sum(T v)
 // rotation-vector orientation (seven derivatives), 5 the direct-differentiation map of one luminaire (forward only), 6 the
 // soft-edged spots' cone angles (adjoint, eight derivatives).
 template <bool ADJ, bool STATS, int WPB, int LDS_D, int MODE>
-// Occupancy floor per instance: the plain forward pass fits seven waves per
-// SIMD (72 VGPRs, no spill), the other instances five, the directional ones
-// four.
+// Occupancy floor per instance: the forward pass with the box or the linear
+// basis fits seven waves per SIMD (72 VGPRs, no spill), the other instances
+// five, the directional ones four.
 __global__ void __launch_bounds__(WPB * 64)
-    __attribute__((amdgpu_waves_per_eu(MODE >= 30 ? 4 : (!ADJ && !STATS && MODE == 0 ? 7 : 5)))) k_trace(TraceArgs a)
+    __attribute__((amdgpu_waves_per_eu(MODE >= 30 ? 4 : (!ADJ && !STATS && MODE <= 1 ? 7 : 5)))) k_trace(TraceArgs a)
 {
     constexpr bool DIR = MODE >= 30;               // directional texels of order MODE - 30
     constexpr int DORD = DIR ? MODE - 30 : 0;
