@@ -288,10 +288,10 @@ int ensure_tiles(lt_ctx* c, long long ppl)
 // stack entries a segment can need: up to three pushes per level of the 4-wide tree
 int stack_need(const lt_ctx* c) { return 3 * c->depth + 1; }
 // overflow entries per lane: what the deepest segment can need beyond the
-// smallest LDS part of any instance (the colour adjoint's)
+// smallest LDS part of any instance (the adjoint's)
 int gstack_depth(const lt_ctx* c)
 {
-    return std::max(0, stack_need(c) - std::min(c->tune.lds_depth, kColourLdsDepth));
+    return std::max(0, stack_need(c) - std::min(c->tune.lds_depth, kAdjLdsDepth));
 }
 
 int ensure_gstack(lt_ctx* c, long long waves)
@@ -1719,7 +1719,7 @@ std::string tune_key(const lt_ctx* c, const lt_trace_cfg* cfg)
     hipDeviceProp_t prop;
     const char* arch = "unknown";
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
-    snprintf(buf, sizeof(buf), "v4 arch=%s tris=%lld texels=%lld lights=%d layouts=%d ppl=%lld hits=%d", arch,
+    snprintf(buf, sizeof(buf), "v5 arch=%s tris=%lld texels=%lld lights=%d layouts=%d ppl=%lld hits=%d", arch,
              (long long)c->n_tris, (long long)c->K, c->L, c->n_layouts, (long long)cfg->paths_per_layout,
              cfg->max_hits);
     for (char* q = buf; *q; ++q)

@@ -15,7 +15,7 @@ constexpr int kPlocRadius = 16;       // nearest-neighbour window of the BVH bui
 constexpr int kBvhWidth = 4;          // children per node of the traversed tree
 constexpr int kEmptyChild = (int)0x80000000;  // unused child slot of a wide node
 constexpr int kNodeRows = 4;                  // 16-byte rows per wide node
-constexpr int kColourLdsDepth = 12;           // traversal-stack entries in LDS of the colour adjoint
+constexpr int kAdjLdsDepth = 12;              // traversal-stack entries in LDS of the plain and colour adjoint
 
 // sticky device status bits (the LT_STATUS_* values of the C ABI)
 constexpr unsigned kStatusOverflow = 1u;   // a texel accumulator reached 2^62

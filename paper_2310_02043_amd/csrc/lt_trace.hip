@@ -618,17 +618,22 @@ __device__ __forceinline__ T wave_sum(T v)
 // soft-edged spots' cone angles (adjoint, eight derivatives).
 template <bool ADJ, bool STATS, int WPB, int LDS_D, int MODE>
 // Occupancy floor per instance: the forward pass with the box or the linear
-// basis fits seven waves per SIMD (72 VGPRs, no spill), the other instances
-// five, the directional ones four.
+// basis fits seven waves per SIMD (72 VGPRs, no spill), the plain adjoint six
+// (80 VGPRs; with kAdjLdsDepth stack entries in LDS, 6.4 KB per wave), the
+// other instances five, the directional ones four.
 __global__ void __launch_bounds__(WPB * 64)
-    __attribute__((amdgpu_waves_per_eu(MODE >= 30 ? 4 : (!ADJ && !STATS && MODE <= 1 ? 7 : 5)))) k_trace(TraceArgs a)
+    __attribute__((amdgpu_waves_per_eu(MODE >= 30 ? 4
+                                                  : (!ADJ && !STATS && MODE <= 1 ? 7
+                                                                                  : (ADJ && !STATS && MODE == 0 ? 6 : 5)))))
+    k_trace(TraceArgs a)
 {
     constexpr bool DIR = MODE >= 30;               // directional texels of order MODE - 30
     constexpr int DORD = DIR ? MODE - 30 : 0;
-    // the colour adjoint keeps kColourLdsDepth stack entries in LDS: its
-    // per-lane colour state takes the rest of the budget of five waves per
-    // SIMD (the overflow part of the stack is sized for it)
-    constexpr int LDS_S = (ADJ && MODE == 2 && LDS_D > kColourLdsDepth) ? kColourLdsDepth : LDS_D;
+    // the plain and the colour adjoint keep kAdjLdsDepth stack entries in
+    // LDS: their per-lane state takes the rest of the budget of six (plain)
+    // or five (colour) waves per SIMD; the overflow part of the stack is
+    // sized for it
+    constexpr int LDS_S = (ADJ && (MODE == 0 || MODE == 2) && LDS_D > kAdjLdsDepth) ? kAdjLdsDepth : LDS_D;
     __shared__ int s_stack[WPB * LDS_S * 64];
     // adjoint per-lane state read once per path (first-hit derivative
     // factors, running contribution sums), kept in LDS instead of registers
