@@ -46,10 +46,11 @@ SLOTS_PER_BOX, SLOTS_PER_TRI = 14, 40
 NODE_BYTES, TRI_BYTES, PATCH_BYTES = 64, 48, 80
 # Per-lane vector-memory requests (one 16 B row each): a node visit loads its
 # four rows, a triangle test three, a hit the five rows of its patch record
-# plus one atomic (forward) or one gather (adjoint).  Every lane's request
-# falls in a different cache line, and the counters (TA/TD busy ~100 %, one
-# TD cycle per lane request) show the vector-memory path serving one such
-# request per CU per clock: 256 CUs x 2.4 GHz.
+# plus one atomic (forward) or one gather (adjoint).  A lane's request mostly
+# falls in a cache line of its own, and the counters (TD busy ~100 %, one TD
+# cycle per lane request) show the vector-memory path serving about one
+# distinct line per CU per clock: 256 CUs x 2.4 GHz (lanes sharing a line in
+# one instruction, at the top of the tree, can take the rate slightly above).
 REQ_PER_NODE, REQ_PER_TRI, REQ_PER_HIT = 4, 3, 6
 VMEM_REQ_PEAK_G = 256 * 2.4e9 / 1e9
 
@@ -381,7 +382,8 @@ def throughput(name, args, paths=0, steps=None, warmup=None):
                                   "unit": "G lane-requests/s", "frac": round(reqs / dur_s / 1e9 / VMEM_REQ_PEAK_G, 4),
                                   "per_launch": int(reqs),
                                   "note": f"per-lane 16 B loads: {REQ_PER_NODE} per node visit, {REQ_PER_TRI} per "
-                                          f"triangle test, {REQ_PER_HIT} per hit; one per CU per clock, 256 CU x 2.4 GHz"},
+                                          f"triangle test, {REQ_PER_HIT} per hit; about one distinct cache line per CU per clock, "
+                                          "256 CU x 2.4 GHz"},
                 "ops_per_launch": int(ops),
                 "hbm": {"achieved": None if traffic is None else round(traffic / dur_s / 1e9, 1),
                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
