@@ -147,11 +147,14 @@ int lt_sync(lt_ctx* ctx, uint32_t* flags_out);
  * takes from ray-tracing hardware, Sec. 6).  Host arrays: h_verts [n_verts,3]
  * f32, h_tris [n_tris,3] i32 vertex indices, h_tri_patch [n_tris] i32,
  * h_patches [n_patches].  Texel ranges of the patches must tile
- * [0, n_texels) in order; at most 2^26 triangles and 2^25 BVH nodes (the
- * traversal addresses both by 32-bit byte offsets).  Builds the BVH on the
- * device (Morton order, PLOC clustering, collapse to a 4-wide tree) and the
- * per-texel area table; replaces any previous scene.  *n_texels_out
- * receives K. */
+ * [0, n_texels) in order; at most 2^26 triangles and a tree under 2^32 bytes
+ * (the traversal addresses triangles and nodes by 32-bit byte offsets);
+ * vertices finite and within 1e8 of the origin (so the slab test's
+ * products with a reciprocal direction, up to 1e30 for an axis-parallel
+ * ray, stay finite).  Builds the BVH on the device (Morton order, PLOC
+ * clustering, collapse to a 4-wide tree) and the per-texel area table;
+ * replaces any previous scene.  *n_texels_out receives K.  LT_EINVAL for
+ * any violation. */
 int lt_scene_upload(lt_ctx* ctx, const float* h_verts, int64_t n_verts, const int32_t* h_tris,
                     const int32_t* h_tri_patch, int64_t n_tris, const lt_patch* h_patches, int32_t n_patches,
                     int64_t* n_texels_out);

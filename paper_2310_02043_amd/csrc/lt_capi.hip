@@ -562,6 +562,9 @@ int lt_scene_upload(lt_ctx* c, const float* h_verts, int64_t n_verts, const int3
             hi[k] = std::max(hi[k], x);
         }
     }
+    // an axis-parallel ray's reciprocal direction is up to 1e30; the slab
+    // test's products with coordinates must stay finite
+    if (amax > 1e8) return fail(c, LT_EINVAL, "vertex coordinates beyond 1e8 in magnitude");
     for (int64_t t = 0; t < n_tris; ++t) {
         for (int k = 0; k < 3; ++k)
             if (h_tris[3 * t + k] < 0 || h_tris[3 * t + k] >= n_verts)

@@ -504,6 +504,10 @@ def test_invalid_arguments_raise(torch_dev):
     bad["texel_base"][1] += 1
     with pytest.raises(LtError):
         ctx.upload_scene(c1["scene"].verts, c1["scene"].tris, c1["scene"].tri_patch, bad)
+    far = c1["scene"].verts.copy()
+    far[0, 0] = 2e8                                            # beyond the coordinate bound
+    with pytest.raises(LtError):
+        ctx.upload_scene(far, c1["scene"].tris, c1["scene"].tri_patch, c1["scene"].patches)
 
 
 @pytest.mark.parametrize("bad", ["negative_power", "nan_position", "inf_tilt", "zero_power"])
