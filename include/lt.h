@@ -461,6 +461,19 @@ int lt_autotune(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, int
 
 int lt_info_get(const lt_ctx* ctx, lt_info* out);
 
+/* Copy the uploaded scene's acceleration structure to host memory, for
+ * inspection (the structure the paper takes from ray-tracing hardware,
+ * Sec. 6).  h_nodes receives the wide nodes (lt_info.bvh_nodes x 64 B: per
+ * axis x, y, z the four slots' lower then upper planes as f16 offsets from
+ * the node origin, rounded outward; then the origin as bf16 x, y, z, the
+ * slot counts internal | leaves << 4, the first internal child's node index
+ * and the first leaf's triangle slot; slots ordered internal, leaves,
+ * unused), h_tris the leaf triangles (lt_info.n_tris x 48 B, 2 x 48 B for a
+ * single-triangle scene: (v0, id), (v1 - v0, patch), (v2 - v0, 0) as f32 /
+ * int bits, in leaf-slot order).  Byte sizes of the host buffers are passed
+ * in; LT_EINVAL if there is no scene or a buffer is too small. */
+int lt_bvh_copy(lt_ctx* ctx, void* h_nodes, int64_t nodes_bytes, void* h_tris, int64_t tris_bytes);
+
 /* Kernel timing.  While enabled, HIP events are recorded on the launch stream
  * around every persistent trace kernel launched outside a graph;
  * lt_timing_read waits for them and returns the summed kernel durations (ms)

@@ -1456,6 +1456,21 @@ int lt_set_tuning(lt_ctx* c, const lt_tuning* t)
     return LT_OK;
 }
 
+int lt_bvh_copy(lt_ctx* c, void* h_nodes, int64_t nodes_bytes, void* h_tris, int64_t tris_bytes)
+{
+    if (!c) return LT_EINVAL;
+    if (!c->nodes || !c->tris) return fail(c, LT_EINVAL, "no scene uploaded");
+    if (!h_nodes || !h_tris) return fail(c, LT_EINVAL, "NULL host buffer");
+    const int64_t nb = (int64_t)c->n_nodes * 16 * kNodeRows;
+    const int64_t tb = (c->n_tris > 1 ? c->n_tris : 2) * 48;   // a single triangle fills both root slots
+    if (nodes_bytes < nb || tris_bytes < tb) return fail(c, LT_EINVAL, "host buffer too small for the BVH");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(h_nodes, c->nodes, (size_t)nb, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(h_tris, c->tris, (size_t)tb, hipMemcpyDeviceToHost));
+    return LT_OK;
+}
+
 int lt_info_get(const lt_ctx* c, lt_info* out)
 {
     if (!c || !out) return LT_EINVAL;

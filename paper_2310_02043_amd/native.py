@@ -29,7 +29,7 @@ EXPORTED = [
     "lt_timing_read", "lt_proposal_set_table", "lt_proposal_get_table", "lt_proposal_set_scale",
     "lt_proposal_mlp_infer",
     "lt_proposal_mlp_train", "lt_proposal_set", "lt_proposal_refresh", "lt_proposal_update_scale",
-    "lt_proposal_train_step", "lt_proposal_get_net", "lt_trace_adjoint_noalloc",
+    "lt_proposal_train_step", "lt_proposal_get_net", "lt_trace_adjoint_noalloc", "lt_bvh_copy",
 ]
 MLP_WEIGHTS, MLP_IN, MLP_BINS = 72832, 32, 1024
 
@@ -114,6 +114,7 @@ def load():
     L.lt_set_tuning.argtypes = [P, C.POINTER(Tuning)]
     L.lt_autotune.argtypes = [P, C.POINTER(TraceCfg), P, P, P, P, P, C.c_char_p, C.POINTER(C.c_float)]
     L.lt_info_get.argtypes = [P, C.POINTER(Info)]
+    L.lt_bvh_copy.argtypes = [P, P, I64, P, I64]
     L.lt_set_timing.argtypes = [P, C.c_int]
     L.lt_proposal_set_table.argtypes = [P, P, P]
     L.lt_proposal_set_scale.argtypes = [P, P]
@@ -606,6 +607,19 @@ class Context:
         nf, na = C.c_int32(), C.c_int32()
         self._check(self.lib.lt_timing_read(self.h, C.byref(f), C.byref(nf), C.byref(a), C.byref(na)))
         return f.value, nf.value, a.value, na.value
+
+    def bvh(self):
+        """The acceleration structure on the host: (nodes [n, 64] u8, triangles
+        [m, 12] f32 rows, the ids and patch ids as int bits)."""
+        import numpy as np
+        n = self.info()["bvh_nodes"]
+        m = max(self.info()["n_tris"], 2)
+        nodes = np.zeros((n, 64), np.uint8)
+        tris = np.zeros((m, 12), np.float32)
+        self._check(self.lib.lt_bvh_copy(self.h, nodes.ctypes.data, nodes.nbytes, tris.ctypes.data, tris.nbytes))
+        if self.info()["n_tris"] > 1:
+            tris = tris[: self.info()["n_tris"]]
+        return nodes, tris
 
     def info(self) -> dict:
         i = Info()
