@@ -1737,7 +1737,7 @@ std::string tune_key(const lt_ctx* c, const lt_trace_cfg* cfg)
     hipDeviceProp_t prop;
     const char* arch = "unknown";
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
-    snprintf(buf, sizeof(buf), "v5 arch=%s tris=%lld texels=%lld lights=%d layouts=%d ppl=%lld hits=%d", arch,
+    snprintf(buf, sizeof(buf), "v6 arch=%s tris=%lld texels=%lld lights=%d layouts=%d ppl=%lld hits=%d", arch,
              (long long)c->n_tris, (long long)c->K, c->L, c->n_layouts, (long long)cfg->paths_per_layout,
              cfg->max_hits);
     for (char* q = buf; *q; ++q)

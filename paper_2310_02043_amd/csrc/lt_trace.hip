@@ -47,6 +47,14 @@ __device__ __forceinline__ void set_ray(Ray& r, V3 o, V3 d)
 __device__ __forceinline__ float f16lo(unsigned w) { return (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xFFFFu)); }
 __device__ __forceinline__ float f16hi(unsigned w) { return (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16)); }
 
+// Lane's entry i of its wave's traversal-stack overflow area (entries
+// interleaved by lane): a 32-bit byte offset from the wave-uniform base,
+// so the access takes the scalar-base form and the base costs no VGPRs.
+__device__ __forceinline__ int* gst_slot(int* gst, int i)
+{
+    return (int*)((char*)gst + (((unsigned)i * 64u + (unsigned)__lane_id()) << 2));
+}
+
 struct Trav {
     float tb;
     int pb, qb;
@@ -151,7 +159,15 @@ __device__ __forceinline__ void trav_step(const Ray& r, int skip, Trav& s, bool&
             s.node = -1;
         } else {
             --s.sp;
-            s.node = s.sp < LDS_D ? lst[s.sp * 64] : gst[(s.sp - LDS_D) * 64];
+            // the LDS and the overflow read stay two accesses: merged, they
+            // would become one generic (flat) access through the vector-memory
+            // path (the empty asm statement keeps the branches distinct)
+            if (s.sp < LDS_D) {
+                s.node = lst[s.sp * 64];
+                __asm__ volatile("");
+            } else {
+                s.node = *gst_slot(gst, s.sp - LDS_D);
+            }
         }
     } else {
         s.node = first + (int)((e0 >> 8) & 3u);
@@ -170,8 +186,12 @@ __device__ __forceinline__ void trav_step(const Ray& r, int skip, Trav& s, bool&
             for (int k = 0; k < 3; ++k) {
                 if (ek[k] != none) {
                     const int cv = first + (int)((ek[k] >> 8) & 3u);
-                    if (s.sp < LDS_D) lst[s.sp * 64] = cv;
-                    else gst[(s.sp - LDS_D) * 64] = cv;
+                    if (s.sp < LDS_D) {
+                        lst[s.sp * 64] = cv;
+                        __asm__ volatile("");   // two stores, not one flat store
+                    } else {
+                        *gst_slot(gst, s.sp - LDS_D) = cv;
+                    }
                     ++s.sp;
                 }
             }
@@ -605,26 +625,29 @@ __device__ __forceinline__ T wave_sum(T v)
 // runs on a converged wave.
 // ---------------------------------------------------------------------------
 
-// Both variants fit 96 VGPRs (five waves per SIMD); the adjoint keeps its
-// per-path first-hit derivative factors and running sums in LDS.  MODE
-// selects at compile time, leaving the other instances as they were: 0 the
-// box texel basis, 1 the piecewise-linear basis (four splats / a four-node
-// gather per hit), 2 colour (three channel-planar texel arrays; the green
-// and blue throughputs and adjoint sums live in LDS beside the red ones in
-// registers), 30 + n directional texels of harmonic order n
-// (hemispherical-harmonic coefficients of the reflected radiance and a
-// glossy BRDF; the adjoint's first-hit BRDF terms live in LDS), 4
-// rotation-vector orientation (seven derivatives), 5 the direct-differentiation map of one luminaire (forward only), 6 the
+// The adjoint keeps its per-path first-hit derivative factors and running
+// sums in LDS.  MODE selects at compile time, leaving the other instances
+// as they were: 0 the box texel basis, 1 the piecewise-linear basis (four
+// splats / a four-node gather per hit), 2 colour (three channel-planar
+// texel arrays; the green and blue throughputs and adjoint sums live in
+// LDS beside the red ones in registers), 30 + n directional texels of
+// harmonic order n (hemispherical-harmonic coefficients of the reflected
+// radiance and a glossy BRDF; the adjoint's first-hit BRDF terms live in
+// LDS), 4 rotation-vector orientation (seven derivatives), 5 the
+// direct-differentiation map of one luminaire (forward only), 6 the
 // soft-edged spots' cone angles (adjoint, eight derivatives).
 template <bool ADJ, bool STATS, int WPB, int LDS_D, int MODE>
-// Occupancy floor per instance: the forward pass with the box or the linear
-// basis fits seven waves per SIMD (72 VGPRs, no spill), the plain adjoint six
-// (80 VGPRs; with kAdjLdsDepth stack entries in LDS, 6.4 KB per wave), the
-// other instances five, the directional ones four.
+// Occupancy floor per instance: the forward pass with the box basis runs
+// eight waves per SIMD (64 VGPRs; the one spilled value is read only when a
+// proposal samples the emission), with the linear basis seven (at eight it
+// would spill its LDS stack address, read on every push and pop), the plain
+// adjoint six (80 VGPRs; with kAdjLdsDepth stack entries in LDS, 6.4 KB per
+// wave), the other instances five, the directional ones four.
 __global__ void __launch_bounds__(WPB * 64)
     __attribute__((amdgpu_waves_per_eu(MODE >= 30 ? 4
-                                                  : (!ADJ && !STATS && MODE <= 1 ? 7
-                                                                                  : (ADJ && !STATS && MODE == 0 ? 6 : 5)))))
+                                                  : (!ADJ && !STATS && MODE == 0 ? 8
+                                                     : (!ADJ && !STATS && MODE == 1 ? 7
+                                                                                    : (ADJ && !STATS && MODE == 0 ? 6 : 5))))))
     k_trace(TraceArgs a)
 {
     constexpr bool DIR = MODE >= 30;               // directional texels of order MODE - 30
@@ -658,10 +681,10 @@ __global__ void __launch_bounds__(WPB * 64)
     float* dst = s_dir + (DIR ? wib * DIRW * 64 + lane : 0);
     // persistent wave: its slot owns one traversal-stack overflow area, and
     // it takes work tiles from the queue(s) until they are drained
-    const long long gw = (long long)blockIdx.x * WPB + wib;
+    const long long gw = (long long)blockIdx.x * WPB + __builtin_amdgcn_readfirstlane(wib);
     if (gw >= a.gstack_waves) return;
     int* lst = s_stack + wib * LDS_S * 64 + lane;
-    int* gst = a.gstack + gw * (long long)a.gdepth * 64 + lane;
+    int* gst = a.gstack + gw * (long long)a.gdepth * 64;   // the wave's overflow area
     const int B = a.max_hits;
     const int thresh = a.refill_threshold;
     // with XCD-aware queues, workgroup b runs on XCD b % 8 and starts on that
@@ -1123,9 +1146,9 @@ __global__ void __launch_bounds__(256) k_record(RecordArgs a)
     __shared__ int s_stack[4 * LDS_D * 64];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
-    const long long gw = (long long)blockIdx.x * 4 + wib;
+    const long long gw = (long long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(wib);
     int* lst = s_stack + wib * LDS_D * 64 + lane;
-    int* gst = a.gstack + gw * (long long)a.gdepth * 64 + lane;
+    int* gst = a.gstack + gw * (long long)a.gdepth * 64;   // the wave's overflow area
     const DevLight& L = a.lights[a.gl];
     const float* g = a.g ? a.g + (long long)a.layout * a.K : nullptr;
     const long long stride = (long long)gridDim.x * 256;
@@ -1248,9 +1271,9 @@ __global__ void __launch_bounds__(256) k_pt(PtArgs a)
     __shared__ double s_grad[ADJ ? kPtMaxLights * 6 : 1];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
-    const long long gw = (long long)blockIdx.x * 4 + wib;
+    const long long gw = (long long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(wib);
     int* lst = s_stack + wib * LDS_D * 64 + lane;
-    int* gst = a.gstack + gw * (long long)a.gdepth * 64 + lane;
+    int* gst = a.gstack + gw * (long long)a.gdepth * 64;   // the wave's overflow area
     if (ADJ) {
         for (int j = threadIdx.x; j < a.nl * 6; j += 256) s_grad[j] = 0.0;
         __syncthreads();
@@ -1748,12 +1771,15 @@ hipError_t launch_wpb(const TraceArgs& a, int lds_depth, int n_cu, hipStream_t s
             launch_persistent<ADJ, STATS, WPB, 32, 4>(a, n_cu, st);
     } else if (a.dir_order >= 0 && !STATS) {
         if constexpr (!STATS) {
-            // the harmonic order as a compile-time constant: MODE 30 + order
+            // the harmonic order as a compile-time constant: MODE 30 + order.
+            // The directional adjoint holds 14 KB of LDS per wave, so a CU
+            // fits 10 of its waves in two-wave blocks but 8 in four-wave ones.
+            constexpr int DW = (ADJ && WPB == 4) ? 2 : WPB;
             switch (a.dir_order) {
-                case 0: launch_dir<ADJ, WPB, 30>(a, lds_depth, n_cu, st); break;
-                case 1: launch_dir<ADJ, WPB, 31>(a, lds_depth, n_cu, st); break;
-                case 2: launch_dir<ADJ, WPB, 32>(a, lds_depth, n_cu, st); break;
-                default: launch_dir<ADJ, WPB, 33>(a, lds_depth, n_cu, st); break;
+                case 0: launch_dir<ADJ, DW, 30>(a, lds_depth, n_cu, st); break;
+                case 1: launch_dir<ADJ, DW, 31>(a, lds_depth, n_cu, st); break;
+                case 2: launch_dir<ADJ, DW, 32>(a, lds_depth, n_cu, st); break;
+                default: launch_dir<ADJ, DW, 33>(a, lds_depth, n_cu, st); break;
             }
         }
     } else if (a.rgb && !STATS) {
