@@ -242,7 +242,8 @@ def intersect(osc: OracleScene, rays: np.ndarray, skip=None):
 def forward(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,
             limit_per_light: int = 0, n_threads: int = 0, proposal: Proposal = None):
     """Alg. 1: returns (S [n_layouts,K] int64 ([n_layouts,3,K] in colour
-    mode), misses)."""
+    mode), misses).  Luminaires of zero power add nothing and are not traced
+    (their paths count no misses)."""
     prm = np.ascontiguousarray(params, np.float32)
     shape = (ol.n_layouts, osc.n_texels) if ol.colour is None else (ol.n_layouts, 3, osc.n_texels)
     if osc.dir_order >= 0:
@@ -257,7 +258,8 @@ def forward(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_lay
 def adjoint(osc: OracleScene, ol: OracleLights, params, seed: int, paths_per_layout: int, max_hits: int,
             dOdE, limit_per_light: int = 0, n_threads: int = 0, proposal: Proposal = None):
     """Alg. 2: returns (grad [L,6] float64, misses); with a proposal holding a
-    histogram, fills proposal.hist.  Grey mode only (see adjoint_rgb)."""
+    histogram, fills proposal.hist.  Grey mode only (see adjoint_rgb).
+    Luminaires of zero power are not traced and get a zero row."""
     if ol.colour is not None:
         raise ValueError("colour mode: use adjoint_rgb")
     if ol.rotvec:

@@ -1286,6 +1286,9 @@ EXPORT int64_t or_forward(const or_scene* S, const or_lights* Ls, const float* p
             olight L;
             int64_t nl = paths_of_light(paths_per_layout, l1 - l0, gl - l0);
             light_setup(Ls, params, gl, nl, &L);
+            /* a luminaire of zero power carries flux P / N = 0 on every path
+             * (Alg. 1), so each of its splats is zero: it is not traced */
+            if (L.P == 0.0f) continue;
             int64_t lim = (limit_per_light > 0 && limit_per_light < nl) ? limit_per_light : nl;
             int64_t m = 0;
 #ifdef _OPENMP
@@ -1324,6 +1327,15 @@ EXPORT int64_t or_adjoint(const or_scene* S, const or_lights* Ls, const float* p
             olight L;
             int64_t nl = paths_of_light(paths_per_layout, l1 - l0, gl - l0);
             light_setup(Ls, params, gl, nl, &L);
+            if (L.P == 0.0f) {
+                /* zero power: the replayed paths (Alg. 2 follows Alg. 1's)
+                 * carry no flux and dO/dP is a 0/0 form there, so the
+                 * luminaire is not traced and its row is zero */
+                for (int c = 0; c < 6; ++c) grad_out[6 * (int64_t)gl + c] = 0.0;
+                if (grad_colour)
+                    for (int c = 0; c < 3; ++c) grad_colour[3 * (int64_t)gl + c] = 0.0;
+                continue;
+            }
             int64_t lim = (limit_per_light > 0 && limit_per_light < nl) ? limit_per_light : nl;
             double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0, c0 = 0, c1 = 0, c2 = 0;
             int64_t m = 0;

@@ -933,6 +933,41 @@ def test_closed_box_absorbs_all_flux(oracle_lib):
     assert abs(absorbed / P - 1) < 1e-5 + 0.75 ** B
 
 
+def test_zero_power_luminaire_adds_nothing(oracle_lib):
+    """Alg. 1 gives every path of a luminaire the flux P / N: at zero power
+    all its splats are zero, so the forward pass that skips it equals one
+    that traces it at a power too small to reach one fixed-point unit, and
+    the other luminaires' texels are those of the full run less its share."""
+    sc = li.closed_box(albedo=0.6)
+    base = [[0.7, 0.6, 0.5, 0, 0, 40.0], [1.3, 0.9, 0.8, 0.3, -0.2, 60.0], [1.0, 1.2, 0.9, -0.1, 0.2, 30.0]]
+    lights = make_lights([POINT, SPOT, POINT], [0.0, 3.0, 0.0], [(0, 0)] * 3, [0, 0, 0], base)
+    osc, ol = oracle_lib.OracleScene(sc), oracle_lib.OracleLights(lights)
+    N, B, seed = 3 * 4096 + 2, 4, 0x2E0
+
+    def fwd(p1):
+        p = lights.params.copy()
+        p[1, 5] = p1
+        return oracle_lib.forward(osc, ol, p, seed, N, B)[0]
+
+    S_zero, S_tiny, S_full = fwd(0.0), fwd(1e-30), fwd(60.0)
+    assert np.array_equal(S_zero, S_tiny)
+    assert np.count_nonzero(S_full - S_zero) > 0
+    only = lights.params.copy()
+    only[0, 5] = only[2, 5] = 0.0
+    S_only = oracle_lib.forward(osc, ol, only, seed, N, B)[0]
+    assert np.array_equal(S_full - S_zero, S_only)
+    # the adjoint: each luminaire's row sums its own paths only, so the other
+    # rows are unchanged (up to the threads' summation order) and the
+    # zero-power row is zero
+    g = oracle_lib.fixed_to_float(S_full).astype(np.float32) - 1.0
+    p_zero = lights.params.copy()
+    p_zero[1, 5] = 0.0
+    G_full, _ = oracle_lib.adjoint(osc, ol, lights.params, seed, N, B, g)
+    G_zero, _ = oracle_lib.adjoint(osc, ol, p_zero, seed, N, B, g)
+    assert np.all(G_zero[1] == 0.0) and np.any(G_full[1] != 0.0)
+    assert np.allclose(G_zero[[0, 2]], G_full[[0, 2]], rtol=1e-12, atol=0.0)
+
+
 # --------------------------------------------------------------------------
 # objective and fixed point
 # --------------------------------------------------------------------------
