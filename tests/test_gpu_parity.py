@@ -182,6 +182,61 @@ def test_room_set_full_size_sampled(torch_dev, oracle_lib):
     full_size_sampled(torch_dev, oracle_lib, li.room_set())
 
 
+@pytest.mark.parametrize("workload", ["office", "building"])
+def test_full_size_one_luminaire_exact(torch_dev, oracle_lib, workload):
+    """The forward kernel at the bench's full size and launch tuning (office:
+    2^26 paths, 5 hits; building floor: 2^28 paths, 6 hits), bit for bit
+    against the oracle for one luminaire's paths.  S is an integer sum, so
+    the difference of two full launches, one with every luminaire and one
+    with this luminaire rejected (negative power: it traces nothing), is
+    exactly its share; the oracle traces its paths alone, the others at zero
+    power.  The adjoint launch at the same size gives that luminaire's
+    gradient row from its own paths only, so the oracle's adjoint of the
+    luminaire alone (the same dO/dE) must agree with it to the gradient
+    bar."""
+    torch = torch_dev
+    from paper_2310_02043_amd.native import LtError, LT_EINVAL
+    c = li.office() if workload == "office" else li.building_floor()
+    sc, lights = c["scene"], c["lights"]
+    N, B, seed = c["paths"], c["max_hits"], c["seed"]
+    ctx = make_ctx(torch, sc, lights)
+    tuning = bench_tuning(sc, lights, N, B)
+    assert tuning is not None
+    ctx.set_tuning(**tuning)
+    say(f"{workload}: {sc.n_tris} triangles, {lights.n_lights} luminaires, {N} paths, tuning {tuning}")
+    l = 5
+    p = np.asarray(lights.params, np.float32).copy()
+    cfg = ctx.cfg(seed, N, B)
+    _, S_all = ctx.trace_forward(torch.tensor(p, device="cuda"), cfg)
+    assert ctx.sync() == 0
+    S_all = S_all.cpu().numpy().copy()
+    p_wo = p.copy()
+    p_wo[l, 5] = -1.0
+    _, S_wo = ctx.trace_forward(torch.tensor(p_wo, device="cuda"), cfg)
+    with pytest.raises(LtError) as ei:
+        ctx.sync()
+    assert ei.value.code == LT_EINVAL
+    S_l = S_all - S_wo.cpu().numpy()
+    only = p.copy()
+    only[:, 5] = 0.0
+    only[l, 5] = p[l, 5]
+    osc = oracle_lib.OracleScene(sc, use_bvh=True)
+    S_ref, _ = oracle_lib.forward(osc, oracle_lib.OracleLights(lights), only, seed, N, B)
+    say(f"  luminaire {l}: {np.count_nonzero(S_ref)} texels reached, "
+        f"bit-identical {np.mean(S_l == S_ref) * 100:.4f} %")
+    assert np.count_nonzero(S_ref) > 0
+    assert np.array_equal(S_l, S_ref)
+    E_all = oracle_lib.fixed_to_float(S_all)
+    Et = np.stack([li.painted_target(sc, float(np.mean(E_all[0])) * 1.5 + 1e-3, seed=3)])
+    _, g = oracle_lib.objective(E_all, Et, sc.texel_area())
+    grad_d = ctx.trace_adjoint(torch.tensor(p, device="cuda"), torch.tensor(g, device="cuda"), cfg)
+    assert ctx.sync() == 0
+    grad_ref, _ = oracle_lib.adjoint(osc, oracle_lib.OracleLights(lights), only, seed, N, B, g)
+    e = grad_rel(grad_d.cpu().numpy()[l], grad_ref[l])
+    say(f"  luminaire {l}: gradient row max rel err {e:.3e}")
+    assert e <= GRAD_BAR
+
+
 def full_size_sampled(torch, oracle_lib, c2, linear=False):
     sc, lights = c2["scene"], c2["lights"]
     ctx = make_ctx(torch, sc, lights)
