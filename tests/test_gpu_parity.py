@@ -182,10 +182,11 @@ def test_room_set_full_size_sampled(torch_dev, oracle_lib):
     full_size_sampled(torch_dev, oracle_lib, li.room_set())
 
 
-@pytest.mark.parametrize("workload", ["office", "building"])
+@pytest.mark.parametrize("workload", ["office", "building", "room_set"])
 def test_full_size_one_luminaire_exact(torch_dev, oracle_lib, workload):
     """The forward kernel at the bench's full size and launch tuning (office:
-    2^26 paths, 5 hits; building floor: 2^28 paths, 6 hits), bit for bit
+    2^26 paths, 5 hits; building floor: 2^28 paths, 6 hits; room set: 64
+    layouts x 2^22 paths, 4 hits, a luminaire of layout 37), bit for bit
     against the oracle for one luminaire's paths.  S is an integer sum, so
     the difference of two full launches, one with every luminaire and one
     with this luminaire rejected (negative power: it traces nothing), is
@@ -196,7 +197,7 @@ def test_full_size_one_luminaire_exact(torch_dev, oracle_lib, workload):
     bar."""
     torch = torch_dev
     from paper_2310_02043_amd.native import LtError, LT_EINVAL
-    c = li.office() if workload == "office" else li.building_floor()
+    c = {"office": li.office, "building": li.building_floor, "room_set": li.room_set}[workload]()
     sc, lights = c["scene"], c["lights"]
     N, B, seed = c["paths"], c["max_hits"], c["seed"]
     ctx = make_ctx(torch, sc, lights)
@@ -204,7 +205,7 @@ def test_full_size_one_luminaire_exact(torch_dev, oracle_lib, workload):
     assert tuning is not None
     ctx.set_tuning(**tuning)
     say(f"{workload}: {sc.n_tris} triangles, {lights.n_lights} luminaires, {N} paths, tuning {tuning}")
-    l = 5
+    l = 5 if workload != "room_set" else int(lights.layout_offsets[37]) + 2
     p = np.asarray(lights.params, np.float32).copy()
     cfg = ctx.cfg(seed, N, B)
     _, S_all = ctx.trace_forward(torch.tensor(p, device="cuda"), cfg)
@@ -227,7 +228,8 @@ def test_full_size_one_luminaire_exact(torch_dev, oracle_lib, workload):
     assert np.count_nonzero(S_ref) > 0
     assert np.array_equal(S_l, S_ref)
     E_all = oracle_lib.fixed_to_float(S_all)
-    Et = np.stack([li.painted_target(sc, float(np.mean(E_all[0])) * 1.5 + 1e-3, seed=3)])
+    Et = np.stack([li.painted_target(sc, float(np.mean(E_all[j])) * 1.5 + 1e-3, seed=3 + j)
+                   for j in range(lights.n_layouts)])
     _, g = oracle_lib.objective(E_all, Et, sc.texel_area())
     grad_d = ctx.trace_adjoint(torch.tensor(p, device="cuda"), torch.tensor(g, device="cuda"), cfg)
     assert ctx.sync() == 0
