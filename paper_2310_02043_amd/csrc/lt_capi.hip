@@ -288,10 +288,10 @@ int ensure_tiles(lt_ctx* c, long long ppl)
 // stack entries a segment can need: up to three pushes per level of the 4-wide tree
 int stack_need(const lt_ctx* c) { return 3 * c->depth + 1; }
 // overflow entries per lane: what the deepest segment can need beyond the
-// smallest LDS part of any instance (the adjoint's)
+// smallest LDS part of any instance (the colour adjoint's)
 int gstack_depth(const lt_ctx* c)
 {
-    return std::max(0, stack_need(c) - std::min(c->tune.lds_depth, kAdjLdsDepth));
+    return std::max(0, stack_need(c) - std::min({c->tune.lds_depth, kAdjLdsDepth, kColAdjLdsDepth}));
 }
 
 int ensure_gstack(lt_ctx* c, long long waves)

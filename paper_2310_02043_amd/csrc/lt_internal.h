@@ -15,7 +15,13 @@ constexpr int kPlocRadius = 16;       // nearest-neighbour window of the BVH bui
 constexpr int kBvhWidth = 4;          // children per node of the traversed tree
 constexpr int kEmptyChild = (int)0x80000000;  // unused child slot of a wide node
 constexpr int kNodeRows = 4;                  // 16-byte rows per wide node
-constexpr int kAdjLdsDepth = 12;              // traversal-stack entries in LDS of the plain and colour adjoint
+// traversal-stack entries in LDS of the plain adjoint: the most that six
+// of its waves per SIMD (6.5 KB each with their per-lane state) fit in a
+// CU's 160 KB
+constexpr int kAdjLdsDepth = 13;
+// the same for the colour adjoint at five waves per SIMD (7.75 KB each; at
+// 13 entries, 8 KB, its fifth block no longer fits)
+constexpr int kColAdjLdsDepth = 12;
 
 // sticky device status bits (the LT_STATUS_* values of the C ABI)
 constexpr unsigned kStatusOverflow = 1u;   // a texel accumulator reached 2^62

@@ -641,7 +641,7 @@ template <bool ADJ, bool STATS, int WPB, int LDS_D, int MODE>
 // eight waves per SIMD (64 VGPRs; the one spilled value is read only when a
 // proposal samples the emission), with the linear basis seven (at eight it
 // would spill its LDS stack address, read on every push and pop), the plain
-// adjoint six (80 VGPRs; with kAdjLdsDepth stack entries in LDS, 6.4 KB per
+// adjoint six (80 VGPRs; with kAdjLdsDepth stack entries in LDS, 6.5 KB per
 // wave), the other instances five, the directional ones four.
 __global__ void __launch_bounds__(WPB * 64)
     __attribute__((amdgpu_waves_per_eu(MODE >= 30 ? 4
@@ -652,11 +652,12 @@ __global__ void __launch_bounds__(WPB * 64)
 {
     constexpr bool DIR = MODE >= 30;               // directional texels of order MODE - 30
     constexpr int DORD = DIR ? MODE - 30 : 0;
-    // the plain and the colour adjoint keep kAdjLdsDepth stack entries in
-    // LDS: their per-lane state takes the rest of the budget of six (plain)
-    // or five (colour) waves per SIMD; the overflow part of the stack is
-    // sized for it
-    constexpr int LDS_S = (ADJ && (MODE == 0 || MODE == 2) && LDS_D > kAdjLdsDepth) ? kAdjLdsDepth : LDS_D;
+    // the plain and the colour adjoint keep kAdjLdsDepth / kColAdjLdsDepth
+    // stack entries in LDS: their per-lane state takes the rest of the
+    // budget of six (plain) or five (colour) waves per SIMD; the overflow
+    // part of the stack is sized for the smaller
+    constexpr int LDS_A = MODE == 2 ? kColAdjLdsDepth : kAdjLdsDepth;
+    constexpr int LDS_S = (ADJ && (MODE == 0 || MODE == 2) && LDS_D > LDS_A) ? LDS_A : LDS_D;
     __shared__ int s_stack[WPB * LDS_S * 64];
     // adjoint per-lane state read once per path (first-hit derivative
     // factors, running contribution sums), kept in LDS instead of registers
