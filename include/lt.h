@@ -115,7 +115,10 @@ typedef struct {
                                   drains its XCD's queue first, then helps the others */
     int32_t tile_paths;        /* paths per work tile (multiple of 64), 0 = automatic */
     int32_t refill_threshold;  /* lanes that must finish a segment before hit processing */
-    int32_t lds_depth;         /* traversal stack entries kept in LDS: 16 or 32 */
+    int32_t lds_depth;         /* traversal stack entries kept in LDS: 16 or 32 (the plain and
+                                  colour adjoint keep at most 13 and 12, the most their
+                                  occupancy leaves room for); the rest overflows to a
+                                  device buffer the context sizes by the tree's depth */
     int32_t tri_share;         /* 1..8: a traversal iteration runs the queued triangle tests once at
                                   least tri_share/8 of the traversing lanes hold some (or all do),
                                   node steps otherwise; 0: both kinds in every iteration */
