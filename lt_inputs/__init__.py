@@ -10,5 +10,5 @@ values, fixed by a seed.
 from .scenes import (  # noqa: F401
     PATCH_DTYPE, LIGHT_DTYPE, Scene, Lights, SceneBuilder,
     box_room, office, room_set, building_floor, plane_scene, closed_box,
-    painted_target, texel_centers, perturb_params, random_scene_tiny,
+    painted_target, texel_centers, perturb_params, random_scene_tiny, crossing_slivers,
 )

@@ -645,3 +645,24 @@ def random_scene_tiny(seed: int, n_quads: int = 24, extent: float = 2.0) -> Scen
         sb.quads(o, a * rng.uniform(0.2, 1.5), b * rng.uniform(0.2, 1.5), rng.uniform(0.3, 0.9),
                  res=(4, 4))
     return sb.build("tiny_%d" % seed, fixed_res=(4, 4))
+
+
+def crossing_slivers(seed: int = 0x5C1, n_dirs: int = 16384, centre=(2.0, 2.0, 1.5), half: float = 1.0,
+                     off: float = 0.01, width: float = 0.02, albedo: float = 0.7):
+    """Narrow quads (2 half x width) in random directions whose every component
+    is at least 0.2, each passing `off` beside and `off` above `centre`, so
+    that every triangle's bounding box contains the centre (an adversarial
+    tree for a traversal stack: a point light placed there enters every box
+    at distance 0).  Returns (scene, centre)."""
+    rng = np.random.default_rng(seed)
+    u = rng.normal(size=(n_dirs, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    u = u[np.all(np.abs(u) >= 0.2, axis=1)][: n_dirs // 2]
+    u = np.concatenate([u, -u[:, [1, 2, 0]]])
+    v = np.cross(u, rng.normal(size=u.shape))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    nrm = np.cross(u, v)
+    c = np.asarray(centre, np.float64)
+    sb = SceneBuilder()
+    sb.quads(c - half * u + off * v - off * nrm, 2 * half * u, width * v, albedo, res=(2, 1))
+    return sb.build("crossing_slivers", fixed_res=(2, 1)), c

@@ -505,26 +505,13 @@ def _guaranteed_stack_depth(nodes, point):
 def test_crossing_slivers_overflow_stack(torch_dev, oracle_lib, lds_depth):
     """15550 narrow 2 m x 2 cm quads in random directions, each passing 1 cm
     beside and 1 cm above a point light: every triangle's box, hence every
-    box of the tree,
-    contains the light, so a segment from it pushes three children at every
+    box of the tree, contains the light, so a segment from it pushes three
+    children at every
     level and its traversal stack runs past its LDS entries (checked on the
     device's own tree) into the wave's overflow area.  Forward bit-identical,
     gradients to the bar, with 16 and 32 LDS entries."""
     torch = torch_dev
-    n, R, off, w = 16384, 1.0, 0.01, 0.02
-    rng = np.random.default_rng(0x5C1)
-    u = rng.normal(size=(n, 3))
-    u /= np.linalg.norm(u, axis=1, keepdims=True)
-    ok = np.all(np.abs(u) >= 0.2, axis=1)
-    u = u[ok][: n // 2]
-    u = np.concatenate([u, -u[:, [1, 2, 0]]])
-    v = np.cross(u, rng.normal(size=u.shape))
-    v /= np.linalg.norm(v, axis=1, keepdims=True)
-    nrm = np.cross(u, v)
-    pl = np.array([2.0, 2.0, 1.5])
-    sb = li.SceneBuilder()
-    sb.quads(pl - R * u + off * v - off * nrm, 2 * R * u, w * v, 0.7, res=(2, 1))
-    sc = sb.build("crossing_slivers", fixed_res=(2, 1))
+    sc, pl = li.crossing_slivers()
     lights = make_lights([POINT], [0.0], [(0, 0)], [0], [[pl[0], pl[1], pl[2], 0, 0, 10.0]])
     ctx = make_ctx(torch, sc, lights)
     nodes, _ = ctx.bvh()

@@ -95,6 +95,16 @@ def test_pt_batched_layouts(torch_dev, oracle_lib):
     run_pt(torch_dev, oracle_lib, c3["scene"], c3["lights"], 0xB2, 1, 2, use_bvh=True)
 
 
+def test_pt_crossing_slivers(torch_dev, oracle_lib):
+    """Narrow quads crossing around the point light (every box of the tree
+    contains it, so traversals toward and from it run deep into the
+    traversal stack's overflow area), one sample per texel, 3 path
+    vertices."""
+    sc, c = li.crossing_slivers(n_dirs=4096)
+    lights = make_lights([POINT], [0.0], [(0, 0)], [0], [[c[0], c[1], c[2], 0, 0, 10.0]])
+    run_pt(torch_dev, oracle_lib, sc, lights, 0xB3, 1, 3, use_bvh=True)
+
+
 def test_pt_invalid_arguments(torch_dev):
     torch = torch_dev
     from paper_2310_02043_amd.native import LtError
