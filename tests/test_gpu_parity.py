@@ -239,6 +239,62 @@ def test_full_size_one_luminaire_exact(torch_dev, oracle_lib, workload):
     assert e <= GRAD_BAR
 
 
+@pytest.mark.parametrize("variant", ["linear", "colour"])
+def test_office_full_size_one_luminaire_variants(torch_dev, oracle_lib, variant):
+    """The office at full size (2^26 paths, 5 hits) and bench tuning with the
+    piecewise-linear texel basis or in colour (per-luminaire channel weights,
+    per-patch channel albedo): one luminaire's texels, isolated as the
+    integer difference of a launch with every luminaire and one with it
+    rejected, bit-identical to the oracle's for that luminaire alone."""
+    torch = torch_dev
+    from paper_2310_02043_amd.native import LtError, LT_EINVAL
+    c = li.office()
+    sc, lights = c["scene"], c["lights"]
+    N, B, seed = c["paths"], c["max_hits"], c["seed"]
+    ctx = make_ctx(torch, sc, lights)
+    ctx.set_tuning(**bench_tuning(sc, lights, N, B))
+    if variant == "colour":
+        rng = np.random.default_rng(seed)
+        alb = rng.uniform(0.3, 0.8, (sc.n_patches, 3)).astype(np.float32)
+        col = rng.dirichlet([2.0, 2.0, 2.0], lights.n_lights).astype(np.float32)
+        ctx.set_albedo_rgb(alb)
+        c_d = torch.tensor(col, device="cuda")
+        cfg = ctx.cfg(seed, N, B)
+
+        def fwd(pp):
+            return ctx.trace_forward_rgb(torch.tensor(pp, device="cuda"), c_d, cfg)[1]
+
+        osc = oracle_lib.OracleScene(sc, use_bvh=True, albedo_rgb=alb)
+        ol = oracle_lib.OracleLights(lights, col)
+    else:
+        cfg = ctx.cfg(seed, N, B, linear=True)
+
+        def fwd(pp):
+            return ctx.trace_forward(torch.tensor(pp, device="cuda"), cfg)[1]
+
+        osc = oracle_lib.OracleScene(sc, use_bvh=True, basis="linear")
+        ol = oracle_lib.OracleLights(lights)
+    l = 9
+    p = np.asarray(lights.params, np.float32).copy()
+    S_all = fwd(p).cpu().numpy().copy()
+    assert ctx.sync() == 0
+    p_wo = p.copy()
+    p_wo[l, 5] = -1.0
+    S_wo = fwd(p_wo).cpu().numpy()
+    with pytest.raises(LtError) as ei:
+        ctx.sync()
+    assert ei.value.code == LT_EINVAL
+    only = p.copy()
+    only[:, 5] = 0.0
+    only[l, 5] = p[l, 5]
+    S_ref, _ = oracle_lib.forward(osc, ol, only, seed, N, B)
+    S_l = S_all - S_wo
+    say(f"office {variant}: luminaire {l}, {np.count_nonzero(S_ref)} texel values reached, "
+        f"bit-identical {np.mean(S_l == S_ref) * 100:.4f} %")
+    assert np.count_nonzero(S_ref) > 0
+    assert np.array_equal(S_l, S_ref)
+
+
 def full_size_sampled(torch, oracle_lib, c2, linear=False):
     sc, lights = c2["scene"], c2["lights"]
     ctx = make_ctx(torch, sc, lights)
