@@ -97,6 +97,8 @@ struct lt_ctx {
     int n_tiles = 0;
     int2* d_range = nullptr;
     long long* d_npaths = nullptr;
+    long long* d_rec_base = nullptr;  // two-pass adjoint: first record of each luminaire's paths [L]
+    long long rec_paths = 0;          // paths of all layouts: records per field
 
     // scratch
     unsigned long long* d_misses = nullptr;
@@ -118,6 +120,8 @@ struct lt_ctx {
     size_t partials8_cap = 0;
     float* d_cone = nullptr;          // cone-angle adjoint: [L,5] per-light constants
     int cone_cap = 0;
+    float* d_rec = nullptr;           // two-pass adjoint: first-hit records [kRecFields][rec_paths]
+    size_t rec_cap = 0;               // floats d_rec holds
     size_t partials7_cap = 0;
 
     lt_tuning tune;
@@ -200,8 +204,9 @@ void free_scene(lt_ctx* c)
 
 void free_tiles(lt_ctx* c)
 {
-    hipFree(c->d_tiles); hipFree(c->d_range); hipFree(c->d_npaths);
-    c->d_tiles = nullptr; c->d_range = nullptr; c->d_npaths = nullptr;
+    hipFree(c->d_tiles); hipFree(c->d_range); hipFree(c->d_npaths); hipFree(c->d_rec_base);
+    c->d_tiles = nullptr; c->d_range = nullptr; c->d_npaths = nullptr; c->d_rec_base = nullptr;
+    c->rec_paths = 0;
     c->tiles_ppl = -1;
     c->tiles_tp = -1;
     c->n_tiles = 0;
@@ -248,13 +253,16 @@ int ensure_tiles(lt_ctx* c, long long ppl)
     if (c->tiles_ppl == ppl && c->tiles_tp == tp) return LT_OK;
     std::vector<int4> tiles;
     std::vector<int2> range(c->L);
-    std::vector<long long> np(c->L);
+    std::vector<long long> np(c->L), rb(c->L);
+    long long total = 0;
     for (int j = 0; j < c->n_layouts; ++j) {
         const int l0 = c->offs[j], l1 = c->offs[j + 1];
         for (int gl = l0; gl < l1; ++gl) {
             const long long nl = paths_of_light(ppl, l1 - l0, gl - l0);
             if (nl > 0xFFFFFFFFll) return fail(c, LT_EINVAL, "more than 2^32 paths for one light");
             np[gl] = nl;
+            rb[gl] = total;
+            total += nl;
             range[gl].x = (int)tiles.size();
             for (long long f = 0; f < nl; f += tp) {
                 const long long cnt = std::min<long long>(tp, nl - f);
@@ -269,6 +277,9 @@ int ensure_tiles(lt_ctx* c, long long ppl)
     HIPCHK(c, hipMalloc(&c->d_tiles, sizeof(int4) * std::max<size_t>(tiles.size(), 1)));
     HIPCHK(c, hipMalloc(&c->d_range, sizeof(int2) * c->L));
     HIPCHK(c, hipMalloc(&c->d_npaths, sizeof(long long) * c->L));
+    HIPCHK(c, hipMalloc(&c->d_rec_base, sizeof(long long) * c->L));
+    HIPCHK(c, hipMemcpy(c->d_rec_base, rb.data(), sizeof(long long) * c->L, hipMemcpyHostToDevice));
+    c->rec_paths = total;
     HIPCHK(c, hipMemcpy(c->d_tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->d_range, range.data(), sizeof(int2) * c->L, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->d_npaths, np.data(), sizeof(long long) * c->L, hipMemcpyHostToDevice));
@@ -282,6 +293,20 @@ int ensure_tiles(lt_ctx* c, long long ppl)
         HIPCHK(c, hipMalloc(&c->d_partials, sizeof(double) * 6 * std::max(c->n_tiles, 1)));
         c->partials_cap = (size_t)std::max(c->n_tiles, 1) * 6;
     }
+    return LT_OK;
+}
+
+// the two-pass adjoint's record planes for the current tiles' paths
+int ensure_rec(lt_ctx* c)
+{
+    const size_t need = (size_t)kRecFields * (size_t)std::max(c->rec_paths, 1ll);
+    if (need <= c->rec_cap) return LT_OK;
+    free_graphs(c);
+    hipFree(c->d_rec);
+    c->d_rec = nullptr;
+    c->rec_cap = 0;
+    HIPCHK(c, hipMalloc(&c->d_rec, sizeof(float) * need));
+    c->rec_cap = need;
     return LT_OK;
 }
 
@@ -509,7 +534,7 @@ void lt_destroy(lt_ctx* c)
     hipFree(c->d_misses); hipFree(c->d_flags); hipFree(c->d_stats); hipFree(c->d_queue);
     hipFree(c->d_objpart); hipFree(c->d_partials); hipFree(c->d_gstack); hipFree(c->d_ptgrad);
     hipFree(c->d_partials_col); hipFree(c->d_partials7); hipFree(c->d_pfd);
-    hipFree(c->d_partials8); hipFree(c->d_cone);
+    hipFree(c->d_partials8); hipFree(c->d_cone); hipFree(c->d_rec);
     if (c->ev_in) hipEventDestroy(c->ev_in);
     if (c->ev_out) hipEventDestroy(c->ev_out);
     if (c->gstream) hipStreamDestroy(c->gstream);
@@ -767,11 +792,25 @@ int lt_trace_adjoint(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     a.g = d_dOdE;
     a.partials = c->d_partials;
     a.bin_hist = d_bin_hist;
+    // without the histogram, in the box basis and below 2^30 paths per
+    // layout (a luminaire's records then lie within 32-bit byte offsets) the
+    // adjoint runs in two passes: the trace records each path's first hit
+    // and adjoint sum, a second kernel forms the paths' contributions and the
+    // tiles' sums
+    const bool two_pass = !d_bin_hist && !(cfg->flags & LT_FLAG_LINEAR) && cfg->paths_per_layout < (1ll << 30);
+    if (two_pass) {
+        rc = ensure_rec(c);
+        if (rc) return rc;
+        a.rec = c->d_rec;
+        a.rec_stride = c->rec_paths;
+        a.rec_base = c->d_rec_base;
+    }
     const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
     auto body = [&](hipStream_t st) -> hipError_t {
         hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess && d_bin_hist) e = launch_fill_f32(d_bin_hist, (long long)c->L * 1024, 0.0f, st);
         if (e == hipSuccess) e = timed_trace(c, true, graph, a, st);
+        if (e == hipSuccess && two_pass) e = launch_rec_grad(a, c->d_partials, st);
         if (e == hipSuccess) e = launch_grad_reduce(c->d_partials, c->d_range, c->L, d_grad, st);
         return e;
     };
@@ -1481,7 +1520,8 @@ int lt_info_get(const lt_ctx* c, lt_info* out)
     out->bvh_nodes = c->n_nodes;
     out->bvh_depth = c->depth;
     out->device_bytes = (int64_t)c->n_nodes * 16 * kNodeRows + c->n_tris * 48 + (int64_t)c->n_patches * sizeof(DevPatch) +
-                        c->K * 4 + (int64_t)c->gstack_cap * 4 + (int64_t)c->partials_cap * 8;
+                        c->K * 4 + (int64_t)c->gstack_cap * 4 + (int64_t)c->partials_cap * 8 +
+                        (int64_t)c->rec_cap * 4;
     out->n_lights = c->L;
     out->n_layouts = c->n_layouts;
     return LT_OK;

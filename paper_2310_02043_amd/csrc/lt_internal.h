@@ -99,7 +99,16 @@ struct TraceArgs {
     double* vote;               // [K] texels of the light's layout
     int vote_light;             // global light index
     int vote_param;             // 0..5
+    // two-pass adjoint (grey, box basis, no histogram): instead of the
+    // per-tile sums, each path leaves a first-hit record, kRecFields planes of
+    // rec_stride floats (x_1 xyz, origin y xyz, patch | flip << 31, a_u, a_v,
+    // Phi_r, s_r), at index rec_base[light] + path; null otherwise
+    float* rec;
+    long long rec_stride;
+    const long long* rec_base;
 };
+
+constexpr int kRecFields = 11;   // floats per path of the two-pass adjoint's records
 
 // Object-space path tracing over the texels of one layout.
 struct PtArgs {
@@ -183,6 +192,9 @@ hipError_t launch_objective(const float* E, const float* Et, const float* alpha,
                             long long n, float* g, double* partials, double* O, hipStream_t st);
 hipError_t launch_grad_reduce(const double* partials, const int2* tile_range, int n_lights, float* grad,
                               hipStream_t st);
+// second pass of the two-pass adjoint: per-tile FP64 partial sums [n_tiles, 6]
+// of the recorded paths' contributions
+hipError_t launch_rec_grad(const TraceArgs& a, double* partials, hipStream_t st);
 // the box [lo, hi] that maps luminaire parameters to network inputs, and a
 // per-parameter factor, passed by value
 struct ParamBox {

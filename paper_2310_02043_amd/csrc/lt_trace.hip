@@ -450,6 +450,7 @@ struct HitInfo {
     V3 x, no;
     long long k;
     float inva, rho;
+    bool flip;   // no is the patch normal negated (the ray arrives from its back)
 };
 
 __device__ __forceinline__ HitInfo hit_info(const Ray& r, float tb, int qb, const DevPatch* __restrict__ patches)
@@ -471,7 +472,8 @@ __device__ __forceinline__ HitInfo hit_info(const Ray& r, float tb, int qb, cons
     hi.rho = nr.w;
     const V3 nq = xyz(nr);
     const float nd = dot(nq, v3(r.dx, r.dy, r.dz));
-    hi.no = nd < 0.0f ? nq : v3(-nq.x, -nq.y, -nq.z);
+    hi.flip = !(nd < 0.0f);
+    hi.no = hi.flip ? v3(-nq.x, -nq.y, -nq.z) : nq;
     return hi;
 }
 
@@ -646,12 +648,16 @@ template <bool ADJ, bool STATS, int WPB, int LDS_D, int MODE>
 __global__ void __launch_bounds__(WPB * 64)
     __attribute__((amdgpu_waves_per_eu(MODE >= 30 ? 4
                                                   : (!ADJ && !STATS && MODE == 0 ? 8
-                                                     : (!ADJ && !STATS && MODE == 1 ? 7
+                                                     : (!STATS && ((!ADJ && MODE == 1) || MODE == 7) ? 7
                                                                                     : (ADJ && !STATS && MODE == 0 ? 6 : 5))))))
     k_trace(TraceArgs a)
 {
     constexpr bool DIR = MODE >= 30;               // directional texels of order MODE - 30
     constexpr int DORD = DIR ? MODE - 30 : 0;
+    // MODE 7: the first pass of the two-pass adjoint (grey, box basis, no
+    // histogram or map): each path leaves a first-hit record and its adjoint
+    // sum instead of adding its contribution to the tile's sums
+    constexpr bool REC = ADJ && MODE == 7;
     // the plain and the colour adjoint keep kAdjLdsDepth / kColAdjLdsDepth
     // stack entries in LDS: their per-lane state takes the rest of the
     // budget of six (plain) or five (colour) waves per SIMD; the overflow
@@ -662,7 +668,7 @@ __global__ void __launch_bounds__(WPB * 64)
     // adjoint per-lane state read once per path (first-hit derivative
     // factors, running contribution sums), kept in LDS instead of registers
     constexpr int NPAR = MODE == 4 ? 7 : (MODE == 6 ? 8 : 6);   // 4: rotation vector, 6: cone angles
-    __shared__ float s_adj[ADJ ? WPB * 2 * NPAR * 64 : 1];
+    __shared__ float s_adj[ADJ && !REC ? WPB * 2 * NPAR * 64 : 1];
     // adjoint with a gradient-contribution map (grey irradiance, box or
     // linear basis): texel of the first hit
     constexpr bool VOTES = ADJ && MODE <= 1;
@@ -675,7 +681,7 @@ __global__ void __launch_bounds__(WPB * 64)
     __shared__ float s_dir[DIR ? WPB * DIRW * 64 : 1];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
-    float* adj = s_adj + (ADJ ? wib * 2 * NPAR * 64 + lane : 0);
+    float* adj = s_adj + (ADJ && !REC ? wib * 2 * NPAR * 64 + lane : 0);
     int k1_reg = 0;
     int* k1 = VOTES ? s_k1 + wib * 64 + lane : &k1_reg;
     float* rgbs = s_rgb + (MODE == 2 ? wib * 7 * 64 + lane : 0);
@@ -734,6 +740,16 @@ __global__ void __launch_bounds__(WPB * 64)
         const int* guide = prop_on ? a.prop_guide + 1025 * (long long)ti.x : nullptr;
         float* hist = (ADJ && a.bin_hist != nullptr && (L.type == 1 || L.type == 2)) ? a.bin_hist + 1024 * (long long)ti.x : nullptr;
         double* vote = (ADJ && a.vote != nullptr && ti.x == a.vote_light) ? a.vote : nullptr;
+        // this luminaire's path 0 in the record planes, wave-uniform (the
+        // host keeps a luminaire's paths under 2^30, so a path's byte offset
+        // from it fits 32 bits)
+        float* rec0 = nullptr;
+        if (REC) {
+            const long long rb = a.rec_base[ti.x];
+            const long long rbu = ((long long)__builtin_amdgcn_readfirstlane((int)(rb >> 32)) << 32) |
+                                  (long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(rb & 0xFFFFFFFFll));
+            rec0 = a.rec + rbu;
+        }
 
         int next = 0;          // paths of this tile handed out so far (uniform)
         bool alive = false;    // lane holds a path
@@ -742,7 +758,7 @@ __global__ void __launch_bounds__(WPB * 64)
         int h = 0, skip = -1, ebin = -1;
         float T = 1.0f, s_r = 0.0f, au = 0.0f, av = 0.0f, phi_r = 0.0f, wq = 0.0f;
         float tdl = 0.0f;      // direct differentiation: dlog_j of the first hit
-        if (ADJ) {
+        if (ADJ && !REC) {
 #pragma unroll
             for (int c = 0; c < 2 * NPAR; ++c) adj[c * 64] = 0.0f;
         }
@@ -983,7 +999,16 @@ __global__ void __launch_bounds__(WPB * 64)
                             rgbs[128] = rgbs[128] + (g[a.K + hi.k] * hi.inva) * rgbs[0];
                             rgbs[192] = rgbs[192] + (g[2 * a.K + hi.k] * hi.inva) * rgbs[64];
                         }
-                        if (h == 1) {
+                        if (h == 1 && REC) {
+                            // what the path's dlog needs, for the second pass
+                            const long long st = a.rec_stride;
+                            const unsigned off = pid << 2;
+                            const float v[10] = {hi.x.x, hi.x.y, hi.x.z, r.ox, r.oy, r.oz,
+                                                 __uint_as_float((unsigned)s.qb | (hi.flip ? 0x80000000u : 0u)),
+                                                 au, av, phi_r};
+#pragma unroll
+                            for (int f = 0; f < 10; ++f) *(float*)((char*)(rec0 + f * st) + off) = v[f];
+                        } else if (h == 1) {
                             float dl[NPAR];
                             first_hit_dlog<MODE == 4>(L, hi.x, v3(r.ox, r.oy, r.oz), hi.no, au, av, dl);
                             if constexpr (MODE == 6)
@@ -1043,7 +1068,11 @@ __global__ void __launch_bounds__(WPB * 64)
                     }
                 }
                 if (end_path) {
-                    if (ADJ && h >= 1) {
+                    if (REC) {
+                        // every path leaves its adjoint sum (0 without a hit,
+                        // which tells the second pass to skip its record)
+                        *(float*)((char*)(rec0 + 10 * a.rec_stride) + (pid << 2)) = s_r;
+                    } else if (ADJ && h >= 1) {
                         // colour: every channel shares the path, so the
                         // geometric terms take the colour-weighted adjoint
                         // sum, and dO/dc_ch gathers s_ch Phi_r
@@ -1099,7 +1128,7 @@ __global__ void __launch_bounds__(WPB * 64)
                 }
             }
         }
-        if (ADJ) {
+        if (ADJ && !REC) {
             double acc[NPAR];
 #pragma unroll
             for (int c = 0; c < NPAR; ++c) acc[c] = wave_sum((double)adj[(NPAR + c) * 64]);
@@ -1657,6 +1686,50 @@ __global__ void __launch_bounds__(64) k_grad_reduce(const double* __restrict__ p
         for (int c = 0; c < NC; ++c) grad[NC * l + c] = (float)acc[c];
 }
 
+// Second pass of the two-pass adjoint (Alg. 2's update at the end of a
+// path): each recorded path of a tile contributes s_r (Phi_r dlog_r), the
+// first hit's dlog from its record (the oriented normal is the patch's, or
+// its negation), the same FP32 products as the one-pass kernel; the tile's
+// sums are FP64, thread-strided in path order and then a fixed tree.
+__global__ void __launch_bounds__(256) k_rec_grad(const int4* __restrict__ tiles, const DevLight* __restrict__ lights,
+                                                  const DevPatch* __restrict__ patches, const float* __restrict__ rec,
+                                                  long long stride, const long long* __restrict__ rec_base,
+                                                  double* __restrict__ partials)
+{
+    __shared__ double sh[6][256];
+    const int4 ti = tiles[blockIdx.x];
+    const DevLight& L = lights[ti.x];
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (!L.invalid) {   // a rejected luminaire traced nothing, so its records are stale
+        const long long base = rec_base[ti.x] + (long long)(uint32_t)ti.y;
+        for (int i = threadIdx.x; i < ti.z; i += 256) {
+            const long long j = base + i;
+            const float se = rec[10 * stride + j];
+            if (se == 0.0f) continue;   // no hit, or nothing to add
+            const V3 x1 = v3(rec[j], rec[stride + j], rec[2 * stride + j]);
+            const V3 y = v3(rec[3 * stride + j], rec[4 * stride + j], rec[5 * stride + j]);
+            const unsigned qf = __float_as_uint(rec[6 * stride + j]);
+            const V3 nq = xyz(patches[qf & 0x7FFFFFFFu].n_rho);
+            const V3 n1 = (qf >> 31) ? v3(-nq.x, -nq.y, -nq.z) : nq;
+            const float phi_r = rec[9 * stride + j];
+            float dl[6];
+            first_hit_dlog(L, x1, y, n1, rec[7 * stride + j], rec[8 * stride + j], dl);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) acc[c] += (double)(se * (phi_r * dl[c]));
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sh[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) partials[(long long)blockIdx.x * 6 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
 // Per-texel area A_k from the patch table (binary search of texel_base).
 __global__ void k_texel_area(const float* __restrict__ patch_area, const long long* __restrict__ base,
                              int n_patches, long long K, float* __restrict__ A)
@@ -1793,6 +1866,13 @@ hipError_t launch_wpb(const TraceArgs& a, int lds_depth, int n_cu, hipStream_t s
             launch_persistent<ADJ, STATS, WPB, 16, 1>(a, n_cu, st);
         else
             launch_persistent<ADJ, STATS, WPB, 32, 1>(a, n_cu, st);
+    } else if (ADJ && !STATS && a.rec != nullptr) {
+        if constexpr (ADJ && !STATS) {
+            if (lds_depth == 16)
+                launch_persistent<ADJ, STATS, WPB, 16, 7>(a, n_cu, st);
+            else
+                launch_persistent<ADJ, STATS, WPB, 32, 7>(a, n_cu, st);
+        }
     } else {
         if (lds_depth == 16)
             launch_persistent<ADJ, STATS, WPB, 16, 0>(a, n_cu, st);
@@ -1972,6 +2052,13 @@ hipError_t launch_objective(const float* E, const float* Et, const float* alpha,
 {
     k_objective<<<kObjBlocks, 256, 0, st>>>(E, Et, alpha, A, K, n, g, partials);
     k_objective_final<<<1, 256, 0, st>>>(partials, kObjBlocks, O);
+    return hipGetLastError();
+}
+
+hipError_t launch_rec_grad(const TraceArgs& a, double* partials, hipStream_t st)
+{
+    if (a.n_tiles > 0)
+        k_rec_grad<<<a.n_tiles, 256, 0, st>>>(a.tiles, a.lights, a.patches, a.rec, a.rec_stride, a.rec_base, partials);
     return hipGetLastError();
 }
 

@@ -55,7 +55,12 @@ def run_cone(torch, oracle_lib, scene, lights, seed, N, B, use_bvh):
     plain = ctx.trace_adjoint(p_d, g_d, cfg)
     assert ctx.sync() == 0
     grad_ref, gc_ref, _ = oracle_lib.adjoint_cone(osc, ol, lights.params, seed, N, B, g)
-    assert torch.equal(grad_d, plain)
+    # the same per-path contributions to the six parameters; the plain adjoint
+    # sums them per tile in FP64 in a second pass, this kernel per lane in FP32
+    # first
+    e0 = max_rel(grad_d.cpu().numpy(), plain.cpu().numpy())
+    say(f"  position, tilt and power vs the plain adjoint: max rel diff {e0:.2e}")
+    assert e0 <= 1e-5
     soft = lights.static["type"] == SOFT
     assert np.all(gc_d.cpu().numpy()[~soft] == 0.0)
     e1 = max_rel(grad_d.cpu().numpy(), grad_ref)

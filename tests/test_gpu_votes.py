@@ -136,7 +136,13 @@ def test_votes_office_full_size(torch_dev, oracle_lib):
     light, j = 7, 3
     v_d, grad_d = ctx.gradient_votes(p_d, g_d, cfg, light, j)
     assert ctx.sync() == 0
-    assert np.array_equal(grad_d.cpu().numpy(), grad_plain)
+    # the same per-path contributions; the plain adjoint sums them per tile in
+    # FP64 in a second pass, the map's kernel per lane in FP32 first
+    gv = grad_d.cpu().numpy().astype(np.float64)
+    gp = grad_plain.astype(np.float64)
+    e = float(np.max(np.abs(gv - gp) / np.maximum(np.abs(gp), 1e-6 * np.abs(gp).max())))
+    say(f"  gradient beside the map vs the plain adjoint: max rel diff {e:.2e}")
+    assert e <= 1e-5
     v = v_d.cpu().numpy()
     scale = float(np.abs(v).sum())
     say(f"  sum of the map {v.sum():.6e} vs gradient {grad_plain[light, j]:.6e}")

@@ -1,6 +1,10 @@
 """The allocation-free adjoint entry point (lt_trace_adjoint_noalloc) against
-lt_trace_adjoint through the C ABI: the same gradient (bit for bit: the same
-kernels, work tiles and reduction order) on two calls in a row, the second
+lt_trace_adjoint through the C ABI: the same gradient (the same per-path
+contributions over the same work tiles; lt_trace_adjoint sums them per tile
+in FP64 in a second pass, the allocation-free form per lane in FP32 first,
+whose rounding, on luminaires with few paths and cancelling contributions,
+reaches a few 1e-4 of a component: the gradient bar, 1e-3, applies) on two
+calls in a row, the second
 with a smaller input, on the box room and the 64-layout room set (1695
 luminaires of uneven counts: the device-built tile table); a request too
 large for its fixed scratch is refused with an error."""
@@ -58,9 +62,8 @@ def test_noalloc_adjoint_matches_adjoint(torch_dev, case):
         a, b = grad_na.cpu().numpy().astype(np.float64), ref.cpu().numpy().astype(np.float64)
         scale = np.maximum(np.abs(b), 1e-6 * np.abs(b).max())
         err = float(np.max(np.abs(a - b) / scale))
-        say(f"  max rel diff to lt_trace_adjoint {err:.3e}, bit-identical {np.array_equal(a, b)}")
+        say(f"  max rel diff to lt_trace_adjoint {err:.3e}")
         assert np.isfinite(a).all() and err <= 1e-3
-        assert np.array_equal(a, b)
 
 
 def test_noalloc_refuses_oversized_work(torch_dev):
