@@ -792,12 +792,12 @@ int lt_trace_adjoint(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     a.g = d_dOdE;
     a.partials = c->d_partials;
     a.bin_hist = d_bin_hist;
-    // without the histogram, in the box basis and below 2^30 paths per
-    // layout (a luminaire's records then lie within 32-bit byte offsets) the
-    // adjoint runs in two passes: the trace records each path's first hit
-    // and adjoint sum, a second kernel forms the paths' contributions and the
-    // tiles' sums
-    const bool two_pass = !d_bin_hist && !(cfg->flags & LT_FLAG_LINEAR) && cfg->paths_per_layout < (1ll << 30);
+    // in the box basis and below 2^30 paths per layout (a luminaire's records
+    // then lie within 32-bit byte offsets) the adjoint runs in two passes:
+    // the trace records each path's first hit and adjoint sum, a second
+    // kernel forms the paths' contributions, the tiles' sums and the
+    // training histogram
+    const bool two_pass = !(cfg->flags & LT_FLAG_LINEAR) && cfg->paths_per_layout < (1ll << 30);
     if (two_pass) {
         rc = ensure_rec(c);
         if (rc) return rc;

@@ -99,16 +99,17 @@ struct TraceArgs {
     double* vote;               // [K] texels of the light's layout
     int vote_light;             // global light index
     int vote_param;             // 0..5
-    // two-pass adjoint (grey, box basis, no histogram): instead of the
-    // per-tile sums, each path leaves a first-hit record, kRecFields planes of
-    // rec_stride floats (x_1 xyz, origin y xyz, patch | flip << 31, a_u, a_v,
-    // Phi_r, s_r), at index rec_base[light] + path; null otherwise
+    // two-pass adjoint (grey, box basis): instead of the per-tile sums, each
+    // path leaves a first-hit record, kRecFields planes of rec_stride floats
+    // (x_1 xyz, origin y xyz, patch | flip << 31, a_u, a_v, Phi_r, s_r, and
+    // with the training histogram the emission cell and its weight), at index
+    // rec_base[light] + path; null otherwise
     float* rec;
     long long rec_stride;
     const long long* rec_base;
 };
 
-constexpr int kRecFields = 11;   // floats per path of the two-pass adjoint's records
+constexpr int kRecFields = 13;   // floats per path of the two-pass adjoint's records
 
 // Object-space path tracing over the texels of one layout.
 struct PtArgs {

@@ -797,6 +797,13 @@ __global__ void __launch_bounds__(WPB * 64)
                 if (newp) {
                     emit_from(L, ru, pid, stream_id, a.key0, a.key1, pdf, cdf, guide, a.alpha_plain, hist != nullptr, y,
                               dir, au, av, phi_r, ebin, wq);
+                    if (REC && hist) {
+                        // the emission cell and its weight, for the second
+                        // pass's training histogram
+                        const long long st = a.rec_stride;
+                        *(float*)((char*)(rec0 + 11 * st) + (pid << 2)) = __int_as_float(ebin);
+                        *(float*)((char*)(rec0 + 12 * st) + (pid << 2)) = wq;
+                    }
                 } else {
                     y = v3(r.ox + s.tb * r.dx, r.oy + s.tb * r.dy, r.oz + s.tb * r.dz);   // as in hit_info
                     dir = cosine_dir(bn, u24(ru.x), u24(ru.y));
@@ -1690,15 +1697,19 @@ __global__ void __launch_bounds__(64) k_grad_reduce(const double* __restrict__ p
 // path): each recorded path of a tile contributes s_r (Phi_r dlog_r), the
 // first hit's dlog from its record (the oriented normal is the patch's, or
 // its negation), the same FP32 products as the one-pass kernel; the tile's
-// sums are FP64, thread-strided in path order and then a fixed tree.
+// sums are FP64, thread-strided in path order and then a fixed tree.  With
+// the training histogram each path also adds its squared normalised
+// contribution, weighted, to its emission cell, as the one-pass kernel does.
 __global__ void __launch_bounds__(256) k_rec_grad(const int4* __restrict__ tiles, const DevLight* __restrict__ lights,
                                                   const DevPatch* __restrict__ patches, const float* __restrict__ rec,
                                                   long long stride, const long long* __restrict__ rec_base,
+                                                  float* __restrict__ bin_hist, const float* __restrict__ inv_sigma,
                                                   double* __restrict__ partials)
 {
     __shared__ double sh[6][256];
     const int4 ti = tiles[blockIdx.x];
     const DevLight& L = lights[ti.x];
+    float* hist = (bin_hist != nullptr && (L.type == 1 || L.type == 2)) ? bin_hist + 1024 * (long long)ti.x : nullptr;
     double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (!L.invalid) {   // a rejected luminaire traced nothing, so its records are stale
         const long long base = rec_base[ti.x] + (long long)(uint32_t)ti.y;
@@ -1714,8 +1725,20 @@ __global__ void __launch_bounds__(256) k_rec_grad(const int4* __restrict__ tiles
             const float phi_r = rec[9 * stride + j];
             float dl[6];
             first_hit_dlog(L, x1, y, n1, rec[7 * stride + j], rec[8 * stride + j], dl);
+            float m2 = 0.0f;
 #pragma unroll
-            for (int c = 0; c < 6; ++c) acc[c] += (double)(se * (phi_r * dl[c]));
+            for (int c = 0; c < 6; ++c) {
+                const float cr = se * (phi_r * dl[c]);
+                acc[c] += (double)cr;
+                if (hist) {
+                    const float z = cr * inv_sigma[6 * ti.x + c];
+                    m2 = m2 + z * z;
+                }
+            }
+            if (hist) {
+                const int ebin = __float_as_int(rec[11 * stride + j]);
+                if (ebin >= 0) atomicAdd(hist + ebin, m2 * rec[12 * stride + j]);
+            }
         }
     }
 #pragma unroll
@@ -2058,7 +2081,8 @@ hipError_t launch_objective(const float* E, const float* Et, const float* alpha,
 hipError_t launch_rec_grad(const TraceArgs& a, double* partials, hipStream_t st)
 {
     if (a.n_tiles > 0)
-        k_rec_grad<<<a.n_tiles, 256, 0, st>>>(a.tiles, a.lights, a.patches, a.rec, a.rec_stride, a.rec_base, partials);
+        k_rec_grad<<<a.n_tiles, 256, 0, st>>>(a.tiles, a.lights, a.patches, a.rec, a.rec_stride, a.rec_base,
+                                              a.bin_hist, a.inv_sigma, partials);
     return hipGetLastError();
 }
 
