@@ -1007,11 +1007,21 @@ int lt_trace_adjoint_rgb(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_para
     a.colour = d_colour;
     a.rho_rgb = c->rho_rgb;
     a.partials_col = c->d_partials_col;
+    // two passes as the grey adjoint's (below 2^30 paths per layout)
+    const bool two_pass = cfg->paths_per_layout < (1ll << 30);
+    if (two_pass) {
+        rc = ensure_rec(c);
+        if (rc) return rc;
+        a.rec = c->d_rec;
+        a.rec_stride = c->rec_paths;
+        a.rec_base = c->d_rec_base;
+    }
     const bool graph = (cfg->flags & LT_FLAG_GRAPH) != 0;
     auto body = [&](hipStream_t st) -> hipError_t {
         hipError_t e = launch_light_setup(d_params, c->d_si, c->d_sf, c->d_npaths, c->L, c->d_lights, c->d_flags, st);
         if (e == hipSuccess && d_bin_hist) e = launch_fill_f32(d_bin_hist, (long long)c->L * 1024, 0.0f, st);
         if (e == hipSuccess) e = timed_trace(c, true, graph, a, st);
+        if (e == hipSuccess && two_pass) e = launch_rec_grad(a, c->d_partials, st);
         if (e == hipSuccess) e = launch_grad_reduce(c->d_partials, c->d_range, c->L, d_grad, st);
         if (e == hipSuccess) e = launch_grad_reduce_col(c->d_partials_col, c->d_range, c->L, d_grad_colour, st);
         return e;

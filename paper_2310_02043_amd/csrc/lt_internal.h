@@ -101,15 +101,15 @@ struct TraceArgs {
     int vote_param;             // 0..5
     // two-pass adjoint (grey, box basis): instead of the per-tile sums, each
     // path leaves a first-hit record, kRecFields planes of rec_stride floats
-    // (x_1 xyz, origin y xyz, patch | flip << 31, a_u, a_v, Phi_r, s_r, and
-    // with the training histogram the emission cell and its weight), at index
-    // rec_base[light] + path; null otherwise
+    // (x_1 xyz, origin y xyz, patch | flip << 31, a_u, a_v, Phi_r, s_r, with
+    // the training histogram the emission cell and its weight, in colour the
+    // green and blue sums), at index rec_base[light] + path; null otherwise
     float* rec;
     long long rec_stride;
     const long long* rec_base;
 };
 
-constexpr int kRecFields = 13;   // floats per path of the two-pass adjoint's records
+constexpr int kRecFields = 15;   // floats per path of the two-pass adjoint's records
 
 // Object-space path tracing over the texels of one layout.
 struct PtArgs {

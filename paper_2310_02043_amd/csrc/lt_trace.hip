@@ -649,15 +649,16 @@ __global__ void __launch_bounds__(WPB * 64)
     __attribute__((amdgpu_waves_per_eu(MODE >= 30 ? 4
                                                   : (!ADJ && !STATS && MODE == 0 ? 8
                                                      : (!STATS && ((!ADJ && MODE == 1) || MODE == 7) ? 7
-                                                                                    : (ADJ && !STATS && MODE == 0 ? 6 : 5))))))
+                                                                                    : (ADJ && !STATS && (MODE == 0 || MODE == 8) ? 6 : 5))))))
     k_trace(TraceArgs a)
 {
     constexpr bool DIR = MODE >= 30;               // directional texels of order MODE - 30
     constexpr int DORD = DIR ? MODE - 30 : 0;
-    // MODE 7: the first pass of the two-pass adjoint (grey, box basis, no
-    // histogram or map): each path leaves a first-hit record and its adjoint
-    // sum instead of adding its contribution to the tile's sums
-    constexpr bool REC = ADJ && MODE == 7;
+    // MODE 7 (grey) and 8 (colour): the first pass of the two-pass adjoint
+    // (box basis, no map): each path leaves a first-hit record and its
+    // adjoint sums instead of adding its contribution to the tile's sums
+    constexpr bool REC = ADJ && (MODE == 7 || MODE == 8);   // 8: the same in colour
+    constexpr bool RGB = MODE == 2 || MODE == 8;
     // the plain and the colour adjoint keep kAdjLdsDepth / kColAdjLdsDepth
     // stack entries in LDS: their per-lane state takes the rest of the
     // budget of six (plain) or five (colour) waves per SIMD; the overflow
@@ -674,7 +675,7 @@ __global__ void __launch_bounds__(WPB * 64)
     constexpr bool VOTES = ADJ && MODE <= 1;
     __shared__ int s_k1[VOTES ? WPB * 64 : 1];
     // colour: per lane T_g, T_b, s_g, s_b and the three channel-weight sums
-    __shared__ float s_rgb[MODE == 2 ? WPB * 7 * 64 : 1];
+    __shared__ float s_rgb[RGB ? WPB * 7 * 64 : 1];
     // directional: forward, the hit's 16 coefficient sums; adjoint T2, R,
     // Q[3], D[3], w_in1[3], 1/r1 and the hit texel's 16 dO/dL values
     constexpr int DIRW = ADJ ? 28 : 16;
@@ -684,7 +685,7 @@ __global__ void __launch_bounds__(WPB * 64)
     float* adj = s_adj + (ADJ && !REC ? wib * 2 * NPAR * 64 + lane : 0);
     int k1_reg = 0;
     int* k1 = VOTES ? s_k1 + wib * 64 + lane : &k1_reg;
-    float* rgbs = s_rgb + (MODE == 2 ? wib * 7 * 64 + lane : 0);
+    float* rgbs = s_rgb + (RGB ? wib * 7 * 64 + lane : 0);
     float* dst = s_dir + (DIR ? wib * DIRW * 64 + lane : 0);
     // persistent wave: its slot owns one traversal-stack overflow area, and
     // it takes work tiles from the queue(s) until they are drained
@@ -722,12 +723,12 @@ __global__ void __launch_bounds__(WPB * 64)
         const int count = L.invalid ? 0 : ti.z;   // a rejected luminaire traces nothing
         const uint32_t stream_id = ((uint32_t)ti.w << 16) | (uint32_t)L.l_local;
         constexpr int NC = DIR ? (DORD + 1) * (DORD + 1) : 1;
-        const long long rowK = (MODE == 2 ? 3 : (DIR ? NC : 1)) * a.K;
+        const long long rowK = (RGB ? 3 : (DIR ? NC : 1)) * a.K;
         const float inv_np = DIR ? 1.0f / (float)a.dir_samples : 0.0f;
         long long* S = ADJ ? nullptr : a.S + (long long)ti.w * rowK;
         const float* g = ADJ ? a.g + (long long)ti.w * rowK : nullptr;
         float c0 = 1.0f, c1 = 1.0f, c2 = 1.0f;   // channel weights of the flux
-        if (MODE == 2) {
+        if (RGB) {
             c0 = a.colour[3 * ti.x];
             c1 = a.colour[3 * ti.x + 1];
             c2 = a.colour[3 * ti.x + 2];
@@ -819,7 +820,7 @@ __global__ void __launch_bounds__(WPB * 64)
                 skip = -1;
                 T = 1.0f;
                 s_r = 0.0f;
-                if (MODE == 2) {
+                if (RGB) {
                     rgbs[0] = 1.0f;
                     rgbs[64] = 1.0f;
                     rgbs[128] = 0.0f;
@@ -961,7 +962,7 @@ __global__ void __launch_bounds__(WPB * 64)
                                 dst[704] = ir1;
                             }
                         }
-                    } else if (!ADJ && MODE == 2) {
+                    } else if (!ADJ && RGB) {
                         const float v0 = ((phi_r * c0) * T) * hi.inva;
                         const float v1 = ((phi_r * c1) * rgbs[0]) * hi.inva;
                         const float v2 = ((phi_r * c2) * rgbs[64]) * hi.inva;
@@ -1002,7 +1003,7 @@ __global__ void __launch_bounds__(WPB * 64)
                             gk = g[hi.k];
                         }
                         s_r = s_r + (gk * hi.inva) * T;
-                        if (MODE == 2) {
+                        if (RGB) {
                             rgbs[128] = rgbs[128] + (g[a.K + hi.k] * hi.inva) * rgbs[0];
                             rgbs[192] = rgbs[192] + (g[2 * a.K + hi.k] * hi.inva) * rgbs[64];
                         }
@@ -1032,7 +1033,7 @@ __global__ void __launch_bounds__(WPB * 64)
                         bnc = true;
                         bn = hi.no;
                         skip = s.qb;
-                        if (MODE == 2) {
+                        if (RGB) {
                             const float4 rho = a.rho_rgb[skip];
                             T = T * rho.x;
                             rgbs[0] = rgbs[0] * rho.y;
@@ -1047,7 +1048,7 @@ __global__ void __launch_bounds__(WPB * 64)
                         skip = s.qb;
                         start_segment(s);
                         trav = true;
-                        if (MODE == 2) {
+                        if (RGB) {
                             const float4 rho = a.rho_rgb[skip];
                             T = T * rho.x;
                             rgbs[0] = rgbs[0] * rho.y;
@@ -1076,15 +1077,19 @@ __global__ void __launch_bounds__(WPB * 64)
                 }
                 if (end_path) {
                     if (REC) {
-                        // every path leaves its adjoint sum (0 without a hit,
-                        // which tells the second pass to skip its record)
+                        // every path leaves its adjoint sum(s) (0 without a
+                        // hit, which tells the second pass to skip its record)
                         *(float*)((char*)(rec0 + 10 * a.rec_stride) + (pid << 2)) = s_r;
+                        if (RGB) {
+                            *(float*)((char*)(rec0 + 13 * a.rec_stride) + (pid << 2)) = rgbs[128];
+                            *(float*)((char*)(rec0 + 14 * a.rec_stride) + (pid << 2)) = rgbs[192];
+                        }
                     } else if (ADJ && h >= 1) {
                         // colour: every channel shares the path, so the
                         // geometric terms take the colour-weighted adjoint
                         // sum, and dO/dc_ch gathers s_ch Phi_r
                         float se = s_r;
-                        if (MODE == 2) {
+                        if (RGB) {
                             se = (s_r * c0 + rgbs[128] * c1) + rgbs[192] * c2;
                             rgbs[256] += s_r * phi_r;
                             rgbs[320] += rgbs[128] * phi_r;
@@ -1143,7 +1148,7 @@ __global__ void __launch_bounds__(WPB * 64)
 #pragma unroll
                 for (int c = 0; c < NPAR; ++c) a.partials[(long long)tile * NPAR + c] = acc[c];
             }
-            if (MODE == 2) {
+            if (RGB) {
                 double accc[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) accc[c] = wave_sum((double)rgbs[(4 + c) * 64]);
@@ -1700,23 +1705,40 @@ __global__ void __launch_bounds__(64) k_grad_reduce(const double* __restrict__ p
 // sums are FP64, thread-strided in path order and then a fixed tree.  With
 // the training histogram each path also adds its squared normalised
 // contribution, weighted, to its emission cell, as the one-pass kernel does.
+// In colour the record holds the three channels' sums: the geometric terms
+// take their colour-weighted sum, and dO/dc_ch gathers s_ch Phi_r.
+template <bool RGB>
 __global__ void __launch_bounds__(256) k_rec_grad(const int4* __restrict__ tiles, const DevLight* __restrict__ lights,
                                                   const DevPatch* __restrict__ patches, const float* __restrict__ rec,
                                                   long long stride, const long long* __restrict__ rec_base,
                                                   float* __restrict__ bin_hist, const float* __restrict__ inv_sigma,
-                                                  double* __restrict__ partials)
+                                                  const float* __restrict__ colour, double* __restrict__ partials,
+                                                  double* __restrict__ partials_col)
 {
-    __shared__ double sh[6][256];
+    constexpr int NA = RGB ? 9 : 6;
+    __shared__ double sh[NA][256];
     const int4 ti = tiles[blockIdx.x];
     const DevLight& L = lights[ti.x];
     float* hist = (bin_hist != nullptr && (L.type == 1 || L.type == 2)) ? bin_hist + 1024 * (long long)ti.x : nullptr;
-    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double acc[NA];
+#pragma unroll
+    for (int c = 0; c < NA; ++c) acc[c] = 0.0;
     if (!L.invalid) {   // a rejected luminaire traced nothing, so its records are stale
         const long long base = rec_base[ti.x] + (long long)(uint32_t)ti.y;
         for (int i = threadIdx.x; i < ti.z; i += 256) {
             const long long j = base + i;
-            const float se = rec[10 * stride + j];
-            if (se == 0.0f) continue;   // no hit, or nothing to add
+            float se = rec[10 * stride + j];
+            if (RGB) {
+                const float s_r = se, s_g = rec[13 * stride + j], s_b = rec[14 * stride + j];
+                if (s_r == 0.0f && s_g == 0.0f && s_b == 0.0f) continue;   // no hit, or nothing to add
+                const float phi = rec[9 * stride + j];
+                se = (s_r * colour[3 * ti.x] + s_g * colour[3 * ti.x + 1]) + s_b * colour[3 * ti.x + 2];
+                acc[6] += (double)(s_r * phi);
+                acc[7] += (double)(s_g * phi);
+                acc[8] += (double)(s_b * phi);
+            } else if (se == 0.0f) {
+                continue;   // no hit, or nothing to add
+            }
             const V3 x1 = v3(rec[j], rec[stride + j], rec[2 * stride + j]);
             const V3 y = v3(rec[3 * stride + j], rec[4 * stride + j], rec[5 * stride + j]);
             const unsigned qf = __float_as_uint(rec[6 * stride + j]);
@@ -1742,15 +1764,17 @@ __global__ void __launch_bounds__(256) k_rec_grad(const int4* __restrict__ tiles
         }
     }
 #pragma unroll
-    for (int c = 0; c < 6; ++c) sh[c][threadIdx.x] = acc[c];
+    for (int c = 0; c < NA; ++c) sh[c][threadIdx.x] = acc[c];
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s)
 #pragma unroll
-            for (int c = 0; c < 6; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + s];
+            for (int c = 0; c < NA; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + s];
         __syncthreads();
     }
     if (threadIdx.x < 6) partials[(long long)blockIdx.x * 6 + threadIdx.x] = sh[threadIdx.x][0];
+    if (RGB && threadIdx.x >= 6 && threadIdx.x < 9)
+        partials_col[(long long)blockIdx.x * 3 + threadIdx.x - 6] = sh[threadIdx.x][0];
 }
 
 // Per-texel area A_k from the patch table (binary search of texel_base).
@@ -1880,6 +1904,15 @@ hipError_t launch_wpb(const TraceArgs& a, int lds_depth, int n_cu, hipStream_t s
             }
         }
     } else if (a.rgb && !STATS) {
+        if constexpr (ADJ) {
+            if (a.rec != nullptr) {
+                if (lds_depth == 16)
+                    launch_persistent<ADJ, STATS, WPB, 16, 8>(a, n_cu, st);
+                else
+                    launch_persistent<ADJ, STATS, WPB, 32, 8>(a, n_cu, st);
+                return hipGetLastError();
+            }
+        }
         if (lds_depth == 16)
             launch_persistent<ADJ, STATS, WPB, 16, 2>(a, n_cu, st);
         else
@@ -2080,9 +2113,12 @@ hipError_t launch_objective(const float* E, const float* Et, const float* alpha,
 
 hipError_t launch_rec_grad(const TraceArgs& a, double* partials, hipStream_t st)
 {
-    if (a.n_tiles > 0)
-        k_rec_grad<<<a.n_tiles, 256, 0, st>>>(a.tiles, a.lights, a.patches, a.rec, a.rec_stride, a.rec_base,
-                                              a.bin_hist, a.inv_sigma, partials);
+    if (a.n_tiles > 0 && a.rgb)
+        k_rec_grad<true><<<a.n_tiles, 256, 0, st>>>(a.tiles, a.lights, a.patches, a.rec, a.rec_stride, a.rec_base,
+                                                    a.bin_hist, a.inv_sigma, a.colour, partials, a.partials_col);
+    else if (a.n_tiles > 0)
+        k_rec_grad<false><<<a.n_tiles, 256, 0, st>>>(a.tiles, a.lights, a.patches, a.rec, a.rec_stride, a.rec_base,
+                                                     a.bin_hist, a.inv_sigma, nullptr, partials, nullptr);
     return hipGetLastError();
 }
 
