@@ -189,12 +189,14 @@ int lt_objective(lt_ctx* ctx, const float* d_E, const float* d_Etarget, const fl
  * writes d_grad [L,6] f32 = dO/dp.  d_bin_hist [L,1024] f32 (may be NULL,
  * overwritten) receives per-light adjoint magnitudes binned by emission
  * direction (see lt_proposal_set_scale); rows of point lights and
- * soft-edged spots stay 0.  In the box basis and below 2^30 paths per layout
- * it runs in two passes: the trace leaves a 52-byte record per path (first
- * hit, origin, flux, adjoint sum, emission cell) in a context-owned device
- * buffer that grows to the largest path count seen (14 GB for 2^28 paths;
+ * soft-edged spots stay 0.  In the box basis, below 2^30 paths per layout
+ * and while the records take at most an eighth of device memory it runs in
+ * two passes: the trace leaves a 60-byte record per path (first hit,
+ * origin, flux, adjoint sums, emission cell) in a context-owned device
+ * buffer that grows to the largest path count seen (16 GB for 2^28 paths;
  * counted in lt_info's device_bytes), and a second kernel forms the
- * per-tile FP64 sums. */
+ * per-tile FP64 sums; otherwise in one pass.  lt_trace_adjoint_rgb runs
+ * the same way. */
 int lt_trace_adjoint(lt_ctx* ctx, const lt_trace_cfg* cfg, const float* d_params, const float* d_dOdE,
                      float* d_grad, float* d_bin_hist);
 

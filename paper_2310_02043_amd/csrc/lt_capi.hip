@@ -64,6 +64,7 @@ struct lt_ctx {
     std::string err;
     int n_cu = 256;
     int waves_per_cu = 32;           // hardware wave slots per CU
+    size_t mem_total = 0;            // device memory (bytes), for the two-pass adjoint's record budget
     unsigned char* noalloc = nullptr;  // this device's scratch array (lt_trace_adjoint_noalloc)
     unsigned* d_queue = nullptr;     // work-queue ticket counters of the persistent trace kernels [8]
 
@@ -296,6 +297,14 @@ int ensure_tiles(lt_ctx* c, long long ppl)
     return LT_OK;
 }
 
+// whether the two-pass adjoint's records for the current tiles' paths fit its
+// budget, an eighth of device memory (36 GB on a 288 GB device); larger
+// jobs take the one-pass kernel, which needs no per-path memory
+bool rec_fits(const lt_ctx* c)
+{
+    return (size_t)kRecFields * sizeof(float) * (size_t)std::max(c->rec_paths, 1ll) <= c->mem_total / 8;
+}
+
 // the two-pass adjoint's record planes for the current tiles' paths
 int ensure_rec(lt_ctx* c)
 {
@@ -501,6 +510,7 @@ int lt_create(int device, void* hip_stream, lt_ctx** out)
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0) {
         c->n_cu = prop.multiProcessorCount;
         if (prop.maxThreadsPerMultiProcessor >= 64) c->waves_per_cu = prop.maxThreadsPerMultiProcessor / 64;
+        c->mem_total = prop.totalGlobalMem;
     }
     if (hipMalloc(&c->d_misses, sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&c->d_flags, sizeof(unsigned)) != hipSuccess ||
@@ -792,12 +802,13 @@ int lt_trace_adjoint(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_params, 
     a.g = d_dOdE;
     a.partials = c->d_partials;
     a.bin_hist = d_bin_hist;
-    // in the box basis and below 2^30 paths per layout (a luminaire's records
-    // then lie within 32-bit byte offsets) the adjoint runs in two passes:
+    // in the box basis, below 2^30 paths per layout (a luminaire's records
+    // then lie within 32-bit byte offsets) and within the record budget the
+    // adjoint runs in two passes:
     // the trace records each path's first hit and adjoint sum, a second
     // kernel forms the paths' contributions, the tiles' sums and the
     // training histogram
-    const bool two_pass = !(cfg->flags & LT_FLAG_LINEAR) && cfg->paths_per_layout < (1ll << 30);
+    const bool two_pass = !(cfg->flags & LT_FLAG_LINEAR) && cfg->paths_per_layout < (1ll << 30) && rec_fits(c);
     if (two_pass) {
         rc = ensure_rec(c);
         if (rc) return rc;
@@ -1008,7 +1019,7 @@ int lt_trace_adjoint_rgb(lt_ctx* c, const lt_trace_cfg* cfg, const float* d_para
     a.rho_rgb = c->rho_rgb;
     a.partials_col = c->d_partials_col;
     // two passes as the grey adjoint's (below 2^30 paths per layout)
-    const bool two_pass = cfg->paths_per_layout < (1ll << 30);
+    const bool two_pass = cfg->paths_per_layout < (1ll << 30) && rec_fits(c);
     if (two_pass) {
         rc = ensure_rec(c);
         if (rc) return rc;
