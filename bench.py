@@ -4,7 +4,8 @@ Headline workload: the procedural 80 x 60 x 3.2 m building floor (2M
 triangles, 16M texels, 128 rectangular cos^n luminaires), 2^28 light paths
 per step, 6 hits per path.  One step is the whole hot path: luminaire setup,
 accumulator clear, primal light tracing, fixed-point to float, objective and
-dO/dE, adjoint light tracing, per-light gradient reduction.  Inputs are
+dO/dE, adjoint light tracing (its first-hit records, then the per-path
+contributions and per-tile sums), per-light gradient reduction.  Inputs are
 resident in HBM before the timed region.
 
 The launch tuning comes from the autotuner (a matching entry of
