@@ -310,6 +310,8 @@ int ensure_rec(lt_ctx* c)
 {
     const size_t need = (size_t)kRecFields * (size_t)std::max(c->rec_paths, 1ll);
     if (need <= c->rec_cap) return LT_OK;
+    // the previous calls' passes may still read or write the old buffer
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     free_graphs(c);
     hipFree(c->d_rec);
     c->d_rec = nullptr;
